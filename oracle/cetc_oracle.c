@@ -1,0 +1,232 @@
+/*
+ * CPU ORACLE for cover-edge triangle counting — TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * this code.  It shares nothing with the GPU library: no headers, helpers, tables or
+ * kernels.  It is deliberately plain and slow so that it can be checked against the
+ * paper by eye:
+ *
+ *   Bader, Li, Du et al., "Cover Edge-Based Novel Triangle Counting" (arXiv 2403.02997)
+ *     Section 2  : graph, neighbour set N(v), triangle = 3 distinct pairwise-adjacent
+ *                  vertices.
+ *     Def. BFS-Edge (Section 4.1): level L(v) = BFS distance from the root; an edge whose
+ *                  endpoints share a level is horizontal.
+ *     Algorithm CETC-Seq (Section 4.2): BFS from every still-unvisited vertex, then for
+ *                  every horizontal edge (u,v) with u < v, every w in N(u) ∩ N(v) is
+ *                  counted when L(u) != L(w), or when L(u) == L(w) and v < w.
+ *     Algorithm CETC-SM (Section 4.4): the same edge loop in parallel; c1 counts apexes
+ *                  on another level, c2 apexes on the same level; T = c1 + c2 / 3.
+ *
+ * Readings where the paper is silent (also listed in the design notes):
+ *   - the BFS restart loop visits candidate roots in ascending vertex ID, so each
+ *     component's root is its smallest vertex ID, and every component starts at level 0;
+ *   - the edge loop scans both stored directions of the symmetric CSR and keeps u < v,
+ *     so every undirected edge is examined once;
+ *   - "c2 / 3" is exact integer division (c2 is a multiple of 3);
+ *   - counts are 64-bit unsigned.
+ *
+ * Input: symmetric CSR, rowptr[n+1], colidx[nnz] (uint32), neighbour lists strictly
+ * increasing, no self-loops.  orc_check_csr verifies exactly that.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_UNVISITED 0xFFFFFFFFu
+
+/* Return codes of orc_check_csr. */
+#define ORC_OK 0
+#define ORC_BAD_ROWPTR (-1)   /* rowptr[0] != 0, not monotone, or rowptr[n] != nnz */
+#define ORC_BAD_INDEX (-2)    /* a neighbour ID >= n                               */
+#define ORC_UNSORTED (-3)     /* a row not strictly increasing (or duplicate)       */
+#define ORC_SELF_LOOP (-4)    /* v in N(v)                                          */
+#define ORC_ASYMMETRIC (-5)   /* v in N(u) but u not in N(v)                        */
+
+/* Binary search for x in the sorted list a[0..len). */
+static int orc_contains(const uint32_t* a, uint64_t len, uint32_t x) {
+  uint64_t lo = 0, hi = len;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < len && a[lo] == x;
+}
+
+/* Validate the input contract: the graph of Section 2 stored as a symmetric CSR. */
+int orc_check_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t nnz) {
+  if (rowptr[0] != 0 || (uint64_t)rowptr[n] != nnz) return ORC_BAD_ROWPTR;
+  for (uint32_t u = 0; u < n; ++u)
+    if (rowptr[u + 1] < rowptr[u]) return ORC_BAD_ROWPTR;
+  for (uint32_t u = 0; u < n; ++u) {
+    for (uint64_t i = rowptr[u]; i < rowptr[u + 1]; ++i) {
+      uint32_t v = colidx[i];
+      if (v >= n) return ORC_BAD_INDEX;
+      if (v == u) return ORC_SELF_LOOP;
+      if (i > rowptr[u] && colidx[i - 1] >= v) return ORC_UNSORTED;
+    }
+  }
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t i = rowptr[u]; i < rowptr[u + 1]; ++i) {
+      uint32_t v = colidx[i];
+      if (!orc_contains(colidx + rowptr[v], rowptr[v + 1] - rowptr[v], u)) return ORC_ASYMMETRIC;
+    }
+  return ORC_OK;
+}
+
+/*
+ * Levels by breadth-first search, restarted from every unvisited vertex (CETC-Seq, the
+ * BFS restart loop; Def. BFS-Edge).  Candidate roots are taken in ascending ID; the
+ * root of each component gets level 0 and every other vertex its shortest distance to
+ * that root.  level[] must hold n entries.  Returns the largest level assigned (0 for an
+ * edgeless graph), or -1 if the queue cannot be allocated.
+ */
+int64_t orc_bfs_levels(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                       uint32_t* level) {
+  uint32_t* queue = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+  if (!queue) return -1;
+  uint32_t max_level = 0;
+  for (uint32_t i = 0; i < n; ++i) level[i] = ORC_UNVISITED;
+  for (uint32_t s = 0; s < n; ++s) {
+    if (level[s] != ORC_UNVISITED) continue;
+    /* BFS(G, s): plain FIFO queue. */
+    uint64_t head = 0, tail = 0;
+    level[s] = 0;
+    queue[tail++] = s;
+    while (head < tail) {
+      uint32_t x = queue[head++];
+      for (uint64_t i = rowptr[x]; i < rowptr[x + 1]; ++i) {
+        uint32_t y = colidx[i];
+        if (level[y] == ORC_UNVISITED) {
+          level[y] = level[x] + 1;
+          if (level[y] > max_level) max_level = level[y];
+          queue[tail++] = y;
+        }
+      }
+    }
+  }
+  free(queue);
+  return (int64_t)max_level;
+}
+
+/*
+ * Size of the cover-edge set of Theorem Gen-CES (Section 4.1): the horizontal edges,
+ * L(u) == L(v), each undirected edge counted once (u < v).  The same test as the
+ * first line of the CETC-Seq edge loop, without the intersections.
+ */
+uint64_t orc_cover_edges(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                         const uint32_t* level) {
+  uint64_t S = 0;
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      uint32_t v = colidx[e];
+      if (level[u] == level[v] && u < v) S += 1;
+    }
+  return S;
+}
+
+/* Statistics of one CETC-Seq run. */
+typedef struct {
+  uint64_t triangles;      /* T                                             */
+  uint64_t cover_edges;    /* |S| = number of horizontal edges (u < v)      */
+  uint64_t probes_min;     /* sum over S of min(d(u), d(v))                 */
+  uint64_t probes_merge;   /* sum over S of d(u) + d(v)                     */
+} orc_stats;
+
+/*
+ * CETC-Seq counting loop (Section 4.2, Algorithm CETC-Seq, after the BFS):
+ *   for every edge (u, v) with L(u) == L(v) and u < v            -- horizontal, once
+ *     for every w in N(u) ∩ N(v)                                  -- two-pointer merge
+ *       if L(u) != L(w), or L(u) == L(w) and v < w:  T <- T + 1
+ * `level` comes from orc_bfs_levels.  If tri_per_vertex is not NULL (n entries, zeroed
+ * by the caller) every counted triangle {u, v, w} adds 1 to each of its three vertices.
+ */
+void orc_cetc_seq(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                  const uint32_t* level, orc_stats* st, uint64_t* tri_per_vertex) {
+  uint64_t T = 0, S = 0, pmin = 0, pmerge = 0;
+  for (uint32_t u = 0; u < n; ++u) {
+    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      uint32_t v = colidx[e];
+      if (!(level[u] == level[v] && u < v)) continue; /* not a cover edge */
+      S += 1;
+      uint64_t du = rowptr[u + 1] - rowptr[u], dv = rowptr[v + 1] - rowptr[v];
+      pmin += du < dv ? du : dv;
+      pmerge += du + dv;
+      /* N(u) ∩ N(v) by merging the two sorted lists. */
+      uint64_t i = rowptr[u], j = rowptr[v];
+      while (i < rowptr[u + 1] && j < rowptr[v + 1]) {
+        if (colidx[i] < colidx[j]) {
+          ++i;
+        } else if (colidx[i] > colidx[j]) {
+          ++j;
+        } else {
+          uint32_t w = colidx[i];
+          if (level[u] != level[w] || (level[u] == level[w] && v < w)) {
+            T += 1;
+            if (tri_per_vertex) {
+              tri_per_vertex[u] += 1;
+              tri_per_vertex[v] += 1;
+              tri_per_vertex[w] += 1;
+            }
+          }
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  st->triangles = T;
+  st->cover_edges = S;
+  st->probes_min = pmin;
+  st->probes_merge = pmerge;
+}
+
+/*
+ * CETC-SM (Section 4.4): the horizontal-edge loop run in parallel with OpenMP over the
+ * first endpoint; for every common neighbour w, c1 counts w on another level and c2
+ * counts w on the same level.  Returns T = c1 + c2 / 3 and writes c1, c2.
+ * nthreads <= 0 uses the OpenMP default.
+ */
+uint64_t orc_cetc_sm(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                     const uint32_t* level, int nthreads, uint64_t* c1_out, uint64_t* c2_out) {
+  uint64_t c1 = 0, c2 = 0;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c1, c2) num_threads(nthreads)
+#endif
+  for (int64_t uu = 0; uu < (int64_t)n; ++uu) {
+    uint32_t u = (uint32_t)uu;
+    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      uint32_t v = colidx[e];
+      if (!(level[u] == level[v] && u < v)) continue;
+      uint64_t i = rowptr[u], j = rowptr[v];
+      while (i < rowptr[u + 1] && j < rowptr[v + 1]) {
+        if (colidx[i] < colidx[j]) {
+          ++i;
+        } else if (colidx[i] > colidx[j]) {
+          ++j;
+        } else {
+          if (level[colidx[i]] != level[u]) c1 += 1;
+          else c2 += 1;
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  if (c1_out) *c1_out = c1;
+  if (c2_out) *c2_out = c2;
+  return c1 + c2 / 3;
+}
+
+/* Threads the OpenMP runtime would use by default (1 without OpenMP). */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,78 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each case plants one mistake in a copy of oracle/cetc_oracle.c (a wrong index, a
+flipped comparison, a dropped condition, a wrong divisor, a broken merge step, a
+different BFS root order), builds the copy with gcc into a temporary directory, and
+checks that at least one pin from test_oracle_pins fails against it.  The committed
+oracle is never modified.
+"""
+import os
+import subprocess
+
+import networkx as nx
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import pins
+from tests.test_oracle_pins import bfs_certificate
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "cetc_oracle.c")
+
+MUTATIONS = {
+    "rule_uses_u_not_v": ("(level[u] == level[w] && v < w)", "(level[u] == level[w] && u < w)"),
+    "rule_level_test_flipped": ("if (level[u] != level[w] || (", "if (level[u] == level[w] || ("),
+    "edge_loop_drops_u_lt_v": ("if (!(level[u] == level[v] && u < v)) continue; /* not a cover edge */",
+                               "if (!(level[u] == level[v])) continue;"),
+    "bfs_level_step_two": ("level[y] = level[x] + 1;", "level[y] = level[x] + 2;"),
+    "sm_divides_by_two": ("return c1 + c2 / 3;", "return c1 + c2 / 2;"),
+    "merge_advances_wrong_list": ("if (colidx[i] < colidx[j]) {\n          ++i;",
+                                  "if (colidx[i] < colidx[j]) {\n          ++j;"),
+    "bfs_roots_descending": ("for (uint32_t s = 0; s < n; ++s) {\n    if (level[s] != ORC_UNVISITED)",
+                             "for (uint32_t s = n; s-- > 0;) {\n    if (level[s] != ORC_UNVISITED)"),
+}
+
+
+def pins_hold() -> bool:
+    """True when every pin passes for the oracle currently in use."""
+    try:
+        k = nx.karate_club_graph()
+        g = gg.from_edges(34, list(k.edges()))
+        r = oracle.cetc_seq(g)
+        if r.triangles != 45 or round(100.0 * r.cover_edges / 78, 1) != 35.9:
+            return False
+        for seed in range(6):
+            g = gg.gnp_small(12 + seed, 0.5, seed)
+            r = oracle.cetc_seq(g)
+            T_sm, c1, c2 = oracle.cetc_sm(g, r.level)
+            if r.triangles != pins.brute_force_triples(g) or T_sm != r.triangles:
+                return False
+        g = gg.rmat(9, 16, 3)
+        r = oracle.cetc_seq(g)
+        if r.triangles != pins.sparse_count(g):
+            return False
+        if oracle.count(gg.complete(9)) != 84 or oracle.count(gg.tri_grid(7, 9)) != 96:
+            return False
+        bfs_certificate(g, r.level)
+    except AssertionError:
+        return False
+    return True
+
+
+def test_unmodified_oracle_passes():
+    assert pins_hold()
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(src.replace(old, new, 1))  # first occurrence only
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                           str(mutated), "-o", str(lib)])
+    with oracle.use_library(str(lib)):
+        assert not pins_hold(), f"planted mistake {name} went unnoticed"

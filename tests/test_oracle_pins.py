@@ -1,0 +1,237 @@
+"""Pins of the CPU oracle against things other than itself (CPU only).
+
+- the paper's printed karate row (Table 1): T = 45, c = 35.9 %;
+- brute force over all triples (the Triples algorithm, Section 3.1) on tiny graphs;
+- trace(A^3) / 6 (Section 3.1) via numpy and scipy on small and medium graphs;
+- closed forms (K_n, triangulated grids, trees, bipartite graphs, cycles, wheels,
+  complete tripartite and friendship graphs, disjoint unions);
+- invariants proven in the paper: every triangle has one or three horizontal edges
+  (Lemmas H-E and HE2), T does not depend on the BFS roots (Theorem Correctness holds
+  for an arbitrarily rooted BFS), CETC-SM's T = c1 + c2 / 3, per-vertex counts sum to 3T
+  and equal diag(A^3) / 2;
+- a BFS certificate for the levels (exact distances from the smallest-ID root).
+"""
+import json
+import math
+import os
+
+import networkx as nx
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def full_check(g):
+    """Oracle result plus the checks that hold for every graph."""
+    assert oracle.check_csr(g) == 0
+    r = oracle.cetc_seq(g, per_vertex=True)
+    T_sm, c1, c2 = oracle.cetc_sm(g, r.level)
+    assert c2 % 3 == 0
+    assert T_sm == r.triangles == c1 + c2 // 3
+    assert int(r.per_vertex.sum()) == 3 * r.triangles
+    return r
+
+
+# ---- the paper's printed example -------------------------------------------------------
+
+def test_karate_table1_row():
+    ref = json.load(open(os.path.join(GOLDEN, "karate_table1.json")))
+    k = nx.karate_club_graph()
+    g = gg.from_edges(k.number_of_nodes(), list(k.edges()))
+    assert g.n == ref["n"] and g.num_edges == ref["m"]
+    r = full_check(g)
+    assert r.triangles == ref["triangles"]
+    assert round(100.0 * r.cover_edges / g.num_edges, 1) == ref["covering_ratio_percent"]
+
+
+# ---- brute force and trace identities ------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(40))
+def test_brute_force_tiny(seed):
+    n = 3 + seed % 14
+    p = [0.1, 0.3, 0.5, 0.8, 1.0][seed % 5]
+    g = gg.gnp_small(n, p, seed)
+    r = full_check(g)
+    assert r.triangles == pins.brute_force_triples(g) == pins.trace_count(g)
+    assert np.array_equal(r.per_vertex.astype(np.int64), pins.per_vertex_trace(g))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_trace_small(seed):
+    n = 50 + 37 * seed
+    g = gg.gnp_small(n, [0.02, 0.05, 0.2][seed % 3], 100 + seed)
+    r = full_check(g)
+    assert r.triangles == pins.trace_count(g)
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(8, 16, 1), (9, 8, 2), (10, 16, 1001), (11, 32, 3),
+                                           (12, 16, 4)])
+def test_rmat_against_sparse_trace(scale, ef, seed):
+    g = gg.rmat(scale, ef, seed)
+    r = full_check(g)
+    assert r.triangles == pins.sparse_count(g)
+    assert np.array_equal(r.per_vertex.astype(np.int64), pins.per_vertex_trace(g))
+
+
+@pytest.mark.parametrize("n,d,seed", [(2000, 8, 1), (5000, 32, 2), (3000, 4, 3)])
+def test_er_against_sparse_trace(n, d, seed):
+    g = gg.erdos_renyi(n, d, seed)
+    r = full_check(g)
+    assert r.triangles == pins.sparse_count(g)
+
+
+# ---- closed forms --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 17, 40])
+def test_complete_graph(n):
+    g = gg.complete(n)
+    r = full_check(g)
+    assert r.triangles == math.comb(n, 3)
+    # root 0 is adjacent to all: every other vertex on level 1, all their edges horizontal
+    assert r.cover_edges == math.comb(n - 1, 2)
+
+
+@pytest.mark.parametrize("R,C", [(1, 1), (1, 5), (2, 2), (3, 7), (16, 16), (40, 25)])
+def test_triangulated_grid(R, C):
+    g = gg.tri_grid(R, C)
+    assert g.num_edges == gg.grid_edges(R, C)
+    r = full_check(g)
+    assert r.triangles == 2 * (R - 1) * (C - 1)
+
+
+def grid_cell_count(g, R, C):
+    """Triangles of a triangulated grid with deletions, by checking both triangles of
+    every cell: {(i,j),(i,j+1),(i+1,j+1)} and {(i,j),(i+1,j),(i+1,j+1)}."""
+    adj = [set(g.colidx[g.rowptr[u]:g.rowptr[u + 1]].tolist()) for u in range(g.n)]
+    t = 0
+    for i in range(R - 1):
+        for j in range(C - 1):
+            a, b, c, d = i * C + j, i * C + j + 1, (i + 1) * C + j, (i + 1) * C + j + 1
+            if d in adj[a]:
+                t += (b in adj[a] and d in adj[b]) + (c in adj[a] and d in adj[c])
+    return t
+
+
+@pytest.mark.parametrize("R,C,frac,seed", [(30, 30, 0.01, 1), (20, 45, 0.1, 2), (64, 64, 0.3, 3)])
+def test_grid_with_deletions(R, C, frac, seed):
+    g = gg.tri_grid(R, C, frac, seed)
+    assert g.num_edges == gg.grid_edges(R, C) - round(frac * gg.grid_edges(R, C))
+    r = full_check(g)
+    assert r.triangles == grid_cell_count(g, R, C)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.path(30), lambda: gg.star(50), lambda: gg.random_tree(200, 7),
+    lambda: gg.complete_bipartite(7, 11), lambda: gg.cycle(4), lambda: gg.cycle(10),
+    lambda: gg.cycle(5), lambda: gg.cycle(31), lambda: gg.hypercube(6),
+    lambda: gg.empty_graph(0), lambda: gg.empty_graph(12),
+])
+def test_triangle_free(make):
+    assert full_check(make()).triangles == 0
+
+
+def test_single_triangle_and_families():
+    assert full_check(gg.cycle(3)).triangles == 1
+    for k in (4, 5, 9, 60):
+        assert full_check(gg.wheel(k)).triangles == k
+    for k in (1, 2, 7, 33):
+        assert full_check(gg.friendship(k)).triangles == k
+    for a, b, c in [(1, 1, 1), (2, 3, 4), (5, 5, 1), (6, 7, 8)]:
+        assert full_check(gg.complete_tripartite(a, b, c)).triangles == a * b * c
+
+
+def test_disjoint_union_additive():
+    parts = [gg.complete(6), gg.wheel(8), gg.rmat(8, 16, 5), gg.empty_graph(3), gg.cycle(3)]
+    u = gg.disjoint_union(parts)
+    assert full_check(u).triangles == sum(full_check(p).triangles for p in parts)
+
+
+# ---- invariants -------------------------------------------------------------------------
+
+def bfs_certificate(g, level):
+    """Levels are exact distances from the smallest ID of each component."""
+    n = g.n
+    rows = np.repeat(np.arange(n), g.degrees())
+    cols = g.colidx.astype(np.int64)
+    lv = level.astype(np.int64)
+    assert np.all(np.abs(lv[rows] - lv[cols]) <= 1)
+    # every non-root has a neighbour one level up
+    has_parent = np.zeros(n, dtype=bool)
+    has_parent[rows[lv[cols] == lv[rows] - 1]] = True
+    roots = lv == 0
+    assert np.all(has_parent | roots)
+    # one root per component, and it is the component's smallest ID
+    comp = np.arange(n)
+    changed = True
+    while changed:  # label propagation to the minimum
+        new = comp.copy()
+        np.minimum.at(new, rows, comp[cols])
+        changed = not np.array_equal(new, comp)
+        comp = new
+    assert np.array_equal(np.flatnonzero(roots), np.unique(comp))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.rmat(10, 16, 1001), lambda: gg.erdos_renyi(3000, 3, 9),
+    lambda: gg.tri_grid(25, 30, 0.05, 4),
+    lambda: gg.disjoint_union([gg.cycle(7), gg.empty_graph(2), gg.rmat(7, 8, 3)]),
+])
+def test_bfs_levels_certificate(make):
+    g = make()
+    level, depth = oracle.bfs_levels(g)
+    bfs_certificate(g, level)
+    assert depth == int(level.max(initial=0))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_every_triangle_has_one_or_three_horizontal_edges(seed):
+    g = gg.rmat(8, 16, 50 + seed) if seed % 2 else gg.gnp_small(60, 0.15, seed)
+    level, _ = oracle.bfs_levels(g)
+    tris = pins.triangles(g)
+    assert len(tris) == oracle.count(g)
+    for a, b, c in tris:
+        h = (level[a] == level[b]) + (level[a] == level[c]) + (level[b] == level[c])
+        assert h in (1, 3)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_count_independent_of_roots(seed):
+    g = gg.rmat(9, 16, 70 + seed) if seed % 2 else gg.disjoint_union(
+        [gg.gnp_small(40, 0.2, seed), gg.wheel(12), gg.tri_grid(6, 9)])
+    T = oracle.count(g)
+    order = gg.permutation(g.n, 900 + seed)
+    level = pins.bfs_levels_from(g, order)
+    r = oracle.cetc_seq(g, level=level)
+    assert r.triangles == T
+    T_sm, c1, c2 = oracle.cetc_sm(g, level)
+    assert T_sm == T and c2 % 3 == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_relabelling_invariance(seed):
+    g = gg.rmat(10, 8, 200 + seed, permute=False)
+    h = gg.relabel(g, gg.permutation(g.n, seed))
+    assert oracle.count(g) == oracle.count(h)
+
+
+def test_check_csr_rejects_bad_input():
+    g = gg.complete(4)
+    assert oracle.check_csr(g) == 0
+    bad = gg.CSR(g.rowptr.copy(), g.colidx.copy())
+    bad.colidx[0] = 0  # self-loop at vertex 0
+    assert oracle.check_csr(bad) == -4
+    bad = gg.CSR(g.rowptr.copy(), g.colidx.copy())
+    bad.colidx[[0, 1]] = bad.colidx[[1, 0]]
+    assert oracle.check_csr(bad) == -3
+    s = gg.star(4)
+    bad = gg.CSR(s.rowptr.copy(), s.colidx.copy())
+    bad.colidx[-1] = 2  # edge 3 -> 2 without 2 -> 3 (and 3 -> 0 dropped)
+    assert oracle.check_csr(bad) == -5
+    bad = gg.CSR(g.rowptr.copy(), g.colidx.copy())
+    bad.rowptr[-1] += 1
+    assert oracle.check_csr(bad) == -1
