@@ -1,0 +1,157 @@
+/*
+ * tc.h — cover-edge triangle counting on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bader, Li, Du et al., "Cover Edge-Based Novel Triangle Counting"
+ * (arXiv 2403.02997).
+ *   - Section 2: simple undirected graph G = (V, E); a triangle is a set of three
+ *     distinct pairwise-adjacent vertices; T = number of triangles.
+ *   - Def. BFS-Edge and Lemma H-E / Theorem Gen-CES (Section 4.1): with L(v) the BFS
+ *     level of v, the horizontal edges (L(u) == L(v)) cover every triangle.
+ *   - Algorithm CETC-Seq and Theorem Correctness (Section 4.2): BFS restarted from every
+ *     unvisited vertex; for every horizontal edge (u, v) with u < v and every
+ *     w in N(u) ∩ N(v), count w when L(w) != L(u), or when L(w) == L(u) and v < w.
+ *   - Algorithm CETC-SM (Section 4.4): the same count, edge-parallel; c1 = apexes on
+ *     another level, c2 = apexes on the same level, T = c1 + c2 / 3.
+ *
+ * Graph format (all entry points): symmetric CSR of a simple graph.
+ *   rowptr[n + 1] : uint32, rowptr[0] = 0, non-decreasing, rowptr[n] = m.
+ *   colidx[m]     : uint32 neighbour IDs < n; each row strictly increasing; no self-loops;
+ *                   v in N(u) iff u in N(v).
+ *   m             : number of stored entries = 2 |E|.  Input edges = m / 2.
+ * The arrays are DEVICE pointers on the current HIP device, owned by the caller and
+ * never written by the library.  Validity is a precondition (a self-loop or duplicate
+ * would be counted); tc_validate_csr checks it on the device.
+ *
+ * Roots: each BFS restarts from the smallest vertex ID of its component (the paper's
+ * restart loop taken in ascending ID).  T does not depend on this choice; the levels,
+ * cover-edge set and diagnostics do.
+ *
+ * Errors: every function returns a tc_status.  On error the outputs are left untouched.
+ * All entry points are stream-ordered on `stream` (0 = the null stream).
+ * Thread safety: calls on different streams may run concurrently; the library keeps no
+ * mutable global state besides a per-device cache of the device properties and the
+ * intersection tuning set by tc_set_isect_params.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TC_OK = 0,
+  TC_ERR_INVALID_ARG = -1,    /* null pointer where data is required, bad size      */
+  TC_ERR_OUT_OF_MEMORY = -2,  /* device workspace allocation failed                 */
+  TC_ERR_HIP = -3,            /* a HIP runtime call failed                          */
+  TC_ERR_INVALID_GRAPH = -4,  /* tc_validate_csr found a contract violation         */
+  TC_ERR_TOO_LARGE = -5,      /* n >= 2^31 or m >= 2^32                             */
+  TC_ERR_INTERNAL = -6        /* an internal consistency check failed               */
+} tc_status;
+
+/* Statistics of one counting run (host struct, filled by tc_count_ex). */
+typedef struct {
+  uint64_t triangles;     /* T                                                     */
+  uint64_t c1;            /* apexes on another level than the cover edge (CETC-SM) */
+  uint64_t c2;            /* apexes on the same level, each triangle seen 3 times  */
+  uint64_t cover_edges;   /* |S| = number of horizontal edges                      */
+  uint64_t probes;        /* neighbour-list elements streamed by the intersection  */
+  uint32_t depth;         /* largest BFS level                                     */
+  uint32_t num_roots;     /* connected components (isolated vertices included)    */
+  uint32_t bfs_levels_bottom_up; /* levels expanded bottom-up                      */
+  uint32_t reserved;
+} tc_stats;
+
+/*
+ * tc_count — number of triangles of one graph (CETC-Seq result, CETC-SM data-parallel
+ * form).  rowptr/colidx/n/m as above; `count` is a HOST pointer receiving T.
+ * Allocates its device workspace stream-ordered on `stream`, frees it before returning,
+ * and synchronises `stream`.  n == 0 or m == 0 gives T = 0 without a launch.
+ * Returns TC_ERR_INVALID_ARG for null pointers (when m > 0) or a null `count`,
+ * TC_ERR_TOO_LARGE for n >= 2^31, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
+ */
+int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+             hipStream_t stream, uint64_t* count);
+
+/*
+ * tc_count_ex — tc_count plus diagnostics.  `level_out` (DEVICE uint32[n], may be NULL)
+ * receives the BFS level of every vertex; `stats` (HOST, may be NULL) the statistics
+ * above.  `count` may be NULL when `stats` is given.
+ */
+int tc_count_ex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+                hipStream_t stream, uint64_t* count, uint32_t* level_out, tc_stats* stats);
+
+/*
+ * tc_count_per_vertex — t(v) = number of triangles containing v, for every v
+ * (Section 2: the vertex-based form of the count; sum of t(v) = 3 T).
+ * `tri_out` is a DEVICE uint64[n] overwritten with t(v).  Blocking like tc_count.
+ */
+int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                        uint64_t m, hipStream_t stream, uint64_t* tri_out);
+
+/*
+ * tc_count_batch — triangle counts of many independent graphs in one persistent launch
+ * (each graph's component roots, BFS, cover-edge selection and intersections run fused,
+ * larger graphs first).
+ * Graph g owns rowptr_cat[row_off[g] .. row_off[g+1]) (its n_g + 1 local offsets,
+ * starting at 0, so n_g = row_off[g+1] - row_off[g] - 1) and
+ * colidx_cat[col_off[g] .. col_off[g+1]) (m_g = col_off[g+1] - col_off[g] entries,
+ * equal to the graph's own rowptr[n_g], holding LOCAL IDs < n_g).
+ * row_off / col_off are DEVICE int64[num_graphs + 1], non-decreasing, starting at 0,
+ * with row_off[g+1] - row_off[g] >= 1 for every g.
+ * total_rows = row_off[num_graphs] (passed by value so the host never reads device
+ * memory).  counts is a DEVICE uint64[num_graphs] receiving T_g.
+ * `workspace` is a DEVICE buffer of at least
+ * tc_count_batch_workspace_size(num_graphs, total_rows) bytes owned by the caller, or
+ * NULL to let the library allocate (and free) it stream-ordered on `stream`.
+ * With a caller workspace the call allocates nothing, issues no memset, never
+ * synchronises and reads no device data on the host, so it can be captured into a HIP
+ * graph and replayed; a workspace must not be shared by calls that overlap in time.
+ * Per graph: n_g < 2^31 and m_g < 2^32 (precondition).  Returns TC_ERR_INVALID_ARG
+ * (null pointers, workspace too small), TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
+ */
+int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
+                   const int64_t* row_off, const int64_t* col_off, uint32_t num_graphs,
+                   uint64_t total_rows, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream, uint64_t* counts);
+
+/* Bytes of device workspace tc_count_batch needs (13 per row plus a small header). */
+size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows);
+
+/*
+ * tc_validate_csr — checks the graph format contract on the device: rowptr[0] == 0,
+ * non-decreasing, rowptr[n] == m, IDs < n, rows strictly increasing, no self-loops,
+ * symmetric.  Returns TC_OK or TC_ERR_INVALID_GRAPH (or an argument/HIP error).
+ * Synchronises `stream`.
+ */
+int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+                    hipStream_t stream);
+
+/*
+ * Intersection tuning (used by the autotuner).  The staged endpoint x of a cover edge
+ * goes to the lane class when d(x) <= lane_max, to the wavefront class when
+ * d(x) <= wave_max (<= 512), else to the workgroup class, which stages N(x) in chunks
+ * of `chunk` (<= 4096) entries and `seg` (<= 256) partners per work item.  The setting
+ * is process-wide; change it only while no count is running.  Out-of-range values give
+ * TC_ERR_INVALID_ARG and leave the setting unchanged.
+ */
+int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, uint32_t seg);
+/* Current setting as {lane_max, wave_max, chunk, seg} into the HOST array out4[4]. */
+int tc_get_isect_params(uint32_t* out4);
+
+/* Static description of a status code. */
+const char* tc_status_string(int status);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int tc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

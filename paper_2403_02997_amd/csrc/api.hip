@@ -1,0 +1,413 @@
+// C ABI of the cover-edge triangle-counting library (declared in include/tc.h) and the
+// host-side orchestration of the single-graph path:
+//
+//   component roots (union-find, smallest ID)          CETC-Seq BFS restart loop
+//   level BFS from all roots, direction-optimising      Def. BFS-Edge
+//   per-vertex info byte (level parity, degree class)
+//   cover-edge extraction: horizontal edges, oriented    Theorem Gen-CES
+//   planning of the intersection classes
+//   intersections with the apex rule                    CETC-Seq / CETC-SM
+//   reduction of the per-block counters
+//
+// The graph is read-only and already resident on the device.  Scratch memory comes from
+// the device's stream-ordered pool and is returned before the call completes.
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "../../include/tc.h"
+#include "tc_device.h"
+#include "tc_launch.h"
+
+namespace tc {
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves aligned sub-buffers out of one allocation.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = (T*)(base + off);
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+struct Layout {
+  size_t bytes;
+};
+
+std::mutex g_pool_mu;
+bool g_pool_ready[64];
+
+// Keep freed stream-ordered memory in the device pool between calls.
+void prepare_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  g_pool_ready[dev] = true;
+}
+
+struct DevAlloc {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  ~DevAlloc() {
+    if (p) hipFreeAsync(p, s);
+  }
+};
+
+#define TC_HIP(call)                          \
+  do {                                        \
+    if ((call) != hipSuccess) {               \
+      (void)hipGetLastError();                \
+      return TC_ERR_HIP;                      \
+    }                                         \
+  } while (0)
+
+#define TC_LAUNCHED()                         \
+  do {                                        \
+    if (hipGetLastError() != hipSuccess) return TC_ERR_HIP; \
+  } while (0)
+
+int alloc_async(DevAlloc& a, size_t bytes, hipStream_t s) {
+  a.s = s;
+  hipError_t e = hipMallocAsync(&a.p, bytes ? bytes : 256, s);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    a.p = nullptr;
+    return TC_ERR_OUT_OF_MEMORY;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    a.p = nullptr;
+    return TC_ERR_HIP;
+  }
+  return TC_OK;
+}
+
+IsectParams default_params() {
+  IsectParams p;
+  p.lane_max = 16;
+  p.wave_max = 512;
+  p.chunk = 4096;
+  p.seg = 256;
+  return p;
+}
+
+IsectParams g_params = default_params();
+
+struct RunOut {
+  u64 c[4];  // c1, c2, t2, probes
+  u64 cover_edges;
+  BfsCtl ctl;
+};
+
+// The whole single-graph pipeline.  `level_out` (device) may be null; `tri` (device,
+// zeroed by the caller) selects per-vertex attribution.
+int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s,
+               u32* level_out, u64* tri, RunOut* out) {
+  prepare_pool();
+  const IsectParams prm = g_params;
+  const u32 ntiles = (m + kTile - 1) / kTile;
+  const u32 max_s = m / 2;
+  const u32 hntiles = (max_s + kTile - 1) / kTile;
+  // ---- workspace ----
+  size_t bytes = 0;
+  {
+    Carver c(nullptr);
+    c.take<u32>(ntiles + 1);         // tile_row
+    c.take<u32>(n);                  // parent
+    c.take<u32>(n);                  // level
+    c.take<u32>(n);                  // queue0
+    c.take<u32>(n);                  // queue1
+    c.take<uint8_t>(n);              // vinfo
+    c.take<u32>((size_t)n + 1);      // hoff
+    c.take<u32>((size_t)n + 1);      // hcur
+    c.take<u32>(scan_tmp_words(n));  // scan tmp
+    c.take<u32>(max_s ? max_s : 1);  // hadj
+    c.take<u32>(hntiles + 1);        // htile_row
+    c.take<u32>(n);                  // wave_x
+    c.take<u32>(n);                  // block_x
+    c.take<u32>((size_t)n + 1);      // block items / offsets
+    c.take<BfsCtl>(1);
+    c.take<Plan>(1);
+    c.take<u64>(kCounterSlots * 4);
+    c.take<u64>(4);
+    bytes = c.off + 256;
+  }
+  DevAlloc ws;
+  int rc = alloc_async(ws, bytes, s);
+  if (rc) return rc;
+  Carver c(ws.p);
+  u32* tile_row = c.take<u32>(ntiles + 1);
+  u32* parent = c.take<u32>(n);
+  u32* level = c.take<u32>(n);
+  u32* q0 = c.take<u32>(n);
+  u32* q1 = c.take<u32>(n);
+  uint8_t* vinfo = c.take<uint8_t>(n);
+  u32* hoff = c.take<u32>((size_t)n + 1);
+  u32* hcur = c.take<u32>((size_t)n + 1);
+  u32* scan_tmp = c.take<u32>(scan_tmp_words(n));
+  u32* hadj = c.take<u32>(max_s ? max_s : 1);
+  u32* htile_row = c.take<u32>(hntiles + 1);
+  u32* wave_x = c.take<u32>(n);
+  u32* block_x = c.take<u32>(n);
+  u32* bitems = c.take<u32>((size_t)n + 1);
+  // control block: ctl, plan, counters, result are contiguous and cleared together
+  BfsCtl* ctl = c.take<BfsCtl>(1);
+  Plan* plan = c.take<Plan>(1);
+  u64* ctr = c.take<u64>(kCounterSlots * 4);
+  u64* out4 = c.take<u64>(4);
+  const size_t ctl_bytes = (char*)(out4 + 4) - (char*)ctl;
+  if (level_out) level = level_out;
+
+  TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
+  TC_HIP(hipMemsetAsync(hoff, 0, sizeof(u32) * ((size_t)n + 1), s));
+  TC_HIP(hipMemsetAsync(bitems, 0, sizeof(u32) * ((size_t)n + 1), s));
+
+  // ---- a1: component roots ----
+  launch_tile_rows(rowptr, n, m, tile_row, s);
+  launch_cc(rowptr, colidx, tile_row, n, m, parent, s);
+  TC_LAUNCHED();
+
+  // ---- a2: level BFS ----
+  launch_bfs_init(rowptr, parent, n, level, q0, ctl, s);
+  TC_LAUNCHED();
+  {
+    const u32 grid = bfs_grid(n);
+    u32 k = 0, batch = 4;
+    while (true) {
+      for (u32 i = 0; i < batch; ++i) launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, ctl, grid, s);
+      TC_LAUNCHED();
+      k += batch;
+      u32 done = 0;
+      TC_HIP(hipMemcpyAsync(&done, &ctl->done, sizeof(u32), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipStreamSynchronize(s));
+      if (done) break;
+      if ((u64)k > (u64)n + 2) return TC_ERR_INTERNAL;  // a BFS has at most n levels
+      batch = batch < 64 ? batch * 2 : 64;
+    }
+  }
+  launch_vinfo(rowptr, level, n, vinfo, s);
+
+  // ---- a3: cover-edge extraction ----
+  launch_extract_count(rowptr, colidx, tile_row, vinfo, n, m, hoff, s);
+  launch_scan(hoff, hoff, n, scan_tmp, s);
+  TC_HIP(hipMemcpyAsync(hcur, hoff, sizeof(u32) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+  launch_extract_write(rowptr, colidx, tile_row, vinfo, n, m, hcur, hadj, s);
+  launch_plan(rowptr, hoff, n, prm, wave_x, block_x, bitems, plan, s);
+  launch_scan(bitems, bitems, n, scan_tmp, s);
+  TC_LAUNCHED();
+  u32 h_ns = 0, h_items = 0;
+  Plan h_plan;
+  TC_HIP(hipMemcpyAsync(&h_ns, hoff + n, sizeof(u32), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&h_items, bitems + n, sizeof(u32), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&h_plan, plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  if (h_ns > max_s) return TC_ERR_INTERNAL;
+
+  // ---- a4: intersections ----
+  DevAlloc items_mem;
+  Item* items = nullptr;
+  if (h_items) {
+    rc = alloc_async(items_mem, sizeof(Item) * (size_t)h_items, s);
+    if (rc) return rc;
+    items = (Item*)items_mem.p;
+    launch_fill_items(rowptr, hoff, block_x, bitems, h_plan.num_block_x, prm, items, s);
+  }
+  if (h_plan.lane_edges) {
+    launch_tile_rows(hoff, n, h_ns, htile_row, s);
+    launch_isect_lane(rowptr, colidx, vinfo, hoff, hadj, htile_row, n, h_ns, prm, ctr, tri, s);
+  }
+  launch_isect_block(rowptr, colidx, vinfo, hoff, hadj, items, h_items, prm, plan, ctr, tri, s);
+  launch_isect_wave(rowptr, colidx, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan, ctr, tri, s);
+  // ---- a5: reduction ----
+  launch_finalize(ctr, out4, s);
+  TC_LAUNCHED();
+  TC_HIP(hipMemcpyAsync(out->c, out4, sizeof(u64) * 4, hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&out->ctl, ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  out->cover_edges = h_ns;
+  // Two independent tallies of the same-level apexes must agree (CETC-SM: c2 / 3).
+  if (out->c[1] % 3 != 0 || out->c[1] / 3 != out->c[2]) return TC_ERR_INTERNAL;
+  return TC_OK;
+}
+
+int check_args(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m) {
+  if (n >= 0x80000000u) return TC_ERR_TOO_LARGE;
+  if (m >= 0x100000000ull) return TC_ERR_TOO_LARGE;
+  if (n > 0 && !rowptr) return TC_ERR_INVALID_ARG;
+  if (m > 0 && (!colidx || n == 0)) return TC_ERR_INVALID_ARG;
+  return TC_OK;
+}
+
+}  // namespace
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" {
+
+int tc_version(void) { return kVersion; }
+
+const char* tc_status_string(int status) {
+  switch (status) {
+    case TC_OK: return "ok";
+    case TC_ERR_INVALID_ARG: return "invalid argument";
+    case TC_ERR_OUT_OF_MEMORY: return "device out of memory";
+    case TC_ERR_HIP: return "HIP runtime error";
+    case TC_ERR_INVALID_GRAPH: return "graph violates the CSR contract";
+    case TC_ERR_TOO_LARGE: return "graph too large (n >= 2^31 or m >= 2^32)";
+    case TC_ERR_INTERNAL: return "internal consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+int tc_count_ex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+                hipStream_t stream, uint64_t* count, uint32_t* level_out, tc_stats* stats) {
+  int rc = check_args(rowptr, colidx, n, m);
+  if (rc) return rc;
+  if (!count && !stats) return TC_ERR_INVALID_ARG;
+  tc_stats st;
+  memset(&st, 0, sizeof(st));
+  if (n == 0 || m == 0) {
+    if (level_out && n > 0) {
+      TC_HIP(hipMemsetAsync(level_out, 0, sizeof(uint32_t) * n, stream));
+      TC_HIP(hipStreamSynchronize(stream));
+    }
+    st.num_roots = n;
+  } else {
+    RunOut ro;
+    memset(&ro, 0, sizeof(ro));
+    rc = run_single(rowptr, colidx, n, (u32)m, stream, level_out, nullptr, &ro);
+    if (rc) return rc;
+    st.c1 = ro.c[0];
+    st.c2 = ro.c[1];
+    st.triangles = ro.c[0] + ro.c[2];
+    st.probes = ro.c[3];
+    st.cover_edges = ro.cover_edges;
+    st.depth = ro.ctl.depth;
+    st.num_roots = ro.ctl.num_roots;
+    st.bfs_levels_bottom_up = ro.ctl.bu_levels;
+  }
+  if (count) *count = st.triangles;
+  if (stats) *stats = st;
+  return TC_OK;
+}
+
+int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+             hipStream_t stream, uint64_t* count) {
+  if (!count) return TC_ERR_INVALID_ARG;
+  return tc_count_ex(rowptr, colidx, n, m, stream, count, nullptr, nullptr);
+}
+
+int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                        uint64_t m, hipStream_t stream, uint64_t* tri_out) {
+  int rc = check_args(rowptr, colidx, n, m);
+  if (rc) return rc;
+  if (n > 0 && !tri_out) return TC_ERR_INVALID_ARG;
+  if (n == 0) return TC_OK;
+  TC_HIP(hipMemsetAsync(tri_out, 0, sizeof(uint64_t) * n, stream));
+  if (m == 0) {
+    TC_HIP(hipStreamSynchronize(stream));
+    return TC_OK;
+  }
+  RunOut ro;
+  memset(&ro, 0, sizeof(ro));
+  return run_single(rowptr, colidx, n, (u32)m, stream, nullptr, (u64*)tri_out, &ro);
+}
+
+int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+                    hipStream_t stream) {
+  int rc = check_args(rowptr, colidx, n, m);
+  if (rc) return rc;
+  if (n == 0) return m == 0 ? TC_OK : TC_ERR_INVALID_GRAPH;
+  prepare_pool();
+  const u32 ntiles = (u32)((m + kTile - 1) / kTile);
+  DevAlloc ws;
+  rc = alloc_async(ws, sizeof(u32) * (ntiles + 1) + 256 + 256, stream);
+  if (rc) return rc;
+  Carver c(ws.p);
+  u32* flag = c.take<u32>(1);
+  u32* tile_row = c.take<u32>(ntiles + 1);
+  TC_HIP(hipMemsetAsync(flag, 0, sizeof(u32), stream));
+  if (!validate_rowptr_ok(rowptr, n, (u32)m, flag, stream)) {
+    TC_HIP(hipGetLastError());
+    return TC_ERR_INVALID_GRAPH;
+  }
+  if (m == 0) return TC_OK;
+  launch_tile_rows(rowptr, n, (u32)m, tile_row, stream);
+  launch_validate(rowptr, colidx, tile_row, n, (u32)m, flag, stream);
+  TC_LAUNCHED();
+  u32 h = 0;
+  TC_HIP(hipMemcpyAsync(&h, flag, sizeof(u32), hipMemcpyDeviceToHost, stream));
+  TC_HIP(hipStreamSynchronize(stream));
+  return h ? TC_ERR_INVALID_GRAPH : TC_OK;
+}
+
+size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows) {
+  return batch_workspace_bytes(num_graphs, total_rows);
+}
+
+int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
+                   const int64_t* row_off, const int64_t* col_off, uint32_t num_graphs,
+                   uint64_t total_rows, void* workspace, size_t workspace_bytes,
+                   hipStream_t stream, uint64_t* counts) {
+  if (num_graphs == 0) return TC_OK;
+  if (!rowptr_cat || !row_off || !col_off || !counts || total_rows < num_graphs)
+    return TC_ERR_INVALID_ARG;
+  const size_t need = batch_workspace_bytes(num_graphs, total_rows);
+  if (workspace) {
+    if (workspace_bytes < need) return TC_ERR_INVALID_ARG;
+    launch_batch(rowptr_cat, colidx_cat, row_off, col_off, num_graphs, total_rows, workspace,
+                 (u64*)counts, stream);
+    TC_LAUNCHED();
+    return TC_OK;
+  }
+  prepare_pool();
+  DevAlloc ws;
+  int rc = alloc_async(ws, need, stream);
+  if (rc) return rc;
+  launch_batch(rowptr_cat, colidx_cat, row_off, col_off, num_graphs, total_rows, ws.p,
+               (u64*)counts, stream);
+  TC_LAUNCHED();
+  return TC_OK;
+}
+
+// Intersection class thresholds (used by the autotuner).  Returns TC_ERR_INVALID_ARG for
+// values outside the ranges the LDS tables are sized for.
+int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, uint32_t seg) {
+  if (wave_max > 512 || lane_max > wave_max || chunk == 0 || chunk > 4096 || seg == 0 ||
+      seg > 256)
+    return TC_ERR_INVALID_ARG;
+  g_params.lane_max = lane_max;
+  g_params.wave_max = wave_max;
+  g_params.chunk = chunk;
+  g_params.seg = seg;
+  return TC_OK;
+}
+
+int tc_get_isect_params(uint32_t* out4) {
+  if (!out4) return TC_ERR_INVALID_ARG;
+  out4[0] = g_params.lane_max;
+  out4[1] = g_params.wave_max;
+  out4[2] = g_params.chunk;
+  out4[3] = g_params.seg;
+  return TC_OK;
+}
+
+}  // extern "C"

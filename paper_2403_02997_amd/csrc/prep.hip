@@ -1,0 +1,242 @@
+// Preparation kernels: CSR tile map, connected components with smallest-ID roots
+// (the root each BFS restart of the paper's CETC-Seq starts from), the per-vertex info
+// byte, a device-wide exclusive scan, and the graph-format validator.
+#include "tc_device.h"
+#include "tc_launch.h"
+
+namespace tc {
+
+static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
+
+int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+    v = 256;
+  if (dev >= 0 && dev < 64) cached[dev] = v;
+  return v;
+}
+
+// ---- tile map ----------------------------------------------------------------------
+// Every tile start t*kTile lies in exactly one non-empty row; that row writes it.
+__global__ void k_tile_rows(const u32* __restrict__ rowptr, u32 n, u32 m, u32 ntiles,
+                            u32* __restrict__ tile_row) {
+  for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const u32 lo = rowptr[r], hi = rowptr[r + 1];
+    if (lo == hi) continue;
+    for (u32 t = (lo + kTile - 1) / kTile; (u64)t * kTile < hi; ++t) tile_row[t] = r;
+    if (lo <= m - 1 && m - 1 < hi) tile_row[ntiles] = r;
+  }
+}
+
+void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  const u32 ntiles = cdiv(m, kTile);
+  const u32 grid = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_tile_rows, dim3(grid), dim3(256), 0, s, rowptr, n, m, ntiles, tile_row);
+}
+
+// ---- connected components ----------------------------------------------------------
+// Union-find over parent[] with the invariant parent[x] <= x: links always go from the
+// larger root to the smaller one, so each component's final root is its smallest
+// vertex ID.  Initialisation takes the smallest neighbour as the first parent and the
+// finds use path halving (both as in ECL-CC, Jaiganesh & Burtscher, HPDC 2018).
+__global__ void k_cc_init(const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+                          u32 n, u32* __restrict__ parent) {
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const u32 lo = rowptr[v], hi = rowptr[v + 1];
+    u32 p = v;
+    if (lo < hi) p = min(v, colidx[lo]);  // rows are sorted: colidx[lo] is the smallest
+    parent[v] = p;
+  }
+}
+
+__global__ void __launch_bounds__(kTileThreads) k_cc_hook(
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+    const u32* __restrict__ tile_row, u32 m, u32* parent) {
+  __shared__ u32 s_rp[kTileRowCap];
+  const u32 ntiles = (m + kTile - 1) / kTile;
+  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileInfo ti = tile_begin(rowptr, tile_row, t, m, s_rp);
+    for (u32 e = ti.e0 + threadIdx.x; e < ti.e1; e += blockDim.x) {
+      const u32 u = tile_row_of(ti, s_rp, rowptr, e);
+      const u32 v = colidx[e];
+      if (v < u) {
+        // skip edges already joined by the initial parents
+        if (load_coherent(&parent[u]) != v) cc_union(parent, u, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_cc_compress(u32 n, u32* parent) {
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    parent[v] = cc_find(parent, v);
+}
+
+void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
+               u32* parent, hipStream_t s) {
+  if (n == 0) return;
+  const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
+  if (m > 0) {
+    const u32 ntiles = cdiv(m, kTile);
+    const u32 gt = min(ntiles, (u32)num_cus() * 8);
+    hipLaunchKernelGGL(k_cc_hook, dim3(gt), dim3(kTileThreads), 0, s, rowptr, colidx, tile_row,
+                       m, parent);
+  }
+  hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
+}
+
+// ---- per-vertex info byte ------------------------------------------------------------
+__global__ void k_vinfo(const u32* __restrict__ rowptr, const u32* __restrict__ level, u32 n,
+                        uint8_t* __restrict__ vinfo) {
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const u32 d = rowptr[v + 1] - rowptr[v];
+    vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | degree_class(d));
+  }
+}
+
+void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, hipStream_t s) {
+  if (n == 0) return;
+  const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_vinfo, dim3(g), dim3(256), 0, s, rowptr, level, n, vinfo);
+}
+
+// ---- device-wide exclusive scan (u32) ------------------------------------------------
+// Three phases: per-block sums of kScanChunk elements, a single-block scan of those
+// sums, then a per-block scan that adds its block offset.
+constexpr u32 kScanThreads = 256;
+constexpr u32 kScanPer = 8;
+constexpr u32 kScanChunk = kScanThreads * kScanPer;
+
+size_t scan_tmp_words(u32 count) { return (size_t)cdiv(count, kScanChunk) + 1; }
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const u32* __restrict__ in,
+                                                              u32 count, u32* __restrict__ sums) {
+  __shared__ u32 s_tmp[kScanThreads / kWave];
+  const u32 base = blockIdx.x * kScanChunk;
+  u32 v = 0;
+  for (u32 i = 0; i < kScanPer; ++i) {
+    const u32 idx = base + i * kScanThreads + threadIdx.x;
+    if (idx < count) v += in[idx];
+  }
+  u32 tot;
+  block_incl_scan(v, s_tmp, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(u32* sums, u32 nb) {
+  __shared__ u32 s_tmp[kScanThreads / kWave];
+  u32 carry = 0;
+  for (u32 base = 0; base < nb; base += kScanThreads) {
+    const u32 idx = base + threadIdx.x;
+    const u32 v = idx < nb ? sums[idx] : 0;
+    u32 tot;
+    const u32 incl = block_incl_scan(v, s_tmp, &tot);
+    if (idx < nb) sums[idx] = carry + incl - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const u32* in, u32* out, u32 count,
+                                                             const u32* __restrict__ sums) {
+  __shared__ u32 s_tmp[kScanThreads / kWave];
+  const u32 base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  u32 vals[kScanPer];
+  u32 local = 0;
+#pragma unroll
+  for (u32 i = 0; i < kScanPer; ++i) {
+    const u32 idx = base + i;
+    vals[i] = idx < count ? in[idx] : 0;
+    local += vals[i];
+  }
+  u32 tot;
+  const u32 incl = block_incl_scan(local, s_tmp, &tot);
+  u32 run = sums[blockIdx.x] + incl - local;
+#pragma unroll
+  for (u32 i = 0; i < kScanPer; ++i) {
+    const u32 idx = base + i;
+    if (idx < count) out[idx] = run;
+    run += vals[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = sums[gridDim.x];
+}
+
+void launch_scan(const u32* in, u32* out, u32 count, u32* tmp, hipStream_t s) {
+  const u32 nb = count ? cdiv(count, kScanChunk) : 1;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, count, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, in, out, count, tmp);
+}
+
+// ---- validator ------------------------------------------------------------------------
+// flag bits: 1 bad rowptr, 2 index out of range, 4 unsorted/duplicate, 8 self-loop,
+// 16 asymmetric.
+__global__ void k_validate_rowptr(const u32* __restrict__ rowptr, u32 n, u32 m,
+                                  u32* __restrict__ flag) {
+  const u32 tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0 && (rowptr[0] != 0 || rowptr[n] != m)) atomicOr(flag, 1u);
+  for (u32 v = tid; v < n; v += gridDim.x * blockDim.x)
+    if (rowptr[v + 1] < rowptr[v]) atomicOr(flag, 1u);
+}
+
+__device__ __forceinline__ bool sorted_contains(const u32* __restrict__ a, u32 len, u32 x) {
+  u32 lo = 0, hi = len;
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < len && a[lo] == x;
+}
+
+__global__ void __launch_bounds__(kTileThreads) k_validate_entries(
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+    const u32* __restrict__ tile_row, u32 n, u32 m, u32* __restrict__ flag) {
+  __shared__ u32 s_rp[kTileRowCap];
+  const u32 ntiles = (m + kTile - 1) / kTile;
+  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileInfo ti = tile_begin(rowptr, tile_row, t, m, s_rp);
+    for (u32 e = ti.e0 + threadIdx.x; e < ti.e1; e += blockDim.x) {
+      const u32 u = tile_row_of(ti, s_rp, rowptr, e);
+      const u32 v = colidx[e];
+      u32 bad = 0;
+      if (v >= n) {
+        bad |= 2u;
+      } else {
+        if (v == u) bad |= 8u;
+        if (e > rowptr[u] && colidx[e - 1] >= v) bad |= 4u;
+        if (!sorted_contains(colidx + rowptr[v], rowptr[v + 1] - rowptr[v], u)) bad |= 16u;
+      }
+      if (bad) atomicOr(flag, bad);
+    }
+    __syncthreads();
+  }
+}
+
+bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t s) {
+  const u32 g = min(cdiv(n + 1, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_validate_rowptr, dim3(g), dim3(256), 0, s, rowptr, n, m, flag);
+  u32 h = 0;
+  if (hipMemcpyAsync(&h, flag, sizeof(u32), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  return h == 0;
+}
+
+void launch_validate(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
+                     u32* flag, hipStream_t s) {
+  if (m == 0) return;
+  const u32 ntiles = cdiv(m, kTile);
+  const u32 g = min(ntiles, (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_validate_entries, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
+                     tile_row, n, m, flag);
+}
+
+}  // namespace tc

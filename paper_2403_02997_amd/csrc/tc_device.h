@@ -1,0 +1,302 @@
+// Device-side building blocks shared by the gfx950 kernels of the cover-edge
+// triangle-counting path: 64-lane wavefront primitives, the CSR tile-to-row lookup,
+// the per-vertex info byte, the LDS open-addressing hash set, and counter slots.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tc {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr u32 kInf = 0xFFFFFFFFu;  // unvisited level / empty hash slot
+constexpr int kCounterSlots = 256; // spread of the u64 result counters (contention)
+
+// ---- CSR tiles ------------------------------------------------------------------
+// Edge-parallel kernels split the m stored entries into tiles of kTile entries.
+// tile_row[t] is the row holding entry t * kTile (tile_row[ntiles] = row of entry m-1),
+// so the rows overlapping tile t are tile_row[t] .. tile_row[t+1].
+constexpr int kTile = 1024;
+constexpr int kTileThreads = 256;
+constexpr int kTileRowCap = 2048;  // rows of one tile staged in LDS
+
+// ---- wavefront primitives ----------------------------------------------------------
+__device__ __forceinline__ u32 lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` in lanes below this one (mbcnt).
+__device__ __forceinline__ u32 mask_rank(u64 mask) {
+  return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+}
+
+__device__ __forceinline__ u64 wave_sum_u64(u64 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ u32 wave_sum_u32(u32 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+__device__ __forceinline__ u32 wave_incl_scan(u32 v) {
+  const u32 lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    u32 t = __shfl_up(v, off, kWave);
+    if (lane >= (u32)off) v += t;
+  }
+  return v;
+}
+
+// Wave-aggregated append: every lane with `pred` gets a distinct slot of `*counter`.
+// Must be reached by all active lanes of the wavefront together.
+__device__ __forceinline__ u32 wave_append(u32* counter, bool pred) {
+  const u64 mask = __ballot(pred);
+  u32 base = 0;
+  if (mask) {
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    if ((int)lane_id() == leader) base = atomicAdd(counter, (u32)__popcll(mask));
+    base = __shfl(base, leader, kWave);
+  }
+  return base + mask_rank(mask);
+}
+
+// Relaxed agent-scope load: bypasses the non-coherent per-CU cache so that values
+// written by other workgroups during the same launch are observed.
+__device__ __forceinline__ u32 load_coherent(const u32* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- block-level inclusive scan (blockDim.x = kTileThreads) --------------------------
+// `s_tmp` holds at least kTileThreads / kWave entries.  Returns the inclusive prefix of
+// v over thread order; *total receives the block sum.
+__device__ __forceinline__ u32 block_incl_scan(u32 v, u32* s_tmp, u32* total) {
+  const u32 lane = lane_id(), wid = threadIdx.x / kWave;
+  const u32 nw = blockDim.x / kWave;
+  u32 x = wave_incl_scan(v);
+  if (lane == kWave - 1) s_tmp[wid] = x;
+  __syncthreads();
+  u32 add = 0, tot = 0;
+  for (u32 w = 0; w < nw; ++w) {
+    const u32 s = s_tmp[w];
+    if (w < wid) add += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return x + add;
+}
+
+// ---- per-vertex info byte ----------------------------------------------------------
+// bit 7: parity of the BFS level (L mod 2); bits 0..6: degree class, a monotone
+// quantised log2 of the degree (4 steps per octave).  Two adjacent vertices are on the
+// same level iff their parities agree, because a BFS edge joins levels that differ by
+// at most one.  Cover edges are oriented towards the endpoint with the larger
+// (degree class, vertex ID) key, whose neighbour list is the one staged in LDS.
+__device__ __forceinline__ u32 degree_class(u32 d) {
+  if (d == 0) return 0;
+  const u32 lg = 31u - (u32)__clz(d);
+  const u32 frac = lg >= 2 ? (d >> (lg - 2)) & 3u : ((d << (2 - lg)) & 3u);
+  const u32 c = 1u + 4u * lg + frac;
+  return c > 127u ? 127u : c;
+}
+
+__device__ __forceinline__ bool key_less(u32 cls_a, u32 a, u32 cls_b, u32 b) {
+  return cls_a < cls_b || (cls_a == cls_b && a < b);
+}
+
+// ---- tile lookup -------------------------------------------------------------------
+// Stage rowptr[r0 .. r1+1] of tile t in LDS.  Returns false (and stages nothing) when
+// the tile spans more than kTileRowCap rows (long runs of empty rows); callers then
+// fall back to a binary search in global memory.
+struct TileInfo {
+  u32 e0, e1;   // entries [e0, e1)
+  u32 r0, r1;   // rows r0 .. r1 overlap the tile
+  bool staged;
+};
+
+__device__ __forceinline__ TileInfo tile_begin(const u32* __restrict__ rowptr,
+                                               const u32* __restrict__ tile_row, u32 t,
+                                               u32 m, u32* s_rp) {
+  TileInfo ti;
+  ti.e0 = t * (u32)kTile;
+  ti.e1 = min(ti.e0 + (u32)kTile, m);
+  ti.r0 = tile_row[t];
+  ti.r1 = tile_row[t + 1];
+  const u32 nr = ti.r1 - ti.r0 + 2;  // rowptr entries r0 .. r1 + 1
+  ti.staged = nr <= (u32)kTileRowCap;
+  if (ti.staged)
+    for (u32 i = threadIdx.x; i < nr; i += blockDim.x) s_rp[i] = rowptr[ti.r0 + i];
+  __syncthreads();
+  return ti;
+}
+
+// Row of entry e (ti.e0 <= e < ti.e1): the largest r in [r0, r1] with rowptr[r] <= e.
+__device__ __forceinline__ u32 tile_row_of(const TileInfo& ti, const u32* s_rp,
+                                           const u32* __restrict__ rowptr, u32 e) {
+  u32 lo = 0, hi = ti.r1 - ti.r0;  // answer index in [lo, hi]
+  if (ti.staged) {
+    while (lo < hi) {
+      const u32 mid = (lo + hi + 1) >> 1;
+      if (s_rp[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+  } else {
+    while (lo < hi) {
+      const u32 mid = (lo + hi + 1) >> 1;
+      if (rowptr[ti.r0 + mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+  }
+  return ti.r0 + lo;
+}
+
+// Orders LDS accesses of one wavefront (writes by some lanes, reads by others).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Mask of a power-of-two hash table holding `keys` keys at load factor <= 1/2, at
+// least 64 and at most `cap` slots.
+__device__ __forceinline__ u32 table_mask(u32 keys, u32 cap) {
+  u32 want = keys * 2;
+  if (want < 64) want = 64;
+  const u32 p = 1u << (32 - __clz(want - 1));
+  return (p > cap ? cap : p) - 1;
+}
+
+// ---- LDS hash set of a neighbour list -----------------------------------------------
+// Open addressing with linear probing over a power-of-two table.  A key is a vertex ID
+// (< 2^31) with bit 31 set when the vertex is on the same BFS level as the list owner.
+// Knuth's multiplicative hash with the high half folded into the low bits, which the
+// power-of-two mask keeps.
+__device__ __forceinline__ u32 hash_mix(u32 w) {
+  const u32 h = w * 2654435761u;
+  return (h >> 16) ^ h;
+}
+
+__device__ __forceinline__ void hash_insert(u32* table, u32 mask, u32 key) {
+  const u32 w = key & 0x7FFFFFFFu;
+  u32 h = hash_mix(w) & mask;
+  while (true) {
+    const u32 old = atomicCAS(&table[h], kInf, key);
+    if (old == kInf) return;
+    h = (h + 1) & mask;
+  }
+}
+
+// Returns 0 when w is absent, 1 when present on another level, 2 when present on the
+// owner's level.
+__device__ __forceinline__ u32 hash_probe(const u32* table, u32 mask, u32 w) {
+  u32 h = hash_mix(w) & mask;
+  while (true) {
+    const u32 k = table[h];
+    if (k == kInf) return 0;
+    if ((k & 0x7FFFFFFFu) == w) return 1u + (k >> 31);
+    h = (h + 1) & mask;
+  }
+}
+
+// ---- union-find with smallest-ID roots ---------------------------------------------
+// parent[x] <= x always holds: links go from the larger root to the smaller one, so the
+// final root of a component is its smallest vertex ID.  Finds use path halving (both
+// ideas as in ECL-CC, Jaiganesh & Burtscher, HPDC 2018).
+__device__ __forceinline__ u32 cc_find(u32* parent, u32 x) {
+  while (true) {
+    const u32 p = load_coherent(&parent[x]);
+    if (p == x) return x;
+    const u32 gp = load_coherent(&parent[p]);
+    if (gp == p) return p;
+    parent[x] = gp;  // path halving: gp is an ancestor of x, gp <= p <= x
+    x = gp;
+  }
+}
+
+__device__ __forceinline__ void cc_union(u32* parent, u32 a, u32 b) {
+  while (true) {
+    a = cc_find(parent, a);
+    b = cc_find(parent, b);
+    if (a == b) return;
+    if (a < b) {
+      const u32 t = a; a = b; b = t;
+    }
+    // a > b: hang root a below b
+    const u32 old = atomicCAS(&parent[a], a, b);
+    if (old == a) return;
+    a = old;  // a was linked meanwhile; continue from its new parent
+  }
+}
+
+// ---- result counters ----------------------------------------------------------------
+// ctr[slot * 4 + {0,1,2,3}] = {c1, c2, c2 with w > max(u, v), cover-edge probes}.
+struct Counts {
+  u64 c1, c2, t2, probes;
+};
+
+// Tally one common neighbour w of the cover edge {x, y}: r = 1 when w is on another
+// level than x (c1), r = 2 on the same level (c2; counted into T only when w is larger
+// than both endpoints).  PV attributes each counted triangle to its three vertices.
+template <bool PV>
+__device__ __forceinline__ void count_hit(u32 r, u32 w, u32 x, u32 y, u32 vmax, Counts& c,
+                                          u64* tri) {
+  bool counted = false;
+  if (r == 1) {
+    c.c1 += 1;
+    counted = true;
+  } else if (r == 2) {
+    c.c2 += 1;
+    if (w > vmax) {
+      c.t2 += 1;
+      counted = true;
+    }
+  }
+  if (PV && counted) {
+    atomicAdd((unsigned long long*)&tri[x], 1ull);
+    atomicAdd((unsigned long long*)&tri[y], 1ull);
+    atomicAdd((unsigned long long*)&tri[w], 1ull);
+  }
+}
+
+// First index in [lo, hi) of the sorted array a with a[i] >= v.
+__device__ __forceinline__ u32 lower_bound_g(const u32* __restrict__ a, u32 lo, u32 hi, u32 v) {
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Block-wide reduction of the four counters followed by one atomic per counter into
+// the slot chosen by the block index.  `s_red` holds 4 * (blockDim.x / kWave) u64.
+__device__ __forceinline__ void block_flush_counts(Counts c, u64* __restrict__ ctr,
+                                                   u64* s_red) {
+  c.c1 = wave_sum_u64(c.c1);
+  c.c2 = wave_sum_u64(c.c2);
+  c.t2 = wave_sum_u64(c.t2);
+  c.probes = wave_sum_u64(c.probes);
+  const u32 wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (lane_id() == 0) {
+    s_red[wid * 4 + 0] = c.c1;
+    s_red[wid * 4 + 1] = c.c2;
+    s_red[wid * 4 + 2] = c.t2;
+    s_red[wid * 4 + 3] = c.probes;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    u64 s = 0;
+    for (u32 w = 0; w < nw; ++w) s += s_red[w * 4 + threadIdx.x];
+    if (s) atomicAdd((unsigned long long*)&ctr[(blockIdx.x % kCounterSlots) * 4 + threadIdx.x],
+                     (unsigned long long)s);
+  }
+}
+
+}  // namespace tc

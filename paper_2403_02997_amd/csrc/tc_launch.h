@@ -1,0 +1,100 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per step).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tc {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+// Control block of the level-synchronous BFS (device memory, zero-initialised).
+struct BfsCtl {
+  u32 qlen[2];      // frontier queue lengths, indexed by level parity
+  u32 mode;         // expansion mode of the next level: 0 top-down, 1 bottom-up
+  u32 done;         // set once a level produced an empty frontier
+  u32 depth;        // largest level assigned so far
+  u32 blocks_done;  // last-block detection
+  u32 bu_levels;    // levels expanded bottom-up
+  u32 num_roots;    // components (roots = smallest ID of each component)
+  u64 mf;           // sum of degrees of the frontier being built
+  u64 mu;           // sum of degrees of vertices not yet visited
+};
+
+// Intersection classes by degree of the staged endpoint x.
+struct IsectParams {
+  u32 lane_max;    // d(x) <= lane_max        : lane-per-cover-edge merge
+  u32 wave_max;    // d(x) <= wave_max        : wavefront per x, LDS hash
+  u32 chunk;       // block items hash at most `chunk` entries of N(x)
+  u32 seg;         // partners per block item
+};
+
+// Planning output (device), read back once by the host.
+struct Plan {
+  u32 num_wave_x;   // vertices of the wavefront class
+  u32 num_block_x;  // vertices of the block class
+  u32 num_items;    // block work items
+  u32 lane_edges;   // cover edges of the lane class
+  u32 next_wave;    // dynamic work counters
+  u32 next_item;
+  u32 pad[2];
+};
+
+struct Item {
+  u32 x, chunk, seg;
+};
+
+// ---- prep ----
+void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_t s);
+void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
+               u32* parent, hipStream_t s);
+void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, hipStream_t s);
+// Exclusive scan of in[0..count) into out[0..count] (out[count] = total); in may == out.
+// tmp needs scan_tmp_words(count) words.
+size_t scan_tmp_words(u32 count);
+void launch_scan(const u32* in, u32* out, u32 count, u32* tmp, hipStream_t s);
+void launch_validate(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
+                     u32* flag, hipStream_t s);
+bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t s);
+
+// ---- BFS ----
+void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
+                     BfsCtl* ctl, hipStream_t s);
+void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,
+                      u32* queue0, u32* queue1, BfsCtl* ctl, u32 grid, hipStream_t s);
+u32 bfs_grid(u32 n);
+
+// ---- cover-edge extraction ----
+void launch_extract_count(const u32* rowptr, const u32* colidx, const u32* tile_row,
+                          const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, hipStream_t s);
+void launch_extract_write(const u32* rowptr, const u32* colidx, const u32* tile_row,
+                          const uint8_t* vinfo, u32 n, u32 m, u32* hcur, u32* hadj,
+                          hipStream_t s);
+void launch_plan(const u32* rowptr, const u32* hoff, u32 n, IsectParams p, u32* wave_x,
+                 u32* block_x, u32* block_items, Plan* plan, hipStream_t s);
+void launch_fill_items(const u32* rowptr, const u32* hoff, const u32* block_x,
+                       const u32* item_off, u32 nbx, IsectParams p, Item* items,
+                       hipStream_t s);
+
+// ---- intersection ----
+void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
+                       const u32* hoff, const u32* hadj, const u32* htile_row, u32 n,
+                       u32 nS, IsectParams p, u64* ctr, u64* tri, hipStream_t s);
+void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
+                       const u32* hoff, const u32* hadj, const u32* wave_x, u32 nwx,
+                       Plan* plan, u64* ctr, u64* tri, hipStream_t s);
+void launch_isect_block(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
+                        const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
+                        IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
+void launch_finalize(const u64* ctr, u64* out4, hipStream_t s);
+
+// ---- batched, fused per-graph pipeline ----
+size_t batch_workspace_bytes(u32 num_graphs, u64 total_rows);
+void launch_batch(const u32* rowptr_cat, const u32* colidx_cat, const int64_t* row_off,
+                  const int64_t* col_off, u32 num_graphs, u64 total_rows, void* ws, u64* counts,
+                  hipStream_t s);
+
+int num_cus();
+
+}  // namespace tc

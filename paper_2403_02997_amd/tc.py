@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libtc.so (include/tc.h): argument marshalling only.
+
+Every step of the counting path runs in the library's gfx950 kernels.  PyTorch supplies
+device memory and streams: tensors are passed by ``data_ptr()`` and the stream by its
+HIP handle.  There is no CPU fallback: if the library is missing or cannot be loaded,
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_OK = 0
+STATUS = {
+    0: "TC_OK",
+    -1: "TC_ERR_INVALID_ARG",
+    -2: "TC_ERR_OUT_OF_MEMORY",
+    -3: "TC_ERR_HIP",
+    -4: "TC_ERR_INVALID_GRAPH",
+    -5: "TC_ERR_TOO_LARGE",
+    -6: "TC_ERR_INTERNAL",
+}
+
+# Every symbol include/tc.h declares.
+EXPORTS = (
+    "tc_count",
+    "tc_count_ex",
+    "tc_count_per_vertex",
+    "tc_count_batch",
+    "tc_count_batch_workspace_size",
+    "tc_validate_csr",
+    "tc_set_isect_params",
+    "tc_get_isect_params",
+    "tc_status_string",
+    "tc_version",
+)
+
+
+class TCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status_string(status)})")
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("triangles", ctypes.c_uint64),
+        ("c1", ctypes.c_uint64),
+        ("c2", ctypes.c_uint64),
+        ("cover_edges", ctypes.c_uint64),
+        ("probes", ctypes.c_uint64),
+        ("depth", ctypes.c_uint32),
+        ("num_roots", ctypes.c_uint32),
+        ("bfs_levels_bottom_up", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+@dataclass
+class Stats:
+    triangles: int
+    c1: int
+    c2: int
+    cover_edges: int
+    probes: int
+    depth: int
+    num_roots: int
+    bfs_levels_bottom_up: int
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libtc.so (built by ``paper_2403_02997_amd.build``).  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2403_02997_amd.build` "
+            "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    i = ctypes.c_int
+    lib.tc_count.argtypes = [vp, vp, u32, u64, vp, ctypes.POINTER(u64)]
+    lib.tc_count.restype = i
+    lib.tc_count_ex.argtypes = [vp, vp, u32, u64, vp, ctypes.POINTER(u64), vp,
+                                ctypes.POINTER(_Stats)]
+    lib.tc_count_ex.restype = i
+    lib.tc_count_per_vertex.argtypes = [vp, vp, u32, u64, vp, vp]
+    lib.tc_count_per_vertex.restype = i
+    lib.tc_count_batch.argtypes = [vp, vp, vp, vp, u32, u64, vp, sz, vp, vp]
+    lib.tc_count_batch.restype = i
+    lib.tc_count_batch_workspace_size.argtypes = [u32, u64]
+    lib.tc_count_batch_workspace_size.restype = sz
+    lib.tc_validate_csr.argtypes = [vp, vp, u32, u64, vp]
+    lib.tc_validate_csr.restype = i
+    lib.tc_set_isect_params.argtypes = [u32, u32, u32, u32]
+    lib.tc_set_isect_params.restype = i
+    lib.tc_get_isect_params.argtypes = [ctypes.POINTER(u32)]
+    lib.tc_get_isect_params.restype = i
+    lib.tc_status_string.argtypes = [i]
+    lib.tc_status_string.restype = ctypes.c_char_p
+    lib.tc_version.argtypes = []
+    lib.tc_version.restype = i
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().tc_status_string(int(status)).decode()
+    except Exception:  # noqa: BLE001 - only used while formatting another error
+        return "?"
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != TC_OK:
+        raise TCError(rc, where)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr() if t.numel() else 0
+
+
+def _n_m(rowptr: torch.Tensor, colidx: torch.Tensor):
+    if rowptr.element_size() != 4 or colidx.element_size() != 4:
+        raise TypeError("rowptr / colidx must hold 4-byte integers (uint32 bit patterns)")
+    n = rowptr.numel() - 1
+    if n < 0:
+        raise ValueError("rowptr needs n + 1 >= 1 entries")
+    return n, colidx.numel()
+
+
+# --------------------------------------------------------------------------------------
+# marshalling helpers
+# --------------------------------------------------------------------------------------
+
+def to_device(rowptr: np.ndarray, colidx: np.ndarray, device="cuda"):
+    """Upload a uint32 CSR as int32 tensors holding the same bit patterns."""
+    r = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.uint32).view(np.int32))
+    c = torch.from_numpy(np.ascontiguousarray(colidx, dtype=np.uint32).view(np.int32))
+    return r.to(device), c.to(device)
+
+
+# --------------------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# --------------------------------------------------------------------------------------
+
+def tc_count(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None) -> int:
+    """T for one graph (blocking)."""
+    lib = load()
+    n, m = _n_m(rowptr, colidx)
+    out = ctypes.c_uint64(0)
+    rc = lib.tc_count(_ptr(rowptr), _ptr(colidx), n, m, _stream_handle(stream),
+                      ctypes.byref(out))
+    _check(rc, "tc_count")
+    return int(out.value)
+
+
+def tc_count_ex(rowptr: torch.Tensor, colidx: torch.Tensor, want_levels: bool = False,
+                stream=None):
+    """(Stats, levels tensor or None)."""
+    lib = load()
+    n, m = _n_m(rowptr, colidx)
+    level = torch.empty(n, dtype=torch.int32, device=rowptr.device) if want_levels else None
+    st = _Stats()
+    cnt = ctypes.c_uint64(0)
+    rc = lib.tc_count_ex(_ptr(rowptr), _ptr(colidx), n, m, _stream_handle(stream),
+                         ctypes.byref(cnt), _ptr(level) if level is not None else None,
+                         ctypes.byref(st))
+    _check(rc, "tc_count_ex")
+    stats = Stats(int(st.triangles), int(st.c1), int(st.c2), int(st.cover_edges),
+                  int(st.probes), int(st.depth), int(st.num_roots),
+                  int(st.bfs_levels_bottom_up))
+    return stats, level
+
+
+def tc_count_per_vertex(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None) -> torch.Tensor:
+    """int64 tensor (uint64 bit patterns) of t(v), the triangles through each vertex."""
+    lib = load()
+    n, m = _n_m(rowptr, colidx)
+    out = torch.empty(max(n, 0), dtype=torch.int64, device=rowptr.device)
+    rc = lib.tc_count_per_vertex(_ptr(rowptr), _ptr(colidx), n, m, _stream_handle(stream),
+                                 _ptr(out) if n else None)
+    _check(rc, "tc_count_per_vertex")
+    return out
+
+
+def tc_count_batch_workspace_size(num_graphs: int, total_rows: int) -> int:
+    return int(load().tc_count_batch_workspace_size(int(num_graphs), int(total_rows)))
+
+
+def tc_count_batch(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor, row_off: torch.Tensor,
+                   col_off: torch.Tensor, total_rows: int | None = None,
+                   workspace: torch.Tensor | None = None, counts: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """Per-graph counts (int64 tensor of uint64 bit patterns) of a concatenated batch.
+    row_off / col_off are int64 device tensors of num_graphs + 1 offsets.  With a caller
+    workspace the call is asynchronous and capturable."""
+    lib = load()
+    if row_off.dtype != torch.int64 or col_off.dtype != torch.int64:
+        raise TypeError("row_off / col_off must be int64")
+    G = row_off.numel() - 1
+    if total_rows is None:
+        total_rows = rowptr_cat.numel()
+    if counts is None:
+        counts = torch.empty(max(G, 0), dtype=torch.int64, device=rowptr_cat.device)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    rc = lib.tc_count_batch(_ptr(rowptr_cat), _ptr(colidx_cat) or None, _ptr(row_off),
+                            _ptr(col_off), G, int(total_rows),
+                            _ptr(workspace) if workspace is not None else None, ws_bytes,
+                            _stream_handle(stream), _ptr(counts) if G else None)
+    _check(rc, "tc_count_batch")
+    return counts
+
+
+def tc_validate_csr(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None) -> int:
+    """Status of the device-side format check (TC_OK or TC_ERR_INVALID_GRAPH)."""
+    lib = load()
+    n, m = _n_m(rowptr, colidx)
+    return int(lib.tc_validate_csr(_ptr(rowptr), _ptr(colidx) or None, n, m,
+                                   _stream_handle(stream)))
+
+
+def tc_set_isect_params(lane_max: int, wave_max: int, chunk: int, seg: int) -> None:
+    _check(load().tc_set_isect_params(lane_max, wave_max, chunk, seg), "tc_set_isect_params")
+
+
+def tc_get_isect_params():
+    arr = (ctypes.c_uint32 * 4)()
+    _check(load().tc_get_isect_params(arr), "tc_get_isect_params")
+    return tuple(int(v) for v in arr)
+
+
+def tc_version() -> int:
+    return int(load().tc_version())
+
+
+def as_u64(t: torch.Tensor) -> np.ndarray:
+    """Host numpy uint64 view of an int64 tensor of uint64 bit patterns."""
+    return t.cpu().numpy().view(np.uint64)
