@@ -1,0 +1,344 @@
+#!/usr/bin/env python3
+"""Throughput of cover-edge triangle counting on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+
+One step is one whole tc_count call on a graph already resident in HBM: component
+roots, level BFS, cover-edge extraction, intersections and reduction, including the
+call's own workspace allocation (the paper charges auxiliary arrays to the algorithm).
+The timed region brackets exactly K steps with device synchronisations.  value =
+input edges (undirected, after cleaning) x K / elapsed seconds.
+
+Alongside, per JSON line:
+  roofline     : the dominant intersection kernel's algorithmic bytes per launch over its
+                 average launch time, from HIP events recorded by the library on the
+                 kernel's own stream during the timed steps, against 8 TB/s HBM; traffic
+                 is the counter-measured HBM bytes per launch stored under profiles/ when
+                 the kernel source still matches, else null.
+  cpu_baseline : the CPU oracle (CETC-SM, OpenMP) timed on this host on a bounded
+                 sample of the same graph, extrapolated in the oracle's merge work.
+
+Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, and batch4096
+(4096 uneven graphs: one captured tc_count_batch launch against 4096 tc_count calls).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "input edges/s for cover-edge TC (bit-exact u64), batched vs per-graph launch"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
+KERNEL_OF_STEP = {"isect_lane": "k_isect_lane", "isect_wave": "k_isect_wave",
+                  "isect_block": "k_isect_block"}
+
+WORKLOAD_TEXT = {
+    "rmat10": "R-MAT scale 10, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1000",
+    "rmat22": "R-MAT scale 22, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1001",
+    "grid4096": "triangulated 4096x4096 grid, 1% of edges deleted, seed 1002",
+    "er22": "Erdos-Renyi G(n=2^22, average degree 32), seed 1003",
+    "batch4096": "4096 graphs: half R-MAT (scale 8-16, edge factor 8-32), half Erdos-Renyi "
+                 "(n log-uniform in [2^8, 2^16], average degree 4-64), seed 1003",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("intersect.hip", "tc_device.h"):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+# ---- algorithmic bytes of the intersection classes ------------------------------------
+
+def degree_class(d: np.ndarray) -> np.ndarray:
+    """Monotone quantised log2 of the degree (4 steps per octave), 0 for d = 0."""
+    d = d.astype(np.int64)
+    out = np.zeros_like(d)
+    nz = d > 0
+    lg = np.floor(np.log2(d[nz])).astype(np.int64)
+    frac = np.where(lg >= 2, (d[nz] >> np.maximum(lg - 2, 0)) & 3, (d[nz] << (2 - np.minimum(lg, 2))) & 3)
+    out[nz] = np.minimum(1 + 4 * lg + frac, 127)
+    return out
+
+
+def class_bytes(g, level: np.ndarray, params) -> dict:
+    """Per intersection class: cover edges, 4 * sum over its cover edges of min(d(u), d(v))
+    (the shorter list streamed once) and 4 * sum of d(x) over its staged vertices x (each
+    staged list read once)."""
+    lane_max, wave_max = params[0], params[1]
+    d = g.degrees()
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), d)
+    cols = g.colidx.astype(np.int64)
+    par = (level & 1).astype(np.int8)
+    m = (par[rows] == par[cols]) & (rows < cols)
+    u, v = rows[m], cols[m]
+    del rows, cols, m
+    cls_d = degree_class(d)
+    key_u = cls_d[u] * (1 << 32) + u
+    key_v = cls_d[v] * (1 << 32) + v
+    x = np.where(key_u > key_v, u, v)
+    dx = d[x]
+    mn = np.minimum(d[u], d[v])
+    out = {}
+    for name, sel in (("isect_lane", dx <= lane_max),
+                      ("isect_wave", (dx > lane_max) & (dx <= wave_max)),
+                      ("isect_block", dx > wave_max)):
+        xs = np.unique(x[sel])
+        out[name] = {"cover_edges": int(sel.sum()),
+                     "bytes": 4 * int(mn[sel].sum()) + 4 * int(d[xs].sum())}
+    return out
+
+
+def stored_traffic(workload: str, kernel: str):
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload, {}).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+# ---- CPU baseline: the oracle on a bounded sample ----------------------------------------
+
+def cpu_baseline(g, target_s: float):
+    import oracle
+
+    t0 = time.perf_counter()
+    level, _ = oracle.bfs_levels(g)
+    t_bfs = time.perf_counter() - t0
+    d = g.degrees()
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), d)
+    cols = g.colidx.astype(np.int64)
+    m = (level[rows] == level[cols]) & (rows < cols)
+    work_u = np.bincount(rows[m], weights=(d[rows[m]] + d[cols[m]]).astype(np.float64),
+                         minlength=g.n)
+    del rows, cols, m
+    cum = np.cumsum(work_u)
+    W = float(cum[-1]) if g.n else 0.0
+    threads = oracle.max_threads()
+    if W == 0:
+        return None
+
+    def run(a, b):
+        t = time.perf_counter()
+        oracle.cetc_sm_range(g, level, a, b)
+        return time.perf_counter() - t
+
+    # calibrate on ~0.2 % of the merge work, then size the sample to ~target_s
+    b0 = int(np.searchsorted(cum, 0.002 * W)) + 1
+    t_cal = run(0, b0)
+    rate = (cum[b0 - 1] / max(t_cal, 1e-6))
+    want = min(W - cum[b0 - 1], rate * target_s)
+    b1 = int(np.searchsorted(cum, cum[b0 - 1] + want)) + 1
+    b1 = min(max(b1, b0 + 1), g.n)
+    t_s = run(b0, b1)
+    w_s = float(cum[b1 - 1] - cum[b0 - 1])
+    t_full = t_bfs + W * t_s / max(w_s, 1.0)
+    return {
+        "value": g.num_edges / t_full,
+        "unit": "input edges/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle BFS restart loop on the whole graph (1 thread, {t_bfs:.2f} s) + "
+                   f"CETC-SM edge loop over first endpoints [{b0}, {b1}) = "
+                   f"{100.0 * w_s / W:.1f}% of the merge work ({t_s:.2f} s, {threads} threads), "
+                   f"extrapolated linearly in merge work to {t_full:.1f} s for the whole graph"),
+    }
+
+
+# ---- single-graph workloads ----------------------------------------------------------------
+
+def bench_single(args, tcm, torch):
+    from tests.workloads import WORKLOADS
+
+    t = time.perf_counter()
+    g = WORKLOADS[args.workload]()
+    log(f"[bench] generated {args.workload}: n={g.n} input edges={g.num_edges} "
+        f"({time.perf_counter() - t:.1f}s)")
+    rp, ci = tcm.to_device(g.rowptr, g.colidx)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        tcm.tc_count(rp, ci)
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    tcm.tc_profile_read(reset=True)
+    tcm.tc_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = None
+    for _ in range(args.steps):
+        T = tcm.tc_count(rp, ci)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tcm.tc_profile_enable(False)
+    prof, calls = tcm.tc_profile_read(reset=True)
+    elapsed = t1 - t0
+    log(f"[bench] timed {args.steps} steps: {elapsed * 1e3 / args.steps:.3f} ms/step")
+
+    stats, level = tcm.tc_count_ex(rp, ci, want_levels=True)
+    assert stats.triangles == T
+    level_np = level.cpu().numpy().view(np.uint32)
+    params = tcm.tc_get_isect_params()
+    cb = class_bytes(g, level_np, params)
+    steps_ms = {k: v / max(calls, 1) for k, v in prof.items()}
+    isect = {k: steps_ms.get(k, 0.0) for k in KERNEL_OF_STEP}
+    dom = max(isect, key=isect.get)
+    dom_ms = isect[dom]
+    achieved = cb[dom]["bytes"] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(args.workload, KERNEL_OF_STEP[dom]),
+                "kernel": KERNEL_OF_STEP[dom], "avg_launch_ms": round(dom_ms, 4),
+                "algorithmic_bytes_per_launch": cb[dom]["bytes"]}
+    out = {
+        "metric": METRIC,
+        "value": g.num_edges * args.steps / elapsed,
+        "unit": "input edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": WORKLOAD_TEXT[args.workload],
+                   "n": g.n, "input_edges": g.num_edges, "triangles": T,
+                   "cover_edges": stats.cover_edges,
+                   "covering_ratio": round(stats.cover_edges / max(g.num_edges, 1), 4),
+                   "bfs_depth": stats.depth, "components": stats.num_roots,
+                   "isect_params": list(params)},
+        "triangles_per_s": T * args.steps / elapsed,
+        "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
+        "isect_classes": {k: {"cover_edges": v["cover_edges"],
+                              "algorithmic_bytes": v["bytes"]} for k, v in cb.items()},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    return out
+
+
+# ---- batched workload ------------------------------------------------------------------------
+
+def bench_batch(args, tcm, torch):
+    import graphgen as gg
+
+    t = time.perf_counter()
+    b = gg.make_batch(4096, gg.config_seed(3))
+    log(f"[bench] generated batch: {b.num_graphs} graphs, {b.total_edges} input edges "
+        f"({time.perf_counter() - t:.1f}s)")
+    rp, ci = tcm.to_device(b.rowptr_cat, b.colidx_cat)
+    ro = torch.from_numpy(b.row_off).cuda()
+    co = torch.from_numpy(b.col_off).cuda()
+    rows = int(b.rowptr_cat.shape[0])
+    ws = torch.empty(tcm.tc_count_batch_workspace_size(b.num_graphs, rows), dtype=torch.uint8,
+                     device="cuda")
+    counts = torch.zeros(b.num_graphs, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(args.warmup, 1)):
+            tcm.tc_count_batch(rp, ci, ro, co, total_rows=rows, workspace=ws, counts=counts)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tcm.tc_count_batch(rp, ci, ro, co, total_rows=rows, workspace=ws, counts=counts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    batched = tcm.as_u64(counts).copy()
+    log(f"[bench] batched: {t_batch * 1e3:.3f} ms per batch")
+
+    # the same graphs through one tc_count call each
+    dev = []
+    for i in range(b.num_graphs):
+        gi = b.graph(i)
+        dev.append(tcm.to_device(gi.rowptr, gi.colidx))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = np.array([tcm.tc_count(r, c) for r, c in dev], dtype=np.uint64)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    log(f"[bench] per-graph: {t_single * 1e3:.3f} ms for {b.num_graphs} calls")
+    assert np.array_equal(single, batched), "batched and per-graph counts differ"
+    return {
+        "metric": METRIC,
+        "value": b.total_edges / t_batch,
+        "unit": "input edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batch4096", "graph": WORKLOAD_TEXT["batch4096"],
+                   "num_graphs": b.num_graphs, "input_edges": b.total_edges,
+                   "triangles": int(batched.sum())},
+        "per_graph_launch": {"value": b.total_edges / t_single, "unit": "input edges/s",
+                             "ms_total": t_single * 1e3},
+        "batched_over_per_graph": t_single / t_batch,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the counting path here is single-GPU "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2403_02997_amd as tcm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    tcm.load()
+    if args.workload == "batch4096":
+        out = bench_batch(args, tcm, torch)
+    else:
+        out = bench_single(args, tcm, torch)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

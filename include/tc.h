@@ -65,6 +65,10 @@ typedef struct {
   uint32_t num_roots;     /* connected components (isolated vertices included)    */
   uint32_t bfs_levels_bottom_up; /* levels expanded bottom-up                      */
   uint32_t reserved;
+  /* per intersection class (0 lane merge, 1 wavefront, 2 workgroup): elements read from
+     the streamed partner lists, and elements of the staged lists N(x) */
+  uint64_t class_streamed[3];
+  uint64_t class_staged[3];
 } tc_stats;
 
 /*
@@ -143,6 +147,19 @@ int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, 
 int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, uint32_t seg);
 /* Current setting as {lane_max, wave_max, chunk, seg} into the HOST array out4[4]. */
 int tc_get_isect_params(uint32_t* out4);
+
+/*
+ * Step timing (diagnostics).  While enabled, tc_count / tc_count_ex /
+ * tc_count_per_vertex record HIP events on their stream at every step boundary and add
+ * each step's elapsed milliseconds to a process-wide accumulator.  tc_profile_read copies
+ * up to `cap` per-step totals into the HOST array ms_out, the number of profiled calls
+ * into *calls, optionally resets, and returns the number of steps; tc_profile_step_name
+ * names step i ("roots", "bfs", "extract", "plan", "isect_lane", "isect_block",
+ * "isect_wave", "reduce").
+ */
+int tc_profile_enable(int on);
+int tc_profile_read(double* ms_out, uint32_t cap, uint64_t* calls, int reset);
+const char* tc_profile_step_name(int step);
 
 /* Static description of a status code. */
 const char* tc_status_string(int status);

@@ -61,6 +61,9 @@ def _bind(lib):
     lib.orc_cetc_sm.argtypes = [vp, vp, u32, vp, ctypes.c_int, ctypes.POINTER(u64),
                                 ctypes.POINTER(u64)]
     lib.orc_cetc_sm.restype = u64
+    lib.orc_cetc_sm_range.argtypes = [vp, vp, u32, vp, u32, u32, ctypes.c_int,
+                                      ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.orc_cetc_sm_range.restype = u64
     lib.orc_cover_edges.argtypes = [vp, vp, u32, vp]
     lib.orc_cover_edges.restype = u64
     lib.orc_max_threads.restype = ctypes.c_int
@@ -171,6 +174,19 @@ def cetc_sm(g, level=None, nthreads: int = 0):
     c1, c2 = ctypes.c_uint64(0), ctypes.c_uint64(0)
     T = _load().orc_cetc_sm(rowptr.ctypes.data, colidx.ctypes.data, g.n, lv.ctypes.data,
                             int(nthreads), ctypes.byref(c1), ctypes.byref(c2))
+    return int(T), int(c1.value), int(c2.value)
+
+
+def cetc_sm_range(g, level, u_begin: int, u_end: int, nthreads: int = 0):
+    """CETC-SM restricted to first endpoints u in [u_begin, u_end): (T, c1, c2)."""
+    rowptr, colidx = _arrs(g)
+    lv = np.ascontiguousarray(level, dtype=np.uint32)
+    if lv.size == 0:
+        lv = np.zeros(1, np.uint32)
+    c1, c2 = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    T = _load().orc_cetc_sm_range(rowptr.ctypes.data, colidx.ctypes.data, g.n, lv.ctypes.data,
+                                  int(u_begin), int(u_end), int(nthreads), ctypes.byref(c1),
+                                  ctypes.byref(c2))
     return int(T), int(c1.value), int(c2.value)
 
 

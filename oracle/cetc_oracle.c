@@ -186,18 +186,22 @@ void orc_cetc_seq(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
 
 /*
  * CETC-SM (Section 4.4): the horizontal-edge loop run in parallel with OpenMP over the
- * first endpoint; for every common neighbour w, c1 counts w on another level and c2
- * counts w on the same level.  Returns T = c1 + c2 / 3 and writes c1, c2.
- * nthreads <= 0 uses the OpenMP default.
+ * first endpoint u; for every common neighbour w, c1 counts w on another level and c2
+ * counts w on the same level.  Only first endpoints u in [u_begin, u_end) are visited
+ * (the whole graph is [0, n)), which lets a caller time a bounded sample.  Writes c1, c2
+ * and returns T = c1 + c2 / 3 for the visited edges.  nthreads <= 0 uses the OpenMP
+ * default.
  */
-uint64_t orc_cetc_sm(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
-                     const uint32_t* level, int nthreads, uint64_t* c1_out, uint64_t* c2_out) {
+uint64_t orc_cetc_sm_range(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                           const uint32_t* level, uint32_t u_begin, uint32_t u_end,
+                           int nthreads, uint64_t* c1_out, uint64_t* c2_out) {
   uint64_t c1 = 0, c2 = 0;
+  if (u_end > n) u_end = n;
 #ifdef _OPENMP
   if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : c1, c2) num_threads(nthreads)
 #endif
-  for (int64_t uu = 0; uu < (int64_t)n; ++uu) {
+  for (int64_t uu = (int64_t)u_begin; uu < (int64_t)u_end; ++uu) {
     uint32_t u = (uint32_t)uu;
     for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
       uint32_t v = colidx[e];
@@ -220,6 +224,12 @@ uint64_t orc_cetc_sm(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
   if (c1_out) *c1_out = c1;
   if (c2_out) *c2_out = c2;
   return c1 + c2 / 3;
+}
+
+/* CETC-SM over the whole graph. */
+uint64_t orc_cetc_sm(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                     const uint32_t* level, int nthreads, uint64_t* c1_out, uint64_t* c2_out) {
+  return orc_cetc_sm_range(rowptr, colidx, n, level, 0, n, nthreads, c1_out, c2_out);
 }
 
 /* Threads the OpenMP runtime would use by default (1 without OpenMP). */

@@ -111,9 +111,55 @@ IsectParams default_params() {
 IsectParams g_params = default_params();
 
 struct RunOut {
-  u64 c[4];  // c1, c2, t2, probes
+  u64 c[kNumCtr];  // see kNumCtr: c1, c2, t2, streamed[3], staged[3]
   u64 cover_edges;
   BfsCtl ctl;
+};
+
+// ---- step timing (diagnostics) ----------------------------------------------------------
+// When enabled, the single-graph path records HIP events on its own stream at every step
+// boundary and accumulates the elapsed time of each step.
+enum Step { kStepRoots, kStepBfs, kStepExtract, kStepPlan, kStepLane, kStepBlock, kStepWave,
+            kStepReduce, kNumSteps };
+const char* kStepNames[kNumSteps] = {"roots", "bfs", "extract", "plan", "isect_lane",
+                                     "isect_block", "isect_wave", "reduce"};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+double g_prof_ms[kNumSteps];
+u64 g_prof_calls = 0;
+
+struct StepTimer {
+  bool on;
+  hipStream_t s;
+  hipEvent_t ev[kNumSteps + 1];
+  int next = 0;
+  StepTimer(hipStream_t st) : s(st) {
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      on = g_prof_on;
+    }
+    if (on)
+      for (int i = 0; i <= kNumSteps; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) on = false;
+  }
+  // Marks the end of the previous step (and the start of the next one).
+  void mark() {
+    if (on && next <= kNumSteps) hipEventRecord(ev[next++], s);
+  }
+  // Called after the stream has been synchronised.
+  void collect() {
+    if (!on || next != kNumSteps + 1) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int i = 0; i < kNumSteps; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) g_prof_ms[i] += ms;
+    }
+    g_prof_calls += 1;
+  }
+  ~StepTimer() {
+    if (on)
+      for (int i = 0; i <= kNumSteps; ++i) hipEventDestroy(ev[i]);
+  }
 };
 
 // The whole single-graph pipeline.  `level_out` (device) may be null; `tri` (device,
@@ -145,8 +191,8 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u32>((size_t)n + 1);      // block items / offsets
     c.take<BfsCtl>(1);
     c.take<Plan>(1);
-    c.take<u64>(kCounterSlots * 4);
-    c.take<u64>(4);
+    c.take<u64>(kCounterSlots * kNumCtr);
+    c.take<u64>(kNumCtr);
     bytes = c.off + 256;
   }
   DevAlloc ws;
@@ -170,21 +216,24 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   // control block: ctl, plan, counters, result are contiguous and cleared together
   BfsCtl* ctl = c.take<BfsCtl>(1);
   Plan* plan = c.take<Plan>(1);
-  u64* ctr = c.take<u64>(kCounterSlots * 4);
-  u64* out4 = c.take<u64>(4);
-  const size_t ctl_bytes = (char*)(out4 + 4) - (char*)ctl;
+  u64* ctr = c.take<u64>(kCounterSlots * kNumCtr);
+  u64* outc = c.take<u64>(kNumCtr);
+  const size_t ctl_bytes = (char*)(outc + kNumCtr) - (char*)ctl;
   if (level_out) level = level_out;
 
   TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
   TC_HIP(hipMemsetAsync(hoff, 0, sizeof(u32) * ((size_t)n + 1), s));
   TC_HIP(hipMemsetAsync(bitems, 0, sizeof(u32) * ((size_t)n + 1), s));
+  StepTimer timer(s);
 
   // ---- a1: component roots ----
+  timer.mark();
   launch_tile_rows(rowptr, n, m, tile_row, s);
   launch_cc(rowptr, colidx, tile_row, n, m, parent, s);
   TC_LAUNCHED();
 
   // ---- a2: level BFS ----
+  timer.mark();
   launch_bfs_init(rowptr, parent, n, level, q0, ctl, s);
   TC_LAUNCHED();
   {
@@ -202,6 +251,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
       batch = batch < 64 ? batch * 2 : 64;
     }
   }
+  timer.mark();
   launch_vinfo(rowptr, level, n, vinfo, s);
 
   // ---- a3: cover-edge extraction ----
@@ -209,6 +259,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   launch_scan(hoff, hoff, n, scan_tmp, s);
   TC_HIP(hipMemcpyAsync(hcur, hoff, sizeof(u32) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
   launch_extract_write(rowptr, colidx, tile_row, vinfo, n, m, hcur, hadj, s);
+  timer.mark();
   launch_plan(rowptr, hoff, n, prm, wave_x, block_x, bitems, plan, s);
   launch_scan(bitems, bitems, n, scan_tmp, s);
   TC_LAUNCHED();
@@ -229,18 +280,23 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     items = (Item*)items_mem.p;
     launch_fill_items(rowptr, hoff, block_x, bitems, h_plan.num_block_x, prm, items, s);
   }
-  if (h_plan.lane_edges) {
-    launch_tile_rows(hoff, n, h_ns, htile_row, s);
+  if (h_plan.lane_edges) launch_tile_rows(hoff, n, h_ns, htile_row, s);
+  timer.mark();
+  if (h_plan.lane_edges)
     launch_isect_lane(rowptr, colidx, vinfo, hoff, hadj, htile_row, n, h_ns, prm, ctr, tri, s);
-  }
+  timer.mark();
   launch_isect_block(rowptr, colidx, vinfo, hoff, hadj, items, h_items, prm, plan, ctr, tri, s);
+  timer.mark();
   launch_isect_wave(rowptr, colidx, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan, ctr, tri, s);
+  timer.mark();
   // ---- a5: reduction ----
-  launch_finalize(ctr, out4, s);
+  launch_finalize(ctr, outc, s);
+  timer.mark();
   TC_LAUNCHED();
-  TC_HIP(hipMemcpyAsync(out->c, out4, sizeof(u64) * 4, hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(out->c, outc, sizeof(u64) * kNumCtr, hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&out->ctl, ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  timer.collect();
   out->cover_edges = h_ns;
   // Two independent tallies of the same-level apexes must agree (CETC-SM: c2 / 3).
   if (out->c[1] % 3 != 0 || out->c[1] / 3 != out->c[2]) return TC_ERR_INTERNAL;
@@ -298,7 +354,11 @@ int tc_count_ex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint
     st.c1 = ro.c[0];
     st.c2 = ro.c[1];
     st.triangles = ro.c[0] + ro.c[2];
-    st.probes = ro.c[3];
+    st.probes = ro.c[3] + ro.c[4] + ro.c[5];
+    for (int i = 0; i < 3; ++i) {
+      st.class_streamed[i] = ro.c[3 + i];
+      st.class_staged[i] = ro.c[6 + i];
+    }
     st.cover_edges = ro.cover_edges;
     st.depth = ro.ctl.depth;
     st.num_roots = ro.ctl.num_roots;
@@ -399,6 +459,28 @@ int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, ui
   g_params.chunk = chunk;
   g_params.seg = seg;
   return TC_OK;
+}
+
+int tc_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return TC_OK;
+}
+
+int tc_profile_read(double* ms_out, uint32_t cap, uint64_t* calls, int reset) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (ms_out)
+    for (uint32_t i = 0; i < cap && i < (uint32_t)kNumSteps; ++i) ms_out[i] = g_prof_ms[i];
+  if (calls) *calls = g_prof_calls;
+  if (reset) {
+    for (int i = 0; i < kNumSteps; ++i) g_prof_ms[i] = 0.0;
+    g_prof_calls = 0;
+  }
+  return kNumSteps;
+}
+
+const char* tc_profile_step_name(int step) {
+  return step >= 0 && step < kNumSteps ? kStepNames[step] : "";
 }
 
 int tc_get_isect_params(uint32_t* out4) {

@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
     __syncthreads();
 
     // ---- 4a. staged vertices of short lists: one wavefront each ----
-    Counts c{0, 0, 0, 0};
+    Counts c{0, 0, 0, 0, 0};
     {
       u32* table = s_tab + wid * kBWSlots;
       u32* plist = s_plist[wid];

@@ -35,8 +35,8 @@ __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
     const u32* __restrict__ htile_row, u32 nS, u32 lane_max, u64* __restrict__ ctr,
     u64* __restrict__ tri) {
   __shared__ u32 s_rp[kTileRowCap];
-  __shared__ u64 s_red[4 * (kTileThreads / kWave)];
-  Counts c{0, 0, 0, 0};
+  __shared__ u64 s_red[5 * (kTileThreads / kWave)];
+  Counts c{0, 0, 0, 0, 0};
   const u32 ntiles = (nS + kTile - 1) / kTile;
   for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TileInfo ti = tile_begin(hoff, htile_row, t, nS, s_rp);
@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
       u32 j = rowptr[y];
       const u32 je = rowptr[y + 1];
       c.probes += je - j;
+      c.staged += ie - i;
       const u32 px = vinfo[x] & 0x80u;
       const u32 vmax = max(x, y);
       if (i < ie && j < je) {
@@ -72,7 +73,7 @@ __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
     }
     __syncthreads();
   }
-  block_flush_counts(c, ctr, s_red);
+  block_flush_counts(c, 0, ctr, s_red);
 }
 
 // ---- wave class: one wavefront per staged vertex x ---------------------------------------
@@ -87,10 +88,10 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
   __shared__ u32 s_incl[kW][kWave];
   __shared__ u32 s_start[kW][kWave];
   __shared__ u32 s_y[kW][kWave];
-  __shared__ u64 s_red[4 * kW];
+  __shared__ u64 s_red[5 * kW];
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   u32* table = s_table[wid];
-  Counts c{0, 0, 0, 0};
+  Counts c{0, 0, 0, 0, 0};
   while (true) {
     u32 idx = 0;
     if (lane == 0) idx = atomicAdd(&plan->next_wave, 1u);
@@ -100,6 +101,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
     const u32 px = vinfo[x] & 0x80u;
     const u32 mask = table_mask(dx, kWaveSlots);
+    c.staged += lane == 0 ? dx : 0;
     for (u32 i = lane; i <= mask; i += kWave) table[i] = kInf;
     wave_lds_sync();
     for (u32 i = lane; i < dx; i += kWave) {
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
       wave_lds_sync();
     }
   }
-  block_flush_counts(c, ctr, s_red);
+  block_flush_counts(c, 1, ctr, s_red);
 }
 
 // ---- block class: one workgroup per (x, chunk, partner segment) ------------------------
@@ -172,9 +174,9 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_block(
   __shared__ u32 s_start[kIsectThreads];
   __shared__ u32 s_y[kIsectThreads];
   __shared__ u32 s_tmp[kIsectThreads / kWave];
-  __shared__ u64 s_red[4 * (kIsectThreads / kWave)];
+  __shared__ u64 s_red[5 * (kIsectThreads / kWave)];
   __shared__ u32 s_item;
-  Counts c{0, 0, 0, 0};
+  Counts c{0, 0, 0, 0, 0};
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(&plan->next_item, 1u);
     __syncthreads();
@@ -188,6 +190,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_block(
     const u32 clen = min(prm.chunk, dx - c0);
     const bool chunked = dx > prm.chunk;
     const u32 mask = table_mask(clen, kBlockSlots);
+    c.staged += threadIdx.x == 0 ? clen : 0;
     for (u32 i = threadIdx.x; i <= mask; i += blockDim.x) s_table[i] = kInf;
     __syncthreads();
     for (u32 i = threadIdx.x; i < clen; i += blockDim.x) {
@@ -247,15 +250,15 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_block(
     }
     __syncthreads();
   }
-  block_flush_counts(c, ctr, s_red);
+  block_flush_counts(c, 2, ctr, s_red);
 }
 
-__global__ void k_finalize(const u64* __restrict__ ctr, u64* __restrict__ out4) {
+__global__ void k_finalize(const u64* __restrict__ ctr, u64* __restrict__ out) {
   const u32 k = threadIdx.x;
-  if (k < 4) {
+  if (k < (u32)kNumCtr) {
     u64 s = 0;
-    for (int i = 0; i < kCounterSlots; ++i) s += ctr[i * 4 + k];
-    out4[k] = s;
+    for (int i = 0; i < kCounterSlots; ++i) s += ctr[i * kNumCtr + k];
+    out[k] = s;
   }
 }
 
@@ -301,8 +304,8 @@ void launch_isect_block(const u32* rowptr, const u32* colidx, const uint8_t* vin
                        vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri);
 }
 
-void launch_finalize(const u64* ctr, u64* out4, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, ctr, out4);
+void launch_finalize(const u64* ctr, u64* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, ctr, out);
 }
 
 }  // namespace tc

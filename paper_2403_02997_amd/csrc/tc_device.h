@@ -236,9 +236,13 @@ __device__ __forceinline__ void cc_union(u32* parent, u32 a, u32 b) {
 }
 
 // ---- result counters ----------------------------------------------------------------
-// ctr[slot * 4 + {0,1,2,3}] = {c1, c2, c2 with w > max(u, v), cover-edge probes}.
+// ctr[slot * kNumCtr + i]: i = 0 c1, 1 c2, 2 t2 (same-level apex with w > max(u, v)),
+// 3 + cls: elements streamed from partner lists, 6 + cls: elements of N(x) staged or
+// merged, for cls = 0 lane, 1 wavefront, 2 workgroup class.
+constexpr int kNumCtr = 10;
+
 struct Counts {
-  u64 c1, c2, t2, probes;
+  u64 c1, c2, t2, probes, staged;
 };
 
 // Tally one common neighbour w of the cover edge {x, y}: r = 1 when w is on another
@@ -275,26 +279,23 @@ __device__ __forceinline__ u32 lower_bound_g(const u32* __restrict__ a, u32 lo, 
   return lo;
 }
 
-// Block-wide reduction of the four counters followed by one atomic per counter into
-// the slot chosen by the block index.  `s_red` holds 4 * (blockDim.x / kWave) u64.
-__device__ __forceinline__ void block_flush_counts(Counts c, u64* __restrict__ ctr,
+// Block-wide reduction of the counters followed by one atomic per counter into the
+// slot chosen by the block index.  `s_red` holds 5 * (blockDim.x / kWave) u64.
+__device__ __forceinline__ void block_flush_counts(Counts c, int cls, u64* __restrict__ ctr,
                                                    u64* s_red) {
-  c.c1 = wave_sum_u64(c.c1);
-  c.c2 = wave_sum_u64(c.c2);
-  c.t2 = wave_sum_u64(c.t2);
-  c.probes = wave_sum_u64(c.probes);
+  u64 v[5] = {c.c1, c.c2, c.t2, c.probes, c.staged};
   const u32 wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  if (lane_id() == 0) {
-    s_red[wid * 4 + 0] = c.c1;
-    s_red[wid * 4 + 1] = c.c2;
-    s_red[wid * 4 + 2] = c.t2;
-    s_red[wid * 4 + 3] = c.probes;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    v[i] = wave_sum_u64(v[i]);
+    if (lane_id() == 0) s_red[wid * 5 + i] = v[i];
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     u64 s = 0;
-    for (u32 w = 0; w < nw; ++w) s += s_red[w * 4 + threadIdx.x];
-    if (s) atomicAdd((unsigned long long*)&ctr[(blockIdx.x % kCounterSlots) * 4 + threadIdx.x],
+    for (u32 w = 0; w < nw; ++w) s += s_red[w * 5 + threadIdx.x];
+    const int idx = threadIdx.x < 3 ? (int)threadIdx.x : (threadIdx.x == 3 ? 3 + cls : 6 + cls);
+    if (s) atomicAdd((unsigned long long*)&ctr[(blockIdx.x % kCounterSlots) * kNumCtr + idx],
                      (unsigned long long)s);
   }
 }

@@ -87,7 +87,7 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinf
 void launch_isect_block(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
                         const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
-void launch_finalize(const u64* ctr, u64* out4, hipStream_t s);
+void launch_finalize(const u64* ctr, u64* out, hipStream_t s);
 
 // ---- batched, fused per-graph pipeline ----
 size_t batch_workspace_bytes(u32 num_graphs, u64 total_rows);

@@ -38,6 +38,9 @@ EXPORTS = (
     "tc_validate_csr",
     "tc_set_isect_params",
     "tc_get_isect_params",
+    "tc_profile_enable",
+    "tc_profile_read",
+    "tc_profile_step_name",
     "tc_status_string",
     "tc_version",
 )
@@ -60,6 +63,8 @@ class _Stats(ctypes.Structure):
         ("num_roots", ctypes.c_uint32),
         ("bfs_levels_bottom_up", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("class_streamed", ctypes.c_uint64 * 3),
+        ("class_staged", ctypes.c_uint64 * 3),
     ]
 
 
@@ -73,6 +78,8 @@ class Stats:
     depth: int
     num_roots: int
     bfs_levels_bottom_up: int
+    class_streamed: tuple = (0, 0, 0)
+    class_staged: tuple = (0, 0, 0)
 
 
 _lib = None
@@ -107,6 +114,12 @@ def load() -> ctypes.CDLL:
     lib.tc_set_isect_params.restype = i
     lib.tc_get_isect_params.argtypes = [ctypes.POINTER(u32)]
     lib.tc_get_isect_params.restype = i
+    lib.tc_profile_enable.argtypes = [i]
+    lib.tc_profile_enable.restype = i
+    lib.tc_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), u32, ctypes.POINTER(u64), i]
+    lib.tc_profile_read.restype = i
+    lib.tc_profile_step_name.argtypes = [i]
+    lib.tc_profile_step_name.restype = ctypes.c_char_p
     lib.tc_status_string.argtypes = [i]
     lib.tc_status_string.restype = ctypes.c_char_p
     lib.tc_version.argtypes = []
@@ -194,7 +207,8 @@ def tc_count_ex(rowptr: torch.Tensor, colidx: torch.Tensor, want_levels: bool = 
     _check(rc, "tc_count_ex")
     stats = Stats(int(st.triangles), int(st.c1), int(st.c2), int(st.cover_edges),
                   int(st.probes), int(st.depth), int(st.num_roots),
-                  int(st.bfs_levels_bottom_up))
+                  int(st.bfs_levels_bottom_up), tuple(int(v) for v in st.class_streamed),
+                  tuple(int(v) for v in st.class_staged))
     return stats, level
 
 
@@ -253,6 +267,24 @@ def tc_get_isect_params():
     arr = (ctypes.c_uint32 * 4)()
     _check(load().tc_get_isect_params(arr), "tc_get_isect_params")
     return tuple(int(v) for v in arr)
+
+
+def tc_profile_enable(on: bool = True) -> None:
+    load().tc_profile_enable(1 if on else 0)
+
+
+def tc_profile_read(reset: bool = False):
+    """({step name: total ms}, number of profiled calls)."""
+    lib = load()
+    ms = (ctypes.c_double * 16)()
+    calls = ctypes.c_uint64(0)
+    k = lib.tc_profile_read(ms, 16, ctypes.byref(calls), 1 if reset else 0)
+    names = [lib.tc_profile_step_name(i).decode() for i in range(k)]
+    return {names[i]: float(ms[i]) for i in range(k)}, int(calls.value)
+
+
+def tc_profile_step_name(step: int) -> str:
+    return load().tc_profile_step_name(int(step)).decode()
 
 
 def tc_version() -> int:

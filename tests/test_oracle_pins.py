@@ -235,3 +235,14 @@ def test_check_csr_rejects_bad_input():
     bad = gg.CSR(g.rowptr.copy(), g.colidx.copy())
     bad.rowptr[-1] += 1
     assert oracle.check_csr(bad) == -1
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sm_range_partitions_the_edge_loop(seed):
+    g = gg.rmat(11, 16, 300 + seed)
+    level, _ = oracle.bfs_levels(g)
+    T, c1, c2 = oracle.cetc_sm(g, level)
+    cut = [0, g.n // 3, g.n // 2, g.n]
+    parts = [oracle.cetc_sm_range(g, level, a, b) for a, b in zip(cut[:-1], cut[1:])]
+    assert sum(p[1] for p in parts) == c1 and sum(p[2] for p in parts) == c2
+    assert T == pins.sparse_count(g)
