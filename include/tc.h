@@ -140,7 +140,7 @@ int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, 
  * Intersection tuning (used by the autotuner).  The staged endpoint x of a cover edge
  * goes to the lane class when d(x) <= lane_max, to the wavefront class when
  * d(x) <= wave_max (<= 512), else to the workgroup class, which stages N(x) in chunks
- * of `chunk` (<= 4096) entries and `seg` (<= 256) partners per work item.  The setting
+ * of `chunk` (<= 16384) entries and takes `seg` (<= 1024) partners per work item.  The setting
  * is process-wide; change it only while no count is running.  Out-of-range values give
  * TC_ERR_INVALID_ARG and leave the setting unchanged.
  */

@@ -103,8 +103,8 @@ IsectParams default_params() {
   IsectParams p;
   p.lane_max = 16;
   p.wave_max = 512;
-  p.chunk = 4096;
-  p.seg = 256;
+  p.chunk = 16384;
+  p.seg = 1024;
   return p;
 }
 
@@ -285,7 +285,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   if (h_plan.lane_edges)
     launch_isect_lane(rowptr, colidx, vinfo, hoff, hadj, htile_row, n, h_ns, prm, ctr, tri, s);
   timer.mark();
-  launch_isect_block(rowptr, colidx, vinfo, hoff, hadj, items, h_items, prm, plan, ctr, tri, s);
+  launch_isect_block(rowptr, colidx, m, vinfo, hoff, hadj, items, h_items, prm, plan, ctr, tri, s);
   timer.mark();
   launch_isect_wave(rowptr, colidx, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan, ctr, tri, s);
   timer.mark();
@@ -451,8 +451,8 @@ int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
 // Intersection class thresholds (used by the autotuner).  Returns TC_ERR_INVALID_ARG for
 // values outside the ranges the LDS tables are sized for.
 int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, uint32_t seg) {
-  if (wave_max > 512 || lane_max > wave_max || chunk == 0 || chunk > 4096 || seg == 0 ||
-      seg > 256)
+  if (wave_max > 512 || lane_max > wave_max || chunk == 0 || chunk > 16384 || seg == 0 ||
+      seg > 1024)
     return TC_ERR_INVALID_ARG;
   g_params.lane_max = lane_max;
   g_params.wave_max = wave_max;

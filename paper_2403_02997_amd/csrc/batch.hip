@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
     const u32* __restrict__ order, BatchCtl* __restrict__ ctl, u32* __restrict__ parent_all,
     u32* __restrict__ level_all, u32* __restrict__ queue_all, uint8_t* __restrict__ vinfo_all,
     u64* __restrict__ counts) {
-  __shared__ u32 s_tab[kBBSlots];  // 4 wavefront tables, or one workgroup table
+  __shared__ __align__(16) u32 s_tab[kBBSlots];  // 4 wavefront tables, or one workgroup table
   __shared__ u32 s_plist[kBW][kBSmallMax];
   __shared__ u32 s_incl[kBT], s_start[kBT], s_y[kBT];
   __shared__ u32 s_tmp[kBW];
@@ -224,8 +224,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
         const u32 bx = rp[x], dx = rp[x + 1] - bx;
         if (dx < 2 || dx > kBSmallMax) continue;
         const u32 vx = vinfo[x], px = vx & 0x80u, cx = vx & 127u;
-        const u32 mask = table_mask(dx, kBWSlots);
-        for (u32 i = lane; i <= mask; i += kWave) table[i] = kInf;
+        const u32 mask = bucket_mask(dx, kBWSlots);
+        for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
         wave_lds_sync();
         u32 np = 0;
         for (u32 i0 = 0; i0 < dx; i0 += kWave) {
@@ -309,8 +309,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
         const u32 nch = (dx + kBChunk - 1) / kBChunk;
         for (u32 ch = 0; ch < nch; ++ch) {
           const u32 c0 = ch * kBChunk, clen = min(kBChunk, dx - c0);
-          const u32 mask = table_mask(clen, kBBSlots);
-          for (u32 i = threadIdx.x; i <= mask; i += kBT) s_tab[i] = kInf;
+          const u32 mask = bucket_mask(clen, kBBSlots);
+          for (u32 i = threadIdx.x; i < (mask + 1) * 4; i += kBT) s_tab[i] = kInf;
           __syncthreads();
           for (u32 i = threadIdx.x; i < clen; i += kBT) {
             const u32 w = ci[bx + c0 + i];

@@ -199,9 +199,7 @@ __global__ void k_plan(const u32* __restrict__ rowptr, const u32* __restrict__ h
     const u32 pb = wave_append(&plan->num_block_x, is_block);
     if (is_block) {
       block_x[pb] = x;
-      const u32 nch = (d + p.chunk - 1) / p.chunk;
-      const u32 nsg = (np + p.seg - 1) / p.seg;
-      block_items[pb] = nch * nsg;
+      block_items[pb] = (np + p.seg - 1) / p.seg;
     }
   }
   lane_edges = wave_sum_u32(lane_edges);
@@ -221,13 +219,10 @@ __global__ void k_fill_items(const u32* __restrict__ rowptr, const u32* __restri
                              u32 nbx, IsectParams p, Item* __restrict__ items) {
   for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < nbx; j += gridDim.x * blockDim.x) {
     const u32 x = block_x[j];
-    const u32 d = rowptr[x + 1] - rowptr[x];
     const u32 np = hoff[x + 1] - hoff[x];
-    const u32 nch = (d + p.chunk - 1) / p.chunk;
     const u32 nsg = (np + p.seg - 1) / p.seg;
     u32 o = item_off[j];
-    for (u32 c = 0; c < nch; ++c)
-      for (u32 sg = 0; sg < nsg; ++sg) items[o++] = Item{x, c, sg};
+    for (u32 sg = 0; sg < nsg; ++sg) items[o++] = Item{x, sg};
   }
 }
 

@@ -13,8 +13,8 @@
 //   wave  : d(x) <= wave_max — one wavefront per x stages N(x) in an LDS hash set and
 //           streams the concatenated partner lists, 64 lanes wide.
 //   block : larger — one workgroup per (x, chunk of N(x), segment of partners); the
-//           chunk goes into a 32 KB LDS hash set, each partner list is cut to the
-//           chunk's ID range by binary search and streamed by all 256 threads.
+//           chunk goes into a 128 KB LDS hash set and each wavefront streams one
+//           partner list at a time with 16-byte loads.
 #include "tc_device.h"
 #include "tc_launch.h"
 
@@ -23,7 +23,6 @@ namespace tc {
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
 constexpr int kWaveSlots = 1024;   // LDS hash slots per wavefront (d(x) <= 512)
-constexpr int kBlockSlots = 8192;  // LDS hash slots per workgroup (chunk <= 4096)
 constexpr int kIsectThreads = 256;
 constexpr int kUnroll = 4;         // independent list loads in flight per lane
 
@@ -84,7 +83,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     const u32* __restrict__ wave_x, u32 nwx, Plan* __restrict__ plan, u64* __restrict__ ctr,
     u64* __restrict__ tri) {
   constexpr int kW = kIsectThreads / kWave;
-  __shared__ u32 s_table[kW][kWaveSlots];
+  __shared__ __align__(16) u32 s_table[kW][kWaveSlots];
   __shared__ u32 s_incl[kW][kWave];
   __shared__ u32 s_start[kW][kWave];
   __shared__ u32 s_y[kW][kWave];
@@ -100,9 +99,9 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     const u32 x = wave_x[idx];
     const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
     const u32 px = vinfo[x] & 0x80u;
-    const u32 mask = table_mask(dx, kWaveSlots);
+    const u32 mask = bucket_mask(dx, kWaveSlots);
     c.staged += lane == 0 ? dx : 0;
-    for (u32 i = lane; i <= mask; i += kWave) table[i] = kInf;
+    for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
     wave_lds_sync();
     for (u32 i = lane; i < dx; i += kWave) {
       const u32 w = colidx[bx + i];
@@ -119,66 +118,76 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
         sy = rowptr[y];
         dy = rowptr[y + 1] - sy;
       }
-      c.probes += dy;
       const u32 incl = wave_incl_scan(dy);
       const u32 total = __shfl(incl, kWave - 1, kWave);
       s_incl[wid][lane] = incl;
       s_start[wid][lane] = sy - (incl - dy);  // element k of partner l sits at start + k
       s_y[wid][lane] = y;
       wave_lds_sync();
+      Tally tl{0, 0, 0, 0};
       for (u32 k0 = 0; k0 < total; k0 += kWave * kUnroll) {
         u32 ws[kUnroll], ls[kUnroll];
+        bool ok[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const u32 k = k0 + u * kWave + lane;
-          ls[u] = kInf;
-          if (k < total) {
-            // partner l: smallest l with incl[l] > k
-            u32 lo = 0, hi = kWave - 1;
-            while (lo < hi) {
-              const u32 mid = (lo + hi) >> 1;
-              if (s_incl[wid][mid] > k) hi = mid;
-              else lo = mid + 1;
-            }
-            ls[u] = lo;
-            ws[u] = colidx[s_start[wid][lo] + k];
+          ok[u] = k < total;
+          // partner l: smallest l with incl[l] > k
+          u32 lo = 0, hi = kWave - 1;
+          while (lo < hi) {
+            const u32 mid = (lo + hi) >> 1;
+            if (s_incl[wid][mid] > k) hi = mid;
+            else lo = mid + 1;
           }
+          ls[u] = lo;
+          ws[u] = ok[u] ? colidx[s_start[wid][lo] + k] : kInf;
         }
+        u32 res[kUnroll];
+        hash_probe_n<kUnroll>(table, mask, ws, ok, res);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (ls[u] != kInf) {
-            const u32 w = ws[u];
-            const u32 r = hash_probe(table, mask, w);
-            if (r) {
-              const u32 y2 = s_y[wid][ls[u]];
-              count_hit<PV>(r, w, x, y2, max(x, y2), c, tri);
-            }
-          }
+          const u32 y2 = s_y[wid][ls[u]];
+          const u32 vmax = max(x, y2);
+          tl.add(res[u], ok[u], ws[u], vmax);
+          if (PV) attribute(tri, res[u], ws[u], x, y2, vmax);
         }
       }
+      tl.fold(c);
       wave_lds_sync();
     }
   }
   block_flush_counts(c, 1, ctr, s_red);
 }
 
-// ---- block class: one workgroup per (x, chunk, partner segment) ------------------------
-template <bool PV>
-__global__ void __launch_bounds__(kIsectThreads) k_isect_block(
-    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+// ---- block class: one 1024-thread workgroup per (x, segment of partners) ----------------
+// N(x) is staged chunk by chunk (at most prm.chunk <= 16384 entries per chunk) in a
+// 128 KB LDS hash set.  For each chunk the segment's partner lists are cut to the chunk's
+// ID range (binary search, only when N(x) needs several chunks), padded out to whole
+// 16-byte quads and concatenated; the workgroup then streams that quad space with one
+// 16-byte load per lane and quad, finding each quad's partner by binary search over the
+// quad prefix sums in LDS.  Every partner element is probed exactly once, against the
+// one chunk whose ID range can hold it.
+constexpr int kBigThreads = 1024;
+constexpr int kBigSlots = 32768;   // 128 KB of LDS
+constexpr int kBigSeg = 1024;      // partners per work item (one per thread for set-up)
+constexpr int kQuadUnroll = 4;     // quads per lane loaded before probing
+
+template <bool PV, bool VEC>
+__global__ void __launch_bounds__(kBigThreads) k_isect_block(
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const uint8_t* __restrict__ vinfo, const u32* __restrict__ hoff, const u32* __restrict__ hadj,
     const Item* __restrict__ items, u32 nitems, IsectParams prm, Plan* __restrict__ plan,
     u64* __restrict__ ctr, u64* __restrict__ tri) {
-  __shared__ u32 s_table[kBlockSlots];
-  __shared__ u32 s_incl[kIsectThreads];
-  __shared__ u32 s_start[kIsectThreads];
-  __shared__ u32 s_y[kIsectThreads];
-  __shared__ u32 s_tmp[kIsectThreads / kWave];
-  __shared__ u64 s_red[5 * (kIsectThreads / kWave)];
+  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
+  __shared__ __align__(16) u32 s_table[kBigSlots];
+  __shared__ u32 s_qincl[kBigSeg], s_qbase[kBigSeg], s_lo[kBigSeg], s_hi[kBigSeg], s_y[kBigSeg];
+  __shared__ u32 s_tmp[kBigThreads / kWave];
+  __shared__ u64 s_red[5 * (kBigThreads / kWave)];
   __shared__ u32 s_item;
+  const u32 tid = threadIdx.x;
   Counts c{0, 0, 0, 0, 0};
   while (true) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&plan->next_item, 1u);
+    if (tid == 0) s_item = atomicAdd(&plan->next_item, 1u);
     __syncthreads();
     const u32 it = s_item;
     if (it >= nitems) break;
@@ -186,69 +195,94 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_block(
     const u32 x = item.x;
     const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
     const u32 px = vinfo[x] & 0x80u;
-    const u32 c0 = item.chunk * prm.chunk;
-    const u32 clen = min(prm.chunk, dx - c0);
-    const bool chunked = dx > prm.chunk;
-    const u32 mask = table_mask(clen, kBlockSlots);
-    c.staged += threadIdx.x == 0 ? clen : 0;
-    for (u32 i = threadIdx.x; i <= mask; i += blockDim.x) s_table[i] = kInf;
-    __syncthreads();
-    for (u32 i = threadIdx.x; i < clen; i += blockDim.x) {
-      const u32 w = colidx[bx + c0 + i];
-      const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
-      hash_insert(s_table, mask, w | (same << 31));
-    }
-    const u32 wlo = colidx[bx + c0], whi = colidx[bx + c0 + clen - 1];
     const u32 hs = hoff[x] + item.seg * prm.seg;
     const u32 pn = min(prm.seg, hoff[x + 1] - hs);
-    u32 y = 0, sy = 0, dy = 0;
-    if (threadIdx.x < pn) {
-      y = hadj[hs + threadIdx.x];
-      sy = rowptr[y];
-      u32 ey = rowptr[y + 1];
-      if (chunked) {
-        sy = lower_bound_g(colidx, sy, ey, wlo);
-        ey = lower_bound_g(colidx, sy, ey, whi + 1u);
-      }
-      dy = ey - sy;
+    u32 y = 0, ylo = 0, yhi = 0;
+    if (tid < pn) {
+      y = hadj[hs + tid];
+      ylo = rowptr[y];
+      yhi = rowptr[y + 1];
     }
-    c.probes += dy;
-    u32 total;
-    const u32 incl = block_incl_scan(dy, s_tmp, &total);
-    s_incl[threadIdx.x] = incl;
-    s_start[threadIdx.x] = sy - (incl - dy);
-    s_y[threadIdx.x] = y;
-    __syncthreads();
-    for (u32 k0 = 0; k0 < total; k0 += kIsectThreads * kUnroll) {
-      u32 ws[kUnroll], ls[kUnroll];
+    const u32 nch = (dx + prm.chunk - 1) / prm.chunk;
+    for (u32 ch = 0; ch < nch; ++ch) {
+      const u32 c0 = ch * prm.chunk, clen = min(prm.chunk, dx - c0);
+      const u32 mask = bucket_mask(clen, kBigSlots);
+      c.staged += tid == 0 ? clen : 0;
+      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) s_table[i] = kInf;
+      // this partner's elements that fall in the chunk's ID range
+      u32 lo = ylo, hi = yhi;
+      if (tid < pn && nch > 1) {
+        if (ch > 0) lo = lower_bound_g(colidx, lo, hi, colidx[bx + c0]);
+        if (ch + 1 < nch) hi = lower_bound_g(colidx, lo, hi, colidx[bx + c0 + clen - 1] + 1u);
+      }
+      const u32 qa = VEC ? (lo & ~3u) : lo;
+      const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
+      u32 total;
+      const u32 incl = block_incl_scan(nq, s_tmp, &total);
+      if (tid < pn) {
+        s_qincl[tid] = incl;
+        s_qbase[tid] = (VEC ? qa >> 2 : qa) - (incl - nq);  // quad q of the partner: qbase + q
+        s_lo[tid] = lo;
+        s_hi[tid] = hi;
+        s_y[tid] = y;
+      }
+      for (u32 i = tid; i < clen; i += blockDim.x) {
+        const u32 w = colidx[bx + c0 + i];
+        const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
+        hash_insert(s_table, mask, w | (same << 31));
+      }
+      __syncthreads();
+      Tally tl{0, 0, 0, 0};
+      for (u32 q0 = 0; q0 < total; q0 += kBigThreads * kQuadUnroll) {
+        u32 e[kQuadUnroll][NE];
+        u32 pp[kQuadUnroll];
+        u32 addr[kQuadUnroll];
+        bool live[kQuadUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const u32 k = k0 + u * kIsectThreads + threadIdx.x;
-        ls[u] = kInf;
-        if (k < total) {
-          u32 lo = 0, hi = pn - 1;
-          while (lo < hi) {
-            const u32 mid = (lo + hi) >> 1;
-            if (s_incl[mid] > k) hi = mid;
-            else lo = mid + 1;
+        for (int u = 0; u < kQuadUnroll; ++u) {
+          const u32 q = q0 + u * kBigThreads + tid;
+          live[u] = q < total;
+          u32 l = 0, h = pn - 1;  // smallest partner with qincl > q
+          while (l < h) {
+            const u32 mid = (l + h) >> 1;
+            if (s_qincl[mid] > q) h = mid;
+            else l = mid + 1;
           }
-          ls[u] = lo;
-          ws[u] = colidx[s_start[lo] + k];
+          pp[u] = l;
+          addr[u] = (s_qbase[l] + q) * NE;
+          if (VEC && live[u] && addr[u] + 3 < m) {
+            const uint4 v = *reinterpret_cast<const uint4*>(colidx + addr[u]);
+            e[u][0] = v.x;
+            e[u][NE > 1 ? 1 : 0] = v.y;
+            e[u][NE > 2 ? 2 : 0] = v.z;
+            e[u][NE > 3 ? 3 : 0] = v.w;
+          } else {
+#pragma unroll
+            for (u32 i = 0; i < NE; ++i)
+              e[u][i] = live[u] && addr[u] + i < m ? colidx[addr[u] + i] : kInf;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kQuadUnroll; ++u) {
+          const u32 plo = s_lo[pp[u]], phi = s_hi[pp[u]];
+          const u32 y2 = s_y[pp[u]];
+          const u32 vmax = max(x, y2);
+          bool ok[NE];
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i)
+            ok[i] = live[u] && addr[u] + i >= plo && addr[u] + i < phi;
+          u32 res[NE];
+          hash_probe_n<NE>(s_table, mask, e[u], ok, res);
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) {
+            tl.add(res[i], ok[i], e[u][i], vmax);
+            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+          }
         }
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        if (ls[u] != kInf) {
-          const u32 w = ws[u];
-          const u32 r = hash_probe(s_table, mask, w);
-          if (r) {
-            const u32 y2 = s_y[ls[u]];
-            count_hit<PV>(r, w, x, y2, max(x, y2), c, tri);
-          }
-        }
-      }
+      tl.fold(c);
+      __syncthreads();
     }
-    __syncthreads();
   }
   block_flush_counts(c, 2, ctr, s_red);
 }
@@ -291,17 +325,23 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinf
                        vinfo, hoff, hadj, wave_x, nwx, plan, ctr, tri);
 }
 
-void launch_isect_block(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
+void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const uint8_t* vinfo,
                         const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
   if (nitems == 0) return;
-  const u32 g = min(nitems, resident_blocks(4));
-  if (tri)
-    hipLaunchKernelGGL(k_isect_block<true>, dim3(g), dim3(kIsectThreads), 0, s, rowptr, colidx,
-                       vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri);
-  else
-    hipLaunchKernelGGL(k_isect_block<false>, dim3(g), dim3(kIsectThreads), 0, s, rowptr, colidx,
-                       vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri);
+  const u32 g = min(nitems, resident_blocks(1));
+  const bool vec = ((uintptr_t)colidx & 15u) == 0;
+#define TC_LAUNCH_BLOCK(PV, VEC)                                                             \
+  hipLaunchKernelGGL((k_isect_block<PV, VEC>), dim3(g), dim3(kBigThreads), 0, s, rowptr, colidx, \
+                     m, vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri)
+  if (tri) {
+    if (vec) TC_LAUNCH_BLOCK(true, true);
+    else TC_LAUNCH_BLOCK(true, false);
+  } else {
+    if (vec) TC_LAUNCH_BLOCK(false, true);
+    else TC_LAUNCH_BLOCK(false, false);
+  }
+#undef TC_LAUNCH_BLOCK
 }
 
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s) {

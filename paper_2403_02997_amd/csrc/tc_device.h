@@ -164,18 +164,23 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Mask of a power-of-two hash table holding `keys` keys at load factor <= 1/2, at
-// least 64 and at most `cap` slots.
-__device__ __forceinline__ u32 table_mask(u32 keys, u32 cap) {
+// ---- LDS hash set of a neighbour list -----------------------------------------------
+// Bucketed open addressing: a table of `slots` u32 (a power of two) is read as buckets of
+// four slots, one 16-byte LDS load per bucket.  A key is a vertex ID (< 2^31) with bit 31
+// set when the vertex is on the same BFS level as the list owner.  Inserts fill a
+// bucket's slots in order and move to the next bucket only when it is full, so a probe
+// ends at the first bucket that holds the key or an empty slot.
+
+// Bucket mask for `keys` keys at load factor <= 1/2: at least 16 buckets (64 slots),
+// at most cap_slots / 4.
+__device__ __forceinline__ u32 bucket_mask(u32 keys, u32 cap_slots) {
   u32 want = keys * 2;
   if (want < 64) want = 64;
-  const u32 p = 1u << (32 - __clz(want - 1));
-  return (p > cap ? cap : p) - 1;
+  u32 p = 1u << (32 - __clz(want - 1));
+  if (p > cap_slots) p = cap_slots;
+  return p / 4 - 1;
 }
 
-// ---- LDS hash set of a neighbour list -----------------------------------------------
-// Open addressing with linear probing over a power-of-two table.  A key is a vertex ID
-// (< 2^31) with bit 31 set when the vertex is on the same BFS level as the list owner.
 // Knuth's multiplicative hash with the high half folded into the low bits, which the
 // power-of-two mask keeps.
 __device__ __forceinline__ u32 hash_mix(u32 w) {
@@ -183,27 +188,83 @@ __device__ __forceinline__ u32 hash_mix(u32 w) {
   return (h >> 16) ^ h;
 }
 
-__device__ __forceinline__ void hash_insert(u32* table, u32 mask, u32 key) {
+__device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 key) {
   const u32 w = key & 0x7FFFFFFFu;
-  u32 h = hash_mix(w) & mask;
+  u32 b = hash_mix(w) & bmask;
   while (true) {
-    const u32 old = atomicCAS(&table[h], kInf, key);
-    if (old == kInf) return;
-    h = (h + 1) & mask;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (atomicCAS(&table[4 * b + j], kInf, key) == kInf) return;
+    b = (b + 1) & bmask;
   }
 }
 
-// Returns 0 when w is absent, 1 when present on another level, 2 when present on the
-// owner's level.
-__device__ __forceinline__ u32 hash_probe(const u32* table, u32 mask, u32 w) {
-  u32 h = hash_mix(w) & mask;
+// 0 when w is absent, 1 when present on another level, 2 on the owner's level; 3 when
+// the bucket is full without w (the probe continues in the next bucket).  Branch-free:
+// keys are unique, so at most one slot matches.
+__device__ __forceinline__ u32 bucket_check(uint4 v, u32 w) {
+  const bool m0 = (v.x & 0x7FFFFFFFu) == w;
+  const bool m1 = (v.y & 0x7FFFFFFFu) == w;
+  const bool m2 = (v.z & 0x7FFFFFFFu) == w;
+  const bool m3 = (v.w & 0x7FFFFFFFu) == w;
+  const u32 sel = m0 ? v.x : (m1 ? v.y : (m2 ? v.z : v.w));
+  const u32 miss = v.w == kInf ? 0u : 3u;  // slots fill in order: room leaves v.w empty
+  return (m0 | m1 | m2 | m3) ? 1u + (sel >> 31) : miss;
+}
+
+__device__ __forceinline__ u32 hash_probe(const u32* table, u32 bmask, u32 w) {
+  const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  u32 b = hash_mix(w) & bmask;
   while (true) {
-    const u32 k = table[h];
-    if (k == kInf) return 0;
-    if ((k & 0x7FFFFFFFu) == w) return 1u + (k >> 31);
-    h = (h + 1) & mask;
+    const u32 r = bucket_check(t4[b], w);
+    if (r != 3u) return r;
+    b = (b + 1) & bmask;
   }
 }
+
+// Probes of N independent keys; res[i] = 0 where !ok[i].  The first bucket of every key
+// is read (always in bounds) before any is examined; the rare overflows continue after.
+template <int N>
+__device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const u32 (&w)[N],
+                                             const bool (&ok)[N], u32 (&res)[N]) {
+  const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  uint4 v[N];
+  u32 b[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    b[i] = hash_mix(w[i]) & bmask;
+    v[i] = t4[b[i]];
+  }
+  bool more = false;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    res[i] = ok[i] ? bucket_check(v[i], w[i]) : 0u;
+    more |= res[i] == 3u;
+  }
+  if (__builtin_expect(more, 0)) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      while (res[i] == 3u) {
+        b[i] = (b[i] + 1) & bmask;
+        res[i] = bucket_check(t4[b[i]], w[i]);
+      }
+    }
+  }
+}
+
+struct Counts;
+
+// Per-thread tallies of one work item in 32-bit registers, folded into Counts after it.
+struct Tally {
+  u32 c1, c2, t2, probes;
+  __device__ __forceinline__ void add(u32 r, bool ok, u32 w, u32 vmax) {
+    c1 += r == 1u;
+    c2 += r == 2u;
+    t2 += (r == 2u) & (w > vmax);
+    probes += ok;
+  }
+  __device__ __forceinline__ void fold(Counts& c);
+};
 
 // ---- union-find with smallest-ID roots ---------------------------------------------
 // parent[x] <= x always holds: links go from the larger root to the smaller one, so the
@@ -244,6 +305,23 @@ constexpr int kNumCtr = 10;
 struct Counts {
   u64 c1, c2, t2, probes, staged;
 };
+
+__device__ __forceinline__ void Tally::fold(Counts& c) {
+  c.c1 += c1;
+  c.c2 += c2;
+  c.t2 += t2;
+  c.probes += probes;
+  c1 = c2 = t2 = probes = 0;
+}
+
+// Per-vertex attribution of a counted triangle {x, y, w} (result r of a probe of w).
+__device__ __forceinline__ void attribute(u64* tri, u32 r, u32 w, u32 x, u32 y, u32 vmax) {
+  if (r == 1u || (r == 2u && w > vmax)) {
+    atomicAdd((unsigned long long*)&tri[x], 1ull);
+    atomicAdd((unsigned long long*)&tri[y], 1ull);
+    atomicAdd((unsigned long long*)&tri[w], 1ull);
+  }
+}
 
 // Tally one common neighbour w of the cover edge {x, y}: r = 1 when w is on another
 // level than x (c1), r = 2 on the same level (c2; counted into T only when w is larger

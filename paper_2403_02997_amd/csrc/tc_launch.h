@@ -26,7 +26,7 @@ struct BfsCtl {
 struct IsectParams {
   u32 lane_max;    // d(x) <= lane_max        : lane-per-cover-edge merge
   u32 wave_max;    // d(x) <= wave_max        : wavefront per x, LDS hash
-  u32 chunk;       // block items hash at most `chunk` entries of N(x)
+  u32 chunk;       // block items stage N(x) in chunks of at most `chunk` entries
   u32 seg;         // partners per block item
 };
 
@@ -42,7 +42,7 @@ struct Plan {
 };
 
 struct Item {
-  u32 x, chunk, seg;
+  u32 x, seg;  // staged vertex, segment of its partner list
 };
 
 // ---- prep ----
@@ -84,7 +84,7 @@ void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinf
 void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
                        const u32* hoff, const u32* hadj, const u32* wave_x, u32 nwx,
                        Plan* plan, u64* ctr, u64* tri, hipStream_t s);
-void launch_isect_block(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
+void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const uint8_t* vinfo,
                         const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);

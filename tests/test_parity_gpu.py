@@ -105,8 +105,8 @@ def test_per_vertex_matches_oracle(tc_lib, name):
     assert np.array_equal(t, r.per_vertex)
 
 
-PARAMS = [(0, 0, 4096, 256), (64, 64, 256, 16), (16, 512, 4096, 256), (0, 512, 64, 1),
-          (512, 512, 4096, 256), (4, 32, 1024, 64)]
+PARAMS = [(0, 0, 4096, 256), (64, 64, 256, 16), (16, 512, 16384, 1024), (0, 512, 64, 1),
+          (512, 512, 4096, 256), (4, 32, 1024, 64), (0, 16, 100, 1000), (16, 128, 16384, 3)]
 
 
 @pytest.mark.parametrize("params", PARAMS)
@@ -122,6 +122,26 @@ def test_every_class_setting_gives_the_same_count(tc_lib, name, params):
     finally:
         tc_lib.tc_set_isect_params(*saved)
     assert stats.triangles == r.triangles and stats.cover_edges == r.cover_edges
+
+
+@pytest.mark.parametrize("name", ["rmat14_ef32", "book10000", "er16_d32", "grid64_del"])
+def test_unaligned_colidx(tc_lib, name):
+    """colidx not 16-byte aligned: the streaming kernels take their scalar-load path."""
+    g, r, _, _ = case(name)
+    say(f"[parity] unaligned colidx {name}")
+    rp, ci = upload(g, tc_lib)
+    buf = torch.zeros(ci.numel() + 1, dtype=torch.int32, device="cuda")
+    buf[1:] = ci
+    shifted = buf[1:]
+    assert shifted.data_ptr() % 16 != 0
+    saved = tc_lib.tc_get_isect_params()
+    try:
+        for params in [saved, (0, 16, 100, 7)]:
+            tc_lib.tc_set_isect_params(*params)
+            stats, _ = tc_lib.tc_count_ex(rp, shifted)
+            assert stats.triangles == r.triangles and stats.cover_edges == r.cover_edges
+    finally:
+        tc_lib.tc_set_isect_params(*saved)
 
 
 def test_empty_inputs(tc_lib):
