@@ -193,6 +193,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<Plan>(1);
     c.take<u64>(kCounterSlots * kNumCtr);
     c.take<u64>(kNumCtr);
+    c.take<u32>(4);
     bytes = c.off + 256;
   }
   DevAlloc ws;
@@ -219,6 +220,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u64* ctr = c.take<u64>(kCounterSlots * kNumCtr);
   u64* outc = c.take<u64>(kNumCtr);
   const size_t ctl_bytes = (char*)(outc + kNumCtr) - (char*)ctl;
+  u32* tail4 = c.take<u32>(4);
   if (level_out) level = level_out;
 
   TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
@@ -285,7 +287,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   if (h_plan.lane_edges)
     launch_isect_lane(rowptr, colidx, vinfo, hoff, hadj, htile_row, n, h_ns, prm, ctr, tri, s);
   timer.mark();
-  launch_isect_block(rowptr, colidx, m, vinfo, hoff, hadj, items, h_items, prm, plan, ctr, tri, s);
+  if (h_items) launch_tail4(colidx, m, tail4, s);
+  launch_isect_block(rowptr, colidx, m, tail4, vinfo, hoff, hadj, items, h_items, prm, plan, ctr,
+                     tri, s);
   timer.mark();
   launch_isect_wave(rowptr, colidx, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan, ctr, tri, s);
   timer.mark();

@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
             vw = vinfo[w];
           }
           const bool same = (vw & 0x80u) == px;
-          if (act) hash_insert(table, mask, w | ((same ? 1u : 0u) << 31));
+          if (act) hash_insert(table, mask, w, same ? 1u : 0u);
           const bool isp = act && same && key_less(vw & 127u, w, cx, x);
           const u64 pm = __ballot(isp);
           if (isp) plist[np + mask_rank(pm)] = w;
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
           for (u32 i = threadIdx.x; i < clen; i += kBT) {
             const u32 w = ci[bx + c0 + i];
             const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
-            hash_insert(s_tab, mask, w | (same << 31));
+            hash_insert(s_tab, mask, w, same);
           }
           const u32 wlo = ci[bx + c0], whi = ci[bx + c0 + clen - 1];
           __syncthreads();

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     for (u32 i = lane; i < dx; i += kWave) {
       const u32 w = colidx[bx + i];
       const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
-      hash_insert(table, mask, w | (same << 31));
+      hash_insert(table, mask, w, same);
     }
     wave_lds_sync();
     const u32 hs = hoff[x], np = hoff[x + 1] - hs;
@@ -118,6 +118,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
         sy = rowptr[y];
         dy = rowptr[y + 1] - sy;
       }
+      c.probes += dy;
       const u32 incl = wave_incl_scan(dy);
       const u32 total = __shfl(incl, kWave - 1, kWave);
       s_incl[wid][lane] = incl;
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
             else lo = mid + 1;
           }
           ls[u] = lo;
-          ws[u] = ok[u] ? colidx[s_start[wid][lo] + k] : kInf;
+          ws[u] = colidx[ok[u] ? s_start[wid][lo] + k : 0u];
         }
         u32 res[kUnroll];
         hash_probe_n<kUnroll>(table, mask, ws, ok, res);
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
         for (int u = 0; u < kUnroll; ++u) {
           const u32 y2 = s_y[wid][ls[u]];
           const u32 vmax = max(x, y2);
-          tl.add(res[u], ok[u], ws[u], vmax);
+          tl.add(res[u], ws[u], vmax);
           if (PV) attribute(tri, res[u], ws[u], x, y2, vmax);
         }
       }
@@ -162,30 +163,36 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
 // ---- block class: one 1024-thread workgroup per (x, segment of partners) ----------------
 // N(x) is staged chunk by chunk (at most prm.chunk <= 16384 entries per chunk) in a
 // 128 KB LDS hash set.  For each chunk the segment's partner lists are cut to the chunk's
-// ID range (binary search, only when N(x) needs several chunks), padded out to whole
-// 16-byte quads and concatenated; the workgroup then streams that quad space with one
-// 16-byte load per lane and quad, finding each quad's partner by binary search over the
-// quad prefix sums in LDS.  Every partner element is probed exactly once, against the
-// one chunk whose ID range can hold it.
+// ID range (binary search, only when N(x) needs several chunks) and padded out to whole
+// 16-byte quads; the concatenated quad space is split into one contiguous range per
+// wavefront.  A wavefront walks its range in windows of 64 quads, one quad (16-byte load)
+// per lane, and keeps the current partner as it goes: the partner boundaries (quad prefix
+// sums in LDS) that fall inside a window are applied with a few lane-uniform steps, so
+// no per-lane search is needed.  Every partner element is probed exactly once, against
+// the one chunk whose ID range can hold it.
 constexpr int kBigThreads = 1024;
+constexpr int kBigWaves = kBigThreads / kWave;
 constexpr int kBigSlots = 32768;   // 128 KB of LDS
 constexpr int kBigSeg = 1024;      // partners per work item (one per thread for set-up)
-constexpr int kQuadUnroll = 4;     // quads per lane loaded before probing
+constexpr int kQuadUnroll = 4;     // windows per wavefront loaded before probing
 
 template <bool PV, bool VEC>
 __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
+    const u32* __restrict__ tail4,
     const uint8_t* __restrict__ vinfo, const u32* __restrict__ hoff, const u32* __restrict__ hadj,
     const Item* __restrict__ items, u32 nitems, IsectParams prm, Plan* __restrict__ plan,
     u64* __restrict__ ctr, u64* __restrict__ tri) {
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
   __shared__ __align__(16) u32 s_table[kBigSlots];
-  __shared__ u32 s_qincl[kBigSeg], s_qbase[kBigSeg], s_lo[kBigSeg], s_hi[kBigSeg], s_y[kBigSeg];
-  __shared__ u32 s_tmp[kBigThreads / kWave];
-  __shared__ u64 s_red[5 * (kBigThreads / kWave)];
+  __shared__ u32 s_qincl[kBigSeg];
+  __shared__ uint4 s_pinfo[kBigSeg];  // {quad base, lo, hi, y} of each partner
+  __shared__ u32 s_tmp[kBigWaves];
+  __shared__ u64 s_red[5 * kBigWaves];
   __shared__ u32 s_item;
-  const u32 tid = threadIdx.x;
+  const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   Counts c{0, 0, 0, 0, 0};
+  Tally tl{0, 0, 0, 0};
   while (true) {
     if (tid == 0) s_item = atomicAdd(&plan->next_item, 1u);
     __syncthreads();
@@ -215,76 +222,109 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
         if (ch > 0) lo = lower_bound_g(colidx, lo, hi, colidx[bx + c0]);
         if (ch + 1 < nch) hi = lower_bound_g(colidx, lo, hi, colidx[bx + c0 + clen - 1] + 1u);
       }
+      tl.probes += hi - lo;
       const u32 qa = VEC ? (lo & ~3u) : lo;
       const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
       u32 total;
       const u32 incl = block_incl_scan(nq, s_tmp, &total);
       if (tid < pn) {
         s_qincl[tid] = incl;
-        s_qbase[tid] = (VEC ? qa >> 2 : qa) - (incl - nq);  // quad q of the partner: qbase + q
-        s_lo[tid] = lo;
-        s_hi[tid] = hi;
-        s_y[tid] = y;
+        s_pinfo[tid] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
       }
       for (u32 i = tid; i < clen; i += blockDim.x) {
         const u32 w = colidx[bx + c0 + i];
-        const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
-        hash_insert(s_table, mask, w | (same << 31));
+        hash_insert(s_table, mask, w, ((vinfo[w] & 0x80u) == px) ? 1u : 0u);
       }
       __syncthreads();
-      Tally tl{0, 0, 0, 0};
-      for (u32 q0 = 0; q0 < total; q0 += kBigThreads * kQuadUnroll) {
+      // this wavefront's contiguous quad range, in whole windows
+      const u32 per = (total + kBigWaves * kWave - 1) / (kBigWaves * kWave) * kWave;
+      const u32 qs = min(wid * per, total), qe = min(qs + per, total);
+      // partner of quad qs: smallest p with qincl[p] > qs (lane-uniform search)
+      u32 pcur = 0;
+      {
+        u32 h = pn - 1;
+        while (pcur < h) {
+          const u32 mid = (pcur + h) >> 1;
+          if (s_qincl[mid] > qs) h = mid;
+          else pcur = mid + 1;
+        }
+      }
+      for (u32 qw = qs; qw < qe; qw += kWave * kQuadUnroll) {
         u32 e[kQuadUnroll][NE];
-        u32 pp[kQuadUnroll];
+        uint4 inf[kQuadUnroll];
         u32 addr[kQuadUnroll];
         bool live[kQuadUnroll];
 #pragma unroll
         for (int u = 0; u < kQuadUnroll; ++u) {
-          const u32 q = q0 + u * kBigThreads + tid;
-          live[u] = q < total;
-          u32 l = 0, h = pn - 1;  // smallest partner with qincl > q
-          while (l < h) {
-            const u32 mid = (l + h) >> 1;
-            if (s_qincl[mid] > q) h = mid;
-            else l = mid + 1;
+          const u32 w0 = qw + u * kWave;        // first quad of this window
+          const u32 q = w0 + lane;
+          live[u] = q < qe;
+          // partner of q: pcur plus the boundaries (qincl values) <= q in this window
+          u32 p = pcur;
+          while (true) {
+            const u32 j = pcur + lane;
+            const u32 bj = j < pn ? s_qincl[j] : kInf;
+            u64 bm = __ballot(bj <= w0 + kWave - 1);
+            const u32 nb = (u32)__popcll(bm);
+            while (bm) {
+              const int jl = __ffsll((unsigned long long)bm) - 1;
+              bm &= bm - 1;
+              p += q >= (u32)__shfl(bj, jl, kWave) ? 1u : 0u;
+            }
+            pcur += nb;
+            if (nb < (u32)kWave) break;
           }
-          pp[u] = l;
-          addr[u] = (s_qbase[l] + q) * NE;
-          if (VEC && live[u] && addr[u] + 3 < m) {
-            const uint4 v = *reinterpret_cast<const uint4*>(colidx + addr[u]);
+          p = min(p, pn - 1);  // lanes past the range keep a valid index
+          inf[u] = s_pinfo[p];
+          addr[u] = (inf[u].x + q) * NE;
+          if (VEC) {
+            // one unconditional 16-byte load: a quad that would run past the end of
+            // colidx (or a dead lane) reads the padded copy of the last partial quad
+            const u32* src = (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
+            const uint4 v = *reinterpret_cast<const uint4*>(src);
             e[u][0] = v.x;
             e[u][NE > 1 ? 1 : 0] = v.y;
             e[u][NE > 2 ? 2 : 0] = v.z;
             e[u][NE > 3 ? 3 : 0] = v.w;
           } else {
-#pragma unroll
-            for (u32 i = 0; i < NE; ++i)
-              e[u][i] = live[u] && addr[u] + i < m ? colidx[addr[u] + i] : kInf;
+            e[u][0] = colidx[live[u] ? addr[u] : 0u];
           }
         }
 #pragma unroll
         for (int u = 0; u < kQuadUnroll; ++u) {
-          const u32 plo = s_lo[pp[u]], phi = s_hi[pp[u]];
-          const u32 y2 = s_y[pp[u]];
+          const u32 y2 = inf[u].w;
           const u32 vmax = max(x, y2);
+          const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
           bool ok[NE];
 #pragma unroll
-          for (u32 i = 0; i < NE; ++i)
-            ok[i] = live[u] && addr[u] + i >= plo && addr[u] + i < phi;
+          for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
           u32 res[NE];
           hash_probe_n<NE>(s_table, mask, e[u], ok, res);
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) {
-            tl.add(res[i], ok[i], e[u][i], vmax);
+            tl.add(res[i], e[u][i], vmax);
             if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
           }
         }
       }
-      tl.fold(c);
       __syncthreads();
     }
+    tl.fold(c);
   }
   block_flush_counts(c, 2, ctr, s_red);
+}
+
+// Copy of colidx's last partial 16-byte quad (elements m & ~3 .. m-1), padded with kInf.
+__global__ void k_tail4(const u32* __restrict__ colidx, u32 m, u32* __restrict__ tail4) {
+  const u32 i = threadIdx.x;
+  if (i < 4) {
+    const u32 idx = (m & ~3u) + i;
+    tail4[i] = idx < m ? colidx[idx] : kInf;
+  }
+}
+
+void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s) {
+  hipLaunchKernelGGL(k_tail4, dim3(1), dim3(64), 0, s, colidx, m, tail4);
 }
 
 __global__ void k_finalize(const u64* __restrict__ ctr, u64* __restrict__ out) {
@@ -325,7 +365,8 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinf
                        vinfo, hoff, hadj, wave_x, nwx, plan, ctr, tri);
 }
 
-void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const uint8_t* vinfo,
+void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
+                        const uint8_t* vinfo,
                         const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
   if (nitems == 0) return;
@@ -333,7 +374,7 @@ void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const uint8
   const bool vec = ((uintptr_t)colidx & 15u) == 0;
 #define TC_LAUNCH_BLOCK(PV, VEC)                                                             \
   hipLaunchKernelGGL((k_isect_block<PV, VEC>), dim3(g), dim3(kBigThreads), 0, s, rowptr, colidx, \
-                     m, vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri)
+                     m, tail4, vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri)
   if (tri) {
     if (vec) TC_LAUNCH_BLOCK(true, true);
     else TC_LAUNCH_BLOCK(true, false);

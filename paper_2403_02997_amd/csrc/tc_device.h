@@ -166,10 +166,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ---- LDS hash set of a neighbour list -----------------------------------------------
 // Bucketed open addressing: a table of `slots` u32 (a power of two) is read as buckets of
-// four slots, one 16-byte LDS load per bucket.  A key is a vertex ID (< 2^31) with bit 31
-// set when the vertex is on the same BFS level as the list owner.  Inserts fill a
-// bucket's slots in order and move to the next bucket only when it is full, so a probe
-// ends at the first bucket that holds the key or an empty slot.
+// four slots, one 16-byte LDS load per bucket.  A vertex w of the staged list is stored
+// as the key (w << 1) | same, with `same` set when w is on the owner's BFS level
+// (w < 2^31 - 1, so a key never equals the empty marker).  Inserts fill a bucket's slots
+// in order and move to the next bucket only when it is full, so a probe ends at the first
+// bucket that holds w or an empty slot.
 
 // Bucket mask for `keys` keys at load factor <= 1/2: at least 16 buckets (64 slots),
 // at most cap_slots / 4.
@@ -181,15 +182,11 @@ __device__ __forceinline__ u32 bucket_mask(u32 keys, u32 cap_slots) {
   return p / 4 - 1;
 }
 
-// Knuth's multiplicative hash with the high half folded into the low bits, which the
-// power-of-two mask keeps.
-__device__ __forceinline__ u32 hash_mix(u32 w) {
-  const u32 h = w * 2654435761u;
-  return (h >> 16) ^ h;
-}
+// Shift-xor mix (full-rate integer ops only); the low bits index the buckets.
+__device__ __forceinline__ u32 hash_mix(u32 w) { return w ^ (w >> 11) ^ (w >> 22); }
 
-__device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 key) {
-  const u32 w = key & 0x7FFFFFFFu;
+__device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 w, u32 same) {
+  const u32 key = (w << 1) | same;
   u32 b = hash_mix(w) & bmask;
   while (true) {
 #pragma unroll
@@ -199,31 +196,30 @@ __device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 key) {
   }
 }
 
-// 0 when w is absent, 1 when present on another level, 2 on the owner's level; 3 when
-// the bucket is full without w (the probe continues in the next bucket).  Branch-free:
-// keys are unique, so at most one slot matches.
-__device__ __forceinline__ u32 bucket_check(uint4 v, u32 w) {
-  const bool m0 = (v.x & 0x7FFFFFFFu) == w;
-  const bool m1 = (v.y & 0x7FFFFFFFu) == w;
-  const bool m2 = (v.z & 0x7FFFFFFFu) == w;
-  const bool m3 = (v.w & 0x7FFFFFFFu) == w;
-  const u32 sel = m0 ? v.x : (m1 ? v.y : (m2 ? v.z : v.w));
-  const u32 miss = v.w == kInf ? 0u : 3u;  // slots fill in order: room leaves v.w empty
-  return (m0 | m1 | m2 | m3) ? 1u + (sel >> 31) : miss;
+// Bucket v against k2 = w << 1: 0 when w is absent (the bucket has room), 1 when present
+// on another level, 2 on the owner's level, 3 when the bucket is full without w (the
+// probe continues in the next bucket).  A slot matches iff key ^ k2 is 0 or 1, and that
+// value is the level flag.
+__device__ __forceinline__ u32 bucket_check(uint4 v, u32 k2) {
+  const u32 mn = min(min(v.x ^ k2, v.y ^ k2), min(v.z ^ k2, v.w ^ k2));
+  return mn <= 1u ? 1u + mn : (v.w == kInf ? 0u : 3u);
 }
 
 __device__ __forceinline__ u32 hash_probe(const u32* table, u32 bmask, u32 w) {
   const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  const u32 k2 = w << 1;
   u32 b = hash_mix(w) & bmask;
   while (true) {
-    const u32 r = bucket_check(t4[b], w);
+    const u32 r = bucket_check(t4[b], k2);
     if (r != 3u) return r;
     b = (b + 1) & bmask;
   }
 }
 
 // Probes of N independent keys; res[i] = 0 where !ok[i].  The first bucket of every key
-// is read (always in bounds) before any is examined; the rare overflows continue after.
+// is read (always in bounds) before any is examined.  Keys whose bucket was full continue
+// in one wave-uniform loop that resolves one pending key per lane and pass, so the rare
+// overflow costs one bucket check per pass rather than one per key position.
 template <int N>
 __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const u32 (&w)[N],
                                              const bool (&ok)[N], u32 (&res)[N]) {
@@ -235,19 +231,31 @@ __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const 
     b[i] = hash_mix(w[i]) & bmask;
     v[i] = t4[b[i]];
   }
-  bool more = false;
+  u32 pend = 0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    res[i] = ok[i] ? bucket_check(v[i], w[i]) : 0u;
-    more |= res[i] == 3u;
+    res[i] = ok[i] ? bucket_check(v[i], w[i] << 1) : 0u;
+    pend |= (res[i] == 3u ? 1u : 0u) << i;
   }
-  if (__builtin_expect(more, 0)) {
+  while (__ballot(pend != 0)) {
+    if (pend) {
+      const u32 i = __ffs(pend) - 1;
+      u32 wi = w[0], bi = b[0];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      while (res[i] == 3u) {
-        b[i] = (b[i] + 1) & bmask;
-        res[i] = bucket_check(t4[b[i]], w[i]);
+      for (int j = 1; j < N; ++j) {
+        wi = (u32)j == i ? w[j] : wi;
+        bi = (u32)j == i ? b[j] : bi;
       }
+      bi = (bi + 1) & bmask;
+      const u32 r = bucket_check(t4[bi], wi << 1);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if ((u32)j == i) {
+          b[j] = bi;
+          res[j] = r;
+        }
+      }
+      if (r != 3u) pend &= pend - 1;
     }
   }
 }
@@ -257,11 +265,10 @@ struct Counts;
 // Per-thread tallies of one work item in 32-bit registers, folded into Counts after it.
 struct Tally {
   u32 c1, c2, t2, probes;
-  __device__ __forceinline__ void add(u32 r, bool ok, u32 w, u32 vmax) {
+  __device__ __forceinline__ void add(u32 r, u32 w, u32 vmax) {
     c1 += r == 1u;
     c2 += r == 2u;
     t2 += (r == 2u) & (w > vmax);
-    probes += ok;
   }
   __device__ __forceinline__ void fold(Counts& c);
 };

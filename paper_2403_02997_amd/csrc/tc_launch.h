@@ -84,7 +84,9 @@ void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinf
 void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
                        const u32* hoff, const u32* hadj, const u32* wave_x, u32 nwx,
                        Plan* plan, u64* ctr, u64* tri, hipStream_t s);
-void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const uint8_t* vinfo,
+void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s);
+void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
+                        const uint8_t* vinfo,
                         const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);
