@@ -172,10 +172,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 // in order and move to the next bucket only when it is full, so a probe ends at the first
 // bucket that holds w or an empty slot.
 
-// Bucket mask for `keys` keys at load factor <= 1/2: at least 16 buckets (64 slots),
-// at most cap_slots / 4.
+// Bucket mask for `keys` keys at load factor <= 1/4 where cap_slots allows (never above
+// 1/2 for the chunk sizes used): at least 16 buckets (64 slots), at most cap_slots / 4.
+// A low load factor keeps bucket overflows, which every lane of a wavefront waits for,
+// rare.
 __device__ __forceinline__ u32 bucket_mask(u32 keys, u32 cap_slots) {
-  u32 want = keys * 2;
+  u32 want = keys * 4;
   if (want < 64) want = 64;
   u32 p = 1u << (32 - __clz(want - 1));
   if (p > cap_slots) p = cap_slots;
