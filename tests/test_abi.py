@@ -84,8 +84,9 @@ def test_isect_params_validation(lib):
     assert lib.tc_get_isect_params(arr) == 0
     saved = tuple(arr)
     assert lib.tc_set_isect_params(16, 4096, 4096, 256) == -1  # wavefront tables hold 512
-    assert lib.tc_set_isect_params(16, 512, 8192, 256) == -1   # workgroup table holds 4096
-    assert lib.tc_set_isect_params(16, 512, 4096, 1024) == -1  # one partner per thread
+    assert lib.tc_set_isect_params(16, 512, 32768, 256) == -1  # workgroup table holds 16384
+    assert lib.tc_set_isect_params(16, 512, 4096, 2048) == -1  # one partner per thread
+    assert lib.tc_set_isect_params(16, 512, 0, 256) == -1
     assert lib.tc_set_isect_params(600, 512, 4096, 256) == -1  # lane class inside wave class
     assert lib.tc_set_isect_params(8, 256, 2048, 128) == 0
     assert lib.tc_get_isect_params(arr) == 0 and tuple(arr) == (8, 256, 2048, 128)
