@@ -20,6 +20,14 @@ Alongside, per JSON line:
 
 Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, and batch4096
 (4096 uneven graphs: one captured tc_count_batch launch against 4096 tc_count calls).
+
+Counter helpers (no bench line):
+  --calibrate-copy MIB  runs a plain device-to-device copy of MIB MiB three times, the
+                        known-size kernel that FETCH_SIZE / WRITE_SIZE are scaled by;
+  --traffic-summary     reads the four rocprofv3 --pmc CSVs (bench FETCH_SIZE and
+                        WRITE_SIZE passes, copy FETCH_SIZE and WRITE_SIZE passes) and
+                        stores the per-launch HBM bytes of each intersection kernel in
+                        profiles/traffic.json under the current kernel source hash.
 """
 from __future__ import annotations
 
@@ -311,6 +319,63 @@ def bench_batch(args, tcm, torch):
     }
 
 
+# ---- counter-measured HBM traffic ---------------------------------------------------------
+
+def _pmc_per_kernel(path: str, counter: str) -> dict:
+    """Mean counter value (KiB) per dispatch, by short kernel name."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        name = r["Kernel_Name"]
+        short = name.split("(")[0].split("<")[0].replace("void ", "").split("::")[-1]
+        acc.setdefault(short, []).append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v), max(v)) for k, v in acc.items()}
+
+
+def traffic_summary(args):
+    mib = args.copy_mib
+    copy_bytes = mib * (1 << 20)
+    cf = _pmc_per_kernel(args.copy_fetch, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][2]
+    cw = _pmc_per_kernel(args.copy_write, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][2]
+    f_fetch = cf * 1024 / copy_bytes
+    f_write = cw * 1024 / copy_bytes
+    fetch = _pmc_per_kernel(args.pmc_fetch, "FETCH_SIZE")
+    write = _pmc_per_kernel(args.pmc_write, "WRITE_SIZE")
+    path = os.path.join(PROFILES, "traffic.json")
+    db = json.load(open(path)) if os.path.exists(path) else {}
+    rec = db.setdefault(args.workload, {})
+    lines = [f"copy calibration: {mib} MiB device copy reads FETCH_SIZE {cf:.1f} KiB "
+             f"(factor {f_fetch:.4f}) and WRITE_SIZE {cw:.1f} KiB (factor {f_write:.4f})"]
+    for k in sorted(KERNEL_OF_STEP.values()):
+        if k not in fetch or k not in write:
+            continue
+        fb = fetch[k][0] * 1024 / f_fetch
+        wb = write[k][0] * 1024 / f_write
+        rec[k] = {"source_sha": source_sha(), "hbm_bytes_per_launch": int(fb + wb),
+                  "fetch_bytes": int(fb), "write_bytes": int(wb),
+                  "fetch_kib_raw": round(fetch[k][0], 1), "write_kib_raw": round(write[k][0], 1),
+                  "dispatches": fetch[k][1], "copy_factor_fetch": round(f_fetch, 5),
+                  "copy_factor_write": round(f_write, 5)}
+        lines.append(f"{k}: FETCH_SIZE {fetch[k][0]:.1f} KiB, WRITE_SIZE {write[k][0]:.1f} KiB "
+                     f"per dispatch ({fetch[k][1]} dispatches) -> {(fb + wb) / 1e9:.3f} GB "
+                     f"of HBM traffic per launch")
+    json.dump(db, open(path, "w"), indent=1, sort_keys=True)
+    print("\n".join(lines))
+
+
+def calibrate_copy(args, torch):
+    n = args.calibrate_copy * (1 << 20)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,7 +384,17 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
+    ap.add_argument("--traffic-summary", action="store_true")
+    ap.add_argument("--pmc-fetch")
+    ap.add_argument("--pmc-write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the counting path here is single-GPU "
@@ -332,6 +407,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        calibrate_copy(args, torch)
+        return
     tcm.load()
     if args.workload == "batch4096":
         out = bench_batch(args, tcm, torch)
