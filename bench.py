@@ -18,8 +18,10 @@ Alongside, per JSON line:
   cpu_baseline : the CPU oracle (CETC-SM, OpenMP) timed on this host on a bounded
                  sample of the same graph, extrapolated in the oracle's merge work.
 
-Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, and batch4096
-(4096 uneven graphs: one captured tc_count_batch launch against 4096 tc_count calls).
+Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, batch4096
+(4096 uneven graphs: one captured tc_count_batch launch against 4096 tc_count calls),
+and serve (a Poisson stream of requests through the tc_serve_* server: p50/p99 latency
+and input edges/s, every result checked against the standalone count).
 
 Counter helpers (no bench line):
   --calibrate-copy MIB  runs a plain device-to-device copy of MIB MiB three times, the
@@ -57,6 +59,8 @@ WORKLOAD_TEXT = {
     "er22": "Erdos-Renyi G(n=2^22, average degree 32), seed 1003",
     "batch4096": "4096 graphs: half R-MAT (scale 8-16, edge factor 8-32), half Erdos-Renyi "
                  "(n log-uniform in [2^8, 2^16], average degree 4-64), seed 1003",
+    "serve": "Poisson request stream: 90% R-MAT scale 12-18, 10% R-MAT scale 22-24, one "
+             "R-MAT scale 26 request, edge factor 16, seed 1005",
 }
 
 
@@ -319,6 +323,125 @@ def bench_batch(args, tcm, torch):
     }
 
 
+# ---- continuous-batching server ----------------------------------------------------------
+
+def bench_serve(args, tcm, torch):
+    """Requests arrive as a Poisson stream whose offered load is --serve-load (default
+    0.8) times the capacity of one-at-a-time standalone processing (pinned upload +
+    tc_count); each result is checked against the standalone count of the same graph."""
+    import graphgen as gg
+
+    base = gg.config_seed(5)
+    rng = np.random.default_rng(base)
+    small_scales = list(range(12, 19))
+    large_scales = [22, 23, 24]
+    pool = {}
+    t = time.perf_counter()
+    for sc in small_scales:
+        for k in range(3):
+            pool[(sc, k)] = gg.rmat(sc, 16, base + 100 * sc + k)
+    for sc in large_scales + ([args.serve_huge_scale] if args.serve_huge_scale else []):
+        pool[(sc, 0)] = gg.rmat(sc, 16, base + 100 * sc)
+        log(f"[bench] generated R-MAT scale {sc} ({time.perf_counter() - t:.1f}s)")
+    # Host CSRs in pinned memory (where a front end would receive them), standalone
+    # results, and standalone service times (upload + count).
+    host, ref, svc = {}, {}, {}
+    for key, g in pool.items():
+        hp = []
+        for a in (g.rowptr, g.colidx):
+            t_ = torch.empty(a.shape[0], dtype=torch.int32, pin_memory=True)
+            t_.numpy()[:] = a.view(np.int32)
+            hp.append(t_)
+        host[key] = tuple(hp)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rp, ci = hp[0].to("cuda"), hp[1].to("cuda")
+            ref[key] = tcm.tc_count(rp, ci)
+            svc[key] = time.perf_counter() - t0
+            del rp, ci
+    torch.cuda.empty_cache()
+    log(f"[bench] standalone counts of {len(pool)} pool graphs done")
+    nreq = args.serve_requests
+    keys = []
+    for _ in range(nreq):
+        if rng.random() < 0.9:
+            keys.append((int(rng.choice(small_scales)), int(rng.integers(0, 3))))
+        else:
+            keys.append((int(rng.choice(large_scales)), 0))
+    if args.serve_huge_scale:
+        keys[nreq // 2] = (args.serve_huge_scale, 0)
+    mean_svc = float(np.mean([svc[k] for k in keys]))
+    rate = args.serve_load / mean_svc
+    gaps = rng.exponential(1.0 / rate, size=nreq)
+    log(f"[bench] {nreq} requests, mean standalone service {mean_svc * 1e3:.2f} ms, "
+        f"arrival rate {rate:.1f}/s")
+    srv = tcm.Server(small_max_entries=args.serve_small_max)
+    tickets = {}
+    results = []
+    t_start = time.perf_counter()
+    next_t = t_start
+    for k, key in enumerate(keys):
+        next_t += gaps[k]
+        while True:
+            results += srv.poll(cap=512, timeout_ms=0)
+            dt = next_t - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.0005))
+        tickets[srv.submit(*host[key])] = key
+        if (k + 1) % 100 == 0:
+            log(f"[bench] submitted {k + 1}/{nreq}")
+    while len(results) < nreq:
+        results += srv.poll(cap=512, timeout_ms=500)
+    st = srv.stats()
+    srv.close()
+    bad = [r for r in results if r.status != 0 or r.triangles != ref[tickets[r.ticket]]]
+    assert not bad, f"{len(bad)} server results differ from the standalone counts"
+    lat = np.array([r.latency_s for r in results])
+    first = min(r.submit_s for r in results)
+    last = max(r.done_s for r in results)
+    edges = sum(r.input_edges for r in results)
+    paths = {"batched": sum(r.path == 0 for r in results),
+             "single_medium": sum(r.path == 1 for r in results),
+             "single_large": sum(r.path == 3 for r in results)}
+    lat_by = {}
+    for name, ids in (("batched", (0,)), ("single_medium", (1,)), ("single_large", (3,))):
+        v = np.array([r.latency_s for r in results if r.path in ids])
+        if v.size:
+            lat_by[name] = {"p50": round(float(np.percentile(v, 50)) * 1e3, 3),
+                            "p99": round(float(np.percentile(v, 99)) * 1e3, 3)}
+    return {
+        "metric": METRIC,
+        "value": edges / (last - first),
+        "unit": "input edges/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": 0,
+        "ms_per_step": (last - first) * 1e3 / nreq,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "serve", "graph": WORKLOAD_TEXT["serve"], "requests": nreq,
+                   "arrival_rate_per_s": round(rate, 2), "offered_load": args.serve_load,
+                   "mean_standalone_service_ms": round(mean_svc * 1e3, 3),
+                   "huge_scale": args.serve_huge_scale,
+                   "small_max_entries": args.serve_small_max},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                       "mean": round(float(lat.mean()) * 1e3, 3),
+                       "max": round(float(lat.max()) * 1e3, 3)},
+        "latency_ms_by_path": lat_by,
+        "input_edges": int(edges),
+        "paths": paths,
+        "server": {k: st[k] for k in ("batches", "singles", "hbm_peak", "hbm_budget")},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 # ---- counter-measured HBM traffic ---------------------------------------------------------
 
 def _pmc_per_kernel(path: str, counter: str) -> dict:
@@ -384,6 +507,10 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-huge-scale", type=int, default=26)
+    ap.add_argument("--serve-small-max", type=int, default=1 << 18)
+    ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--traffic-summary", action="store_true")
     ap.add_argument("--pmc-fetch")
@@ -413,6 +540,8 @@ def main():
     tcm.load()
     if args.workload == "batch4096":
         out = bench_batch(args, tcm, torch)
+    elif args.workload == "serve":
+        out = bench_serve(args, tcm, torch)
     else:
         out = bench_single(args, tcm, torch)
     print(json.dumps(out), flush=True)

@@ -128,6 +128,82 @@ int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
 size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows);
 
 /*
+ * ---- continuous-batching server ----------------------------------------------------
+ * A server counts a stream of independent graphs handed over as HOST CSR arrays (same
+ * format as above).  It admits a request when the request's device footprint (its CSR
+ * plus the scratch of its path) fits the HBM budget: first-fit in arrival order, except
+ * that while the oldest waiting request does not fit, later ones are admitted only if
+ * the oldest would still fit beside them.  Requests with at most small_max_entries stored
+ * entries are packed, whenever the previous batch has completed, into one tc_count_batch
+ * launch over everything admitted meanwhile; larger requests run through tc_count, those
+ * below large_min_entries and the rest on two separate workers, so that no request waits
+ * behind the upload of a much larger one.  The three paths overlap on the device.
+ * Results equal tc_count's.  Each server drives the device that is current at
+ * tc_serve_create with three host threads and three non-blocking streams of default
+ * priority.
+ */
+typedef struct tc_server tc_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;   /* device bytes admitted requests may hold; 0 = 80 % of the
+                                  device memory free at creation                          */
+  uint64_t small_max_entries;  /* requests with m <= this use the batched path; 0 = 2^18  */
+  uint32_t batch_max_graphs;   /* requests per batched launch at most; 0 = 4096           */
+  uint32_t reserved;           /* set to 0                                                */
+  uint64_t batch_max_entries;  /* stored entries per batched launch at most (a single
+                                  request above it still forms its own batch); 0 = 2^28  */
+  uint64_t large_min_entries;  /* single-graph requests with m >= this use the large
+                                  worker, the others the medium one; 0 = 2^25            */
+} tc_serve_config;
+
+typedef struct {
+  uint64_t ticket;             /* as returned by tc_serve_submit                          */
+  uint64_t triangles;          /* T (0 when status != TC_OK)                              */
+  int32_t status;              /* TC_OK, or the error of its path; TC_ERR_OUT_OF_MEMORY
+                                  when the request can never fit the budget               */
+  uint32_t path;               /* 0 batched, 1 single-graph (medium), 3 single-graph
+                                  (large), 2 rejected at submission                      */
+  uint64_t input_edges;        /* m / 2                                                   */
+  double submit_s, admit_s, done_s;  /* server clock, seconds since tc_serve_create       */
+} tc_serve_result;
+
+typedef struct {
+  uint64_t submitted, completed, rejected;
+  uint64_t batches, singles;   /* launches of each path                                   */
+  uint64_t queued;             /* waiting for admission                                   */
+  uint64_t in_flight;          /* submitted and not yet completed                         */
+  uint64_t hbm_in_use, hbm_peak, hbm_budget;  /* admitted footprint, bytes                */
+} tc_serve_stats;
+
+/* Creates a server on the current device; `cfg` may be NULL (all defaults). */
+int tc_serve_create(const tc_serve_config* cfg, tc_server** out);
+
+/*
+ * Queues one graph.  rowptr[n + 1] and colidx[m] are HOST arrays that must stay valid
+ * and unchanged until this request's result has been returned by tc_serve_poll.  Writes
+ * the request's ticket.  Returns TC_ERR_INVALID_ARG for null pointers,
+ * TC_ERR_TOO_LARGE for n >= 2^31 or m >= 2^32; a request whose footprint exceeds the
+ * whole budget is accepted and completes at once with TC_ERR_OUT_OF_MEMORY.
+ */
+int tc_serve_submit(tc_server* server, const uint32_t* rowptr, const uint32_t* colidx,
+                    uint32_t n, uint64_t m, uint64_t* ticket);
+
+/*
+ * Moves up to `cap` completed results (completion order) into the HOST array `out`;
+ * *got receives how many.  Waits up to timeout_ms for the first one (0 = do not wait,
+ * negative = wait without limit).
+ */
+int tc_serve_poll(tc_server* server, tc_serve_result* out, uint32_t cap, uint32_t* got,
+                  int32_t timeout_ms);
+
+/* Counters of the server (HOST struct). */
+int tc_serve_get_stats(tc_server* server, tc_serve_stats* stats);
+
+/* Waits until every submitted request has completed, then stops the server's threads
+   and frees it.  Results not yet polled are dropped. */
+int tc_serve_destroy(tc_server* server);
+
+/*
  * tc_validate_csr — checks the graph format contract on the device: rowptr[0] == 0,
  * non-decreasing, rowptr[n] == m, IDs < n, rows strictly increasing, no self-loops,
  * symmetric.  Returns TC_OK or TC_ERR_INVALID_GRAPH (or an argument/HIP error).

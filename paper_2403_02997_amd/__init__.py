@@ -8,6 +8,8 @@ C ABI of ``include/tc.h``; :mod:`.tc` is the Python binding with the same names.
 """
 from .tc import (  # noqa: F401
     EXPORTS,
+    Server,
+    ServeResult,
     Stats,
     TCError,
     as_u64,

@@ -194,6 +194,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u64>(kCounterSlots * kNumCtr);
     c.take<u64>(kNumCtr);
     c.take<u32>(4);
+    c.take<u32>(4);                  // cc mode
     bytes = c.off + 256;
   }
   DevAlloc ws;
@@ -221,6 +222,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u64* outc = c.take<u64>(kNumCtr);
   const size_t ctl_bytes = (char*)(outc + kNumCtr) - (char*)ctl;
   u32* tail4 = c.take<u32>(4);
+  u32* cc_mode = c.take<u32>(4);
   if (level_out) level = level_out;
 
   TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
@@ -231,7 +233,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   // ---- a1: component roots ----
   timer.mark();
   launch_tile_rows(rowptr, n, m, tile_row, s);
-  launch_cc(rowptr, colidx, tile_row, n, m, parent, s);
+  launch_cc(rowptr, colidx, tile_row, n, m, parent, cc_mode, s);
   TC_LAUNCHED();
 
   // ---- a2: level BFS ----

@@ -178,29 +178,58 @@ void launch_extract_write(const u32* rowptr, const u32* colidx, const u32* tile_
 }
 
 // ---- planning: split the staged endpoints x into the three intersection classes ----
-__global__ void k_plan(const u32* __restrict__ rowptr, const u32* __restrict__ hoff, u32 n,
-                       IsectParams p, u32* __restrict__ wave_x, u32* __restrict__ block_x,
-                       u32* __restrict__ block_items, Plan* __restrict__ plan) {
-  const u32 stride = gridDim.x * blockDim.x;
-  const u32 nr = (n + kWave - 1) / kWave * kWave;
+// Each workgroup classifies kPlanPer * 256 consecutive vertices per pass and reserves
+// its slots of both lists with one global atomic each (a per-wavefront atomic on one
+// shared counter serialises at the L2 for millions of vertices).
+constexpr u32 kPlanPer = 8;
+
+__global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
+                                              const u32* __restrict__ hoff, u32 n, IsectParams p,
+                                              u32* __restrict__ wave_x, u32* __restrict__ block_x,
+                                              u32* __restrict__ block_items,
+                                              Plan* __restrict__ plan) {
+  __shared__ u32 s_tmp[2][256 / kWave];
+  __shared__ u32 s_base[2];
+  const u32 span = kPlanPer * blockDim.x;
   u32 lane_edges = 0;
-  for (u32 x = blockIdx.x * blockDim.x + threadIdx.x; x < nr; x += stride) {
-    u32 np = 0, d = 0;
-    if (x < n) {
-      np = hoff[x + 1] - hoff[x];
-      d = rowptr[x + 1] - rowptr[x];
+  for (u32 base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+    u32 cls = 0;  // 2 bits per vertex: 1 wavefront class, 2 workgroup class
+    u32 cw = 0, cb = 0;
+#pragma unroll
+    for (u32 k = 0; k < kPlanPer; ++k) {
+      const u32 x = base + k * blockDim.x + threadIdx.x;
+      u32 np = 0, d = 0;
+      if (x < n) {
+        np = hoff[x + 1] - hoff[x];
+        d = rowptr[x + 1] - rowptr[x];
+      }
+      const u32 c = np == 0 ? 0u : d <= p.lane_max ? 0u : d <= p.wave_max ? 1u : 2u;
+      if (np > 0 && d <= p.lane_max) lane_edges += np;
+      cls |= c << (2 * k);
+      cw += c == 1u;
+      cb += c == 2u;
     }
-    const bool is_lane = np > 0 && d <= p.lane_max;
-    const bool is_wave = np > 0 && d > p.lane_max && d <= p.wave_max;
-    const bool is_block = np > 0 && d > p.wave_max;
-    if (is_lane) lane_edges += np;
-    const u32 pw = wave_append(&plan->num_wave_x, is_wave);
-    if (is_wave) wave_x[pw] = x;
-    const u32 pb = wave_append(&plan->num_block_x, is_block);
-    if (is_block) {
-      block_x[pb] = x;
-      block_items[pb] = (np + p.seg - 1) / p.seg;
+    u32 tw, tb;
+    const u32 iw = block_incl_scan(cw, s_tmp[0], &tw);
+    const u32 ib = block_incl_scan(cb, s_tmp[1], &tb);
+    if (threadIdx.x == 0) {
+      s_base[0] = tw ? atomicAdd(&plan->num_wave_x, tw) : 0u;
+      s_base[1] = tb ? atomicAdd(&plan->num_block_x, tb) : 0u;
     }
+    __syncthreads();
+    u32 pw = s_base[0] + iw - cw, pb = s_base[1] + ib - cb;
+#pragma unroll
+    for (u32 k = 0; k < kPlanPer; ++k) {
+      const u32 x = base + k * blockDim.x + threadIdx.x;
+      const u32 c = (cls >> (2 * k)) & 3u;
+      if (c == 1u) wave_x[pw++] = x;
+      if (c == 2u) {
+        block_x[pb] = x;
+        block_items[pb] = (hoff[x + 1] - hoff[x] + p.seg - 1) / p.seg;
+        ++pb;
+      }
+    }
+    __syncthreads();  // s_base is rewritten by the next pass
   }
   lane_edges = wave_sum_u32(lane_edges);
   if (lane_id() == 0 && lane_edges) atomicAdd(&plan->lane_edges, lane_edges);
@@ -209,7 +238,7 @@ __global__ void k_plan(const u32* __restrict__ rowptr, const u32* __restrict__ h
 void launch_plan(const u32* rowptr, const u32* hoff, u32 n, IsectParams p, u32* wave_x,
                  u32* block_x, u32* block_items, Plan* plan, hipStream_t s) {
   if (n == 0) return;
-  const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
+  const u32 g = min(cdiv(n, 256 * kPlanPer), (u32)num_cus() * 4);
   hipLaunchKernelGGL(k_plan, dim3(g), dim3(256), 0, s, rowptr, hoff, n, p, wave_x, block_x,
                      block_items, plan);
 }

@@ -54,22 +54,14 @@ __global__ void k_cc_init(const u32* __restrict__ rowptr, const u32* __restrict_
   }
 }
 
-__global__ void __launch_bounds__(kTileThreads) k_cc_hook(
-    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
-    const u32* __restrict__ tile_row, u32 m, u32* parent) {
-  __shared__ u32 s_rp[kTileRowCap];
-  const u32 ntiles = (m + kTile - 1) / kTile;
-  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const TileInfo ti = tile_begin(rowptr, tile_row, t, m, s_rp);
-    for (u32 e = ti.e0 + threadIdx.x; e < ti.e1; e += blockDim.x) {
-      const u32 u = tile_row_of(ti, s_rp, rowptr, e);
-      const u32 v = colidx[e];
-      if (v < u) {
-        // skip edges already joined by the initial parents
-        if (load_coherent(&parent[u]) != v) cc_union(parent, u, v);
-      }
-    }
-    __syncthreads();
+// Second sampled link: every vertex joins its second-smallest neighbour.  With the
+// initial parents this already assembles most of a dominant component (Afforest,
+// Sutton, Ben-Nun & Barak, IPDPS 2018).
+__global__ void k_cc_sample(const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+                            u32 n, u32* parent) {
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const u32 lo = rowptr[v], hi = rowptr[v + 1];
+    if (hi - lo >= 2) cc_union(parent, v, colidx[lo + 1]);
   }
 }
 
@@ -78,16 +70,75 @@ __global__ void k_cc_compress(u32 n, u32* parent) {
     parent[v] = cc_find(parent, v);
 }
 
+// The most frequent root among kModeSamples spread-out vertices (one workgroup).
+constexpr u32 kModeSamples = 1024;
+
+__global__ void __launch_bounds__(kModeSamples) k_cc_mode(u32 n, u32* parent,
+                                                           u32* __restrict__ mode) {
+  __shared__ u32 s_root[kModeSamples];
+  __shared__ u64 s_best[kModeSamples / kWave];
+  const u32 i = threadIdx.x;
+  const u32 v = (u32)(((u64)i * 2654435761ull + 12345u) % n);
+  const u32 r = cc_find(parent, v);
+  s_root[i] = r;
+  __syncthreads();
+  u32 cnt = 0;
+  for (u32 j = 0; j < kModeSamples; ++j) cnt += s_root[j] == r;
+  // largest (count, root) pair; ties go to the larger root value, any choice is correct
+  u64 key = ((u64)cnt << 32) | r;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const u64 o = __shfl_xor(key, off, kWave);
+    key = o > key ? o : key;
+  }
+  if (lane_id() == 0) s_best[i / kWave] = key;
+  __syncthreads();
+  if (i == 0) {
+    u64 b = 0;
+    for (u32 w = 0; w < kModeSamples / kWave; ++w) b = s_best[w] > b ? s_best[w] : b;
+    *mode = (u32)b;
+  }
+}
+
+// Remaining links: every vertex outside the dominant component joins all its
+// neighbours.  An edge is skipped only when both endpoints already belong to the
+// dominant component, because a vertex skips its list only once it is found inside it.
+__global__ void __launch_bounds__(256) k_cc_finish(const u32* __restrict__ rowptr,
+                                                   const u32* __restrict__ colidx, u32 n,
+                                                   u32* parent, const u32* __restrict__ mode) {
+  const u32 c = *mode;
+  const u32 lane = lane_id();
+  const u32 nr = (n + kWave - 1) / kWave * kWave;
+  for (u32 u = blockIdx.x * blockDim.x + threadIdx.x; u < nr; u += gridDim.x * blockDim.x) {
+    u32 lo = 0, d = 0;
+    if (u < n && load_coherent(&parent[u]) != c) {
+      lo = rowptr[u];
+      d = rowptr[u + 1] - lo;
+    }
+    const bool big = d > kWave / 2;
+    if (!big)
+      for (u32 j = 0; j < d; ++j) cc_union(parent, u, colidx[lo + j]);
+    u64 bigmask = __ballot(big);
+    while (bigmask) {
+      const int b = __ffsll((unsigned long long)bigmask) - 1;
+      bigmask &= bigmask - 1;
+      const u32 bu = __shfl(u, b, kWave), blo = __shfl(lo, b, kWave), bd = __shfl(d, b, kWave);
+      for (u32 j = lane; j < bd; j += kWave) cc_union(parent, bu, colidx[blo + j]);
+    }
+  }
+}
+
 void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
-               u32* parent, hipStream_t s) {
+               u32* parent, u32* mode, hipStream_t s) {
+  (void)tile_row;
   if (n == 0) return;
   const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
   hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
   if (m > 0) {
-    const u32 ntiles = cdiv(m, kTile);
-    const u32 gt = min(ntiles, (u32)num_cus() * 8);
-    hipLaunchKernelGGL(k_cc_hook, dim3(gt), dim3(kTileThreads), 0, s, rowptr, colidx, tile_row,
-                       m, parent);
+    hipLaunchKernelGGL(k_cc_sample, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
+    hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
+    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(kModeSamples), 0, s, n, parent, mode);
+    hipLaunchKernelGGL(k_cc_finish, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent, mode);
   }
   hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
 }

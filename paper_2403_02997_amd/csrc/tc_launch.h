@@ -47,8 +47,10 @@ struct Item {
 
 // ---- prep ----
 void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_t s);
+// Component roots: parent[v] = smallest vertex ID of v's component.  `mode` is one
+// device word of scratch.
 void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
-               u32* parent, hipStream_t s);
+               u32* parent, u32* mode, hipStream_t s);
 void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, hipStream_t s);
 // Exclusive scan of in[0..count) into out[0..count] (out[count] = total); in may == out.
 // tmp needs scan_tmp_words(count) words.

@@ -35,6 +35,11 @@ EXPORTS = (
     "tc_count_per_vertex",
     "tc_count_batch",
     "tc_count_batch_workspace_size",
+    "tc_serve_create",
+    "tc_serve_submit",
+    "tc_serve_poll",
+    "tc_serve_get_stats",
+    "tc_serve_destroy",
     "tc_validate_csr",
     "tc_set_isect_params",
     "tc_get_isect_params",
@@ -82,6 +87,36 @@ class Stats:
     class_staged: tuple = (0, 0, 0)
 
 
+class _ServeConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("small_max_entries", ctypes.c_uint64),
+        ("batch_max_graphs", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("batch_max_entries", ctypes.c_uint64),
+        ("large_min_entries", ctypes.c_uint64),
+    ]
+
+
+class _ServeResult(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("triangles", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("path", ctypes.c_uint32),
+        ("input_edges", ctypes.c_uint64),
+        ("submit_s", ctypes.c_double),
+        ("admit_s", ctypes.c_double),
+        ("done_s", ctypes.c_double),
+    ]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "submitted", "completed", "rejected", "batches", "singles", "queued", "in_flight",
+        "hbm_in_use", "hbm_peak", "hbm_budget")]
+
+
 _lib = None
 
 
@@ -108,6 +143,17 @@ def load() -> ctypes.CDLL:
     lib.tc_count_batch.restype = i
     lib.tc_count_batch_workspace_size.argtypes = [u32, u64]
     lib.tc_count_batch_workspace_size.restype = sz
+    P = ctypes.POINTER
+    lib.tc_serve_create.argtypes = [P(_ServeConfig), P(vp)]
+    lib.tc_serve_create.restype = i
+    lib.tc_serve_submit.argtypes = [vp, vp, vp, u32, u64, P(u64)]
+    lib.tc_serve_submit.restype = i
+    lib.tc_serve_poll.argtypes = [vp, P(_ServeResult), u32, P(u32), ctypes.c_int32]
+    lib.tc_serve_poll.restype = i
+    lib.tc_serve_get_stats.argtypes = [vp, P(_ServeStats)]
+    lib.tc_serve_get_stats.restype = i
+    lib.tc_serve_destroy.argtypes = [vp]
+    lib.tc_serve_destroy.restype = i
     lib.tc_validate_csr.argtypes = [vp, vp, u32, u64, vp]
     lib.tc_validate_csr.restype = i
     lib.tc_set_isect_params.argtypes = [u32, u32, u32, u32]
@@ -289,6 +335,96 @@ def tc_profile_step_name(step: int) -> str:
 
 def tc_version() -> int:
     return int(load().tc_version())
+
+
+# --------------------------------------------------------------------------------------
+# continuous-batching server
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class ServeResult:
+    ticket: int
+    triangles: int
+    status: int
+    path: int  # 0 batched, 1 single-graph medium, 3 single-graph large, 2 rejected
+    input_edges: int
+    submit_s: float
+    admit_s: float
+    done_s: float
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.submit_s
+
+
+class Server:
+    """tc_serve_* on the current device.  submit() takes HOST CSR arrays (numpy arrays or
+    CPU torch tensors, e.g. pinned ones) and keeps references to them until their result
+    has been polled (the C ABI's lifetime rule)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, small_max_entries: int = 0,
+                 batch_max_graphs: int = 0, batch_max_entries: int = 0,
+                 large_min_entries: int = 0):
+        lib = load()
+        cfg = _ServeConfig(int(hbm_budget_bytes), int(small_max_entries),
+                           int(batch_max_graphs), 0, int(batch_max_entries),
+                           int(large_min_entries))
+        h = ctypes.c_void_p()
+        _check(lib.tc_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "tc_serve_create")
+        self._h = h
+        self._held = {}
+
+    @staticmethod
+    def _host(a):
+        if isinstance(a, torch.Tensor):
+            if a.is_cuda or a.element_size() != 4 or not a.is_contiguous():
+                raise ValueError("host CSR tensors must be contiguous 4-byte CPU tensors")
+            return a, a.data_ptr() if a.numel() else None, a.numel()
+        arr = np.ascontiguousarray(a, dtype=np.uint32)
+        return arr, arr.ctypes.data if arr.size else None, arr.shape[0]
+
+    def submit(self, rowptr, colidx) -> int:
+        rp, rp_ptr, rp_len = self._host(rowptr)
+        ci, ci_ptr, m = self._host(colidx)
+        n = rp_len - 1
+        if n < 0:
+            raise ValueError("rowptr needs n + 1 >= 1 entries")
+        t = ctypes.c_uint64(0)
+        rc = load().tc_serve_submit(self._h, rp_ptr, ci_ptr, n, m, ctypes.byref(t))
+        _check(rc, "tc_serve_submit")
+        self._held[int(t.value)] = (rp, ci)
+        return int(t.value)
+
+    def poll(self, cap: int = 256, timeout_ms: int = 0):
+        arr = (_ServeResult * cap)()
+        got = ctypes.c_uint32(0)
+        _check(load().tc_serve_poll(self._h, arr, cap, ctypes.byref(got), int(timeout_ms)),
+               "tc_serve_poll")
+        out = []
+        for k in range(got.value):
+            r = arr[k]
+            self._held.pop(int(r.ticket), None)
+            out.append(ServeResult(int(r.ticket), int(r.triangles), int(r.status), int(r.path),
+                                   int(r.input_edges), float(r.submit_s), float(r.admit_s),
+                                   float(r.done_s)))
+        return out
+
+    def stats(self) -> dict:
+        st = _ServeStats()
+        _check(load().tc_serve_get_stats(self._h, ctypes.byref(st)), "tc_serve_get_stats")
+        return {k: int(getattr(st, k)) for k, _ in _ServeStats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().tc_serve_destroy(self._h), "tc_serve_destroy")
+            self._h = None
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def as_u64(t: torch.Tensor) -> np.ndarray:

@@ -91,3 +91,18 @@ def test_isect_params_validation(lib):
     assert lib.tc_set_isect_params(8, 256, 2048, 128) == 0
     assert lib.tc_get_isect_params(arr) == 0 and tuple(arr) == (8, 256, 2048, 128)
     assert lib.tc_set_isect_params(*saved) == 0
+
+
+def test_serve_argument_errors_without_gpu(lib):
+    vp = ctypes.c_void_p
+    lib.tc_serve_submit.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.c_uint64, vp]
+    lib.tc_serve_poll.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_int32]
+    lib.tc_serve_get_stats.argtypes = [vp, vp]
+    lib.tc_serve_destroy.argtypes = [vp]
+    lib.tc_serve_create.argtypes = [vp, vp]
+    t = ctypes.c_uint64(0)
+    assert lib.tc_serve_create(None, None) == -1
+    assert lib.tc_serve_submit(None, None, None, 0, 0, ctypes.byref(t)) == -1
+    assert lib.tc_serve_poll(None, None, 0, None, 0) == -1
+    assert lib.tc_serve_get_stats(None, None) == -1
+    assert lib.tc_serve_destroy(None) == -1

@@ -1,0 +1,135 @@
+"""GPU tests of the continuous-batching server (tc_serve_*): every result equals the
+standalone tc_count result (and the oracle's), whether the request went through a
+batched launch or its own single-graph call, with admission under a small HBM budget
+and a request that can never fit."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pool():
+    gs = [gg.empty_graph(0), gg.empty_graph(5), gg.complete(9), gg.wheel(300),
+          gg.friendship(25), gg.tri_grid(30, 40, 0.05, 3)]
+    gs += [gg.rmat(s, 16, 500 + s) for s in range(6, 14)]
+    gs += [gg.erdos_renyi(1 << s, 12, 600 + s) for s in range(8, 13)]
+    return gs
+
+
+_cache = {}
+
+
+def pool_with_counts(tc_lib):
+    if "p" not in _cache:
+        gs = pool()
+        ref = [oracle.count(g) for g in gs]
+        for g, t in zip(gs, ref):
+            rp, ci = tc_lib.to_device(g.rowptr, g.colidx)
+            assert tc_lib.tc_count(rp, ci) == t, g.name
+        _cache["p"] = (gs, ref)
+    return _cache["p"]
+
+
+def drain(srv, want, deadline_s=120.0):
+    out = []
+    t_end = time.time() + deadline_s
+    while len(out) < want:
+        assert time.time() < t_end, f"server returned {len(out)} of {want} results"
+        out += srv.poll(cap=256, timeout_ms=200)
+    return out
+
+
+def footprint_batched(g):
+    return 4 * (g.n + 1) + 4 * g.nnz + 13 * (g.n + 1) + 64
+
+
+def test_serve_results_equal_standalone(tc_lib):
+    gs, ref = pool_with_counts(tc_lib)
+    rng = np.random.default_rng(77)
+    picks = rng.integers(0, len(gs), size=150)
+    say(f"[serve] 150 requests over {len(gs)} graphs, mixed paths")
+    with tc_lib.Server(small_max_entries=20000, batch_max_graphs=32,
+                       large_min_entries=60000) as srv:
+        tickets = {}
+
+        def producer():
+            for k, i in enumerate(picks):
+                g = gs[int(i)]
+                tickets[srv.submit(g.rowptr, g.colidx)] = int(i)
+                if k % 10 == 0:
+                    time.sleep(0.002)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        res = drain(srv, len(picks))
+        st = srv.stats()
+    assert len({r.ticket for r in res}) == len(picks)
+    paths = set()
+    for r in res:
+        i = tickets[r.ticket]
+        assert r.status == 0, (r, gs[i].name)
+        assert r.triangles == ref[i], gs[i].name
+        assert r.input_edges == gs[i].nnz // 2
+        assert r.submit_s <= r.admit_s <= r.done_s
+        paths.add(r.path)
+        nnz = gs[i].nnz
+        assert r.path == (0 if nnz <= 20000 else 1 if nnz < 60000 else 3)
+    assert paths == {0, 1, 3}
+    assert st["completed"] == len(picks) and st["in_flight"] == 0 and st["hbm_in_use"] == 0
+    assert st["batches"] >= 1 and st["singles"] >= 1
+
+
+def test_serve_admission_under_small_budget(tc_lib):
+    gs, ref = pool_with_counts(tc_lib)
+    small = [i for i, g in enumerate(gs) if g.nnz <= 40000]
+    budget = 3 * max(footprint_batched(gs[i]) for i in small)
+    say(f"[serve] admission with a {budget}-byte budget")
+    rng = np.random.default_rng(5)
+    picks = [small[int(k)] for k in rng.integers(0, len(small), size=120)]
+    with tc_lib.Server(hbm_budget_bytes=budget, small_max_entries=1 << 22) as srv:
+        tickets = {}
+        for i in picks:
+            tickets[srv.submit(gs[i].rowptr, gs[i].colidx)] = i
+        st0 = srv.stats()
+        res = drain(srv, len(picks))
+        st = srv.stats()
+    assert st0["submitted"] == len(picks)
+    assert st["hbm_peak"] <= budget
+    assert st["completed"] == len(picks) and st["hbm_in_use"] == 0
+    for r in res:
+        assert r.status == 0 and r.triangles == ref[tickets[r.ticket]]
+
+
+def test_serve_rejects_a_request_that_cannot_fit(tc_lib):
+    big = gg.rmat(12, 16, 9)
+    tiny = gg.complete(6)
+    with tc_lib.Server(hbm_budget_bytes=1 << 16) as srv:
+        t_big = srv.submit(big.rowptr, big.colidx)
+        t_tiny = srv.submit(tiny.rowptr, tiny.colidx)
+        res = {r.ticket: r for r in drain(srv, 2)}
+    assert res[t_big].status == -2  # TC_ERR_OUT_OF_MEMORY
+    assert res[t_big].path == 2
+    assert res[t_tiny].status == 0 and res[t_tiny].triangles == 20
+
+
+def test_serve_destroy_waits_for_submitted_work(tc_lib):
+    gs, ref = pool_with_counts(tc_lib)
+    srv = tc_lib.Server(small_max_entries=20000)
+    for g in gs:
+        srv.submit(g.rowptr, g.colidx)
+    srv.close()  # returns once every request has completed
+    torch.cuda.synchronize()
