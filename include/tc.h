@@ -50,7 +50,7 @@ typedef enum {
   TC_ERR_OUT_OF_MEMORY = -2,  /* device workspace allocation failed                 */
   TC_ERR_HIP = -3,            /* a HIP runtime call failed                          */
   TC_ERR_INVALID_GRAPH = -4,  /* tc_validate_csr found a contract violation         */
-  TC_ERR_TOO_LARGE = -5,      /* n >= 2^31 or m >= 2^32                             */
+  TC_ERR_TOO_LARGE = -5,      /* n >= 2^30 or m >= 2^32                             */
   TC_ERR_INTERNAL = -6        /* an internal consistency check failed               */
 } tc_status;
 
@@ -77,7 +77,7 @@ typedef struct {
  * Allocates its device workspace stream-ordered on `stream`, frees it before returning,
  * and synchronises `stream`.  n == 0 or m == 0 gives T = 0 without a launch.
  * Returns TC_ERR_INVALID_ARG for null pointers (when m > 0) or a null `count`,
- * TC_ERR_TOO_LARGE for n >= 2^31, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
+ * TC_ERR_TOO_LARGE for n >= 2^30 or m >= 2^32, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
 int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
              hipStream_t stream, uint64_t* count);
@@ -116,7 +116,7 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
  * With a caller workspace the call allocates nothing, issues no memset, never
  * synchronises and reads no device data on the host, so it can be captured into a HIP
  * graph and replayed; a workspace must not be shared by calls that overlap in time.
- * Per graph: n_g < 2^31 and m_g < 2^32 (precondition).  Returns TC_ERR_INVALID_ARG
+ * Per graph: n_g < 2^30 and m_g < 2^32 (precondition).  Returns TC_ERR_INVALID_ARG
  * (null pointers, workspace too small), TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
 int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
@@ -182,7 +182,7 @@ int tc_serve_create(const tc_serve_config* cfg, tc_server** out);
  * Queues one graph.  rowptr[n + 1] and colidx[m] are HOST arrays that must stay valid
  * and unchanged until this request's result has been returned by tc_serve_poll.  Writes
  * the request's ticket.  Returns TC_ERR_INVALID_ARG for null pointers,
- * TC_ERR_TOO_LARGE for n >= 2^31 or m >= 2^32; a request whose footprint exceeds the
+ * TC_ERR_TOO_LARGE for n >= 2^30 or m >= 2^32; a request whose footprint exceeds the
  * whole budget is accepted and completes at once with TC_ERR_OUT_OF_MEMORY.
  */
 int tc_serve_submit(tc_server* server, const uint32_t* rowptr, const uint32_t* colidx,
@@ -216,7 +216,7 @@ int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, 
  * Intersection tuning (used by the autotuner).  The staged endpoint x of a cover edge
  * goes to the lane class when d(x) <= lane_max, to the wavefront class when
  * d(x) <= wave_max (<= 512), else to the workgroup class, which stages N(x) in chunks
- * of `chunk` (<= 16384) entries and takes `seg` (<= 1024) partners per work item.  The setting
+ * of `chunk` (<= 16384; default 4096) entries and takes `seg` (<= 1024) partners per work item.  The setting
  * is process-wide; change it only while no count is running.  Out-of-range values give
  * TC_ERR_INVALID_ARG and leave the setting unchanged.
  */

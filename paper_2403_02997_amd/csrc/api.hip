@@ -103,7 +103,7 @@ IsectParams default_params() {
   IsectParams p;
   p.lane_max = 16;
   p.wave_max = 512;
-  p.chunk = 16384;
+  p.chunk = 4096;
   p.seg = 1024;
   return p;
 }
@@ -289,11 +289,12 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   if (h_plan.lane_edges)
     launch_isect_lane(rowptr, colidx, vinfo, hoff, hadj, htile_row, n, h_ns, prm, ctr, tri, s);
   timer.mark();
-  if (h_items) launch_tail4(colidx, m, tail4, s);
+  launch_tail4(colidx, m, tail4, s);
   launch_isect_block(rowptr, colidx, m, tail4, vinfo, hoff, hadj, items, h_items, prm, plan, ctr,
                      tri, s);
   timer.mark();
-  launch_isect_wave(rowptr, colidx, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan, ctr, tri, s);
+  launch_isect_wave(rowptr, colidx, m, tail4, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan,
+                    ctr, tri, s);
   timer.mark();
   // ---- a5: reduction ----
   launch_finalize(ctr, outc, s);
@@ -310,7 +311,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
 }
 
 int check_args(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m) {
-  if (n >= 0x80000000u) return TC_ERR_TOO_LARGE;
+  if (n >= 0x40000000u) return TC_ERR_TOO_LARGE;  // LDS hash keys hold (w << 1) | same < 2^31
   if (m >= 0x100000000ull) return TC_ERR_TOO_LARGE;
   if (n > 0 && !rowptr) return TC_ERR_INVALID_ARG;
   if (m > 0 && (!colidx || n == 0)) return TC_ERR_INVALID_ARG;

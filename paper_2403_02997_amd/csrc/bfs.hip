@@ -19,35 +19,64 @@ static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
 constexpr int kBfsThreads = 256;
 constexpr u32 kBfsLaneMax = 32;  // frontier vertices up to this degree expand per lane
+constexpr u32 kBfsPer = 8;       // vertices per thread and pass in the vertex sweeps
 
 __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict__ rowptr,
                                                           const u32* __restrict__ parent, u32 n,
                                                           u32* __restrict__ level,
                                                           u32* __restrict__ queue0,
                                                           BfsCtl* __restrict__ ctl) {
+  __shared__ u32 s_tmp[kBfsThreads / kWave];
+  __shared__ u32 s_base;
   u64 mu = 0;
   u32 roots = 0;
-  const u32 stride = gridDim.x * blockDim.x;
-  const u32 nr = (n + kWave - 1) / kWave * kWave;  // whole wavefronts iterate together
-  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < nr; v += stride) {
-    bool root = false, push = false;
-    u32 d = 0;
-    if (v < n) {
-      d = rowptr[v + 1] - rowptr[v];
-      root = parent[v] == v;
-      level[v] = root ? 0u : kInf;
-      push = root && d > 0;
-      roots += root;
-      if (!root) mu += d;
+  const u32 span = kBfsPer * blockDim.x;
+  for (u32 base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+    u32 bits = 0, cnt = 0;
+#pragma unroll
+    for (u32 k = 0; k < kBfsPer; ++k) {
+      const u32 v = base + k * blockDim.x + threadIdx.x;
+      if (v < n) {
+        const u32 d = rowptr[v + 1] - rowptr[v];
+        const bool root = parent[v] == v;
+        level[v] = root ? 0u : kInf;
+        roots += root;
+        if (!root) mu += d;
+        if (root && d > 0) {
+          bits |= 1u << k;
+          ++cnt;
+        }
+      }
     }
-    const u32 pos = wave_append(&ctl->qlen[0], push);
-    if (push) queue0[pos] = v;
+    u32 tot;
+    const u32 incl = block_incl_scan(cnt, s_tmp, &tot);
+    if (threadIdx.x == 0) s_base = tot ? atomicAdd(&ctl->qlen[0], tot) : 0u;
+    __syncthreads();
+    u32 pos = s_base + incl - cnt;
+#pragma unroll
+    for (u32 k = 0; k < kBfsPer; ++k)
+      if (bits & (1u << k)) queue0[pos++] = base + k * blockDim.x + threadIdx.x;
+    __syncthreads();  // s_base is rewritten by the next pass
   }
+  // one atomic per workgroup and counter
+  __shared__ u64 s_mu[kBfsThreads / kWave];
+  __shared__ u32 s_roots[kBfsThreads / kWave];
   mu = wave_sum_u64(mu);
   roots = wave_sum_u32(roots);
   if (lane_id() == 0) {
-    if (mu) atomicAdd((unsigned long long*)&ctl->mu, (unsigned long long)mu);
-    if (roots) atomicAdd(&ctl->num_roots, roots);
+    s_mu[threadIdx.x / kWave] = mu;
+    s_roots[threadIdx.x / kWave] = roots;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 a = 0;
+    u32 b = 0;
+    for (u32 w = 0; w < blockDim.x / kWave; ++w) {
+      a += s_mu[w];
+      b += s_roots[w];
+    }
+    if (a) atomicAdd((unsigned long long*)&ctl->mu, (unsigned long long)a);
+    if (b) atomicAdd(&ctl->num_roots, b);
   }
 }
 
@@ -131,27 +160,61 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
     }
   } else {
     // ---- bottom-up: every unvisited vertex looks for a neighbour on level k ----
-    const u32 nr = (n + kWave - 1) / kWave * kWave;
-    for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < nr; v += stride) {
-      bool found = false;
-      u32 d = 0;
-      if (v < n && level[v] == kInf) {
-        const u32 lo = rowptr[v], hi = rowptr[v + 1];
-        d = hi - lo;
-        for (u32 j = lo; j < hi; ++j) {
-          if (level[colidx[j]] == k) {
-            found = true;
-            break;
+    __shared__ u32 s_tmp[kBfsThreads / kWave];
+    __shared__ u32 s_base;
+    const u32 span = kBfsPer * blockDim.x;
+    for (u32 base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+      u32 bits = 0, cnt = 0;
+#pragma unroll
+      for (u32 kk = 0; kk < kBfsPer; ++kk) {
+        const u32 v = base + kk * blockDim.x + threadIdx.x;
+        u32 lo = 0, d = 0;
+        if (v < n && level[v] == kInf) {
+          lo = rowptr[v];
+          d = rowptr[v + 1] - lo;
+        }
+        bool found = false;
+        // short lists: per lane, four neighbours per step
+        const bool big = d > kBfsLaneMax;
+        if (!big) {
+          for (u32 j = 0; j < d && !found; j += 4) {
+            u32 w[4];
+#pragma unroll
+            for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : 0u;
+#pragma unroll
+            for (u32 i = 0; i < 4; ++i) found |= j + i < d && level[w[i]] == k;
           }
         }
-        if (found) level[v] = next;
+        // long lists: the whole wavefront, 64 neighbours per step
+        u64 bm = __ballot(big);
+        while (bm) {
+          const int b = __ffsll((unsigned long long)bm) - 1;
+          bm &= bm - 1;
+          const u32 blo = __shfl(lo, b, kWave), bd = __shfl(d, b, kWave);
+          bool bf = false;
+          for (u32 j0 = 0; j0 < bd && !bf; j0 += kWave) {
+            const u32 j = j0 + lane;
+            bf = __ballot(j < bd && level[colidx[blo + j]] == k) != 0;
+          }
+          if ((int)lane == b) found = bf;
+        }
+        if (found) {
+          level[v] = next;
+          bits |= 1u << kk;
+          ++cnt;
+          mf += d;
+          mu_dec += d;
+        }
       }
-      const u32 pos = wave_append(qlen_out, found);
-      if (found) {
-        qout[pos] = v;
-        mf += d;
-        mu_dec += d;
-      }
+      u32 tot;
+      const u32 incl = block_incl_scan(cnt, s_tmp, &tot);
+      if (threadIdx.x == 0) s_base = tot ? atomicAdd(qlen_out, tot) : 0u;
+      __syncthreads();
+      u32 pos = s_base + incl - cnt;
+#pragma unroll
+      for (u32 kk = 0; kk < kBfsPer; ++kk)
+        if (bits & (1u << kk)) qout[pos++] = base + kk * blockDim.x + threadIdx.x;
+      __syncthreads();  // s_base is rewritten by the next pass
     }
   }
 
@@ -199,7 +262,9 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
   }
 }
 
-u32 bfs_grid(u32 n) { return max(1u, min(cdiv(n, kBfsThreads), (u32)num_cus() * 4)); }
+// Two workgroups per CU: the per-level totals cost three same-address atomics per
+// workgroup.
+u32 bfs_grid(u32 n) { return max(1u, min(cdiv(n, kBfsThreads), (u32)num_cus() * 2)); }
 
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
                      BfsCtl* ctl, hipStream_t s) {

@@ -22,9 +22,11 @@ namespace tc {
 
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
-constexpr int kWaveSlots = 1024;   // LDS hash slots per wavefront (d(x) <= 512)
+constexpr int kWaveSlots = 2048;   // LDS hash slots per wavefront (d(x) <= 512)
 constexpr int kIsectThreads = 256;
 constexpr int kUnroll = 4;         // independent list loads in flight per lane
+static_assert(kUnroll == 4, "the wavefront kernel packs one mark byte per window in a word");
+constexpr u32 kWaveClaim = 16;     // wavefront-class vertices claimed per counter atomic
 
 // ---- lane class: one thread per cover edge ---------------------------------------------
 template <bool PV>
@@ -76,28 +78,42 @@ __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
 }
 
 // ---- wave class: one wavefront per staged vertex x ---------------------------------------
-template <bool PV>
+// N(x) goes to a per-wavefront LDS hash set.  The partners' lists are taken 64 at a time,
+// padded out to whole 16-byte quads (VEC) and concatenated; each lane then loads one quad
+// per window, so a lane has 4 * kUnroll list elements in flight.  The partner of a quad
+// comes from the partners' quad ends: those inside the current windows mark their
+// positions in LDS, and a ballot plus a population count gives every lane its partner.
+template <bool PV, bool VEC>
 __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
-    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
-    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hoff, const u32* __restrict__ hadj,
-    const u32* __restrict__ wave_x, u32 nwx, Plan* __restrict__ plan, u64* __restrict__ ctr,
-    u64* __restrict__ tri) {
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
+    const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
+    const u32* __restrict__ hoff, const u32* __restrict__ hadj, const u32* __restrict__ wave_x,
+    u32 nwx, Plan* __restrict__ plan, u64* __restrict__ ctr, u64* __restrict__ tri) {
   constexpr int kW = kIsectThreads / kWave;
+  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
   __shared__ __align__(16) u32 s_table[kW][kWaveSlots];
-  __shared__ u32 s_incl[kW][kWave];
-  __shared__ u32 s_start[kW][kWave];
-  __shared__ u32 s_y[kW][kWave];
+  __shared__ uint4 s_pinfo[kW][kWave];  // {quad base, lo, hi, y} of each compacted partner
+  __shared__ u32 s_end[kW][kWave];
+  __shared__ u32 s_mark[kW][kWave];
   __shared__ u64 s_red[5 * kW];
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   u32* table = s_table[wid];
+  const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
   Counts c{0, 0, 0, 0, 0};
+  // Vertices are claimed kWaveClaim at a time: one counter atomic per vertex would
+  // serialise hundreds of thousands of same-address atomics at the L2.
+  u32 idx = 0, idx_end = 0;
   while (true) {
-    u32 idx = 0;
-    if (lane == 0) idx = atomicAdd(&plan->next_wave, 1u);
-    idx = __shfl(idx, 0, kWave);
+    if (idx == idx_end) {
+      u32 c0 = 0;
+      if (lane == 0) c0 = atomicAdd(&plan->next_wave, kWaveClaim);
+      idx = __shfl(c0, 0, kWave);
+      idx_end = min(idx + kWaveClaim, nwx);
+    }
     if (idx >= nwx) break;
-    const u32 x = wave_x[idx];
+    const u32 x = wave_x[idx++];
     const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
+    const u32 hs = hoff[x], np = hoff[x + 1] - hs;
     const u32 px = vinfo[x] & 0x80u;
     const u32 mask = bucket_mask(dx, kWaveSlots);
     c.staged += lane == 0 ? dx : 0;
@@ -109,67 +125,102 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
       hash_insert(table, mask, w, same);
     }
     wave_lds_sync();
-    const u32 hs = hoff[x], np = hoff[x + 1] - hs;
+    Tally tl{0, 0, 0, 0};
     for (u32 pb = 0; pb < np; pb += kWave) {
       const u32 p = pb + lane;
-      u32 y = 0, sy = 0, dy = 0;
+      u32 y = 0, lo = 0, hi = 0;
       if (p < np) {
         y = hadj[hs + p];
-        sy = rowptr[y];
-        dy = rowptr[y + 1] - sy;
+        lo = rowptr[y];
+        hi = rowptr[y + 1];
       }
-      c.probes += dy;
-      const u32 incl = wave_incl_scan(dy);
+      tl.probes += hi - lo;
+      const u32 qa = VEC ? (lo & ~3u) : lo;
+      const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
+      const u32 incl = wave_incl_scan(nq);
       const u32 total = __shfl(incl, kWave - 1, kWave);
-      s_incl[wid][lane] = incl;
-      s_start[wid][lane] = sy - (incl - dy);  // element k of partner l sits at start + k
-      s_y[wid][lane] = y;
+      // partners with elements, compacted: their quad ends are strictly increasing
+      const u64 ne = __ballot(nq > 0);
+      const u32 npc = (u32)__popcll(ne);
+      if (nq > 0) {
+        const u32 r = mask_rank(ne);
+        s_pinfo[wid][r] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
+        s_end[wid][r] = incl;
+      }
       wave_lds_sync();
-      Tally tl{0, 0, 0, 0};
+      const u32 my_end = lane < npc ? s_end[wid][lane] : kInf;  // quad end of partner `lane`
       for (u32 k0 = 0; k0 < total; k0 += kWave * kUnroll) {
-        u32 ws[kUnroll], ls[kUnroll];
-        bool ok[kUnroll];
+        // Quad q belongs to partner #{r : end_r <= q}.  Partner ends strictly inside one
+        // of the kUnroll windows of 64 quads from k0 mark their position (byte u of word
+        // j for position 64 u + j); ends at a window start count in that window's base.
+        s_mark[wid][lane] = 0;
+        wave_lds_sync();
+        const u32 t = my_end - k0;
+        if (my_end > k0 && t < kWave * kUnroll && (t & (kWave - 1)) != 0)
+          reinterpret_cast<uint8_t*>(s_mark[wid])[(t & (kWave - 1)) * 4 + t / kWave] = 1;
+        wave_lds_sync();
+        const u32 word = s_mark[wid][lane];
+        u32 e[kUnroll][NE];
+        uint4 inf[kUnroll];
+        u32 addr[kUnroll];
+        bool live[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const u32 k = k0 + u * kWave + lane;
-          ok[u] = k < total;
-          // partner l: smallest l with incl[l] > k
-          u32 lo = 0, hi = kWave - 1;
-          while (lo < hi) {
-            const u32 mid = (lo + hi) >> 1;
-            if (s_incl[wid][mid] > k) hi = mid;
-            else lo = mid + 1;
+          const u32 w0 = k0 + u * kWave;
+          const u32 q = w0 + lane;
+          const u64 mk = __ballot(((word >> (8 * u)) & 0xFFu) != 0);
+          const u32 base = (u32)__popcll(__ballot(my_end <= w0));
+          const u32 l = min(base + (u32)__popcll(mk & le), npc - 1);
+          live[u] = q < total;
+          inf[u] = s_pinfo[wid][l];
+          addr[u] = (inf[u].x + q) * NE;
+          if (VEC) {
+            // one unconditional 16-byte load: a quad that would run past the end of
+            // colidx (or a dead lane) reads the padded copy of the last partial quad
+            const u32* src = (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
+            const uint4 v = *reinterpret_cast<const uint4*>(src);
+            e[u][0] = v.x;
+            e[u][NE > 1 ? 1 : 0] = v.y;
+            e[u][NE > 2 ? 2 : 0] = v.z;
+            e[u][NE > 3 ? 3 : 0] = v.w;
+          } else {
+            e[u][0] = colidx[live[u] ? addr[u] : 0u];
           }
-          ls[u] = lo;
-          ws[u] = colidx[ok[u] ? s_start[wid][lo] + k : 0u];
         }
-        u32 res[kUnroll];
-        hash_probe_n<kUnroll>(table, mask, ws, ok, res);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const u32 y2 = s_y[wid][ls[u]];
+          const u32 y2 = inf[u].w;
           const u32 vmax = max(x, y2);
-          tl.add(res[u], ws[u], vmax);
-          if (PV) attribute(tri, res[u], ws[u], x, y2, vmax);
+          const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
+          bool ok[NE];
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
+          u32 res[NE];
+          hash_probe_n<NE>(table, mask, e[u], ok, res);
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) {
+            tl.add(res[i], e[u][i], vmax);
+            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+          }
         }
       }
-      tl.fold(c);
       wave_lds_sync();
     }
+    tl.fold(c);
   }
   block_flush_counts(c, 1, ctr, s_red);
 }
 
 // ---- block class: one 1024-thread workgroup per (x, segment of partners) ----------------
-// N(x) is staged chunk by chunk (at most prm.chunk <= 16384 entries per chunk) in a
-// 128 KB LDS hash set.  For each chunk the segment's partner lists are cut to the chunk's
-// ID range (binary search, only when N(x) needs several chunks) and padded out to whole
-// 16-byte quads; the concatenated quad space is split into one contiguous range per
+// N(x) is staged chunk by chunk (at most prm.chunk <= 16384 entries per chunk, 4096 by
+// default so that the 128 KB LDS hash set stays at most 1/8 full).  For each chunk every
+// partner list is cut at the chunk's largest ID (one binary search from the previous
+// chunk's cut, only when N(x) needs several chunks) and padded out to whole 16-byte quads; the concatenated quad space is split into one contiguous range per
 // wavefront.  A wavefront walks its range in windows of 64 quads, one quad (16-byte load)
 // per lane, and keeps the current partner as it goes: the partner boundaries (quad prefix
 // sums in LDS) that fall inside a window are applied with a few lane-uniform steps, so
 // no per-lane search is needed.  Every partner element is probed exactly once, against
-// the one chunk whose ID range can hold it.
+// the first chunk whose largest ID is not below it.
 constexpr int kBigThreads = 1024;
 constexpr int kBigWaves = kBigThreads / kWave;
 constexpr int kBigSlots = 32768;   // 128 KB of LDS
@@ -211,17 +262,16 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
       yhi = rowptr[y + 1];
     }
     const u32 nch = (dx + prm.chunk - 1) / prm.chunk;
+    u32 lo = ylo;  // cursor: elements below it were probed against earlier chunks
     for (u32 ch = 0; ch < nch; ++ch) {
       const u32 c0 = ch * prm.chunk, clen = min(prm.chunk, dx - c0);
       const u32 mask = bucket_mask(clen, kBigSlots);
       c.staged += tid == 0 ? clen : 0;
       for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) s_table[i] = kInf;
-      // this partner's elements that fall in the chunk's ID range
-      u32 lo = ylo, hi = yhi;
-      if (tid < pn && nch > 1) {
-        if (ch > 0) lo = lower_bound_g(colidx, lo, hi, colidx[bx + c0]);
-        if (ch + 1 < nch) hi = lower_bound_g(colidx, lo, hi, colidx[bx + c0 + clen - 1] + 1u);
-      }
+      // this partner's elements up to the chunk's largest ID (the ones between two
+      // chunks are in no chunk and find nothing in either)
+      u32 hi = yhi;
+      if (tid < pn && ch + 1 < nch) hi = lower_bound_g(colidx, lo, yhi, colidx[bx + c0 + clen - 1] + 1u);
       tl.probes += hi - lo;
       const u32 qa = VEC ? (lo & ~3u) : lo;
       const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
@@ -308,6 +358,7 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
         }
       }
       __syncthreads();
+      lo = hi;
     }
     tl.fold(c);
   }
@@ -352,17 +403,23 @@ void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinf
                        vinfo, hoff, hadj, htile_row, nS, p.lane_max, ctr, tri);
 }
 
-void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
-                       const u32* hoff, const u32* hadj, const u32* wave_x, u32 nwx,
-                       Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
+void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
+                       const uint8_t* vinfo, const u32* hoff, const u32* hadj, const u32* wave_x,
+                       u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
   if (nwx == 0) return;
   const u32 g = min(cdiv(nwx, kIsectThreads / kWave), resident_blocks(8));
-  if (tri)
-    hipLaunchKernelGGL(k_isect_wave<true>, dim3(g), dim3(kIsectThreads), 0, s, rowptr, colidx,
-                       vinfo, hoff, hadj, wave_x, nwx, plan, ctr, tri);
-  else
-    hipLaunchKernelGGL(k_isect_wave<false>, dim3(g), dim3(kIsectThreads), 0, s, rowptr, colidx,
-                       vinfo, hoff, hadj, wave_x, nwx, plan, ctr, tri);
+  const bool vec = ((uintptr_t)colidx & 15u) == 0;
+#define TC_LAUNCH_WAVE(PV, VEC)                                                                \
+  hipLaunchKernelGGL((k_isect_wave<PV, VEC>), dim3(g), dim3(kIsectThreads), 0, s, rowptr,       \
+                     colidx, m, tail4, vinfo, hoff, hadj, wave_x, nwx, plan, ctr, tri)
+  if (tri) {
+    if (vec) TC_LAUNCH_WAVE(true, true);
+    else TC_LAUNCH_WAVE(true, false);
+  } else {
+    if (vec) TC_LAUNCH_WAVE(false, true);
+    else TC_LAUNCH_WAVE(false, false);
+  }
+#undef TC_LAUNCH_WAVE
 }
 
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,

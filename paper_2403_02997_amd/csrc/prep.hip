@@ -54,14 +54,25 @@ __global__ void k_cc_init(const u32* __restrict__ rowptr, const u32* __restrict_
   }
 }
 
-// Second sampled link: every vertex joins its second-smallest neighbour.  With the
-// initial parents this already assembles most of a dominant component (Afforest,
-// Sutton, Ben-Nun & Barak, IPDPS 2018).
+// Sampled links (Afforest, Sutton, Ben-Nun & Barak, IPDPS 2018): every vertex links the
+// current roots of itself and of its two smallest neighbours, which already assembles
+// most of a dominant component.  A link lowers parent[r_hi] to r_lo with one atomicMin
+// (no retry loop): if r_hi had been linked meanwhile, its old link may be dropped, which
+// only leaves two sets unmerged that are truly connected.  Every parent stays within
+// its component, and the links not made here are made by k_cc_finish.
+__device__ __forceinline__ void cc_min_link(u32* parent, u32 a, u32 b) {
+  const u32 ra = load_coherent(&parent[a]), rb = load_coherent(&parent[b]);
+  if (ra == rb) return;
+  const u32 hi = max(ra, rb), lo = min(ra, rb);
+  if (load_coherent(&parent[hi]) > lo) atomicMin(&parent[hi], lo);
+}
+
 __global__ void k_cc_sample(const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
                             u32 n, u32* parent) {
   for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const u32 lo = rowptr[v], hi = rowptr[v + 1];
-    if (hi - lo >= 2) cc_union(parent, v, colidx[lo + 1]);
+    if (hi - lo >= 1 && colidx[lo] > v) cc_min_link(parent, v, colidx[lo]);
+    if (hi - lo >= 2) cc_min_link(parent, v, colidx[lo + 1]);
   }
 }
 
@@ -135,6 +146,8 @@ void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n,
   const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
   hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
   if (m > 0) {
+    // flatten the initial forest first, so that the sampled links start from short paths
+    hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
     hipLaunchKernelGGL(k_cc_sample, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
     hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
     hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(kModeSamples), 0, s, n, parent, mode);

@@ -168,24 +168,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Bucketed open addressing: a table of `slots` u32 (a power of two) is read as buckets of
 // four slots, one 16-byte LDS load per bucket.  A vertex w of the staged list is stored
 // as the key (w << 1) | same, with `same` set when w is on the owner's BFS level
-// (w < 2^31 - 1, so a key never equals the empty marker).  Inserts fill a bucket's slots
-// in order and move to the next bucket only when it is full, so a probe ends at the first
-// bucket that holds w or an empty slot.
+// (w < 2^30 - 1, so keys stay below 2^31 and never equal the empty marker).  Inserts fill
+// a bucket's slots in order; an insert that finds its bucket full sets the overflow flag
+// (bit 31) of the bucket's last slot and moves on to the next bucket.  A probe therefore
+// ends at the first bucket that holds w or carries no flag, and the rare flagged bucket
+// is the only case in which a wavefront has to wait for some of its lanes.
+constexpr u32 kFlag = 0x80000000u;
 
-// Bucket mask for `keys` keys at load factor <= 1/4 where cap_slots allows (never above
-// 1/2 for the chunk sizes used): at least 16 buckets (64 slots), at most cap_slots / 4.
-// A low load factor keeps bucket overflows, which every lane of a wavefront waits for,
-// rare.
+// Bucket mask for `keys` keys at load factor <= 1/8 where cap_slots allows: at least 16
+// buckets (64 slots), at most cap_slots / 4.  The chunk sizes keep the load factor of
+// the workgroup table at 1/8 and of the wavefront tables at 1/4 or less.
 __device__ __forceinline__ u32 bucket_mask(u32 keys, u32 cap_slots) {
-  u32 want = keys * 4;
+  u32 want = keys * 8;
   if (want < 64) want = 64;
   u32 p = 1u << (32 - __clz(want - 1));
   if (p > cap_slots) p = cap_slots;
   return p / 4 - 1;
 }
 
-// Shift-xor mix (full-rate integer ops only); the low bits index the buckets.
-__device__ __forceinline__ u32 hash_mix(u32 w) { return w ^ (w >> 11) ^ (w >> 22); }
+// Shift-xor mix (one shift and one fused xor-and per key); the low bits index the
+// buckets, and bits 13 and up are folded onto them.
+__device__ __forceinline__ u32 hash_mix(u32 w) { return w ^ (w >> 13); }
 
 __device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 w, u32 same) {
   const u32 key = (w << 1) | same;
@@ -194,17 +197,20 @@ __device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 w, u32 sa
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (atomicCAS(&table[4 * b + j], kInf, key) == kInf) return;
+    atomicOr(&table[4 * b + 3], kFlag);  // the bucket is full: probes must go on
     b = (b + 1) & bmask;
   }
 }
 
-// Bucket v against k2 = w << 1: 0 when w is absent (the bucket has room), 1 when present
-// on another level, 2 on the owner's level, 3 when the bucket is full without w (the
-// probe continues in the next bucket).  A slot matches iff key ^ k2 is 0 or 1, and that
-// value is the level flag.
+// Bucket v against k2 = w << 1: 1 when w is present on another level, 2 on the owner's
+// level, 3 when absent here but the bucket is flagged (the probe continues in the next
+// bucket), 0 when absent.  A slot matches iff key ^ k2 is 0 or 1, and that value is the
+// level flag; only the last slot can carry the overflow flag, and an empty slot (all
+// ones) never matches.
 __device__ __forceinline__ u32 bucket_check(uint4 v, u32 k2) {
-  const u32 mn = min(min(v.x ^ k2, v.y ^ k2), min(v.z ^ k2, v.w ^ k2));
-  return mn <= 1u ? 1u + mn : (v.w == kInf ? 0u : 3u);
+  const u32 mn = min(min(v.x ^ k2, v.y ^ k2), min(v.z ^ k2, (v.w & ~kFlag) ^ k2));
+  const bool flagged = v.w - kFlag < kInf - kFlag;  // kFlag <= v.w < kInf
+  return mn <= 1u ? 1u + mn : (flagged ? 3u : 0u);
 }
 
 __device__ __forceinline__ u32 hash_probe(const u32* table, u32 bmask, u32 w) {
@@ -233,12 +239,18 @@ __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const 
     b[i] = hash_mix(w[i]) & bmask;
     v[i] = t4[b[i]];
   }
-  u32 pend = 0;
+  // branch-free first checks; the overflow path below is entered only when some lane
+  // of the wavefront met a full bucket
+  bool any = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    res[i] = ok[i] ? bucket_check(v[i], w[i] << 1) : 0u;
-    pend |= (res[i] == 3u ? 1u : 0u) << i;
+    res[i] = bucket_check(v[i], w[i] << 1) & (0u - (u32)ok[i]);
+    any |= res[i] == 3u;
   }
+  if (!__ballot(any)) return;
+  u32 pend = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) pend |= (res[i] == 3u ? 1u : 0u) << i;
   while (__ballot(pend != 0)) {
     if (pend) {
       const u32 i = __ffs(pend) - 1;
@@ -265,12 +277,15 @@ __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const 
 struct Counts;
 
 // Per-thread tallies of one work item in 32-bit registers, folded into Counts after it.
+// For a probe result r in {0, 1, 2}: s accumulates r (= c1 + 2 c2), c2 the same-level
+// hits r >> 1, t2 the same-level hits above both endpoints.
 struct Tally {
-  u32 c1, c2, t2, probes;
+  u32 s, c2, t2, probes;
   __device__ __forceinline__ void add(u32 r, u32 w, u32 vmax) {
-    c1 += r == 1u;
-    c2 += r == 2u;
-    t2 += (r == 2u) & (w > vmax);
+    const u32 q = r >> 1;
+    s += r;
+    c2 += q;
+    t2 += w > vmax ? q : 0u;
   }
   __device__ __forceinline__ void fold(Counts& c);
 };
@@ -316,11 +331,11 @@ struct Counts {
 };
 
 __device__ __forceinline__ void Tally::fold(Counts& c) {
-  c.c1 += c1;
+  c.c1 += s - 2 * c2;
   c.c2 += c2;
   c.t2 += t2;
   c.probes += probes;
-  c1 = c2 = t2 = probes = 0;
+  s = c2 = t2 = probes = 0;
 }
 
 // Per-vertex attribution of a counted triangle {x, y, w} (result r of a probe of w).

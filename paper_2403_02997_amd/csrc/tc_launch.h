@@ -83,9 +83,9 @@ void launch_fill_items(const u32* rowptr, const u32* hoff, const u32* block_x,
 void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
                        const u32* hoff, const u32* hadj, const u32* htile_row, u32 n,
                        u32 nS, IsectParams p, u64* ctr, u64* tri, hipStream_t s);
-void launch_isect_wave(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
-                       const u32* hoff, const u32* hadj, const u32* wave_x, u32 nwx,
-                       Plan* plan, u64* ctr, u64* tri, hipStream_t s);
+void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
+                       const uint8_t* vinfo, const u32* hoff, const u32* hadj, const u32* wave_x,
+                       u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
 void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s);
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                         const uint8_t* vinfo,

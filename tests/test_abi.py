@@ -57,8 +57,9 @@ def test_argument_errors_without_gpu(lib):
     out = u64(7)
     # null count pointer
     assert lib.tc_count(None, None, 0, 0, None, None) == -1
-    # n >= 2^31 and m >= 2^32 are refused before any device work
+    # n >= 2^30 and m >= 2^32 are refused before any device work
     assert lib.tc_count(None, None, 0x80000000, 0, None, ctypes.byref(out)) == -5
+    assert lib.tc_count(None, None, 0x40000000, 0, None, ctypes.byref(out)) == -5
     assert lib.tc_count(None, None, 10, 1 << 32, None, ctypes.byref(out)) == -5
     # data required when m > 0
     assert lib.tc_count(None, None, 10, 4, None, ctypes.byref(out)) == -1
