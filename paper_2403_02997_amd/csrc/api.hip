@@ -170,7 +170,6 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   const IsectParams prm = g_params;
   const u32 ntiles = (m + kTile - 1) / kTile;
   const u32 max_s = m / 2;
-  const u32 hntiles = (max_s + kTile - 1) / kTile;
   // ---- workspace ----
   size_t bytes = 0;
   {
@@ -180,12 +179,12 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u32>(n);                  // level
     c.take<u32>(n);                  // queue0
     c.take<u32>(n);                  // queue1
+    c.take<u32>(3 * (((size_t)n + 31) / 32));  // frontier bitmaps
     c.take<uint8_t>(n);              // vinfo
-    c.take<u32>((size_t)n + 1);      // hoff
-    c.take<u32>((size_t)n + 1);      // hcur
+    c.take<u32>(n);                  // hcnt
     c.take<u32>(scan_tmp_words(n));  // scan tmp
-    c.take<u32>(max_s ? max_s : 1);  // hadj
-    c.take<u32>(hntiles + 1);        // htile_row
+    c.take<u32>(m);                  // hadj (partner lists in place of the rows)
+    c.take<u32>(n);                  // lane_x
     c.take<u32>(n);                  // wave_x
     c.take<u32>(n);                  // block_x
     c.take<u32>((size_t)n + 1);      // block items / offsets
@@ -206,12 +205,13 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u32* level = c.take<u32>(n);
   u32* q0 = c.take<u32>(n);
   u32* q1 = c.take<u32>(n);
+  const size_t fb_words = 3 * (((size_t)n + 31) / 32);
+  u32* fb = c.take<u32>(fb_words);
   uint8_t* vinfo = c.take<uint8_t>(n);
-  u32* hoff = c.take<u32>((size_t)n + 1);
-  u32* hcur = c.take<u32>((size_t)n + 1);
+  u32* hcnt = c.take<u32>(n);
   u32* scan_tmp = c.take<u32>(scan_tmp_words(n));
-  u32* hadj = c.take<u32>(max_s ? max_s : 1);
-  u32* htile_row = c.take<u32>(hntiles + 1);
+  u32* hadj = c.take<u32>(m);
+  u32* lane_x = c.take<u32>(n);
   u32* wave_x = c.take<u32>(n);
   u32* block_x = c.take<u32>(n);
   u32* bitems = c.take<u32>((size_t)n + 1);
@@ -226,7 +226,8 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   if (level_out) level = level_out;
 
   TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
-  TC_HIP(hipMemsetAsync(hoff, 0, sizeof(u32) * ((size_t)n + 1), s));
+  TC_HIP(hipMemsetAsync(fb, 0, sizeof(u32) * fb_words, s));
+  TC_HIP(hipMemsetAsync(hcnt, 0, sizeof(u32) * (size_t)n, s));
   TC_HIP(hipMemsetAsync(bitems, 0, sizeof(u32) * ((size_t)n + 1), s));
   StepTimer timer(s);
 
@@ -238,13 +239,13 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
 
   // ---- a2: level BFS ----
   timer.mark();
-  launch_bfs_init(rowptr, parent, n, level, q0, ctl, s);
+  launch_bfs_init(rowptr, parent, n, level, q0, fb, ctl, s);
   TC_LAUNCHED();
   {
     const u32 grid = bfs_grid(n);
     u32 k = 0, batch = 4;
     while (true) {
-      for (u32 i = 0; i < batch; ++i) launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, ctl, grid, s);
+      for (u32 i = 0; i < batch; ++i) launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, fb, ctl, grid, s);
       TC_LAUNCHED();
       k += batch;
       u32 done = 0;
@@ -259,20 +260,17 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   launch_vinfo(rowptr, level, n, vinfo, s);
 
   // ---- a3: cover-edge extraction ----
-  launch_extract_count(rowptr, colidx, tile_row, vinfo, n, m, hoff, s);
-  launch_scan(hoff, hoff, n, scan_tmp, s);
-  TC_HIP(hipMemcpyAsync(hcur, hoff, sizeof(u32) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
-  launch_extract_write(rowptr, colidx, tile_row, vinfo, n, m, hcur, hadj, s);
+  launch_extract(rowptr, colidx, tile_row, vinfo, n, m, hcnt, hadj, s);
   timer.mark();
-  launch_plan(rowptr, hoff, n, prm, wave_x, block_x, bitems, plan, s);
+  launch_plan(rowptr, hcnt, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
   launch_scan(bitems, bitems, n, scan_tmp, s);
   TC_LAUNCHED();
-  u32 h_ns = 0, h_items = 0;
+  u32 h_items = 0;
   Plan h_plan;
-  TC_HIP(hipMemcpyAsync(&h_ns, hoff + n, sizeof(u32), hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&h_items, bitems + n, sizeof(u32), hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&h_plan, plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  const u32 h_ns = h_plan.num_cover;
   if (h_ns > max_s) return TC_ERR_INTERNAL;
 
   // ---- a4: intersections ----
@@ -282,18 +280,16 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     rc = alloc_async(items_mem, sizeof(Item) * (size_t)h_items, s);
     if (rc) return rc;
     items = (Item*)items_mem.p;
-    launch_fill_items(rowptr, hoff, block_x, bitems, h_plan.num_block_x, prm, items, s);
+    launch_fill_items(rowptr, hcnt, block_x, bitems, h_plan.num_block_x, prm, items, s);
   }
-  if (h_plan.lane_edges) launch_tile_rows(hoff, n, h_ns, htile_row, s);
   timer.mark();
-  if (h_plan.lane_edges)
-    launch_isect_lane(rowptr, colidx, vinfo, hoff, hadj, htile_row, n, h_ns, prm, ctr, tri, s);
+  launch_isect_lane(rowptr, colidx, vinfo, hcnt, hadj, lane_x, h_plan.num_lane_x, ctr, tri, s);
   timer.mark();
   launch_tail4(colidx, m, tail4, s);
-  launch_isect_block(rowptr, colidx, m, tail4, vinfo, hoff, hadj, items, h_items, prm, plan, ctr,
+  launch_isect_block(rowptr, colidx, m, tail4, vinfo, hcnt, hadj, items, h_items, prm, plan, ctr,
                      tri, s);
   timer.mark();
-  launch_isect_wave(rowptr, colidx, m, tail4, vinfo, hoff, hadj, wave_x, h_plan.num_wave_x, plan,
+  launch_isect_wave(rowptr, colidx, m, tail4, vinfo, hcnt, hadj, wave_x, h_plan.num_wave_x, plan,
                     ctr, tri, s);
   timer.mark();
   // ---- a5: reduction ----

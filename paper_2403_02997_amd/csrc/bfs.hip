@@ -10,6 +10,10 @@
 // m_u / 14 (m_u = edges of unvisited vertices), bottom-up until the frontier shrinks
 // below n / 24.  The last block of each level takes that decision on the device, so the
 // host enqueues many levels without waiting and only polls `done` between batches.
+// Each level's frontier is also kept as a bitmap (n bits, small enough to stay in the
+// L2): bottom-up steps test neighbours against it instead of gathering their levels.
+// Three bitmaps rotate: level k reads bitmap k mod 3, fills (k + 1) mod 3 and clears
+// (k + 2) mod 3, the frontier of level k - 1, which level k + 1 fills next.
 #include "tc_device.h"
 #include "tc_launch.h"
 
@@ -21,10 +25,19 @@ constexpr int kBfsThreads = 256;
 constexpr u32 kBfsLaneMax = 32;  // frontier vertices up to this degree expand per lane
 constexpr u32 kBfsPer = 8;       // vertices per thread and pass in the vertex sweeps
 
+// Stores the frontier bits of 32 consecutive vertices v0 .. v0 + 31 handled by one half
+// of a wavefront (v0 a multiple of 32), which no other thread writes in this sweep.
+__device__ __forceinline__ void store_bits_half(u32* bm, u32 v, bool set, u32 n) {
+  const u64 b = __ballot(set);
+  const u32 lane = lane_id();
+  if ((lane & 31u) == 0 && v < n) bm[v >> 5] = (u32)(b >> (lane & 32u));
+}
+
 __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict__ rowptr,
                                                           const u32* __restrict__ parent, u32 n,
                                                           u32* __restrict__ level,
                                                           u32* __restrict__ queue0,
+                                                          u32* __restrict__ fb0,
                                                           BfsCtl* __restrict__ ctl) {
   __shared__ u32 s_tmp[kBfsThreads / kWave];
   __shared__ u32 s_base;
@@ -47,6 +60,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict_
           ++cnt;
         }
       }
+      store_bits_half(fb0, v, (bits >> k) & 1u, n);
     }
     u32 tot;
     const u32 incl = block_incl_scan(cnt, s_tmp, &tot);
@@ -89,7 +103,7 @@ __device__ __forceinline__ bool bfs_claim(u32* level, u32 y, u32 next) {
 __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 n, u32 k,
     u32* __restrict__ level, u32* __restrict__ queue0, u32* __restrict__ queue1,
-    BfsCtl* __restrict__ ctl) {
+    u32* __restrict__ fb, BfsCtl* __restrict__ ctl) {
   __shared__ u64 s_red[2 * (kBfsThreads / kWave)];
   __shared__ bool s_last;
   if (load_coherent(&ctl->done)) return;  // uniform across the grid
@@ -101,6 +115,11 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
   u64 mf = 0, mu_dec = 0;
   const u32 lane = lane_id();
   const u32 stride = gridDim.x * blockDim.x;
+  const u32 nw = (n + 31) / 32;
+  const u32* fcur = fb + (k % 3) * (size_t)nw;
+  u32* fnext = fb + ((k + 1) % 3) * (size_t)nw;
+  u32* fold = fb + ((k + 2) % 3) * (size_t)nw;
+  for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) fold[i] = 0;
 
   if (mode == 0) {
     // ---- top-down: expand the frontier queue ----
@@ -129,6 +148,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
         const u32 pos = wave_append(qlen_out, claimed);
         if (claimed) {
           qout[pos] = y;
+          atomicOr(&fnext[y >> 5], 1u << (y & 31));
           const u32 dy = rowptr[y + 1] - rowptr[y];
           mf += dy;
           mu_dec += dy;
@@ -151,6 +171,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
           const u32 pos = wave_append(qlen_out, claimed);
           if (claimed) {
             qout[pos] = y;
+            atomicOr(&fnext[y >> 5], 1u << (y & 31));
             const u32 dy = rowptr[y + 1] - rowptr[y];
             mf += dy;
             mu_dec += dy;
@@ -182,7 +203,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
 #pragma unroll
             for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : 0u;
 #pragma unroll
-            for (u32 i = 0; i < 4; ++i) found |= j + i < d && level[w[i]] == k;
+            for (u32 i = 0; i < 4; ++i) found |= j + i < d && ((fcur[w[i] >> 5] >> (w[i] & 31)) & 1u);
           }
         }
         // long lists: the whole wavefront, 64 neighbours per step
@@ -194,7 +215,12 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
           bool bf = false;
           for (u32 j0 = 0; j0 < bd && !bf; j0 += kWave) {
             const u32 j = j0 + lane;
-            bf = __ballot(j < bd && level[colidx[blo + j]] == k) != 0;
+            bool hit = false;
+            if (j < bd) {
+              const u32 w = colidx[blo + j];
+              hit = (fcur[w >> 5] >> (w & 31)) & 1u;
+            }
+            bf = __ballot(hit) != 0;
           }
           if ((int)lane == b) found = bf;
         }
@@ -205,6 +231,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
           mf += d;
           mu_dec += d;
         }
+        store_bits_half(fnext, v, found, n);
       }
       u32 tot;
       const u32 incl = block_incl_scan(cnt, s_tmp, &tot);
@@ -267,16 +294,16 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
 u32 bfs_grid(u32 n) { return max(1u, min(cdiv(n, kBfsThreads), (u32)num_cus() * 2)); }
 
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
-                     BfsCtl* ctl, hipStream_t s) {
+                     u32* fb, BfsCtl* ctl, hipStream_t s) {
   const u32 g = bfs_grid(n);
   hipLaunchKernelGGL(k_bfs_init, dim3(g), dim3(kBfsThreads), 0, s, rowptr, parent, n, level,
-                     queue0, ctl);
+                     queue0, fb, ctl);
 }
 
 void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,
-                      u32* queue0, u32* queue1, BfsCtl* ctl, u32 grid, hipStream_t s) {
+                      u32* queue0, u32* queue1, u32* fb, BfsCtl* ctl, u32 grid, hipStream_t s) {
   hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kBfsThreads), 0, s, rowptr, colidx, n, k,
-                     level, queue0, queue1, ctl);
+                     level, queue0, queue1, fb, ctl);
 }
 
 }  // namespace tc

@@ -7,9 +7,11 @@
 // and the streamed list the shorter one.  The ID order u < v of the paper's edge loop is
 // applied later, in the apex rule, where it is needed.
 //
-// The result is a CSR over x: hoff[n+1] and hadj[|S|].  Both passes run over CSR tiles:
-// a wavefront ballot marks the horizontal, oriented entries, a block-wide prefix count
-// ranks them, and one atomic per (tile, row) reserves each row's output range.
+// H+(x) is written in place of N(x)'s own range: hadj[rowptr[x] .. rowptr[x] + hcnt[x])
+// (a partner list is never longer than the neighbour list), so one pass suffices.  The
+// pass runs over CSR tiles: a wavefront ballot marks the horizontal, oriented entries, a
+// block-wide prefix count ranks them, and one atomic per (tile, row) on hcnt[x] reserves
+// that row's output range.
 #include "tc_device.h"
 #include "tc_launch.h"
 
@@ -80,43 +82,10 @@ __device__ __forceinline__ void row_span(const TileInfo& ti, const u32* __restri
   *b = min(hi, ti.e1) - ti.e0;
 }
 
-__global__ void __launch_bounds__(kTileThreads) k_extract_count(
-    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
-    const u32* __restrict__ tile_row, const uint8_t* __restrict__ vinfo, u32 m,
-    u32* __restrict__ hcnt) {
-  __shared__ u32 s_rp[kTileRowCap];
-  __shared__ u32 s_excl[kTile + 1];
-  __shared__ u32 s_tmp[kTileThreads / kWave];
-  const u32 ntiles = (m + kTile - 1) / kTile;
-  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const TileInfo ti = tile_begin(rowptr, tile_row, t, m, s_rp);
-    u32 rows[kPer], ys[kPer];
-    bool preds[kPer];
-    mark_tile(ti, s_rp, rowptr, colidx, vinfo, s_excl, s_tmp, rows, ys, preds);
-    if (s_excl[kTile] > 0) {
-      if (ti.staged) {
-        for (u32 x = ti.r0 + threadIdx.x; x <= ti.r1; x += blockDim.x) {
-          u32 a, b;
-          row_span(ti, rowptr, s_rp, x, &a, &b);
-          if (a < b) {
-            const u32 c = s_excl[b] - s_excl[a];
-            if (c) atomicAdd(&hcnt[x], c);
-          }
-        }
-      } else {
-#pragma unroll
-        for (u32 r = 0; r < kPer; ++r)
-          if (preds[r]) atomicAdd(&hcnt[rows[r]], 1u);
-      }
-    }
-    __syncthreads();
-  }
-}
-
 __global__ void __launch_bounds__(kTileThreads) k_extract_write(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
     const u32* __restrict__ tile_row, const uint8_t* __restrict__ vinfo, u32 m,
-    u32* __restrict__ hcur, u32* __restrict__ hadj) {
+    u32* __restrict__ hcnt, u32* __restrict__ hadj) {
   __shared__ u32 s_rp[kTileRowCap];
   __shared__ u32 s_excl[kTile + 1];
   __shared__ u32 s_base[kTileRowCap];
@@ -136,7 +105,7 @@ __global__ void __launch_bounds__(kTileThreads) k_extract_write(
           u32 base = 0;
           if (a < b) {
             const u32 c = s_excl[b] - s_excl[a];
-            if (c) base = atomicAdd(&hcur[x], c) - s_excl[a];
+            if (c) base = s_rp[x - ti.r0] + atomicAdd(&hcnt[x], c) - s_excl[a];
           }
           s_base[x - ti.r0] = base;
         }
@@ -151,116 +120,120 @@ __global__ void __launch_bounds__(kTileThreads) k_extract_write(
       } else {
 #pragma unroll
         for (u32 r = 0; r < kPer; ++r)
-          if (preds[r]) hadj[atomicAdd(&hcur[rows[r]], 1u)] = ys[r];
+          if (preds[r]) hadj[rowptr[rows[r]] + atomicAdd(&hcnt[rows[r]], 1u)] = ys[r];
       }
     }
     __syncthreads();
   }
 }
 
-void launch_extract_count(const u32* rowptr, const u32* colidx, const u32* tile_row,
-                          const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, hipStream_t s) {
-  (void)n;
-  if (m == 0) return;
-  const u32 g = min(cdiv(m, kTile), (u32)num_cus() * 8);
-  hipLaunchKernelGGL(k_extract_count, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                     tile_row, vinfo, m, hcnt);
-}
-
-void launch_extract_write(const u32* rowptr, const u32* colidx, const u32* tile_row,
-                          const uint8_t* vinfo, u32 n, u32 m, u32* hcur, u32* hadj,
-                          hipStream_t s) {
+void launch_extract(const u32* rowptr, const u32* colidx, const u32* tile_row,
+                    const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, u32* hadj, hipStream_t s) {
   (void)n;
   if (m == 0) return;
   const u32 g = min(cdiv(m, kTile), (u32)num_cus() * 8);
   hipLaunchKernelGGL(k_extract_write, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                     tile_row, vinfo, m, hcur, hadj);
+                     tile_row, vinfo, m, hcnt, hadj);
 }
 
 // ---- planning: split the staged endpoints x into the three intersection classes ----
 // Each workgroup classifies kPlanPer * 256 consecutive vertices per pass and reserves
-// its slots of both lists with one global atomic each (a per-wavefront atomic on one
-// shared counter serialises at the L2 for millions of vertices).
+// its slots of the three lists with one global atomic each (a per-wavefront atomic on
+// one shared counter serialises at the L2 for millions of vertices).  The total number
+// of cover edges is summed on the way.
 constexpr u32 kPlanPer = 8;
 
 __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
-                                              const u32* __restrict__ hoff, u32 n, IsectParams p,
-                                              u32* __restrict__ wave_x, u32* __restrict__ block_x,
+                                              const u32* __restrict__ hcnt, u32 n, IsectParams p,
+                                              u32* __restrict__ lane_x, u32* __restrict__ wave_x,
+                                              u32* __restrict__ block_x,
                                               u32* __restrict__ block_items,
                                               Plan* __restrict__ plan) {
-  __shared__ u32 s_tmp[2][256 / kWave];
-  __shared__ u32 s_base[2];
+  __shared__ u32 s_tmp[3][256 / kWave];
+  __shared__ u32 s_base[3];
+  __shared__ u32 s_cov[256 / kWave];
+  u32* const counters[3] = {&plan->num_lane_x, &plan->num_wave_x, &plan->num_block_x};
   const u32 span = kPlanPer * blockDim.x;
-  u32 lane_edges = 0;
+  u32 cover = 0;
   for (u32 base = blockIdx.x * span; base < n; base += gridDim.x * span) {
-    u32 cls = 0;  // 2 bits per vertex: 1 wavefront class, 2 workgroup class
-    u32 cw = 0, cb = 0;
+    u32 cls = 0;  // 2 bits per vertex: 0 no partners, 1 lane, 2 wavefront, 3 workgroup class
+    u32 cnt[3] = {0, 0, 0};
 #pragma unroll
     for (u32 k = 0; k < kPlanPer; ++k) {
       const u32 x = base + k * blockDim.x + threadIdx.x;
       u32 np = 0, d = 0;
       if (x < n) {
-        np = hoff[x + 1] - hoff[x];
+        np = hcnt[x];
         d = rowptr[x + 1] - rowptr[x];
       }
-      const u32 c = np == 0 ? 0u : d <= p.lane_max ? 0u : d <= p.wave_max ? 1u : 2u;
-      if (np > 0 && d <= p.lane_max) lane_edges += np;
+      const u32 c = np == 0 ? 0u : d <= p.lane_max ? 1u : d <= p.wave_max ? 2u : 3u;
+      cover += np;
       cls |= c << (2 * k);
-      cw += c == 1u;
-      cb += c == 2u;
+      cnt[0] += c == 1u;
+      cnt[1] += c == 2u;
+      cnt[2] += c == 3u;
     }
-    u32 tw, tb;
-    const u32 iw = block_incl_scan(cw, s_tmp[0], &tw);
-    const u32 ib = block_incl_scan(cb, s_tmp[1], &tb);
-    if (threadIdx.x == 0) {
-      s_base[0] = tw ? atomicAdd(&plan->num_wave_x, tw) : 0u;
-      s_base[1] = tb ? atomicAdd(&plan->num_block_x, tb) : 0u;
+    u32 pos[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      u32 tot;
+      const u32 incl = block_incl_scan(cnt[l], s_tmp[l], &tot);
+      if (threadIdx.x == 0) s_base[l] = tot ? atomicAdd(counters[l], tot) : 0u;
+      pos[l] = incl - cnt[l];
     }
     __syncthreads();
-    u32 pw = s_base[0] + iw - cw, pb = s_base[1] + ib - cb;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) pos[l] += s_base[l];
 #pragma unroll
     for (u32 k = 0; k < kPlanPer; ++k) {
       const u32 x = base + k * blockDim.x + threadIdx.x;
       const u32 c = (cls >> (2 * k)) & 3u;
-      if (c == 1u) wave_x[pw++] = x;
-      if (c == 2u) {
-        block_x[pb] = x;
-        block_items[pb] = (hoff[x + 1] - hoff[x] + p.seg - 1) / p.seg;
-        ++pb;
+      if (c == 1u) lane_x[pos[0]++] = x;
+      if (c == 2u) wave_x[pos[1]++] = x;
+      if (c == 3u) {
+        block_x[pos[2]] = x;
+        block_items[pos[2]] = (hcnt[x] + p.seg - 1) / p.seg;
+        ++pos[2];
       }
     }
     __syncthreads();  // s_base is rewritten by the next pass
   }
-  lane_edges = wave_sum_u32(lane_edges);
-  if (lane_id() == 0 && lane_edges) atomicAdd(&plan->lane_edges, lane_edges);
+  cover = wave_sum_u32(cover);
+  if (lane_id() == 0) s_cov[threadIdx.x / kWave] = cover;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u32 t = 0;
+    for (u32 w = 0; w < blockDim.x / kWave; ++w) t += s_cov[w];
+    if (t) atomicAdd(&plan->num_cover, t);
+  }
 }
 
-void launch_plan(const u32* rowptr, const u32* hoff, u32 n, IsectParams p, u32* wave_x,
-                 u32* block_x, u32* block_items, Plan* plan, hipStream_t s) {
+void launch_plan(const u32* rowptr, const u32* hcnt, u32 n, IsectParams p, u32* lane_x,
+                 u32* wave_x, u32* block_x, u32* block_items, Plan* plan, hipStream_t s) {
   if (n == 0) return;
   const u32 g = min(cdiv(n, 256 * kPlanPer), (u32)num_cus() * 4);
-  hipLaunchKernelGGL(k_plan, dim3(g), dim3(256), 0, s, rowptr, hoff, n, p, wave_x, block_x,
-                     block_items, plan);
+  hipLaunchKernelGGL(k_plan, dim3(g), dim3(256), 0, s, rowptr, hcnt, n, p, lane_x, wave_x,
+                     block_x, block_items, plan);
 }
 
-__global__ void k_fill_items(const u32* __restrict__ rowptr, const u32* __restrict__ hoff,
+__global__ void k_fill_items(const u32* __restrict__ rowptr, const u32* __restrict__ hcnt,
                              const u32* __restrict__ block_x, const u32* __restrict__ item_off,
                              u32 nbx, IsectParams p, Item* __restrict__ items) {
   for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < nbx; j += gridDim.x * blockDim.x) {
     const u32 x = block_x[j];
-    const u32 np = hoff[x + 1] - hoff[x];
+    const u32 np = hcnt[x];
     const u32 nsg = (np + p.seg - 1) / p.seg;
     u32 o = item_off[j];
     for (u32 sg = 0; sg < nsg; ++sg) items[o++] = Item{x, sg};
   }
 }
 
-void launch_fill_items(const u32* rowptr, const u32* hoff, const u32* block_x,
+void launch_fill_items(const u32* rowptr, const u32* hcnt, const u32* block_x,
                        const u32* item_off, u32 nbx, IsectParams p, Item* items,
                        hipStream_t s) {
   if (nbx == 0) return;
   const u32 g = min(cdiv(nbx, 256), (u32)num_cus() * 8);
-  hipLaunchKernelGGL(k_fill_items, dim3(g), dim3(256), 0, s, rowptr, hoff, block_x, item_off,
+  hipLaunchKernelGGL(k_fill_items, dim3(g), dim3(256), 0, s, rowptr, hcnt, block_x, item_off,
                      nbx, p, items);
 }
 

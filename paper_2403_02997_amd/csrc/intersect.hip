@@ -32,32 +32,27 @@ constexpr u32 kWaveClaim = 16;     // wavefront-class vertices claimed per count
 template <bool PV>
 __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
-    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hoff, const u32* __restrict__ hadj,
-    const u32* __restrict__ htile_row, u32 nS, u32 lane_max, u64* __restrict__ ctr,
-    u64* __restrict__ tri) {
-  __shared__ u32 s_rp[kTileRowCap];
+    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
+    const u32* __restrict__ lane_x, u32 nlx, u64* __restrict__ ctr, u64* __restrict__ tri) {
   __shared__ u64 s_red[5 * (kTileThreads / kWave)];
   Counts c{0, 0, 0, 0, 0};
-  const u32 ntiles = (nS + kTile - 1) / kTile;
-  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const TileInfo ti = tile_begin(hoff, htile_row, t, nS, s_rp);
-    for (u32 e = ti.e0 + threadIdx.x; e < ti.e1; e += blockDim.x) {
-      const u32 x = tile_row_of(ti, s_rp, hoff, e);
-      u32 i = rowptr[x];
-      const u32 ie = rowptr[x + 1];
-      if (ie - i > lane_max) continue;
-      const u32 y = hadj[e];
-      u32 j = rowptr[y];
+  const u32 stride = gridDim.x * blockDim.x;
+  for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < nlx; t += stride) {
+    const u32 x = lane_x[t];
+    const u32 bx = rowptr[x], ex = rowptr[x + 1], np = hcnt[x];
+    const u32 px = vinfo[x] & 0x80u;
+    for (u32 q = 0; q < np; ++q) {
+      const u32 y = hadj[bx + q];
+      u32 i = bx, j = rowptr[y];
       const u32 je = rowptr[y + 1];
       c.probes += je - j;
-      c.staged += ie - i;
-      const u32 px = vinfo[x] & 0x80u;
+      c.staged += ex - i;
       const u32 vmax = max(x, y);
-      if (i < ie && j < je) {
+      if (i < ex && j < je) {
         u32 a = colidx[i], b = colidx[j];
         while (true) {
           if (a < b) {
-            if (++i == ie) break;
+            if (++i == ex) break;
             a = colidx[i];
           } else if (a > b) {
             if (++j == je) break;
@@ -65,14 +60,13 @@ __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
           } else {
             const u32 r = 1u + (((vinfo[a] & 0x80u) == px) ? 1u : 0u);
             count_hit<PV>(r, a, x, y, vmax, c, tri);
-            if (++i == ie || ++j == je) break;
+            if (++i == ex || ++j == je) break;
             a = colidx[i];
             b = colidx[j];
           }
         }
       }
     }
-    __syncthreads();
   }
   block_flush_counts(c, 0, ctr, s_red);
 }
@@ -87,7 +81,7 @@ template <bool PV, bool VEC>
 __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
-    const u32* __restrict__ hoff, const u32* __restrict__ hadj, const u32* __restrict__ wave_x,
+    const u32* __restrict__ hcnt, const u32* __restrict__ hadj, const u32* __restrict__ wave_x,
     u32 nwx, Plan* __restrict__ plan, u64* __restrict__ ctr, u64* __restrict__ tri) {
   constexpr int kW = kIsectThreads / kWave;
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
@@ -113,7 +107,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     if (idx >= nwx) break;
     const u32 x = wave_x[idx++];
     const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
-    const u32 hs = hoff[x], np = hoff[x + 1] - hs;
+    const u32 hs = bx, np = hcnt[x];  // H+(x) sits in place of N(x)
     const u32 px = vinfo[x] & 0x80u;
     const u32 mask = bucket_mask(dx, kWaveSlots);
     c.staged += lane == 0 ? dx : 0;
@@ -231,7 +225,7 @@ template <bool PV, bool VEC>
 __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4,
-    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hoff, const u32* __restrict__ hadj,
+    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
     const Item* __restrict__ items, u32 nitems, IsectParams prm, Plan* __restrict__ plan,
     u64* __restrict__ ctr, u64* __restrict__ tri) {
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
@@ -253,8 +247,8 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32 x = item.x;
     const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
     const u32 px = vinfo[x] & 0x80u;
-    const u32 hs = hoff[x] + item.seg * prm.seg;
-    const u32 pn = min(prm.seg, hoff[x + 1] - hs);
+    const u32 hs = bx + item.seg * prm.seg;  // H+(x) sits in place of N(x)
+    const u32 pn = min(prm.seg, hcnt[x] - item.seg * prm.seg);
     u32 y = 0, ylo = 0, yhi = 0;
     if (tid < pn) {
       y = hadj[hs + tid];
@@ -390,28 +384,27 @@ __global__ void k_finalize(const u64* __restrict__ ctr, u64* __restrict__ out) {
 static u32 resident_blocks(u32 per_cu) { return (u32)num_cus() * per_cu; }
 
 void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
-                       const u32* hoff, const u32* hadj, const u32* htile_row, u32 n, u32 nS,
-                       IsectParams p, u64* ctr, u64* tri, hipStream_t s) {
-  (void)n;
-  if (nS == 0) return;
-  const u32 g = min(cdiv(nS, kTile), resident_blocks(8));
+                       const u32* hcnt, const u32* hadj, const u32* lane_x, u32 nlx, u64* ctr,
+                       u64* tri, hipStream_t s) {
+  if (nlx == 0) return;
+  const u32 g = min(cdiv(nlx, kTileThreads), resident_blocks(8));
   if (tri)
     hipLaunchKernelGGL(k_isect_lane<true>, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                       vinfo, hoff, hadj, htile_row, nS, p.lane_max, ctr, tri);
+                       vinfo, hcnt, hadj, lane_x, nlx, ctr, tri);
   else
     hipLaunchKernelGGL(k_isect_lane<false>, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                       vinfo, hoff, hadj, htile_row, nS, p.lane_max, ctr, tri);
+                       vinfo, hcnt, hadj, lane_x, nlx, ctr, tri);
 }
 
 void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                       const uint8_t* vinfo, const u32* hoff, const u32* hadj, const u32* wave_x,
+                       const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const u32* wave_x,
                        u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
   if (nwx == 0) return;
   const u32 g = min(cdiv(nwx, kIsectThreads / kWave), resident_blocks(8));
   const bool vec = ((uintptr_t)colidx & 15u) == 0;
 #define TC_LAUNCH_WAVE(PV, VEC)                                                                \
   hipLaunchKernelGGL((k_isect_wave<PV, VEC>), dim3(g), dim3(kIsectThreads), 0, s, rowptr,       \
-                     colidx, m, tail4, vinfo, hoff, hadj, wave_x, nwx, plan, ctr, tri)
+                     colidx, m, tail4, vinfo, hcnt, hadj, wave_x, nwx, plan, ctr, tri)
   if (tri) {
     if (vec) TC_LAUNCH_WAVE(true, true);
     else TC_LAUNCH_WAVE(true, false);
@@ -424,14 +417,14 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* t
 
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                         const uint8_t* vinfo,
-                        const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
+                        const u32* hcnt, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
   if (nitems == 0) return;
   const u32 g = min(nitems, resident_blocks(1));
   const bool vec = ((uintptr_t)colidx & 15u) == 0;
 #define TC_LAUNCH_BLOCK(PV, VEC)                                                             \
   hipLaunchKernelGGL((k_isect_block<PV, VEC>), dim3(g), dim3(kBigThreads), 0, s, rowptr, colidx, \
-                     m, tail4, vinfo, hoff, hadj, items, nitems, p, plan, ctr, tri)
+                     m, tail4, vinfo, hcnt, hadj, items, nitems, p, plan, ctr, tri)
   if (tri) {
     if (vec) TC_LAUNCH_BLOCK(true, true);
     else TC_LAUNCH_BLOCK(true, false);

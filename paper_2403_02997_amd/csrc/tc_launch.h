@@ -32,13 +32,14 @@ struct IsectParams {
 
 // Planning output (device), read back once by the host.
 struct Plan {
+  u32 num_lane_x;   // vertices of the lane class
   u32 num_wave_x;   // vertices of the wavefront class
   u32 num_block_x;  // vertices of the block class
   u32 num_items;    // block work items
-  u32 lane_edges;   // cover edges of the lane class
+  u32 num_cover;    // cover edges |S| = sum of hcnt
   u32 next_wave;    // dynamic work counters
   u32 next_item;
-  u32 pad[2];
+  u32 pad;
 };
 
 struct Item {
@@ -62,34 +63,34 @@ bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t 
 
 // ---- BFS ----
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
-                     BfsCtl* ctl, hipStream_t s);
+                     u32* fb, BfsCtl* ctl, hipStream_t s);
+// fb: three frontier bitmaps of (n + 31) / 32 words each, zeroed before launch_bfs_init.
 void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,
-                      u32* queue0, u32* queue1, BfsCtl* ctl, u32 grid, hipStream_t s);
+                      u32* queue0, u32* queue1, u32* fb, BfsCtl* ctl, u32 grid, hipStream_t s);
 u32 bfs_grid(u32 n);
 
 // ---- cover-edge extraction ----
-void launch_extract_count(const u32* rowptr, const u32* colidx, const u32* tile_row,
-                          const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, hipStream_t s);
-void launch_extract_write(const u32* rowptr, const u32* colidx, const u32* tile_row,
-                          const uint8_t* vinfo, u32 n, u32 m, u32* hcur, u32* hadj,
-                          hipStream_t s);
-void launch_plan(const u32* rowptr, const u32* hoff, u32 n, IsectParams p, u32* wave_x,
-                 u32* block_x, u32* block_items, Plan* plan, hipStream_t s);
-void launch_fill_items(const u32* rowptr, const u32* hoff, const u32* block_x,
+// Partner lists in place: H+(x) = hadj[rowptr[x] .. rowptr[x] + hcnt[x]) (hadj has m
+// entries; hcnt zeroed before the launch).
+void launch_extract(const u32* rowptr, const u32* colidx, const u32* tile_row,
+                    const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, u32* hadj, hipStream_t s);
+void launch_plan(const u32* rowptr, const u32* hcnt, u32 n, IsectParams p, u32* lane_x,
+                 u32* wave_x, u32* block_x, u32* block_items, Plan* plan, hipStream_t s);
+void launch_fill_items(const u32* rowptr, const u32* hcnt, const u32* block_x,
                        const u32* item_off, u32 nbx, IsectParams p, Item* items,
                        hipStream_t s);
 
 // ---- intersection ----
 void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
-                       const u32* hoff, const u32* hadj, const u32* htile_row, u32 n,
-                       u32 nS, IsectParams p, u64* ctr, u64* tri, hipStream_t s);
+                       const u32* hcnt, const u32* hadj, const u32* lane_x, u32 nlx, u64* ctr,
+                       u64* tri, hipStream_t s);
 void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                       const uint8_t* vinfo, const u32* hoff, const u32* hadj, const u32* wave_x,
+                       const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const u32* wave_x,
                        u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
 void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s);
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                         const uint8_t* vinfo,
-                        const u32* hoff, const u32* hadj, const Item* items, u32 nitems,
+                        const u32* hcnt, const u32* hadj, const Item* items, u32 nitems,
                         IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);
 
