@@ -507,6 +507,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--isect", default="", metavar="LANE,WAVE,CHUNK,SEG",
+                    help="intersection class parameters (tc_set_isect_params) for this run")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-huge-scale", type=int, default=26)
     ap.add_argument("--serve-small-max", type=int, default=1 << 18)
@@ -538,6 +540,8 @@ def main():
         calibrate_copy(args, torch)
         return
     tcm.load()
+    if args.isect:
+        tcm.tc_set_isect_params(*[int(v) for v in args.isect.split(",")])
     if args.workload == "batch4096":
         out = bench_batch(args, tcm, torch)
     elif args.workload == "serve":

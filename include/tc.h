@@ -76,6 +76,8 @@ typedef struct {
  * form).  rowptr/colidx/n/m as above; `count` is a HOST pointer receiving T.
  * Allocates its device workspace stream-ordered on `stream`, frees it before returning,
  * and synchronises `stream`.  n == 0 or m == 0 gives T = 0 without a launch.
+ * For cover edges staged as long lists, a same-level apex w <= max(u, v) can never
+ * count, so those list entries are skipped: T = c1 + t2 is computed, c2 is not.
  * Returns TC_ERR_INVALID_ARG for null pointers (when m > 0) or a null `count`,
  * TC_ERR_TOO_LARGE for n >= 2^30 or m >= 2^32, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
@@ -85,7 +87,9 @@ int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_
 /*
  * tc_count_ex — tc_count plus diagnostics.  `level_out` (DEVICE uint32[n], may be NULL)
  * receives the BFS level of every vertex; `stats` (HOST, may be NULL) the statistics
- * above.  `count` may be NULL when `stats` is given.
+ * above.  `count` may be NULL when `stats` is given.  With `stats` every intersection
+ * streams whole lists and tallies c1, c2 and t2, and the call fails with
+ * TC_ERR_INTERNAL unless c2 = 3 t2; without `stats` it counts like tc_count.
  */
 int tc_count_ex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
                 hipStream_t stream, uint64_t* count, uint32_t* level_out, tc_stats* stats);

@@ -165,7 +165,7 @@ struct StepTimer {
 // The whole single-graph pipeline.  `level_out` (device) may be null; `tri` (device,
 // zeroed by the caller) selects per-vertex attribution.
 int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s,
-               u32* level_out, u64* tri, RunOut* out) {
+               u32* level_out, u64* tri, bool pruned, RunOut* out) {
   prepare_pool();
   const IsectParams prm = g_params;
   const u32 ntiles = (m + kTile - 1) / kTile;
@@ -182,8 +182,10 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u32>(3 * (((size_t)n + 31) / 32));  // frontier bitmaps
     c.take<uint8_t>(n);              // vinfo
     c.take<u32>(n);                  // hcnt
+    c.take<u32>(n);                  // split
     c.take<u32>(scan_tmp_words(n));  // scan tmp
     c.take<u32>(m);                  // hadj (partner lists in place of the rows)
+    c.take<u32>(m);                  // colidx2 (rows split by level)
     c.take<u32>(n);                  // lane_x
     c.take<u32>(n);                  // wave_x
     c.take<u32>(n);                  // block_x
@@ -193,6 +195,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u64>(kCounterSlots * kNumCtr);
     c.take<u64>(kNumCtr);
     c.take<u32>(4);
+    c.take<u32>(4);                  // padded last quad of colidx2
     c.take<u32>(4);                  // cc mode
     bytes = c.off + 256;
   }
@@ -209,8 +212,10 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u32* fb = c.take<u32>(fb_words);
   uint8_t* vinfo = c.take<uint8_t>(n);
   u32* hcnt = c.take<u32>(n);
+  u32* split = c.take<u32>(n);
   u32* scan_tmp = c.take<u32>(scan_tmp_words(n));
   u32* hadj = c.take<u32>(m);
+  u32* colidx2 = c.take<u32>(m);
   u32* lane_x = c.take<u32>(n);
   u32* wave_x = c.take<u32>(n);
   u32* block_x = c.take<u32>(n);
@@ -222,12 +227,12 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u64* outc = c.take<u64>(kNumCtr);
   const size_t ctl_bytes = (char*)(outc + kNumCtr) - (char*)ctl;
   u32* tail4 = c.take<u32>(4);
+  u32* tail4b = c.take<u32>(4);
   u32* cc_mode = c.take<u32>(4);
   if (level_out) level = level_out;
 
   TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
   TC_HIP(hipMemsetAsync(fb, 0, sizeof(u32) * fb_words, s));
-  TC_HIP(hipMemsetAsync(hcnt, 0, sizeof(u32) * (size_t)n, s));
   TC_HIP(hipMemsetAsync(bitems, 0, sizeof(u32) * ((size_t)n + 1), s));
   StepTimer timer(s);
 
@@ -260,7 +265,8 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   launch_vinfo(rowptr, level, n, vinfo, s);
 
   // ---- a3: cover-edge extraction ----
-  launch_extract(rowptr, colidx, tile_row, vinfo, n, m, hcnt, hadj, s);
+  // the BFS queues are free again: q1 lists the long rows
+  launch_split_rows(rowptr, colidx, vinfo, n, colidx2, split, hcnt, hadj, q1, &plan->num_long, s);
   timer.mark();
   launch_plan(rowptr, hcnt, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
   launch_scan(bitems, bitems, n, scan_tmp, s);
@@ -286,8 +292,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   launch_isect_lane(rowptr, colidx, vinfo, hcnt, hadj, lane_x, h_plan.num_lane_x, ctr, tri, s);
   timer.mark();
   launch_tail4(colidx, m, tail4, s);
-  launch_isect_block(rowptr, colidx, m, tail4, vinfo, hcnt, hadj, items, h_items, prm, plan, ctr,
-                     tri, s);
+  launch_tail4(colidx2, m, tail4b, s);
+  launch_isect_block(rowptr, colidx, m, tail4, colidx2, split, tail4b, vinfo, hcnt, hadj, items,
+                     h_items, prm, plan, ctr, tri, pruned && !tri, s);
   timer.mark();
   launch_isect_wave(rowptr, colidx, m, tail4, vinfo, hcnt, hadj, wave_x, h_plan.num_wave_x, plan,
                     ctr, tri, s);
@@ -301,8 +308,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   TC_HIP(hipStreamSynchronize(s));
   timer.collect();
   out->cover_edges = h_ns;
-  // Two independent tallies of the same-level apexes must agree (CETC-SM: c2 / 3).
-  if (out->c[1] % 3 != 0 || out->c[1] / 3 != out->c[2]) return TC_ERR_INTERNAL;
+  // Two independent tallies of the same-level apexes must agree (CETC-SM: c2 / 3); the
+  // pruned count does not tally c2.
+  if (!pruned && (out->c[1] % 3 != 0 || out->c[1] / 3 != out->c[2])) return TC_ERR_INTERNAL;
   return TC_OK;
 }
 
@@ -352,7 +360,8 @@ int tc_count_ex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint
   } else {
     RunOut ro;
     memset(&ro, 0, sizeof(ro));
-    rc = run_single(rowptr, colidx, n, (u32)m, stream, level_out, nullptr, &ro);
+    // without statistics the pruned count runs (no c2); with them every tally is kept
+    rc = run_single(rowptr, colidx, n, (u32)m, stream, level_out, nullptr, stats == nullptr, &ro);
     if (rc) return rc;
     st.c1 = ro.c[0];
     st.c2 = ro.c[1];
@@ -391,7 +400,7 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
   }
   RunOut ro;
   memset(&ro, 0, sizeof(ro));
-  return run_single(rowptr, colidx, n, (u32)m, stream, nullptr, (u64*)tri_out, &ro);
+  return run_single(rowptr, colidx, n, (u32)m, stream, nullptr, (u64*)tri_out, false, &ro);
 }
 
 int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,

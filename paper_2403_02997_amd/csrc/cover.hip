@@ -7,11 +7,14 @@
 // and the streamed list the shorter one.  The ID order u < v of the paper's edge loop is
 // applied later, in the apex rule, where it is needed.
 //
-// H+(x) is written in place of N(x)'s own range: hadj[rowptr[x] .. rowptr[x] + hcnt[x])
-// (a partner list is never longer than the neighbour list), so one pass suffices.  The
-// pass runs over CSR tiles: a wavefront ballot marks the horizontal, oriented entries, a
-// block-wide prefix count ranks them, and one atomic per (tile, row) on hcnt[x] reserves
-// that row's output range.
+// One row-centric pass per vertex v writes
+//   colidx2[rowptr[v] .. split[v])       the neighbours on v's level, ascending,
+//   colidx2[split[v] .. rowptr[v + 1])   the neighbours on the other levels, ascending,
+//   hadj[rowptr[v] .. rowptr[v] + hcnt[v]) the partner list H+(v) (in place of N(v)'s
+//                                          range: a partner list is never longer).
+// Rows of at most 32 entries are handled by one lane, longer ones by a whole wavefront,
+// 64 entries per step, with ballot ranks keeping both parts in order.  The level split
+// lets the counting skip the same-level neighbours that cannot be a counted apex.
 #include "tc_device.h"
 #include "tc_launch.h"
 
@@ -19,121 +22,192 @@ namespace tc {
 
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
-constexpr u32 kPer = kTile / kTileThreads;  // entries per thread and tile
+constexpr u32 kSplitLane = 32;     // rows up to this length are split by one lane
+constexpr u32 kSplitWave = 4096;   // rows up to this length by one wavefront; longer rows
+                                   // by a whole workgroup (k_split_long)
+constexpr u32 kSplitUnroll = 4;    // 64-entry steps per wavefront iteration
 
-__device__ __forceinline__ bool cover_pred(const uint8_t* __restrict__ vinfo, u32 x, u32 y) {
-  const u32 vx = vinfo[x], vy = vinfo[y];
-  return ((vx ^ vy) & 0x80u) == 0 && key_less(vy & 127u, y, vx & 127u, x);
-}
-
-// Mark entries of tile ti and build s_excl[i] = number of marked entries before e0 + i
-// (s_excl[kTile] = tile total).  rows[] / ys[] receive each thread's entries.
-__device__ __forceinline__ void mark_tile(const TileInfo& ti, const u32* s_rp,
-                                          const u32* __restrict__ rowptr,
-                                          const u32* __restrict__ colidx,
-                                          const uint8_t* __restrict__ vinfo, u32* s_excl,
-                                          u32* s_tmp, u32 rows[kPer], u32 ys[kPer],
-                                          bool preds[kPer]) {
-  u32 run = 0;
+// Partition step over entries j0 .. j0 + 64 kSplitUnroll of the row at `lo` (d entries):
+// counts (COUNT) or writes (!COUNT) the same-level entries, the other-level entries and
+// the partners, advancing the running counts cs / co / ch.
+template <bool COUNT>
+__device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
+                                            const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
+                                            u32 lo, u32 j0, u32 jend, u32 same_base,
+                                            u32 other_base, u32 part_base,
+                                            u32* __restrict__ colidx2, u32* __restrict__ hadj,
+                                            u32& cs, u32& co, u32& ch) {
+  const u32 lane = lane_id();
+  u32 w[kSplitUnroll], vw[kSplitUnroll];
 #pragma unroll
-  for (u32 r = 0; r < kPer; ++r) {
-    const u32 e = ti.e0 + r * kTileThreads + threadIdx.x;
-    bool p = false;
-    u32 x = 0, y = 0;
-    if (e < ti.e1) {
-      x = tile_row_of(ti, s_rp, rowptr, e);
-      y = colidx[e];
-      p = cover_pred(vinfo, x, y);
-    }
-    rows[r] = x;
-    ys[r] = y;
-    preds[r] = p;
-    // wave ballot + mbcnt for the in-wave rank, then a cross-wave prefix
-    const u64 mask = __ballot(p);
-    const u32 wid = threadIdx.x / kWave;
-    if (lane_id() == 0) s_tmp[wid] = (u32)__popcll(mask);
-    __syncthreads();
-    u32 before = 0, tot = 0;
-    for (u32 w = 0; w < kTileThreads / kWave; ++w) {
-      const u32 c = s_tmp[w];
-      if (w < wid) before += c;
-      tot += c;
-    }
-    s_excl[r * kTileThreads + threadIdx.x] = run + before + mask_rank(mask);
-    run += tot;
-    __syncthreads();
+  for (u32 u = 0; u < kSplitUnroll; ++u) {
+    const u32 j = j0 + u * kWave + lane;
+    w[u] = j < jend ? colidx[lo + j] : v;
   }
-  if (threadIdx.x == 0) s_excl[kTile] = run;
-  __syncthreads();
-}
-
-// Marked entries of row x inside the tile: [excl(start), excl(end)).
-__device__ __forceinline__ void row_span(const TileInfo& ti, const u32* __restrict__ rowptr,
-                                         const u32* s_rp, u32 x, u32* a, u32* b) {
-  u32 lo, hi;
-  if (ti.staged) {
-    lo = s_rp[x - ti.r0];
-    hi = s_rp[x - ti.r0 + 1];
-  } else {
-    lo = rowptr[x];
-    hi = rowptr[x + 1];
-  }
-  *a = max(lo, ti.e0) - ti.e0;
-  *b = min(hi, ti.e1) - ti.e0;
-}
-
-__global__ void __launch_bounds__(kTileThreads) k_extract_write(
-    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
-    const u32* __restrict__ tile_row, const uint8_t* __restrict__ vinfo, u32 m,
-    u32* __restrict__ hcnt, u32* __restrict__ hadj) {
-  __shared__ u32 s_rp[kTileRowCap];
-  __shared__ u32 s_excl[kTile + 1];
-  __shared__ u32 s_base[kTileRowCap];
-  __shared__ u32 s_tmp[kTileThreads / kWave];
-  const u32 ntiles = (m + kTile - 1) / kTile;
-  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const TileInfo ti = tile_begin(rowptr, tile_row, t, m, s_rp);
-    u32 rows[kPer], ys[kPer];
-    bool preds[kPer];
-    mark_tile(ti, s_rp, rowptr, colidx, vinfo, s_excl, s_tmp, rows, ys, preds);
-    if (s_excl[kTile] > 0) {
-      if (ti.staged) {
-        // one reservation per row segment of this tile
-        for (u32 x = ti.r0 + threadIdx.x; x <= ti.r1; x += blockDim.x) {
-          u32 a, b;
-          row_span(ti, rowptr, s_rp, x, &a, &b);
-          u32 base = 0;
-          if (a < b) {
-            const u32 c = s_excl[b] - s_excl[a];
-            if (c) base = s_rp[x - ti.r0] + atomicAdd(&hcnt[x], c) - s_excl[a];
-          }
-          s_base[x - ti.r0] = base;
-        }
-        __syncthreads();
 #pragma unroll
-        for (u32 r = 0; r < kPer; ++r) {
-          if (preds[r]) {
-            const u32 i = r * kTileThreads + threadIdx.x;
-            hadj[s_base[rows[r] - ti.r0] + s_excl[i]] = ys[r];
+  for (u32 u = 0; u < kSplitUnroll; ++u) vw[u] = vinfo[w[u]];
+#pragma unroll
+  for (u32 u = 0; u < kSplitUnroll; ++u) {
+    const u32 j = j0 + u * kWave + lane;
+    const bool in = j < jend;
+    const bool same = in && ((vw[u] ^ vx) & 0x80u) == 0;
+    const bool part = same && key_less(vw[u] & 127u, w[u], vx & 127u, v);
+    const u64 ms = __ballot(same), mo = __ballot(in && !same), mh = __ballot(part);
+    if (!COUNT) {
+      if (same) colidx2[lo + same_base + cs + mask_rank(ms)] = w[u];
+      else if (in) colidx2[lo + other_base + co + mask_rank(mo)] = w[u];
+      if (part) hadj[lo + part_base + ch + mask_rank(mh)] = w[u];
+    }
+    cs += (u32)__popcll(ms);
+    co += (u32)__popcll(mo);
+    ch += (u32)__popcll(mh);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowptr,
+                                                   const u32* __restrict__ colidx,
+                                                   const uint8_t* __restrict__ vinfo, u32 n,
+                                                   u32* __restrict__ colidx2,
+                                                   u32* __restrict__ split, u32* __restrict__ hcnt,
+                                                   u32* __restrict__ hadj,
+                                                   u32* __restrict__ long_rows,
+                                                   u32* __restrict__ num_long) {
+  const u32 lane = lane_id();
+  const u32 nr = (n + kWave - 1) / kWave * kWave;  // whole wavefronts iterate together
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < nr; v += gridDim.x * blockDim.x) {
+    u32 lo = 0, d = 0, vx = 0;
+    if (v < n) {
+      lo = rowptr[v];
+      d = rowptr[v + 1] - lo;
+      vx = vinfo[v];
+    }
+    const bool mid = d > kSplitLane && d <= kSplitWave;
+    const bool lng = d > kSplitWave;
+    if (v < n && d <= kSplitLane) {
+      // four entries per step keep four independent gathers in flight
+      u32 ns = 0;
+      for (u32 j = 0; j < d; j += 4) {
+        u32 w[4], vw[4];
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) ns += (j + i < d) && ((vw[i] ^ vx) & 0x80u) == 0;
+      }
+      u32 is = lo, io = lo + ns, ih = lo;
+      for (u32 j = 0; j < d; j += 4) {
+        u32 w[4], vw[4];
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) {
+          if (j + i < d) {
+            if (((vw[i] ^ vx) & 0x80u) == 0) {
+              colidx2[is++] = w[i];
+              if (key_less(vw[i] & 127u, w[i], vx & 127u, v)) hadj[ih++] = w[i];
+            } else {
+              colidx2[io++] = w[i];
+            }
           }
         }
-      } else {
-#pragma unroll
-        for (u32 r = 0; r < kPer; ++r)
-          if (preds[r]) hadj[rowptr[rows[r]] + atomicAdd(&hcnt[rows[r]], 1u)] = ys[r];
+      }
+      split[v] = lo + ns;
+      hcnt[v] = ih - lo;
+    }
+    // long rows go to the workgroup kernel
+    const u32 pos = wave_append(num_long, lng);
+    if (lng) long_rows[pos] = v;
+    // medium rows: one wavefront each, 64 kSplitUnroll entries per step
+    u64 mm = __ballot(mid);
+    while (mm) {
+      const int b = __ffsll((unsigned long long)mm) - 1;
+      mm &= mm - 1;
+      const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
+      const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
+      u32 ns = 0, no = 0, nh = 0;
+      for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
+        split_steps<true>(colidx, vinfo, bv, bvx, blo, j0, bd, 0, 0, 0, colidx2, hadj, ns, no,
+                          nh);
+      u32 cs = 0, co = 0, ch = 0;
+      for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
+        split_steps<false>(colidx, vinfo, bv, bvx, blo, j0, bd, 0, ns, 0, colidx2, hadj, cs, co,
+                           ch);
+      if ((int)lane == b) {
+        split[bv] = blo + ns;
+        hcnt[bv] = nh;
       }
     }
-    __syncthreads();
   }
 }
 
-void launch_extract(const u32* rowptr, const u32* colidx, const u32* tile_row,
-                    const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, u32* hadj, hipStream_t s) {
-  (void)n;
-  if (m == 0) return;
-  const u32 g = min(cdiv(m, kTile), (u32)num_cus() * 8);
-  hipLaunchKernelGGL(k_extract_write, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                     tile_row, vinfo, m, hcnt, hadj);
+// Long rows: one 1024-thread workgroup per row; each wavefront takes a contiguous
+// segment, and a workgroup scan of the segments' counts gives every wavefront its output
+// offsets, so both parts stay in ascending order.
+constexpr u32 kLongThreads = 1024;
+constexpr u32 kLongWaves = kLongThreads / kWave;
+
+__global__ void __launch_bounds__(kLongThreads) k_split_long(
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+    const uint8_t* __restrict__ vinfo, const u32* __restrict__ long_rows,
+    const u32* __restrict__ num_long, u32* __restrict__ next_long, u32* __restrict__ colidx2,
+    u32* __restrict__ split, u32* __restrict__ hcnt, u32* __restrict__ hadj) {
+  __shared__ u32 s_cnt[2][kLongWaves];
+  __shared__ u32 s_row;
+  const u32 wid = threadIdx.x / kWave, lane = lane_id();
+  const u32 nl = *num_long;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const u32 i = atomicAdd(next_long, 1u);
+      s_row = i < nl ? long_rows[i] : kInf;
+    }
+    __syncthreads();
+    const u32 v = s_row;
+    if (v == kInf) break;
+    const u32 lo = rowptr[v], d = rowptr[v + 1] - lo, vx = vinfo[v];
+    const u32 step = kWave * kSplitUnroll;
+    const u32 seg = (d + kLongWaves * step - 1) / (kLongWaves * step) * step;
+    const u32 j0 = min(wid * seg, d), j1 = min(j0 + seg, d);
+    u32 ns = 0, no = 0, nh = 0;
+    for (u32 j = j0; j < j1; j += step)
+      split_steps<true>(colidx, vinfo, v, vx, lo, j, j1, 0, 0, 0, colidx2, hadj, ns, no, nh);
+    if (lane == 0) {
+      s_cnt[0][wid] = ns;
+      s_cnt[1][wid] = nh;
+    }
+    __syncthreads();
+    u32 bs = 0, bh = 0, ts = 0, th = 0;
+    for (u32 w = 0; w < kLongWaves; ++w) {
+      if (w < wid) {
+        bs += s_cnt[0][w];
+        bh += s_cnt[1][w];
+      }
+      ts += s_cnt[0][w];
+      th += s_cnt[1][w];
+    }
+    u32 cs = 0, co = 0, ch = 0;
+    for (u32 j = j0; j < j1; j += step)
+      split_steps<false>(colidx, vinfo, v, vx, lo, j, j1, bs, ts + (j0 - bs), bh, colidx2, hadj,
+                         cs, co, ch);
+    if (threadIdx.x == 0) {
+      split[v] = lo + ts;
+      hcnt[v] = th;
+    }
+    __syncthreads();  // s_cnt and s_row are rewritten for the next row
+  }
+}
+
+void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n,
+                       u32* colidx2, u32* split, u32* hcnt, u32* hadj, u32* long_rows,
+                       u32* counters, hipStream_t s) {
+  if (n == 0) return;
+  const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, s, rowptr, colidx, vinfo, n, colidx2,
+                     split, hcnt, hadj, long_rows, counters);
+  hipLaunchKernelGGL(k_split_long, dim3(num_cus()), dim3(kLongThreads), 0, s, rowptr, colidx,
+                     vinfo, long_rows, counters, counters + 1, colidx2, split, hcnt, hadj);
 }
 
 // ---- planning: split the staged endpoints x into the three intersection classes ----

@@ -221,21 +221,168 @@ constexpr int kBigSlots = 32768;   // 128 KB of LDS
 constexpr int kBigSeg = 1024;      // partners per work item (one per thread for set-up)
 constexpr int kQuadUnroll = 4;     // windows per wavefront loaded before probing
 
-template <bool PV, bool VEC>
+// What one pass of the workgroup kernel stages, streams and tallies:
+//   kFull     : N(x) with level flags; each partner's whole list; c1, c2 and t2
+//               (diagnostics and per-vertex counts);
+//   kPrunedOne: N(x) with level flags in one chunk; each partner's same-level
+//               neighbours above max(x, y) and its other-level ones (one contiguous
+//               range of the level-split rows); c1 and t2;
+//   kOther    : the other-level part of N(x); each partner's other-level part; c1;
+//   kSame     : the same-level part of N(x) above x; each partner's same-level part
+//               above max(x, y); t2 (every hit is a same-level apex above both ends).
+// A same-level apex w <= max(x, y) is never counted (the apex rule), so the pruned
+// passes skip those list entries entirely and leave c2 uncounted.
+enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3 };
+
+struct BlockShared {
+  u32* table;
+  u32* qincl;
+  uint4* pinfo;
+  u32* tmp;
+};
+
+// One pass over the partners of a work item.  The staged keys ga[gs .. ge) are taken in
+// chunks of prm.chunk (ascending IDs where there are several chunks); partner `tid` < pn
+// streams sa[plo .. phi), cut at each chunk's largest ID.  All threads of the workgroup
+// call it together.
+template <bool PV, bool VEC, int MODE>
+__device__ __forceinline__ void block_pass(
+    const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
+    u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
+    u32 phi, IsectParams prm, const BlockShared& sh, Tally& tl, Counts& c, u64* __restrict__ tri) {
+  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
+  const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  const u32 glen = ge - gs;
+  const u32 nch = (glen + prm.chunk - 1) / prm.chunk;
+  u32 lo = plo;  // cursor: elements below it were probed against earlier chunks
+  for (u32 ch = 0; ch < nch; ++ch) {
+    const u32 c0 = gs + ch * prm.chunk, clen = min(prm.chunk, ge - c0);
+    const u32 mask = bucket_mask(clen, kBigSlots);
+    c.staged += tid == 0 ? clen : 0;
+    for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) sh.table[i] = kInf;
+    // this partner's elements up to the chunk's largest ID (the ones between two
+    // chunks are in no chunk and find nothing in either)
+    u32 hi = phi;
+    if (tid < pn && ch + 1 < nch) hi = lower_bound_g(sa, lo, phi, ga[c0 + clen - 1] + 1u);
+    tl.probes += hi - lo;
+    const u32 qa = VEC ? (lo & ~3u) : lo;
+    const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
+    u32 total;
+    const u32 incl = block_incl_scan(nq, sh.tmp, &total);
+    if (tid < pn) {
+      sh.qincl[tid] = incl;
+      sh.pinfo[tid] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
+    }
+    for (u32 i = tid; i < clen; i += blockDim.x) {
+      const u32 w = ga[c0 + i];
+      const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
+      hash_insert(sh.table, mask, w, same ? 1u : 0u);
+    }
+    __syncthreads();
+    // this wavefront's contiguous quad range, in whole windows
+    const u32 per = (total + kBigWaves * kWave - 1) / (kBigWaves * kWave) * kWave;
+    const u32 qs = min(wid * per, total), qe = min(qs + per, total);
+    // partner of quad qs: smallest p with qincl[p] > qs (lane-uniform search)
+    u32 pcur = 0;
+    {
+      u32 h = pn - 1;
+      while (pcur < h) {
+        const u32 mid = (pcur + h) >> 1;
+        if (sh.qincl[mid] > qs) h = mid;
+        else pcur = mid + 1;
+      }
+    }
+    for (u32 qw = qs; qw < qe; qw += kWave * kQuadUnroll) {
+      u32 e[kQuadUnroll][NE];
+      uint4 inf[kQuadUnroll];
+      u32 addr[kQuadUnroll];
+      bool live[kQuadUnroll];
+#pragma unroll
+      for (int u = 0; u < kQuadUnroll; ++u) {
+        const u32 w0 = qw + u * kWave;        // first quad of this window
+        const u32 q = w0 + lane;
+        live[u] = q < qe;
+        // partner of q: pcur plus the boundaries (qincl values) <= q in this window
+        u32 p = pcur;
+        while (true) {
+          const u32 j = pcur + lane;
+          const u32 bj = j < pn ? sh.qincl[j] : kInf;
+          u64 bm = __ballot(bj <= w0 + kWave - 1);
+          const u32 nb = (u32)__popcll(bm);
+          while (bm) {
+            const int jl = __ffsll((unsigned long long)bm) - 1;
+            bm &= bm - 1;
+            p += q >= (u32)__shfl(bj, jl, kWave) ? 1u : 0u;
+          }
+          pcur += nb;
+          if (nb < (u32)kWave) break;
+        }
+        p = min(p, pn - 1);  // lanes past the range keep a valid index
+        inf[u] = sh.pinfo[p];
+        addr[u] = (inf[u].x + q) * NE;
+        if (VEC) {
+          // one unconditional 16-byte load: a quad that would run past the end of the
+          // streamed array (or a dead lane) reads the padded copy of its last partial quad
+          const u32* src = (live[u] && addr[u] + 3 < m) ? sa + addr[u] : st4;
+          const uint4 v = *reinterpret_cast<const uint4*>(src);
+          e[u][0] = v.x;
+          e[u][NE > 1 ? 1 : 0] = v.y;
+          e[u][NE > 2 ? 2 : 0] = v.z;
+          e[u][NE > 3 ? 3 : 0] = v.w;
+        } else {
+          e[u][0] = sa[live[u] ? addr[u] : 0u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kQuadUnroll; ++u) {
+        const u32 y2 = inf[u].w;
+        const u32 vmax = max(x, y2);
+        const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
+        bool ok[NE];
+#pragma unroll
+        for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
+        u32 res[NE];
+        hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
+#pragma unroll
+        for (u32 i = 0; i < NE; ++i) {
+          if (MODE == kFull) {
+            tl.add(res[i], e[u][i], vmax);
+            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+          } else if (MODE == kPrunedOne) {
+            tl.s += res[i] & 1u;  // other-level apex (c1)
+            tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
+          } else if (MODE == kOther) {
+            tl.s += res[i];
+          } else {
+            tl.t2 += res[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    lo = hi;
+  }
+}
+
+// PRUNED = false: kFull pass over colidx.  PRUNED = true: the level-split rows colidx2
+// (split[v] = start of v's other-level neighbours), one kPrunedOne pass when N(x) fits
+// one chunk, else a kOther and a kSame pass.
+template <bool PV, bool VEC, bool PRUNED>
 __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
-    const u32* __restrict__ tail4,
+    const u32* __restrict__ tail4, const u32* __restrict__ colidx2,
+    const u32* __restrict__ split, const u32* __restrict__ tail4b,
     const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
     const Item* __restrict__ items, u32 nitems, IsectParams prm, Plan* __restrict__ plan,
     u64* __restrict__ ctr, u64* __restrict__ tri) {
-  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
   __shared__ __align__(16) u32 s_table[kBigSlots];
   __shared__ u32 s_qincl[kBigSeg];
   __shared__ uint4 s_pinfo[kBigSeg];  // {quad base, lo, hi, y} of each partner
   __shared__ u32 s_tmp[kBigWaves];
   __shared__ u64 s_red[5 * kBigWaves];
   __shared__ u32 s_item;
-  const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  const BlockShared sh{s_table, s_qincl, s_pinfo, s_tmp};
+  const u32 tid = threadIdx.x;
   Counts c{0, 0, 0, 0, 0};
   Tally tl{0, 0, 0, 0};
   while (true) {
@@ -245,114 +392,36 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     if (it >= nitems) break;
     const Item item = items[it];
     const u32 x = item.x;
-    const u32 bx = rowptr[x], dx = rowptr[x + 1] - bx;
+    const u32 bx = rowptr[x], ex = rowptr[x + 1], dx = ex - bx;
     const u32 px = vinfo[x] & 0x80u;
     const u32 hs = bx + item.seg * prm.seg;  // H+(x) sits in place of N(x)
     const u32 pn = min(prm.seg, hcnt[x] - item.seg * prm.seg);
-    u32 y = 0, ylo = 0, yhi = 0;
+    u32 y = 0, yr = 0, ye = 0;
     if (tid < pn) {
       y = hadj[hs + tid];
-      ylo = rowptr[y];
-      yhi = rowptr[y + 1];
+      yr = rowptr[y];
+      ye = rowptr[y + 1];
     }
-    const u32 nch = (dx + prm.chunk - 1) / prm.chunk;
-    u32 lo = ylo;  // cursor: elements below it were probed against earlier chunks
-    for (u32 ch = 0; ch < nch; ++ch) {
-      const u32 c0 = ch * prm.chunk, clen = min(prm.chunk, dx - c0);
-      const u32 mask = bucket_mask(clen, kBigSlots);
-      c.staged += tid == 0 ? clen : 0;
-      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) s_table[i] = kInf;
-      // this partner's elements up to the chunk's largest ID (the ones between two
-      // chunks are in no chunk and find nothing in either)
-      u32 hi = yhi;
-      if (tid < pn && ch + 1 < nch) hi = lower_bound_g(colidx, lo, yhi, colidx[bx + c0 + clen - 1] + 1u);
-      tl.probes += hi - lo;
-      const u32 qa = VEC ? (lo & ~3u) : lo;
-      const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
-      u32 total;
-      const u32 incl = block_incl_scan(nq, s_tmp, &total);
+    if (!PRUNED) {
+      block_pass<PV, VEC, kFull>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y, pn, yr, ye,
+                                 prm, sh, tl, c, tri);
+    } else {
+      u32 ys = 0, lb = 0;
       if (tid < pn) {
-        s_qincl[tid] = incl;
-        s_pinfo[tid] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
+        ys = split[y];
+        lb = lower_bound_g(colidx2, yr, ys, max(x, y) + 1u);  // same-level part above max
       }
-      for (u32 i = tid; i < clen; i += blockDim.x) {
-        const u32 w = colidx[bx + c0 + i];
-        hash_insert(s_table, mask, w, ((vinfo[w] & 0x80u) == px) ? 1u : 0u);
+      if (dx <= prm.chunk) {
+        block_pass<false, VEC, kPrunedOne>(colidx2, m, tail4b, colidx, bx, ex, vinfo, x, px, y,
+                                           pn, lb, ye, prm, sh, tl, c, tri);
+      } else {
+        const u32 sx = split[x];
+        const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
+        block_pass<false, VEC, kOther>(colidx2, m, tail4b, colidx2, sx, ex, vinfo, x, px, y, pn,
+                                       ys, ye, prm, sh, tl, c, tri);
+        block_pass<false, VEC, kSame>(colidx2, m, tail4b, colidx2, gx, sx, vinfo, x, px, y, pn,
+                                      lb, ys, prm, sh, tl, c, tri);
       }
-      __syncthreads();
-      // this wavefront's contiguous quad range, in whole windows
-      const u32 per = (total + kBigWaves * kWave - 1) / (kBigWaves * kWave) * kWave;
-      const u32 qs = min(wid * per, total), qe = min(qs + per, total);
-      // partner of quad qs: smallest p with qincl[p] > qs (lane-uniform search)
-      u32 pcur = 0;
-      {
-        u32 h = pn - 1;
-        while (pcur < h) {
-          const u32 mid = (pcur + h) >> 1;
-          if (s_qincl[mid] > qs) h = mid;
-          else pcur = mid + 1;
-        }
-      }
-      for (u32 qw = qs; qw < qe; qw += kWave * kQuadUnroll) {
-        u32 e[kQuadUnroll][NE];
-        uint4 inf[kQuadUnroll];
-        u32 addr[kQuadUnroll];
-        bool live[kQuadUnroll];
-#pragma unroll
-        for (int u = 0; u < kQuadUnroll; ++u) {
-          const u32 w0 = qw + u * kWave;        // first quad of this window
-          const u32 q = w0 + lane;
-          live[u] = q < qe;
-          // partner of q: pcur plus the boundaries (qincl values) <= q in this window
-          u32 p = pcur;
-          while (true) {
-            const u32 j = pcur + lane;
-            const u32 bj = j < pn ? s_qincl[j] : kInf;
-            u64 bm = __ballot(bj <= w0 + kWave - 1);
-            const u32 nb = (u32)__popcll(bm);
-            while (bm) {
-              const int jl = __ffsll((unsigned long long)bm) - 1;
-              bm &= bm - 1;
-              p += q >= (u32)__shfl(bj, jl, kWave) ? 1u : 0u;
-            }
-            pcur += nb;
-            if (nb < (u32)kWave) break;
-          }
-          p = min(p, pn - 1);  // lanes past the range keep a valid index
-          inf[u] = s_pinfo[p];
-          addr[u] = (inf[u].x + q) * NE;
-          if (VEC) {
-            // one unconditional 16-byte load: a quad that would run past the end of
-            // colidx (or a dead lane) reads the padded copy of the last partial quad
-            const u32* src = (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
-            const uint4 v = *reinterpret_cast<const uint4*>(src);
-            e[u][0] = v.x;
-            e[u][NE > 1 ? 1 : 0] = v.y;
-            e[u][NE > 2 ? 2 : 0] = v.z;
-            e[u][NE > 3 ? 3 : 0] = v.w;
-          } else {
-            e[u][0] = colidx[live[u] ? addr[u] : 0u];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kQuadUnroll; ++u) {
-          const u32 y2 = inf[u].w;
-          const u32 vmax = max(x, y2);
-          const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
-          bool ok[NE];
-#pragma unroll
-          for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
-          u32 res[NE];
-          hash_probe_n<NE>(s_table, mask, e[u], ok, res);
-#pragma unroll
-          for (u32 i = 0; i < NE; ++i) {
-            tl.add(res[i], e[u][i], vmax);
-            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
-          }
-        }
-      }
-      __syncthreads();
-      lo = hi;
     }
     tl.fold(c);
   }
@@ -416,21 +485,26 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* t
 }
 
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                        const uint8_t* vinfo,
-                        const u32* hcnt, const u32* hadj, const Item* items, u32 nitems,
-                        IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
+                        const u32* colidx2, const u32* split, const u32* tail4b,
+                        const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const Item* items,
+                        u32 nitems, IsectParams p, Plan* plan, u64* ctr, u64* tri, bool pruned,
+                        hipStream_t s) {
   if (nitems == 0) return;
   const u32 g = min(nitems, resident_blocks(1));
-  const bool vec = ((uintptr_t)colidx & 15u) == 0;
-#define TC_LAUNCH_BLOCK(PV, VEC)                                                             \
-  hipLaunchKernelGGL((k_isect_block<PV, VEC>), dim3(g), dim3(kBigThreads), 0, s, rowptr, colidx, \
-                     m, tail4, vinfo, hcnt, hadj, items, nitems, p, plan, ctr, tri)
+  const bool vec = ((uintptr_t)colidx & 15u) == 0 && ((uintptr_t)colidx2 & 15u) == 0;
+#define TC_LAUNCH_BLOCK(PV, VEC, PR)                                                           \
+  hipLaunchKernelGGL((k_isect_block<PV, VEC, PR>), dim3(g), dim3(kBigThreads), 0, s, rowptr,    \
+                     colidx, m, tail4, colidx2, split, tail4b, vinfo, hcnt, hadj, items, nitems, \
+                     p, plan, ctr, tri)
   if (tri) {
-    if (vec) TC_LAUNCH_BLOCK(true, true);
-    else TC_LAUNCH_BLOCK(true, false);
+    if (vec) TC_LAUNCH_BLOCK(true, true, false);
+    else TC_LAUNCH_BLOCK(true, false, false);
+  } else if (pruned) {
+    if (vec) TC_LAUNCH_BLOCK(false, true, true);
+    else TC_LAUNCH_BLOCK(false, false, true);
   } else {
-    if (vec) TC_LAUNCH_BLOCK(false, true);
-    else TC_LAUNCH_BLOCK(false, false);
+    if (vec) TC_LAUNCH_BLOCK(false, true, false);
+    else TC_LAUNCH_BLOCK(false, false, false);
   }
 #undef TC_LAUNCH_BLOCK
 }

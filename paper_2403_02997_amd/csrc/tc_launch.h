@@ -39,7 +39,8 @@ struct Plan {
   u32 num_cover;    // cover edges |S| = sum of hcnt
   u32 next_wave;    // dynamic work counters
   u32 next_item;
-  u32 pad;
+  u32 num_long;     // rows split by a whole workgroup, and their work counter
+  u32 next_long;
 };
 
 struct Item {
@@ -70,10 +71,13 @@ void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* l
 u32 bfs_grid(u32 n);
 
 // ---- cover-edge extraction ----
-// Partner lists in place: H+(x) = hadj[rowptr[x] .. rowptr[x] + hcnt[x]) (hadj has m
-// entries; hcnt zeroed before the launch).
-void launch_extract(const u32* rowptr, const u32* colidx, const u32* tile_row,
-                    const uint8_t* vinfo, u32 n, u32 m, u32* hcnt, u32* hadj, hipStream_t s);
+// Per vertex v: colidx2[rowptr[v] .. split[v]) = neighbours on v's level (ascending),
+// colidx2[split[v] .. rowptr[v + 1]) = the others (ascending), and the partner list
+// H+(v) = hadj[rowptr[v] .. rowptr[v] + hcnt[v]).  colidx2 and hadj hold m entries.
+// long_rows: n words of scratch; counters: two words, zeroed before the launch.
+void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n,
+                       u32* colidx2, u32* split, u32* hcnt, u32* hadj, u32* long_rows,
+                       u32* counters, hipStream_t s);
 void launch_plan(const u32* rowptr, const u32* hcnt, u32 n, IsectParams p, u32* lane_x,
                  u32* wave_x, u32* block_x, u32* block_items, Plan* plan, hipStream_t s);
 void launch_fill_items(const u32* rowptr, const u32* hcnt, const u32* block_x,
@@ -88,10 +92,13 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* t
                        const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const u32* wave_x,
                        u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
 void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s);
+// pruned: count c1 and t2 only, from the level-split rows colidx2 / split (tail4b is
+// the padded last quad of colidx2); otherwise c1, c2 and t2 from colidx.
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                        const uint8_t* vinfo,
-                        const u32* hcnt, const u32* hadj, const Item* items, u32 nitems,
-                        IsectParams p, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
+                        const u32* colidx2, const u32* split, const u32* tail4b,
+                        const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const Item* items,
+                        u32 nitems, IsectParams p, Plan* plan, u64* ctr, u64* tri, bool pruned,
+                        hipStream_t s);
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);
 
 // ---- batched, fused per-graph pipeline ----

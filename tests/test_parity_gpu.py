@@ -119,9 +119,11 @@ def test_every_class_setting_gives_the_same_count(tc_lib, name, params):
     try:
         tc_lib.tc_set_isect_params(*params)
         stats, _ = tc_lib.tc_count_ex(rp, ci)
+        pruned = tc_lib.tc_count(rp, ci)
     finally:
         tc_lib.tc_set_isect_params(*saved)
     assert stats.triangles == r.triangles and stats.cover_edges == r.cover_edges
+    assert pruned == r.triangles
 
 
 @pytest.mark.parametrize("name", ["rmat14_ef32", "book10000", "er16_d32", "grid64_del"])
@@ -140,6 +142,7 @@ def test_unaligned_colidx(tc_lib, name):
             tc_lib.tc_set_isect_params(*params)
             stats, _ = tc_lib.tc_count_ex(rp, shifted)
             assert stats.triangles == r.triangles and stats.cover_edges == r.cover_edges
+            assert tc_lib.tc_count(rp, shifted) == r.triangles
     finally:
         tc_lib.tc_set_isect_params(*saved)
 
