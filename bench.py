@@ -49,8 +49,10 @@ METRIC = "input edges/s for cover-edge TC (bit-exact u64), batched vs per-graph 
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
-KERNEL_OF_STEP = {"isect_lane": "k_isect_lane", "isect_wave": "k_isect_wave",
-                  "isect_block": "k_isect_block"}
+# The kernel instance tc_count launches for each intersection step (16-byte aligned
+# colidx, no per-vertex attribution; the workgroup class in its pruned form).
+KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>", "isect_wave": "k_isect_wave<false, true>",
+                  "isect_block": "k_isect_block<false, true, true>"}
 
 WORKLOAD_TEXT = {
     "rmat10": "R-MAT scale 10, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1000",
@@ -89,30 +91,51 @@ def degree_class(d: np.ndarray) -> np.ndarray:
 
 
 def class_bytes(g, level: np.ndarray, params) -> dict:
-    """Per intersection class: cover edges, 4 * sum over its cover edges of min(d(u), d(v))
-    (the shorter list streamed once) and 4 * sum of d(x) over its staged vertices x (each
-    staged list read once)."""
-    lane_max, wave_max = params[0], params[1]
-    d = g.degrees()
+    """Per intersection class of tc_count: cover edges and the bytes its kernel has to
+    read at least once.  A cover edge {x, y} is staged under x (larger degree class, then
+    ID) and streams y's list.  Lane and wavefront classes stream all of N(y) and stage
+    N(x); the workgroup class streams only y's other-level neighbours and its same-level
+    neighbours above max(x, y), and stages N(x) whole when it fits one chunk, else its
+    other-level part and its same-level part above x.  Each staged list counts once."""
+    lane_max, wave_max, chunk = params[0], params[1], params[2]
+    d = g.degrees().astype(np.int64)
+    rp = g.rowptr.astype(np.int64)
     rows = np.repeat(np.arange(g.n, dtype=np.int64), d)
     cols = g.colidx.astype(np.int64)
     par = (level & 1).astype(np.int8)
+    same_entry = par[rows] == par[cols]
+    cs = np.concatenate([[0], np.cumsum(same_entry, dtype=np.int64)])
+    del same_entry
     m = (par[rows] == par[cols]) & (rows < cols)
     u, v = rows[m], cols[m]
-    del rows, cols, m
+    del m
+    key = rows * (1 << 32) + cols  # sorted: rows ascending, columns ascending within
+    del rows, cols
     cls_d = degree_class(d)
     key_u = cls_d[u] * (1 << 32) + u
     key_v = cls_d[v] * (1 << 32) + v
     x = np.where(key_u > key_v, u, v)
+    y = np.where(key_u > key_v, v, u)
+    del u, v, key_u, key_v
     dx = d[x]
-    mn = np.minimum(d[u], d[v])
     out = {}
     for name, sel in (("isect_lane", dx <= lane_max),
                       ("isect_wave", (dx > lane_max) & (dx <= wave_max)),
                       ("isect_block", dx > wave_max)):
         xs = np.unique(x[sel])
-        out[name] = {"cover_edges": int(sel.sum()),
-                     "bytes": 4 * int(mn[sel].sum()) + 4 * int(d[xs].sum())}
+        ys = y[sel]
+        if name != "isect_block":
+            streamed = int(d[ys].sum())
+            staged = int(d[xs].sum())
+        else:
+            vmax = np.maximum(x[sel], ys)
+            pos = np.searchsorted(key, ys * (1 << 32) + vmax, side="right")
+            skip = cs[pos] - cs[rp[ys]]
+            streamed = int((d[ys] - skip).sum())
+            same_x = cs[rp[xs + 1]] - cs[rp[xs]]
+            above = cs[rp[xs + 1]] - cs[np.searchsorted(key, xs * (1 << 32) + xs, side="right")]
+            staged = int(np.where(d[xs] <= chunk, d[xs], d[xs] - same_x + above).sum())
+        out[name] = {"cover_edges": int(sel.sum()), "bytes": 4 * (streamed + staged)}
     return out
 
 
@@ -445,15 +468,14 @@ def bench_serve(args, tcm, torch):
 # ---- counter-measured HBM traffic ---------------------------------------------------------
 
 def _pmc_per_kernel(path: str, counter: str) -> dict:
-    """Mean counter value (KiB) per dispatch, by short kernel name."""
+    """Mean counter value (KiB) per dispatch, by kernel name with template arguments."""
     import csv
     acc = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        name = r["Kernel_Name"]
-        short = name.split("(")[0].split("<")[0].replace("void ", "").split("::")[-1]
-        acc.setdefault(short, []).append(float(r["Counter_Value"]))
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("tc::", "")
+        acc.setdefault(name, []).append(float(r["Counter_Value"]))
     return {k: (sum(v) / len(v), len(v), max(v)) for k, v in acc.items()}
 
 
@@ -471,8 +493,8 @@ def traffic_summary(args):
     rec = db.setdefault(args.workload, {})
     lines = [f"copy calibration: {mib} MiB device copy reads FETCH_SIZE {cf:.1f} KiB "
              f"(factor {f_fetch:.4f}) and WRITE_SIZE {cw:.1f} KiB (factor {f_write:.4f})"]
-    for k in sorted(KERNEL_OF_STEP.values()):
-        if k not in fetch or k not in write:
+    for k in sorted(fetch):
+        if not k.startswith("k_isect") or k not in write:
             continue
         fb = fetch[k][0] * 1024 / f_fetch
         wb = write[k][0] * 1024 / f_write

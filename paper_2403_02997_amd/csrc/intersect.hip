@@ -241,29 +241,51 @@ struct BlockShared {
   u32* tmp;
 };
 
-// One pass over the partners of a work item.  The staged keys ga[gs .. ge) are taken in
-// chunks of prm.chunk (ascending IDs where there are several chunks); partner `tid` < pn
-// streams sa[plo .. phi), cut at each chunk's largest ID.  All threads of the workgroup
-// call it together.
-template <bool PV, bool VEC, int MODE>
+// One pass over the partners of a work item.  The staged keys ga[gs .. ge) (ascending)
+// go to LDS either as hash sets of at most prm.chunk keys (BM = false) or, for the
+// level-specific pruned passes, as bitmaps of one 2^kWinBits-ID window each (BM = true,
+// one bit per ID: these passes need membership only).  Partner `tid` < pn streams
+// sa[plo .. phi), cut at each chunk's largest ID or window end.  All threads of the
+// workgroup call it together.
+constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
+
+template <bool PV, bool VEC, int MODE, bool BM>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
     u32 phi, IsectParams prm, const BlockShared& sh, Tally& tl, Counts& c, u64* __restrict__ tri) {
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
   const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  static_assert(!BM || MODE == kOther || MODE == kSame, "bitmaps hold membership only");
   const u32 glen = ge - gs;
-  const u32 nch = (glen + prm.chunk - 1) / prm.chunk;
+  // hash chunks by count, or bitmap windows by ID
+  const u32 w_first = BM && glen ? ga[gs] >> kWinBits : 0u;
+  const u32 nch = BM ? (glen ? (ga[ge - 1] >> kWinBits) - w_first + 1 : 0u)
+                     : (glen + prm.chunk - 1) / prm.chunk;
   u32 lo = plo;  // cursor: elements below it were probed against earlier chunks
+  u32 c0 = gs;   // first staged key of the chunk
   for (u32 ch = 0; ch < nch; ++ch) {
-    const u32 c0 = gs + ch * prm.chunk, clen = min(prm.chunk, ge - c0);
-    const u32 mask = bucket_mask(clen, kBigSlots);
+    const u32 wb = (w_first + ch) << kWinBits;  // BM: window [wb, wb + 2^kWinBits)
+    u32 clen;
+    if (BM) {
+      clen = lower_bound_g(ga, c0, ge, wb + (1u << kWinBits)) - c0;
+      if (clen == 0) continue;  // no staged key in this window (uniform)
+    } else {
+      clen = min(prm.chunk, ge - c0);
+    }
+    const u32 mask = BM ? 0u : bucket_mask(clen, kBigSlots);
     c.staged += tid == 0 ? clen : 0;
-    for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) sh.table[i] = kInf;
-    // this partner's elements up to the chunk's largest ID (the ones between two
-    // chunks are in no chunk and find nothing in either)
+    if (BM) {
+      uint4* t4 = reinterpret_cast<uint4*>(sh.table);
+      for (u32 i = tid; i < (u32)kBigSlots / 4; i += blockDim.x) t4[i] = make_uint4(0, 0, 0, 0);
+    } else {
+      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) sh.table[i] = kInf;
+    }
+    // this partner's elements up to the chunk's largest ID or the window's end (the
+    // ones between two chunks are in no chunk and find nothing in either)
     u32 hi = phi;
-    if (tid < pn && ch + 1 < nch) hi = lower_bound_g(sa, lo, phi, ga[c0 + clen - 1] + 1u);
+    if (tid < pn && ch + 1 < nch)
+      hi = lower_bound_g(sa, lo, phi, BM ? wb + (1u << kWinBits) : ga[c0 + clen - 1] + 1u);
     tl.probes += hi - lo;
     const u32 qa = VEC ? (lo & ~3u) : lo;
     const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
@@ -273,10 +295,18 @@ __device__ __forceinline__ void block_pass(
       sh.qincl[tid] = incl;
       sh.pinfo[tid] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
     }
-    for (u32 i = tid; i < clen; i += blockDim.x) {
-      const u32 w = ga[c0 + i];
-      const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
-      hash_insert(sh.table, mask, w, same ? 1u : 0u);
+    if (BM) {
+      __syncthreads();  // the bitmap is cleared
+      for (u32 i = tid; i < clen; i += blockDim.x) {
+        const u32 k = ga[c0 + i] - wb;
+        atomicOr(&sh.table[k >> 5], 1u << (k & 31u));
+      }
+    } else {
+      for (u32 i = tid; i < clen; i += blockDim.x) {
+        const u32 w = ga[c0 + i];
+        const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
+        hash_insert(sh.table, mask, w, same ? 1u : 0u);
+      }
     }
     __syncthreads();
     // this wavefront's contiguous quad range, in whole windows
@@ -342,7 +372,18 @@ __device__ __forceinline__ void block_pass(
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
         u32 res[NE];
-        hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
+        if (BM) {
+          // elements of earlier, skipped windows fall outside [wb, wb + 2^kWinBits)
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) {
+            const u32 k = e[u][i] - wb;
+            const bool in = ok[i] && k < (1u << kWinBits);
+            const u32 kk = in ? k : 0u;
+            res[i] = in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
+          }
+        } else {
+          hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
+        }
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) {
           if (MODE == kFull) {
@@ -361,7 +402,16 @@ __device__ __forceinline__ void block_pass(
     }
     __syncthreads();
     lo = hi;
+    c0 += clen;
   }
+}
+
+// Bitmap windows for the sorted keys a[s .. e) when they take fewer passes than hash
+// chunks of `chunk` keys.
+__device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32 e, u32 chunk) {
+  if (e - s <= chunk) return false;
+  const u32 wins = (a[e - 1] >> kWinBits) - (a[s] >> kWinBits) + 1;
+  return wins < (e - s + chunk - 1) / chunk;
 }
 
 // PRUNED = false: kFull pass over colidx.  PRUNED = true: the level-split rows colidx2
@@ -403,8 +453,8 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
       ye = rowptr[y + 1];
     }
     if (!PRUNED) {
-      block_pass<PV, VEC, kFull>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y, pn, yr, ye,
-                                 prm, sh, tl, c, tri);
+      block_pass<PV, VEC, kFull, false>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y, pn, yr,
+                                        ye, prm, sh, tl, c, tri);
     } else {
       u32 ys = 0, lb = 0;
       if (tid < pn) {
@@ -412,15 +462,24 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
         lb = lower_bound_g(colidx2, yr, ys, max(x, y) + 1u);  // same-level part above max
       }
       if (dx <= prm.chunk) {
-        block_pass<false, VEC, kPrunedOne>(colidx2, m, tail4b, colidx, bx, ex, vinfo, x, px, y,
-                                           pn, lb, ye, prm, sh, tl, c, tri);
+        block_pass<false, VEC, kPrunedOne, false>(colidx2, m, tail4b, colidx, bx, ex, vinfo, x, px,
+                                                  y, pn, lb, ye, prm, sh, tl, c, tri);
       } else {
         const u32 sx = split[x];
         const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
-        block_pass<false, VEC, kOther>(colidx2, m, tail4b, colidx2, sx, ex, vinfo, x, px, y, pn,
-                                       ys, ye, prm, sh, tl, c, tri);
-        block_pass<false, VEC, kSame>(colidx2, m, tail4b, colidx2, gx, sx, vinfo, x, px, y, pn,
-                                      lb, ys, prm, sh, tl, c, tri);
+        // bitmap windows where they need fewer passes than hash chunks
+        if (use_bitmap(colidx2, sx, ex, prm.chunk))
+          block_pass<false, VEC, kOther, true>(colidx2, m, tail4b, colidx2, sx, ex, vinfo, x, px, y,
+                                               pn, ys, ye, prm, sh, tl, c, tri);
+        else
+          block_pass<false, VEC, kOther, false>(colidx2, m, tail4b, colidx2, sx, ex, vinfo, x, px,
+                                                y, pn, ys, ye, prm, sh, tl, c, tri);
+        if (use_bitmap(colidx2, gx, sx, prm.chunk))
+          block_pass<false, VEC, kSame, true>(colidx2, m, tail4b, colidx2, gx, sx, vinfo, x, px, y,
+                                              pn, lb, ys, prm, sh, tl, c, tri);
+        else
+          block_pass<false, VEC, kSame, false>(colidx2, m, tail4b, colidx2, gx, sx, vinfo, x, px, y,
+                                               pn, lb, ys, prm, sh, tl, c, tri);
       }
     }
     tl.fold(c);
