@@ -288,7 +288,8 @@ def bench_batch(args, tcm, torch):
     ro = torch.from_numpy(b.row_off).cuda()
     co = torch.from_numpy(b.col_off).cuda()
     rows = int(b.rowptr_cat.shape[0])
-    ws = torch.empty(tcm.tc_count_batch_workspace_size(b.num_graphs, rows), dtype=torch.uint8,
+    ws = torch.empty(tcm.tc_count_batch_workspace_size(b.num_graphs, rows,
+                                                              int(b.colidx_cat.shape[0])), dtype=torch.uint8,
                      device="cuda")
     counts = torch.zeros(b.num_graphs, dtype=torch.int64, device="cuda")
     s = torch.cuda.Stream()

@@ -103,33 +103,36 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
                         uint64_t m, hipStream_t stream, uint64_t* tri_out);
 
 /*
- * tc_count_batch — triangle counts of many independent graphs in one persistent launch
- * (each graph's component roots, BFS, cover-edge selection and intersections run fused,
- * larger graphs first).
+ * tc_count_batch — triangle counts of many independent graphs in one persistent launch:
+ * one workgroup per graph at a time, larger graphs first, each running component roots,
+ * BFS, level split, cover-edge selection and intersections without waiting for others.
  * Graph g owns rowptr_cat[row_off[g] .. row_off[g+1]) (its n_g + 1 local offsets,
  * starting at 0, so n_g = row_off[g+1] - row_off[g] - 1) and
  * colidx_cat[col_off[g] .. col_off[g+1]) (m_g = col_off[g+1] - col_off[g] entries,
  * equal to the graph's own rowptr[n_g], holding LOCAL IDs < n_g).
  * row_off / col_off are DEVICE int64[num_graphs + 1], non-decreasing, starting at 0,
  * with row_off[g+1] - row_off[g] >= 1 for every g.
- * total_rows = row_off[num_graphs] (passed by value so the host never reads device
- * memory).  counts is a DEVICE uint64[num_graphs] receiving T_g.
- * `workspace` is a DEVICE buffer of at least
- * tc_count_batch_workspace_size(num_graphs, total_rows) bytes owned by the caller, or
- * NULL to let the library allocate (and free) it stream-ordered on `stream`.
+ * total_rows = row_off[num_graphs] and total_cols = col_off[num_graphs] (passed by value
+ * so the host never reads device memory).  counts is a DEVICE uint64[num_graphs]
+ * receiving T_g.  `workspace` is a DEVICE buffer of at least
+ * tc_count_batch_workspace_size(num_graphs, total_rows, total_cols) bytes owned by the
+ * caller, or NULL to let the library allocate (and free) it stream-ordered on `stream`.
  * With a caller workspace the call allocates nothing, issues no memset, never
  * synchronises and reads no device data on the host, so it can be captured into a HIP
  * graph and replayed; a workspace must not be shared by calls that overlap in time.
  * Per graph: n_g < 2^30 and m_g < 2^32 (precondition).  Returns TC_ERR_INVALID_ARG
- * (null pointers, workspace too small), TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
+ * (null pointers, workspace too small), TC_ERR_TOO_LARGE (totals >= 2^32 - 16),
+ * TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
 int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
                    const int64_t* row_off, const int64_t* col_off, uint32_t num_graphs,
-                   uint64_t total_rows, void* workspace, size_t workspace_bytes,
-                   hipStream_t stream, uint64_t* counts);
+                   uint64_t total_rows, uint64_t total_cols, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream, uint64_t* counts);
 
-/* Bytes of device workspace tc_count_batch needs (13 per row plus a small header). */
-size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows);
+/* Bytes of device workspace tc_count_batch needs: 21 per row, 8 per stored entry, and a
+   small header. */
+size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows,
+                                     uint64_t total_cols);
 
 /*
  * ---- continuous-batching server ----------------------------------------------------

@@ -431,22 +431,26 @@ int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, 
   return h ? TC_ERR_INVALID_GRAPH : TC_OK;
 }
 
-size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows) {
-  return batch_workspace_bytes(num_graphs, total_rows);
+size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows,
+                                     uint64_t total_cols) {
+  return batch_workspace_bytes(num_graphs, total_rows, total_cols);
 }
 
 int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
                    const int64_t* row_off, const int64_t* col_off, uint32_t num_graphs,
-                   uint64_t total_rows, void* workspace, size_t workspace_bytes,
-                   hipStream_t stream, uint64_t* counts) {
+                   uint64_t total_rows, uint64_t total_cols, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream, uint64_t* counts) {
   if (num_graphs == 0) return TC_OK;
-  if (!rowptr_cat || !row_off || !col_off || !counts || total_rows < num_graphs)
+  if (!rowptr_cat || !row_off || !col_off || !counts || total_rows < num_graphs ||
+      (total_cols > 0 && !colidx_cat))
     return TC_ERR_INVALID_ARG;
-  const size_t need = batch_workspace_bytes(num_graphs, total_rows);
+  if (total_cols >= 0xFFFFFFF0ull || total_rows >= 0xFFFFFFF0ull) return TC_ERR_TOO_LARGE;
+  const IsectParams prm = g_params;
+  const size_t need = batch_workspace_bytes(num_graphs, total_rows, total_cols);
   if (workspace) {
     if (workspace_bytes < need) return TC_ERR_INVALID_ARG;
-    launch_batch(rowptr_cat, colidx_cat, row_off, col_off, num_graphs, total_rows, workspace,
-                 (u64*)counts, stream);
+    launch_batch(rowptr_cat, colidx_cat, row_off, col_off, num_graphs, total_rows, total_cols,
+                 workspace, prm, (u64*)counts, stream);
     TC_LAUNCHED();
     return TC_OK;
   }
@@ -454,8 +458,8 @@ int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
   DevAlloc ws;
   int rc = alloc_async(ws, need, stream);
   if (rc) return rc;
-  launch_batch(rowptr_cat, colidx_cat, row_off, col_off, num_graphs, total_rows, ws.p,
-               (u64*)counts, stream);
+  launch_batch(rowptr_cat, colidx_cat, row_off, col_off, num_graphs, total_rows, total_cols,
+               ws.p, prm, (u64*)counts, stream);
   TC_LAUNCHED();
   return TC_OK;
 }

@@ -1,36 +1,35 @@
 // Batched counting: many independent graphs in one persistent launch.
 //
 // A planner orders the graphs by stored entries, largest power-of-two class first.  Then
-// one persistent grid of workgroups pops graphs from that order; the workgroup that
-// takes a graph runs the whole method on it without leaving the kernel:
+// one persistent grid of 1024-thread workgroups (one per compute unit) pops graphs from
+// that order; the workgroup that takes a graph runs the whole method on it without
+// leaving the kernel and without waiting for any other workgroup:
 //
 //   1. component roots: union-find with smallest-ID roots (the root each restart of
 //      the paper's CETC-Seq BFS loop starts from);
 //   2. level BFS from all roots, one frontier level per workgroup barrier;
 //   3. per-vertex info byte (level parity, degree class);
-//   4. cover edges and intersections fused: every vertex x selects its horizontal
-//      neighbours y of smaller (degree class, ID) key on the fly, stages N(x) in an LDS
-//      hash set (per wavefront when d(x) <= 512, per workgroup in 4096-entry chunks
-//      otherwise) and streams the partners' lists through it with the apex rule of
-//      CETC-Seq (Section 4.2);
-//   5. counts[g] = c1 + t2.
+//   4. level split of every row and the partner lists H+(x) (Theorem Gen-CES), with the
+//      same row routines as the single-graph path (rows longer than kSplitWave by the
+//      whole workgroup);
+//   5. intersections with the apex rule of CETC-Seq (Section 4.2), with the same
+//      per-vertex routines as the single-graph kernels: lane merges for d(x) <= lane_max,
+//      one wavefront per staged vertex for d(x) <= wave_max (the 128 KB table split into
+//      16 wavefront tables), and the pruned workgroup passes for longer lists;
+//   6. counts[g] = c1 + t2.
 //
-// Per-vertex scratch (parent, level, queue, info) lives in the caller's workspace at the
-// graph's row offset, so graphs never share memory and the call allocates nothing.
-#include "tc_device.h"
-#include "tc_launch.h"
+// Per-vertex scratch (parent, level, queue, info, partner counts, split points) lives in
+// the workspace at the graph's row offset, per-entry scratch (level-split rows, partner
+// lists) at its column offset, so graphs never share memory and the call allocates
+// nothing.
+#include "tc_isect.h"
 
 namespace tc {
 
-constexpr int kBT = 256;                 // threads per workgroup
-constexpr int kBW = kBT / kWave;         // wavefronts per workgroup
-constexpr u32 kBSmallMax = 512;          // d(x) staged per wavefront
-constexpr int kBWSlots = 1024;           // hash slots per wavefront
-constexpr int kBBSlots = 8192;           // hash slots per workgroup
-constexpr u32 kBChunk = 4096;            // entries of N(x) per workgroup table
-constexpr u32 kBuckets = 40;             // planner cost classes
-constexpr u32 kLaneDeg = 32;             // lists up to this length are walked per lane
-constexpr int kBUnroll = 4;
+constexpr int kBT = kBigThreads;   // threads per workgroup
+constexpr int kBW = kBT / kWave;   // wavefronts per workgroup
+constexpr u32 kBuckets = 40;       // planner cost classes
+constexpr u32 kLaneDeg = 32;       // lists up to this length are walked per lane
 
 struct BatchCtl {
   u32 next;
@@ -54,6 +53,8 @@ __global__ void __launch_bounds__(256) k_batch_prepare(const int64_t* __restrict
   if (threadIdx.x == 0) {
     ctl->next = 0;
     ctl->status = 0;
+    ctl->pad[0] = 0;
+    ctl->pad[1] = 0;
   }
   __syncthreads();
   for (u32 g = threadIdx.x; g < G; g += blockDim.x)
@@ -115,18 +116,36 @@ __device__ __forceinline__ void block_for_each_entry(const u32* __restrict__ rp,
   }
 }
 
-__global__ void __launch_bounds__(kBT) k_batch_main(
-    const u32* __restrict__ rowptr_cat, const u32* __restrict__ colidx_cat,
-    const int64_t* __restrict__ row_off, const int64_t* __restrict__ col_off, u32 G,
-    const u32* __restrict__ order, BatchCtl* __restrict__ ctl, u32* __restrict__ parent_all,
-    u32* __restrict__ level_all, u32* __restrict__ queue_all, uint8_t* __restrict__ vinfo_all,
-    u64* __restrict__ counts) {
-  __shared__ __align__(16) u32 s_tab[kBBSlots];  // 4 wavefront tables, or one workgroup table
-  __shared__ u32 s_plist[kBW][kBSmallMax];
-  __shared__ u32 s_incl[kBT], s_start[kBT], s_y[kBT];
+struct BatchArrays {
+  const u32* rowptr_cat;
+  const u32* colidx_cat;
+  u32 m_total;        // entries of colidx_cat
+  const u32* tail4;   // padded last quad of colidx_cat
+  const int64_t* row_off;
+  const int64_t* col_off;
+  u32* parent_all;
+  u32* level_all;
+  u32* queue_all;
+  uint8_t* vinfo_all;
+  u32* hcnt_all;
+  u32* split_all;
+  u32* colidx2_all;   // m_total + 4 entries (the padding keeps quad loads in bounds)
+  u32* hadj_all;
+};
+
+template <bool VEC>
+__global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
+                                                   const u32* __restrict__ order,
+                                                   BatchCtl* __restrict__ ctl, IsectParams prm,
+                                                   u64* __restrict__ counts) {
+  __shared__ __align__(16) u32 s_table[kBigSlots];  // one workgroup table or 16 wave tables
+  __shared__ u32 s_qincl[kBigSeg];                    // also the wavefronts' partner ends
+  __shared__ uint4 s_pinfo[kBigSeg];                  // also the wavefronts' partner info
+  __shared__ u32 s_mark[kBigSeg];                     // wavefront marks / block-class list
   __shared__ u32 s_tmp[kBW];
   __shared__ u64 s_red[3 * kBW];
-  __shared__ u32 s_g, s_qtail, s_xnext, s_cnt;
+  __shared__ u32 s_g, s_qtail, s_cnt, s_next;
+  const BlockShared sh{s_table, s_qincl, s_pinfo, s_tmp};
   const u32 lane = lane_id(), wid = threadIdx.x / kWave;
 
   while (true) {
@@ -134,27 +153,29 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
       const u32 idx = atomicAdd(&ctl->next, 1u);
       s_g = idx < G ? order[idx] : kInf;
       s_qtail = 0;
-      s_xnext = 0;
       s_cnt = 0;
+      s_next = 0;
     }
     __syncthreads();
     const u32 g = s_g;
     if (g == kInf) break;
-    const int64_t rb = row_off[g];
-    const u32 n = (u32)(row_off[g + 1] - rb - 1);
-    const int64_t cb = col_off[g];
-    const u32 m = (u32)(col_off[g + 1] - cb);
+    const int64_t rb = A.row_off[g];
+    const u32 n = (u32)(A.row_off[g + 1] - rb - 1);
+    const u32 cb = (u32)A.col_off[g];
+    const u32 m = (u32)(A.col_off[g + 1] - A.col_off[g]);
     if (n == 0 || m == 0) {
       if (threadIdx.x == 0) counts[g] = 0;
       __syncthreads();
       continue;
     }
-    const u32* rp = rowptr_cat + rb;
-    const u32* ci = colidx_cat + cb;
-    u32* parent = parent_all + rb;
-    u32* level = level_all + rb;
-    u32* queue = queue_all + rb;
-    uint8_t* vinfo = vinfo_all + rb;
+    const u32* rp = A.rowptr_cat + rb;
+    const u32* ci = A.colidx_cat + cb;  // local view for the traversals
+    u32* parent = A.parent_all + rb;
+    u32* level = A.level_all + rb;
+    u32* queue = A.queue_all + rb;
+    uint8_t* vinfo = A.vinfo_all + rb;
+    u32* hcnt = A.hcnt_all + rb;
+    u32* split = A.split_all + rb;
 
     // ---- 1. component roots ----
     for (u32 v = threadIdx.x; v < n; v += kBT) {
@@ -208,230 +229,219 @@ __global__ void __launch_bounds__(kBT) k_batch_main(
       vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | degree_class(rp[v + 1] - rp[v]));
     __syncthreads();
 
-    // ---- 4a. staged vertices of short lists: one wavefront each ----
-    Counts c{0, 0, 0, 0, 0};
-    {
-      u32* table = s_tab + wid * kBWSlots;
-      u32* plist = s_plist[wid];
-      u32* incl_w = s_incl + wid * kWave;
-      u32* start_w = s_start + wid * kWave;
-      u32* y_w = s_y + wid * kWave;
-      while (true) {
-        u32 x = 0;
-        if (lane == 0) x = atomicAdd(&s_xnext, 1u);
-        x = __shfl(x, 0, kWave);
-        if (x >= n) break;
-        const u32 bx = rp[x], dx = rp[x + 1] - bx;
-        if (dx < 2 || dx > kBSmallMax) continue;
-        const u32 vx = vinfo[x], px = vx & 0x80u, cx = vx & 127u;
-        const u32 mask = bucket_mask(dx, kBWSlots);
-        for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
-        wave_lds_sync();
-        u32 np = 0;
-        for (u32 i0 = 0; i0 < dx; i0 += kWave) {
-          const u32 i = i0 + lane;
-          const bool act = i < dx;
-          u32 w = 0, vw = 0;
-          if (act) {
-            w = ci[bx + i];
-            vw = vinfo[w];
-          }
-          const bool same = (vw & 0x80u) == px;
-          if (act) hash_insert(table, mask, w, same ? 1u : 0u);
-          const bool isp = act && same && key_less(vw & 127u, w, cx, x);
-          const u64 pm = __ballot(isp);
-          if (isp) plist[np + mask_rank(pm)] = w;
-          np += (u32)__popcll(pm);
-        }
-        wave_lds_sync();
-        for (u32 pb = 0; pb < np; pb += kWave) {
-          const u32 p = pb + lane;
-          u32 y = 0, sy = 0, dy = 0;
-          if (p < np) {
-            y = plist[p];
-            sy = rp[y];
-            dy = rp[y + 1] - sy;
-          }
-          const u32 incl = wave_incl_scan(dy);
-          const u32 total = __shfl(incl, kWave - 1, kWave);
-          incl_w[lane] = incl;
-          start_w[lane] = sy - (incl - dy);
-          y_w[lane] = y;
-          wave_lds_sync();
-          for (u32 k0 = 0; k0 < total; k0 += kWave * kBUnroll) {
-            u32 ws[kBUnroll], ls[kBUnroll];
-#pragma unroll
-            for (int u = 0; u < kBUnroll; ++u) {
-              const u32 kk = k0 + u * kWave + lane;
-              ls[u] = kInf;
-              if (kk < total) {
-                u32 lo = 0, hi = kWave - 1;
-                while (lo < hi) {
-                  const u32 mid = (lo + hi) >> 1;
-                  if (incl_w[mid] > kk) hi = mid;
-                  else lo = mid + 1;
-                }
-                ls[u] = lo;
-                ws[u] = ci[start_w[lo] + kk];
-              }
-            }
-#pragma unroll
-            for (int u = 0; u < kBUnroll; ++u) {
-              if (ls[u] != kInf) {
-                const u32 r = hash_probe(table, mask, ws[u]);
-                if (r) {
-                  const u32 y2 = y_w[ls[u]];
-                  count_hit<false>(r, ws[u], x, y2, max(x, y2), c, nullptr);
-                }
-              }
-            }
-          }
-          wave_lds_sync();
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- 4b. staged vertices of long lists: the whole workgroup, chunk by chunk ----
+    // ---- 4. level split and partner lists (split[] local, arrays at cb) ----
     {
       const u32 nr = (n + kWave - 1) / kWave * kWave;
       for (u32 v = threadIdx.x; v < nr; v += kBT) {
-        const bool isl = v < n && rp[v + 1] - rp[v] > kBSmallMax;
-        const u32 pos = wave_append(&s_cnt, isl);
-        if (isl) queue[pos] = v;  // the BFS queue is free again
-      }
-      __syncthreads();
-      const u32 nl = s_cnt;
-      for (u32 li = 0; li < nl; ++li) {
-        const u32 x = queue[li];
-        const u32 bx = rp[x], dx = rp[x + 1] - bx;
-        const u32 vx = vinfo[x], px = vx & 0x80u, cx = vx & 127u;
-        const u32 nch = (dx + kBChunk - 1) / kBChunk;
-        for (u32 ch = 0; ch < nch; ++ch) {
-          const u32 c0 = ch * kBChunk, clen = min(kBChunk, dx - c0);
-          const u32 mask = bucket_mask(clen, kBBSlots);
-          for (u32 i = threadIdx.x; i < (mask + 1) * 4; i += kBT) s_tab[i] = kInf;
-          __syncthreads();
-          for (u32 i = threadIdx.x; i < clen; i += kBT) {
-            const u32 w = ci[bx + c0 + i];
-            const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
-            hash_insert(s_tab, mask, w, same);
-          }
-          const u32 wlo = ci[bx + c0], whi = ci[bx + c0 + clen - 1];
-          __syncthreads();
-          for (u32 j0 = 0; j0 < dx; j0 += kBT) {
-            const u32 j = j0 + threadIdx.x;
-            u32 y = 0, sy = 0, dy = 0;
-            if (j < dx) {
-              y = ci[bx + j];
-              const u32 vy = vinfo[y];
-              if ((vy & 0x80u) == px && key_less(vy & 127u, y, cx, x)) {
-                sy = rp[y];
-                u32 ey = rp[y + 1];
-                if (nch > 1) {
-                  sy = lower_bound_g(ci, sy, ey, wlo);
-                  ey = lower_bound_g(ci, sy, ey, whi + 1u);
-                }
-                dy = ey - sy;
-              }
-            }
-            u32 total;
-            const u32 incl = block_incl_scan(dy, s_tmp, &total);
-            s_incl[threadIdx.x] = incl;
-            s_start[threadIdx.x] = sy - (incl - dy);
-            s_y[threadIdx.x] = y;
-            __syncthreads();
-            for (u32 k0 = 0; k0 < total; k0 += kBT * kBUnroll) {
-              u32 ws[kBUnroll], ls[kBUnroll];
-#pragma unroll
-              for (int u = 0; u < kBUnroll; ++u) {
-                const u32 kk = k0 + u * kBT + threadIdx.x;
-                ls[u] = kInf;
-                if (kk < total) {
-                  u32 lo = 0, hi = kBT - 1;
-                  while (lo < hi) {
-                    const u32 mid = (lo + hi) >> 1;
-                    if (s_incl[mid] > kk) hi = mid;
-                    else lo = mid + 1;
-                  }
-                  ls[u] = lo;
-                  ws[u] = ci[s_start[lo] + kk];
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < kBUnroll; ++u) {
-                if (ls[u] != kInf) {
-                  const u32 r = hash_probe(s_tab, mask, ws[u]);
-                  if (r) {
-                    const u32 y2 = s_y[ls[u]];
-                    count_hit<false>(r, ws[u], x, y2, max(x, y2), c, nullptr);
-                  }
-                }
-              }
-            }
-            __syncthreads();
+        u32 lo = 0, d = 0, vx = 0;
+        if (v < n) {
+          lo = rp[v];
+          d = rp[v + 1] - lo;
+          vx = vinfo[v];
+        }
+        if (v < n && d <= kSplitLane) {
+          u32 ns, nh;
+          split_short_row(A.colidx_cat, vinfo, v, vx, cb + lo, d, A.colidx2_all, A.hadj_all, &ns,
+                          &nh);
+          split[v] = lo + ns;
+          hcnt[v] = nh;
+        }
+        const bool lng = d > kSplitWave;
+        const u32 pos = wave_append(&s_cnt, lng);
+        if (lng) queue[pos] = v;  // the BFS queue is free again
+        u64 mm = __ballot(d > kSplitLane && d <= kSplitWave);
+        while (mm) {
+          const int b = __ffsll((unsigned long long)mm) - 1;
+          mm &= mm - 1;
+          const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
+          const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
+          u32 ns = 0, no = 0, nh = 0;
+          for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
+            split_steps<true>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, 0, 0,
+                              A.colidx2_all, A.hadj_all, ns, no, nh);
+          u32 cs = 0, co = 0, ch = 0;
+          for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
+            split_steps<false>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, ns, 0,
+                               A.colidx2_all, A.hadj_all, cs, co, ch);
+          if ((int)lane == b) {
+            split[bv] = blo + ns;
+            hcnt[bv] = nh;
           }
         }
       }
+      __syncthreads();
+      // long rows: each wavefront takes a contiguous segment of the row
+      const u32 nl = s_cnt;
+      for (u32 li = 0; li < nl; ++li) {
+        const u32 v = queue[li];
+        const u32 lo = rp[v], d = rp[v + 1] - lo, vx = vinfo[v];
+        const u32 step = kWave * kSplitUnroll;
+        const u32 segw = (d + kBW * step - 1) / (kBW * step) * step;
+        const u32 j0 = min(wid * segw, d), j1 = min(j0 + segw, d);
+        u32 ns = 0, no = 0, nh = 0;
+        for (u32 j = j0; j < j1; j += step)
+          split_steps<true>(A.colidx_cat, vinfo, v, vx, cb + lo, j, j1, 0, 0, 0, A.colidx2_all,
+                            A.hadj_all, ns, no, nh);
+        if (lane == 0) {
+          s_mark[wid] = ns;
+          s_mark[kBW + wid] = nh;
+        }
+        __syncthreads();
+        u32 bs = 0, bh = 0, ts = 0, th = 0;
+        for (u32 w = 0; w < (u32)kBW; ++w) {
+          if (w < wid) {
+            bs += s_mark[w];
+            bh += s_mark[kBW + w];
+          }
+          ts += s_mark[w];
+          th += s_mark[kBW + w];
+        }
+        u32 cs = 0, co = 0, ch = 0;
+        for (u32 j = j0; j < j1; j += step)
+          split_steps<false>(A.colidx_cat, vinfo, v, vx, cb + lo, j, j1, bs, ts + (j0 - bs), bh,
+                             A.colidx2_all, A.hadj_all, cs, co, ch);
+        if (threadIdx.x == 0) {
+          split[v] = lo + ts;
+          hcnt[v] = th;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+
+    // ---- 5a. lane class ----
+    Counts c{0, 0, 0, 0, 0};
+    for (u32 v = threadIdx.x; v < n; v += kBT)
+      if (hcnt[v] > 0 && rp[v + 1] - rp[v] <= prm.lane_max)
+        lane_vertex<false>(rp, cb, A.colidx_cat, vinfo, hcnt, A.hadj_all, v, c, nullptr);
+
+    // ---- 5b. wavefront class: 16 wavefront tables in the workgroup table ----
+    {
+      u32 idx = 0, idx_end = 0;
+      while (true) {
+        if (idx == idx_end) {
+          u32 c0 = 0;
+          if (lane == 0) c0 = atomicAdd(&s_next, kWaveClaim);
+          idx = __shfl(c0, 0, kWave);
+          idx_end = min(idx + kWaveClaim, n);
+        }
+        if (idx >= n) break;
+        const u32 x = idx++;
+        const u32 dx = rp[x + 1] - rp[x];
+        if (hcnt[x] == 0 || dx <= prm.lane_max || dx > prm.wave_max) continue;  // wave-uniform
+        Tally tl{0, 0, 0, 0};
+        wave_vertex<false, VEC>(rp, cb, A.colidx_cat, A.m_total, A.tail4, vinfo, hcnt,
+                                A.hadj_all, x, s_table + wid * kWaveSlots, s_pinfo + wid * kWave,
+                                s_qincl + wid * kWave, s_mark + wid * kWave, tl, c, nullptr);
+        tl.fold(c);
+      }
+    }
+    __syncthreads();
+
+    // ---- 5c. workgroup class, pruned, over batches of up to 1024 staged vertices ----
+    {
+      Tally tl{0, 0, 0, 0};
+      for (u32 base = 0; base < n; base += kBT) {
+        const u32 v = base + threadIdx.x;
+        const bool isx = v < n && hcnt[v] > 0 && rp[v + 1] - rp[v] > prm.wave_max;
+        u32 tot;
+        const u32 incl = block_incl_scan(isx ? 1u : 0u, s_tmp, &tot);
+        if (isx) s_mark[incl - 1] = v;
+        __syncthreads();
+        for (u32 i = 0; i < tot; ++i) {
+          const u32 x = s_mark[i];
+          const u32 nseg = (hcnt[x] + prm.seg - 1) / prm.seg;
+          for (u32 sg = 0; sg < nseg; ++sg)
+            // colidx2 carries 4 padding entries, so its quad loads never need a tail copy
+            block_item<false, VEC, true>(rp, cb, A.colidx_cat, A.m_total, A.tail4, A.colidx2_all,
+                                         A.m_total + 4, split, A.tail4, vinfo, hcnt, A.hadj_all, x,
+                                         sg, prm, sh, tl, c, nullptr);
+        }
+        __syncthreads();  // s_mark is rewritten by the next batch
+      }
+      tl.fold(c);
     }
 
-    // ---- 5. per-graph totals ----
-    c.c1 = wave_sum_u64(c.c1);
-    c.c2 = wave_sum_u64(c.c2);
-    c.t2 = wave_sum_u64(c.t2);
+    // ---- 6. per-graph total ----
+    const u64 c1 = wave_sum_u64(c.c1), t2 = wave_sum_u64(c.t2);
     if (lane == 0) {
-      s_red[3 * wid] = c.c1;
-      s_red[3 * wid + 1] = c.c2;
-      s_red[3 * wid + 2] = c.t2;
+      s_red[2 * wid] = c1;
+      s_red[2 * wid + 1] = t2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      u64 c1 = 0, c2 = 0, t2 = 0;
+      u64 a = 0, b = 0;
       for (int w = 0; w < kBW; ++w) {
-        c1 += s_red[3 * w];
-        c2 += s_red[3 * w + 1];
-        t2 += s_red[3 * w + 2];
+        a += s_red[2 * w];
+        b += s_red[2 * w + 1];
       }
-      counts[g] = c1 + t2;
-      if (c2 != 3 * t2) atomicOr(&ctl->status, 1u);
+      counts[g] = a + b;
     }
     __syncthreads();
   }
 }
 
-size_t batch_workspace_bytes(u32 G, u64 total_rows) {
-  size_t b = batch_ctl_bytes();
-  b += ((size_t)G * 4 + 255) / 256 * 256;
-  b += (total_rows * 4 + 255) / 256 * 256 * 3;
-  b += (total_rows + 255) / 256 * 256;
-  return b + 256;
+// ---- workspace ------------------------------------------------------------------------
+struct BatchLayout {
+  size_t ctl, order, parent, level, queue, vinfo, hcnt, split, colidx2, hadj, tail, bytes;
+};
+
+static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+static BatchLayout batch_layout(u32 G, u64 rows, u64 cols) {
+  BatchLayout L;
+  size_t o = 0;
+  L.ctl = o; o += up256(batch_ctl_bytes());
+  L.order = o; o += up256((size_t)G * 4);
+  L.parent = o; o += up256(rows * 4);
+  L.level = o; o += up256(rows * 4);
+  L.queue = o; o += up256(rows * 4);
+  L.vinfo = o; o += up256(rows);
+  L.hcnt = o; o += up256(rows * 4);
+  L.split = o; o += up256(rows * 4);
+  L.colidx2 = o; o += up256((cols + 4) * 4);
+  L.hadj = o; o += up256(cols * 4);
+  L.tail = o; o += 256;
+  L.bytes = o + 256;  // alignment slack of the caller's pointer
+  return L;
 }
 
-int batch_grid() {
-  // Two workgroups of ~46 KB LDS per compute unit.
-  return num_cus() * 2;
+size_t batch_workspace_bytes(u32 G, u64 total_rows, u64 total_cols) {
+  return batch_layout(G, total_rows, total_cols).bytes;
 }
 
 void launch_batch(const u32* rowptr_cat, const u32* colidx_cat, const int64_t* row_off,
-                  const int64_t* col_off, u32 G, u64 total_rows, void* ws, u64* counts,
-                  hipStream_t s) {
+                  const int64_t* col_off, u32 G, u64 total_rows, u64 total_cols, void* ws,
+                  IsectParams p, u64* counts, hipStream_t s) {
+  const BatchLayout L = batch_layout(G, total_rows, total_cols);
   char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
-  BatchCtl* ctl = (BatchCtl*)base;
-  base += batch_ctl_bytes();
-  u32* order = (u32*)base;
-  base += ((size_t)G * 4 + 255) / 256 * 256;
-  const size_t vb = (total_rows * 4 + 255) / 256 * 256;
-  u32* parent = (u32*)base;
-  base += vb;
-  u32* level = (u32*)base;
-  base += vb;
-  u32* queue = (u32*)base;
-  base += vb;
-  uint8_t* vinfo = (uint8_t*)base;
+  BatchCtl* ctl = (BatchCtl*)(base + L.ctl);
+  u32* order = (u32*)(base + L.order);
+  u32* tail4 = (u32*)(base + L.tail);
+  BatchArrays A;
+  A.rowptr_cat = rowptr_cat;
+  A.colidx_cat = colidx_cat;
+  A.m_total = (u32)total_cols;
+  A.tail4 = tail4;
+  A.row_off = row_off;
+  A.col_off = col_off;
+  A.parent_all = (u32*)(base + L.parent);
+  A.level_all = (u32*)(base + L.level);
+  A.queue_all = (u32*)(base + L.queue);
+  A.vinfo_all = (uint8_t*)(base + L.vinfo);
+  A.hcnt_all = (u32*)(base + L.hcnt);
+  A.split_all = (u32*)(base + L.split);
+  A.colidx2_all = (u32*)(base + L.colidx2);
+  A.hadj_all = (u32*)(base + L.hadj);
   hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(256), 0, s, col_off, G, ctl, order);
-  const u32 grid = (u32)min((int)G, batch_grid());
-  hipLaunchKernelGGL(k_batch_main, dim3(grid), dim3(kBT), 0, s, rowptr_cat, colidx_cat, row_off,
-                     col_off, G, order, ctl, parent, level, queue, vinfo, counts);
+  if (total_cols > 0) launch_tail4(colidx_cat, (u32)total_cols, tail4, s);
+  const u32 grid = (u32)min((int)G, num_cus());
+  if ((((uintptr_t)colidx_cat) & 15u) == 0)
+    hipLaunchKernelGGL(k_batch_main<true>, dim3(grid), dim3(kBT), 0, s, A, G, order, ctl, p,
+                       counts);
+  else
+    hipLaunchKernelGGL(k_batch_main<false>, dim3(grid), dim3(kBT), 0, s, A, G, order, ctl, p,
+                       counts);
 }
 
 }  // namespace tc

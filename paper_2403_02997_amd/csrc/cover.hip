@@ -15,54 +15,11 @@
 // Rows of at most 32 entries are handled by one lane, longer ones by a whole wavefront,
 // 64 entries per step, with ballot ranks keeping both parts in order.  The level split
 // lets the counting skip the same-level neighbours that cannot be a counted apex.
-#include "tc_device.h"
-#include "tc_launch.h"
+#include "tc_isect.h"
 
 namespace tc {
 
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
-
-constexpr u32 kSplitLane = 32;     // rows up to this length are split by one lane
-constexpr u32 kSplitWave = 4096;   // rows up to this length by one wavefront; longer rows
-                                   // by a whole workgroup (k_split_long)
-constexpr u32 kSplitUnroll = 4;    // 64-entry steps per wavefront iteration
-
-// Partition step over entries j0 .. j0 + 64 kSplitUnroll of the row at `lo` (d entries):
-// counts (COUNT) or writes (!COUNT) the same-level entries, the other-level entries and
-// the partners, advancing the running counts cs / co / ch.
-template <bool COUNT>
-__device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
-                                            const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
-                                            u32 lo, u32 j0, u32 jend, u32 same_base,
-                                            u32 other_base, u32 part_base,
-                                            u32* __restrict__ colidx2, u32* __restrict__ hadj,
-                                            u32& cs, u32& co, u32& ch) {
-  const u32 lane = lane_id();
-  u32 w[kSplitUnroll], vw[kSplitUnroll];
-#pragma unroll
-  for (u32 u = 0; u < kSplitUnroll; ++u) {
-    const u32 j = j0 + u * kWave + lane;
-    w[u] = j < jend ? colidx[lo + j] : v;
-  }
-#pragma unroll
-  for (u32 u = 0; u < kSplitUnroll; ++u) vw[u] = vinfo[w[u]];
-#pragma unroll
-  for (u32 u = 0; u < kSplitUnroll; ++u) {
-    const u32 j = j0 + u * kWave + lane;
-    const bool in = j < jend;
-    const bool same = in && ((vw[u] ^ vx) & 0x80u) == 0;
-    const bool part = same && key_less(vw[u] & 127u, w[u], vx & 127u, v);
-    const u64 ms = __ballot(same), mo = __ballot(in && !same), mh = __ballot(part);
-    if (!COUNT) {
-      if (same) colidx2[lo + same_base + cs + mask_rank(ms)] = w[u];
-      else if (in) colidx2[lo + other_base + co + mask_rank(mo)] = w[u];
-      if (part) hadj[lo + part_base + ch + mask_rank(mh)] = w[u];
-    }
-    cs += (u32)__popcll(ms);
-    co += (u32)__popcll(mo);
-    ch += (u32)__popcll(mh);
-  }
-}
 
 __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowptr,
                                                    const u32* __restrict__ colidx,
@@ -84,38 +41,10 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
     const bool mid = d > kSplitLane && d <= kSplitWave;
     const bool lng = d > kSplitWave;
     if (v < n && d <= kSplitLane) {
-      // four entries per step keep four independent gathers in flight
-      u32 ns = 0;
-      for (u32 j = 0; j < d; j += 4) {
-        u32 w[4], vw[4];
-#pragma unroll
-        for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
-#pragma unroll
-        for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
-#pragma unroll
-        for (u32 i = 0; i < 4; ++i) ns += (j + i < d) && ((vw[i] ^ vx) & 0x80u) == 0;
-      }
-      u32 is = lo, io = lo + ns, ih = lo;
-      for (u32 j = 0; j < d; j += 4) {
-        u32 w[4], vw[4];
-#pragma unroll
-        for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
-#pragma unroll
-        for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
-#pragma unroll
-        for (u32 i = 0; i < 4; ++i) {
-          if (j + i < d) {
-            if (((vw[i] ^ vx) & 0x80u) == 0) {
-              colidx2[is++] = w[i];
-              if (key_less(vw[i] & 127u, w[i], vx & 127u, v)) hadj[ih++] = w[i];
-            } else {
-              colidx2[io++] = w[i];
-            }
-          }
-        }
-      }
+      u32 ns, nh;
+      split_short_row(colidx, vinfo, v, vx, lo, d, colidx2, hadj, &ns, &nh);
       split[v] = lo + ns;
-      hcnt[v] = ih - lo;
+      hcnt[v] = nh;
     }
     // long rows go to the workgroup kernel
     const u32 pos = wave_append(num_long, lng);

@@ -54,7 +54,7 @@ inline uint64_t single_footprint(uint32_t n, uint64_t m) {
   return csr_bytes(n, m) + 48ull * n + 3ull * m + (1ull << 20);
 }
 inline uint64_t batched_footprint(uint32_t n, uint64_t m) {
-  return csr_bytes(n, m) + 13ull * ((uint64_t)n + 1) + 64;
+  return csr_bytes(n, m) + 21ull * ((uint64_t)n + 1) + 8ull * m + 64;
 }
 
 }  // namespace
@@ -139,7 +139,7 @@ struct tc_server {
       col_off[i + 1] = col_off[i] + (int64_t)b[i].m;
     }
     const uint64_t rows = (uint64_t)row_off[G], cols = (uint64_t)col_off[G];
-    const size_t ws_bytes = tc_count_batch_workspace_size(G, rows);
+    const size_t ws_bytes = tc_count_batch_workspace_size(G, rows, cols);
     char* dev = nullptr;
     const size_t o_rp = 0;
     const size_t o_ci = (o_rp + 4 * rows + 255) / 256 * 256;
@@ -171,7 +171,7 @@ struct tc_server {
     if (rc == TC_OK)
       rc = tc_count_batch((const uint32_t*)(dev + o_rp), (const uint32_t*)(dev + o_ci),
                           (const int64_t*)(dev + o_ro), (const int64_t*)(dev + o_co), G, rows,
-                          dev + o_ws, ws_bytes, s_batch, (uint64_t*)(dev + o_cnt));
+                          cols, dev + o_ws, ws_bytes, s_batch, (uint64_t*)(dev + o_cnt));
     counts.assign(G, 0);
     if (rc == TC_OK && hipMemcpyAsync(counts.data(), dev + o_cnt, 8 * (size_t)G,
                                       hipMemcpyDeviceToHost, s_batch) != hipSuccess)

@@ -1,0 +1,523 @@
+// Per-vertex and per-item intersection routines shared by the single-graph kernels and
+// the batched per-graph kernel, and the row-split step of cover-edge extraction.
+//
+// Indexing: vertex IDs and rowptr / split values are local to a graph; neighbour
+// arrays (colidx, colidx2, hadj) are indexed absolutely, at cb + a local offset, where
+// cb is the graph's first stored entry (0 for a single graph).  Quads of 16 bytes are
+// aligned to the start of the neighbour array, so per-graph offsets need no alignment.
+#pragma once
+
+#include "tc_device.h"
+#include "tc_launch.h"
+
+namespace tc {
+
+constexpr int kWaveSlots = 2048;   // LDS hash slots per wavefront (d(x) <= 512)
+constexpr int kIsectThreads = 256;
+constexpr int kUnroll = 4;         // independent list loads in flight per lane
+static_assert(kUnroll == 4, "the wavefront routine packs one mark byte per window in a word");
+constexpr u32 kWaveClaim = 16;     // wavefront-class vertices claimed per counter atomic
+constexpr int kBigThreads = 1024;
+constexpr int kBigWaves = kBigThreads / kWave;
+constexpr int kBigSlots = 32768;   // 128 KB of LDS
+constexpr int kBigSeg = 1024;      // partners per work item (one per thread for set-up)
+constexpr int kQuadUnroll = 4;     // windows per wavefront loaded before probing
+static_assert(kBigSlots == kBigWaves * kWaveSlots, "the wavefront tables share the big table");
+
+// ---- lane class: one thread merges N(x) with each partner's list ---------------------
+template <bool PV>
+__device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 cb,
+                                            const u32* __restrict__ colidx,
+                                            const uint8_t* __restrict__ vinfo,
+                                            const u32* __restrict__ hcnt,
+                                            const u32* __restrict__ hadj, u32 x, Counts& c,
+                                            u64* __restrict__ tri) {
+  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1], np = hcnt[x];
+  const u32 px = vinfo[x] & 0x80u;
+  for (u32 q = 0; q < np; ++q) {
+    const u32 y = hadj[bx + q];
+    u32 i = bx, j = cb + rowptr[y];
+    const u32 je = cb + rowptr[y + 1];
+    c.probes += je - j;
+    c.staged += ex - i;
+    const u32 vmax = max(x, y);
+    if (i < ex && j < je) {
+      u32 a = colidx[i], b = colidx[j];
+      while (true) {
+        if (a < b) {
+          if (++i == ex) break;
+          a = colidx[i];
+        } else if (a > b) {
+          if (++j == je) break;
+          b = colidx[j];
+        } else {
+          const u32 r = 1u + (((vinfo[a] & 0x80u) == px) ? 1u : 0u);
+          count_hit<PV>(r, a, x, y, vmax, c, tri);
+          if (++i == ex || ++j == je) break;
+          a = colidx[i];
+          b = colidx[j];
+        }
+      }
+    }
+  }
+}
+
+// ---- wave class: one wavefront per staged vertex x -----------------------------------
+// N(x) goes to the wavefront's LDS hash set (kWaveSlots slots).  The partners' lists are
+// taken 64 at a time, padded out to whole 16-byte quads (VEC) and concatenated; each lane
+// then loads one quad per window, so a lane has 4 * kUnroll list elements in flight.
+// The partner of a quad comes from the partners' quad ends: those inside the current
+// windows mark their positions in LDS, and a ballot plus a population count gives every
+// lane its partner.  pinfo / pend / mark are the wavefront's 64-entry LDS arrays.
+template <bool PV, bool VEC>
+__device__ __forceinline__ void wave_vertex(
+    const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
+    const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
+    const u32* __restrict__ hcnt, const u32* __restrict__ hadj, u32 x, u32* table,
+    uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c, u64* __restrict__ tri) {
+  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
+  const u32 lane = lane_id();
+  const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
+  const u32 bx = cb + rowptr[x], dx = cb + rowptr[x + 1] - bx;
+  const u32 hs = bx, np = hcnt[x];  // H+(x) sits in place of N(x)
+  const u32 px = vinfo[x] & 0x80u;
+  const u32 mask = bucket_mask(dx, kWaveSlots);
+  c.staged += lane == 0 ? dx : 0;
+  for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
+  wave_lds_sync();
+  for (u32 i = lane; i < dx; i += kWave) {
+    const u32 w = colidx[bx + i];
+    const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
+    hash_insert(table, mask, w, same);
+  }
+  wave_lds_sync();
+  for (u32 pb = 0; pb < np; pb += kWave) {
+    const u32 p = pb + lane;
+    u32 y = 0, lo = 0, hi = 0;
+    if (p < np) {
+      y = hadj[hs + p];
+      lo = cb + rowptr[y];
+      hi = cb + rowptr[y + 1];
+    }
+    tl.probes += hi - lo;
+    const u32 qa = VEC ? (lo & ~3u) : lo;
+    const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
+    const u32 incl = wave_incl_scan(nq);
+    const u32 total = __shfl(incl, kWave - 1, kWave);
+    // partners with elements, compacted: their quad ends are strictly increasing
+    const u64 ne = __ballot(nq > 0);
+    const u32 npc = (u32)__popcll(ne);
+    if (nq > 0) {
+      const u32 r = mask_rank(ne);
+      pinfo[r] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
+      pend[r] = incl;
+    }
+    wave_lds_sync();
+    const u32 my_end = lane < npc ? pend[lane] : kInf;  // quad end of partner `lane`
+    for (u32 k0 = 0; k0 < total; k0 += kWave * kUnroll) {
+      // Quad q belongs to partner #{r : end_r <= q}.  Partner ends strictly inside one of
+      // the kUnroll windows of 64 quads from k0 mark their position (byte u of word j for
+      // position 64 u + j); ends at a window start count in that window's base.
+      mark[lane] = 0;
+      wave_lds_sync();
+      const u32 t = my_end - k0;
+      if (my_end > k0 && t < kWave * kUnroll && (t & (kWave - 1)) != 0)
+        reinterpret_cast<uint8_t*>(mark)[(t & (kWave - 1)) * 4 + t / kWave] = 1;
+      wave_lds_sync();
+      const u32 word = mark[lane];
+      u32 e[kUnroll][NE];
+      uint4 inf[kUnroll];
+      u32 addr[kUnroll];
+      bool live[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const u32 w0 = k0 + u * kWave;
+        const u32 q = w0 + lane;
+        const u64 mk = __ballot(((word >> (8 * u)) & 0xFFu) != 0);
+        const u32 base = (u32)__popcll(__ballot(my_end <= w0));
+        const u32 l = min(base + (u32)__popcll(mk & le), npc - 1);
+        live[u] = q < total;
+        inf[u] = pinfo[l];
+        addr[u] = (inf[u].x + q) * NE;
+        if (VEC) {
+          // one unconditional 16-byte load: a quad that would run past the end of colidx
+          // (or a dead lane) reads the padded copy of the last partial quad
+          const u32* src = (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
+          const uint4 v = *reinterpret_cast<const uint4*>(src);
+          e[u][0] = v.x;
+          e[u][NE > 1 ? 1 : 0] = v.y;
+          e[u][NE > 2 ? 2 : 0] = v.z;
+          e[u][NE > 3 ? 3 : 0] = v.w;
+        } else {
+          e[u][0] = colidx[live[u] ? addr[u] : 0u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const u32 y2 = inf[u].w;
+        const u32 vmax = max(x, y2);
+        const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
+        bool ok[NE];
+#pragma unroll
+        for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
+        u32 res[NE];
+        hash_probe_n<NE>(table, mask, e[u], ok, res);
+#pragma unroll
+        for (u32 i = 0; i < NE; ++i) {
+          tl.add(res[i], e[u][i], vmax);
+          if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+// ---- block class: one 1024-thread workgroup per (x, segment of partners) ------------
+// N(x) is staged chunk by chunk (at most prm.chunk <= 16384 entries per chunk, 4096 by
+// default so that the 128 KB LDS hash set stays at most 1/8 full).  For each chunk every
+// partner list is cut at the chunk's largest ID (one binary search from the previous
+// chunk's cut, only when N(x) needs several chunks) and padded out to whole 16-byte quads;
+// the concatenated quad space is split into one contiguous range per wavefront.  A
+// wavefront walks its range in windows of 64 quads, one quad (16-byte load) per lane,
+// and keeps the current partner as it goes: the partner boundaries (quad prefix sums in
+// LDS) that fall inside a window are applied with a few lane-uniform steps, so no
+// per-lane search is needed.  Every partner element is probed exactly once, against the
+// first chunk whose largest ID is not below it.
+// What one pass of the workgroup kernel stages, streams and tallies:
+//   kFull     : N(x) with level flags; each partner's whole list; c1, c2 and t2
+//               (diagnostics and per-vertex counts);
+//   kPrunedOne: N(x) with level flags in one chunk; each partner's same-level
+//               neighbours above max(x, y) and its other-level ones (one contiguous
+//               range of the level-split rows); c1 and t2;
+//   kOther    : the other-level part of N(x); each partner's other-level part; c1;
+//   kSame     : the same-level part of N(x) above x; each partner's same-level part
+//               above max(x, y); t2 (every hit is a same-level apex above both ends).
+// A same-level apex w <= max(x, y) is never counted (the apex rule), so the pruned
+// passes skip those list entries entirely and leave c2 uncounted.
+enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3 };
+
+struct BlockShared {
+  u32* table;
+  u32* qincl;
+  uint4* pinfo;
+  u32* tmp;
+};
+
+// One pass over the partners of a work item.  The staged keys ga[gs .. ge) (ascending)
+// go to LDS either as hash sets of at most prm.chunk keys (BM = false) or, for the
+// level-specific pruned passes, as bitmaps of one 2^kWinBits-ID window each (BM = true,
+// one bit per ID: these passes need membership only).  Partner `tid` < pn streams
+// sa[plo .. phi), cut at each chunk's largest ID or window end.  All threads of the
+// workgroup call it together.
+constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
+
+template <bool PV, bool VEC, int MODE, bool BM>
+__device__ __forceinline__ void block_pass(
+    const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
+    u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
+    u32 phi, IsectParams prm, const BlockShared& sh, Tally& tl, Counts& c, u64* __restrict__ tri) {
+  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
+  const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  static_assert(!BM || MODE == kOther || MODE == kSame, "bitmaps hold membership only");
+  const u32 glen = ge - gs;
+  // hash chunks by count, or bitmap windows by ID
+  const u32 w_first = BM && glen ? ga[gs] >> kWinBits : 0u;
+  const u32 nch = BM ? (glen ? (ga[ge - 1] >> kWinBits) - w_first + 1 : 0u)
+                     : (glen + prm.chunk - 1) / prm.chunk;
+  u32 lo = plo;  // cursor: elements below it were probed against earlier chunks
+  u32 c0 = gs;   // first staged key of the chunk
+  for (u32 ch = 0; ch < nch; ++ch) {
+    const u32 wb = (w_first + ch) << kWinBits;  // BM: window [wb, wb + 2^kWinBits)
+    u32 clen;
+    if (BM) {
+      clen = lower_bound_g(ga, c0, ge, wb + (1u << kWinBits)) - c0;
+      if (clen == 0) continue;  // no staged key in this window (uniform)
+    } else {
+      clen = min(prm.chunk, ge - c0);
+    }
+    const u32 mask = BM ? 0u : bucket_mask(clen, kBigSlots);
+    c.staged += tid == 0 ? clen : 0;
+    if (BM) {
+      uint4* t4 = reinterpret_cast<uint4*>(sh.table);
+      for (u32 i = tid; i < (u32)kBigSlots / 4; i += blockDim.x) t4[i] = make_uint4(0, 0, 0, 0);
+    } else {
+      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) sh.table[i] = kInf;
+    }
+    // this partner's elements up to the chunk's largest ID or the window's end (the
+    // ones between two chunks are in no chunk and find nothing in either)
+    u32 hi = phi;
+    if (tid < pn && ch + 1 < nch)
+      hi = lower_bound_g(sa, lo, phi, BM ? wb + (1u << kWinBits) : ga[c0 + clen - 1] + 1u);
+    tl.probes += hi - lo;
+    const u32 qa = VEC ? (lo & ~3u) : lo;
+    const u32 nq = lo < hi ? (VEC ? (hi - qa + 3u) >> 2 : hi - lo) : 0u;
+    u32 total;
+    const u32 incl = block_incl_scan(nq, sh.tmp, &total);
+    if (tid < pn) {
+      sh.qincl[tid] = incl;
+      sh.pinfo[tid] = make_uint4((VEC ? qa >> 2 : qa) - (incl - nq), lo, hi, y);
+    }
+    if (BM) {
+      __syncthreads();  // the bitmap is cleared
+      for (u32 i = tid; i < clen; i += blockDim.x) {
+        const u32 k = ga[c0 + i] - wb;
+        atomicOr(&sh.table[k >> 5], 1u << (k & 31u));
+      }
+    } else {
+      for (u32 i = tid; i < clen; i += blockDim.x) {
+        const u32 w = ga[c0 + i];
+        const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
+        hash_insert(sh.table, mask, w, same ? 1u : 0u);
+      }
+    }
+    __syncthreads();
+    // this wavefront's contiguous quad range, in whole windows
+    const u32 per = (total + kBigWaves * kWave - 1) / (kBigWaves * kWave) * kWave;
+    const u32 qs = min(wid * per, total), qe = min(qs + per, total);
+    // partner of quad qs: smallest p with qincl[p] > qs (lane-uniform search)
+    u32 pcur = 0;
+    {
+      u32 h = pn - 1;
+      while (pcur < h) {
+        const u32 mid = (pcur + h) >> 1;
+        if (sh.qincl[mid] > qs) h = mid;
+        else pcur = mid + 1;
+      }
+    }
+    for (u32 qw = qs; qw < qe; qw += kWave * kQuadUnroll) {
+      u32 e[kQuadUnroll][NE];
+      uint4 inf[kQuadUnroll];
+      u32 addr[kQuadUnroll];
+      bool live[kQuadUnroll];
+#pragma unroll
+      for (int u = 0; u < kQuadUnroll; ++u) {
+        const u32 w0 = qw + u * kWave;        // first quad of this window
+        const u32 q = w0 + lane;
+        live[u] = q < qe;
+        // partner of q: pcur plus the boundaries (qincl values) <= q in this window
+        u32 p = pcur;
+        while (true) {
+          const u32 j = pcur + lane;
+          const u32 bj = j < pn ? sh.qincl[j] : kInf;
+          u64 bm = __ballot(bj <= w0 + kWave - 1);
+          const u32 nb = (u32)__popcll(bm);
+          while (bm) {
+            const int jl = __ffsll((unsigned long long)bm) - 1;
+            bm &= bm - 1;
+            p += q >= (u32)__shfl(bj, jl, kWave) ? 1u : 0u;
+          }
+          pcur += nb;
+          if (nb < (u32)kWave) break;
+        }
+        p = min(p, pn - 1);  // lanes past the range keep a valid index
+        inf[u] = sh.pinfo[p];
+        addr[u] = (inf[u].x + q) * NE;
+        if (VEC) {
+          // one unconditional 16-byte load: a quad that would run past the end of the
+          // streamed array (or a dead lane) reads the padded copy of its last partial quad
+          const u32* src = (live[u] && addr[u] + 3 < m) ? sa + addr[u] : st4;
+          const uint4 v = *reinterpret_cast<const uint4*>(src);
+          e[u][0] = v.x;
+          e[u][NE > 1 ? 1 : 0] = v.y;
+          e[u][NE > 2 ? 2 : 0] = v.z;
+          e[u][NE > 3 ? 3 : 0] = v.w;
+        } else {
+          e[u][0] = sa[live[u] ? addr[u] : 0u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kQuadUnroll; ++u) {
+        const u32 y2 = inf[u].w;
+        const u32 vmax = max(x, y2);
+        const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
+        bool ok[NE];
+#pragma unroll
+        for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
+        u32 res[NE];
+        if (BM) {
+          // elements of earlier, skipped windows fall outside [wb, wb + 2^kWinBits)
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) {
+            const u32 k = e[u][i] - wb;
+            const bool in = ok[i] && k < (1u << kWinBits);
+            const u32 kk = in ? k : 0u;
+            res[i] = in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
+          }
+        } else {
+          hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
+        }
+#pragma unroll
+        for (u32 i = 0; i < NE; ++i) {
+          if (MODE == kFull) {
+            tl.add(res[i], e[u][i], vmax);
+            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+          } else if (MODE == kPrunedOne) {
+            tl.s += res[i] & 1u;  // other-level apex (c1)
+            tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
+          } else if (MODE == kOther) {
+            tl.s += res[i];
+          } else {
+            tl.t2 += res[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    lo = hi;
+    c0 += clen;
+  }
+}
+
+// Bitmap windows for the sorted keys a[s .. e) when they take fewer passes than hash
+// chunks of `chunk` keys.
+__device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32 e, u32 chunk) {
+  if (e - s <= chunk) return false;
+  const u32 wins = (a[e - 1] >> kWinBits) - (a[s] >> kWinBits) + 1;
+  return wins < (e - s + chunk - 1) / chunk;
+}
+
+// One work item: staged vertex x, partner segment `seg` (all threads call it together).
+// PRUNED = false: one kFull pass over colidx.  PRUNED = true: the level-split rows
+// colidx2 (split[v] = local start of v's other-level neighbours), one kPrunedOne pass
+// when N(x) fits one chunk, else a kOther and a kSame pass.  m / m2 bound the quad loads
+// from colidx / colidx2 (beyond them the padded copies tail4 / tail4b are read).
+template <bool PV, bool VEC, bool PRUNED>
+__device__ __forceinline__ void block_item(
+    const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
+    const u32* __restrict__ tail4, const u32* __restrict__ colidx2, u32 m2,
+    const u32* __restrict__ split, const u32* __restrict__ tail4b,
+    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt,
+    const u32* __restrict__ hadj, u32 x, u32 seg, IsectParams prm, const BlockShared& sh,
+    Tally& tl, Counts& c, u64* __restrict__ tri) {
+  const u32 tid = threadIdx.x;
+  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1], dx = ex - bx;
+  const u32 px = vinfo[x] & 0x80u;
+  const u32 hs = bx + seg * prm.seg;  // H+(x) sits in place of N(x)
+  const u32 pn = min(prm.seg, hcnt[x] - seg * prm.seg);
+  u32 y = 0, yr = 0, ye = 0;
+  if (tid < pn) {
+    y = hadj[hs + tid];
+    yr = cb + rowptr[y];
+    ye = cb + rowptr[y + 1];
+  }
+  if (!PRUNED) {
+    block_pass<PV, VEC, kFull, false>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y, pn, yr,
+                                      ye, prm, sh, tl, c, tri);
+  } else {
+    u32 ys = 0, lb = 0;
+    if (tid < pn) {
+      ys = cb + split[y];
+      lb = lower_bound_g(colidx2, yr, ys, max(x, y) + 1u);  // same-level part above max
+    }
+    if (dx <= prm.chunk) {
+      block_pass<false, VEC, kPrunedOne, false>(colidx2, m2, tail4b, colidx, bx, ex, vinfo, x, px,
+                                                y, pn, lb, ye, prm, sh, tl, c, tri);
+    } else {
+      const u32 sx = cb + split[x];
+      const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
+      // bitmap windows where they need fewer passes than hash chunks
+      if (use_bitmap(colidx2, sx, ex, prm.chunk))
+        block_pass<false, VEC, kOther, true>(colidx2, m2, tail4b, colidx2, sx, ex, vinfo, x, px, y,
+                                             pn, ys, ye, prm, sh, tl, c, tri);
+      else
+        block_pass<false, VEC, kOther, false>(colidx2, m2, tail4b, colidx2, sx, ex, vinfo, x, px, y,
+                                              pn, ys, ye, prm, sh, tl, c, tri);
+      if (use_bitmap(colidx2, gx, sx, prm.chunk))
+        block_pass<false, VEC, kSame, true>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo, x, px, y,
+                                            pn, lb, ys, prm, sh, tl, c, tri);
+      else
+        block_pass<false, VEC, kSame, false>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo, x, px, y,
+                                             pn, lb, ys, prm, sh, tl, c, tri);
+    }
+  }
+}
+
+// ---- level split of one row ------------------------------------------------------------
+// The row of v (vx = vinfo[v]) at absolute offset lo is rewritten in colidx2 as
+// [neighbours on v's level, ascending | the others, ascending], and the partners
+// (same-level neighbours of smaller (degree class, ID) key) go to hadj from lo on.
+constexpr u32 kSplitLane = 32;     // rows up to this length are split by one lane
+constexpr u32 kSplitWave = 4096;   // rows up to this length by one wavefront; longer rows
+                                   // by a whole workgroup (k_split_long)
+constexpr u32 kSplitUnroll = 4;    // 64-entry steps per wavefront iteration
+
+// Partition step over entries j0 .. j0 + 64 kSplitUnroll of the row at `lo` (d entries):
+// counts (COUNT) or writes (!COUNT) the same-level entries, the other-level entries and
+// the partners, advancing the running counts cs / co / ch.
+template <bool COUNT>
+__device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
+                                            const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
+                                            u32 lo, u32 j0, u32 jend, u32 same_base,
+                                            u32 other_base, u32 part_base,
+                                            u32* __restrict__ colidx2, u32* __restrict__ hadj,
+                                            u32& cs, u32& co, u32& ch) {
+  const u32 lane = lane_id();
+  u32 w[kSplitUnroll], vw[kSplitUnroll];
+#pragma unroll
+  for (u32 u = 0; u < kSplitUnroll; ++u) {
+    const u32 j = j0 + u * kWave + lane;
+    w[u] = j < jend ? colidx[lo + j] : v;
+  }
+#pragma unroll
+  for (u32 u = 0; u < kSplitUnroll; ++u) vw[u] = vinfo[w[u]];
+#pragma unroll
+  for (u32 u = 0; u < kSplitUnroll; ++u) {
+    const u32 j = j0 + u * kWave + lane;
+    const bool in = j < jend;
+    const bool same = in && ((vw[u] ^ vx) & 0x80u) == 0;
+    const bool part = same && key_less(vw[u] & 127u, w[u], vx & 127u, v);
+    const u64 ms = __ballot(same), mo = __ballot(in && !same), mh = __ballot(part);
+    if (!COUNT) {
+      if (same) colidx2[lo + same_base + cs + mask_rank(ms)] = w[u];
+      else if (in) colidx2[lo + other_base + co + mask_rank(mo)] = w[u];
+      if (part) hadj[lo + part_base + ch + mask_rank(mh)] = w[u];
+    }
+    cs += (u32)__popcll(ms);
+    co += (u32)__popcll(mo);
+    ch += (u32)__popcll(mh);
+  }
+}
+
+// A row of at most kSplitLane entries, by one lane (four entries per step keep four
+// independent gathers in flight).  Returns the number of same-level entries in *ns and
+// of partners in *nh.
+__device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
+                                                const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
+                                                u32 lo, u32 d, u32* __restrict__ colidx2,
+                                                u32* __restrict__ hadj, u32* ns_out,
+                                                u32* nh_out) {
+  u32 ns = 0;
+  for (u32 j = 0; j < d; j += 4) {
+    u32 w[4], vw[4];
+#pragma unroll
+    for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
+#pragma unroll
+    for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
+#pragma unroll
+    for (u32 i = 0; i < 4; ++i) ns += (j + i < d) && ((vw[i] ^ vx) & 0x80u) == 0;
+  }
+  u32 is = lo, io = lo + ns, ih = lo;
+  for (u32 j = 0; j < d; j += 4) {
+    u32 w[4], vw[4];
+#pragma unroll
+    for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
+#pragma unroll
+    for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
+#pragma unroll
+    for (u32 i = 0; i < 4; ++i) {
+      if (j + i < d) {
+        if (((vw[i] ^ vx) & 0x80u) == 0) {
+          colidx2[is++] = w[i];
+          if (key_less(vw[i] & 127u, w[i], vx & 127u, v)) hadj[ih++] = w[i];
+        } else {
+          colidx2[io++] = w[i];
+        }
+      }
+    }
+  }
+  *ns_out = ns;
+  *nh_out = ih - lo;
+}
+
+}  // namespace tc

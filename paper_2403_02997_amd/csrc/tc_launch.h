@@ -102,10 +102,10 @@ void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* 
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);
 
 // ---- batched, fused per-graph pipeline ----
-size_t batch_workspace_bytes(u32 num_graphs, u64 total_rows);
+size_t batch_workspace_bytes(u32 num_graphs, u64 total_rows, u64 total_cols);
 void launch_batch(const u32* rowptr_cat, const u32* colidx_cat, const int64_t* row_off,
-                  const int64_t* col_off, u32 num_graphs, u64 total_rows, void* ws, u64* counts,
-                  hipStream_t s);
+                  const int64_t* col_off, u32 num_graphs, u64 total_rows, u64 total_cols,
+                  void* ws, IsectParams p, u64* counts, hipStream_t s);
 
 int num_cus();
 

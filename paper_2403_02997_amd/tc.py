@@ -139,9 +139,9 @@ def load() -> ctypes.CDLL:
     lib.tc_count_ex.restype = i
     lib.tc_count_per_vertex.argtypes = [vp, vp, u32, u64, vp, vp]
     lib.tc_count_per_vertex.restype = i
-    lib.tc_count_batch.argtypes = [vp, vp, vp, vp, u32, u64, vp, sz, vp, vp]
+    lib.tc_count_batch.argtypes = [vp, vp, vp, vp, u32, u64, u64, vp, sz, vp, vp]
     lib.tc_count_batch.restype = i
-    lib.tc_count_batch_workspace_size.argtypes = [u32, u64]
+    lib.tc_count_batch_workspace_size.argtypes = [u32, u64, u64]
     lib.tc_count_batch_workspace_size.restype = sz
     P = ctypes.POINTER
     lib.tc_serve_create.argtypes = [P(_ServeConfig), P(vp)]
@@ -269,16 +269,18 @@ def tc_count_per_vertex(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None)
     return out
 
 
-def tc_count_batch_workspace_size(num_graphs: int, total_rows: int) -> int:
-    return int(load().tc_count_batch_workspace_size(int(num_graphs), int(total_rows)))
+def tc_count_batch_workspace_size(num_graphs: int, total_rows: int, total_cols: int) -> int:
+    return int(load().tc_count_batch_workspace_size(int(num_graphs), int(total_rows),
+                                                    int(total_cols)))
 
 
 def tc_count_batch(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor, row_off: torch.Tensor,
                    col_off: torch.Tensor, total_rows: int | None = None,
                    workspace: torch.Tensor | None = None, counts: torch.Tensor | None = None,
-                   stream=None) -> torch.Tensor:
+                   stream=None, total_cols: int | None = None) -> torch.Tensor:
     """Per-graph counts (int64 tensor of uint64 bit patterns) of a concatenated batch.
-    row_off / col_off are int64 device tensors of num_graphs + 1 offsets.  With a caller
+    row_off / col_off are int64 device tensors of num_graphs + 1 offsets; total_rows and
+    total_cols default to the lengths of rowptr_cat and colidx_cat.  With a caller
     workspace the call is asynchronous and capturable."""
     lib = load()
     if row_off.dtype != torch.int64 or col_off.dtype != torch.int64:
@@ -286,11 +288,13 @@ def tc_count_batch(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor, row_off: 
     G = row_off.numel() - 1
     if total_rows is None:
         total_rows = rowptr_cat.numel()
+    if total_cols is None:
+        total_cols = colidx_cat.numel()
     if counts is None:
         counts = torch.empty(max(G, 0), dtype=torch.int64, device=rowptr_cat.device)
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     rc = lib.tc_count_batch(_ptr(rowptr_cat), _ptr(colidx_cat) or None, _ptr(row_off),
-                            _ptr(col_off), G, int(total_rows),
+                            _ptr(col_off), G, int(total_rows), int(total_cols),
                             _ptr(workspace) if workspace is not None else None, ws_bytes,
                             _stream_handle(stream), _ptr(counts) if G else None)
     _check(rc, "tc_count_batch")

@@ -66,18 +66,21 @@ def test_argument_errors_without_gpu(lib):
     assert out.value == 7  # untouched on error
     # batch: null inputs with graphs
     lib.tc_count_batch.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_uint64,
-                                                          ctypes.c_void_p, ctypes.c_size_t,
-                                                          ctypes.c_void_p, ctypes.c_void_p]
-    assert lib.tc_count_batch(None, None, None, None, 3, 10, None, 0, None, None) == -1
-    assert lib.tc_count_batch(None, None, None, None, 0, 0, None, 0, None, None) == 0
+                                                          ctypes.c_uint64, ctypes.c_void_p,
+                                                          ctypes.c_size_t, ctypes.c_void_p,
+                                                          ctypes.c_void_p]
+    assert lib.tc_count_batch(None, None, None, None, 3, 10, 20, None, 0, None, None) == -1
+    assert lib.tc_count_batch(None, None, None, None, 0, 0, 0, None, 0, None, None) == 0
 
 
 def test_workspace_size_grows_with_rows(lib):
-    lib.tc_count_batch_workspace_size.argtypes = [ctypes.c_uint32, ctypes.c_uint64]
+    lib.tc_count_batch_workspace_size.argtypes = [ctypes.c_uint32, ctypes.c_uint64,
+                                                  ctypes.c_uint64]
     lib.tc_count_batch_workspace_size.restype = ctypes.c_size_t
-    a = lib.tc_count_batch_workspace_size(10, 1000)
-    b = lib.tc_count_batch_workspace_size(10, 100000)
-    assert b > a >= 13 * 1000
+    a = lib.tc_count_batch_workspace_size(10, 1000, 5000)
+    b = lib.tc_count_batch_workspace_size(10, 100000, 5000)
+    c = lib.tc_count_batch_workspace_size(10, 100000, 500000)
+    assert c > b > a >= 21 * 1000 + 8 * 5000
 
 
 def test_isect_params_validation(lib):

@@ -61,7 +61,8 @@ def test_batch_caller_workspace_and_repeat(tc_lib):
     exp = expected(b, "mixed")
     rp, ci, ro, co = upload_batch(b)
     rows = b.rowptr_cat.shape[0]
-    ws = torch.empty(tc_lib.tc_count_batch_workspace_size(b.num_graphs, rows),
+    ws = torch.empty(tc_lib.tc_count_batch_workspace_size(b.num_graphs, rows,
+                                                              int(b.colidx_cat.shape[0])),
                      dtype=torch.uint8, device="cuda")
     for _ in range(3):
         counts = tc_lib.tc_count_batch(rp, ci, ro, co, total_rows=rows, workspace=ws)
@@ -94,7 +95,8 @@ def test_batch_hip_graph_replays(tc_lib):
     exp = expected(b, "mixed")
     rp, ci, ro, co = upload_batch(b)
     rows = b.rowptr_cat.shape[0]
-    ws = torch.empty(tc_lib.tc_count_batch_workspace_size(b.num_graphs, rows),
+    ws = torch.empty(tc_lib.tc_count_batch_workspace_size(b.num_graphs, rows,
+                                                              int(b.colidx_cat.shape[0])),
                      dtype=torch.uint8, device="cuda")
     counts = torch.zeros(b.num_graphs, dtype=torch.int64, device="cuda")
     s = torch.cuda.Stream()

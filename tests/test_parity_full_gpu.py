@@ -57,7 +57,8 @@ def test_batch4096_sampled_members(tc_lib):
     ro = torch.from_numpy(b.row_off).cuda()
     co = torch.from_numpy(b.col_off).cuda()
     rows = int(b.rowptr_cat.shape[0])
-    ws = torch.empty(tc_lib.tc_count_batch_workspace_size(b.num_graphs, rows),
+    ws = torch.empty(tc_lib.tc_count_batch_workspace_size(b.num_graphs, rows,
+                                                              int(b.colidx_cat.shape[0])),
                      dtype=torch.uint8, device="cuda")
     say("[full] tc_count_batch 4096 graphs")
     counts = tc_lib.as_u64(tc_lib.tc_count_batch(rp, ci, ro, co, total_rows=rows, workspace=ws))
