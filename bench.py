@@ -72,7 +72,7 @@ def log(*a):
 
 def source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("intersect.hip", "tc_device.h"):
+    for f in ("intersect.hip", "tc_isect.h", "tc_device.h"):
         h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -12,14 +12,147 @@
 //   colidx2[split[v] .. rowptr[v + 1])   the neighbours on the other levels, ascending,
 //   hadj[rowptr[v] .. rowptr[v] + hcnt[v]) the partner list H+(v) (in place of N(v)'s
 //                                          range: a partner list is never longer).
-// Rows of at most 32 entries are handled by one lane, longer ones by a whole wavefront,
-// 64 entries per step, with ballot ranks keeping both parts in order.  The level split
+// Rows of at most 32 entries are handled by one lane, rows of at most 4096 by one
+// wavefront (ballot ranks keep both parts in order), longer ones by a whole workgroup.  The level split
 // lets the counting skip the same-level neighbours that cannot be a counted apex.
 #include "tc_isect.h"
 
 namespace tc {
 
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
+
+// Register-resident row splits.  Every entry of a row (or of a 1024-entry chunk) is
+// loaded before the first vinfo gather is issued, so a row costs one load round trip
+// and one gather round trip instead of one of each per few entries; the same-level and
+// partner flags are kept as bit masks, so writing the row needs no second gather.
+
+// A row of at most kSplitLane entries, by one lane.  more[b] (wavefront-uniform) says
+// whether any lane's row is longer than 8 b entries; blocks of 8 past every lane's row
+// are skipped.
+__device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colidx,
+                                                   const uint8_t* __restrict__ vinfo, u32 v,
+                                                   u32 vx, u32 lo, u32 d, const bool* more,
+                                                   u32* __restrict__ colidx2,
+                                                   u32* __restrict__ hadj, u32* ns_out,
+                                                   u32* nh_out) {
+  constexpr u32 B = 8, NB = kSplitLane / B;
+  static_assert(kSplitLane <= 32, "flags are one 32-bit mask per lane");
+  u32 w[kSplitLane];
+#pragma unroll
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b]) {
+#pragma unroll
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        w[j] = j < d ? colidx[lo + j] : v;
+      }
+    }
+  }
+  u32 sm = 0, pm = 0;
+#pragma unroll
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b]) {
+#pragma unroll
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        const u32 vw = vinfo[w[j]];
+        const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
+        const bool part = same && key_less(vw & 127u, w[j], vx & 127u, v);
+        sm |= (same ? 1u : 0u) << j;
+        pm |= (part ? 1u : 0u) << j;
+      }
+    }
+  }
+  const u32 ns = (u32)__popc(sm);
+#pragma unroll
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b]) {
+#pragma unroll
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        if (j < d) {
+          const u32 below = (1u << j) - 1u;
+          const u32 rs = (u32)__popc(sm & below);
+          if ((sm >> j) & 1u) colidx2[lo + rs] = w[j];
+          else colidx2[lo + ns + (j - rs)] = w[j];
+          if ((pm >> j) & 1u) hadj[lo + (u32)__popc(pm & below)] = w[j];
+        }
+      }
+    }
+  }
+  *ns_out = ns;
+  *nh_out = (u32)__popc(pm);
+}
+
+// Entries c0 .. c0 + 64 kSplitRegU of the row of v at `lo` (d entries), by one wavefront,
+// lane l holding entries c0 + 64 u + l.  MODE 0 counts the same-level entries (into cs)
+// and the partners (into ch); MODE 1 writes them, the other-level part starting at
+// ns_total; MODE 2 is a whole row in one chunk: it counts, then writes.
+constexpr u32 kSplitRegU = 16;
+constexpr u32 kSplitReg = kSplitRegU * kWave;  // rows up to this length in one chunk
+
+template <int MODE>
+__device__ __forceinline__ void split_chunk_reg(const u32* __restrict__ colidx,
+                                                const uint8_t* __restrict__ vinfo, u32 v,
+                                                u32 vx, u32 lo, u32 c0, u32 d, u32 ns_total,
+                                                u32* __restrict__ colidx2, u32* __restrict__ hadj,
+                                                u32& cs, u32& co, u32& ch) {
+  constexpr u32 U = kSplitRegU;
+  const u32 lane = lane_id();
+  const u32 nu = min((d - c0 + kWave - 1) / kWave, U);  // wavefront-uniform
+  u32 w[U];
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      const u32 j = c0 + u * kWave + lane;
+      w[u] = j < d ? colidx[lo + j] : v;
+    }
+  }
+  u32 sm = 0, pm = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      const u32 j = c0 + u * kWave + lane;
+      const u32 vw = vinfo[w[u]];
+      const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
+      const bool part = same && key_less(vw & 127u, w[u], vx & 127u, v);
+      sm |= (same ? 1u : 0u) << u;
+      pm |= (part ? 1u : 0u) << u;
+    }
+  }
+  if (MODE == 0) {
+#pragma unroll
+    for (u32 u = 0; u < U; ++u) {
+      if (u < nu) {
+        cs += (u32)__popcll(__ballot((sm >> u) & 1u));
+        ch += (u32)__popcll(__ballot((pm >> u) & 1u));
+      }
+    }
+    return;
+  }
+  u32 nsb = ns_total;
+  if (MODE == 2) {
+    nsb = 0;
+#pragma unroll
+    for (u32 u = 0; u < U; ++u)
+      if (u < nu) nsb += (u32)__popcll(__ballot((sm >> u) & 1u));
+  }
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      const u32 j = c0 + u * kWave + lane;
+      const bool in = j < d;
+      const bool same = (sm >> u) & 1u, part = (pm >> u) & 1u;
+      const u64 ms = __ballot(same), mo = __ballot(in && !same), mh = __ballot(part);
+      if (same) colidx2[lo + cs + mask_rank(ms)] = w[u];
+      else if (in) colidx2[lo + nsb + co + mask_rank(mo)] = w[u];
+      if (part) hadj[lo + ch + mask_rank(mh)] = w[u];
+      cs += (u32)__popcll(ms);
+      co += (u32)__popcll(mo);
+      ch += (u32)__popcll(mh);
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowptr,
                                                    const u32* __restrict__ colidx,
@@ -38,35 +171,42 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
       d = rowptr[v + 1] - lo;
       vx = vinfo[v];
     }
+    const bool short_row = v < n && d <= kSplitLane;
     const bool mid = d > kSplitLane && d <= kSplitWave;
     const bool lng = d > kSplitWave;
-    if (v < n && d <= kSplitLane) {
+    bool more[kSplitLane / 8];
+#pragma unroll
+    for (u32 b = 0; b < kSplitLane / 8; ++b) more[b] = __ballot(short_row && d > b * 8) != 0;
+    if (short_row) {
       u32 ns, nh;
-      split_short_row(colidx, vinfo, v, vx, lo, d, colidx2, hadj, &ns, &nh);
+      split_lane_row_reg(colidx, vinfo, v, vx, lo, d, more, colidx2, hadj, &ns, &nh);
       split[v] = lo + ns;
       hcnt[v] = nh;
     }
     // long rows go to the workgroup kernel
     const u32 pos = wave_append(num_long, lng);
     if (lng) long_rows[pos] = v;
-    // medium rows: one wavefront each, 64 kSplitUnroll entries per step
+    // medium rows: one wavefront each, kSplitReg entries per chunk
     u64 mm = __ballot(mid);
     while (mm) {
       const int b = __ffsll((unsigned long long)mm) - 1;
       mm &= mm - 1;
       const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
       const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
-      u32 ns = 0, no = 0, nh = 0;
-      for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
-        split_steps<true>(colidx, vinfo, bv, bvx, blo, j0, bd, 0, 0, 0, colidx2, hadj, ns, no,
-                          nh);
       u32 cs = 0, co = 0, ch = 0;
-      for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
-        split_steps<false>(colidx, vinfo, bv, bvx, blo, j0, bd, 0, ns, 0, colidx2, hadj, cs, co,
-                           ch);
+      if (bd <= kSplitReg) {
+        split_chunk_reg<2>(colidx, vinfo, bv, bvx, blo, 0, bd, 0, colidx2, hadj, cs, co, ch);
+      } else {
+        u32 ns = 0, nh = 0, unused = 0;
+        for (u32 c0 = 0; c0 < bd; c0 += kSplitReg)
+          split_chunk_reg<0>(colidx, vinfo, bv, bvx, blo, c0, bd, 0, colidx2, hadj, ns, unused,
+                             nh);
+        for (u32 c0 = 0; c0 < bd; c0 += kSplitReg)
+          split_chunk_reg<1>(colidx, vinfo, bv, bvx, blo, c0, bd, ns, colidx2, hadj, cs, co, ch);
+      }
       if ((int)lane == b) {
-        split[bv] = blo + ns;
-        hcnt[bv] = nh;
+        split[bv] = blo + cs;
+        hcnt[bv] = ch;
       }
     }
   }
