@@ -51,7 +51,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
 # The kernel instance tc_count launches for each intersection step (16-byte aligned
 # colidx, no per-vertex attribution; the workgroup class in its pruned form).
-KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>", "isect_wave": "k_isect_wave<false, true>",
+KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>",
+                  "isect_wave": "k_isect_wave<false, true, true>",
                   "isect_block": "k_isect_block<false, true, true>"}
 
 WORKLOAD_TEXT = {
@@ -93,11 +94,11 @@ def degree_class(d: np.ndarray) -> np.ndarray:
 def class_bytes(g, level: np.ndarray, params) -> dict:
     """Per intersection class of tc_count: cover edges and the bytes its kernel has to
     read at least once.  A cover edge {x, y} is staged under x (larger degree class, then
-    ID) and streams y's list.  Lane and wavefront classes stream all of N(y) and stage
-    N(x); the workgroup class streams only y's other-level neighbours and its same-level
-    neighbours above max(x, y), and stages N(x) whole when it fits one chunk, else its
-    other-level part and its same-level part above x.  Each staged list counts once."""
-    lane_max, wave_max, chunk = params[0], params[1], params[2]
+    ID) and streams y's list.  The lane class streams all of N(y) and stages N(x); the
+    wavefront and workgroup classes stream only y's other-level neighbours and its
+    same-level neighbours above max(x, y), and stage x's other-level neighbours and its
+    same-level neighbours above x.  Each staged list counts once."""
+    lane_max, wave_max = params[0], params[1]
     d = g.degrees().astype(np.int64)
     rp = g.rowptr.astype(np.int64)
     rows = np.repeat(np.arange(g.n, dtype=np.int64), d)
@@ -124,7 +125,7 @@ def class_bytes(g, level: np.ndarray, params) -> dict:
                       ("isect_block", dx > wave_max)):
         xs = np.unique(x[sel])
         ys = y[sel]
-        if name != "isect_block":
+        if name == "isect_lane":
             streamed = int(d[ys].sum())
             staged = int(d[xs].sum())
         else:
@@ -134,7 +135,7 @@ def class_bytes(g, level: np.ndarray, params) -> dict:
             streamed = int((d[ys] - skip).sum())
             same_x = cs[rp[xs + 1]] - cs[rp[xs]]
             above = cs[rp[xs + 1]] - cs[np.searchsorted(key, xs * (1 << 32) + xs, side="right")]
-            staged = int(np.where(d[xs] <= chunk, d[xs], d[xs] - same_x + above).sum())
+            staged = int((d[xs] - same_x + above).sum())
         out[name] = {"cover_edges": int(sel.sum()), "bytes": 4 * (streamed + staged)}
     return out
 

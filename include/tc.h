@@ -20,7 +20,10 @@
  *   m             : number of stored entries = 2 |E|.  Input edges = m / 2.
  * The arrays are DEVICE pointers on the current HIP device, owned by the caller and
  * never written by the library.  Validity is a precondition (a self-loop or duplicate
- * would be counted); tc_validate_csr checks it on the device.
+ * would be counted); tc_validate_csr checks it on the device.  The single-graph calls
+ * return TC_ERR_INVALID_GRAPH when they meet an asymmetry between two vertices on the
+ * same BFS level (their partner records would be inconsistent); other violations are
+ * not detected.
  *
  * Roots: each BFS restarts from the smallest vertex ID of its component (the paper's
  * restart loop taken in ascending ID).  T does not depend on this choice; the levels,
@@ -49,7 +52,7 @@ typedef enum {
   TC_ERR_INVALID_ARG = -1,    /* null pointer where data is required, bad size      */
   TC_ERR_OUT_OF_MEMORY = -2,  /* device workspace allocation failed                 */
   TC_ERR_HIP = -3,            /* a HIP runtime call failed                          */
-  TC_ERR_INVALID_GRAPH = -4,  /* tc_validate_csr found a contract violation         */
+  TC_ERR_INVALID_GRAPH = -4,  /* a contract violation was found (see above)         */
   TC_ERR_TOO_LARGE = -5,      /* n >= 2^30 or m >= 2^32                             */
   TC_ERR_INTERNAL = -6        /* an internal consistency check failed               */
 } tc_status;

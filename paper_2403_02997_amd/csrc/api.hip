@@ -183,8 +183,10 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<uint8_t>(n);              // vinfo
     c.take<u32>(n);                  // hcnt
     c.take<u32>(n);                  // split
+    c.take<u32>(n);                  // sabove
+    c.take<u32>(n);                  // hcur (record cursors)
     c.take<u32>(scan_tmp_words(n));  // scan tmp
-    c.take<u32>(m);                  // hadj (partner lists in place of the rows)
+    c.take<uint4>(m);                // hrec (partner records in place of the rows)
     c.take<u32>(m);                  // colidx2 (rows split by level)
     c.take<u32>(n);                  // lane_x
     c.take<u32>(n);                  // wave_x
@@ -213,8 +215,10 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   uint8_t* vinfo = c.take<uint8_t>(n);
   u32* hcnt = c.take<u32>(n);
   u32* split = c.take<u32>(n);
+  u32* sabove = c.take<u32>(n);
+  u32* hcur = c.take<u32>(n);
   u32* scan_tmp = c.take<u32>(scan_tmp_words(n));
-  u32* hadj = c.take<u32>(m);
+  uint4* hrec = c.take<uint4>(m);
   u32* colidx2 = c.take<u32>(m);
   u32* lane_x = c.take<u32>(n);
   u32* wave_x = c.take<u32>(n);
@@ -262,13 +266,14 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     }
   }
   timer.mark();
-  launch_vinfo(rowptr, level, n, vinfo, s);
+  launch_vinfo(rowptr, level, n, vinfo, hcur, s);
 
   // ---- a3: cover-edge extraction ----
   // the BFS queues are free again: q1 lists the long rows
-  launch_split_rows(rowptr, colidx, vinfo, n, colidx2, split, hcnt, hadj, q1, &plan->num_long, s);
+  launch_split_rows(rowptr, colidx, vinfo, n, m, colidx2, split, sabove, hcnt, hcur, hrec, q1,
+                    &plan->num_long, s);
   timer.mark();
-  launch_plan(rowptr, hcnt, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
+  launch_plan(rowptr, hcnt, hcur, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
   launch_scan(bitems, bitems, n, scan_tmp, s);
   TC_LAUNCHED();
   u32 h_items = 0;
@@ -276,6 +281,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   TC_HIP(hipMemcpyAsync(&h_items, bitems + n, sizeof(u32), hipMemcpyDeviceToHost, s));
   TC_HIP(hipMemcpyAsync(&h_plan, plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
+  // a graph that is not symmetric can leave partner records unwritten: stop before
+  // any intersection reads them
+  if (h_plan.bad_records) return TC_ERR_INVALID_GRAPH;
   const u32 h_ns = h_plan.num_cover;
   if (h_ns > max_s) return TC_ERR_INTERNAL;
 
@@ -288,16 +296,17 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     items = (Item*)items_mem.p;
     launch_fill_items(rowptr, hcnt, block_x, bitems, h_plan.num_block_x, prm, items, s);
   }
+  const SplitView sv{colidx2, split, sabove, hcnt, hrec, tail4b};
   timer.mark();
-  launch_isect_lane(rowptr, colidx, vinfo, hcnt, hadj, lane_x, h_plan.num_lane_x, ctr, tri, s);
+  launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
   timer.mark();
   launch_tail4(colidx, m, tail4, s);
   launch_tail4(colidx2, m, tail4b, s);
-  launch_isect_block(rowptr, colidx, m, tail4, colidx2, split, tail4b, vinfo, hcnt, hadj, items,
-                     h_items, prm, plan, ctr, tri, pruned && !tri, s);
+  launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
+                     pruned && !tri, s);
   timer.mark();
-  launch_isect_wave(rowptr, colidx, m, tail4, vinfo, hcnt, hadj, wave_x, h_plan.num_wave_x, plan,
-                    ctr, tri, s);
+  launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
+                    tri, pruned && !tri, s);
   timer.mark();
   // ---- a5: reduction ----
   launch_finalize(ctr, outc, s);

@@ -10,11 +10,14 @@
 // One row-centric pass per vertex v writes
 //   colidx2[rowptr[v] .. split[v])       the neighbours on v's level, ascending,
 //   colidx2[split[v] .. rowptr[v + 1])   the neighbours on the other levels, ascending,
-//   hadj[rowptr[v] .. rowptr[v] + hcnt[v]) the partner list H+(v) (in place of N(v)'s
-//                                          range: a partner list is never longer).
-// Rows of at most 32 entries are handled by one lane, rows of at most 4096 by one
-// wavefront (ballot ranks keep both parts in order), longer ones by a whole workgroup.  The level split
-// lets the counting skip the same-level neighbours that cannot be a counted apex.
+//   sabove[v]                            the first entry of the first part above v,
+//   hcnt[v]                              |H+(v)|,
+// and the partner records of H+(w) for its same-level neighbours w that stage v, at
+// hrec[rowptr[w] .. rowptr[w] + hcnt[w]) (in place of N(w)'s range: a partner list is
+// never longer).  Rows of at most 32 entries are handled by one lane, rows of at most
+// 4096 by one wavefront (ballot ranks keep both parts in order), longer ones by a whole
+// workgroup.  The level split and the records let the counting skip the same-level
+// neighbours that cannot be a counted apex.
 #include "tc_isect.h"
 
 namespace tc {
@@ -23,8 +26,24 @@ static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
 // Register-resident row splits.  Every entry of a row (or of a 1024-entry chunk) is
 // loaded before the first vinfo gather is issued, so a row costs one load round trip
-// and one gather round trip instead of one of each per few entries; the same-level and
-// partner flags are kept as bit masks, so writing the row needs no second gather.
+// and one gather round trip instead of one of each per few entries; the same-level,
+// partner and below-v flags are kept as bit masks, so writing the row needs no second
+// gather.
+//
+// Besides the level-split row, the split of row v writes sabove[v] (the first
+// same-level neighbour above v) and, for every same-level neighbour w that stages v
+// (key(w) > key(v): v is in H+(w)), v's partner record under w: the first entry of v's
+// same-level part above max(v, w) (w's rank + 1 when w > v, else v's own rank), the
+// start of v's other-level part and the end of v's row.  Records are appended to w's
+// slots at rowptr[w] through the cursor hcur[w] (initialised to rowptr[w]); a symmetric
+// graph fills exactly hcnt[w] of them, which the planner checks.
+
+struct SplitOut {
+  u32* colidx2;
+  u32* hcur;
+  uint4* hrec;
+  u32 m;  // records are written only below m (a guard for graphs that break the contract)
+};
 
 // A row of at most kSplitLane entries, by one lane.  more[b] (wavefront-uniform) says
 // whether any lane's row is longer than 8 b entries; blocks of 8 past every lane's row
@@ -32,9 +51,8 @@ static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colidx,
                                                    const uint8_t* __restrict__ vinfo, u32 v,
                                                    u32 vx, u32 lo, u32 d, const bool* more,
-                                                   u32* __restrict__ colidx2,
-                                                   u32* __restrict__ hadj, u32* ns_out,
-                                                   u32* nh_out) {
+                                                   const SplitOut& o, u32* ns_out, u32* nh_out,
+                                                   u32* sr_out) {
   constexpr u32 B = 8, NB = kSplitLane / B;
   static_assert(kSplitLane <= 32, "flags are one 32-bit mask per lane");
   u32 w[kSplitLane];
@@ -48,7 +66,7 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
       }
     }
   }
-  u32 sm = 0, pm = 0;
+  u32 sm = 0, pm = 0, lm = 0, rm = 0;  // same level, partner, below v, record for w
 #pragma unroll
   for (u32 b = 0; b < NB; ++b) {
     if (more[b]) {
@@ -60,10 +78,12 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
         const bool part = same && key_less(vw & 127u, w[j], vx & 127u, v);
         sm |= (same ? 1u : 0u) << j;
         pm |= (part ? 1u : 0u) << j;
+        lm |= (same && w[j] < v ? 1u : 0u) << j;
+        rm |= (same && !part && w[j] != v ? 1u : 0u) << j;
       }
     }
   }
-  const u32 ns = (u32)__popc(sm);
+  const u32 ns = (u32)__popc(sm), sr = (u32)__popc(lm);
 #pragma unroll
   for (u32 b = 0; b < NB; ++b) {
     if (more[b]) {
@@ -71,85 +91,116 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
       for (u32 i = 0; i < B; ++i) {
         const u32 j = b * B + i;
         if (j < d) {
-          const u32 below = (1u << j) - 1u;
-          const u32 rs = (u32)__popc(sm & below);
-          if ((sm >> j) & 1u) colidx2[lo + rs] = w[j];
-          else colidx2[lo + ns + (j - rs)] = w[j];
-          if ((pm >> j) & 1u) hadj[lo + (u32)__popc(pm & below)] = w[j];
+          const u32 rs = (u32)__popc(sm & ((1u << j) - 1u));
+          if ((sm >> j) & 1u) o.colidx2[lo + rs] = w[j];
+          else o.colidx2[lo + ns + (j - rs)] = w[j];
+        }
+      }
+    }
+  }
+  // records, 8 entries at a time: the cursor atomics of a block are all in flight
+  // before the first record is stored
+#pragma unroll
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b] && __ballot((rm >> (b * B)) & 0xFFu) != 0) {
+      u32 idx[B];
+#pragma unroll
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        idx[i] = (rm >> j) & 1u ? atomicAdd(&o.hcur[w[j]], 1u) : o.m;
+      }
+#pragma unroll
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        if (idx[i] < o.m) {
+          const u32 rs = (u32)__popc(sm & ((1u << j) - 1u));
+          o.hrec[idx[i]] = make_uint4(w[j] > v ? lo + rs + 1 : lo + sr, lo + ns, lo + d, v);
         }
       }
     }
   }
   *ns_out = ns;
   *nh_out = (u32)__popc(pm);
+  *sr_out = sr;
 }
 
-// Entries c0 .. c0 + 64 kSplitRegU of the row of v at `lo` (d entries), by one wavefront,
-// lane l holding entries c0 + 64 u + l.  MODE 0 counts the same-level entries (into cs)
-// and the partners (into ch); MODE 1 writes them, the other-level part starting at
-// ns_total; MODE 2 is a whole row in one chunk: it counts, then writes.
+// Entries c0 .. min(c0 + kSplitReg, cend) of the row of v (colidx[lo .. lo + d)), one
+// wavefront, lane l holding entries c0 + 64 u + l.
 constexpr u32 kSplitRegU = 16;
-constexpr u32 kSplitReg = kSplitRegU * kWave;  // rows up to this length in one chunk
+constexpr u32 kSplitReg = kSplitRegU * kWave;
 
-template <int MODE>
-__device__ __forceinline__ void split_chunk_reg(const u32* __restrict__ colidx,
-                                                const uint8_t* __restrict__ vinfo, u32 v,
-                                                u32 vx, u32 lo, u32 c0, u32 d, u32 ns_total,
-                                                u32* __restrict__ colidx2, u32* __restrict__ hadj,
-                                                u32& cs, u32& co, u32& ch) {
+struct ChunkRegs {
+  u32 w[kSplitRegU];
+  u32 sm, pm, lm, rm, nu;  // flag bits per u: same level, partner of v, same level below
+                           // v, record of v for w
+};
+
+__device__ __forceinline__ void chunk_load(const u32* __restrict__ colidx,
+                                           const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
+                                           u32 lo, u32 c0, u32 cend, ChunkRegs& r) {
   constexpr u32 U = kSplitRegU;
   const u32 lane = lane_id();
-  const u32 nu = min((d - c0 + kWave - 1) / kWave, U);  // wavefront-uniform
-  u32 w[U];
+  r.nu = min((cend - c0 + kWave - 1) / kWave, U);  // wavefront-uniform
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
-    if (u < nu) {
+    if (u < r.nu) {
       const u32 j = c0 + u * kWave + lane;
-      w[u] = j < d ? colidx[lo + j] : v;
+      r.w[u] = j < cend ? colidx[lo + j] : v;
     }
   }
-  u32 sm = 0, pm = 0;
+  r.sm = r.pm = r.lm = r.rm = 0;
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
-    if (u < nu) {
+    if (u < r.nu) {
       const u32 j = c0 + u * kWave + lane;
-      const u32 vw = vinfo[w[u]];
-      const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
-      const bool part = same && key_less(vw & 127u, w[u], vx & 127u, v);
-      sm |= (same ? 1u : 0u) << u;
-      pm |= (part ? 1u : 0u) << u;
+      const u32 vw = vinfo[r.w[u]];
+      const bool same = j < cend && ((vw ^ vx) & 0x80u) == 0;
+      const bool part = same && key_less(vw & 127u, r.w[u], vx & 127u, v);
+      r.sm |= (same ? 1u : 0u) << u;
+      r.pm |= (part ? 1u : 0u) << u;
+      r.lm |= (same && r.w[u] < v ? 1u : 0u) << u;
+      r.rm |= (same && !part && r.w[u] != v ? 1u : 0u) << u;
     }
   }
-  if (MODE == 0) {
+}
+
+// Adds the chunk's same-level entries, partners and same-level entries below v.
+__device__ __forceinline__ void chunk_count(const ChunkRegs& r, u32& ns, u32& nh, u32& sr) {
 #pragma unroll
-    for (u32 u = 0; u < U; ++u) {
-      if (u < nu) {
-        cs += (u32)__popcll(__ballot((sm >> u) & 1u));
-        ch += (u32)__popcll(__ballot((pm >> u) & 1u));
-      }
+  for (u32 u = 0; u < kSplitRegU; ++u) {
+    if (u < r.nu) {
+      ns += (u32)__popcll(__ballot((r.sm >> u) & 1u));
+      nh += (u32)__popcll(__ballot((r.pm >> u) & 1u));
+      sr += (u32)__popcll(__ballot((r.lm >> u) & 1u));
     }
-    return;
   }
-  u32 nsb = ns_total;
-  if (MODE == 2) {
-    nsb = 0;
+}
+
+// Writes the chunk: its same-level entries from same_base + cs of v's same part, its
+// other-level ones from other_base + co of the row; ns / sr are the row's totals.
+__device__ __forceinline__ void chunk_write(const ChunkRegs& r, u32 v, u32 lo, u32 d, u32 c0,
+                                            u32 cend, u32 same_base, u32 other_base, u32 ns,
+                                            u32 sr, const SplitOut& o, u32& cs, u32& co) {
+  const u32 lane = lane_id();
+  // the cursor atomics of the whole chunk are in flight before the first store
+  u32 idx[kSplitRegU];
 #pragma unroll
-    for (u32 u = 0; u < U; ++u)
-      if (u < nu) nsb += (u32)__popcll(__ballot((sm >> u) & 1u));
-  }
+  for (u32 u = 0; u < kSplitRegU; ++u)
+    if (u < r.nu) idx[u] = (r.rm >> u) & 1u ? atomicAdd(&o.hcur[r.w[u]], 1u) : o.m;
 #pragma unroll
-  for (u32 u = 0; u < U; ++u) {
-    if (u < nu) {
+  for (u32 u = 0; u < kSplitRegU; ++u) {
+    if (u < r.nu) {
       const u32 j = c0 + u * kWave + lane;
-      const bool in = j < d;
-      const bool same = (sm >> u) & 1u, part = (pm >> u) & 1u;
-      const u64 ms = __ballot(same), mo = __ballot(in && !same), mh = __ballot(part);
-      if (same) colidx2[lo + cs + mask_rank(ms)] = w[u];
-      else if (in) colidx2[lo + nsb + co + mask_rank(mo)] = w[u];
-      if (part) hadj[lo + ch + mask_rank(mh)] = w[u];
+      const bool in = j < cend;
+      const bool same = (r.sm >> u) & 1u;
+      const u64 ms = __ballot(same), mo = __ballot(in && !same);
+      const u32 ps = same_base + cs + mask_rank(ms);  // position in v's same part
+      if (same) o.colidx2[lo + ps] = r.w[u];
+      else if (in) o.colidx2[lo + other_base + co + mask_rank(mo)] = r.w[u];
+      if (idx[u] < o.m)
+        o.hrec[idx[u]] = make_uint4(r.w[u] > v ? lo + ps + 1 : lo + sr, lo + ns, lo + d, v);
       cs += (u32)__popcll(ms);
       co += (u32)__popcll(mo);
-      ch += (u32)__popcll(mh);
     }
   }
 }
@@ -157,9 +208,9 @@ __device__ __forceinline__ void split_chunk_reg(const u32* __restrict__ colidx,
 __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowptr,
                                                    const u32* __restrict__ colidx,
                                                    const uint8_t* __restrict__ vinfo, u32 n,
-                                                   u32* __restrict__ colidx2,
-                                                   u32* __restrict__ split, u32* __restrict__ hcnt,
-                                                   u32* __restrict__ hadj,
+                                                   SplitOut o, u32* __restrict__ split,
+                                                   u32* __restrict__ sabove,
+                                                   u32* __restrict__ hcnt,
                                                    u32* __restrict__ long_rows,
                                                    u32* __restrict__ num_long) {
   const u32 lane = lane_id();
@@ -178,9 +229,10 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
 #pragma unroll
     for (u32 b = 0; b < kSplitLane / 8; ++b) more[b] = __ballot(short_row && d > b * 8) != 0;
     if (short_row) {
-      u32 ns, nh;
-      split_lane_row_reg(colidx, vinfo, v, vx, lo, d, more, colidx2, hadj, &ns, &nh);
+      u32 ns, nh, sr;
+      split_lane_row_reg(colidx, vinfo, v, vx, lo, d, more, o, &ns, &nh, &sr);
       split[v] = lo + ns;
+      sabove[v] = lo + sr;
       hcnt[v] = nh;
     }
     // long rows go to the workgroup kernel
@@ -193,20 +245,26 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
       mm &= mm - 1;
       const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
       const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
-      u32 cs = 0, co = 0, ch = 0;
+      u32 ns = 0, nh = 0, sr = 0, cs = 0, co = 0;
+      ChunkRegs r;
       if (bd <= kSplitReg) {
-        split_chunk_reg<2>(colidx, vinfo, bv, bvx, blo, 0, bd, 0, colidx2, hadj, cs, co, ch);
+        chunk_load(colidx, vinfo, bv, bvx, blo, 0, bd, r);
+        chunk_count(r, ns, nh, sr);
+        chunk_write(r, bv, blo, bd, 0, bd, 0, ns, ns, sr, o, cs, co);
       } else {
-        u32 ns = 0, nh = 0, unused = 0;
-        for (u32 c0 = 0; c0 < bd; c0 += kSplitReg)
-          split_chunk_reg<0>(colidx, vinfo, bv, bvx, blo, c0, bd, 0, colidx2, hadj, ns, unused,
-                             nh);
-        for (u32 c0 = 0; c0 < bd; c0 += kSplitReg)
-          split_chunk_reg<1>(colidx, vinfo, bv, bvx, blo, c0, bd, ns, colidx2, hadj, cs, co, ch);
+        for (u32 c0 = 0; c0 < bd; c0 += kSplitReg) {
+          chunk_load(colidx, vinfo, bv, bvx, blo, c0, bd, r);
+          chunk_count(r, ns, nh, sr);
+        }
+        for (u32 c0 = 0; c0 < bd; c0 += kSplitReg) {
+          chunk_load(colidx, vinfo, bv, bvx, blo, c0, bd, r);
+          chunk_write(r, bv, blo, bd, c0, bd, 0, ns, ns, sr, o, cs, co);
+        }
       }
       if ((int)lane == b) {
-        split[bv] = blo + cs;
-        hcnt[bv] = ch;
+        split[bv] = blo + ns;
+        sabove[bv] = blo + sr;
+        hcnt[bv] = nh;
       }
     }
   }
@@ -214,16 +272,17 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
 
 // Long rows: one 1024-thread workgroup per row; each wavefront takes a contiguous
 // segment, and a workgroup scan of the segments' counts gives every wavefront its output
-// offsets, so both parts stay in ascending order.
+// offsets, so both parts stay in ascending order.  A segment of at most kSplitReg entries
+// stays in registers across the scan.
 constexpr u32 kLongThreads = 1024;
 constexpr u32 kLongWaves = kLongThreads / kWave;
 
 __global__ void __launch_bounds__(kLongThreads) k_split_long(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
     const uint8_t* __restrict__ vinfo, const u32* __restrict__ long_rows,
-    const u32* __restrict__ num_long, u32* __restrict__ next_long, u32* __restrict__ colidx2,
-    u32* __restrict__ split, u32* __restrict__ hcnt, u32* __restrict__ hadj) {
-  __shared__ u32 s_cnt[2][kLongWaves];
+    const u32* __restrict__ num_long, u32* __restrict__ next_long, SplitOut o,
+    u32* __restrict__ split, u32* __restrict__ sabove, u32* __restrict__ hcnt) {
+  __shared__ u32 s_cnt[3][kLongWaves];
   __shared__ u32 s_row;
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   const u32 nl = *num_long;
@@ -236,47 +295,52 @@ __global__ void __launch_bounds__(kLongThreads) k_split_long(
     const u32 v = s_row;
     if (v == kInf) break;
     const u32 lo = rowptr[v], d = rowptr[v + 1] - lo, vx = vinfo[v];
-    const u32 step = kWave * kSplitUnroll;
-    const u32 seg = (d + kLongWaves * step - 1) / (kLongWaves * step) * step;
+    const u32 seg = (d + kLongWaves * kWave - 1) / (kLongWaves * kWave) * kWave;
     const u32 j0 = min(wid * seg, d), j1 = min(j0 + seg, d);
-    u32 ns = 0, no = 0, nh = 0;
-    for (u32 j = j0; j < j1; j += step)
-      split_steps<true>(colidx, vinfo, v, vx, lo, j, j1, 0, 0, 0, colidx2, hadj, ns, no, nh);
+    const bool one = seg <= kSplitReg;  // workgroup-uniform
+    u32 ns = 0, nh = 0, sr = 0;
+    ChunkRegs r;
+    for (u32 c0 = j0; c0 < j1; c0 += kSplitReg) {
+      chunk_load(colidx, vinfo, v, vx, lo, c0, j1, r);
+      chunk_count(r, ns, nh, sr);
+    }
     if (lane == 0) {
       s_cnt[0][wid] = ns;
       s_cnt[1][wid] = nh;
+      s_cnt[2][wid] = sr;
     }
     __syncthreads();
-    u32 bs = 0, bh = 0, ts = 0, th = 0;
+    u32 bs = 0, ts = 0, th = 0, tsr = 0;
     for (u32 w = 0; w < kLongWaves; ++w) {
-      if (w < wid) {
-        bs += s_cnt[0][w];
-        bh += s_cnt[1][w];
-      }
+      if (w < wid) bs += s_cnt[0][w];
       ts += s_cnt[0][w];
       th += s_cnt[1][w];
+      tsr += s_cnt[2][w];
     }
-    u32 cs = 0, co = 0, ch = 0;
-    for (u32 j = j0; j < j1; j += step)
-      split_steps<false>(colidx, vinfo, v, vx, lo, j, j1, bs, ts + (j0 - bs), bh, colidx2, hadj,
-                         cs, co, ch);
+    u32 cs = 0, co = 0;
+    for (u32 c0 = j0; c0 < j1; c0 += kSplitReg) {
+      if (!one) chunk_load(colidx, vinfo, v, vx, lo, c0, j1, r);
+      chunk_write(r, v, lo, d, c0, j1, bs, ts + (j0 - bs), ts, tsr, o, cs, co);
+    }
     if (threadIdx.x == 0) {
       split[v] = lo + ts;
+      sabove[v] = lo + tsr;
       hcnt[v] = th;
     }
     __syncthreads();  // s_cnt and s_row are rewritten for the next row
   }
 }
 
-void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n,
-                       u32* colidx2, u32* split, u32* hcnt, u32* hadj, u32* long_rows,
-                       u32* counters, hipStream_t s) {
+void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n, u32 m,
+                       u32* colidx2, u32* split, u32* sabove, u32* hcnt, u32* hcur, uint4* hrec,
+                       u32* long_rows, u32* counters, hipStream_t s) {
   if (n == 0) return;
+  const SplitOut o{colidx2, hcur, hrec, m};
   const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
-  hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, s, rowptr, colidx, vinfo, n, colidx2,
-                     split, hcnt, hadj, long_rows, counters);
+  hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, s, rowptr, colidx, vinfo, n, o, split,
+                     sabove, hcnt, long_rows, counters);
   hipLaunchKernelGGL(k_split_long, dim3(num_cus()), dim3(kLongThreads), 0, s, rowptr, colidx,
-                     vinfo, long_rows, counters, counters + 1, colidx2, split, hcnt, hadj);
+                     vinfo, long_rows, counters, counters + 1, o, split, sabove, hcnt);
 }
 
 // ---- planning: split the staged endpoints x into the three intersection classes ----
@@ -287,7 +351,8 @@ void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinf
 constexpr u32 kPlanPer = 8;
 
 __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
-                                              const u32* __restrict__ hcnt, u32 n, IsectParams p,
+                                              const u32* __restrict__ hcnt,
+                                              const u32* __restrict__ hcur, u32 n, IsectParams p,
                                               u32* __restrict__ lane_x, u32* __restrict__ wave_x,
                                               u32* __restrict__ block_x,
                                               u32* __restrict__ block_items,
@@ -297,7 +362,7 @@ __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
   __shared__ u32 s_cov[256 / kWave];
   u32* const counters[3] = {&plan->num_lane_x, &plan->num_wave_x, &plan->num_block_x};
   const u32 span = kPlanPer * blockDim.x;
-  u32 cover = 0;
+  u32 cover = 0, bad = 0;
   for (u32 base = blockIdx.x * span; base < n; base += gridDim.x * span) {
     u32 cls = 0;  // 2 bits per vertex: 0 no partners, 1 lane, 2 wavefront, 3 workgroup class
     u32 cnt[3] = {0, 0, 0};
@@ -306,8 +371,10 @@ __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
       const u32 x = base + k * blockDim.x + threadIdx.x;
       u32 np = 0, d = 0;
       if (x < n) {
+        const u32 lo = rowptr[x];
         np = hcnt[x];
-        d = rowptr[x + 1] - rowptr[x];
+        d = rowptr[x + 1] - lo;
+        bad += hcur[x] != lo + np ? 1u : 0u;
       }
       const u32 c = np == 0 ? 0u : d <= p.lane_max ? 1u : d <= p.wave_max ? 2u : 3u;
       cover += np;
@@ -341,6 +408,7 @@ __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
     }
     __syncthreads();  // s_base is rewritten by the next pass
   }
+  if (bad) atomicAdd(&plan->bad_records, bad);
   cover = wave_sum_u32(cover);
   if (lane_id() == 0) s_cov[threadIdx.x / kWave] = cover;
   __syncthreads();
@@ -351,12 +419,13 @@ __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
   }
 }
 
-void launch_plan(const u32* rowptr, const u32* hcnt, u32 n, IsectParams p, u32* lane_x,
-                 u32* wave_x, u32* block_x, u32* block_items, Plan* plan, hipStream_t s) {
+void launch_plan(const u32* rowptr, const u32* hcnt, const u32* hcur, u32 n, IsectParams p,
+                 u32* lane_x, u32* wave_x, u32* block_x, u32* block_items, Plan* plan,
+                 hipStream_t s) {
   if (n == 0) return;
   const u32 g = min(cdiv(n, 256 * kPlanPer), (u32)num_cus() * 4);
-  hipLaunchKernelGGL(k_plan, dim3(g), dim3(256), 0, s, rowptr, hcnt, n, p, lane_x, wave_x,
-                     block_x, block_items, plan);
+  hipLaunchKernelGGL(k_plan, dim3(g), dim3(256), 0, s, rowptr, hcnt, hcur, n, p, lane_x,
+                     wave_x, block_x, block_items, plan);
 }
 
 __global__ void k_fill_items(const u32* __restrict__ rowptr, const u32* __restrict__ hcnt,

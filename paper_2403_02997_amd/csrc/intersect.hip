@@ -15,33 +15,47 @@
 //   block : larger — one workgroup per (x, chunk of N(x), segment of partners); the
 //           chunk goes into a 128 KB LDS hash set and each wavefront streams one
 //           partner list at a time with 16-byte loads.
+// The counting call runs the pruned forms of the wave and block classes: from the
+// partner records and the level-split rows, x stages only its entries from sabove[x] on
+// and each partner streams only the range of its record, so every common entry is a
+// counted apex and the LDS sets hold IDs without level flags.  The full forms (c1, c2,
+// t2 and per-vertex counts) stage all of N(x) and stream whole rows of colidx.
 #include "tc_isect.h"
 
 namespace tc {
 
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
+// Partner IDs of the full forms: the .w fields of the partner records.
+__device__ __forceinline__ const u32* record_ids(const uint4* hrec) {
+  return reinterpret_cast<const u32*>(hrec) + 3;
+}
+
 // ---- lane class: one thread per staged vertex ---------------------------------------------
 template <bool PV>
 __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
-    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
-    const u32* __restrict__ lane_x, u32 nlx, u64* __restrict__ ctr, u64* __restrict__ tri) {
+    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt,
+    const uint4* __restrict__ hrec, const u32* __restrict__ lane_x, u32 nlx,
+    u64* __restrict__ ctr, u64* __restrict__ tri) {
   __shared__ u64 s_red[5 * (kTileThreads / kWave)];
   Counts c{0, 0, 0, 0, 0};
   const u32 stride = gridDim.x * blockDim.x;
   for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < nlx; t += stride)
-    lane_vertex<PV>(rowptr, 0u, colidx, vinfo, hcnt, hadj, lane_x[t], c, tri);
+    lane_vertex<PV, 4>(rowptr, 0u, colidx, vinfo, hcnt, record_ids(hrec), lane_x[t], c, tri);
   block_flush_counts(c, 0, ctr, s_red);
 }
 
 // ---- wave class: one wavefront per staged vertex x ---------------------------------------
-template <bool PV, bool VEC>
+// REC: the pruned form over the level-split rows (colidx = colidx2, tail4 = its padded
+// last quad); otherwise the full form over colidx.
+template <bool PV, bool VEC, bool REC>
 __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
-    const u32* __restrict__ hcnt, const u32* __restrict__ hadj, const u32* __restrict__ wave_x,
-    u32 nwx, Plan* __restrict__ plan, u64* __restrict__ ctr, u64* __restrict__ tri) {
+    const u32* __restrict__ hcnt, const uint4* __restrict__ hrec,
+    const u32* __restrict__ sabove, const u32* __restrict__ wave_x, u32 nwx,
+    Plan* __restrict__ plan, u64* __restrict__ ctr, u64* __restrict__ tri) {
   constexpr int kW = kIsectThreads / kWave;
   __shared__ __align__(16) u32 s_table[kW][kWaveSlots];
   __shared__ uint4 s_pinfo[kW][kWave];  // {quad base, lo, hi, y} of each compacted partner
@@ -62,8 +76,9 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     }
     if (idx >= nwx) break;
     Tally tl{0, 0, 0, 0};
-    wave_vertex<PV, VEC>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, hadj, wave_x[idx++],
-                         s_table[wid], s_pinfo[wid], s_end[wid], s_mark[wid], tl, c, tri);
+    wave_vertex<PV, VEC, REC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
+                                 hrec, sabove, wave_x[idx++], s_table[wid], s_pinfo[wid],
+                                 s_end[wid], s_mark[wid], tl, c, tri);
     tl.fold(c);
   }
   block_flush_counts(c, 1, ctr, s_red);
@@ -74,10 +89,11 @@ template <bool PV, bool VEC, bool PRUNED>
 __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const u32* __restrict__ colidx2,
-    const u32* __restrict__ split, const u32* __restrict__ tail4b,
-    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
-    const Item* __restrict__ items, u32 nitems, IsectParams prm, Plan* __restrict__ plan,
-    u64* __restrict__ ctr, u64* __restrict__ tri) {
+    const u32* __restrict__ split, const u32* __restrict__ sabove,
+    const u32* __restrict__ tail4b, const uint8_t* __restrict__ vinfo,
+    const u32* __restrict__ hcnt, const uint4* __restrict__ hrec, const Item* __restrict__ items,
+    u32 nitems, IsectParams prm, Plan* __restrict__ plan, u64* __restrict__ ctr,
+    u64* __restrict__ tri) {
   __shared__ __align__(16) u32 s_table[kBigSlots];
   __shared__ u32 s_qincl[kBigSeg];
   __shared__ uint4 s_pinfo[kBigSeg];  // {quad base, lo, hi, y} of each partner
@@ -94,8 +110,13 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32 it = s_item;
     if (it >= nitems) break;
     const Item item = items[it];
-    block_item<PV, VEC, PRUNED>(rowptr, 0u, colidx, m, tail4, colidx2, m, split, tail4b, vinfo,
-                                hcnt, hadj, item.x, item.seg, prm, sh, tl, c, tri);
+    if (PRUNED)
+      block_item_rec<VEC>(rowptr, colidx2, m, tail4b, split, sabove, hcnt, hrec, item.x, item.seg,
+                          prm, sh, tl, c);
+    else
+      block_item<PV, VEC, false, 4>(rowptr, 0u, colidx, m, tail4, colidx2, m, split, tail4b,
+                                    vinfo, hcnt, record_ids(hrec), item.x, item.seg, prm, sh, tl,
+                                    c, tri);
     tl.fold(c);
   }
   block_flush_counts(c, 2, ctr, s_red);
@@ -126,53 +147,60 @@ __global__ void k_finalize(const u64* __restrict__ ctr, u64* __restrict__ out) {
 static u32 resident_blocks(u32 per_cu) { return (u32)num_cus() * per_cu; }
 
 void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
-                       const u32* hcnt, const u32* hadj, const u32* lane_x, u32 nlx, u64* ctr,
-                       u64* tri, hipStream_t s) {
+                       const SplitView& sv, const u32* lane_x, u32 nlx, u64* ctr, u64* tri,
+                       hipStream_t s) {
   if (nlx == 0) return;
   const u32 g = min(cdiv(nlx, kTileThreads), resident_blocks(8));
   if (tri)
     hipLaunchKernelGGL(k_isect_lane<true>, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                       vinfo, hcnt, hadj, lane_x, nlx, ctr, tri);
+                       vinfo, sv.hcnt, sv.hrec, lane_x, nlx, ctr, tri);
   else
     hipLaunchKernelGGL(k_isect_lane<false>, dim3(g), dim3(kTileThreads), 0, s, rowptr, colidx,
-                       vinfo, hcnt, hadj, lane_x, nlx, ctr, tri);
+                       vinfo, sv.hcnt, sv.hrec, lane_x, nlx, ctr, tri);
 }
 
 void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                       const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const u32* wave_x,
-                       u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s) {
+                       const uint8_t* vinfo, const SplitView& sv, const u32* wave_x, u32 nwx,
+                       Plan* plan, u64* ctr, u64* tri, bool pruned, hipStream_t s) {
   if (nwx == 0) return;
   const u32 g = min(cdiv(nwx, kIsectThreads / kWave), resident_blocks(8));
-  const bool vec = ((uintptr_t)colidx & 15u) == 0;
-#define TC_LAUNCH_WAVE(PV, VEC)                                                                \
-  hipLaunchKernelGGL((k_isect_wave<PV, VEC>), dim3(g), dim3(kIsectThreads), 0, s, rowptr,       \
-                     colidx, m, tail4, vinfo, hcnt, hadj, wave_x, nwx, plan, ctr, tri)
+  const bool rec = pruned && !tri;
+  const u32* src = rec ? sv.colidx2 : colidx;  // the streamed and staged rows
+  const u32* tail = rec ? sv.tail4b : tail4;
+  const bool vec = ((uintptr_t)src & 15u) == 0;
+#define TC_LAUNCH_WAVE(PV, VEC, REC)                                                           \
+  hipLaunchKernelGGL((k_isect_wave<PV, VEC, REC>), dim3(g), dim3(kIsectThreads), 0, s, rowptr,  \
+                     src, m, tail, vinfo, sv.hcnt, sv.hrec, sv.sabove, wave_x, nwx, plan, ctr,  \
+                     tri)
   if (tri) {
-    if (vec) TC_LAUNCH_WAVE(true, true);
-    else TC_LAUNCH_WAVE(true, false);
+    if (vec) TC_LAUNCH_WAVE(true, true, false);
+    else TC_LAUNCH_WAVE(true, false, false);
+  } else if (rec) {
+    if (vec) TC_LAUNCH_WAVE(false, true, true);
+    else TC_LAUNCH_WAVE(false, false, true);
   } else {
-    if (vec) TC_LAUNCH_WAVE(false, true);
-    else TC_LAUNCH_WAVE(false, false);
+    if (vec) TC_LAUNCH_WAVE(false, true, false);
+    else TC_LAUNCH_WAVE(false, false, false);
   }
 #undef TC_LAUNCH_WAVE
 }
 
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                        const u32* colidx2, const u32* split, const u32* tail4b,
-                        const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const Item* items,
+                        const uint8_t* vinfo, const SplitView& sv, const Item* items,
                         u32 nitems, IsectParams p, Plan* plan, u64* ctr, u64* tri, bool pruned,
                         hipStream_t s) {
   if (nitems == 0) return;
   const u32 g = min(nitems, resident_blocks(1));
-  const bool vec = ((uintptr_t)colidx & 15u) == 0 && ((uintptr_t)colidx2 & 15u) == 0;
+  const bool rec = pruned && !tri;
+  const bool vec = ((uintptr_t)(rec ? sv.colidx2 : colidx) & 15u) == 0;
 #define TC_LAUNCH_BLOCK(PV, VEC, PR)                                                           \
   hipLaunchKernelGGL((k_isect_block<PV, VEC, PR>), dim3(g), dim3(kBigThreads), 0, s, rowptr,    \
-                     colidx, m, tail4, colidx2, split, tail4b, vinfo, hcnt, hadj, items, nitems, \
-                     p, plan, ctr, tri)
+                     colidx, m, tail4, sv.colidx2, sv.split, sv.sabove, sv.tail4b, vinfo,       \
+                     sv.hcnt, sv.hrec, items, nitems, p, plan, ctr, tri)
   if (tri) {
     if (vec) TC_LAUNCH_BLOCK(true, true, false);
     else TC_LAUNCH_BLOCK(true, false, false);
-  } else if (pruned) {
+  } else if (rec) {
     if (vec) TC_LAUNCH_BLOCK(false, true, true);
     else TC_LAUNCH_BLOCK(false, false, true);
   } else {

@@ -158,17 +158,20 @@ void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n,
 
 // ---- per-vertex info byte ------------------------------------------------------------
 __global__ void k_vinfo(const u32* __restrict__ rowptr, const u32* __restrict__ level, u32 n,
-                        uint8_t* __restrict__ vinfo) {
+                        uint8_t* __restrict__ vinfo, u32* __restrict__ hcur) {
   for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const u32 d = rowptr[v + 1] - rowptr[v];
+    const u32 lo = rowptr[v];
+    const u32 d = rowptr[v + 1] - lo;
     vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | degree_class(d));
+    hcur[v] = lo;
   }
 }
 
-void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, hipStream_t s) {
+void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
+                  hipStream_t s) {
   if (n == 0) return;
   const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
-  hipLaunchKernelGGL(k_vinfo, dim3(g), dim3(256), 0, s, rowptr, level, n, vinfo);
+  hipLaunchKernelGGL(k_vinfo, dim3(g), dim3(256), 0, s, rowptr, level, n, vinfo, hcur);
 }
 
 // ---- device-wide exclusive scan (u32) ------------------------------------------------

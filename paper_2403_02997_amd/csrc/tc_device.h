@@ -213,6 +213,20 @@ __device__ __forceinline__ u32 bucket_check(uint4 v, u32 k2) {
   return mn <= 1u ? 1u + mn : (flagged ? 3u : 0u);
 }
 
+// Membership form of bucket_check for sets built without level flags (every key is
+// w << 1): 1 when present, 3 when absent but flagged, 0 when absent.  An empty slot
+// (all ones, or all ones but the flag bit in the last slot) is odd and never matches.
+__device__ __forceinline__ u32 bucket_has(uint4 v, u32 k2) {
+  const bool hit = v.x == k2 || v.y == k2 || v.z == k2 || (v.w & ~kFlag) == k2;
+  const bool flagged = v.w - kFlag < kInf - kFlag;  // kFlag <= v.w < kInf
+  return hit ? 1u : (flagged ? 3u : 0u);
+}
+
+template <bool MEMBER>
+__device__ __forceinline__ u32 bucket_result(uint4 v, u32 k2) {
+  return MEMBER ? bucket_has(v, k2) : bucket_check(v, k2);
+}
+
 __device__ __forceinline__ u32 hash_probe(const u32* table, u32 bmask, u32 w) {
   const uint4* t4 = reinterpret_cast<const uint4*>(table);
   const u32 k2 = w << 1;
@@ -227,8 +241,9 @@ __device__ __forceinline__ u32 hash_probe(const u32* table, u32 bmask, u32 w) {
 // Probes of N independent keys; res[i] = 0 where !ok[i].  The first bucket of every key
 // is read (always in bounds) before any is examined.  Keys whose bucket was full continue
 // in one wave-uniform loop that resolves one pending key per lane and pass, so the rare
-// overflow costs one bucket check per pass rather than one per key position.
-template <int N>
+// overflow costs one bucket check per pass rather than one per key position.  MEMBER
+// selects the membership check (sets without level flags; results 0 or 1).
+template <int N, bool MEMBER = false>
 __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const u32 (&w)[N],
                                              const bool (&ok)[N], u32 (&res)[N]) {
   const uint4* t4 = reinterpret_cast<const uint4*>(table);
@@ -244,7 +259,7 @@ __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const 
   bool any = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    res[i] = bucket_check(v[i], w[i] << 1) & (0u - (u32)ok[i]);
+    res[i] = bucket_result<MEMBER>(v[i], w[i] << 1) & (0u - (u32)ok[i]);
     any |= res[i] == 3u;
   }
   if (!__ballot(any)) return;
@@ -261,7 +276,7 @@ __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const 
         bi = (u32)j == i ? b[j] : bi;
       }
       bi = (bi + 1) & bmask;
-      const u32 r = bucket_check(t4[bi], wi << 1);
+      const u32 r = bucket_result<MEMBER>(t4[bi], wi << 1);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         if ((u32)j == i) {

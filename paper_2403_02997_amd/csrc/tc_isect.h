@@ -5,6 +5,16 @@
 // arrays (colidx, colidx2, hadj) are indexed absolutely, at cb + a local offset, where
 // cb is the graph's first stored entry (0 for a single graph).  Quads of 16 bytes are
 // aligned to the start of the neighbour array, so per-graph offsets need no alignment.
+// Partner IDs are read as hadj[i * HS]: HS = 1 for a plain partner list, 4 for the
+// .w field of the single-graph partner records (PartnerRec).
+//
+// A partner record (uint4) of cover edge {x, y}, stored under x, holds absolute offsets
+// into the level-split rows: .x = the first same-level neighbour of y above max(x, y),
+// .y = the start of y's other-level neighbours, .z = the end of y's row, .w = y.  The
+// apex rule counts exactly the common neighbours of x and y in y's entries .x .. .z
+// that are other-level or above x, which are the entries of x's row from sabove[x] on
+// (its same-level neighbours above x, then its other-level ones): every hit of the two
+// ranges is one counted apex, so the pruned passes need membership only.
 #pragma once
 
 #include "tc_device.h"
@@ -25,7 +35,7 @@ constexpr int kQuadUnroll = 4;     // windows per wavefront loaded before probin
 static_assert(kBigSlots == kBigWaves * kWaveSlots, "the wavefront tables share the big table");
 
 // ---- lane class: one thread merges N(x) with each partner's list ---------------------
-template <bool PV>
+template <bool PV, int HS = 1>
 __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 cb,
                                             const u32* __restrict__ colidx,
                                             const uint8_t* __restrict__ vinfo,
@@ -35,7 +45,7 @@ __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 
   const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1], np = hcnt[x];
   const u32 px = vinfo[x] & 0x80u;
   for (u32 q = 0; q < np; ++q) {
-    const u32 y = hadj[bx + q];
+    const u32 y = hadj[(size_t)(bx + q) * HS];
     u32 i = bx, j = cb + rowptr[y];
     const u32 je = cb + rowptr[y + 1];
     c.probes += je - j;
@@ -69,16 +79,24 @@ __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 
 // The partner of a quad comes from the partners' quad ends: those inside the current
 // windows mark their positions in LDS, and a ballot plus a population count gives every
 // lane its partner.  pinfo / pend / mark are the wavefront's 64-entry LDS arrays.
-template <bool PV, bool VEC>
+// REC = false: the full form (N(x) with level flags against each partner's whole row of
+// colidx; c1, c2, t2).  REC = true: the pruned form over the level-split rows (colidx
+// is then colidx2): x's entries from sabove[x] on against each partner record's range,
+// membership only; every hit goes to s.
+template <bool PV, bool VEC, bool REC = false, int HS = 1>
 __device__ __forceinline__ void wave_vertex(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
-    const u32* __restrict__ hcnt, const u32* __restrict__ hadj, u32 x, u32* table,
+    const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
+    const uint4* __restrict__ hrec, const u32* __restrict__ sabove, u32 x, u32* table,
     uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c, u64* __restrict__ tri) {
+  static_assert(!(REC && PV), "per-vertex counts use the full form");
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
   const u32 lane = lane_id();
   const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
-  const u32 bx = cb + rowptr[x], dx = cb + rowptr[x + 1] - bx;
+  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
+  const u32 sb = REC ? sabove[x] : bx;  // first staged entry
+  const u32 dx = ex - sb;
   const u32 hs = bx, np = hcnt[x];  // H+(x) sits in place of N(x)
   const u32 px = vinfo[x] & 0x80u;
   const u32 mask = bucket_mask(dx, kWaveSlots);
@@ -86,8 +104,8 @@ __device__ __forceinline__ void wave_vertex(
   for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
   wave_lds_sync();
   for (u32 i = lane; i < dx; i += kWave) {
-    const u32 w = colidx[bx + i];
-    const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
+    const u32 w = colidx[sb + i];
+    const u32 same = !REC && ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
     hash_insert(table, mask, w, same);
   }
   wave_lds_sync();
@@ -95,9 +113,16 @@ __device__ __forceinline__ void wave_vertex(
     const u32 p = pb + lane;
     u32 y = 0, lo = 0, hi = 0;
     if (p < np) {
-      y = hadj[hs + p];
-      lo = cb + rowptr[y];
-      hi = cb + rowptr[y + 1];
+      if (REC) {
+        const uint4 r = hrec[hs + p];
+        y = r.w;
+        lo = r.x;
+        hi = r.z;
+      } else {
+        y = hadj[(size_t)(hs + p) * HS];
+        lo = cb + rowptr[y];
+        hi = cb + rowptr[y + 1];
+      }
     }
     tl.probes += hi - lo;
     const u32 qa = VEC ? (lo & ~3u) : lo;
@@ -161,11 +186,15 @@ __device__ __forceinline__ void wave_vertex(
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
         u32 res[NE];
-        hash_probe_n<NE>(table, mask, e[u], ok, res);
+        hash_probe_n<NE, REC>(table, mask, e[u], ok, res);
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) {
-          tl.add(res[i], e[u][i], vmax);
-          if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+          if (REC) {
+            tl.s += res[i];
+          } else {
+            tl.add(res[i], e[u][i], vmax);
+            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+          }
         }
       }
     }
@@ -192,10 +221,13 @@ __device__ __forceinline__ void wave_vertex(
 //               range of the level-split rows); c1 and t2;
 //   kOther    : the other-level part of N(x); each partner's other-level part; c1;
 //   kSame     : the same-level part of N(x) above x; each partner's same-level part
-//               above max(x, y); t2 (every hit is a same-level apex above both ends).
+//               above max(x, y); t2 (every hit is a same-level apex above both ends);
+//   kMember   : x's entries from sabove[x] on in one chunk; each partner record's range;
+//               s (every hit is a counted apex).
 // A same-level apex w <= max(x, y) is never counted (the apex rule), so the pruned
-// passes skip those list entries entirely and leave c2 uncounted.
-enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3 };
+// passes skip those list entries entirely and leave c2 uncounted.  kOther, kSame and
+// kMember stage without level flags and probe for membership only.
+enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3, kMember = 4 };
 
 struct BlockShared {
   u32* table;
@@ -220,6 +252,7 @@ __device__ __forceinline__ void block_pass(
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
   const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   static_assert(!BM || MODE == kOther || MODE == kSame, "bitmaps hold membership only");
+  constexpr bool MEMBER = MODE == kOther || MODE == kSame || MODE == kMember;
   const u32 glen = ge - gs;
   // hash chunks by count, or bitmap windows by ID
   const u32 w_first = BM && glen ? ga[gs] >> kWinBits : 0u;
@@ -345,7 +378,7 @@ __device__ __forceinline__ void block_pass(
             res[i] = in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
           }
         } else {
-          hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
+          hash_probe_n<NE, MEMBER>(sh.table, mask, e[u], ok, res);
         }
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) {
@@ -355,7 +388,7 @@ __device__ __forceinline__ void block_pass(
           } else if (MODE == kPrunedOne) {
             tl.s += res[i] & 1u;  // other-level apex (c1)
             tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
-          } else if (MODE == kOther) {
+          } else if (MODE == kOther || MODE == kMember) {
             tl.s += res[i];
           } else {
             tl.t2 += res[i];
@@ -382,7 +415,7 @@ __device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32
 // colidx2 (split[v] = local start of v's other-level neighbours), one kPrunedOne pass
 // when N(x) fits one chunk, else a kOther and a kSame pass.  m / m2 bound the quad loads
 // from colidx / colidx2 (beyond them the padded copies tail4 / tail4b are read).
-template <bool PV, bool VEC, bool PRUNED>
+template <bool PV, bool VEC, bool PRUNED, int HS = 1>
 __device__ __forceinline__ void block_item(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const u32* __restrict__ colidx2, u32 m2,
@@ -397,7 +430,7 @@ __device__ __forceinline__ void block_item(
   const u32 pn = min(prm.seg, hcnt[x] - seg * prm.seg);
   u32 y = 0, yr = 0, ye = 0;
   if (tid < pn) {
-    y = hadj[hs + tid];
+    y = hadj[(size_t)(hs + tid) * HS];
     yr = cb + rowptr[y];
     ye = cb + rowptr[y + 1];
   }
@@ -430,6 +463,44 @@ __device__ __forceinline__ void block_item(
         block_pass<false, VEC, kSame, false>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo, x, px, y,
                                              pn, lb, ys, prm, sh, tl, c, tri);
     }
+  }
+}
+
+// One work item from partner records (single graph, counting only): x's entries from
+// sabove[x] on are staged once, membership only.  When they fit one chunk, one kMember
+// pass streams each record's range .x .. .z; otherwise a kOther pass (x's other-level
+// part against .y .. .z) and a kSame pass (x's same-level part above x against
+// .x .. .y), each with hash chunks or bitmap windows, whichever takes fewer passes.
+template <bool VEC>
+__device__ __forceinline__ void block_item_rec(
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx2, u32 m2,
+    const u32* __restrict__ tail4b, const u32* __restrict__ split,
+    const u32* __restrict__ sabove, const u32* __restrict__ hcnt,
+    const uint4* __restrict__ hrec, u32 x, u32 seg, IsectParams prm, const BlockShared& sh,
+    Tally& tl, Counts& c) {
+  const u32 tid = threadIdx.x;
+  const u32 bx = rowptr[x], ex = rowptr[x + 1];
+  const u32 gx = sabove[x], sx = split[x];
+  const u32 hs = bx + seg * prm.seg;  // the records sit in place of N(x)
+  const u32 pn = min(prm.seg, hcnt[x] - seg * prm.seg);
+  uint4 r = make_uint4(0, 0, 0, 0);
+  if (tid < pn) r = hrec[hs + tid];
+  if (ex - gx <= prm.chunk) {
+    block_pass<false, VEC, kMember, false>(colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0,
+                                           r.w, pn, r.x, r.z, prm, sh, tl, c, nullptr);
+  } else {
+    if (use_bitmap(colidx2, sx, ex, prm.chunk))
+      block_pass<false, VEC, kOther, true>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
+                                           r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
+    else
+      block_pass<false, VEC, kOther, false>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
+                                            r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
+    if (use_bitmap(colidx2, gx, sx, prm.chunk))
+      block_pass<false, VEC, kSame, true>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
+                                          r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
+    else
+      block_pass<false, VEC, kSame, false>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
+                                           r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
   }
 }
 

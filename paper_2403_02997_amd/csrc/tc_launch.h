@@ -41,6 +41,7 @@ struct Plan {
   u32 next_item;
   u32 num_long;     // rows split by a whole workgroup, and their work counter
   u32 next_long;
+  u32 bad_records;  // vertices whose record cursor disagrees with hcnt (broken contract)
 };
 
 struct Item {
@@ -53,7 +54,9 @@ void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_
 // device word of scratch.
 void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
                u32* parent, u32* mode, hipStream_t s);
-void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, hipStream_t s);
+// vinfo[v] = (L(v) mod 2) << 7 | degree class; hcur[v] = rowptr[v] (the record cursors).
+void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
+                  hipStream_t s);
 // Exclusive scan of in[0..count) into out[0..count] (out[count] = total); in may == out.
 // tmp needs scan_tmp_words(count) words.
 size_t scan_tmp_words(u32 count);
@@ -72,31 +75,44 @@ u32 bfs_grid(u32 n);
 
 // ---- cover-edge extraction ----
 // Per vertex v: colidx2[rowptr[v] .. split[v]) = neighbours on v's level (ascending),
-// colidx2[split[v] .. rowptr[v + 1]) = the others (ascending), and the partner list
-// H+(v) = hadj[rowptr[v] .. rowptr[v] + hcnt[v]).  colidx2 and hadj hold m entries.
-// long_rows: n words of scratch; counters: two words, zeroed before the launch.
-void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n,
-                       u32* colidx2, u32* split, u32* hcnt, u32* hadj, u32* long_rows,
-                       u32* counters, hipStream_t s);
-void launch_plan(const u32* rowptr, const u32* hcnt, u32 n, IsectParams p, u32* lane_x,
-                 u32* wave_x, u32* block_x, u32* block_items, Plan* plan, hipStream_t s);
+// colidx2[split[v] .. rowptr[v + 1]) = the others (ascending), sabove[v] = the first of
+// the former above v, hcnt[v] = |H+(v)|, and the partner records of H+(v) at
+// hrec[rowptr[v] .. rowptr[v] + hcnt[v]) (absolute offsets into colidx2; .w = partner).
+// colidx2 and hrec hold m entries; hcur comes from launch_vinfo.  long_rows: n words of
+// scratch; counters: two words, zeroed before the launch.
+void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n, u32 m,
+                       u32* colidx2, u32* split, u32* sabove, u32* hcnt, u32* hcur, uint4* hrec,
+                       u32* long_rows, u32* counters, hipStream_t s);
+// Also counts in plan->bad_records the vertices with hcur[v] != rowptr[v] + hcnt[v].
+void launch_plan(const u32* rowptr, const u32* hcnt, const u32* hcur, u32 n, IsectParams p,
+                 u32* lane_x, u32* wave_x, u32* block_x, u32* block_items, Plan* plan,
+                 hipStream_t s);
 void launch_fill_items(const u32* rowptr, const u32* hcnt, const u32* block_x,
                        const u32* item_off, u32 nbx, IsectParams p, Item* items,
                        hipStream_t s);
 
 // ---- intersection ----
+// The intersection launchers take the split's outputs in one struct.  pruned: count
+// only T (in the c1 slot), from the level-split rows and the partner records (tail4b
+// is the padded last quad of colidx2); otherwise c1, c2 and t2 from colidx, with the
+// partners read from the records' .w fields.
+struct SplitView {
+  const u32* colidx2;
+  const u32* split;
+  const u32* sabove;
+  const u32* hcnt;
+  const uint4* hrec;
+  const u32* tail4b;
+};
 void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinfo,
-                       const u32* hcnt, const u32* hadj, const u32* lane_x, u32 nlx, u64* ctr,
-                       u64* tri, hipStream_t s);
+                       const SplitView& sv, const u32* lane_x, u32 nlx, u64* ctr, u64* tri,
+                       hipStream_t s);
 void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                       const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const u32* wave_x,
-                       u32 nwx, Plan* plan, u64* ctr, u64* tri, hipStream_t s);
+                       const uint8_t* vinfo, const SplitView& sv, const u32* wave_x, u32 nwx,
+                       Plan* plan, u64* ctr, u64* tri, bool pruned, hipStream_t s);
 void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s);
-// pruned: count c1 and t2 only, from the level-split rows colidx2 / split (tail4b is
-// the padded last quad of colidx2); otherwise c1, c2 and t2 from colidx.
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
-                        const u32* colidx2, const u32* split, const u32* tail4b,
-                        const uint8_t* vinfo, const u32* hcnt, const u32* hadj, const Item* items,
+                        const uint8_t* vinfo, const SplitView& sv, const Item* items,
                         u32 nitems, IsectParams p, Plan* plan, u64* ctr, u64* tri, bool pruned,
                         hipStream_t s);
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);

@@ -182,3 +182,16 @@ def test_validate_accepts_and_rejects(tc_lib):
     r3 = g.rowptr.copy(); r3[-1] -= 1; bad.append((r3, g.colidx))        # rowptr[n] != m
     for rp, ci in bad:
         assert tc_lib.tc_validate_csr(*tc_lib.to_device(rp, ci)) == -4
+
+
+def test_count_reports_same_level_asymmetry(tc_lib):
+    """Star centre 0 with leaves 1..4, the entry 0 of leaf 4's row replaced by 2: 4 lists 2
+    as a same-level partner, 2 does not list 4, so 4's partner records stay short and the
+    count stops with TC_ERR_INVALID_GRAPH before any intersection."""
+    say("[parity] asymmetric same-level entry")
+    s = gg.star(5)
+    x = s.colidx.copy()
+    x[-1] = 2
+    with pytest.raises(tc_lib.TCError) as e:
+        tc_lib.tc_count(*tc_lib.to_device(s.rowptr, x))
+    assert e.value.status == -4
