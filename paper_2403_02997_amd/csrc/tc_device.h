@@ -190,8 +190,9 @@ __device__ __forceinline__ u32 bucket_mask(u32 keys, u32 cap_slots) {
 // buckets, and bits 13 and up are folded onto them.
 __device__ __forceinline__ u32 hash_mix(u32 w) { return w ^ (w >> 13); }
 
-__device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 w, u32 same) {
-  const u32 key = (w << 1) | same;
+// Inserts key (derived from w: (w << 1) | level flag, or w itself in membership sets)
+// into the bucket chain of w.
+__device__ __forceinline__ void hash_insert_key(u32* table, u32 bmask, u32 w, u32 key) {
   u32 b = hash_mix(w) & bmask;
   while (true) {
 #pragma unroll
@@ -200,6 +201,10 @@ __device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 w, u32 sa
     atomicOr(&table[4 * b + 3], kFlag);  // the bucket is full: probes must go on
     b = (b + 1) & bmask;
   }
+}
+
+__device__ __forceinline__ void hash_insert(u32* table, u32 bmask, u32 w, u32 same) {
+  hash_insert_key(table, bmask, w, (w << 1) | same);
 }
 
 // Bucket v against k2 = w << 1: 1 when w is present on another level, 2 on the owner's
@@ -285,6 +290,60 @@ __device__ __forceinline__ void hash_probe_n(const u32* table, u32 bmask, const 
         }
       }
       if (r != 3u) pend &= pend - 1;
+    }
+  }
+}
+
+// Membership probes of N independent keys against a set of plain IDs (built with
+// hash_insert_key(.., w, w)); adds to hits the number of this lane's keys with ok[i]
+// that are present.  Keys whose first bucket was full and flagged continue bucket by
+// bucket in a rare wavefront-uniform loop.  An empty slot (all ones, or all ones but
+// the flag bit) never equals an ID below 2^30.
+__device__ __forceinline__ bool bucket_holds(uint4 v, u32 w) {
+  return v.x == w || v.y == w || v.z == w || (v.w & ~kFlag) == w;
+}
+__device__ __forceinline__ bool bucket_flagged(uint4 v) { return v.w - kFlag < kInf - kFlag; }
+
+template <int N>
+__device__ __forceinline__ void hash_count_n(const u32* table, u32 bmask, const u32 (&w)[N],
+                                             const bool (&ok)[N], u32& hits) {
+  const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  uint4 v[N];
+  u32 b[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    b[i] = hash_mix(w[i]) & bmask;
+    v[i] = t4[b[i]];
+  }
+  bool more = false;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const bool hit = bucket_holds(v[i], w[i]);
+    hits += ok[i] && hit ? 1u : 0u;
+    more |= ok[i] && !hit && bucket_flagged(v[i]);
+  }
+  if (!__ballot(more)) return;
+  u32 pend = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    pend |= (ok[i] && !bucket_holds(v[i], w[i]) && bucket_flagged(v[i]) ? 1u : 0u) << i;
+  while (__ballot(pend != 0)) {
+    if (pend) {
+      const u32 i = __ffs(pend) - 1;
+      u32 wi = w[0], bi = b[0];
+#pragma unroll
+      for (int j = 1; j < N; ++j) {
+        wi = (u32)j == i ? w[j] : wi;
+        bi = (u32)j == i ? b[j] : bi;
+      }
+      bi = (bi + 1) & bmask;
+      const uint4 vv = t4[bi];
+      const bool hit = bucket_holds(vv, wi);
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if ((u32)j == i) b[j] = bi;
+      hits += hit ? 1u : 0u;
+      if (hit || !bucket_flagged(vv)) pend &= pend - 1;
     }
   }
 }

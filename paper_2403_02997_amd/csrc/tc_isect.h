@@ -105,8 +105,12 @@ __device__ __forceinline__ void wave_vertex(
   wave_lds_sync();
   for (u32 i = lane; i < dx; i += kWave) {
     const u32 w = colidx[sb + i];
-    const u32 same = !REC && ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
-    hash_insert(table, mask, w, same);
+    if (REC) {
+      hash_insert_key(table, mask, w, w);
+    } else {
+      const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
+      hash_insert(table, mask, w, same);
+    }
   }
   wave_lds_sync();
   for (u32 pb = 0; pb < np; pb += kWave) {
@@ -185,13 +189,13 @@ __device__ __forceinline__ void wave_vertex(
         bool ok[NE];
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
-        u32 res[NE];
-        hash_probe_n<NE, REC>(table, mask, e[u], ok, res);
+        if (REC) {
+          hash_count_n<NE>(table, mask, e[u], ok, tl.s);
+        } else {
+          u32 res[NE];
+          hash_probe_n<NE>(table, mask, e[u], ok, res);
 #pragma unroll
-        for (u32 i = 0; i < NE; ++i) {
-          if (REC) {
-            tl.s += res[i];
-          } else {
+          for (u32 i = 0; i < NE; ++i) {
             tl.add(res[i], e[u][i], vmax);
             if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
           }
@@ -219,14 +223,15 @@ __device__ __forceinline__ void wave_vertex(
 //   kPrunedOne: N(x) with level flags in one chunk; each partner's same-level
 //               neighbours above max(x, y) and its other-level ones (one contiguous
 //               range of the level-split rows); c1 and t2;
-//   kOther    : the other-level part of N(x); each partner's other-level part; c1;
+//   kOther    : the other-level part of N(x); each partner's other-level part (hits
+//               are the other-level apexes);
 //   kSame     : the same-level part of N(x) above x; each partner's same-level part
-//               above max(x, y); t2 (every hit is a same-level apex above both ends);
-//   kMember   : x's entries from sabove[x] on in one chunk; each partner record's range;
-//               s (every hit is a counted apex).
+//               above max(x, y) (hits are the same-level apexes above both ends);
+//   kMember   : x's entries from sabove[x] on in one chunk; each partner record's range
+//               (hits are the counted apexes of both kinds).
 // A same-level apex w <= max(x, y) is never counted (the apex rule), so the pruned
 // passes skip those list entries entirely and leave c2 uncounted.  kOther, kSame and
-// kMember stage without level flags and probe for membership only.
+// kMember stage plain IDs, probe for membership only and add their hits to s.
 enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3, kMember = 4 };
 
 struct BlockShared {
@@ -300,8 +305,12 @@ __device__ __forceinline__ void block_pass(
     } else {
       for (u32 i = tid; i < clen; i += blockDim.x) {
         const u32 w = ga[c0 + i];
-        const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
-        hash_insert(sh.table, mask, w, same ? 1u : 0u);
+        if (MEMBER) {
+          hash_insert_key(sh.table, mask, w, w);
+        } else {
+          const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
+          hash_insert(sh.table, mask, w, same ? 1u : 0u);
+        }
       }
     }
     __syncthreads();
@@ -367,7 +376,6 @@ __device__ __forceinline__ void block_pass(
         bool ok[NE];
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
-        u32 res[NE];
         if (BM) {
           // elements of earlier, skipped windows fall outside [wb, wb + 2^kWinBits)
 #pragma unroll
@@ -375,23 +383,22 @@ __device__ __forceinline__ void block_pass(
             const u32 k = e[u][i] - wb;
             const bool in = ok[i] && k < (1u << kWinBits);
             const u32 kk = in ? k : 0u;
-            res[i] = in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
+            tl.s += in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
           }
+        } else if (MEMBER) {
+          hash_count_n<NE>(sh.table, mask, e[u], ok, tl.s);
         } else {
-          hash_probe_n<NE, MEMBER>(sh.table, mask, e[u], ok, res);
-        }
+          u32 res[NE];
+          hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
 #pragma unroll
-        for (u32 i = 0; i < NE; ++i) {
-          if (MODE == kFull) {
-            tl.add(res[i], e[u][i], vmax);
-            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
-          } else if (MODE == kPrunedOne) {
-            tl.s += res[i] & 1u;  // other-level apex (c1)
-            tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
-          } else if (MODE == kOther || MODE == kMember) {
-            tl.s += res[i];
-          } else {
-            tl.t2 += res[i];
+          for (u32 i = 0; i < NE; ++i) {
+            if (MODE == kFull) {
+              tl.add(res[i], e[u][i], vmax);
+              if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+            } else {
+              tl.s += res[i] & 1u;  // other-level apex (c1)
+              tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
+            }
           }
         }
       }
