@@ -180,6 +180,8 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u32>(n);                  // queue0
     c.take<u32>(n);                  // queue1
     c.take<u32>(3 * (((size_t)n + 31) / 32));  // frontier bitmaps
+    c.take<u64>(bfs_part_words());   // per-workgroup BFS level totals
+    c.take<u32>(2 * bfs_big_cap(n, m));  // queues of big frontier vertices
     c.take<uint8_t>(n);              // vinfo
     c.take<u32>(n);                  // hcnt
     c.take<u32>(n);                  // split
@@ -212,6 +214,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u32* q1 = c.take<u32>(n);
   const size_t fb_words = 3 * (((size_t)n + 31) / 32);
   u32* fb = c.take<u32>(fb_words);
+  u64* bfs_part = c.take<u64>(bfs_part_words());
+  u32* bigq0 = c.take<u32>(2 * bfs_big_cap(n, m));
+  u32* bigq1 = bigq0 + bfs_big_cap(n, m);
   uint8_t* vinfo = c.take<uint8_t>(n);
   u32* hcnt = c.take<u32>(n);
   u32* split = c.take<u32>(n);
@@ -248,13 +253,15 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
 
   // ---- a2: level BFS ----
   timer.mark();
-  launch_bfs_init(rowptr, parent, n, level, q0, fb, ctl, s);
+  launch_bfs_init(rowptr, parent, n, level, q0, bigq0, fb, ctl, s);
   TC_LAUNCHED();
   {
     const u32 grid = bfs_grid(n);
     u32 k = 0, batch = 4;
     while (true) {
-      for (u32 i = 0; i < batch; ++i) launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, fb, ctl, grid, s);
+      for (u32 i = 0; i < batch; ++i)
+        launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, bigq0, bigq1, fb, ctl, bfs_part,
+                         grid, s);
       TC_LAUNCHED();
       k += batch;
       u32 done = 0;

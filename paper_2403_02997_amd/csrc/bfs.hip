@@ -10,6 +10,15 @@
 // m_u / 14 (m_u = edges of unvisited vertices), bottom-up until the frontier shrinks
 // below n / 24.  The last block of each level takes that decision on the device, so the
 // host enqueues many levels without waiting and only polls `done` between batches.
+// Blocks leave their totals in their own slots of `part` and take one ticket atomic;
+// the last block sums the slots with all its threads.
+//
+// Top-down levels expand the frontier queue, short lists per lane and lists of up to
+// kBfsBig entries per wavefront; longer lists are also kept in a small queue of big
+// vertices, whose lists every workgroup shares in kBfsChunk-entry pieces, so that one
+// hub on the frontier does not leave its whole list to a single wavefront.  Bottom-up
+// levels test the first four entries of every unvisited row together before any row
+// goes on, so most vertices find their parent in two memory round trips.
 // Each level's frontier is also kept as a bitmap (n bits, small enough to stay in the
 // L2): bottom-up steps test neighbours against it instead of gathering their levels.
 // Three bitmaps rotate: level k reads bitmap k mod 3, fills (k + 1) mod 3 and clears
@@ -22,8 +31,12 @@ namespace tc {
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
 constexpr int kBfsThreads = 256;
-constexpr u32 kBfsLaneMax = 32;  // frontier vertices up to this degree expand per lane
-constexpr u32 kBfsPer = 8;       // vertices per thread and pass in the vertex sweeps
+constexpr u32 kBfsLaneMax = 32;    // top-down: frontier lists up to this length per lane
+constexpr u32 kBfsBig = 1024;      // top-down: longer frontier lists are shared by the grid
+constexpr u32 kBfsChunk = 1024;    // entries of a big list per workgroup task
+constexpr u32 kBfsVisit = 4;       // top-down: neighbours per lane claimed together
+constexpr u32 kBfsPer = 8;         // vertices per thread and pass in the vertex sweeps
+constexpr u32 kBfsBlocksPerCu = 2;
 
 // Stores the frontier bits of 32 consecutive vertices v0 .. v0 + 31 handled by one half
 // of a wavefront (v0 a multiple of 32), which no other thread writes in this sweep.
@@ -37,6 +50,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict_
                                                           const u32* __restrict__ parent, u32 n,
                                                           u32* __restrict__ level,
                                                           u32* __restrict__ queue0,
+                                                          u32* __restrict__ bigq0,
                                                           u32* __restrict__ fb0,
                                                           BfsCtl* __restrict__ ctl) {
   __shared__ u32 s_tmp[kBfsThreads / kWave];
@@ -58,6 +72,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict_
         if (root && d > 0) {
           bits |= 1u << k;
           ++cnt;
+          if (d > kBfsBig) bigq0[atomicAdd(&ctl->bqlen[0], 1u)] = v;
         }
       }
       store_bits_half(fb0, v, (bits >> k) & 1u, n);
@@ -100,24 +115,72 @@ __device__ __forceinline__ bool bfs_claim(u32* level, u32 y, u32 next) {
   return atomicCAS(&level[y], kInf, next) == kInf;
 }
 
+// Where a level's output goes: the next frontier queue (and its length), the queue of
+// big vertices among it, and the next frontier bitmap.
+struct BfsOut {
+  u32* q;
+  u32* qlen;
+  u32* bq;
+  u32* bqlen;
+  u32* bits;
+};
+
+// Top-down visit of the neighbours y[i] with act[i] of every lane; all lanes of the
+// wavefront call it together.  Their level loads, then their claims, are issued
+// together, and the claimed ones join the next frontier with one queue atomic per
+// wavefront.
+__device__ __forceinline__ void td_visit(const u32 (&y)[kBfsVisit], const bool (&act)[kBfsVisit],
+                                         u32 next, const u32* __restrict__ rowptr,
+                                         u32* __restrict__ level, const BfsOut& o, u64& mf,
+                                         u64& mu_dec) {
+  u32 lv[kBfsVisit];
+#pragma unroll
+  for (u32 i = 0; i < kBfsVisit; ++i) lv[i] = act[i] ? load_coherent(&level[y[i]]) : 0u;
+  bool cl[kBfsVisit];
+  u32 cnt = 0;
+#pragma unroll
+  for (u32 i = 0; i < kBfsVisit; ++i) {
+    cl[i] = act[i] && lv[i] == kInf && atomicCAS(&level[y[i]], kInf, next) == kInf;
+    cnt += cl[i] ? 1u : 0u;
+  }
+  const u32 incl = wave_incl_scan(cnt);
+  const u32 total = __shfl(incl, kWave - 1, kWave);
+  if (total == 0) return;  // uniform
+  u32 base = 0;
+  if (lane_id() == 0) base = atomicAdd(o.qlen, total);
+  u32 pos = __shfl(base, 0, kWave) + incl - cnt;
+#pragma unroll
+  for (u32 i = 0; i < kBfsVisit; ++i) {
+    if (cl[i]) {
+      o.q[pos++] = y[i];
+      atomicOr(&o.bits[y[i] >> 5], 1u << (y[i] & 31));
+      const u32 dy = rowptr[y[i] + 1] - rowptr[y[i]];
+      mf += dy;
+      mu_dec += dy;
+      if (dy > kBfsBig) o.bq[atomicAdd(o.bqlen, 1u)] = y[i];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 n, u32 k,
     u32* __restrict__ level, u32* __restrict__ queue0, u32* __restrict__ queue1,
-    u32* __restrict__ fb, BfsCtl* __restrict__ ctl) {
+    u32* __restrict__ bigq0, u32* __restrict__ bigq1, u32* __restrict__ fb,
+    BfsCtl* __restrict__ ctl, u64* __restrict__ part) {
   __shared__ u64 s_red[2 * (kBfsThreads / kWave)];
   __shared__ bool s_last;
   if (load_coherent(&ctl->done)) return;  // uniform across the grid
   const u32 mode = load_coherent(&ctl->mode);
   const u32* qin = (k & 1) ? queue1 : queue0;
-  u32* qout = (k & 1) ? queue0 : queue1;
-  u32* qlen_out = &ctl->qlen[(k + 1) & 1];
+  const u32* bqin = (k & 1) ? bigq1 : bigq0;
   const u32 next = k + 1;
+  const u32 nw = (n + 31) / 32;
+  const u32* fcur = fb + (k % 3) * (size_t)nw;
+  const BfsOut o{(k & 1) ? queue0 : queue1, &ctl->qlen[(k + 1) & 1], (k & 1) ? bigq0 : bigq1,
+                 &ctl->bqlen[(k + 1) & 1], fb + ((k + 1) % 3) * (size_t)nw};
   u64 mf = 0, mu_dec = 0;
   const u32 lane = lane_id();
   const u32 stride = gridDim.x * blockDim.x;
-  const u32 nw = (n + 31) / 32;
-  const u32* fcur = fb + (k % 3) * (size_t)nw;
-  u32* fnext = fb + ((k + 1) % 3) * (size_t)nw;
   u32* fold = fb + ((k + 2) % 3) * (size_t)nw;
   for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) fold[i] = 0;
 
@@ -131,6 +194,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
         x = qin[i];
         lo = rowptr[x];
         d = rowptr[x + 1] - lo;
+        if (d > kBfsBig) d = 0;  // shared by the grid below
       }
       const bool big = d > kBfsLaneMax;
       // small frontier vertices: each lane walks its own list in lockstep
@@ -138,44 +202,54 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
       u32 dmax = dl;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, (u32)__shfl_xor(dmax, off, kWave));
-      for (u32 j = 0; j < dmax; ++j) {
-        bool claimed = false;
-        u32 y = 0;
-        if (j < dl) {
-          y = colidx[lo + j];
-          claimed = bfs_claim(level, y, next);
+      for (u32 j = 0; j < dmax; j += kBfsVisit) {
+        u32 y[kBfsVisit];
+        bool act[kBfsVisit];
+#pragma unroll
+        for (u32 i = 0; i < kBfsVisit; ++i) {
+          act[i] = j + i < dl;
+          y[i] = act[i] ? colidx[lo + j + i] : 0u;
         }
-        const u32 pos = wave_append(qlen_out, claimed);
-        if (claimed) {
-          qout[pos] = y;
-          atomicOr(&fnext[y >> 5], 1u << (y & 31));
-          const u32 dy = rowptr[y + 1] - rowptr[y];
-          mf += dy;
-          mu_dec += dy;
-        }
+        td_visit(y, act, next, rowptr, level, o, mf, mu_dec);
       }
-      // large frontier vertices: the whole wavefront strides each list
+      // larger frontier vertices: the whole wavefront strides each list
       u64 bigmask = __ballot(big);
       while (bigmask) {
         const int b = __ffsll((unsigned long long)bigmask) - 1;
         bigmask &= bigmask - 1;
         const u32 blo = __shfl(lo, b, kWave), bd = __shfl(d, b, kWave);
-        for (u32 j0 = 0; j0 < bd; j0 += kWave) {
-          const u32 j = j0 + lane;
-          bool claimed = false;
-          u32 y = 0;
-          if (j < bd) {
-            y = colidx[blo + j];
-            claimed = bfs_claim(level, y, next);
+        for (u32 j0 = 0; j0 < bd; j0 += kWave * kBfsVisit) {
+          u32 y[kBfsVisit];
+          bool act[kBfsVisit];
+#pragma unroll
+          for (u32 i = 0; i < kBfsVisit; ++i) {
+            const u32 j = j0 + i * kWave + lane;
+            act[i] = j < bd;
+            y[i] = act[i] ? colidx[blo + j] : 0u;
           }
-          const u32 pos = wave_append(qlen_out, claimed);
-          if (claimed) {
-            qout[pos] = y;
-            atomicOr(&fnext[y >> 5], 1u << (y & 31));
-            const u32 dy = rowptr[y + 1] - rowptr[y];
-            mf += dy;
-            mu_dec += dy;
+          td_visit(y, act, next, rowptr, level, o, mf, mu_dec);
+        }
+      }
+    }
+    // big frontier vertices: piece c of the bi-th list goes to workgroup (c + 131 bi) % grid
+    const u32 nb = load_coherent(&ctl->bqlen[k & 1]);
+    for (u32 bi = 0; bi < nb; ++bi) {
+      const u32 x = bqin[bi];
+      const u32 lo = rowptr[x], d = rowptr[x + 1] - lo;
+      const u32 nch = (d + kBfsChunk - 1) / kBfsChunk;
+      const u32 shift = (u32)(((u64)bi * 131u) % gridDim.x);
+      for (u32 c = (blockIdx.x + gridDim.x - shift) % gridDim.x; c < nch; c += gridDim.x) {
+        const u32 ce = min(d, (c + 1) * kBfsChunk);
+        for (u32 j0 = c * kBfsChunk; j0 < ce; j0 += blockDim.x * kBfsVisit) {
+          u32 y[kBfsVisit];
+          bool act[kBfsVisit];
+#pragma unroll
+          for (u32 i = 0; i < kBfsVisit; ++i) {
+            const u32 j = j0 + i * blockDim.x + threadIdx.x;
+            act[i] = j < ce;
+            y[i] = act[i] ? colidx[lo + j] : 0u;
           }
+          td_visit(y, act, next, rowptr, level, o, mf, mu_dec);
         }
       }
     }
@@ -185,62 +259,92 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
     __shared__ u32 s_base;
     const u32 span = kBfsPer * blockDim.x;
     for (u32 base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+      u32 lo[kBfsPer], d[kBfsPer];
+      u32 act = 0;  // bit kk: vertex kk is unvisited
+#pragma unroll
+      for (u32 kk = 0; kk < kBfsPer; ++kk) {
+        const u32 v = base + kk * blockDim.x + threadIdx.x;
+        lo[kk] = 0;
+        d[kk] = 0;
+        if (v < n) {
+          const u32 lv = level[v];
+          const u32 r0 = rowptr[v], r1 = rowptr[v + 1];
+          if (lv == kInf) {
+            act |= 1u << kk;
+            lo[kk] = r0;
+            d[kk] = r1 - r0;
+          }
+        }
+      }
+      // the first four entries of every unvisited row, all loaded before any test
+      u32 w[kBfsPer][4];
+#pragma unroll
+      for (u32 kk = 0; kk < kBfsPer; ++kk)
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) w[kk][i] = i < d[kk] ? colidx[lo[kk] + i] : 0u;
+      u32 found = 0;
+#pragma unroll
+      for (u32 kk = 0; kk < kBfsPer; ++kk) {
+        bool f = false;
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i)
+          f |= i < d[kk] && ((fcur[w[kk][i] >> 5] >> (w[kk][i] & 31)) & 1u);
+        found |= (f ? 1u : 0u) << kk;
+      }
       u32 bits = 0, cnt = 0;
 #pragma unroll
       for (u32 kk = 0; kk < kBfsPer; ++kk) {
         const u32 v = base + kk * blockDim.x + threadIdx.x;
-        u32 lo = 0, d = 0;
-        if (v < n && level[v] == kInf) {
-          lo = rowptr[v];
-          d = rowptr[v + 1] - lo;
-        }
-        bool found = false;
-        // short lists: per lane, four neighbours per step
-        const bool big = d > kBfsLaneMax;
+        const u32 lk = lo[kk], dk = d[kk];
+        bool fk = (found >> kk) & 1u;
+        // the rest of a short row, four neighbours per step
+        const bool big = dk > kBfsLaneMax;
         if (!big) {
-          for (u32 j = 0; j < d && !found; j += 4) {
-            u32 w[4];
+          for (u32 j = 4; j < dk && !fk; j += 4) {
+            u32 ww[4];
 #pragma unroll
-            for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : 0u;
+            for (u32 i = 0; i < 4; ++i) ww[i] = j + i < dk ? colidx[lk + j + i] : 0u;
 #pragma unroll
-            for (u32 i = 0; i < 4; ++i) found |= j + i < d && ((fcur[w[i] >> 5] >> (w[i] & 31)) & 1u);
+            for (u32 i = 0; i < 4; ++i)
+              fk |= j + i < dk && ((fcur[ww[i] >> 5] >> (ww[i] & 31)) & 1u);
           }
         }
-        // long lists: the whole wavefront, 64 neighbours per step
-        u64 bm = __ballot(big);
+        // the rest of a long row: the whole wavefront, 64 neighbours per step
+        u64 bm = __ballot(big && !fk);
         while (bm) {
           const int b = __ffsll((unsigned long long)bm) - 1;
           bm &= bm - 1;
-          const u32 blo = __shfl(lo, b, kWave), bd = __shfl(d, b, kWave);
+          const u32 blo = __shfl(lk, b, kWave), bd = __shfl(dk, b, kWave);
           bool bf = false;
-          for (u32 j0 = 0; j0 < bd && !bf; j0 += kWave) {
+          for (u32 j0 = 4; j0 < bd && !bf; j0 += kWave) {
             const u32 j = j0 + lane;
             bool hit = false;
             if (j < bd) {
-              const u32 w = colidx[blo + j];
-              hit = (fcur[w >> 5] >> (w & 31)) & 1u;
+              const u32 ww = colidx[blo + j];
+              hit = (fcur[ww >> 5] >> (ww & 31)) & 1u;
             }
             bf = __ballot(hit) != 0;
           }
-          if ((int)lane == b) found = bf;
+          if ((int)lane == b) fk = bf;
         }
-        if (found) {
+        if (fk) {
           level[v] = next;
           bits |= 1u << kk;
           ++cnt;
-          mf += d;
-          mu_dec += d;
+          mf += dk;
+          mu_dec += dk;
+          if (dk > kBfsBig) o.bq[atomicAdd(o.bqlen, 1u)] = v;
         }
-        store_bits_half(fnext, v, found, n);
+        store_bits_half(o.bits, v, fk, n);
       }
       u32 tot;
       const u32 incl = block_incl_scan(cnt, s_tmp, &tot);
-      if (threadIdx.x == 0) s_base = tot ? atomicAdd(qlen_out, tot) : 0u;
+      if (threadIdx.x == 0) s_base = tot ? atomicAdd(o.qlen, tot) : 0u;
       __syncthreads();
       u32 pos = s_base + incl - cnt;
 #pragma unroll
       for (u32 kk = 0; kk < kBfsPer; ++kk)
-        if (bits & (1u << kk)) qout[pos++] = base + kk * blockDim.x + threadIdx.x;
+        if (bits & (1u << kk)) o.q[pos++] = base + kk * blockDim.x + threadIdx.x;
       __syncthreads();  // s_base is rewritten by the next pass
     }
   }
@@ -260,18 +364,36 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
       a += s_red[2 * w];
       b += s_red[2 * w + 1];
     }
-    if (a) atomicAdd((unsigned long long*)&ctl->mf, (unsigned long long)a);
-    if (b) atomicAdd((unsigned long long*)&ctl->mu, (unsigned long long)(0 - b));
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
     __threadfence();
     const u32 ticket = atomicAdd(&ctl->blocks_done, 1u);
     s_last = ticket == gridDim.x - 1;
   }
   __syncthreads();
-  if (s_last && threadIdx.x == 0) {
-    __threadfence();
-    const u32 nf = __hip_atomic_load(qlen_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const u64 mfs = __hip_atomic_load(&ctl->mf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const u64 mus = __hip_atomic_load(&ctl->mu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!s_last) return;  // uniform within the block
+  __threadfence();
+  u64 a = 0, b = 0;
+  for (u32 i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+    a += __hip_atomic_load(&part[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b += __hip_atomic_load(&part[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  a = wave_sum_u64(a);
+  b = wave_sum_u64(b);
+  if (lane == 0) {  // thread 0 read s_red before the last barrier
+    s_red[2 * wid] = a;
+    s_red[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 mfs = 0, dec = 0;
+    for (u32 w = 0; w < blockDim.x / kWave; ++w) {
+      mfs += s_red[2 * w];
+      dec += s_red[2 * w + 1];
+    }
+    const u32 nf = __hip_atomic_load(o.qlen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 mus = __hip_atomic_load(&ctl->mu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - dec;
+    ctl->mu = mus;
     if (mode == 1) ctl->bu_levels += 1;
     if (nf == 0) {
       ctl->done = 1;
@@ -282,28 +404,33 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
       else if (mode == 1 && (u64)nf * 24 < (u64)n) nm = 0;
       ctl->mode = nm;
     }
-    ctl->qlen[k & 1] = 0;  // this level's input queue is the next level's output
-    ctl->mf = 0;
+    // this level's input queues are the next level's output
+    ctl->qlen[k & 1] = 0;
+    ctl->bqlen[k & 1] = 0;
     ctl->blocks_done = 0;
     __threadfence();
   }
 }
 
-// Two workgroups per CU: the per-level totals cost three same-address atomics per
-// workgroup.
-u32 bfs_grid(u32 n) { return max(1u, min(cdiv(n, kBfsThreads), (u32)num_cus() * 2)); }
+u32 bfs_grid(u32 n) {
+  return max(1u, min(cdiv(n, kBfsThreads * kBfsPer), (u32)num_cus() * kBfsBlocksPerCu));
+}
+size_t bfs_part_words() { return 2 * (size_t)num_cus() * kBfsBlocksPerCu; }
+size_t bfs_big_cap(u32 n, u64 m) { return (size_t)min((u64)n, m / (kBfsBig + 1) + 1); }
 
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
-                     u32* fb, BfsCtl* ctl, hipStream_t s) {
-  const u32 g = bfs_grid(n);
+                     u32* bigq0, u32* fb, BfsCtl* ctl, hipStream_t s) {
+  // each workgroup adds its totals with same-address atomics
+  const u32 g = max(1u, min(cdiv(n, kBfsThreads), (u32)num_cus() * kBfsBlocksPerCu));
   hipLaunchKernelGGL(k_bfs_init, dim3(g), dim3(kBfsThreads), 0, s, rowptr, parent, n, level,
-                     queue0, fb, ctl);
+                     queue0, bigq0, fb, ctl);
 }
 
 void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,
-                      u32* queue0, u32* queue1, u32* fb, BfsCtl* ctl, u32 grid, hipStream_t s) {
+                      u32* queue0, u32* queue1, u32* bigq0, u32* bigq1, u32* fb, BfsCtl* ctl,
+                      u64* part, u32 grid, hipStream_t s) {
   hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kBfsThreads), 0, s, rowptr, colidx, n, k,
-                     level, queue0, queue1, fb, ctl);
+                     level, queue0, queue1, bigq0, bigq1, fb, ctl, part);
 }
 
 }  // namespace tc

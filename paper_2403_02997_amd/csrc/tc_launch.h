@@ -18,7 +18,7 @@ struct BfsCtl {
   u32 blocks_done;  // last-block detection
   u32 bu_levels;    // levels expanded bottom-up
   u32 num_roots;    // components (roots = smallest ID of each component)
-  u64 mf;           // sum of degrees of the frontier being built
+  u32 bqlen[2];     // lengths of the queues of big frontier vertices, by level parity
   u64 mu;           // sum of degrees of vertices not yet visited
 };
 
@@ -66,12 +66,18 @@ void launch_validate(const u32* rowptr, const u32* colidx, const u32* tile_row, 
 bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t s);
 
 // ---- BFS ----
+// queue0 / queue1: n words each; bigq0 / bigq1: bfs_big_cap(n, m) words each (room for
+// every vertex whose list is shared by the grid in top-down levels).
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
-                     u32* fb, BfsCtl* ctl, hipStream_t s);
+                     u32* bigq0, u32* fb, BfsCtl* ctl, hipStream_t s);
 // fb: three frontier bitmaps of (n + 31) / 32 words each, zeroed before launch_bfs_init.
+// part: bfs_part_words() words of per-workgroup totals; grid <= bfs_grid(n).
 void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,
-                      u32* queue0, u32* queue1, u32* fb, BfsCtl* ctl, u32 grid, hipStream_t s);
+                      u32* queue0, u32* queue1, u32* bigq0, u32* bigq1, u32* fb, BfsCtl* ctl,
+                      u64* part, u32 grid, hipStream_t s);
 u32 bfs_grid(u32 n);
+size_t bfs_part_words();
+size_t bfs_big_cap(u32 n, u64 m);
 
 // ---- cover-edge extraction ----
 // Per vertex v: colidx2[rowptr[v] .. split[v]) = neighbours on v's level (ascending),
