@@ -189,7 +189,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u32>(n);                  // hcur (record cursors)
     c.take<u32>(scan_tmp_words(n));  // scan tmp
     c.take<uint4>(m);                // hrec (partner records in place of the rows)
-    c.take<u32>(m);                  // colidx2 (rows split by level)
+    c.take<u32>((size_t)m + 4);      // colidx2 (rows split by level), 4 readable padding entries
     c.take<u32>(n);                  // lane_x
     c.take<u32>(n);                  // wave_x
     c.take<u32>(n);                  // block_x
@@ -224,7 +224,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u32* hcur = c.take<u32>(n);
   u32* scan_tmp = c.take<u32>(scan_tmp_words(n));
   uint4* hrec = c.take<uint4>(m);
-  u32* colidx2 = c.take<u32>(m);
+  u32* colidx2 = c.take<u32>((size_t)m + 4);
   u32* lane_x = c.take<u32>(n);
   u32* wave_x = c.take<u32>(n);
   u32* block_x = c.take<u32>(n);

@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     if (it >= nitems) break;
     const Item item = items[it];
     if (PRUNED)
-      block_item_rec<VEC>(rowptr, colidx2, m, tail4b, split, sabove, hcnt, hrec, item.x, item.seg,
-                          prm, sh, tl, c);
+      block_item_rec<VEC, true>(rowptr, colidx2, m, tail4b, split, sabove, hcnt, hrec, item.x,
+                                item.seg, prm, sh, tl, c);
     else
       block_item<PV, VEC, false, 4>(rowptr, 0u, colidx, m, tail4, colidx2, m, split, tail4b,
                                     vinfo, hcnt, record_ids(hrec), item.x, item.seg, prm, sh, tl,

@@ -170,8 +170,10 @@ __device__ __forceinline__ void wave_vertex(
         addr[u] = (inf[u].x + q) * NE;
         if (VEC) {
           // one unconditional 16-byte load: a quad that would run past the end of colidx
-          // (or a dead lane) reads the padded copy of the last partial quad
-          const u32* src = (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
+          // (or a dead lane) reads the padded copy of the last partial quad; REC rows
+          // (colidx2) have 4 readable entries past m, so a quad only clamps its address
+          const u32* src = REC ? colidx + min(addr[u], (m - 1) & ~3u)
+                               : (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
           const uint4 v = *reinterpret_cast<const uint4*>(src);
           e[u][0] = v.x;
           e[u][NE > 1 ? 1 : 0] = v.y;
@@ -249,7 +251,9 @@ struct BlockShared {
 // workgroup call it together.
 constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
 
-template <bool PV, bool VEC, int MODE, bool BM>
+// PAD: the streamed array has at least 4 readable entries past its m counted ones, so
+// every live quad is read in place and dead lanes only clamp their address.
+template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
@@ -357,8 +361,10 @@ __device__ __forceinline__ void block_pass(
         addr[u] = (inf[u].x + q) * NE;
         if (VEC) {
           // one unconditional 16-byte load: a quad that would run past the end of the
-          // streamed array (or a dead lane) reads the padded copy of its last partial quad
-          const u32* src = (live[u] && addr[u] + 3 < m) ? sa + addr[u] : st4;
+          // streamed array (or a dead lane) reads the padded copy of its last partial quad,
+          // or with PAD its own padded tail (a live quad starts at or below m - 1)
+          const u32* src = PAD ? sa + min(addr[u], (m - 1) & ~3u)
+                               : (live[u] && addr[u] + 3 < m) ? sa + addr[u] : st4;
           const uint4 v = *reinterpret_cast<const uint4*>(src);
           e[u][0] = v.x;
           e[u][NE > 1 ? 1 : 0] = v.y;
@@ -478,7 +484,8 @@ __device__ __forceinline__ void block_item(
 // pass streams each record's range .x .. .z; otherwise a kOther pass (x's other-level
 // part against .y .. .z) and a kSame pass (x's same-level part above x against
 // .x .. .y), each with hash chunks or bitmap windows, whichever takes fewer passes.
-template <bool VEC>
+// PAD: colidx2 has 4 readable entries past its m2 counted ones.
+template <bool VEC, bool PAD = false>
 __device__ __forceinline__ void block_item_rec(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx2, u32 m2,
     const u32* __restrict__ tail4b, const u32* __restrict__ split,
@@ -493,20 +500,20 @@ __device__ __forceinline__ void block_item_rec(
   uint4 r = make_uint4(0, 0, 0, 0);
   if (tid < pn) r = hrec[hs + tid];
   if (ex - gx <= prm.chunk) {
-    block_pass<false, VEC, kMember, false>(colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0,
+    block_pass<false, VEC, kMember, false, PAD>(colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0,
                                            r.w, pn, r.x, r.z, prm, sh, tl, c, nullptr);
   } else {
     if (use_bitmap(colidx2, sx, ex, prm.chunk))
-      block_pass<false, VEC, kOther, true>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
+      block_pass<false, VEC, kOther, true, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
                                            r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
     else
-      block_pass<false, VEC, kOther, false>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
+      block_pass<false, VEC, kOther, false, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
                                             r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
     if (use_bitmap(colidx2, gx, sx, prm.chunk))
-      block_pass<false, VEC, kSame, true>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
+      block_pass<false, VEC, kSame, true, PAD>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
                                           r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
     else
-      block_pass<false, VEC, kSame, false>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
+      block_pass<false, VEC, kSame, false, PAD>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
                                            r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
   }
 }

@@ -99,9 +99,9 @@ void launch_fill_items(const u32* rowptr, const u32* hcnt, const u32* block_x,
 
 // ---- intersection ----
 // The intersection launchers take the split's outputs in one struct.  pruned: count
-// only T (in the c1 slot), from the level-split rows and the partner records (tail4b
-// is the padded last quad of colidx2); otherwise c1, c2 and t2 from colidx, with the
-// partners read from the records' .w fields.
+// only T (in the c1 slot), from the level-split rows (colidx2 holds m entries plus 4
+// readable padding entries) and the partner records; otherwise c1, c2 and t2 from
+// colidx, with the partners read from the records' .w fields.
 struct SplitView {
   const u32* colidx2;
   const u32* split;
