@@ -354,9 +354,10 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const u32 nseg = (hcnt[x] + prm.seg - 1) / prm.seg;
           for (u32 sg = 0; sg < nseg; ++sg)
             // colidx2 carries 4 padding entries, so its quad loads never need a tail copy
-            block_item<false, VEC, true>(rp, cb, A.colidx_cat, A.m_total, A.tail4, A.colidx2_all,
-                                         A.m_total + 4, split, A.tail4, vinfo, hcnt, A.hadj_all, x,
-                                         sg, prm, sh, tl, c, nullptr);
+            // (two windows per wavefront keep the whole kernel within its registers)
+            block_item<false, VEC, true, 1, 2>(rp, cb, A.colidx_cat, A.m_total, A.tail4,
+                                               A.colidx2_all, A.m_total + 4, split, A.tail4, vinfo,
+                                               hcnt, A.hadj_all, x, sg, prm, sh, tl, c, nullptr);
         }
         __syncthreads();  // s_mark is rewritten by the next batch
       }

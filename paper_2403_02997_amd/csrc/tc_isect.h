@@ -253,7 +253,8 @@ constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
 
 // PAD: the streamed array has at least 4 readable entries past its m counted ones, so
 // every live quad is read in place and dead lanes only clamp their address.
-template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false>
+// QU windows of 64 quads per wavefront are loaded before probing.
+template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
@@ -331,13 +332,13 @@ __device__ __forceinline__ void block_pass(
         else pcur = mid + 1;
       }
     }
-    for (u32 qw = qs; qw < qe; qw += kWave * kQuadUnroll) {
-      u32 e[kQuadUnroll][NE];
-      uint4 inf[kQuadUnroll];
-      u32 addr[kQuadUnroll];
-      bool live[kQuadUnroll];
+    for (u32 qw = qs; qw < qe; qw += kWave * QU) {
+      u32 e[QU][NE];
+      uint4 inf[QU];
+      u32 addr[QU];
+      bool live[QU];
 #pragma unroll
-      for (int u = 0; u < kQuadUnroll; ++u) {
+      for (int u = 0; u < QU; ++u) {
         const u32 w0 = qw + u * kWave;        // first quad of this window
         const u32 q = w0 + lane;
         live[u] = q < qe;
@@ -375,7 +376,7 @@ __device__ __forceinline__ void block_pass(
         }
       }
 #pragma unroll
-      for (int u = 0; u < kQuadUnroll; ++u) {
+      for (int u = 0; u < QU; ++u) {
         const u32 y2 = inf[u].w;
         const u32 vmax = max(x, y2);
         const u32 span = inf[u].z - inf[u].y;  // elements lo .. hi-1 are valid
@@ -428,7 +429,7 @@ __device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32
 // colidx2 (split[v] = local start of v's other-level neighbours), one kPrunedOne pass
 // when N(x) fits one chunk, else a kOther and a kSame pass.  m / m2 bound the quad loads
 // from colidx / colidx2 (beyond them the padded copies tail4 / tail4b are read).
-template <bool PV, bool VEC, bool PRUNED, int HS = 1>
+template <bool PV, bool VEC, bool PRUNED, int HS = 1, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const u32* __restrict__ colidx2, u32 m2,
@@ -448,8 +449,8 @@ __device__ __forceinline__ void block_item(
     ye = cb + rowptr[y + 1];
   }
   if (!PRUNED) {
-    block_pass<PV, VEC, kFull, false>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y, pn, yr,
-                                      ye, prm, sh, tl, c, tri);
+    block_pass<PV, VEC, kFull, false, false, QU>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px,
+                                                 y, pn, yr, ye, prm, sh, tl, c, tri);
   } else {
     u32 ys = 0, lb = 0;
     if (tid < pn) {
@@ -457,24 +458,26 @@ __device__ __forceinline__ void block_item(
       lb = lower_bound_g(colidx2, yr, ys, max(x, y) + 1u);  // same-level part above max
     }
     if (dx <= prm.chunk) {
-      block_pass<false, VEC, kPrunedOne, false>(colidx2, m2, tail4b, colidx, bx, ex, vinfo, x, px,
-                                                y, pn, lb, ye, prm, sh, tl, c, tri);
+      block_pass<false, VEC, kPrunedOne, false, false, QU>(colidx2, m2, tail4b, colidx, bx, ex,
+                                                           vinfo, x, px, y, pn, lb, ye, prm, sh,
+                                                           tl, c, tri);
     } else {
       const u32 sx = cb + split[x];
       const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
       // bitmap windows where they need fewer passes than hash chunks
       if (use_bitmap(colidx2, sx, ex, prm.chunk))
-        block_pass<false, VEC, kOther, true>(colidx2, m2, tail4b, colidx2, sx, ex, vinfo, x, px, y,
-                                             pn, ys, ye, prm, sh, tl, c, tri);
+        block_pass<false, VEC, kOther, true, false, QU>(colidx2, m2, tail4b, colidx2, sx, ex, vinfo,
+                                                        x, px, y, pn, ys, ye, prm, sh, tl, c, tri);
       else
-        block_pass<false, VEC, kOther, false>(colidx2, m2, tail4b, colidx2, sx, ex, vinfo, x, px, y,
-                                              pn, ys, ye, prm, sh, tl, c, tri);
+        block_pass<false, VEC, kOther, false, false, QU>(colidx2, m2, tail4b, colidx2, sx, ex,
+                                                         vinfo, x, px, y, pn, ys, ye, prm, sh, tl,
+                                                         c, tri);
       if (use_bitmap(colidx2, gx, sx, prm.chunk))
-        block_pass<false, VEC, kSame, true>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo, x, px, y,
-                                            pn, lb, ys, prm, sh, tl, c, tri);
+        block_pass<false, VEC, kSame, true, false, QU>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo,
+                                                       x, px, y, pn, lb, ys, prm, sh, tl, c, tri);
       else
-        block_pass<false, VEC, kSame, false>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo, x, px, y,
-                                             pn, lb, ys, prm, sh, tl, c, tri);
+        block_pass<false, VEC, kSame, false, false, QU>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo,
+                                                        x, px, y, pn, lb, ys, prm, sh, tl, c, tri);
     }
   }
 }
@@ -507,8 +510,8 @@ __device__ __forceinline__ void block_item_rec(
       block_pass<false, VEC, kOther, true, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
                                            r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
     else
-      block_pass<false, VEC, kOther, false, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
-                                            r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
+      block_pass<false, VEC, kOther, false, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x,
+                                                 0, r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
     if (use_bitmap(colidx2, gx, sx, prm.chunk))
       block_pass<false, VEC, kSame, true, PAD>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
                                           r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
