@@ -23,6 +23,10 @@ Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, batch4096
 and serve (a Poisson stream of requests through the tc_serve_* server: p50/p99 latency
 and input edges/s, every result checked against the standalone count).
 
+--autotune picks the intersection thresholds (tc_set_isect_params) on the workload
+itself before the warm-up, by the package's coordinate-descent autotuner; the chosen
+setting is in config.isect_params of every line either way.
+
 Counter helpers (no bench line):
   --calibrate-copy MIB  runs a plain device-to-device copy of MIB MiB three times, the
                         known-size kernel that FETCH_SIZE / WRITE_SIZE are scaled by;
@@ -212,6 +216,13 @@ def bench_single(args, tcm, torch):
         f"({time.perf_counter() - t:.1f}s)")
     rp, ci = tcm.to_device(g.rowptr, g.colidx)
     torch.cuda.synchronize()
+    tuned = None
+    if args.autotune:
+        from paper_2403_02997_amd import autotune as at
+        t = time.perf_counter()
+        tuned = at.autotune(rp, ci, reps=2, cache=None)
+        log(f"[bench] autotune: {tuned['params']} after {tuned['measured']} settings "
+            f"({time.perf_counter() - t:.1f}s)")
     for i in range(args.warmup):
         tcm.tc_count(rp, ci)
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
@@ -262,7 +273,7 @@ def bench_single(args, tcm, torch):
                    "cover_edges": stats.cover_edges,
                    "covering_ratio": round(stats.cover_edges / max(g.num_edges, 1), 4),
                    "bfs_depth": stats.depth, "components": stats.num_roots,
-                   "isect_params": list(params)},
+                   "isect_params": list(params), "autotuned": tuned is not None},
         "triangles_per_s": T * args.steps / elapsed,
         "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
         "isect_classes": {k: {"cover_edges": v["cover_edges"],
@@ -289,10 +300,16 @@ def bench_batch(args, tcm, torch):
     ro = torch.from_numpy(b.row_off).cuda()
     co = torch.from_numpy(b.col_off).cuda()
     rows = int(b.rowptr_cat.shape[0])
-    ws = torch.empty(tcm.tc_count_batch_workspace_size(b.num_graphs, rows,
-                                                              int(b.colidx_cat.shape[0])), dtype=torch.uint8,
-                     device="cuda")
+    ws_bytes = tcm.tc_count_batch_workspace_size(b.num_graphs, rows, int(b.colidx_cat.shape[0]))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     counts = torch.zeros(b.num_graphs, dtype=torch.int64, device="cuda")
+    tuned = None
+    if args.autotune:
+        from paper_2403_02997_amd import autotune as at
+        t = time.perf_counter()
+        tuned = at.autotune_batch(rp, ci, ro, co, workspace=ws, reps=1, cache=None)
+        log(f"[bench] autotune: {tuned['params']} after {tuned['measured']} settings "
+            f"({time.perf_counter() - t:.1f}s)")
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -339,7 +356,9 @@ def bench_batch(args, tcm, torch):
         "data": "synthetic",
         "config": {"workload": "batch4096", "graph": WORKLOAD_TEXT["batch4096"],
                    "num_graphs": b.num_graphs, "input_edges": b.total_edges,
-                   "triangles": int(batched.sum())},
+                   "triangles": int(batched.sum()),
+                   "isect_params": list(tcm.tc_get_isect_params()),
+                   "autotuned": tuned is not None},
         "per_graph_launch": {"value": b.total_edges / t_single, "unit": "input edges/s",
                              "ms_total": t_single * 1e3},
         "batched_over_per_graph": t_single / t_batch,
@@ -533,6 +552,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--isect", default="", metavar="LANE,WAVE,CHUNK,SEG",
                     help="intersection class parameters (tc_set_isect_params) for this run")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the intersection class parameters on the workload first")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-huge-scale", type=int, default=26)
     ap.add_argument("--serve-small-max", type=int, default=1 << 18)

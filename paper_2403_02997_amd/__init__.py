@@ -4,7 +4,8 @@ Method: Bader, Li, Du et al., "Cover Edge-Based Novel Triangle Counting"
 (arXiv 2403.02997): BFS levels restarted per component, the horizontal (same-level)
 edges as cover-edge set, and one sorted-list intersection per cover edge with the
 paper's level/order rule.  The kernels live in ``csrc/`` and are reached through the
-C ABI of ``include/tc.h``; :mod:`.tc` is the Python binding with the same names.
+C ABI of ``include/tc.h``; :mod:`.tc` is the Python binding with the same names, and
+:mod:`.autotune` picks the intersection class thresholds on the caller's own input.
 """
 from .tc import (  # noqa: F401
     EXPORTS,
