@@ -76,22 +76,45 @@ __global__ void k_cc_sample(const u32* __restrict__ rowptr, const u32* __restric
   }
 }
 
-__global__ void k_cc_compress(u32 n, u32* parent) {
+// A second sampling round (the third and fourth smallest neighbours), run only when
+// mode[1] says that the first one left too many vertices outside the dominant component
+// (many links lost to races, as on graphs without hubs, where every root is contended
+// about equally); otherwise it returns at once.
+__global__ void k_cc_sample_more(const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
+                                 u32 n, u32* parent, const u32* __restrict__ mode) {
+  if (mode[1] == 0) return;
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const u32 lo = rowptr[v], hi = rowptr[v + 1];
+    if (hi - lo >= 3) cc_min_link(parent, v, colidx[lo + 2]);
+    if (hi - lo >= 4) cc_min_link(parent, v, colidx[lo + 3]);
+  }
+}
+
+// REDO: only when mode[1] is set (after k_cc_sample_more).
+template <bool REDO>
+__global__ void k_cc_compress(u32 n, u32* parent, const u32* __restrict__ mode) {
+  if (REDO && mode[1] == 0) return;
   for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
     parent[v] = cc_find(parent, v);
 }
 
-// The most frequent root among kModeSamples spread-out vertices (one workgroup).
+// The most frequent root among kModeSamples spread-out vertices (one workgroup) in
+// mode[0].  The first pass (REDO = false) also sets mode[1] when fewer than 90 % of the
+// sampled vertices with neighbours have that root; the second pass runs only then.
 constexpr u32 kModeSamples = 1024;
 
-__global__ void __launch_bounds__(kModeSamples) k_cc_mode(u32 n, u32* parent,
-                                                           u32* __restrict__ mode) {
+template <bool REDO>
+__global__ void __launch_bounds__(kModeSamples) k_cc_mode(const u32* __restrict__ rowptr, u32 n,
+                                                           u32* parent, u32* __restrict__ mode) {
   __shared__ u32 s_root[kModeSamples];
   __shared__ u64 s_best[kModeSamples / kWave];
+  __shared__ u32 s_live[kModeSamples / kWave];
+  if (REDO && mode[1] == 0) return;  // uniform
   const u32 i = threadIdx.x;
   const u32 v = (u32)(((u64)i * 2654435761ull + 12345u) % n);
   const u32 r = cc_find(parent, v);
-  s_root[i] = r;
+  const bool live = rowptr[v + 1] > rowptr[v];
+  s_root[i] = live ? r : kInf;  // isolated vertices are their own components
   __syncthreads();
   u32 cnt = 0;
   for (u32 j = 0; j < kModeSamples; ++j) cnt += s_root[j] == r;
@@ -102,12 +125,21 @@ __global__ void __launch_bounds__(kModeSamples) k_cc_mode(u32 n, u32* parent,
     const u64 o = __shfl_xor(key, off, kWave);
     key = o > key ? o : key;
   }
-  if (lane_id() == 0) s_best[i / kWave] = key;
+  const u32 nlive = (u32)__popcll(__ballot(live));
+  if (lane_id() == 0) {
+    s_best[i / kWave] = key;
+    s_live[i / kWave] = nlive;
+  }
   __syncthreads();
   if (i == 0) {
     u64 b = 0;
-    for (u32 w = 0; w < kModeSamples / kWave; ++w) b = s_best[w] > b ? s_best[w] : b;
-    *mode = (u32)b;
+    u32 tl = 0;
+    for (u32 w = 0; w < kModeSamples / kWave; ++w) {
+      b = s_best[w] > b ? s_best[w] : b;
+      tl += s_live[w];
+    }
+    mode[0] = (u32)b;
+    if (!REDO) mode[1] = (u32)(b >> 32) * 10 < tl * 9 ? 1u : 0u;
   }
 }
 
@@ -147,13 +179,20 @@ void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n,
   hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
   if (m > 0) {
     // flatten the initial forest first, so that the sampled links start from short paths
-    hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
+    hipLaunchKernelGGL(k_cc_compress<false>, dim3(gv), dim3(256), 0, s, n, parent, mode);
     hipLaunchKernelGGL(k_cc_sample, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
-    hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
-    hipLaunchKernelGGL(k_cc_mode, dim3(1), dim3(kModeSamples), 0, s, n, parent, mode);
+    hipLaunchKernelGGL(k_cc_compress<false>, dim3(gv), dim3(256), 0, s, n, parent, mode);
+    hipLaunchKernelGGL(k_cc_mode<false>, dim3(1), dim3(kModeSamples), 0, s, rowptr, n, parent,
+                       mode);
+    // second sampling round, only where the first left the dominant component thin
+    hipLaunchKernelGGL(k_cc_sample_more, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent,
+                       mode);
+    hipLaunchKernelGGL(k_cc_compress<true>, dim3(gv), dim3(256), 0, s, n, parent, mode);
+    hipLaunchKernelGGL(k_cc_mode<true>, dim3(1), dim3(kModeSamples), 0, s, rowptr, n, parent,
+                       mode);
     hipLaunchKernelGGL(k_cc_finish, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent, mode);
   }
-  hipLaunchKernelGGL(k_cc_compress, dim3(gv), dim3(256), 0, s, n, parent);
+  hipLaunchKernelGGL(k_cc_compress<false>, dim3(gv), dim3(256), 0, s, n, parent, mode);
 }
 
 // ---- per-vertex info byte ------------------------------------------------------------
