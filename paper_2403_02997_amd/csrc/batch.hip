@@ -331,7 +331,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
         if (hcnt[x] == 0 || dx <= prm.lane_max || dx > prm.wave_max) continue;  // wave-uniform
         Tally tl{0, 0, 0, 0};
         wave_vertex<false, VEC>(rp, cb, A.colidx_cat, A.m_total, A.tail4, vinfo, hcnt,
-                                A.hadj_all, nullptr, nullptr, x, s_table + wid * kWaveSlots,
+                                A.hadj_all, nullptr, nullptr, x, WaveMeta{},
+                                s_table + wid * kWaveSlots,
                                 s_pinfo + wid * kWave,
                                 s_qincl + wid * kWave, s_mark + wid * kWave, tl, c, nullptr);
         tl.fold(c);

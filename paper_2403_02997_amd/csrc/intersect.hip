@@ -64,22 +64,43 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
   __shared__ u64 s_red[5 * kW];
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   Counts c{0, 0, 0, 0, 0};
-  // Vertices are claimed kWaveClaim at a time: one counter atomic per vertex would
-  // serialise hundreds of thousands of same-address atomics at the L2.
-  u32 idx = 0, idx_end = 0;
-  while (true) {
-    if (idx == idx_end) {
-      u32 c0 = 0;
-      if (lane == 0) c0 = atomicAdd(&plan->next_wave, kWaveClaim);
-      idx = __shfl(c0, 0, kWave);
-      idx_end = min(idx + kWaveClaim, nwx);
+  // Vertices are claimed kWaveClaim at a time (one counter atomic per vertex would
+  // serialise hundreds of thousands of same-address atomics at the L2), with all their
+  // IDs loaded at once; the next vertex's row data is loaded while the current one runs.
+  u32 base = 0, cnt = 0, xs = 0, j = 0;
+  auto claim = [&]() {
+    u32 c0 = 0;
+    if (lane == 0) c0 = atomicAdd(&plan->next_wave, kWaveClaim);
+    base = __shfl(c0, 0, kWave);
+    cnt = base < nwx ? min(kWaveClaim, nwx - base) : 0u;
+    xs = lane < cnt ? wave_x[base + lane] : 0u;
+    j = 0;
+  };
+  claim();
+  if (cnt > 0) {
+    u32 x = __shfl(xs, 0, kWave);
+    j = 1;
+    WaveMeta mt{};
+    if (REC) mt = wave_meta(rowptr, sabove, hcnt, x);
+    while (true) {
+      if (j == cnt) claim();
+      const bool more = cnt > 0;
+      u32 x1 = 0;
+      WaveMeta mt1{};
+      if (more) {
+        x1 = __shfl(xs, j, kWave);
+        ++j;
+        if (REC) mt1 = wave_meta(rowptr, sabove, hcnt, x1);
+      }
+      Tally tl{0, 0, 0, 0};
+      wave_vertex<PV, VEC, REC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
+                                   hrec, sabove, x, mt, s_table[wid], s_pinfo[wid], s_end[wid],
+                                   s_mark[wid], tl, c, tri);
+      tl.fold(c);
+      if (!more) break;
+      x = x1;
+      mt = mt1;
     }
-    if (idx >= nwx) break;
-    Tally tl{0, 0, 0, 0};
-    wave_vertex<PV, VEC, REC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
-                                 hrec, sabove, wave_x[idx++], s_table[wid], s_pinfo[wid],
-                                 s_end[wid], s_mark[wid], tl, c, tri);
-    tl.fold(c);
   }
   block_flush_counts(c, 1, ctr, s_red);
 }

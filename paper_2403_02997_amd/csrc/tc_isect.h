@@ -73,6 +73,17 @@ __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 
 }
 
 // ---- wave class: one wavefront per staged vertex x -----------------------------------
+// Row data of a staged vertex, loaded ahead of its turn by the pruned kernel.
+struct WaveMeta {
+  u32 bx, ex, sb, np;  // row start and end, first staged entry, partner count
+};
+
+__device__ __forceinline__ WaveMeta wave_meta(const u32* __restrict__ rowptr,
+                                              const u32* __restrict__ sabove,
+                                              const u32* __restrict__ hcnt, u32 x) {
+  return WaveMeta{rowptr[x], rowptr[x + 1], sabove[x], hcnt[x]};
+}
+
 // N(x) goes to the wavefront's LDS hash set (kWaveSlots slots).  The partners' lists are
 // taken 64 at a time, padded out to whole 16-byte quads (VEC) and concatenated; each lane
 // then loads one quad per window, so a lane has 4 * kUnroll list elements in flight.
@@ -82,23 +93,28 @@ __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 
 // REC = false: the full form (N(x) with level flags against each partner's whole row of
 // colidx; c1, c2, t2).  REC = true: the pruned form over the level-split rows (colidx
 // is then colidx2): x's entries from sabove[x] on against each partner record's range,
-// membership only; every hit goes to s.
+// membership only; every hit goes to s.  With REC the row data comes in mt (loaded
+// ahead by the caller) and the first 64 partner records are loaded before the staged
+// set is built, so their latency overlaps the inserts.
 template <bool PV, bool VEC, bool REC = false, int HS = 1>
 __device__ __forceinline__ void wave_vertex(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
     const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
-    const uint4* __restrict__ hrec, const u32* __restrict__ sabove, u32 x, u32* table,
-    uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c, u64* __restrict__ tri) {
+    const uint4* __restrict__ hrec, const u32* __restrict__ sabove, u32 x, WaveMeta mt,
+    u32* table, uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c,
+    u64* __restrict__ tri) {
   static_assert(!(REC && PV), "per-vertex counts use the full form");
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
   const u32 lane = lane_id();
   const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
-  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
-  const u32 sb = REC ? sabove[x] : bx;  // first staged entry
+  const u32 bx = REC ? mt.bx : cb + rowptr[x], ex = REC ? mt.ex : cb + rowptr[x + 1];
+  const u32 sb = REC ? mt.sb : bx;  // first staged entry
   const u32 dx = ex - sb;
-  const u32 hs = bx, np = hcnt[x];  // H+(x) sits in place of N(x)
-  const u32 px = vinfo[x] & 0x80u;
+  const u32 hs = bx, np = REC ? mt.np : hcnt[x];  // H+(x) sits in place of N(x)
+  const u32 px = REC ? 0u : vinfo[x] & 0x80u;
+  uint4 r0 = make_uint4(0, 0, 0, 0);  // REC: the first batch of partner records
+  if (REC && lane < np) r0 = hrec[hs + lane];
   const u32 mask = bucket_mask(dx, kWaveSlots);
   c.staged += lane == 0 ? dx : 0;
   for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
@@ -118,7 +134,7 @@ __device__ __forceinline__ void wave_vertex(
     u32 y = 0, lo = 0, hi = 0;
     if (p < np) {
       if (REC) {
-        const uint4 r = hrec[hs + p];
+        const uint4 r = pb == 0 ? r0 : hrec[hs + p];
         y = r.w;
         lo = r.x;
         hi = r.z;
