@@ -57,7 +57,8 @@ CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
 # colidx, no per-vertex attribution; the workgroup class in its pruned form).
 KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>",
                   "isect_wave": "k_isect_wave<false, true, true>",
-                  "isect_block": "k_isect_block<false, true, true>"}
+                  "isect_block": "k_isect_block<false, true, true>",
+                  "isect_hub": "k_hub_count<8>"}
 
 WORKLOAD_TEXT = {
     "rmat10": "R-MAT scale 10, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1000",
@@ -95,15 +96,36 @@ def degree_class(d: np.ndarray) -> np.ndarray:
     return out
 
 
-def class_bytes(g, level: np.ndarray, params) -> dict:
+def hub_set(d: np.ndarray, max_hubs: int, min_degree: int) -> np.ndarray:
+    """The hubs of tc_count's hub pass (tc_set_hub_params): the vertices of degree class
+    >= c*, c* the smallest class >= max(class(min_degree), 1) whose vertices and those of
+    the classes above number between 1 and max_hubs (no hubs if there is none)."""
+    cls = degree_class(d)
+    if max_hubs == 0 or len(d) == 0:
+        return np.zeros(len(d), dtype=bool)
+    suf = np.cumsum(np.bincount(cls, minlength=128)[::-1])[::-1]
+    cmin = max(int(degree_class(np.array([min_degree]))[0]), 1)
+    for c in range(cmin, 128):
+        if 0 < suf[c] <= max_hubs:
+            return cls >= c
+    return np.zeros(len(d), dtype=bool)
+
+
+def class_bytes(g, level: np.ndarray, params, hubs=(0, 0)) -> dict:
     """Per intersection class of tc_count: cover edges and the bytes its kernel has to
     read at least once.  A cover edge {x, y} is staged under x (larger degree class, then
     ID) and streams y's list.  The lane class streams all of N(y) and stages N(x); the
     wavefront and workgroup classes stream only y's other-level neighbours and its
     same-level neighbours above max(x, y), and stage x's other-level neighbours and its
-    same-level neighbours above x.  Each staged list counts once."""
+    same-level neighbours above x.  Each staged list counts once.  Cover edges staged
+    under a hub (hubs = tc_get_hub_params()) go to the hub pass: each partner y of a hub
+    streams N'(y) (its other-level neighbours and its same-level neighbours above y) once,
+    looks every entry up in a mask of NW words (4 for at most 128 hubs, else 8) and reads
+    its own mask H(y); building the masks reads every hub's S list (its other-level
+    neighbours and same-level neighbours above it) and writes NW words per vertex."""
     lane_max, wave_max = params[0], params[1]
     d = g.degrees().astype(np.int64)
+    hub = hub_set(d, hubs[0], hubs[1])
     rp = g.rowptr.astype(np.int64)
     rows = np.repeat(np.arange(g.n, dtype=np.int64), d)
     cols = g.colidx.astype(np.int64)
@@ -123,10 +145,11 @@ def class_bytes(g, level: np.ndarray, params) -> dict:
     y = np.where(key_u > key_v, v, u)
     del u, v, key_u, key_v
     dx = d[x]
+    hx = hub[x]
     out = {}
-    for name, sel in (("isect_lane", dx <= lane_max),
-                      ("isect_wave", (dx > lane_max) & (dx <= wave_max)),
-                      ("isect_block", dx > wave_max)):
+    for name, sel in (("isect_lane", (dx <= lane_max) & ~hx),
+                      ("isect_wave", (dx > lane_max) & (dx <= wave_max) & ~hx),
+                      ("isect_block", (dx > wave_max) & ~hx)):
         xs = np.unique(x[sel])
         ys = y[sel]
         if name == "isect_lane":
@@ -141,6 +164,18 @@ def class_bytes(g, level: np.ndarray, params) -> dict:
             above = cs[rp[xs + 1]] - cs[np.searchsorted(key, xs * (1 << 32) + xs, side="right")]
             staged = int((d[xs] - same_x + above).sum())
         out[name] = {"cover_edges": int(sel.sum()), "bytes": 4 * (streamed + staged)}
+    nh = int(hub.sum())
+    hb = 0
+    if nh:
+        nw = 4 if nh <= 128 else 8
+        vs = np.arange(g.n, dtype=np.int64)
+        same_v = cs[rp[1:]] - cs[rp[:-1]]
+        above_v = cs[rp[1:]] - cs[np.searchsorted(key, vs * (1 << 32) + vs, side="right")]
+        nprime = d - same_v + above_v  # N'(v), also S(v)
+        ys = np.unique(y[hx])
+        hb = int((4 + 4 * nw) * nprime[ys].sum() + 4 * nw * len(ys)
+                 + 4 * nprime[hub].sum() + 4 * nw * g.n)
+    out["isect_hub"] = {"cover_edges": int(hx.sum()), "bytes": hb}
     return out
 
 
@@ -244,7 +279,8 @@ def bench_single(args, tcm, torch):
     assert stats.triangles == T
     level_np = level.cpu().numpy().view(np.uint32)
     params = tcm.tc_get_isect_params()
-    cb = class_bytes(g, level_np, params)
+    hubs = tcm.tc_get_hub_params()
+    cb = class_bytes(g, level_np, params, hubs)
     steps_ms = {k: v / max(calls, 1) for k, v in prof.items()}
     isect = {k: steps_ms.get(k, 0.0) for k in KERNEL_OF_STEP}
     dom = max(isect, key=isect.get)
@@ -273,7 +309,9 @@ def bench_single(args, tcm, torch):
                    "cover_edges": stats.cover_edges,
                    "covering_ratio": round(stats.cover_edges / max(g.num_edges, 1), 4),
                    "bfs_depth": stats.depth, "components": stats.num_roots,
-                   "isect_params": list(params), "autotuned": tuned is not None},
+                   "isect_params": list(params), "hub_params": list(hubs),
+                   "hubs": int(hub_set(g.degrees(), *hubs).sum()),
+                   "autotuned": tuned is not None},
         "triangles_per_s": T * args.steps / elapsed,
         "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
         "isect_classes": {k: {"cover_edges": v["cover_edges"],
@@ -552,6 +590,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--isect", default="", metavar="LANE,WAVE,CHUNK,SEG",
                     help="intersection class parameters (tc_set_isect_params) for this run")
+    ap.add_argument("--hubs", default="", metavar="MAX_HUBS,MIN_DEGREE",
+                    help="hub pass parameters (tc_set_hub_params) for this run; 0,0 turns it off")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the intersection class parameters on the workload first")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -587,6 +627,8 @@ def main():
     tcm.load()
     if args.isect:
         tcm.tc_set_isect_params(*[int(v) for v in args.isect.split(",")])
+    if args.hubs:
+        tcm.tc_set_hub_params(*[int(v) for v in args.hubs.split(",")])
     if args.workload == "batch4096":
         out = bench_batch(args, tcm, torch)
     elif args.workload == "serve":

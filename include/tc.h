@@ -33,7 +33,7 @@
  * All entry points are stream-ordered on `stream` (0 = the null stream).
  * Thread safety: calls on different streams may run concurrently; the library keeps no
  * mutable global state besides a per-device cache of the device properties and the
- * intersection tuning set by tc_set_isect_params.
+ * tuning set by tc_set_isect_params and tc_set_hub_params.
  */
 #ifndef TC_H_
 #define TC_H_
@@ -233,6 +233,24 @@ int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, 
 int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, uint32_t seg);
 /* Current setting as {lane_max, wave_max, chunk, seg} into the HOST array out4[4]. */
 int tc_get_isect_params(uint32_t* out4);
+
+/*
+ * Hub pass of tc_count (Section 5's pruned count, Alg. 10's per-edge sum regrouped; the
+ * result is the same T).  The hubs are the vertices of the highest degree classes: as
+ * many whole classes as hold at most max_hubs (<= 256) vertices together, each class at
+ * least the class of min_degree (classes are four per octave of the degree).  The cover
+ * edges staged under a hub are not intersected one by one: for each partner y the pass
+ * streams y's other-level neighbours and its same-level neighbours above y once and looks
+ * each one up in a per-vertex bit mask of the hubs whose pruned list holds it, masked
+ * with the hubs that stage y.  max_hubs = 0 turns the pass off.  tc_count_ex and
+ * tc_count_per_vertex never use it.  Default {256, 4096}; process-wide, change it only
+ * while no count is running; max_hubs > 256 gives TC_ERR_INVALID_ARG.
+ * Workspace of tc_count with the pass on: 64 bytes per vertex more, plus 8 bytes per
+ * work item (at most n + m / 1024 items).
+ */
+int tc_set_hub_params(uint32_t max_hubs, uint32_t min_degree);
+/* Current setting as {max_hubs, min_degree} into the HOST array out2[2]. */
+int tc_get_hub_params(uint32_t* out2);
 
 /*
  * Step timing (diagnostics).  While enabled, tc_count / tc_count_ex /

@@ -20,9 +20,11 @@ from .tc import (  # noqa: F401
     tc_count_batch_workspace_size,
     tc_count_ex,
     tc_count_per_vertex,
+    tc_get_hub_params,
     tc_get_isect_params,
     tc_profile_enable,
     tc_profile_read,
+    tc_set_hub_params,
     tc_set_isect_params,
     tc_validate_csr,
     tc_version,

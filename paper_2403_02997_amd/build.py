@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtc.so")
-SOURCES = ["prep.hip", "bfs.hip", "cover.hip", "intersect.hip", "batch.hip", "api.hip",
+SOURCES = ["prep.hip", "bfs.hip", "cover.hip", "hub.hip", "intersect.hip", "batch.hip", "api.hip",
            "serve.hip"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 

@@ -110,6 +110,22 @@ IsectParams default_params() {
 
 IsectParams g_params = default_params();
 
+// Host copy of the device degree class (4 steps per octave).
+u32 host_degree_class(u32 d) {
+  if (d == 0) return 0;
+  u32 lg = 31;
+  while (!((d >> lg) & 1u)) --lg;
+  const u32 frac = lg >= 2 ? (d >> (lg - 2)) & 3u : ((d << (2 - lg)) & 3u);
+  const u32 c = 1u + 4u * lg + frac;
+  return c > 127u ? 127u : c;
+}
+
+// Hub pass: up to 256 hubs of degree at least 4096 (by class).
+constexpr u32 kDefaultHubs = kMaxHubs;
+constexpr u32 kDefaultHubDegree = 4096;
+u32 g_hub_max = kDefaultHubs;
+u32 g_hub_min_degree = kDefaultHubDegree;
+
 struct RunOut {
   u64 c[kNumCtr];  // see kNumCtr: c1, c2, t2, streamed[3], staged[3]
   u64 cover_edges;
@@ -120,9 +136,9 @@ struct RunOut {
 // When enabled, the single-graph path records HIP events on its own stream at every step
 // boundary and accumulates the elapsed time of each step.
 enum Step { kStepRoots, kStepBfs, kStepExtract, kStepPlan, kStepLane, kStepBlock, kStepWave,
-            kStepReduce, kNumSteps };
+            kStepHub, kStepReduce, kNumSteps };
 const char* kStepNames[kNumSteps] = {"roots", "bfs", "extract", "plan", "isect_lane",
-                                     "isect_block", "isect_wave", "reduce"};
+                                     "isect_block", "isect_wave", "isect_hub", "reduce"};
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 double g_prof_ms[kNumSteps];
@@ -168,6 +184,11 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
                u32* level_out, u64* tri, bool pruned, RunOut* out) {
   prepare_pool();
   const IsectParams prm = g_params;
+  // the hub pass serves the pruned count only (per-vertex and c1 / c2 tallies stay per edge)
+  const HubParams hp{pruned && !tri ? g_hub_max : 0u, host_degree_class(g_hub_min_degree)};
+  const bool hub_on = hp.max_hubs > 0;
+  const size_t hub_cap = hub_on ? (size_t)n + m / kHubChunk + 1 : 0;
+  const size_t hub_cuts = hub_on ? hub_cut_words(hp.max_hubs, n) : 0;
   const u32 ntiles = (m + kTile - 1) / kTile;
   const u32 max_s = m / 2;
   // ---- workspace ----
@@ -194,8 +215,15 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     c.take<u32>(n);                  // wave_x
     c.take<u32>(n);                  // block_x
     c.take<u32>((size_t)n + 1);      // block items / offsets
+    c.take<uint8_t>(hub_on ? n : 0);                  // hubidx
+    c.take<u32>(hub_on ? kMaxHubs : 0);               // hublist
+    c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0);  // H(y)
+    c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0);  // hub masks M(w)
+    c.take<uint2>(hub_cap);                           // hub work items
+    c.take<u32>(hub_cuts);                            // hub window cuts
     c.take<BfsCtl>(1);
     c.take<Plan>(1);
+    c.take<u32>(128);                // degree-class histogram
     c.take<u64>(kCounterSlots * kNumCtr);
     c.take<u64>(kNumCtr);
     c.take<u32>(4);
@@ -229,9 +257,16 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u32* wave_x = c.take<u32>(n);
   u32* block_x = c.take<u32>(n);
   u32* bitems = c.take<u32>((size_t)n + 1);
-  // control block: ctl, plan, counters, result are contiguous and cleared together
+  uint8_t* hubidx = c.take<uint8_t>(hub_on ? n : 0);
+  u32* hublist = c.take<u32>(hub_on ? kMaxHubs : 0);
+  u32* hy = reinterpret_cast<u32*>(c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0));
+  u32* hubmask = reinterpret_cast<u32*>(c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0));
+  uint2* hitems = c.take<uint2>(hub_cap);
+  u32* hcuts = c.take<u32>(hub_cuts);
+  // control block: ctl, plan, histogram, counters, result are contiguous and cleared together
   BfsCtl* ctl = c.take<BfsCtl>(1);
   Plan* plan = c.take<Plan>(1);
+  u32* chist = c.take<u32>(128);
   u64* ctr = c.take<u64>(kCounterSlots * kNumCtr);
   u64* outc = c.take<u64>(kNumCtr);
   const size_t ctl_bytes = (char*)(outc + kNumCtr) - (char*)ctl;
@@ -273,12 +308,14 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     }
   }
   timer.mark();
-  launch_vinfo(rowptr, level, n, vinfo, hcur, s);
+  launch_vinfo(rowptr, level, n, vinfo, hcur, hub_on ? chist : nullptr, s);
+  if (hub_on) launch_hub_select(vinfo, n, chist, hp, hubidx, hublist, plan, s);
 
   // ---- a3: cover-edge extraction ----
   // the BFS queues are free again: q1 lists the long rows
+  const HubView hv{&plan->hub_lim, hubidx, hy, hitems, &plan->num_hub_items, (u32)hub_cap};
   launch_split_rows(rowptr, colidx, vinfo, n, m, colidx2, split, sabove, hcnt, hcur, hrec, q1,
-                    &plan->num_long, s);
+                    &plan->num_long, hv, s);
   timer.mark();
   launch_plan(rowptr, hcnt, hcur, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
   launch_scan(bitems, bitems, n, scan_tmp, s);
@@ -293,6 +330,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   if (h_plan.bad_records) return TC_ERR_INVALID_GRAPH;
   const u32 h_ns = h_plan.num_cover;
   if (h_ns > max_s) return TC_ERR_INTERNAL;
+  if (h_plan.num_hubs > hp.max_hubs || h_plan.num_hub_items > hub_cap) return TC_ERR_INTERNAL;
 
   // ---- a4: intersections ----
   DevAlloc items_mem;
@@ -314,6 +352,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   timer.mark();
   launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
                     tri, pruned && !tri, s);
+  timer.mark();
+  launch_hub_pass(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hy, hitems,
+                  h_plan.num_hub_items, hcuts, hubmask, ctr, s);
   timer.mark();
   // ---- a5: reduction ----
   launch_finalize(ctr, outc, s);
@@ -490,6 +531,20 @@ int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, ui
   g_params.wave_max = wave_max;
   g_params.chunk = chunk;
   g_params.seg = seg;
+  return TC_OK;
+}
+
+int tc_set_hub_params(uint32_t max_hubs, uint32_t min_degree) {
+  if (max_hubs > kMaxHubs) return TC_ERR_INVALID_ARG;
+  g_hub_max = max_hubs;
+  g_hub_min_degree = min_degree;
+  return TC_OK;
+}
+
+int tc_get_hub_params(uint32_t* out2) {
+  if (!out2) return TC_ERR_INVALID_ARG;
+  out2[0] = g_hub_max;
+  out2[1] = g_hub_min_degree;
   return TC_OK;
 }
 

@@ -18,6 +18,12 @@
 // 4096 by one wavefront (ballot ranks keep both parts in order), longer ones by a whole
 // workgroup.  The level split and the records let the counting skip the same-level
 // neighbours that cannot be a counted apex.
+//
+// Hub partners: when w is a hub (degree class >= the hub threshold), the edge {v, w} is
+// counted by the hub pass instead: v's split still advances w's cursor (the planner's
+// check) but writes bit hubidx[w] of H(v) in place of the record, and appends v's work
+// items (N'(v) in kHubChunk pieces) once per row.  A hub row flags its hcnt with kHubFlag
+// so that the planner gives it no intersection work.
 #include "tc_isect.h"
 
 namespace tc {
@@ -43,7 +49,38 @@ struct SplitOut {
   u32* hcur;
   uint4* hrec;
   u32 m;  // records are written only below m (a guard for graphs that break the contract)
+  HubView hub;
 };
+
+// Degree class from which a vertex is a hub (255: none).
+__device__ __forceinline__ u32 hub_limit(const HubView& hv) {
+  const u32 lim = *hv.lim;
+  return lim ? lim : 255u;
+}
+
+// H(v) is gathered in LDS (kHubWords words per row being split): a lane's own slot for
+// lane rows, the slot of the row's lane for wavefront rows, one per workgroup for long
+// rows.  hub_or sets hub k's bit; hub_store writes the words to hy[v].
+__device__ __forceinline__ void hub_or(u32* s_hy, u32 k) {
+  atomicOr(&s_hy[k >> 5], 1u << (k & 31u));
+}
+
+__device__ __forceinline__ void hub_store(const HubView& hv, const u32* s_hy, u32 v) {
+  uint4* d = reinterpret_cast<uint4*>(hv.hy + (size_t)v * kHubWords);
+#pragma unroll
+  for (u32 q = 0; q < kHubWords / 4; ++q)
+    d[q] = make_uint4(s_hy[4 * q], s_hy[4 * q + 1], s_hy[4 * q + 2], s_hy[4 * q + 3]);
+}
+
+// Hub work items of row v: N'(v) = its entries from sabove[v] on (len of them), in
+// pieces of kHubChunk, appended from *num_items on (one lane).
+__device__ __forceinline__ void hub_items(const HubView& hv, u32 v, u32 len) {
+  const u32 nch = (len + kHubChunk - 1) / kHubChunk;
+  if (nch == 0) return;
+  const u32 pos = atomicAdd(hv.num_items, nch);
+  for (u32 i = 0; i < nch; ++i)
+    if (pos + i < hv.cap) hv.items[pos + i] = make_uint2(v, i * kHubChunk);
+}
 
 // A row of at most kSplitLane entries, by one lane.  more[b] (wavefront-uniform) says
 // whether any lane's row is longer than 8 b entries; blocks of 8 past every lane's row
@@ -51,8 +88,8 @@ struct SplitOut {
 __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colidx,
                                                    const uint8_t* __restrict__ vinfo, u32 v,
                                                    u32 vx, u32 lo, u32 d, const bool* more,
-                                                   const SplitOut& o, u32* ns_out, u32* nh_out,
-                                                   u32* sr_out) {
+                                                   const SplitOut& o, u32 hl, u32* s_hy,
+                                                   u32* ns_out, u32* nh_out, u32* sr_out) {
   constexpr u32 B = 8, NB = kSplitLane / B;
   static_assert(kSplitLane <= 32, "flags are one 32-bit mask per lane");
   u32 w[kSplitLane];
@@ -66,7 +103,8 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
       }
     }
   }
-  u32 sm = 0, pm = 0, lm = 0, rm = 0;  // same level, partner, below v, record for w
+  // same level, partner, below v, record for w, w is a hub
+  u32 sm = 0, pm = 0, lm = 0, rm = 0, hm = 0;
 #pragma unroll
   for (u32 b = 0; b < NB; ++b) {
     if (more[b]) {
@@ -76,10 +114,12 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
         const u32 vw = vinfo[w[j]];
         const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
         const bool part = same && key_less(vw & 127u, w[j], vx & 127u, v);
+        const bool rec = same && !part && w[j] != v;
         sm |= (same ? 1u : 0u) << j;
         pm |= (part ? 1u : 0u) << j;
         lm |= (same && w[j] < v ? 1u : 0u) << j;
-        rm |= (same && !part && w[j] != v ? 1u : 0u) << j;
+        rm |= (rec ? 1u : 0u) << j;
+        hm |= (rec && (vw & 127u) >= hl ? 1u : 0u) << j;
       }
     }
   }
@@ -112,11 +152,36 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
 #pragma unroll
       for (u32 i = 0; i < B; ++i) {
         const u32 j = b * B + i;
-        if (idx[i] < o.m) {
+        if (idx[i] < o.m && !((hm >> j) & 1u)) {
           const u32 rs = (u32)__popc(sm & ((1u << j) - 1u));
           o.hrec[idx[i]] = make_uint4(w[j] > v ? lo + rs + 1 : lo + sr, lo + ns, lo + d, v);
         }
       }
+    }
+  }
+  // hub partners: H(v) in this lane's LDS slot, and v's hub work items
+  if (__ballot(hm != 0)) {
+    if (hm) {
+#pragma unroll
+      for (u32 q = 0; q < kHubWords; ++q) s_hy[q] = 0;
+    }
+#pragma unroll
+    for (u32 b = 0; b < NB; ++b) {
+      if (more[b] && __ballot((hm >> (b * B)) & 0xFFu) != 0) {
+        u32 hk[B];
+#pragma unroll
+        for (u32 i = 0; i < B; ++i) {
+          const u32 j = b * B + i;
+          hk[i] = (hm >> j) & 1u ? (u32)o.hub.hubidx[w[j]] : 0u;
+        }
+#pragma unroll
+        for (u32 i = 0; i < B; ++i)
+          if ((hm >> (b * B + i)) & 1u) hub_or(s_hy, hk[i]);
+      }
+    }
+    if (hm) {
+      hub_store(o.hub, s_hy, v);
+      hub_items(o.hub, v, d - sr);
     }
   }
   *ns_out = ns;
@@ -131,13 +196,13 @@ constexpr u32 kSplitReg = kSplitRegU * kWave;
 
 struct ChunkRegs {
   u32 w[kSplitRegU];
-  u32 sm, pm, lm, rm, nu;  // flag bits per u: same level, partner of v, same level below
-                           // v, record of v for w
+  u32 sm, pm, lm, rm, hm, nu;  // flag bits per u: same level, partner of v, same level
+                               // below v, record of v for w, w is a hub
 };
 
 __device__ __forceinline__ void chunk_load(const u32* __restrict__ colidx,
                                            const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
-                                           u32 lo, u32 c0, u32 cend, ChunkRegs& r) {
+                                           u32 lo, u32 c0, u32 cend, u32 hl, ChunkRegs& r) {
   constexpr u32 U = kSplitRegU;
   const u32 lane = lane_id();
   r.nu = min((cend - c0 + kWave - 1) / kWave, U);  // wavefront-uniform
@@ -148,7 +213,7 @@ __device__ __forceinline__ void chunk_load(const u32* __restrict__ colidx,
       r.w[u] = j < cend ? colidx[lo + j] : v;
     }
   }
-  r.sm = r.pm = r.lm = r.rm = 0;
+  r.sm = r.pm = r.lm = r.rm = r.hm = 0;
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
     if (u < r.nu) {
@@ -156,10 +221,12 @@ __device__ __forceinline__ void chunk_load(const u32* __restrict__ colidx,
       const u32 vw = vinfo[r.w[u]];
       const bool same = j < cend && ((vw ^ vx) & 0x80u) == 0;
       const bool part = same && key_less(vw & 127u, r.w[u], vx & 127u, v);
+      const bool rec = same && !part && r.w[u] != v;
       r.sm |= (same ? 1u : 0u) << u;
       r.pm |= (part ? 1u : 0u) << u;
       r.lm |= (same && r.w[u] < v ? 1u : 0u) << u;
-      r.rm |= (same && !part && r.w[u] != v ? 1u : 0u) << u;
+      r.rm |= (rec ? 1u : 0u) << u;
+      r.hm |= (rec && (vw & 127u) >= hl ? 1u : 0u) << u;
     }
   }
 }
@@ -180,7 +247,8 @@ __device__ __forceinline__ void chunk_count(const ChunkRegs& r, u32& ns, u32& nh
 // other-level ones from other_base + co of the row; ns / sr are the row's totals.
 __device__ __forceinline__ void chunk_write(const ChunkRegs& r, u32 v, u32 lo, u32 d, u32 c0,
                                             u32 cend, u32 same_base, u32 other_base, u32 ns,
-                                            u32 sr, const SplitOut& o, u32& cs, u32& co) {
+                                            u32 sr, const SplitOut& o, u32& cs, u32& co,
+                                            u32* s_hy, u32& nhub) {
   const u32 lane = lane_id();
   // the cursor atomics of the whole chunk are in flight before the first store
   u32 idx[kSplitRegU];
@@ -197,11 +265,17 @@ __device__ __forceinline__ void chunk_write(const ChunkRegs& r, u32 v, u32 lo, u
       const u32 ps = same_base + cs + mask_rank(ms);  // position in v's same part
       if (same) o.colidx2[lo + ps] = r.w[u];
       else if (in) o.colidx2[lo + other_base + co + mask_rank(mo)] = r.w[u];
-      if (idx[u] < o.m)
+      if (idx[u] < o.m && !((r.hm >> u) & 1u))
         o.hrec[idx[u]] = make_uint4(r.w[u] > v ? lo + ps + 1 : lo + sr, lo + ns, lo + d, v);
       cs += (u32)__popcll(ms);
       co += (u32)__popcll(mo);
     }
+  }
+  if (__ballot(r.hm != 0)) {
+    nhub += (u32)__popc(r.hm);
+#pragma unroll
+    for (u32 u = 0; u < kSplitRegU; ++u)
+      if (u < r.nu && ((r.hm >> u) & 1u)) hub_or(s_hy, o.hub.hubidx[r.w[u]]);
   }
 }
 
@@ -213,7 +287,10 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
                                                    u32* __restrict__ hcnt,
                                                    u32* __restrict__ long_rows,
                                                    u32* __restrict__ num_long) {
+  __shared__ u32 s_hy[256 * kHubWords];  // H(v) of the row of each lane
   const u32 lane = lane_id();
+  const u32 hl = hub_limit(o.hub);
+  u32* const my_hy = s_hy + threadIdx.x * kHubWords;
   const u32 nr = (n + kWave - 1) / kWave * kWave;  // whole wavefronts iterate together
   for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < nr; v += gridDim.x * blockDim.x) {
     u32 lo = 0, d = 0, vx = 0;
@@ -230,10 +307,10 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
     for (u32 b = 0; b < kSplitLane / 8; ++b) more[b] = __ballot(short_row && d > b * 8) != 0;
     if (short_row) {
       u32 ns, nh, sr;
-      split_lane_row_reg(colidx, vinfo, v, vx, lo, d, more, o, &ns, &nh, &sr);
+      split_lane_row_reg(colidx, vinfo, v, vx, lo, d, more, o, hl, my_hy, &ns, &nh, &sr);
       split[v] = lo + ns;
       sabove[v] = lo + sr;
-      hcnt[v] = nh;
+      hcnt[v] = nh | ((vx & 127u) >= hl ? kHubFlag : 0u);
     }
     // long rows go to the workgroup kernel
     const u32 pos = wave_append(num_long, lng);
@@ -245,26 +322,33 @@ __global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowp
       mm &= mm - 1;
       const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
       const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
-      u32 ns = 0, nh = 0, sr = 0, cs = 0, co = 0;
+      u32 ns = 0, nh = 0, sr = 0, cs = 0, co = 0, nhub = 0;
       ChunkRegs r;
+      // the slot of lane b (which split no lane row in this pass) gathers H(bv)
+      u32* const row_hy = s_hy + (threadIdx.x - lane + (u32)b) * kHubWords;
+      if (lane < kHubWords) row_hy[lane] = 0;
       if (bd <= kSplitReg) {
-        chunk_load(colidx, vinfo, bv, bvx, blo, 0, bd, r);
+        chunk_load(colidx, vinfo, bv, bvx, blo, 0, bd, hl, r);
         chunk_count(r, ns, nh, sr);
-        chunk_write(r, bv, blo, bd, 0, bd, 0, ns, ns, sr, o, cs, co);
+        chunk_write(r, bv, blo, bd, 0, bd, 0, ns, ns, sr, o, cs, co, row_hy, nhub);
       } else {
         for (u32 c0 = 0; c0 < bd; c0 += kSplitReg) {
-          chunk_load(colidx, vinfo, bv, bvx, blo, c0, bd, r);
+          chunk_load(colidx, vinfo, bv, bvx, blo, c0, bd, hl, r);
           chunk_count(r, ns, nh, sr);
         }
         for (u32 c0 = 0; c0 < bd; c0 += kSplitReg) {
-          chunk_load(colidx, vinfo, bv, bvx, blo, c0, bd, r);
-          chunk_write(r, bv, blo, bd, c0, bd, 0, ns, ns, sr, o, cs, co);
+          chunk_load(colidx, vinfo, bv, bvx, blo, c0, bd, hl, r);
+          chunk_write(r, bv, blo, bd, c0, bd, 0, ns, ns, sr, o, cs, co, row_hy, nhub);
         }
+      }
+      if (__ballot(nhub != 0) && (int)lane == b) {
+        hub_store(o.hub, row_hy, bv);  // the wavefront's LDS operations complete in order
+        hub_items(o.hub, bv, bd - sr);
       }
       if ((int)lane == b) {
         split[bv] = blo + ns;
         sabove[bv] = blo + sr;
-        hcnt[bv] = nh;
+        hcnt[bv] = nh | ((bvx & 127u) >= hl ? kHubFlag : 0u);
       }
     }
   }
@@ -284,13 +368,18 @@ __global__ void __launch_bounds__(kLongThreads) k_split_long(
     u32* __restrict__ split, u32* __restrict__ sabove, u32* __restrict__ hcnt) {
   __shared__ u32 s_cnt[3][kLongWaves];
   __shared__ u32 s_row;
+  __shared__ u32 s_hy[kHubWords];
+  __shared__ u32 s_any;
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   const u32 nl = *num_long;
+  const u32 hl = hub_limit(o.hub);
   while (true) {
     if (threadIdx.x == 0) {
       const u32 i = atomicAdd(next_long, 1u);
       s_row = i < nl ? long_rows[i] : kInf;
+      s_any = 0;
     }
+    if (threadIdx.x < kHubWords) s_hy[threadIdx.x] = 0;
     __syncthreads();
     const u32 v = s_row;
     if (v == kInf) break;
@@ -301,7 +390,7 @@ __global__ void __launch_bounds__(kLongThreads) k_split_long(
     u32 ns = 0, nh = 0, sr = 0;
     ChunkRegs r;
     for (u32 c0 = j0; c0 < j1; c0 += kSplitReg) {
-      chunk_load(colidx, vinfo, v, vx, lo, c0, j1, r);
+      chunk_load(colidx, vinfo, v, vx, lo, c0, j1, hl, r);
       chunk_count(r, ns, nh, sr);
     }
     if (lane == 0) {
@@ -317,25 +406,32 @@ __global__ void __launch_bounds__(kLongThreads) k_split_long(
       th += s_cnt[1][w];
       tsr += s_cnt[2][w];
     }
-    u32 cs = 0, co = 0;
+    u32 cs = 0, co = 0, nhub = 0;
     for (u32 c0 = j0; c0 < j1; c0 += kSplitReg) {
-      if (!one) chunk_load(colidx, vinfo, v, vx, lo, c0, j1, r);
-      chunk_write(r, v, lo, d, c0, j1, bs, ts + (j0 - bs), ts, tsr, o, cs, co);
+      if (!one) chunk_load(colidx, vinfo, v, vx, lo, c0, j1, hl, r);
+      chunk_write(r, v, lo, d, c0, j1, bs, ts + (j0 - bs), ts, tsr, o, cs, co, s_hy, nhub);
     }
+    nhub = wave_sum_u32(nhub);
+    if (lane == 0 && nhub) s_any = 1u;
+    __syncthreads();  // s_hy is complete
     if (threadIdx.x == 0) {
       split[v] = lo + ts;
       sabove[v] = lo + tsr;
-      hcnt[v] = th;
+      hcnt[v] = th | ((vx & 127u) >= hl ? kHubFlag : 0u);
+      if (s_any) {
+        hub_store(o.hub, s_hy, v);
+        hub_items(o.hub, v, d - tsr);
+      }
     }
-    __syncthreads();  // s_cnt and s_row are rewritten for the next row
+    __syncthreads();  // s_cnt, s_hy and s_row are rewritten for the next row
   }
 }
 
 void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n, u32 m,
                        u32* colidx2, u32* split, u32* sabove, u32* hcnt, u32* hcur, uint4* hrec,
-                       u32* long_rows, u32* counters, hipStream_t s) {
+                       u32* long_rows, u32* counters, const HubView& hv, hipStream_t s) {
   if (n == 0) return;
-  const SplitOut o{colidx2, hcur, hrec, m};
+  const SplitOut o{colidx2, hcur, hrec, m, hv};
   const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
   hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, s, rowptr, colidx, vinfo, n, o, split,
                      sabove, hcnt, long_rows, counters);
@@ -370,13 +466,16 @@ __global__ void __launch_bounds__(256) k_plan(const u32* __restrict__ rowptr,
     for (u32 k = 0; k < kPlanPer; ++k) {
       const u32 x = base + k * blockDim.x + threadIdx.x;
       u32 np = 0, d = 0;
+      bool hub = false;  // a hub's cover edges go to the hub pass
       if (x < n) {
         const u32 lo = rowptr[x];
-        np = hcnt[x];
+        const u32 hc = hcnt[x];
+        np = hc & ~kHubFlag;
+        hub = (hc & kHubFlag) != 0;
         d = rowptr[x + 1] - lo;
         bad += hcur[x] != lo + np ? 1u : 0u;
       }
-      const u32 c = np == 0 ? 0u : d <= p.lane_max ? 1u : d <= p.wave_max ? 2u : 3u;
+      const u32 c = np == 0 || hub ? 0u : d <= p.lane_max ? 1u : d <= p.wave_max ? 2u : 3u;
       cover += np;
       cls |= c << (2 * k);
       cnt[0] += c == 1u;

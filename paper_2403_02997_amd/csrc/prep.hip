@@ -196,21 +196,37 @@ void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n,
 }
 
 // ---- per-vertex info byte ------------------------------------------------------------
-__global__ void k_vinfo(const u32* __restrict__ rowptr, const u32* __restrict__ level, u32 n,
-                        uint8_t* __restrict__ vinfo, u32* __restrict__ hcur) {
+__global__ void __launch_bounds__(256) k_vinfo(const u32* __restrict__ rowptr,
+                                               const u32* __restrict__ level, u32 n,
+                                               uint8_t* __restrict__ vinfo,
+                                               u32* __restrict__ hcur,
+                                               u32* __restrict__ class_hist) {
+  __shared__ u32 s_hist[128];
+  if (class_hist) {
+    if (threadIdx.x < 128) s_hist[threadIdx.x] = 0;
+    __syncthreads();
+  }
   for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const u32 lo = rowptr[v];
     const u32 d = rowptr[v + 1] - lo;
-    vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | degree_class(d));
+    const u32 c = degree_class(d);
+    vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | c);
     hcur[v] = lo;
+    if (class_hist) atomicAdd(&s_hist[c], 1u);
+  }
+  if (class_hist) {
+    __syncthreads();
+    if (threadIdx.x < 128 && s_hist[threadIdx.x]) atomicAdd(&class_hist[threadIdx.x],
+                                                            s_hist[threadIdx.x]);
   }
 }
 
 void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
-                  hipStream_t s) {
+                  u32* class_hist, hipStream_t s) {
   if (n == 0) return;
   const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
-  hipLaunchKernelGGL(k_vinfo, dim3(g), dim3(256), 0, s, rowptr, level, n, vinfo, hcur);
+  hipLaunchKernelGGL(k_vinfo, dim3(g), dim3(256), 0, s, rowptr, level, n, vinfo, hcur,
+                     class_hist);
 }
 
 // ---- device-wide exclusive scan (u32) ------------------------------------------------

@@ -42,6 +42,38 @@ struct Plan {
   u32 num_long;     // rows split by a whole workgroup, and their work counter
   u32 next_long;
   u32 bad_records;  // vertices whose record cursor disagrees with hcnt (broken contract)
+  u32 hub_lim;      // degree class from which a vertex is a hub (0: no hubs)
+  u32 num_hubs;     // hubs, indexed 0 .. num_hubs - 1 in hublist
+  u32 num_hub_items;  // work items of the hub pass
+};
+
+// ---- hubs -------------------------------------------------------------------------
+// The cover edges staged under the highest-degree vertices (hubs) are counted by one
+// pass per partner y instead of one intersection per edge: y's pruned list N'(y) (its
+// other-level neighbours and its same-level neighbours above y) is streamed once, and
+// each entry w looks up the hub bitmask of w (bit k: w is in hub k's pruned list S(h_k))
+// against the mask H(y) of the hubs that stage y.  The hubs are the vertices of the top
+// degree classes, as many whole classes as fit in max_hubs, from class min_class up.
+struct HubParams {
+  u32 max_hubs;   // 0 (no hub pass) .. kMaxHubs
+  u32 min_class;  // smallest degree class a hub may have
+};
+constexpr u32 kMaxHubs = 256;
+constexpr u32 kHubWords = kMaxHubs / 32;  // words of H(y) per vertex
+constexpr u32 kHubChunk = 1024;           // entries of N'(y) per hub work item
+constexpr u32 kHubFlag = 0x80000000u;     // hcnt flag of a hub row (its edges go to the hub pass)
+
+// What the split needs for the hub pass.  lim: device word with the hub class
+// threshold (0: no hubs, then nothing else is read); hubidx: hub index per hub vertex;
+// hy: kHubWords words per vertex, written for the rows that have hub partners; items:
+// (y, offset into N'(y)) work items, at most cap, counted in *num_items.
+struct HubView {
+  const u32* lim;
+  const uint8_t* hubidx;
+  u32* hy;
+  uint2* items;
+  u32* num_items;
+  u32 cap;
 };
 
 struct Item {
@@ -55,8 +87,9 @@ void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_
 void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
                u32* parent, u32* mode, hipStream_t s);
 // vinfo[v] = (L(v) mod 2) << 7 | degree class; hcur[v] = rowptr[v] (the record cursors).
+// class_hist (128 words, zeroed; may be null): vertices per degree class.
 void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
-                  hipStream_t s);
+                  u32* class_hist, hipStream_t s);
 // Exclusive scan of in[0..count) into out[0..count] (out[count] = total); in may == out.
 // tmp needs scan_tmp_words(count) words.
 size_t scan_tmp_words(u32 count);
@@ -86,16 +119,33 @@ size_t bfs_big_cap(u32 n, u64 m);
 // hrec[rowptr[v] .. rowptr[v] + hcnt[v]) (absolute offsets into colidx2; .w = partner).
 // colidx2 and hrec hold m entries; hcur comes from launch_vinfo.  long_rows: n words of
 // scratch; counters: two words, zeroed before the launch.
+// Hub rows get hcnt[v] = |H+(v)| | kHubFlag and no records; a partner that is a hub
+// advances its cursor but its record is replaced by a bit of H(y) in hv.hy.
 void launch_split_rows(const u32* rowptr, const u32* colidx, const uint8_t* vinfo, u32 n, u32 m,
                        u32* colidx2, u32* split, u32* sabove, u32* hcnt, u32* hcur, uint4* hrec,
-                       u32* long_rows, u32* counters, hipStream_t s);
-// Also counts in plan->bad_records the vertices with hcur[v] != rowptr[v] + hcnt[v].
+                       u32* long_rows, u32* counters, const HubView& hv, hipStream_t s);
+// Also counts in plan->bad_records the vertices with hcur[v] != rowptr[v] + |H+(v)|.
 void launch_plan(const u32* rowptr, const u32* hcnt, const u32* hcur, u32 n, IsectParams p,
                  u32* lane_x, u32* wave_x, u32* block_x, u32* block_items, Plan* plan,
                  hipStream_t s);
 void launch_fill_items(const u32* rowptr, const u32* hcnt, const u32* block_x,
                        const u32* item_off, u32 nbx, IsectParams p, Item* items,
                        hipStream_t s);
+
+// ---- hub pass ----
+// Picks the hub class threshold from class_hist (plan->hub_lim) and numbers the hubs
+// (hubidx, hublist, plan->num_hubs).
+void launch_hub_select(const uint8_t* vinfo, u32 n, const u32* class_hist, HubParams hp,
+                       uint8_t* hubidx, u32* hublist, Plan* plan, hipStream_t s);
+// Words of the window cut table and of the hub bitmasks (per vertex) for nhubs hubs.
+size_t hub_cut_words(u32 nhubs, u32 n);
+u32 hub_mask_words(u32 nhubs);
+// Builds the hub bitmasks of all n vertices (hub_mask_words(nhubs) words each) and
+// counts the hub items' triangles into the c1 counter.
+void launch_hub_pass(const u32* rowptr, const u32* colidx2, const u32* split,
+                     const u32* sabove, const u32* hublist, u32 nhubs, u32 n, const u32* hy,
+                     const uint2* items, u32 nitems, u32* cuts, u32* hubmask, u64* ctr,
+                     hipStream_t s);
 
 // ---- intersection ----
 // The intersection launchers take the split's outputs in one struct.  pruned: count

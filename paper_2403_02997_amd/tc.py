@@ -43,6 +43,8 @@ EXPORTS = (
     "tc_validate_csr",
     "tc_set_isect_params",
     "tc_get_isect_params",
+    "tc_set_hub_params",
+    "tc_get_hub_params",
     "tc_profile_enable",
     "tc_profile_read",
     "tc_profile_step_name",
@@ -160,6 +162,10 @@ def load() -> ctypes.CDLL:
     lib.tc_set_isect_params.restype = i
     lib.tc_get_isect_params.argtypes = [ctypes.POINTER(u32)]
     lib.tc_get_isect_params.restype = i
+    lib.tc_set_hub_params.argtypes = [u32, u32]
+    lib.tc_set_hub_params.restype = i
+    lib.tc_get_hub_params.argtypes = [ctypes.POINTER(u32)]
+    lib.tc_get_hub_params.restype = i
     lib.tc_profile_enable.argtypes = [i]
     lib.tc_profile_enable.restype = i
     lib.tc_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), u32, ctypes.POINTER(u64), i]
@@ -316,6 +322,16 @@ def tc_set_isect_params(lane_max: int, wave_max: int, chunk: int, seg: int) -> N
 def tc_get_isect_params():
     arr = (ctypes.c_uint32 * 4)()
     _check(load().tc_get_isect_params(arr), "tc_get_isect_params")
+    return tuple(int(v) for v in arr)
+
+
+def tc_set_hub_params(max_hubs: int, min_degree: int) -> None:
+    _check(load().tc_set_hub_params(max_hubs, min_degree), "tc_set_hub_params")
+
+
+def tc_get_hub_params():
+    arr = (ctypes.c_uint32 * 2)()
+    _check(load().tc_get_hub_params(arr), "tc_get_hub_params")
     return tuple(int(v) for v in arr)
 
 

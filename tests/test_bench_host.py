@@ -1,5 +1,5 @@
-"""Host logic of bench.py: the algorithmic bytes of each intersection class, checked
-against a per-edge count written directly from the definitions (no GPU)."""
+"""Host logic of bench.py: the algorithmic bytes of each intersection class and the hub
+selection, checked against counts written directly from the definitions (no GPU)."""
 import numpy as np
 import pytest
 
@@ -8,18 +8,41 @@ import graphgen as gg
 import oracle
 
 
-def brute_class_bytes(g, level, lane_max, wave_max):
+def brute_hubs(d, max_hubs, min_degree):
+    """Among the thresholds c >= max(class(min_degree), 1), the vertex sets {class >= c}
+    with 1 .. max_hubs members; the hubs are the largest of them (none if there is none)."""
+    cls = bench.degree_class(d)
+    cmin = max(int(bench.degree_class(np.array([min_degree]))[0]), 1)
+    best = set()
+    for c in range(cmin, 128):
+        s = {v for v in range(len(d)) if cls[v] >= c}
+        if 1 <= len(s) <= max_hubs and len(s) > len(best):
+            best = s
+    return best
+
+
+def brute_class_bytes(g, level, lane_max, wave_max, hubs=frozenset()):
     """Cover edges {x, y} (same level, x the larger (degree class, ID) key) per class of
     d(x).  The lane class streams all of N(y) and stages N(x); the other classes stream
     y's neighbours that are on another level or above max(x, y), and stage x's
-    neighbours that are on another level or above x.  Each staged x counts once."""
+    neighbours that are on another level or above x.  Each staged x counts once.  Edges
+    with x a hub go to the hub pass: every partner y of a hub once streams its neighbours
+    on another level or above y, looking each up in a mask of nw words, and reads its own
+    mask; the masks take every hub's neighbours on another level or above it, and nw
+    words per vertex are written."""
     n = g.n
     rows = [g.colidx[g.rowptr[v]:g.rowptr[v + 1]].tolist() for v in range(n)]
     d = np.diff(g.rowptr.astype(np.int64))
     cls = bench.degree_class(d)
     par = [int(level[v]) & 1 for v in range(n)]
-    out = {k: {"cover_edges": 0, "bytes": 0} for k in ("isect_lane", "isect_wave", "isect_block")}
+    out = {k: {"cover_edges": 0, "bytes": 0}
+           for k in ("isect_lane", "isect_wave", "isect_block", "isect_hub")}
     staged = {k: set() for k in out}
+    hub_partners = set()
+
+    def pruned(v):
+        return sum(1 for w in rows[v] if par[w] != par[v] or w > v)
+
     for u in range(n):
         for v in rows[u]:
             if u < v and par[u] == par[v]:
@@ -27,6 +50,10 @@ def brute_class_bytes(g, level, lane_max, wave_max):
                     x, y = u, v
                 else:
                     x, y = v, u
+                if x in hubs:
+                    out["isect_hub"]["cover_edges"] += 1
+                    hub_partners.add(y)
+                    continue
                 name = ("isect_lane" if d[x] <= lane_max else
                         "isect_wave" if d[x] <= wave_max else "isect_block")
                 out[name]["cover_edges"] += 1
@@ -41,7 +68,11 @@ def brute_class_bytes(g, level, lane_max, wave_max):
             if name == "isect_lane":
                 out[name]["bytes"] += 4 * len(rows[x])
             else:
-                out[name]["bytes"] += 4 * sum(1 for w in rows[x] if par[w] != par[x] or w > x)
+                out[name]["bytes"] += 4 * pruned(x)
+    if hubs:
+        nw = 4 if len(hubs) <= 128 else 8
+        out["isect_hub"]["bytes"] = (sum((4 + 4 * nw) * pruned(y) + 4 * nw for y in hub_partners)
+                                     + sum(4 * pruned(h) for h in hubs) + 4 * nw * n)
     return out
 
 
@@ -57,3 +88,37 @@ def test_class_bytes_matches_definition(graph, params):
     want = brute_class_bytes(g, level, params[0], params[1])
     assert got == want
     assert sum(v["cover_edges"] for v in got.values()) > 0
+
+
+@pytest.mark.parametrize("graph,hubs", [
+    (lambda: gg.rmat(9, 8, seed=7), (7, 1)),
+    (lambda: gg.rmat(9, 8, seed=7), (200, 1)),
+    (lambda: gg.rmat(8, 16, seed=3), (256, 64)),
+    (lambda: gg.complete(12), (256, 1)),
+    (lambda: gg.complete(12), (5, 1)),
+])
+def test_hub_class_bytes_match_definition(graph, hubs):
+    g = graph()
+    level, _ = oracle.bfs_levels(g)
+    d = g.degrees()
+    hs = brute_hubs(d, *hubs)
+    assert set(np.nonzero(bench.hub_set(d, *hubs))[0].tolist()) == hs
+    got = bench.class_bytes(g, np.asarray(level).astype(np.uint32), (4, 24, 4096), hubs)
+    want = brute_class_bytes(g, level, 4, 24, hs)
+    assert got == want
+
+
+@pytest.mark.parametrize("max_hubs,min_degree", [(1, 1), (7, 1), (128, 1), (129, 1),
+                                                 (256, 1), (200, 64), (256, 4096), (0, 0)])
+def test_hub_selection_matches_definition(max_hubs, min_degree):
+    for g in (gg.rmat(10, 16, seed=5), gg.rmat(9, 8, seed=2), gg.star(40), gg.complete(9)):
+        d = g.degrees()
+        assert (set(np.nonzero(bench.hub_set(d, max_hubs, min_degree))[0].tolist())
+                == brute_hubs(d, max_hubs, min_degree))
+
+
+def test_gpu_hub_cases_reach_the_hub_pass():
+    """The hub settings of the GPU parity tests do select hubs on their R-MAT cases."""
+    for g in (gg.rmat(14, 32, 14), gg.rmat(16, 16, 16)):
+        for hubs in [(1, 1), (7, 1), (128, 1), (129, 1), (256, 1), (200, 64)]:
+            assert bench.hub_set(g.degrees(), *hubs).sum() > 0, (g.name, hubs)

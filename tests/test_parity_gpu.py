@@ -195,3 +195,55 @@ def test_count_reports_same_level_asymmetry(tc_lib):
     with pytest.raises(tc_lib.TCError) as e:
         tc_lib.tc_count(*tc_lib.to_device(s.rowptr, x))
     assert e.value.status == -4
+
+
+# ---- hub pass (tc_set_hub_params) -------------------------------------------------------
+# (max_hubs, min_degree): a single hub, hub sets either side of the 4- / 8-word mask
+# boundary (128 hubs), the default, and settings that leave some graphs without hubs.
+HUB_PARAMS = [(1, 1), (7, 1), (128, 1), (129, 1), (256, 1), (200, 64), (256, 4096), (0, 0)]
+HUB_CASES = ["rmat14_ef32", "rmat16", "book10000", "er16_d32", "union", "wheel500", "K40",
+             "star5000", "friendship100", "tripartite", "karate"]
+
+
+@pytest.mark.parametrize("hubs", HUB_PARAMS)
+@pytest.mark.parametrize("name", HUB_CASES)
+def test_hub_pass_gives_the_same_count(tc_lib, name, hubs):
+    import bench
+    g, r, _, _ = case(name)
+    nh = int(bench.hub_set(g.degrees(), *hubs).sum())
+    say(f"[parity] hub params {hubs} on {name}: {nh} hubs")
+    rp, ci = upload(g, tc_lib)
+    saved = tc_lib.tc_get_hub_params()
+    try:
+        tc_lib.tc_set_hub_params(*hubs)
+        got = [tc_lib.tc_count(rp, ci) for _ in range(2)]
+        stats, _ = tc_lib.tc_count_ex(rp, ci)  # never uses the hub pass
+    finally:
+        tc_lib.tc_set_hub_params(*saved)
+    assert got == [r.triangles] * 2
+    assert stats.triangles == r.triangles and stats.cover_edges == r.cover_edges
+
+
+def test_hub_partner_asymmetry_is_reported(tc_lib):
+    """Vertex 1 (leaves 4..13, the only hub with max_hubs = 1) and vertex 2 sit on level 1
+    under root 0; vertex 3 hangs off 2 on level 2.  Row 2 lists 1 but row 1 lists 3 in
+    place of 2 (a level-2 entry, no partner), so hub 1's cursor ends one past its own
+    partner count and the count stops with TC_ERR_INVALID_GRAPH."""
+    say("[parity] asymmetric hub partner")
+    e = [(0, 1), (0, 2), (1, 2), (2, 3)] + [(1, w) for w in range(4, 14)]
+    g = gg.from_edges(14, e, "hub_asym")
+    x = g.colidx.copy()
+    lo, hi = int(g.rowptr[1]), int(g.rowptr[2])
+    row = x[lo:hi]
+    assert list(row[:3]) == [0, 2, 4]
+    row[1] = 3
+    x[lo:hi] = row
+    saved = tc_lib.tc_get_hub_params()
+    try:
+        tc_lib.tc_set_hub_params(1, 1)
+        assert tc_lib.tc_count(*upload(g, tc_lib)) == 1  # the symmetric graph: one triangle
+        with pytest.raises(tc_lib.TCError) as err:
+            tc_lib.tc_count(*tc_lib.to_device(g.rowptr, x))
+    finally:
+        tc_lib.tc_set_hub_params(*saved)
+    assert err.value.status == -4
