@@ -12,9 +12,11 @@ input edges (undirected, after cleaning) x K / elapsed seconds.
 Alongside, per JSON line:
   roofline     : the dominant intersection kernel's algorithmic bytes per launch over its
                  average launch time, from HIP events recorded by the library on the
-                 kernel's own stream during the timed steps, against 8 TB/s HBM; traffic
-                 is the counter-measured HBM bytes per launch stored under profiles/ when
-                 the kernel source still matches, else null.
+                 kernel's own stream in --profile-steps step-timed calls after the timed
+                 steps (there the intersection classes run one after another), against
+                 8 TB/s HBM; traffic is the counter-measured HBM bytes per launch stored
+                 under profiles/ when the kernel sources and the class and hub settings
+                 still match, else null.
   cpu_baseline : the CPU oracle (CETC-SM, OpenMP) timed on this host on a bounded
                  sample of the same graph, extrapolated in the oracle's merge work.
 
@@ -23,9 +25,10 @@ Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, batch4096
 and serve (a Poisson stream of requests through the tc_serve_* server: p50/p99 latency
 and input edges/s, every result checked against the standalone count).
 
---autotune picks the intersection thresholds (tc_set_isect_params) on the workload
-itself before the warm-up, by the package's coordinate-descent autotuner; the chosen
-setting is in config.isect_params of every line either way.
+--autotune picks the intersection thresholds (tc_set_isect_params) and, for a single
+graph, the hub count (tc_set_hub_params) on the workload itself before the warm-up, by
+the package's coordinate-descent autotuner; the settings are in config.isect_params and
+config.hub_params of every line either way.
 
 Counter helpers (no bench line):
   --calibrate-copy MIB  runs a plain device-to-device copy of MIB MiB three times, the
@@ -77,9 +80,13 @@ def log(*a):
 
 
 def source_sha() -> str:
+    """Hash of every kernel source: any change to how the work is divided or done makes a
+    stored traffic record stale."""
     h = hashlib.sha256()
-    for f in ("intersect.hip", "tc_isect.h", "tc_device.h"):
-        h.update(open(os.path.join(CSRC, f), "rb").read())
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -179,7 +186,9 @@ def class_bytes(g, level: np.ndarray, params, hubs=(0, 0)) -> dict:
     return out
 
 
-def stored_traffic(workload: str, kernel: str):
+def stored_traffic(workload: str, kernel: str, settings: dict):
+    """Counter-measured HBM bytes per launch of `kernel` on `workload`, if recorded for the
+    current kernel sources and the same class and hub settings, else None."""
     path = os.path.join(PROFILES, "traffic.json")
     if not os.path.exists(path):
         return None
@@ -189,7 +198,14 @@ def stored_traffic(workload: str, kernel: str):
         return None
     if not rec or rec.get("source_sha") != source_sha():
         return None
+    if any(rec.get(k) != v for k, v in settings.items()):
+        return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def current_settings(tcm) -> dict:
+    return {"isect_params": list(tcm.tc_get_isect_params()),
+            "hub_params": list(tcm.tc_get_hub_params())}
 
 
 # ---- CPU baseline: the oracle on a bounded sample ----------------------------------------
@@ -261,8 +277,6 @@ def bench_single(args, tcm, torch):
     for i in range(args.warmup):
         tcm.tc_count(rp, ci)
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    tcm.tc_profile_read(reset=True)
-    tcm.tc_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     T = None
@@ -270,10 +284,19 @@ def bench_single(args, tcm, torch):
         T = tcm.tc_count(rp, ci)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tcm.tc_profile_enable(False)
-    prof, calls = tcm.tc_profile_read(reset=True)
     elapsed = t1 - t0
     log(f"[bench] timed {args.steps} steps: {elapsed * 1e3 / args.steps:.3f} ms/step")
+    # Step breakdown and roofline: further calls with step timing on.  The library then
+    # runs the intersection classes one after another on the caller's stream (in the
+    # timed steps the wavefront class and the hub pass run beside the workgroup class),
+    # so each step's events bracket its own kernels.
+    tcm.tc_profile_read(reset=True)
+    tcm.tc_profile_enable(True)
+    for _ in range(args.profile_steps):
+        assert tcm.tc_count(rp, ci) == T
+    tcm.tc_profile_enable(False)
+    prof, calls = tcm.tc_profile_read(reset=True)
+    log(f"[bench] {calls} step-timed calls")
 
     stats, level = tcm.tc_count_ex(rp, ci, want_levels=True)
     assert stats.triangles == T
@@ -288,8 +311,9 @@ def bench_single(args, tcm, torch):
     achieved = cb[dom]["bytes"] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(args.workload, KERNEL_OF_STEP[dom]),
+                "traffic": stored_traffic(args.workload, KERNEL_OF_STEP[dom], current_settings(tcm)),
                 "kernel": KERNEL_OF_STEP[dom], "avg_launch_ms": round(dom_ms, 4),
+                "timed_in": f"{calls} step-timed calls (intersection classes one after another)",
                 "algorithmic_bytes_per_launch": cb[dom]["bytes"]}
     out = {
         "metric": METRIC,
@@ -538,7 +562,7 @@ def _pmc_per_kernel(path: str, counter: str) -> dict:
     return {k: (sum(v) / len(v), len(v), max(v)) for k, v in acc.items()}
 
 
-def traffic_summary(args):
+def traffic_summary(args, settings: dict):
     mib = args.copy_mib
     copy_bytes = mib * (1 << 20)
     cf = _pmc_per_kernel(args.copy_fetch, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][2]
@@ -557,7 +581,7 @@ def traffic_summary(args):
             continue
         fb = fetch[k][0] * 1024 / f_fetch
         wb = write[k][0] * 1024 / f_write
-        rec[k] = {"source_sha": source_sha(), "hbm_bytes_per_launch": int(fb + wb),
+        rec[k] = {"source_sha": source_sha(), **settings, "hbm_bytes_per_launch": int(fb + wb),
                   "fetch_bytes": int(fb), "write_bytes": int(wb),
                   "fetch_kib_raw": round(fetch[k][0], 1), "write_kib_raw": round(write[k][0], 1),
                   "dispatches": fetch[k][1], "copy_factor_fetch": round(f_fetch, 5),
@@ -590,6 +614,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--isect", default="", metavar="LANE,WAVE,CHUNK,SEG",
                     help="intersection class parameters (tc_set_isect_params) for this run")
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="step-timed calls after the timed steps (step breakdown, roofline)")
     ap.add_argument("--hubs", default="", metavar="MAX_HUBS,MIN_DEGREE",
                     help="hub pass parameters (tc_set_hub_params) for this run; 0,0 turns it off")
     ap.add_argument("--autotune", action="store_true",
@@ -607,7 +633,14 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.traffic_summary:
-        traffic_summary(args)
+        # the settings of the counter runs: the library defaults unless given here too
+        import paper_2403_02997_amd as tcm
+        tcm.load()
+        if args.isect:
+            tcm.tc_set_isect_params(*[int(v) for v in args.isect.split(",")])
+        if args.hubs:
+            tcm.tc_set_hub_params(*[int(v) for v in args.hubs.split(",")])
+        traffic_summary(args, current_settings(tcm))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

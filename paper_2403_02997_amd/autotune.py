@@ -3,7 +3,9 @@
 The staged endpoint x of a cover edge goes to the lane class when d(x) <= lane_max, to
 the wavefront class when d(x) <= wave_max, else to the workgroup class, which stages
 x's entries in chunks of `chunk` keys and takes `seg` partners per work item
-(tc_set_isect_params).  The best setting depends on the degree distribution and on the
+(tc_set_isect_params); for a single graph, the cover edges staged under the up to
+max_hubs vertices of the top degree classes go to the hub pass instead
+(tc_set_hub_params).  The best setting depends on the degree distribution and on the
 device, so this module measures candidates on the caller's own graph (or batch) by
 coordinate descent: one parameter at a time over its candidate values, the others held
 at the best setting so far.  A setting changes only how the work is divided, never the
@@ -25,22 +27,39 @@ import torch
 
 from . import tc as _tc
 
-NAMES = ("lane_max", "wave_max", "chunk", "seg")
+# Settings are tuples in NAMES order: the four class thresholds, then (single graphs
+# only) the hub count.
+NAMES = ("lane_max", "wave_max", "chunk", "seg", "max_hubs")
 CANDIDATES = {
     "lane_max": (4, 8, 16, 32),
     "wave_max": (128, 256, 512),
     "chunk": (2048, 4096, 8192),
     "seg": (256, 512, 1024),
+    "max_hubs": (0, 32, 128, 256),
 }
-ORDER = ("wave_max", "lane_max", "chunk", "seg")
+ORDER = ("max_hubs", "wave_max", "lane_max", "chunk", "seg")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2403_02997_amd",
                              "autotune.json")
 
 
 def valid(p) -> bool:
-    """The range tc_set_isect_params accepts."""
-    lane_max, wave_max, chunk, seg = p
-    return (0 <= lane_max <= wave_max <= 512 and 0 < chunk <= 16384 and 0 < seg <= 1024)
+    """The range tc_set_isect_params (and tc_set_hub_params) accept."""
+    lane_max, wave_max, chunk, seg = p[:4]
+    hubs_ok = len(p) < 5 or 0 <= p[4] <= 256
+    return (0 <= lane_max <= wave_max <= 512 and 0 < chunk <= 16384 and 0 < seg <= 1024
+            and hubs_ok)
+
+
+def apply(p) -> None:
+    """Sets the library to setting p (4 values, or 5 with the hub count)."""
+    _tc.tc_set_isect_params(*p[:4])
+    if len(p) > 4:
+        _tc.tc_set_hub_params(int(p[4]), _tc.tc_get_hub_params()[1])
+
+
+def current(with_hubs: bool) -> tuple:
+    p = tuple(_tc.tc_get_isect_params())
+    return p + (_tc.tc_get_hub_params()[0],) if with_hubs else p
 
 
 def device_key() -> str:
@@ -77,13 +96,16 @@ def store_cache(path: str | None, db: dict) -> None:
 
 def descend(measure, start, order=ORDER, candidates=CANDIDATES):
     """Coordinate descent.  measure(params) -> (result, seconds); params are tuples in
-    NAMES order.  Returns (best params, best seconds, number of settings measured).
-    Raises RuntimeError when a setting's result differs from the first one's."""
+    NAMES order, as long as `start` (the names past its length are not tuned).  Returns
+    (best params, best seconds, number of settings measured).  Raises RuntimeError when
+    a setting's result differs from the first one's."""
     best = tuple(int(v) for v in start)
     ref, best_t = measure(best)
     tried = {best}
     for name in order:
         i = NAMES.index(name)
+        if i >= len(best):
+            continue
         for v in candidates[name]:
             cand = best[:i] + (int(v),) + best[i + 1:]
             if cand in tried or not valid(cand):
@@ -97,15 +119,17 @@ def descend(measure, start, order=ORDER, candidates=CANDIDATES):
     return best, best_t, len(tried)
 
 
-def _tune(key: str, run, reps: int, cache: str | None, refresh: bool) -> dict:
+def _tune(key: str, run, reps: int, cache: str | None, refresh: bool,
+          with_hubs: bool) -> dict:
     db = load_cache(cache)
     hit = db.get(key)
-    if hit and not refresh and valid(tuple(hit["params"])):
-        _tc.tc_set_isect_params(*hit["params"])
+    if (hit and not refresh and valid(tuple(hit["params"]))
+            and len(hit["params"]) == (5 if with_hubs else 4)):
+        apply(tuple(hit["params"]))
         return {"params": tuple(hit["params"]), "ms": hit["ms"], "measured": 0, "key": key}
 
     def measure(p):
-        _tc.tc_set_isect_params(*p)
+        apply(p)
         res, _ = run()  # warm-up (and the result)
         times = []
         for _ in range(max(reps, 1)):
@@ -115,13 +139,13 @@ def _tune(key: str, run, reps: int, cache: str | None, refresh: bool) -> dict:
             times.append(t)
         return res, min(times)
 
-    start = _tc.tc_get_isect_params()
+    start = current(with_hubs)
     try:
         best, best_t, n = descend(measure, start)
     except BaseException:
-        _tc.tc_set_isect_params(*start)
+        apply(start)
         raise
-    _tc.tc_set_isect_params(*best)
+    apply(best)
     db[key] = {"params": list(best), "ms": round(best_t * 1e3, 4)}
     store_cache(cache, db)
     return {"params": best, "ms": best_t * 1e3, "measured": n, "key": key}
@@ -129,21 +153,23 @@ def _tune(key: str, run, reps: int, cache: str | None, refresh: bool) -> dict:
 
 def autotune(rowptr: torch.Tensor, colidx: torch.Tensor, reps: int = 2,
              cache: str | None = DEFAULT_CACHE, refresh: bool = False) -> dict:
-    """Tunes and applies the thresholds for tc_count on this graph (device CSR tensors).
-    Returns {"params": (lane_max, wave_max, chunk, seg), "ms", "measured", "key"}."""
+    """Tunes and applies the thresholds and the hub count for tc_count on this graph
+    (device CSR tensors).  Returns {"params": (lane_max, wave_max, chunk, seg, max_hubs),
+    "ms", "measured", "key"}."""
     def run():
         t0 = time.perf_counter()
         c = _tc.tc_count(rowptr, colidx)  # blocking
         return c, time.perf_counter() - t0
 
     key = device_key() + "|" + workload_key("single", rowptr.numel() - 1, colidx.numel())
-    return _tune(key, run, reps, cache, refresh)
+    return _tune(key, run, reps, cache, refresh, with_hubs=True)
 
 
 def autotune_batch(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor, row_off: torch.Tensor,
                    col_off: torch.Tensor, workspace: torch.Tensor | None = None, reps: int = 2,
                    cache: str | None = DEFAULT_CACHE, refresh: bool = False) -> dict:
-    """Tunes and applies the thresholds for tc_count_batch on this batch."""
+    """Tunes and applies the thresholds for tc_count_batch on this batch (the batched
+    kernel has no hub pass)."""
     G = row_off.numel() - 1
     counts = torch.empty(max(G, 0), dtype=torch.int64, device=rowptr_cat.device)
 
@@ -157,4 +183,4 @@ def autotune_batch(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor, row_off: 
         return tuple(counts.cpu().tolist()), dt
 
     key = device_key() + "|" + workload_key("batch", rowptr_cat.numel(), colidx_cat.numel(), G)
-    return _tune(key, run, reps, cache, refresh)
+    return _tune(key, run, reps, cache, refresh, with_hubs=False)

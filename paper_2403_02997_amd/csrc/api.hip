@@ -62,6 +62,59 @@ void prepare_pool() {
   g_pool_ready[dev] = true;
 }
 
+// This thread's second stream on the current device (default priority), on which the
+// wavefront class and the hub pass run beside the workgroup class.  Null if it cannot be
+// created; the caller then stays on its own stream.
+hipStream_t side_stream() {
+  thread_local hipStream_t ss[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (!ss[dev] && hipStreamCreateWithFlags(&ss[dev], hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    ss[dev] = nullptr;
+  }
+  return ss[dev];
+}
+
+// Fork / join of the side stream: start() orders it after the work queued on the main
+// stream, join() (also run on destruction, before the workspace is released) orders the
+// main stream after everything queued on the side stream.
+struct SideFork {
+  hipStream_t s = nullptr, s2 = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool active = false;
+  bool start(hipStream_t main, hipStream_t side) {
+    s = main;
+    s2 = side;
+    if (!s2) return false;
+    for (hipEvent_t& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        e = nullptr;
+        return false;
+      }
+    if (hipEventRecord(ev[0], s) != hipSuccess || hipStreamWaitEvent(s2, ev[0], 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    active = true;
+    return true;
+  }
+  bool join() {
+    if (!active) return true;
+    active = false;
+    return hipEventRecord(ev[1], s2) == hipSuccess && hipStreamWaitEvent(s, ev[1], 0) == hipSuccess;
+  }
+  ~SideFork() {
+    if (!join()) (void)hipGetLastError();
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
+  }
+};
+
 struct DevAlloc {
   void* p = nullptr;
   hipStream_t s = nullptr;
@@ -308,7 +361,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     }
   }
   timer.mark();
-  launch_vinfo(rowptr, level, n, vinfo, hcur, hub_on ? chist : nullptr, s);
+  launch_vinfo(rowptr, level, n, vinfo, hcur, hub_on ? chist : nullptr, hp.min_class, s);
   if (hub_on) launch_hub_select(vinfo, n, chist, hp, hubidx, hublist, plan, s);
 
   // ---- a3: cover-edge extraction ----
@@ -342,20 +395,31 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     launch_fill_items(rowptr, hcnt, block_x, bitems, h_plan.num_block_x, prm, items, s);
   }
   const SplitView sv{colidx2, split, sabove, hcnt, hrec, tail4b};
+  launch_tail4(colidx, m, tail4, s);
+  launch_tail4(colidx2, m, tail4b, s);
+  TC_LAUNCHED();
+  // The workgroup class is bound by HBM streaming, the wavefront class and the hub pass
+  // by latency: the latter two run on the side stream, beside it (one after another
+  // while step timing is on).
+  SideFork fork;
+  const hipStream_t sw = !timer.on && fork.start(s, side_stream()) ? fork.s2 : s;
   timer.mark();
   launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
   timer.mark();
-  launch_tail4(colidx, m, tail4, s);
-  launch_tail4(colidx2, m, tail4b, s);
   launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
                      pruned && !tri, s);
   timer.mark();
   launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
-                    tri, pruned && !tri, s);
+                    tri, pruned && !tri, sw);
   timer.mark();
   launch_hub_pass(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hy, hitems,
-                  h_plan.num_hub_items, hcuts, hubmask, ctr, s);
+                  h_plan.num_hub_items, hcuts, hubmask, ctr, sw);
   timer.mark();
+  TC_LAUNCHED();
+  if (!fork.join()) {
+    (void)hipGetLastError();
+    return TC_ERR_HIP;
+  }
   // ---- a5: reduction ----
   launch_finalize(ctr, outc, s);
   timer.mark();

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_vinfo(const u32* __restrict__ rowptr,
                                                const u32* __restrict__ level, u32 n,
                                                uint8_t* __restrict__ vinfo,
                                                u32* __restrict__ hcur,
-                                               u32* __restrict__ class_hist) {
+                                               u32* __restrict__ class_hist, u32 hist_min) {
   __shared__ u32 s_hist[128];
   if (class_hist) {
     if (threadIdx.x < 128) s_hist[threadIdx.x] = 0;
@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(256) k_vinfo(const u32* __restrict__ rowptr,
     const u32 c = degree_class(d);
     vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | c);
     hcur[v] = lo;
-    if (class_hist) atomicAdd(&s_hist[c], 1u);
+    if (class_hist && c >= hist_min) atomicAdd(&s_hist[c], 1u);
   }
   if (class_hist) {
     __syncthreads();
@@ -222,11 +222,11 @@ __global__ void __launch_bounds__(256) k_vinfo(const u32* __restrict__ rowptr,
 }
 
 void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
-                  u32* class_hist, hipStream_t s) {
+                  u32* class_hist, u32 hist_min, hipStream_t s) {
   if (n == 0) return;
   const u32 g = min(cdiv(n, 256), (u32)num_cus() * 8);
   hipLaunchKernelGGL(k_vinfo, dim3(g), dim3(256), 0, s, rowptr, level, n, vinfo, hcur,
-                     class_hist);
+                     class_hist, hist_min);
 }
 
 // ---- device-wide exclusive scan (u32) ------------------------------------------------

@@ -87,9 +87,10 @@ void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_
 void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
                u32* parent, u32* mode, hipStream_t s);
 // vinfo[v] = (L(v) mod 2) << 7 | degree class; hcur[v] = rowptr[v] (the record cursors).
-// class_hist (128 words, zeroed; may be null): vertices per degree class.
+// class_hist (128 words, zeroed; may be null): vertices per degree class, for the
+// classes >= hist_min (the others stay 0).
 void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
-                  u32* class_hist, hipStream_t s);
+                  u32* class_hist, u32 hist_min, hipStream_t s);
 // Exclusive scan of in[0..count) into out[0..count] (out[count] = total); in may == out.
 // tmp needs scan_tmp_words(count) words.
 size_t scan_tmp_words(u32 count);

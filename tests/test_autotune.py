@@ -28,6 +28,19 @@ def test_descent_reaches_the_best_grid_point_of_a_separable_cost():
     assert all(at.valid(p) for p in seen)
 
 
+def test_descent_tunes_the_hub_count_when_given():
+    seen = []
+
+    def measure(p):
+        seen.append(p)
+        return 0, abs(p[4] - 128) + 0.001 * p[0]
+
+    best, _, _ = at.descend(measure, (16, 512, 4096, 1024, 256))
+    assert best[4] == 128 and all(len(p) == 5 for p in seen)
+    assert {p[4] for p in seen} == set(at.CANDIDATES["max_hubs"])
+    assert not at.valid((16, 512, 4096, 1024, 257))
+
+
 def test_descent_never_measures_an_invalid_setting():
     seen = []
 

@@ -13,8 +13,10 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture
 def restore_params(tc_lib):
     saved = tc_lib.tc_get_isect_params()
+    saved_hubs = tc_lib.tc_get_hub_params()
     yield
     tc_lib.tc_set_isect_params(*saved)
+    tc_lib.tc_set_hub_params(*saved_hubs)
 
 
 def test_autotune_single_graph(tc_lib, restore_params, tmp_path):
@@ -24,13 +26,16 @@ def test_autotune_single_graph(tc_lib, restore_params, tmp_path):
     rp, ci = tc_lib.to_device(g.rowptr, g.colidx)
     cache = str(tmp_path / "at.json")
     r = at.autotune(rp, ci, reps=1, cache=cache)
-    assert r["measured"] > 1 and at.valid(r["params"])
-    assert tc_lib.tc_get_isect_params() == tuple(r["params"])
+    assert r["measured"] > 1 and at.valid(r["params"]) and len(r["params"]) == 5
+    assert tc_lib.tc_get_isect_params() == tuple(r["params"][:4])
+    assert tc_lib.tc_get_hub_params()[0] == r["params"][4]
     assert tc_lib.tc_count(rp, ci) == T
     tc_lib.tc_set_isect_params(16, 512, 4096, 1024)
+    tc_lib.tc_set_hub_params(0, 4096)
     r2 = at.autotune(rp, ci, reps=1, cache=cache)
     assert r2["measured"] == 0 and tuple(r2["params"]) == tuple(r["params"])
-    assert tc_lib.tc_get_isect_params() == tuple(r["params"])
+    assert tc_lib.tc_get_isect_params() == tuple(r["params"][:4])
+    assert tc_lib.tc_get_hub_params()[0] == r["params"][4]
 
 
 def test_autotune_batch(tc_lib, restore_params, tmp_path):
