@@ -577,7 +577,7 @@ def traffic_summary(args, settings: dict):
     lines = [f"copy calibration: {mib} MiB device copy reads FETCH_SIZE {cf:.1f} KiB "
              f"(factor {f_fetch:.4f}) and WRITE_SIZE {cw:.1f} KiB (factor {f_write:.4f})"]
     for k in sorted(fetch):
-        if not k.startswith("k_isect") or k not in write:
+        if not k.startswith(("k_isect", "k_hub_count")) or k not in write:
             continue
         fb = fetch[k][0] * 1024 / f_fetch
         wb = write[k][0] * 1024 / f_write

@@ -34,6 +34,12 @@
  * Thread safety: calls on different streams may run concurrently; the library keeps no
  * mutable global state besides a per-device cache of the device properties and the
  * tuning set by tc_set_isect_params and tc_set_hub_params.
+ *
+ * Streams: on graphs of at least 2^22 stored entries, tc_count runs its wavefront-class
+ * intersections and its hub pass on a second stream that it creates for the call
+ * (default priority), ordered after the work queued on `stream`, joined back into it and
+ * destroyed before the call returns; everything else runs on `stream`.  The server's
+ * worker threads keep to their own streams.
  */
 #ifndef TC_H_
 #define TC_H_
@@ -150,7 +156,7 @@ size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows,
  * behind the upload of a much larger one.  The three paths overlap on the device.
  * Results equal tc_count's.  Each server drives the device that is current at
  * tc_serve_create with three host threads and three non-blocking streams of default
- * priority.
+ * priority; its tc_count calls keep to those streams (no second stream per call).
  */
 typedef struct tc_server tc_server;
 

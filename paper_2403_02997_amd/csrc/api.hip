@@ -21,6 +21,10 @@
 #include "tc_launch.h"
 
 namespace tc {
+
+thread_local bool t_side_on = true;  // see set_thread_side_stream
+void set_thread_side_stream(bool on) { t_side_on = on; }
+
 namespace {
 
 constexpr int kVersion = 10000;  // 1.0.0
@@ -62,34 +66,26 @@ void prepare_pool() {
   g_pool_ready[dev] = true;
 }
 
-// This thread's second stream on the current device (default priority), on which the
-// wavefront class and the hub pass run beside the workgroup class.  Null if it cannot be
-// created; the caller then stays on its own stream.
-hipStream_t side_stream() {
-  thread_local hipStream_t ss[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  if (!ss[dev] && hipStreamCreateWithFlags(&ss[dev], hipStreamNonBlocking) != hipSuccess) {
-    (void)hipGetLastError();
-    ss[dev] = nullptr;
-  }
-  return ss[dev];
-}
-
-// Fork / join of the side stream: start() orders it after the work queued on the main
-// stream, join() (also run on destruction, before the workspace is released) orders the
-// main stream after everything queued on the side stream.
+// Fork / join of a second stream (default priority) on which the wavefront class and the
+// hub pass run beside the workgroup class.  The stream lives for one call only: a
+// process has few hardware queues (four by default), and a stream kept alive would take
+// one of them for good, so that other long-lived streams (a server's workers) could end
+// up sharing a queue and waiting behind each other's kernels.  start() creates it and
+// orders it after the work queued on the main stream; join() (also run on destruction,
+// before the workspace is released) orders the main stream after everything queued on
+// it.  If anything fails, the caller stays on its own stream.
 struct SideFork {
   hipStream_t s = nullptr, s2 = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool active = false;
-  bool start(hipStream_t main, hipStream_t side) {
+  bool start(hipStream_t main) {
     s = main;
-    s2 = side;
-    if (!s2) return false;
+    if (!t_side_on) return false;
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      s2 = nullptr;
+      return false;
+    }
     for (hipEvent_t& e : ev)
       if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
@@ -112,8 +108,13 @@ struct SideFork {
     if (!join()) (void)hipGetLastError();
     for (hipEvent_t e : ev)
       if (e) hipEventDestroy(e);
+    if (s2) hipStreamDestroy(s2);  // its work is ordered before the main stream's next work
   }
 };
+
+// Calls below this many stored entries stay on one stream (the fork costs more than the
+// overlap saves).
+constexpr u32 kSideMinEntries = 1u << 22;
 
 struct DevAlloc {
   void* p = nullptr;
@@ -231,6 +232,74 @@ struct StepTimer {
   }
 };
 
+size_t hub_item_cap(u32 n, u32 m) { return (size_t)n + m / kHubChunk + 1; }
+
+// Device workspace of one single-graph call, carved from `base` in this order (every
+// array 256-byte aligned).  The control block (ctl .. outc) is contiguous so that one
+// memset clears it.  Returns the bytes needed; with base = nullptr only sizes.
+struct SingleWs {
+  u32 *tile_row, *parent, *level, *q0, *q1, *fb;
+  size_t fb_words;
+  u64* bfs_part;
+  u32* bigq0;
+  uint8_t* vinfo;
+  u32 *hcnt, *split, *sabove, *hcur, *scan_tmp;
+  uint4* hrec;
+  u32 *colidx2, *lane_x, *wave_x, *block_x, *bitems;
+  uint8_t* hubidx;
+  u32 *hublist, *hy, *hubmask;
+  uint2* hitems;
+  u32* hcuts;
+  BfsCtl* ctl;
+  Plan* plan;
+  u32* chist;
+  u64 *ctr, *outc;
+  u32 *tail4, *tail4b, *cc_mode;
+};
+
+size_t carve_single(void* base, u32 n, u32 m, bool hub_on, SingleWs* out) {
+  SingleWs w;
+  Carver c(base);
+  const u32 ntiles = (m + kTile - 1) / kTile;
+  w.tile_row = c.take<u32>(ntiles + 1);
+  w.parent = c.take<u32>(n);
+  w.level = c.take<u32>(n);
+  w.q0 = c.take<u32>(n);
+  w.q1 = c.take<u32>(n);                        // BFS queue, then the list of long rows
+  w.fb_words = 3 * (((size_t)n + 31) / 32);     // three frontier bitmaps
+  w.fb = c.take<u32>(w.fb_words);
+  w.bfs_part = c.take<u64>(bfs_part_words());   // per-workgroup BFS level totals
+  w.bigq0 = c.take<u32>(2 * bfs_big_cap(n, m));  // queues of big frontier vertices
+  w.vinfo = c.take<uint8_t>(n);
+  w.hcnt = c.take<u32>(n);
+  w.split = c.take<u32>(n);
+  w.sabove = c.take<u32>(n);
+  w.hcur = c.take<u32>(n);                      // record cursors
+  w.scan_tmp = c.take<u32>(scan_tmp_words(n));
+  w.hrec = c.take<uint4>(m);                    // partner records in place of the rows
+  w.colidx2 = c.take<u32>((size_t)m + 4);       // level-split rows, 4 readable padding entries
+  w.lane_x = c.take<u32>(n);
+  w.wave_x = c.take<u32>(n);
+  w.block_x = c.take<u32>(n);
+  w.bitems = c.take<u32>((size_t)n + 1);        // block items / offsets
+  w.hubidx = c.take<uint8_t>(hub_on ? n : 0);
+  w.hublist = c.take<u32>(hub_on ? kMaxHubs : 0);
+  w.hy = reinterpret_cast<u32*>(c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0));
+  w.hubmask = reinterpret_cast<u32*>(c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0));
+  w.hitems = c.take<uint2>(hub_on ? hub_item_cap(n, m) : 0);
+  w.hcuts = c.take<u32>(hub_on ? hub_cut_words(kMaxHubs, n) : 0);
+  w.ctl = c.take<BfsCtl>(1);
+  w.plan = c.take<Plan>(1);
+  w.chist = c.take<u32>(128);                   // degree-class histogram
+  w.ctr = c.take<u64>(kCounterSlots * kNumCtr);
+  w.outc = c.take<u64>(kNumCtr);
+  w.tail4 = c.take<u32>(4);
+  w.tail4b = c.take<u32>(4);                    // padded last quad of colidx2
+  w.cc_mode = c.take<u32>(4);
+  if (out) *out = w;
+  return c.off + 256;
+}
+
 // The whole single-graph pipeline.  `level_out` (device) may be null; `tri` (device,
 // zeroed by the caller) selects per-vertex attribution.
 int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s,
@@ -240,92 +309,52 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   // the hub pass serves the pruned count only (per-vertex and c1 / c2 tallies stay per edge)
   const HubParams hp{pruned && !tri ? g_hub_max : 0u, host_degree_class(g_hub_min_degree)};
   const bool hub_on = hp.max_hubs > 0;
-  const size_t hub_cap = hub_on ? (size_t)n + m / kHubChunk + 1 : 0;
-  const size_t hub_cuts = hub_on ? hub_cut_words(hp.max_hubs, n) : 0;
-  const u32 ntiles = (m + kTile - 1) / kTile;
+  const size_t hub_cap = hub_on ? hub_item_cap(n, m) : 0;
   const u32 max_s = m / 2;
   // ---- workspace ----
-  size_t bytes = 0;
-  {
-    Carver c(nullptr);
-    c.take<u32>(ntiles + 1);         // tile_row
-    c.take<u32>(n);                  // parent
-    c.take<u32>(n);                  // level
-    c.take<u32>(n);                  // queue0
-    c.take<u32>(n);                  // queue1
-    c.take<u32>(3 * (((size_t)n + 31) / 32));  // frontier bitmaps
-    c.take<u64>(bfs_part_words());   // per-workgroup BFS level totals
-    c.take<u32>(2 * bfs_big_cap(n, m));  // queues of big frontier vertices
-    c.take<uint8_t>(n);              // vinfo
-    c.take<u32>(n);                  // hcnt
-    c.take<u32>(n);                  // split
-    c.take<u32>(n);                  // sabove
-    c.take<u32>(n);                  // hcur (record cursors)
-    c.take<u32>(scan_tmp_words(n));  // scan tmp
-    c.take<uint4>(m);                // hrec (partner records in place of the rows)
-    c.take<u32>((size_t)m + 4);      // colidx2 (rows split by level), 4 readable padding entries
-    c.take<u32>(n);                  // lane_x
-    c.take<u32>(n);                  // wave_x
-    c.take<u32>(n);                  // block_x
-    c.take<u32>((size_t)n + 1);      // block items / offsets
-    c.take<uint8_t>(hub_on ? n : 0);                  // hubidx
-    c.take<u32>(hub_on ? kMaxHubs : 0);               // hublist
-    c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0);  // H(y)
-    c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0);  // hub masks M(w)
-    c.take<uint2>(hub_cap);                           // hub work items
-    c.take<u32>(hub_cuts);                            // hub window cuts
-    c.take<BfsCtl>(1);
-    c.take<Plan>(1);
-    c.take<u32>(128);                // degree-class histogram
-    c.take<u64>(kCounterSlots * kNumCtr);
-    c.take<u64>(kNumCtr);
-    c.take<u32>(4);
-    c.take<u32>(4);                  // padded last quad of colidx2
-    c.take<u32>(4);                  // cc mode
-    bytes = c.off + 256;
-  }
+  const size_t bytes = carve_single(nullptr, n, m, hub_on, nullptr);
   DevAlloc ws;
   int rc = alloc_async(ws, bytes, s);
   if (rc) return rc;
-  Carver c(ws.p);
-  u32* tile_row = c.take<u32>(ntiles + 1);
-  u32* parent = c.take<u32>(n);
-  u32* level = c.take<u32>(n);
-  u32* q0 = c.take<u32>(n);
-  u32* q1 = c.take<u32>(n);
-  const size_t fb_words = 3 * (((size_t)n + 31) / 32);
-  u32* fb = c.take<u32>(fb_words);
-  u64* bfs_part = c.take<u64>(bfs_part_words());
-  u32* bigq0 = c.take<u32>(2 * bfs_big_cap(n, m));
+  SingleWs w;
+  carve_single(ws.p, n, m, hub_on, &w);
+  u32* tile_row = w.tile_row;
+  u32* parent = w.parent;
+  u32* level = w.level;
+  u32* q0 = w.q0;
+  u32* q1 = w.q1;
+  const size_t fb_words = w.fb_words;
+  u32* fb = w.fb;
+  u64* bfs_part = w.bfs_part;
+  u32* bigq0 = w.bigq0;
   u32* bigq1 = bigq0 + bfs_big_cap(n, m);
-  uint8_t* vinfo = c.take<uint8_t>(n);
-  u32* hcnt = c.take<u32>(n);
-  u32* split = c.take<u32>(n);
-  u32* sabove = c.take<u32>(n);
-  u32* hcur = c.take<u32>(n);
-  u32* scan_tmp = c.take<u32>(scan_tmp_words(n));
-  uint4* hrec = c.take<uint4>(m);
-  u32* colidx2 = c.take<u32>((size_t)m + 4);
-  u32* lane_x = c.take<u32>(n);
-  u32* wave_x = c.take<u32>(n);
-  u32* block_x = c.take<u32>(n);
-  u32* bitems = c.take<u32>((size_t)n + 1);
-  uint8_t* hubidx = c.take<uint8_t>(hub_on ? n : 0);
-  u32* hublist = c.take<u32>(hub_on ? kMaxHubs : 0);
-  u32* hy = reinterpret_cast<u32*>(c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0));
-  u32* hubmask = reinterpret_cast<u32*>(c.take<uint4>(hub_on ? (size_t)n * kHubWords / 4 : 0));
-  uint2* hitems = c.take<uint2>(hub_cap);
-  u32* hcuts = c.take<u32>(hub_cuts);
-  // control block: ctl, plan, histogram, counters, result are contiguous and cleared together
-  BfsCtl* ctl = c.take<BfsCtl>(1);
-  Plan* plan = c.take<Plan>(1);
-  u32* chist = c.take<u32>(128);
-  u64* ctr = c.take<u64>(kCounterSlots * kNumCtr);
-  u64* outc = c.take<u64>(kNumCtr);
+  uint8_t* vinfo = w.vinfo;
+  u32* hcnt = w.hcnt;
+  u32* split = w.split;
+  u32* sabove = w.sabove;
+  u32* hcur = w.hcur;
+  u32* scan_tmp = w.scan_tmp;
+  uint4* hrec = w.hrec;
+  u32* colidx2 = w.colidx2;
+  u32* lane_x = w.lane_x;
+  u32* wave_x = w.wave_x;
+  u32* block_x = w.block_x;
+  u32* bitems = w.bitems;
+  uint8_t* hubidx = w.hubidx;
+  u32* hublist = w.hublist;
+  u32* hy = w.hy;
+  u32* hubmask = w.hubmask;
+  uint2* hitems = w.hitems;
+  u32* hcuts = w.hcuts;
+  BfsCtl* ctl = w.ctl;
+  Plan* plan = w.plan;
+  u32* chist = w.chist;
+  u64* ctr = w.ctr;
+  u64* outc = w.outc;
   const size_t ctl_bytes = (char*)(outc + kNumCtr) - (char*)ctl;
-  u32* tail4 = c.take<u32>(4);
-  u32* tail4b = c.take<u32>(4);
-  u32* cc_mode = c.take<u32>(4);
+  u32* tail4 = w.tail4;
+  u32* tail4b = w.tail4b;
+  u32* cc_mode = w.cc_mode;
   if (level_out) level = level_out;
 
   TC_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, s));
@@ -402,7 +431,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   // by latency: the latter two run on the side stream, beside it (one after another
   // while step timing is on).
   SideFork fork;
-  const hipStream_t sw = !timer.on && fork.start(s, side_stream()) ? fork.s2 : s;
+  const hipStream_t sw = !timer.on && m >= kSideMinEntries && fork.start(s) ? fork.s2 : s;
   timer.mark();
   launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
   timer.mark();
@@ -444,6 +473,13 @@ int check_args(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint6
 }
 
 }  // namespace
+
+size_t single_call_bytes(u32 n, u64 m) {
+  const IsectParams prm = g_params;
+  const size_t items = (size_t)n + m / prm.seg + 1;  // workgroup items (allocated after planning)
+  return carve_single(nullptr, n, (u32)m, g_hub_max > 0, nullptr) + sizeof(Item) * items + 256;
+}
+
 }  // namespace tc
 
 using namespace tc;

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/tc.h"
+#include "tc_launch.h"
 
 namespace tc {
 namespace {
@@ -48,10 +49,10 @@ struct Request {
 
 inline uint64_t csr_bytes(uint32_t n, uint64_t m) { return 4ull * ((uint64_t)n + 1) + 4ull * m; }
 
-// Device bytes a request holds while admitted.  The single-graph path needs about
-// 41 bytes per vertex and 2 per stored entry of scratch, plus its work items.
+// Device bytes a request holds while admitted: its CSR and, on the single-graph path,
+// what the tc_count call allocates.
 inline uint64_t single_footprint(uint32_t n, uint64_t m) {
-  return csr_bytes(n, m) + 48ull * n + 3ull * m + (1ull << 20);
+  return csr_bytes(n, m) + single_call_bytes(n, m);
 }
 inline uint64_t batched_footprint(uint32_t n, uint64_t m) {
   return csr_bytes(n, m) + 21ull * ((uint64_t)n + 1) + 8ull * m + 64;
@@ -232,6 +233,7 @@ struct tc_server {
 
   void single_loop(int k) {
     (void)hipSetDevice(device);
+    set_thread_side_stream(false);  // this thread's stream is one of the server's three
     while (true) {
       Request r;
       {
