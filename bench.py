@@ -61,7 +61,7 @@ CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
 KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>",
                   "isect_wave": "k_isect_wave<false, true, true>",
                   "isect_block": "k_isect_block<false, true, true>",
-                  "isect_hub": "k_hub_count<8>"}
+                  "isect_hub": "k_hub_count<8u>"}
 
 WORKLOAD_TEXT = {
     "rmat10": "R-MAT scale 10, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1000",

@@ -247,3 +247,34 @@ def test_hub_partner_asymmetry_is_reported(tc_lib):
     finally:
         tc_lib.tc_set_hub_params(*saved)
     assert err.value.status == -4
+
+
+def test_concurrent_counts_on_two_streams(tc_lib):
+    """Two host threads count graphs of more than 2^22 entries at once, each on its own
+    stream (each call forks and joins its own side stream): every result is exact."""
+    import threading
+    cases = [case("rmat17_ef32"), case("rmat17_ef32")]
+    for g, _, _, _ in cases:
+        assert g.nnz >= 1 << 22
+    say("[parity] concurrent tc_count on two streams")
+    dev = [upload(g, tc_lib) for g, _, _, _ in cases]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    got = [[], []]
+    errors = []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                for _ in range(6):
+                    got[i].append(tc_lib.tc_count(*dev[i], stream=streams[i]))
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not errors, errors
+    for i, (g, r, _, _) in enumerate(cases):
+        assert got[i] == [r.triangles] * 6, (g.name, got[i])
