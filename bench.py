@@ -80,11 +80,12 @@ def log(*a):
 
 
 def source_sha() -> str:
-    """Hash of every kernel source: any change to how the work is divided or done makes a
-    stored traffic record stale."""
+    """Hash of every source that defines a kernel or its launch shape (all of csrc but the
+    host-side call orchestration of api.hip and serve.hip): any change to how the work is
+    divided or done makes a stored traffic record stale."""
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h")) and f not in ("api.hip", "serve.hip"):
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
@@ -104,11 +105,12 @@ def degree_class(d: np.ndarray) -> np.ndarray:
 
 
 def hub_set(d: np.ndarray, max_hubs: int, min_degree: int) -> np.ndarray:
-    """The hubs of tc_count's hub pass (tc_set_hub_params): the vertices of degree class
-    >= c*, c* the smallest class >= max(class(min_degree), 1) whose vertices and those of
-    the classes above number between 1 and max_hubs (no hubs if there is none)."""
+    """The hubs of tc_count's hub pass (tc_set_hub_params): none on graphs of fewer than
+    1024 * min_degree stored entries; else the vertices of degree class >= c*, c* the
+    smallest class >= max(class(min_degree), 1) whose vertices and those of the classes
+    above number between 1 and max_hubs (no hubs if there is none)."""
     cls = degree_class(d)
-    if max_hubs == 0 or len(d) == 0:
+    if max_hubs == 0 or len(d) == 0 or int(np.sum(d, dtype=np.int64)) < 1024 * min_degree:
         return np.zeros(len(d), dtype=bool)
     suf = np.cumsum(np.bincount(cls, minlength=128)[::-1])[::-1]
     cmin = max(int(degree_class(np.array([min_degree]))[0]), 1)

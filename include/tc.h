@@ -248,7 +248,8 @@ int tc_get_isect_params(uint32_t* out4);
  * edges staged under a hub are not intersected one by one: for each partner y the pass
  * streams y's other-level neighbours and its same-level neighbours above y once and looks
  * each one up in a per-vertex bit mask of the hubs whose pruned list holds it, masked
- * with the hubs that stage y.  max_hubs = 0 turns the pass off.  tc_count_ex and
+ * with the hubs that stage y.  The pass runs on graphs of at least 1024 * min_degree
+ * stored entries (2^22 by default); max_hubs = 0 turns it off.  tc_count_ex and
  * tc_count_per_vertex never use it.  Default {256, 4096}; process-wide, change it only
  * while no count is running; max_hubs > 256 gives TC_ERR_INVALID_ARG.
  * Workspace of tc_count with the pass on: 64 bytes per vertex more, plus 8 bytes per

@@ -177,6 +177,7 @@ u32 host_degree_class(u32 d) {
 // Hub pass: up to 256 hubs of degree at least 4096 (by class).
 constexpr u32 kDefaultHubs = kMaxHubs;
 constexpr u32 kDefaultHubDegree = 4096;
+constexpr u64 kHubEntriesPerDegree = 1024;
 u32 g_hub_max = kDefaultHubs;
 u32 g_hub_min_degree = kDefaultHubDegree;
 
@@ -306,8 +307,12 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
                u32* level_out, u64* tri, bool pruned, RunOut* out) {
   prepare_pool();
   const IsectParams prm = g_params;
-  // the hub pass serves the pruned count only (per-vertex and c1 / c2 tallies stay per edge)
-  const HubParams hp{pruned && !tri ? g_hub_max : 0u, host_degree_class(g_hub_min_degree)};
+  // the hub pass serves the pruned count only (per-vertex and c1 / c2 tallies stay per
+  // edge), on graphs of at least kHubEntriesPerDegree stored entries per unit of the hub
+  // degree floor (smaller ones cannot give hubs enough partners to pay for the pass)
+  const bool hub_size = (u64)m >= (u64)kHubEntriesPerDegree * g_hub_min_degree;
+  const HubParams hp{pruned && !tri && hub_size ? g_hub_max : 0u,
+                     host_degree_class(g_hub_min_degree)};
   const bool hub_on = hp.max_hubs > 0;
   const size_t hub_cap = hub_on ? hub_item_cap(n, m) : 0;
   const u32 max_s = m / 2;

@@ -9,8 +9,11 @@ import oracle
 
 
 def brute_hubs(d, max_hubs, min_degree):
-    """Among the thresholds c >= max(class(min_degree), 1), the vertex sets {class >= c}
-    with 1 .. max_hubs members; the hubs are the largest of them (none if there is none)."""
+    """No hubs below 1024 * min_degree stored entries.  Else, among the thresholds
+    c >= max(class(min_degree), 1), the vertex sets {class >= c} with 1 .. max_hubs
+    members; the hubs are the largest of them (none if there is none)."""
+    if sum(int(v) for v in d) < 1024 * min_degree:
+        return set()
     cls = bench.degree_class(d)
     cmin = max(int(bench.degree_class(np.array([min_degree]))[0]), 1)
     best = set()
@@ -111,7 +114,8 @@ def test_hub_class_bytes_match_definition(graph, hubs):
 @pytest.mark.parametrize("max_hubs,min_degree", [(1, 1), (7, 1), (128, 1), (129, 1),
                                                  (256, 1), (200, 64), (256, 4096), (0, 0)])
 def test_hub_selection_matches_definition(max_hubs, min_degree):
-    for g in (gg.rmat(10, 16, seed=5), gg.rmat(9, 8, seed=2), gg.star(40), gg.complete(9)):
+    for g in (gg.rmat(10, 16, seed=5), gg.rmat(9, 8, seed=2), gg.star(40), gg.complete(9),
+              gg.complete(40)):
         d = g.degrees()
         assert (set(np.nonzero(bench.hub_set(d, max_hubs, min_degree))[0].tolist())
                 == brute_hubs(d, max_hubs, min_degree))

@@ -225,13 +225,15 @@ def test_hub_pass_gives_the_same_count(tc_lib, name, hubs):
 
 
 def test_hub_partner_asymmetry_is_reported(tc_lib):
-    """Vertex 1 (leaves 4..13, the only hub with max_hubs = 1) and vertex 2 sit on level 1
+    """Vertex 1 (leaves 4..599, the only hub with max_hubs = 1; the graph's 1200 stored
+    entries reach the pass's size floor of 1024 * min_degree) and vertex 2 sit on level 1
     under root 0; vertex 3 hangs off 2 on level 2.  Row 2 lists 1 but row 1 lists 3 in
     place of 2 (a level-2 entry, no partner), so hub 1's cursor ends one past its own
     partner count and the count stops with TC_ERR_INVALID_GRAPH."""
     say("[parity] asymmetric hub partner")
-    e = [(0, 1), (0, 2), (1, 2), (2, 3)] + [(1, w) for w in range(4, 14)]
-    g = gg.from_edges(14, e, "hub_asym")
+    e = [(0, 1), (0, 2), (1, 2), (2, 3)] + [(1, w) for w in range(4, 600)]
+    g = gg.from_edges(600, e, "hub_asym")
+    assert g.nnz >= 1024
     x = g.colidx.copy()
     lo, hi = int(g.rowptr[1]), int(g.rowptr[2])
     row = x[lo:hi]
