@@ -431,24 +431,48 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   const SplitView sv{colidx2, split, sabove, hcnt, hrec, tail4b};
   launch_tail4(colidx, m, tail4, s);
   launch_tail4(colidx2, m, tail4b, s);
+  // the hub masks are built before the fork: their window kernel needs more LDS than a
+  // compute unit has left beside a workgroup-class workgroup, so beside it it would wait
+  // for the workgroup class to drain (with step timing on they run in the hub step)
+  const bool hubs = h_plan.num_hubs > 0 && h_plan.num_hub_items > 0;
+  if (hubs && !timer.on)
+    launch_hub_masks(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hcuts, hubmask,
+                     s);
   TC_LAUNCHED();
-  // The workgroup class is bound by HBM streaming, the wavefront class and the hub pass
-  // by latency: the latter two run on the side stream, beside it (one after another
-  // while step timing is on).
+  // The workgroup class is bound by HBM streaming, the wavefront class and the hub count
+  // by latency: the latter two run on the side stream, beside it (all on the caller's
+  // stream, one after another, while step timing is on).
   SideFork fork;
   const hipStream_t sw = !timer.on && m >= kSideMinEntries && fork.start(s) ? fork.s2 : s;
-  timer.mark();
-  launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
-  timer.mark();
-  launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
-                     pruned && !tri, s);
-  timer.mark();
-  launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
-                    tri, pruned && !tri, sw);
-  timer.mark();
-  launch_hub_pass(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hy, hitems,
-                  h_plan.num_hub_items, hcuts, hubmask, ctr, sw);
-  timer.mark();
+  if (sw != s) {
+    // side stream first: the hub count and the wavefront class take compute units while
+    // the workgroup class (persistent workgroups that hold their units to the end) ramps up
+    if (hubs)
+      launch_hub_count(rowptr, colidx2, sabove, h_plan.num_hubs, hy, hubmask, hitems,
+                       h_plan.num_hub_items, ctr, sw);
+    launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
+                      tri, pruned && !tri, sw);
+    launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
+    launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
+                       pruned && !tri, s);
+  } else {
+    timer.mark();
+    launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
+    timer.mark();
+    launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
+                       pruned && !tri, s);
+    timer.mark();
+    launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
+                      tri, pruned && !tri, s);
+    timer.mark();
+    if (hubs && timer.on)
+      launch_hub_masks(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hcuts, hubmask,
+                       s);
+    if (hubs)
+      launch_hub_count(rowptr, colidx2, sabove, h_plan.num_hubs, hy, hubmask, hitems,
+                       h_plan.num_hub_items, ctr, s);
+    timer.mark();
+  }
   TC_LAUNCHED();
   if (!fork.join()) {
     (void)hipGetLastError();

@@ -234,29 +234,35 @@ __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowpt
   }
 }
 
-void launch_hub_pass(const u32* rowptr, const u32* colidx2, const u32* split,
-                     const u32* sabove, const u32* hublist, u32 nhubs, u32 n, const u32* hy,
-                     const uint2* items, u32 nitems, u32* cuts, u32* hubmask, u64* ctr,
-                     hipStream_t s) {
-  if (nhubs == 0 || nitems == 0 || n == 0) return;
+void launch_hub_masks(const u32* rowptr, const u32* colidx2, const u32* split,
+                      const u32* sabove, const u32* hublist, u32 nhubs, u32 n, u32* cuts,
+                      u32* hubmask, hipStream_t s) {
+  if (nhubs == 0 || n == 0) return;
   const u32 nw = hub_mask_words(nhubs);
   const u32 win = hub_window(nw), nwin = hub_windows(n, nw);
   const u32 ncut = 2 * nhubs * (nwin + 1);
   hipLaunchKernelGGL(k_hub_cuts, dim3(min(cdiv(ncut, 256), (u32)num_cus() * 8)), dim3(256), 0,
                      s, rowptr, colidx2, split, sabove, hublist, 2 * nhubs, nwin, win, cuts);
   const u32 gm = min(nwin, (u32)num_cus() * 4);
-  const u32 gc = min(cdiv(nitems, 256 / kWave), (u32)num_cus() * 8);
-  if (nw == 4) {
+  if (nw == 4)
     hipLaunchKernelGGL(k_hub_mask<4>, dim3(gm), dim3(kHubThreads), 0, s, colidx2, cuts, nhubs, n,
                        nwin, hubmask);
-    hipLaunchKernelGGL(k_hub_count<4>, dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, hy,
-                       hubmask, items, nitems, ctr);
-  } else {
+  else
     hipLaunchKernelGGL(k_hub_mask<8>, dim3(gm), dim3(kHubThreads), 0, s, colidx2, cuts, nhubs, n,
                        nwin, hubmask);
+}
+
+void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove, u32 nhubs,
+                      const u32* hy, const u32* hubmask, const uint2* items, u32 nitems,
+                      u64* ctr, hipStream_t s) {
+  if (nhubs == 0 || nitems == 0) return;
+  const u32 gc = min(cdiv(nitems, 256 / kWave), (u32)num_cus() * 8);
+  if (hub_mask_words(nhubs) == 4)
+    hipLaunchKernelGGL(k_hub_count<4>, dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, hy,
+                       hubmask, items, nitems, ctr);
+  else
     hipLaunchKernelGGL(k_hub_count<8>, dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, hy,
                        hubmask, items, nitems, ctr);
-  }
 }
 
 }  // namespace tc

@@ -141,12 +141,15 @@ void launch_hub_select(const uint8_t* vinfo, u32 n, const u32* class_hist, HubPa
 // Words of the window cut table and of the hub bitmasks (per vertex) for nhubs hubs.
 size_t hub_cut_words(u32 nhubs, u32 n);
 u32 hub_mask_words(u32 nhubs);
-// Builds the hub bitmasks of all n vertices (hub_mask_words(nhubs) words each) and
-// counts the hub items' triangles into the c1 counter.
-void launch_hub_pass(const u32* rowptr, const u32* colidx2, const u32* split,
-                     const u32* sabove, const u32* hublist, u32 nhubs, u32 n, const u32* hy,
-                     const uint2* items, u32 nitems, u32* cuts, u32* hubmask, u64* ctr,
-                     hipStream_t s);
+// Builds the hub bitmasks of all n vertices (hub_mask_words(nhubs) words each; the
+// window kernel takes about 70 KB of LDS per workgroup).
+void launch_hub_masks(const u32* rowptr, const u32* colidx2, const u32* split,
+                      const u32* sabove, const u32* hublist, u32 nhubs, u32 n, u32* cuts,
+                      u32* hubmask, hipStream_t s);
+// Counts the hub items' triangles into the c1 counter (no LDS).
+void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove, u32 nhubs,
+                      const u32* hy, const u32* hubmask, const uint2* items, u32 nitems,
+                      u64* ctr, hipStream_t s);
 
 // ---- intersection ----
 // The intersection launchers take the split's outputs in one struct.  pruned: count
