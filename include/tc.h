@@ -36,7 +36,7 @@
  * tuning set by tc_set_isect_params and tc_set_hub_params.
  *
  * Streams: on graphs of at least 2^22 stored entries, tc_count runs its wavefront-class
- * intersections and its hub pass on a second stream that it creates for the call
+ * intersections and its hub count on a second stream that it creates for the call
  * (default priority), ordered after the work queued on `stream`, joined back into it and
  * destroyed before the call returns; everything else runs on `stream`.  The server's
  * worker threads keep to their own streams.

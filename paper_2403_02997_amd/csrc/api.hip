@@ -18,12 +18,14 @@
 
 #include "../../include/tc.h"
 #include "tc_device.h"
+#include "host_api.h"
 #include "tc_launch.h"
 
 namespace tc {
 
 thread_local bool t_side_on = true;  // see set_thread_side_stream
 void set_thread_side_stream(bool on) { t_side_on = on; }
+
 
 namespace {
 
@@ -67,7 +69,7 @@ void prepare_pool() {
 }
 
 // Fork / join of a second stream (default priority) on which the wavefront class and the
-// hub pass run beside the workgroup class.  The stream lives for one call only: a
+// hub count run beside the workgroup class.  The stream lives for one call only: a
 // process has few hardware queues (four by default), and a stream kept alive would take
 // one of them for good, so that other long-lived streams (a server's workers) could end
 // up sharing a queue and waiting behind each other's kernels.  start() creates it and

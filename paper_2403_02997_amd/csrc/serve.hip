@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/tc.h"
+#include "host_api.h"
 #include "tc_launch.h"
 
 namespace tc {

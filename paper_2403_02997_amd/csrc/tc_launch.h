@@ -185,14 +185,4 @@ void launch_batch(const u32* rowptr_cat, const u32* colidx_cat, const int64_t* r
 
 int num_cus();
 
-// Whether the single-graph path of the calling thread may run the wavefront class and
-// the hub pass on a second, per-call stream (default on).  A thread whose own stream is
-// one of several long-lived streams that already fill the device's few hardware queues
-// (the server's workers) turns it off, so that no call adds a stream beside them.
-void set_thread_side_stream(bool on);
-
-// Device bytes one tc_count call on n vertices and m stored entries allocates (its
-// workspace and its workgroup items), under the current settings.
-size_t single_call_bytes(u32 n, u64 m);
-
 }  // namespace tc
