@@ -513,6 +513,19 @@ def bench_serve(args, tcm, torch):
     paths = {"batched": sum(r.path == 0 for r in results),
              "single_medium": sum(r.path == 1 for r in results),
              "single_large": sum(r.path == 3 for r in results)}
+    # the large path's requests: admission wait, admit-to-done time and the standalone
+    # service time, per request in submission order (the huge request is marked)
+    large = sorted((r for r in results if r.path == 3), key=lambda r: r.submit_s)
+    huge = (args.serve_huge_scale, 0) if args.serve_huge_scale else None
+    large_path = {
+        "admit_wait_ms_sum": round(sum(r.admit_s - r.submit_s for r in large) * 1e3, 1),
+        "service_ms_sum": round(sum(r.done_s - r.admit_s for r in large) * 1e3, 1),
+        "standalone_ms_sum": round(sum(svc[tickets[r.ticket]] for r in large) * 1e3, 1),
+        "huge": [{"latency_ms": round(r.latency_s * 1e3, 1),
+                  "admit_wait_ms": round((r.admit_s - r.submit_s) * 1e3, 1),
+                  "standalone_ms": round(svc[tickets[r.ticket]] * 1e3, 1)}
+                 for r in large if tickets[r.ticket] == huge],
+    }
     lat_by = {}
     for name, ids in (("batched", (0,)), ("single_medium", (1,)), ("single_large", (3,))):
         v = np.array([r.latency_s for r in results if r.path in ids])
@@ -545,6 +558,7 @@ def bench_serve(args, tcm, torch):
         "input_edges": int(edges),
         "paths": paths,
         "server": {k: st[k] for k in ("batches", "singles", "hbm_peak", "hbm_budget")},
+        "large_path": large_path,
         "roofline": None,
         "cpu_baseline": None,
     }
