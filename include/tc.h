@@ -260,6 +260,25 @@ int tc_set_hub_params(uint32_t max_hubs, uint32_t min_degree);
 int tc_get_hub_params(uint32_t* out2);
 
 /*
+ * tc_last_call_info — how the calling thread's last successful tc_count, tc_count_ex or
+ * tc_count_per_vertex divided its work (diagnostics; all zero before the first such
+ * call on this thread, and after a call on an empty graph).  HOST output.
+ */
+typedef struct {
+  uint64_t cover_edges;     /* |S|                                                   */
+  uint32_t lane_vertices;   /* staged vertices of the lane class                     */
+  uint32_t wave_vertices;   /* staged vertices of the wavefront class                */
+  uint32_t block_vertices;  /* staged vertices of the workgroup class                */
+  uint32_t block_items;     /* workgroup-class work items                            */
+  uint32_t hubs;            /* hubs of the hub pass (0: the pass did not run)        */
+  uint32_t hub_items;       /* hub-pass work items                                   */
+  uint32_t side_stream;     /* 1: the wavefront class and hub count ran on a second  */
+                            /*    stream beside the workgroup class                  */
+  uint32_t reserved;
+} tc_call_info;
+int tc_last_call_info(tc_call_info* out);
+
+/*
  * Step timing (diagnostics).  While enabled, tc_count / tc_count_ex /
  * tc_count_per_vertex record HIP events on their stream at every step boundary and add
  * each step's elapsed milliseconds to a process-wide accumulator.  tc_profile_read copies

@@ -22,6 +22,7 @@ from .tc import (  # noqa: F401
     tc_count_per_vertex,
     tc_get_hub_params,
     tc_get_isect_params,
+    tc_last_call_info,
     tc_profile_enable,
     tc_profile_read,
     tc_set_hub_params,

@@ -23,6 +23,7 @@
 
 namespace tc {
 
+thread_local tc_call_info t_last_info{};  // see tc_last_call_info
 thread_local bool t_side_on = true;  // see set_thread_side_stream
 void set_thread_side_stream(bool on) { t_side_on = on; }
 
@@ -492,6 +493,16 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   // Two independent tallies of the same-level apexes must agree (CETC-SM: c2 / 3); the
   // pruned count does not tally c2.
   if (!pruned && (out->c[1] % 3 != 0 || out->c[1] / 3 != out->c[2])) return TC_ERR_INTERNAL;
+  tc_call_info info{};
+  info.cover_edges = h_ns;
+  info.lane_vertices = h_plan.num_lane_x;
+  info.wave_vertices = h_plan.num_wave_x;
+  info.block_vertices = h_plan.num_block_x;
+  info.block_items = h_items;
+  info.hubs = hubs ? h_plan.num_hubs : 0u;
+  info.hub_items = hubs ? h_plan.num_hub_items : 0u;
+  info.side_stream = sw != s ? 1u : 0u;
+  t_last_info = info;
   return TC_OK;
 }
 
@@ -540,6 +551,7 @@ int tc_count_ex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint
   tc_stats st;
   memset(&st, 0, sizeof(st));
   if (n == 0 || m == 0) {
+    t_last_info = tc_call_info{};
     if (level_out && n > 0) {
       TC_HIP(hipMemsetAsync(level_out, 0, sizeof(uint32_t) * n, stream));
       TC_HIP(hipStreamSynchronize(stream));
@@ -580,6 +592,7 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
   int rc = check_args(rowptr, colidx, n, m);
   if (rc) return rc;
   if (n > 0 && !tri_out) return TC_ERR_INVALID_ARG;
+  if (n == 0 || m == 0) t_last_info = tc_call_info{};
   if (n == 0) return TC_OK;
   TC_HIP(hipMemsetAsync(tri_out, 0, sizeof(uint64_t) * n, stream));
   if (m == 0) {
@@ -676,6 +689,12 @@ int tc_get_hub_params(uint32_t* out2) {
   if (!out2) return TC_ERR_INVALID_ARG;
   out2[0] = g_hub_max;
   out2[1] = g_hub_min_degree;
+  return TC_OK;
+}
+
+int tc_last_call_info(tc_call_info* out) {
+  if (!out) return TC_ERR_INVALID_ARG;
+  *out = t_last_info;
   return TC_OK;
 }
 

@@ -45,6 +45,7 @@ EXPORTS = (
     "tc_get_isect_params",
     "tc_set_hub_params",
     "tc_get_hub_params",
+    "tc_last_call_info",
     "tc_profile_enable",
     "tc_profile_read",
     "tc_profile_step_name",
@@ -87,6 +88,20 @@ class Stats:
     bfs_levels_bottom_up: int
     class_streamed: tuple = (0, 0, 0)
     class_staged: tuple = (0, 0, 0)
+
+
+class _CallInfo(ctypes.Structure):
+    _fields_ = [
+        ("cover_edges", ctypes.c_uint64),
+        ("lane_vertices", ctypes.c_uint32),
+        ("wave_vertices", ctypes.c_uint32),
+        ("block_vertices", ctypes.c_uint32),
+        ("block_items", ctypes.c_uint32),
+        ("hubs", ctypes.c_uint32),
+        ("hub_items", ctypes.c_uint32),
+        ("side_stream", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
 
 
 class _ServeConfig(ctypes.Structure):
@@ -162,6 +177,8 @@ def load() -> ctypes.CDLL:
     lib.tc_set_isect_params.restype = i
     lib.tc_get_isect_params.argtypes = [ctypes.POINTER(u32)]
     lib.tc_get_isect_params.restype = i
+    lib.tc_last_call_info.argtypes = [ctypes.POINTER(_CallInfo)]
+    lib.tc_last_call_info.restype = i
     lib.tc_set_hub_params.argtypes = [u32, u32]
     lib.tc_set_hub_params.restype = i
     lib.tc_get_hub_params.argtypes = [ctypes.POINTER(u32)]
@@ -323,6 +340,14 @@ def tc_get_isect_params():
     arr = (ctypes.c_uint32 * 4)()
     _check(load().tc_get_isect_params(arr), "tc_get_isect_params")
     return tuple(int(v) for v in arr)
+
+
+def tc_last_call_info() -> dict:
+    """How this thread's last single-graph call divided its work (tc_last_call_info)."""
+    info = _CallInfo()
+    _check(load().tc_last_call_info(ctypes.byref(info)), "tc_last_call_info")
+    return {name: int(getattr(info, name)) for name, _ in _CallInfo._fields_
+            if name != "reserved"}
 
 
 def tc_set_hub_params(max_hubs: int, min_degree: int) -> None:

@@ -280,3 +280,40 @@ def test_concurrent_counts_on_two_streams(tc_lib):
     assert not errors, errors
     for i, (g, r, _, _) in enumerate(cases):
         assert got[i] == [r.triangles] * 6, (g.name, got[i])
+
+
+@pytest.mark.parametrize("hubs", [(1, 1), (7, 1), (129, 1), (256, 1), (0, 0)])
+@pytest.mark.parametrize("name", ["rmat14_ef32", "rmat17_ef32", "union"])
+def test_device_picks_the_hubs_of_the_host_rule(tc_lib, name, hubs):
+    """The device's hub selection (class histogram, threshold, numbering) yields exactly
+    as many hubs as the host rule of bench.hub_set, the pass has work items when it has
+    hubs, tc_count_ex never runs it, and the side stream is used from 2^22 entries on."""
+    import bench
+    g, r, _, _ = case(name)
+    want = int(bench.hub_set(g.degrees(), *hubs).sum())
+    say(f"[parity] device hub selection {hubs} on {name}: {want} hubs expected")
+    rp, ci = upload(g, tc_lib)
+    saved = tc_lib.tc_get_hub_params()
+    try:
+        tc_lib.tc_set_hub_params(*hubs)
+        assert tc_lib.tc_count(rp, ci) == r.triangles
+        info = tc_lib.tc_last_call_info()
+        tc_lib.tc_count_ex(rp, ci)
+        info_ex = tc_lib.tc_last_call_info()
+    finally:
+        tc_lib.tc_set_hub_params(*saved)
+    assert info["hubs"] == want
+    assert (info["hub_items"] > 0) == (want > 0)
+    assert info["cover_edges"] == r.cover_edges == info_ex["cover_edges"]
+    assert info_ex["hubs"] == 0 and info_ex["hub_items"] == 0
+    assert info["side_stream"] == (1 if g.nnz >= 1 << 22 else 0)
+    assert info_ex["side_stream"] == (1 if g.nnz >= 1 << 22 else 0)
+
+
+def test_last_call_info_of_an_empty_graph(tc_lib):
+    g, r, _, _ = case("rmat12")
+    tc_lib.tc_count(*upload(g, tc_lib))
+    assert tc_lib.tc_last_call_info()["cover_edges"] == r.cover_edges
+    e = gg.empty_graph(5)
+    tc_lib.tc_count(*upload(e, tc_lib))
+    assert all(v == 0 for v in tc_lib.tc_last_call_info().values())
