@@ -73,16 +73,19 @@ void prepare_pool() {
 // hub count run beside the workgroup class.  The stream lives for one call only: a
 // process has few hardware queues (four by default), and a stream kept alive would take
 // one of them for good, so that other long-lived streams (a server's workers) could end
-// up sharing a queue and waiting behind each other's kernels.  start() creates it and
-// orders it after the work queued on the main stream; join() (also run on destruction,
-// before the workspace is released) orders the main stream after everything queued on
-// it.  If anything fails, the caller stays on its own stream.
+// up sharing a queue and waiting behind each other's kernels.  create() makes it (early
+// in the call, while the GPU runs the BFS); start() orders it after the work queued on
+// the main stream; join() (also run on destruction, before the workspace is released)
+// orders the main stream after everything queued on it.  If anything fails, the caller
+// stays on its own stream.
 struct SideFork {
   hipStream_t s = nullptr, s2 = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool active = false;
-  bool start(hipStream_t main) {
-    s = main;
+  // Creates the stream and its two events (done early, while the host would otherwise
+  // wait on the GPU).  False if any of them cannot be made.
+  bool create() {
+    if (s2) return true;
     if (!t_side_on) return false;
     if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
       (void)hipGetLastError();
@@ -95,6 +98,11 @@ struct SideFork {
         e = nullptr;
         return false;
       }
+    return true;
+  }
+  bool start(hipStream_t main) {
+    s = main;
+    if (!create()) return false;
     if (hipEventRecord(ev[0], s) != hipSuccess || hipStreamWaitEvent(s2, ev[0], 0) != hipSuccess) {
       (void)hipGetLastError();
       return false;
@@ -380,14 +388,17 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   timer.mark();
   launch_bfs_init(rowptr, parent, n, level, q0, bigq0, fb, ctl, s);
   TC_LAUNCHED();
+  SideFork fork;  // its stream is made while the first BFS levels run
+  const bool want_side = !timer.on && m >= kSideMinEntries;
   {
     const u32 grid = bfs_grid(n);
-    u32 k = 0, batch = 4;
+    u32 k = 0, batch = 8;  // low-diameter graphs finish within one poll
     while (true) {
       for (u32 i = 0; i < batch; ++i)
         launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, bigq0, bigq1, fb, ctl, bfs_part,
                          grid, s);
       TC_LAUNCHED();
+      if (k == 0 && want_side) fork.create();
       k += batch;
       u32 done = 0;
       TC_HIP(hipMemcpyAsync(&done, &ctl->done, sizeof(u32), hipMemcpyDeviceToHost, s));
@@ -409,6 +420,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   timer.mark();
   launch_plan(rowptr, hcnt, hcur, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
   launch_scan(bitems, bitems, n, scan_tmp, s);
+  // padded last quads of both rows arrays, queued before the host waits for the plan
+  launch_tail4(colidx, m, tail4, s);
+  launch_tail4(colidx2, m, tail4b, s);
   TC_LAUNCHED();
   u32 h_items = 0;
   Plan h_plan;
@@ -432,8 +446,6 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     launch_fill_items(rowptr, hcnt, block_x, bitems, h_plan.num_block_x, prm, items, s);
   }
   const SplitView sv{colidx2, split, sabove, hcnt, hrec, tail4b};
-  launch_tail4(colidx, m, tail4, s);
-  launch_tail4(colidx2, m, tail4b, s);
   // the hub masks are built before the fork: their window kernel needs more LDS than a
   // compute unit has left beside a workgroup-class workgroup, so beside it it would wait
   // for the workgroup class to drain (with step timing on they run in the hub step)
@@ -445,8 +457,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   // The workgroup class is bound by HBM streaming, the wavefront class and the hub count
   // by latency: the latter two run on the side stream, beside it (all on the caller's
   // stream, one after another, while step timing is on).
-  SideFork fork;
-  const hipStream_t sw = !timer.on && m >= kSideMinEntries && fork.start(s) ? fork.s2 : s;
+  const hipStream_t sw = want_side && fork.start(s) ? fork.s2 : s;
   if (sw != s) {
     // side stream first: the hub count and the wavefront class take compute units while
     // the workgroup class (persistent workgroups that hold their units to the end) ramps up
