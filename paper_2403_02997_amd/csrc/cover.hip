@@ -279,7 +279,10 @@ __device__ __forceinline__ void chunk_write(const ChunkRegs& r, u32 v, u32 lo, u
   }
 }
 
-__global__ void __launch_bounds__(256) k_split_rows(const u32* __restrict__ rowptr,
+// Four wavefronts per SIMD (at most 128 registers): the split is bound by the latency
+// of its gathers and scattered record writes, and the compiler's free choice (about
+// 144 registers, three wavefronts) measured slower.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_split_rows(const u32* __restrict__ rowptr,
                                                    const u32* __restrict__ colidx,
                                                    const uint8_t* __restrict__ vinfo, u32 n,
                                                    SplitOut o, u32* __restrict__ split,
