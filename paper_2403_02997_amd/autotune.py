@@ -94,11 +94,16 @@ def store_cache(path: str | None, db: dict) -> None:
     os.replace(tmp, path)
 
 
-def descend(measure, start, order=ORDER, candidates=CANDIDATES):
+MIN_GAIN = 0.02  # a candidate must beat the best time so far by this fraction
+
+
+def descend(measure, start, order=ORDER, candidates=CANDIDATES, min_gain=MIN_GAIN):
     """Coordinate descent.  measure(params) -> (result, seconds); params are tuples in
-    NAMES order, as long as `start` (the names past its length are not tuned).  Returns
-    (best params, best seconds, number of settings measured).  Raises RuntimeError when
-    a setting's result differs from the first one's."""
+    NAMES order, as long as `start` (the names past its length are not tuned).  A
+    candidate replaces the best setting only when it is faster by more than min_gain
+    (a relative margin: run-to-run noise of a few tenths of a percent must not move the
+    setting).  Returns (best params, best seconds, number of settings measured).  Raises
+    RuntimeError when a setting's result differs from the first one's."""
     best = tuple(int(v) for v in start)
     ref, best_t = measure(best)
     tried = {best}
@@ -114,7 +119,7 @@ def descend(measure, start, order=ORDER, candidates=CANDIDATES):
             res, t = measure(cand)
             if res != ref:
                 raise RuntimeError(f"setting {cand} changed the result: {res!r} != {ref!r}")
-            if t < best_t:
+            if t < best_t * (1.0 - min_gain):
                 best, best_t = cand, t
     return best, best_t, len(tried)
 

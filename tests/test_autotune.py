@@ -41,6 +41,14 @@ def test_descent_tunes_the_hub_count_when_given():
     assert not at.valid((16, 512, 4096, 1024, 257))
 
 
+def test_descent_keeps_the_start_against_noise_sized_gains():
+    def measure(p):  # every other setting 1 % faster: within the margin
+        return 0, 1.0 if p == (16, 512, 4096, 1024) else 0.99
+
+    best, t, _ = at.descend(measure, (16, 512, 4096, 1024))
+    assert best == (16, 512, 4096, 1024) and t == 1.0
+
+
 def test_descent_never_measures_an_invalid_setting():
     seen = []
 
