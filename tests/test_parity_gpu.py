@@ -317,3 +317,24 @@ def test_last_call_info_of_an_empty_graph(tc_lib):
     e = gg.empty_graph(5)
     tc_lib.tc_count(*upload(e, tc_lib))
     assert all(v == 0 for v in tc_lib.tc_last_call_info().values())
+
+
+def test_step_timed_calls_match_and_stay_on_one_stream(tc_lib):
+    """With step timing on, tc_count runs every class on the caller's stream one after
+    another (no side stream); the count is the same as in the overlapped call."""
+    g, r, _, _ = case("rmat17_ef32")
+    say("[parity] step-timed tc_count on rmat17_ef32")
+    rp, ci = upload(g, tc_lib)
+    assert tc_lib.tc_count(rp, ci) == r.triangles
+    assert tc_lib.tc_last_call_info()["side_stream"] == 1
+    tc_lib.tc_profile_read(reset=True)
+    tc_lib.tc_profile_enable(True)
+    try:
+        got = tc_lib.tc_count(rp, ci)
+        info = tc_lib.tc_last_call_info()
+    finally:
+        tc_lib.tc_profile_enable(False)
+    steps, calls = tc_lib.tc_profile_read(reset=True)
+    assert got == r.triangles
+    assert info["side_stream"] == 0 and info["hubs"] > 0
+    assert calls == 1 and steps["isect_block"] > 0 and steps["isect_hub"] > 0
