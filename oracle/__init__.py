@@ -6,7 +6,7 @@ the two share no code (the seeded input generators in ``graphgen`` serve both an
 counting arithmetic).
 
 The arithmetic lives in ``cetc_oracle.c`` (plain C, one function per step of the paper's
-CETC-Seq and CETC-SM algorithms, Sections 4.2 and 4.4).  This module builds it with gcc
+CETC-Seq, CETC-Seq-S and CETC-SM algorithms, Sections 4.2 to 4.4).  This module builds it with gcc
 and marshals numpy arrays into it.
 """
 from __future__ import annotations
@@ -64,6 +64,8 @@ def _bind(lib):
     lib.orc_cetc_sm_range.argtypes = [vp, vp, u32, vp, u32, u32, ctypes.c_int,
                                       ctypes.POINTER(u64), ctypes.POINTER(u64)]
     lib.orc_cetc_sm_range.restype = u64
+    lib.orc_cetc_split.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.orc_cetc_split.restype = u64
     lib.orc_cover_edges.argtypes = [vp, vp, u32, vp]
     lib.orc_cover_edges.restype = u64
     lib.orc_max_threads.restype = ctypes.c_int
@@ -188,6 +190,23 @@ def cetc_sm_range(g, level, u_begin: int, u_end: int, nthreads: int = 0):
                                   int(u_begin), int(u_end), int(nthreads), ctypes.byref(c1),
                                   ctypes.byref(c2))
     return int(T), int(c1.value), int(c2.value)
+
+
+def cetc_split(g, level=None):
+    """CETC-Seq-S (Section 4.3): (T, t0, t1) with t0 = forward-hashed triangles of the
+    horizontal subgraph G0 and t1 = the hashed G1 intersections over horizontal edges."""
+    rowptr, colidx = _arrs(g)
+    if level is None:
+        level, _ = bfs_levels(g)
+    lv = np.ascontiguousarray(level, dtype=np.uint32)
+    if lv.size == 0:
+        lv = np.zeros(1, np.uint32)
+    t0, t1 = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    T = int(_load().orc_cetc_split(rowptr.ctypes.data, colidx.ctypes.data, g.n, lv.ctypes.data,
+                                   ctypes.byref(t0), ctypes.byref(t1)))
+    if T == 0xFFFFFFFFFFFFFFFF:
+        raise MemoryError("oracle split allocation failed")
+    return T, int(t0.value), int(t1.value)
 
 
 def cover_edges(g, level) -> int:

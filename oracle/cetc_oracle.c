@@ -16,6 +16,9 @@
  *                  counted when L(u) != L(w), or when L(u) == L(w) and v < w.
  *     Algorithm CETC-SM (Section 4.4): the same edge loop in parallel; c1 counts apexes
  *                  on another level, c2 apexes on the same level; T = c1 + c2 / 3.
+ *     Algorithm CETC-Seq-S (Section 4.3): the edges split into G0 (horizontal) and G1
+ *                  (the rest); forward-hashed on G0, plus hashed N_G1(u) ∩ N_G1(v) for
+ *                  every horizontal (u,v) with u < v.
  *
  * Readings where the paper is silent (also listed in the design notes):
  *   - the BFS restart loop visits candidate roots in ascending vertex ID, so each
@@ -23,6 +26,7 @@
  *   - the edge loop scans both stored directions of the symmetric CSR and keeps u < v,
  *     so every undirected edge is examined once;
  *   - "c2 / 3" is exact integer division (c2 is a multiple of 3);
+ *   - the forward pass of CETC-Seq-S takes G0's edges by first endpoint in ascending ID;
  *   - counts are 64-bit unsigned.
  *
  * Input: symmetric CSR, rowptr[n+1], colidx[nnz] (uint32), neighbour lists strictly
@@ -230,6 +234,89 @@ uint64_t orc_cetc_sm_range(const uint32_t* rowptr, const uint32_t* colidx, uint3
 uint64_t orc_cetc_sm(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
                      const uint32_t* level, int nthreads, uint64_t* c1_out, uint64_t* c2_out) {
   return orc_cetc_sm_range(rowptr, colidx, n, level, 0, n, nthreads, c1_out, c2_out);
+}
+
+/*
+ * CETC-Seq-S (Section 4.3, the split variant, Algorithm CETC-Seq-S), after the BFS:
+ *   1. every edge goes to G0 when its endpoints share a level (horizontal), else to G1;
+ *   2. t0 <- TC_forward-hashed(G0) (Section 3, Algorithm Forward-Hashed): for every edge
+ *      (u, v) of G0 with u < v, count A(u) ∩ A(v) with a Boolean array, then add u to
+ *      A(v); edges are taken by first endpoint in ascending ID, so A(u) already holds
+ *      every smaller G0 neighbour of u when u's own edges are taken;
+ *   3. t1 <- for every u, mark N_G1(u) in the Boolean array; for every v in N_G0(u) with
+ *      u < v, count the w in N_G1(v) that are marked; clear the marks.
+ * T = t0 + t1: t0 counts the triangles whose three edges are all horizontal, t1 the
+ * others, each at its one horizontal edge.  The Boolean array is indexed by vertex
+ * (n entries).  Writes t0 and t1; returns T, or UINT64_MAX if an allocation fails.
+ */
+uint64_t orc_cetc_split(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
+                        const uint32_t* level, uint64_t* t0_out, uint64_t* t1_out) {
+  size_t rows = (size_t)n + 1;
+  uint64_t nnz = rowptr[n];
+  uint64_t* rp0 = (uint64_t*)calloc(rows, sizeof(uint64_t));
+  uint64_t* rp1 = (uint64_t*)calloc(rows, sizeof(uint64_t));
+  uint32_t* ci0 = (uint32_t*)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
+  uint32_t* ci1 = (uint32_t*)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
+  uint32_t* aset = (uint32_t*)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
+  uint64_t* alen = (uint64_t*)calloc(n ? n : 1, sizeof(uint64_t));
+  unsigned char* hash = (unsigned char*)calloc(n ? n : 1, 1);
+  uint64_t t0 = 0, t1 = 0, ret = UINT64_MAX;
+  if (!rp0 || !rp1 || !ci0 || !ci1 || !aset || !alen || !hash) goto done;
+
+  /* Step 1: partition E into E0 (horizontal) and E1, as two symmetric CSRs. */
+  for (uint32_t u = 0; u < n; ++u) {
+    uint64_t h = 0;
+    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
+      if (level[colidx[e]] == level[u]) ++h;
+    rp0[u + 1] = rp0[u] + h;
+    rp1[u + 1] = rp1[u] + (rowptr[u + 1] - rowptr[u] - h);
+  }
+  for (uint32_t u = 0; u < n; ++u) {
+    uint64_t i0 = rp0[u], i1 = rp1[u];
+    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      uint32_t v = colidx[e];
+      if (level[v] == level[u]) ci0[i0++] = v;
+      else ci1[i1++] = v;
+    }
+  }
+
+  /* Step 2: forward-hashed on G0.  A(v) lives in aset[rp0[v] .. rp0[v] + alen[v]); it
+   * only ever holds G0 neighbours of v, so d_G0(v) slots suffice. */
+  for (uint32_t u = 0; u < n; ++u) {
+    for (uint64_t e = rp0[u]; e < rp0[u + 1]; ++e) {
+      uint32_t v = ci0[e];
+      if (!(u < v)) continue;
+      for (uint64_t k = 0; k < alen[u]; ++k) hash[aset[rp0[u] + k]] = 1;
+      for (uint64_t k = 0; k < alen[v]; ++k)
+        if (hash[aset[rp0[v] + k]]) t0 += 1;
+      for (uint64_t k = 0; k < alen[u]; ++k) hash[aset[rp0[u] + k]] = 0;
+      aset[rp0[v] + alen[v]++] = u;
+    }
+  }
+
+  /* Step 3: hashed intersections on G1 for every horizontal edge (u, v), u < v. */
+  for (uint32_t u = 0; u < n; ++u) {
+    for (uint64_t e = rp1[u]; e < rp1[u + 1]; ++e) hash[ci1[e]] = 1;
+    for (uint64_t e = rp0[u]; e < rp0[u + 1]; ++e) {
+      uint32_t v = ci0[e];
+      if (!(u < v)) continue;
+      for (uint64_t k = rp1[v]; k < rp1[v + 1]; ++k)
+        if (hash[ci1[k]]) t1 += 1;
+    }
+    for (uint64_t e = rp1[u]; e < rp1[u + 1]; ++e) hash[ci1[e]] = 0;
+  }
+  if (t0_out) *t0_out = t0;
+  if (t1_out) *t1_out = t1;
+  ret = t0 + t1;
+done:
+  free(rp0);
+  free(rp1);
+  free(ci0);
+  free(ci1);
+  free(aset);
+  free(alen);
+  free(hash);
+  return ret;
 }
 
 /* Threads the OpenMP runtime would use by default (1 without OpenMP). */

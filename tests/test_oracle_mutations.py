@@ -2,7 +2,8 @@
 
 Each case plants one mistake in a copy of oracle/cetc_oracle.c (a wrong index, a
 flipped comparison, a dropped condition, a wrong divisor, a broken merge step, a
-different BFS root order), builds the copy with gcc into a temporary directory, and
+different BFS root order, a split pass that adds to the wrong set, leaves marks behind or
+drops a term), builds the copy with gcc into a temporary directory, and
 checks that at least one pin from test_oracle_pins fails against it.  The committed
 oracle is never modified.
 """
@@ -16,7 +17,7 @@ import pytest
 import graphgen as gg
 import oracle
 from tests import pins
-from tests.test_oracle_pins import bfs_certificate
+from tests.test_oracle_pins import bfs_certificate, split_by_enumeration
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "cetc_oracle.c")
 
@@ -29,6 +30,13 @@ MUTATIONS = {
     "sm_divides_by_two": ("return c1 + c2 / 3;", "return c1 + c2 / 2;"),
     "merge_advances_wrong_list": ("if (colidx[i] < colidx[j]) {\n          ++i;",
                                   "if (colidx[i] < colidx[j]) {\n          ++j;"),
+    "split_forward_adds_wrong_end": ("aset[rp0[v] + alen[v]++] = u;",
+                                     "aset[rp0[u] + alen[u]++] = v;"),
+    "split_cross_drops_u_lt_v": ("      if (!(u < v)) continue;\n      for (uint64_t k = rp1[v];",
+                                 "      for (uint64_t k = rp1[v];"),
+    "split_forward_marks_not_cleared": (
+        "      for (uint64_t k = 0; k < alen[u]; ++k) hash[aset[rp0[u] + k]] = 0;\n", ""),
+    "split_total_drops_g0": ("ret = t0 + t1;", "ret = t1;"),
     "bfs_roots_descending": ("for (uint32_t s = 0; s < n; ++s) {\n    if (level[s] != ORC_UNVISITED)",
                              "for (uint32_t s = n; s-- > 0;) {\n    if (level[s] != ORC_UNVISITED)"),
 }
@@ -55,6 +63,14 @@ def pins_hold() -> bool:
         if oracle.count(gg.complete(9)) != 84 or oracle.count(gg.tri_grid(7, 9)) != 96:
             return False
         bfs_certificate(g, r.level)
+        if oracle.cetc_split(gg.complete(9)) != (84, 56, 28):
+            return False
+        for seed in range(4):
+            g = gg.gnp_small(40 + seed, 0.25, seed)
+            level, _ = oracle.bfs_levels(g)
+            T, t0, t1 = oracle.cetc_split(g, level)
+            if (t0, t1) != split_by_enumeration(g, level) or T != pins.brute_force_triples(g):
+                return False
     except AssertionError:
         return False
     return True

@@ -194,9 +194,12 @@ def test_every_triangle_has_one_or_three_horizontal_edges(seed):
     level, _ = oracle.bfs_levels(g)
     tris = pins.triangles(g)
     assert len(tris) == oracle.count(g)
+    seen = set()
     for a, b, c in tris:
-        h = (level[a] == level[b]) + (level[a] == level[c]) + (level[b] == level[c])
+        h = int(level[a] == level[b]) + int(level[a] == level[c]) + int(level[b] == level[c])
         assert h in (1, 3)
+        seen.add(h)
+    assert seen == {1, 3}  # both kinds occur on these graphs
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -246,3 +249,70 @@ def test_sm_range_partitions_the_edge_loop(seed):
     parts = [oracle.cetc_sm_range(g, level, a, b) for a, b in zip(cut[:-1], cut[1:])]
     assert sum(p[1] for p in parts) == c1 and sum(p[2] for p in parts) == c2
     assert T == pins.sparse_count(g)
+
+
+# ---- CETC-Seq-S: the split into G0 (horizontal edges) and G1 (the rest), Section 4.3 ----
+
+def split_by_enumeration(g, level):
+    """(t0, t1) by enumerating every triangle: t0 = triangles whose three vertices share a
+    label, t1 = triangles with exactly one same-label edge (the two parts the split
+    algorithm counts; a triangle with no same-label edge is in neither)."""
+    t0 = t1 = 0
+    for a, b, c in pins.triangles(g):
+        h = int(level[a] == level[b]) + int(level[a] == level[c]) + int(level[b] == level[c])
+        t0 += h == 3
+        t1 += h == 1
+    return int(t0), int(t1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 9, 17])
+def test_split_complete_graph(n):
+    # Root 0 alone on level 0, the other n - 1 vertices on level 1: G0 is K_{n-1}.
+    assert oracle.cetc_split(gg.complete(n)) == (
+        math.comb(n, 3), math.comb(n - 1, 3), math.comb(n - 1, 2))
+
+
+def test_split_wheels_friendship_and_triangle_free():
+    for k in (4, 5, 9, 60):  # hub 0 is the root; each triangle has one rim edge
+        assert oracle.cetc_split(gg.wheel(k)) == (k, 0, k)
+    for k in (1, 2, 7):
+        assert oracle.cetc_split(gg.friendship(k)) == (k, 0, k)
+    for g in (gg.complete_bipartite(7, 11), gg.cycle(5), gg.cycle(31), gg.hypercube(5),
+              gg.empty_graph(0), gg.empty_graph(12)):
+        assert oracle.cetc_split(g) == (0, 0, 0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_split_terms_by_enumeration(seed):
+    g = gg.gnp_small(40 + seed, 0.25, seed) if seed % 2 else gg.rmat(8, 16, 80 + seed)
+    level, _ = oracle.bfs_levels(g)
+    T, t0, t1 = oracle.cetc_split(g, level)
+    assert (t0, t1) == split_by_enumeration(g, level)
+    assert T == pins.brute_force_triples(g) if g.n <= 48 else T == pins.sparse_count(g)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_split_terms_under_arbitrary_labels(seed):
+    # Each step is checked on its own with labels that are not BFS levels: one shared
+    # label makes G0 the whole graph (the forward-hashed step alone counts every
+    # triangle); random labels give triangles with zero, one and three same-label edges.
+    g = gg.rmat(9, 16, 120 + seed)
+    T = pins.sparse_count(g)
+    assert oracle.cetc_split(g, np.zeros(g.n, np.uint32)) == (T, T, 0)
+    rng = np.random.default_rng(seed)
+    lab = rng.integers(0, 3, g.n).astype(np.uint32)
+    _, t0, t1 = oracle.cetc_split(g, lab)
+    assert (t0, t1) == split_by_enumeration(g, lab)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_split_matches_cetc_sm_terms_and_any_root(seed):
+    # t1 is CETC-SM's c1 (apexes on another level) and 3·t0 its c2; T holds for any roots.
+    g = gg.rmat(11, 16, 140 + seed) if seed % 2 else gg.erdos_renyi(4000, 8, seed)
+    T = pins.sparse_count(g)
+    level, _ = oracle.bfs_levels(g)
+    Ts, t0, t1 = oracle.cetc_split(g, level)
+    _, c1, c2 = oracle.cetc_sm(g, level)
+    assert Ts == T and t1 == c1 and 3 * t0 == c2
+    other = pins.bfs_levels_from(g, gg.permutation(g.n, 500 + seed))
+    assert oracle.cetc_split(g, other)[0] == T

@@ -95,6 +95,23 @@ def test_count_matches_oracle(tc_lib, name):
     assert tc_lib.tc_count(rp, ci) == r.triangles
 
 
+@pytest.mark.parametrize("name", ["karate", "wheel500", "tripartite", "grid64_del", "rmat12",
+                                  "rmat16", "er16_d32", "union"])
+def test_split_terms_match_cetc_s(tc_lib, name):
+    # CETC-Seq-S (Section 4.3) counts the triangles of the horizontal subgraph G0 by
+    # forward-hashing (t0) and the G1 intersections over horizontal edges (t1).  The GPU
+    # counts both in one pass: its other-level apexes are t1 and its same-level apexes
+    # see each G0 triangle from its three edges.
+    g, r, _, _ = case(name)
+    T, t0, t1 = oracle.cetc_split(g, r.level)
+    say(f"[parity] split terms {name}: n={g.n} m={g.nnz} t0={t0} t1={t1}")
+    rp, ci = upload(g, tc_lib)
+    stats, _ = tc_lib.tc_count_ex(rp, ci)
+    assert T == r.triangles
+    assert stats.c1 == t1 and stats.c2 == 3 * t0 and stats.triangles == t0 + t1
+    assert tc_lib.tc_count(rp, ci) == t0 + t1
+
+
 @pytest.mark.parametrize("name", ["karate", "wheel500", "rmat12", "er14_d4", "book10000",
                                   "grid64_del", "union"])
 def test_per_vertex_matches_oracle(tc_lib, name):
