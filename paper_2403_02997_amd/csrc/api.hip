@@ -548,7 +548,7 @@ const char* tc_status_string(int status) {
     case TC_ERR_OUT_OF_MEMORY: return "device out of memory";
     case TC_ERR_HIP: return "HIP runtime error";
     case TC_ERR_INVALID_GRAPH: return "graph violates the CSR contract";
-    case TC_ERR_TOO_LARGE: return "graph too large (n >= 2^31 or m >= 2^32)";
+    case TC_ERR_TOO_LARGE: return "graph too large (n >= 2^30 or m >= 2^32)";
     case TC_ERR_INTERNAL: return "internal consistency check failed";
     default: return "unknown status";
   }

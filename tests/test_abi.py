@@ -47,6 +47,8 @@ def test_status_strings_and_version(lib):
         s = lib.tc_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.tc_status_string(-99).decode() == "unknown status"
+    # the limits named in the message are the ones check_args applies
+    assert "2^30" in lib.tc_status_string(-5).decode()
     assert lib.tc_version() >= 10000
 
 
