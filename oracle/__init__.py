@@ -66,6 +66,8 @@ def _bind(lib):
     lib.orc_cetc_sm_range.restype = u64
     lib.orc_cetc_split.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
     lib.orc_cetc_split.restype = u64
+    lib.orc_local_clustering.argtypes = [vp, vp, u32, vp]
+    lib.orc_local_clustering.restype = None
     lib.orc_cover_edges.argtypes = [vp, vp, u32, vp]
     lib.orc_cover_edges.restype = u64
     lib.orc_max_threads.restype = ctypes.c_int
@@ -207,6 +209,18 @@ def cetc_split(g, level=None):
     if T == 0xFFFFFFFFFFFFFFFF:
         raise MemoryError("oracle split allocation failed")
     return T, int(t0.value), int(t1.value)
+
+
+def local_clustering(g) -> np.ndarray:
+    """C(v) = 2 t(v) / (d(v) (d(v) - 1)) in float64 (0 for d(v) < 2), from CETC-Seq's
+    per-vertex counts."""
+    rowptr, _ = _arrs(g)
+    t = np.ascontiguousarray(cetc_seq(g, per_vertex=True).per_vertex, dtype=np.uint64)
+    if t.size == 0:
+        t = np.zeros(1, np.uint64)
+    cc = np.empty(max(g.n, 1), dtype=np.float64)
+    _load().orc_local_clustering(rowptr.ctypes.data, t.ctypes.data, g.n, cc.ctypes.data)
+    return cc[: g.n]
 
 
 def cover_edges(g, level) -> int:

@@ -319,6 +319,24 @@ done:
   return ret;
 }
 
+/*
+ * Local clustering coefficient (Watts and Strogatz; Section 1 lists clustering
+ * coefficients among the uses of triangle counts), from the vertex form of the count of
+ * Section 2: C(v) = |Delta(v)| / (d(v) choose 2) = 2 t(v) / (d(v) (d(v) - 1)), 0 when
+ * d(v) < 2.  tri holds t(v) (orc_cetc_seq's per-vertex counts); cc gets n doubles.
+ */
+void orc_local_clustering(const uint32_t* rowptr, const uint64_t* tri, uint32_t n, double* cc) {
+  for (uint32_t v = 0; v < n; ++v) {
+    uint64_t d = rowptr[v + 1] - rowptr[v];
+    if (d < 2) {
+      cc[v] = 0.0;
+    } else {
+      double pairs = (double)d * (double)(d - 1) / 2.0; /* neighbour pairs, exact */
+      cc[v] = (double)tri[v] / pairs;
+    }
+  }
+}
+
 /* Threads the OpenMP runtime would use by default (1 without OpenMP). */
 int orc_max_threads(void) {
 #ifdef _OPENMP

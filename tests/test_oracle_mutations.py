@@ -3,7 +3,7 @@
 Each case plants one mistake in a copy of oracle/cetc_oracle.c (a wrong index, a
 flipped comparison, a dropped condition, a wrong divisor, a broken merge step, a
 different BFS root order, a split pass that adds to the wrong set, leaves marks behind or
-drops a term), builds the copy with gcc into a temporary directory, and
+drops a term, a clustering coefficient over ordered pairs), builds the copy with gcc into a temporary directory, and
 checks that at least one pin from test_oracle_pins fails against it.  The committed
 oracle is never modified.
 """
@@ -37,6 +37,7 @@ MUTATIONS = {
     "split_forward_marks_not_cleared": (
         "      for (uint64_t k = 0; k < alen[u]; ++k) hash[aset[rp0[u] + k]] = 0;\n", ""),
     "split_total_drops_g0": ("ret = t0 + t1;", "ret = t1;"),
+    "clustering_counts_ordered_pairs": ("(double)(d - 1) / 2.0;", "(double)(d - 1);"),
     "bfs_roots_descending": ("for (uint32_t s = 0; s < n; ++s) {\n    if (level[s] != ORC_UNVISITED)",
                              "for (uint32_t s = n; s-- > 0;) {\n    if (level[s] != ORC_UNVISITED)"),
 }
@@ -63,6 +64,8 @@ def pins_hold() -> bool:
         if oracle.count(gg.complete(9)) != 84 or oracle.count(gg.tri_grid(7, 9)) != 96:
             return False
         bfs_certificate(g, r.level)
+        if not np.all(oracle.local_clustering(gg.complete(6)) == 1.0):
+            return False
         if oracle.cetc_split(gg.complete(9)) != (84, 56, 28):
             return False
         for seed in range(4):

@@ -316,3 +316,37 @@ def test_split_matches_cetc_sm_terms_and_any_root(seed):
     assert Ts == T and t1 == c1 and 3 * t0 == c2
     other = pins.bfs_levels_from(g, gg.permutation(g.n, 500 + seed))
     assert oracle.cetc_split(g, other)[0] == T
+
+
+# ---- local clustering coefficients from the per-vertex counts ---------------------------
+
+def test_clustering_closed_forms():
+    for n in (3, 4, 9, 30):
+        assert np.all(oracle.local_clustering(gg.complete(n)) == 1.0)
+    assert np.all(oracle.local_clustering(gg.complete(2)) == 0.0)
+    for k in (4, 5, 9, 60):  # hub 0: k triangles over C(k, 2) pairs; rim: 2 of 3 pairs
+        cc = oracle.local_clustering(gg.wheel(k))
+        assert cc[0] == 2.0 / (k - 1) and np.all(cc[1:] == 2.0 / 3.0)
+    for k in (1, 2, 7):  # centre: k of C(2k, 2) pairs; the others sit in one triangle
+        cc = oracle.local_clustering(gg.friendship(k))
+        assert cc[0] == 1.0 / (2 * k - 1) and np.all(cc[1:] == 1.0)
+    for g in (gg.star(9), gg.path(12), gg.cycle(8), gg.complete_bipartite(4, 6),
+              gg.empty_graph(5)):
+        assert np.all(oracle.local_clustering(g) == 0.0)
+    assert oracle.local_clustering(gg.empty_graph(0)).size == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_clustering_against_networkx(seed):
+    # networkx's clustering() is an independent routine for the same definition.
+    if seed == 0:
+        k = nx.karate_club_graph()
+        g = gg.from_edges(34, list(k.edges()))
+    else:
+        g = gg.gnp_small(50 + seed, 0.2, seed) if seed % 2 else gg.rmat(9, 16, 160 + seed)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    G.add_edges_from(zip(rows.tolist(), g.colidx.tolist()))
+    ref = nx.clustering(G)
+    assert np.array_equal(oracle.local_clustering(g), np.array([ref[v] for v in range(g.n)]))
