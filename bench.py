@@ -80,12 +80,14 @@ def log(*a):
 
 
 def source_sha() -> str:
-    """Hash of every source that defines a kernel or its launch shape (all of csrc but the
-    host-side call orchestration of api.hip, serve.hip and host_api.h): any change to how
-    the work is divided or done makes a stored traffic record stale."""
+    """Hash of every source that defines a counting kernel or its launch shape (all of csrc
+    but the host-side call orchestration of api.hip, serve.hip and host_api.h, and the
+    clustering-coefficient kernel of cluster.hip, which no counting step runs): any change
+    to how the work is divided or done makes a stored traffic record stale."""
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".h")) and f not in ("api.hip", "serve.hip", "host_api.h"):
+        if f.endswith((".hip", ".h")) and f not in ("api.hip", "serve.hip", "host_api.h",
+                                                    "cluster.hip"):
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]

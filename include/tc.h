@@ -112,6 +112,22 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
                         uint64_t m, hipStream_t stream, uint64_t* tri_out);
 
 /*
+ * tc_local_clustering — local clustering coefficient of every vertex from its triangle
+ * count (Watts and Strogatz; Section 1 names clustering coefficients among the uses of
+ * triangle counts): C(v) = 2 t(v) / (d(v) (d(v) - 1)), the fraction of v's neighbour
+ * pairs that are adjacent, and C(v) = 0 when d(v) < 2.
+ * rowptr is the graph's DEVICE uint32[n + 1] (degrees only; colidx is not read), tri the
+ * DEVICE uint64[n] that tc_count_per_vertex wrote, cc_out a DEVICE double[n] that is
+ * overwritten.  Computed in double with one correctly rounded division per vertex.
+ * Stream-ordered on `stream`: returns after queueing one kernel, without synchronising,
+ * so tri may come from a tc_count_per_vertex call on the same stream.  Nothing is
+ * allocated.  Returns TC_OK at once for n = 0, TC_ERR_INVALID_ARG for null pointers,
+ * TC_ERR_TOO_LARGE for n >= 2^30, TC_ERR_HIP if the launch fails.
+ */
+int tc_local_clustering(const uint32_t* rowptr, const uint64_t* tri, uint32_t n,
+                        hipStream_t stream, double* cc_out);
+
+/*
  * tc_count_batch — triangle counts of many independent graphs in one persistent launch:
  * one workgroup per graph at a time, larger graphs first, each running component roots,
  * BFS, level split, cover-edge selection and intersections without waiting for others.

@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtc.so")
-SOURCES = ["prep.hip", "bfs.hip", "cover.hip", "hub.hip", "intersect.hip", "batch.hip", "api.hip",
-           "serve.hip"]
+SOURCES = ["prep.hip", "bfs.hip", "cover.hip", "hub.hip", "intersect.hip", "batch.hip",
+           "cluster.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -22,7 +22,8 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",
-    # packed FP32 instructions stay off (there is no floating point here anyway)
+    # packed FP32 instructions stay off (the only floating point is the fp64 division
+    # of the clustering coefficients)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -33,6 +33,7 @@ EXPORTS = (
     "tc_count",
     "tc_count_ex",
     "tc_count_per_vertex",
+    "tc_local_clustering",
     "tc_count_batch",
     "tc_count_batch_workspace_size",
     "tc_serve_create",
@@ -156,6 +157,8 @@ def load() -> ctypes.CDLL:
     lib.tc_count_ex.restype = i
     lib.tc_count_per_vertex.argtypes = [vp, vp, u32, u64, vp, vp]
     lib.tc_count_per_vertex.restype = i
+    lib.tc_local_clustering.argtypes = [vp, vp, u32, vp, vp]
+    lib.tc_local_clustering.restype = i
     lib.tc_count_batch.argtypes = [vp, vp, vp, vp, u32, u64, u64, vp, sz, vp, vp]
     lib.tc_count_batch.restype = i
     lib.tc_count_batch_workspace_size.argtypes = [u32, u64, u64]
@@ -289,6 +292,23 @@ def tc_count_per_vertex(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None)
     rc = lib.tc_count_per_vertex(_ptr(rowptr), _ptr(colidx), n, m, _stream_handle(stream),
                                  _ptr(out) if n else None)
     _check(rc, "tc_count_per_vertex")
+    return out
+
+
+def tc_local_clustering(rowptr: torch.Tensor, tri: torch.Tensor, stream=None) -> torch.Tensor:
+    """float64 tensor of C(v) = 2 t(v) / (d(v) (d(v) - 1)) (0 for d(v) < 2), from the
+    per-vertex counts `tri` that tc_count_per_vertex returned for the same graph.
+    Stream-ordered: no synchronisation."""
+    lib = load()
+    n = int(rowptr.numel()) - 1
+    if rowptr.element_size() != 4 or tri.element_size() != 8 or tri.is_floating_point():
+        raise TypeError("rowptr must hold 4-byte and tri 8-byte integers")
+    if n < 0 or tri.numel() != n:
+        raise ValueError(f"tri has {tri.numel()} entries for {max(n, 0)} vertices")
+    out = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    rc = lib.tc_local_clustering(_ptr(rowptr), _ptr(tri) if n else None, max(n, 0),
+                                 _stream_handle(stream), _ptr(out) if n else None)
+    _check(rc, "tc_local_clustering")
     return out
 
 

@@ -73,6 +73,12 @@ def test_argument_errors_without_gpu(lib):
                                                           ctypes.c_void_p]
     assert lib.tc_count_batch(None, None, None, None, 3, 10, 20, None, 0, None, None) == -1
     assert lib.tc_count_batch(None, None, None, None, 0, 0, 0, None, 0, None, None) == 0
+    # clustering coefficients: checked before the launch
+    lib.tc_local_clustering.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.tc_local_clustering(None, None, 0, None, None) == 0
+    assert lib.tc_local_clustering(None, None, 5, None, None) == -1
+    assert lib.tc_local_clustering(None, None, 0x40000000, None, None) == -5
 
 
 def test_workspace_size_grows_with_rows(lib):

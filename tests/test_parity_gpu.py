@@ -122,6 +122,23 @@ def test_per_vertex_matches_oracle(tc_lib, name):
     assert np.array_equal(t, r.per_vertex)
 
 
+@pytest.mark.parametrize("name", ["karate", "K40", "K2", "K1", "wheel500", "friendship100", "star5000",
+                                  "edgeless100", "rmat12", "er14_d4", "union"])
+def test_local_clustering_matches_oracle(tc_lib, name):
+    # Both sides divide exact doubles once (2 t / (d (d - 1)) here, t / pairs in the
+    # oracle), so the coefficients agree bit for bit.
+    g, _, _, _ = case(name)
+    say(f"[parity] tc_local_clustering {name}")
+    rp, ci = upload(g, tc_lib)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        tri = tc_lib.tc_count_per_vertex(rp, ci, stream=s)
+        cc = tc_lib.tc_local_clustering(rp, tri, stream=s)
+    s.synchronize()
+    assert cc.dtype == torch.float64 and cc.numel() == g.n
+    assert np.array_equal(cc.cpu().numpy(), oracle.local_clustering(g))
+
+
 PARAMS = [(0, 0, 4096, 256), (64, 64, 256, 16), (16, 512, 16384, 1024), (0, 512, 64, 1),
           (512, 512, 4096, 256), (4, 32, 1024, 64), (0, 16, 100, 1000), (16, 128, 16384, 3)]
 
