@@ -59,7 +59,7 @@ typedef enum {
   TC_ERR_OUT_OF_MEMORY = -2,  /* device workspace allocation failed                 */
   TC_ERR_HIP = -3,            /* a HIP runtime call failed                          */
   TC_ERR_INVALID_GRAPH = -4,  /* a contract violation was found (see above)         */
-  TC_ERR_TOO_LARGE = -5,      /* n >= 2^30 or m >= 2^32                             */
+  TC_ERR_TOO_LARGE = -5,      /* n >= 2^30 or m > 2^32 - 2^20                       */
   TC_ERR_INTERNAL = -6        /* an internal consistency check failed               */
 } tc_status;
 
@@ -88,7 +88,7 @@ typedef struct {
  * For cover edges staged as long lists, a same-level apex w <= max(u, v) can never
  * count, so those list entries are skipped: T = c1 + t2 is computed, c2 is not.
  * Returns TC_ERR_INVALID_ARG for null pointers (when m > 0) or a null `count`,
- * TC_ERR_TOO_LARGE for n >= 2^30 or m >= 2^32, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
+ * TC_ERR_TOO_LARGE for n >= 2^30 or m > 2^32 - 2^20, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
 int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
              hipStream_t stream, uint64_t* count);
@@ -145,9 +145,9 @@ int tc_local_clustering(const uint32_t* rowptr, const uint64_t* tri, uint32_t n,
  * With a caller workspace the call allocates nothing, issues no memset, never
  * synchronises and reads no device data on the host, so it can be captured into a HIP
  * graph and replayed; a workspace must not be shared by calls that overlap in time.
- * Per graph: n_g < 2^30 and m_g < 2^32 (precondition).  Returns TC_ERR_INVALID_ARG
- * (null pointers, workspace too small), TC_ERR_TOO_LARGE (totals >= 2^32 - 16),
- * TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
+ * Per graph: n_g < 2^30 and m_g <= 2^32 - 2^20 (precondition).  Returns
+ * TC_ERR_INVALID_ARG (null pointers, workspace too small), TC_ERR_TOO_LARGE (total_rows or
+ * total_cols > 2^32 - 2^20), TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
 int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
                    const int64_t* row_off, const int64_t* col_off, uint32_t num_graphs,
@@ -214,7 +214,7 @@ int tc_serve_create(const tc_serve_config* cfg, tc_server** out);
  * Queues one graph.  rowptr[n + 1] and colidx[m] are HOST arrays that must stay valid
  * and unchanged until this request's result has been returned by tc_serve_poll.  Writes
  * the request's ticket.  Returns TC_ERR_INVALID_ARG for null pointers,
- * TC_ERR_TOO_LARGE for n >= 2^30 or m >= 2^32; a request whose footprint exceeds the
+ * TC_ERR_TOO_LARGE for n >= 2^30 or m > 2^32 - 2^20; a request whose footprint exceeds the
  * whole budget is accepted and completes at once with TC_ERR_OUT_OF_MEMORY.
  */
 int tc_serve_submit(tc_server* server, const uint32_t* rowptr, const uint32_t* colidx,

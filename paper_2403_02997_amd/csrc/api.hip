@@ -519,7 +519,9 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
 
 int check_args(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m) {
   if (n >= 0x40000000u) return TC_ERR_TOO_LARGE;  // LDS hash keys hold (w << 1) | same < 2^31
-  if (m >= 0x100000000ull) return TC_ERR_TOO_LARGE;
+  // 32-bit entry offsets: tile ends (e0 + kTile) and rounded-up tile counts need headroom
+  // below 2^32, so m stops 2^20 short of it.
+  if (m > kMaxEntries) return TC_ERR_TOO_LARGE;
   if (n > 0 && !rowptr) return TC_ERR_INVALID_ARG;
   if (m > 0 && (!colidx || n == 0)) return TC_ERR_INVALID_ARG;
   return TC_OK;
@@ -548,7 +550,7 @@ const char* tc_status_string(int status) {
     case TC_ERR_OUT_OF_MEMORY: return "device out of memory";
     case TC_ERR_HIP: return "HIP runtime error";
     case TC_ERR_INVALID_GRAPH: return "graph violates the CSR contract";
-    case TC_ERR_TOO_LARGE: return "graph too large (n >= 2^30 or m >= 2^32)";
+    case TC_ERR_TOO_LARGE: return "graph too large (n >= 2^30 or m > 2^32 - 2^20)";
     case TC_ERR_INTERNAL: return "internal consistency check failed";
     default: return "unknown status";
   }
@@ -656,7 +658,7 @@ int tc_count_batch(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
   if (!rowptr_cat || !row_off || !col_off || !counts || total_rows < num_graphs ||
       (total_cols > 0 && !colidx_cat))
     return TC_ERR_INVALID_ARG;
-  if (total_cols >= 0xFFFFFFF0ull || total_rows >= 0xFFFFFFF0ull) return TC_ERR_TOO_LARGE;
+  if (total_cols > kMaxEntries || total_rows > kMaxEntries) return TC_ERR_TOO_LARGE;
   const IsectParams prm = g_params;
   const size_t need = batch_workspace_bytes(num_graphs, total_rows, total_cols);
   if (workspace) {

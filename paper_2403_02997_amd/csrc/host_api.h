@@ -7,6 +7,11 @@
 
 namespace tc {
 
+// Largest number of stored entries (and of concatenated rows or entries in a batch) the
+// entry points accept: entry offsets are 32-bit, and the tile arithmetic over them (a
+// tile end e0 + 1024, a tile count rounded up) needs headroom below 2^32.
+constexpr uint64_t kMaxEntries = 0x100000000ull - 0x100000ull;  // 2^32 - 2^20
+
 // Whether the single-graph path of the calling thread may run the wavefront class and
 // the hub count on a second stream (default on).  A thread whose own stream is one of
 // several long-lived streams that already fill the device's few hardware queues (the

@@ -295,7 +295,7 @@ int tc_serve_create(const tc_serve_config* cfg, tc_server** out) {
 int tc_serve_submit(tc_server* s, const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
                     uint64_t m, uint64_t* ticket) {
   if (!s || !ticket || !rowptr || (m > 0 && !colidx)) return TC_ERR_INVALID_ARG;
-  if (n >= 0x40000000u || m >= 0x100000000ull) return TC_ERR_TOO_LARGE;
+  if (n >= 0x40000000u || m > tc::kMaxEntries) return TC_ERR_TOO_LARGE;
   Request r{};
   r.rowptr = rowptr;
   r.colidx = colidx;

@@ -49,6 +49,7 @@ def test_status_strings_and_version(lib):
     assert lib.tc_status_string(-99).decode() == "unknown status"
     # the limits named in the message are the ones check_args applies
     assert "2^30" in lib.tc_status_string(-5).decode()
+    assert "2^32 - 2^20" in lib.tc_status_string(-5).decode()
     assert lib.tc_version() >= 10000
 
 
@@ -63,6 +64,8 @@ def test_argument_errors_without_gpu(lib):
     assert lib.tc_count(None, None, 0x80000000, 0, None, ctypes.byref(out)) == -5
     assert lib.tc_count(None, None, 0x40000000, 0, None, ctypes.byref(out)) == -5
     assert lib.tc_count(None, None, 10, 1 << 32, None, ctypes.byref(out)) == -5
+    # entry offsets keep 2^20 of headroom below 2^32 for the tile arithmetic
+    assert lib.tc_count(None, None, 10, (1 << 32) - (1 << 20) + 1, None, ctypes.byref(out)) == -5
     # data required when m > 0
     assert lib.tc_count(None, None, 10, 4, None, ctypes.byref(out)) == -1
     assert out.value == 7  # untouched on error
