@@ -238,6 +238,57 @@ def wheel(k: int) -> CSR:
     return from_edges(k + 1, e, f"W{k}")
 
 
+def clique_union(parts, book_pages: int = 0, chunk_entries: int = 1 << 26) -> CSR:
+    """Disjoint union of `count` copies of K_k for each (k, count) in `parts`, in that order
+    with consecutive IDs, then (if book_pages >= 1) one book K_{1,1,q}: vertices r, h
+    joined to each other and to q pages (r first, then h, then the pages).  Built directly
+    as CSR with vectorised fills, so it scales to billions of stored entries."""
+    parts = [(int(k), int(c)) for k, c in parts if c > 0]
+    assert all(k >= 1 for k, _ in parts)
+    deg_groups = [(k - 1, k * c) for k, c in parts]
+    n_cl = sum(k * c for k, c in parts)
+    q = int(book_pages)
+    n = n_cl + (q + 2 if q else 0)
+    m = sum(k * (k - 1) * c for k, c in parts) + (4 * q + 2 if q else 0)
+    assert m < (1 << 32) and n < (1 << 31)
+    deg = np.empty(n, dtype=np.uint64)
+    pos = 0
+    for d, cnt in deg_groups:
+        deg[pos:pos + cnt] = d
+        pos += cnt
+    if q:
+        deg[pos:pos + 2] = q + 1
+        deg[pos + 2:] = 2
+    rowptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(deg, out=rowptr[1:])
+    colidx = np.empty(m, dtype=np.uint32)
+    vbase, ebase = 0, 0
+    for k, c in parts:
+        kk = k * (k - 1)
+        j = np.arange(k - 1, dtype=np.uint32)
+        pat = (j[None, :] + (j[None, :] >= np.arange(k, dtype=np.uint32)[:, None])).ravel()
+        per = max(1, chunk_entries // max(kk, 1))
+        for c0 in range(0, c, per):
+            cc = min(per, c - c0)
+            if kk:
+                bases = (vbase + (c0 + np.arange(cc, dtype=np.uint64)) * k).astype(np.uint32)
+                out = colidx[ebase + c0 * kk: ebase + (c0 + cc) * kk].reshape(cc, kk)
+                np.add(pat[None, :], bases[:, None], out=out)
+        vbase += k * c
+        ebase += kk * c
+    if q:
+        r, h = vbase, vbase + 1
+        pages = np.arange(vbase + 2, vbase + 2 + q, dtype=np.uint32)
+        colidx[ebase] = h
+        colidx[ebase + 1: ebase + 1 + q] = pages
+        colidx[ebase + 1 + q] = r
+        colidx[ebase + 2 + q: ebase + 2 + 2 * q] = pages
+        pr = colidx[ebase + 2 + 2 * q:].reshape(q, 2)
+        pr[:, 0] = r
+        pr[:, 1] = h
+    return CSR(rowptr.astype(np.uint32), colidx, f"cliques{len(parts)}+B{q}")
+
+
 def friendship(k: int) -> CSR:
     """k triangles sharing vertex 0."""
     e = []

@@ -448,7 +448,8 @@ __device__ __forceinline__ void count_hit(u32 r, u32 w, u32 x, u32 y, u32 vmax, 
 // First index in [lo, hi) of the sorted array a with a[i] >= v.
 __device__ __forceinline__ u32 lower_bound_g(const u32* __restrict__ a, u32 lo, u32 hi, u32 v) {
   while (lo < hi) {
-    const u32 mid = (lo + hi) >> 1;
+    // lo and hi are absolute entry positions (up to 2^32 - 2^20): lo + hi would wrap
+    const u32 mid = lo + ((hi - lo) >> 1);
     if (a[mid] < v) lo = mid + 1;
     else hi = mid;
   }
