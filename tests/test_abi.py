@@ -76,6 +76,11 @@ def test_argument_errors_without_gpu(lib):
                                                           ctypes.c_void_p]
     assert lib.tc_count_batch(None, None, None, None, 3, 10, 20, None, 0, None, None) == -1
     assert lib.tc_count_batch(None, None, None, None, 0, 0, 0, None, 0, None, None) == 0
+    # totals above 2^32 - 2^20 are refused before the workspace or any launch
+    dummy = (ctypes.c_uint64 * 4)()
+    p = ctypes.cast(dummy, ctypes.c_void_p)
+    assert lib.tc_count_batch(p, p, p, p, 1, 2, (1 << 32) - (1 << 20) + 1, None, 0, None,
+                              p) == -5
     # clustering coefficients: checked before the launch
     lib.tc_local_clustering.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_void_p]
