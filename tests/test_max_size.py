@@ -85,6 +85,17 @@ def test_big_instance_crosses_2_31_before_its_small_parts():
     assert total < (1 << 32) - (1 << 20)
 
 
+def test_big_instance_hubs_are_the_book_spine():
+    # The default hub rule (256 hubs, degree class >= class(4096)) on the large instance's
+    # degrees picks exactly r and h, the two vertices of degree q + 1.
+    import bench
+    d = np.concatenate([np.full(k * c, k - 1, np.int64) for k, c in PARTS_BIG]
+                       + [np.full(2, PAGES_BIG + 1), np.full(PAGES_BIG, 2)])
+    hubs = np.flatnonzero(bench.hub_set(d, 256, 4096))
+    spine = sum(k * c for k, c in PARTS_BIG)
+    assert hubs.tolist() == [spine, spine + 1]
+
+
 @pytest.mark.gpu
 def test_more_than_2_31_entries(tc_lib):
     import torch
