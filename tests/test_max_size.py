@@ -66,6 +66,21 @@ def closed_form_per_vertex(parts, q):
     return np.concatenate(chunks)
 
 
+def test_clique_union_equals_edge_list_construction():
+    # The vectorised builder gives the same CSR as the generic edge-list builder.
+    parts, q = [(4, 3), (1, 2), (2, 2), (6, 1)], 5
+    edges, base = [], 0
+    for k, c in parts:
+        for _ in range(c):
+            edges += [(base + i, base + j) for i in range(k) for j in range(i + 1, k)]
+            base += k
+    r, h = base, base + 1
+    edges += [(r, h)] + [(r, base + 2 + i) for i in range(q)] + [(h, base + 2 + i) for i in range(q)]
+    ref = gg.from_edges(base + 2 + q, edges)
+    got = gg.clique_union(parts, q, chunk_entries=7)  # several fill chunks per part
+    assert np.array_equal(got.rowptr, ref.rowptr) and np.array_equal(got.colidx, ref.colidx)
+
+
 def test_closed_forms_match_oracle():
     g = gg.clique_union(PARTS_SMALL, PAGES_SMALL)
     assert oracle.check_csr(g) == 0
