@@ -116,7 +116,7 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
  * count (Watts and Strogatz; Section 1 names clustering coefficients among the uses of
  * triangle counts): C(v) = 2 t(v) / (d(v) (d(v) - 1)), the fraction of v's neighbour
  * pairs that are adjacent, and C(v) = 0 when d(v) < 2.
- * rowptr is the graph's DEVICE uint32[n + 1] (degrees only; colidx is not read), tri the
+ * rowptr is the graph's DEVICE uint32[n + 1] (read for the degrees only), tri the
  * DEVICE uint64[n] that tc_count_per_vertex wrote, cc_out a DEVICE double[n] that is
  * overwritten.  Computed in double with one correctly rounded division per vertex.
  * Stream-ordered on `stream`: returns after queueing one kernel, without synchronising,
