@@ -91,6 +91,10 @@ def test_closed_forms_match_oracle():
     assert np.array_equal(r.level, closed_form_levels(PARTS_SMALL, PAGES_SMALL))
     assert r.depth == f["depth"]
     assert np.array_equal(r.per_vertex, closed_form_per_vertex(PARTS_SMALL, PAGES_SMALL))
+    # the split variant: G0 holds each K_k's level-1 clique K_{k-1} (t0 = C(k-1, 3)); every
+    # other triangle has the root as its apex (t1 = C(k-1, 2), and q in the book)
+    t0 = sum(c * math.comb(k - 1, 3) for k, c in PARTS_SMALL)
+    assert oracle.cetc_split(g, r.level) == (f["T"], t0, f["S"])
 
 
 def test_big_instance_crosses_2_31_before_its_small_parts():
