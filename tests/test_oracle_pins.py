@@ -9,7 +9,11 @@
   (Lemmas H-E and HE2), T does not depend on the BFS roots (Theorem Correctness holds
   for an arbitrarily rooted BFS), CETC-SM's T = c1 + c2 / 3, per-vertex counts sum to 3T
   and equal diag(A^3) / 2;
-- a BFS certificate for the levels (exact distances from the smallest-ID root).
+- a BFS certificate for the levels (exact distances from the smallest-ID root);
+- the split variant CETC-Seq-S (Section 4.3): closed forms, both terms against triangle
+  enumeration by kind under BFS levels and under arbitrary labels, and t1 = c1,
+  3 t0 = c2 of CETC-SM;
+- local clustering coefficients: closed forms and networkx's clustering().
 """
 import json
 import math
