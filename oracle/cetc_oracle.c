@@ -117,18 +117,16 @@ int64_t orc_bfs_levels(const uint32_t* rowptr, const uint32_t* colidx, uint32_t 
 }
 
 /*
- * Size of the cover-edge set of Theorem Gen-CES (Section 4.1): the horizontal edges,
- * L(u) == L(v), each undirected edge counted once (u < v).  The same test as the
- * first line of the CETC-Seq edge loop, without the intersections.
+ * Size of the cover-edge set of Theorem Gen-CES (Section 4.1): the number of horizontal
+ * edges, those whose endpoints share a BFS level.  Every undirected edge is stored twice
+ * in the CSR; only the copy in the row of its smaller endpoint is counted.
  */
 uint64_t orc_cover_edges(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
                          const uint32_t* level) {
   uint64_t S = 0;
   for (uint32_t u = 0; u < n; ++u)
-    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
-      uint32_t v = colidx[e];
-      if (level[u] == level[v] && u < v) S += 1;
-    }
+    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
+      S += (u < colidx[e] && level[colidx[e]] == level[u]) ? 1u : 0u;
   return S;
 }
 
@@ -141,10 +139,14 @@ typedef struct {
 } orc_stats;
 
 /*
- * CETC-Seq counting loop (Section 4.2, Algorithm CETC-Seq, after the BFS):
- *   for every edge (u, v) with L(u) == L(v) and u < v            -- horizontal, once
- *     for every w in N(u) ∩ N(v)                                  -- two-pointer merge
- *       if L(u) != L(w), or L(u) == L(w) and v < w:  T <- T + 1
+ * The counting step of CETC-Seq (Section 4.2), after the BFS.  Each undirected edge
+ * {u, v} is taken once, from the row of its smaller endpoint u.  When u and v share a
+ * level the edge is a cover edge, and every common neighbour w of u and v is the apex of
+ * one triangle {u, v, w} that contains it.  Such a triangle has either this one
+ * horizontal edge (w on another level) or three (w on the same level; Lemma HE2).  The
+ * first kind is counted here at once; the second kind is counted only at its edge of the
+ * two smallest IDs, i.e. when w is larger than v (Theorem Correctness).  The common
+ * neighbours come from a two-pointer walk over the two sorted rows.
  * `level` comes from orc_bfs_levels.  If tri_per_vertex is not NULL (n entries, zeroed
  * by the caller) every counted triangle {u, v, w} adds 1 to each of its three vertices.
  */
@@ -152,23 +154,25 @@ void orc_cetc_seq(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,
                   const uint32_t* level, orc_stats* st, uint64_t* tri_per_vertex) {
   uint64_t T = 0, S = 0, pmin = 0, pmerge = 0;
   for (uint32_t u = 0; u < n; ++u) {
-    for (uint64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
-      uint32_t v = colidx[e];
-      if (!(level[u] == level[v] && u < v)) continue; /* not a cover edge */
+    const uint64_t ub = rowptr[u], ue = rowptr[u + 1];
+    for (uint64_t e = ub; e < ue; ++e) {
+      const uint32_t v = colidx[e];
+      if (v <= u) continue;                /* the copy in the larger endpoint's row */
+      if (level[v] != level[u]) continue;  /* not horizontal: covers nothing */
       S += 1;
-      uint64_t du = rowptr[u + 1] - rowptr[u], dv = rowptr[v + 1] - rowptr[v];
-      pmin += du < dv ? du : dv;
-      pmerge += du + dv;
-      /* N(u) ∩ N(v) by merging the two sorted lists. */
-      uint64_t i = rowptr[u], j = rowptr[v];
-      while (i < rowptr[u + 1] && j < rowptr[v + 1]) {
+      const uint64_t vb = rowptr[v], ve = rowptr[v + 1];
+      pmin += (ue - ub) < (ve - vb) ? (ue - ub) : (ve - vb);
+      pmerge += (ue - ub) + (ve - vb);
+      uint64_t i = ub, j = vb;
+      while (i < ue && j < ve) {
         if (colidx[i] < colidx[j]) {
           ++i;
         } else if (colidx[i] > colidx[j]) {
           ++j;
         } else {
-          uint32_t w = colidx[i];
-          if (level[u] != level[w] || (level[u] == level[w] && v < w)) {
+          const uint32_t w = colidx[i];
+          const int one_horizontal = level[w] != level[u];
+          if (one_horizontal || w > v) {
             T += 1;
             if (tri_per_vertex) {
               tri_per_vertex[u] += 1;

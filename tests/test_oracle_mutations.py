@@ -2,10 +2,11 @@
 
 Each case plants one mistake in a copy of oracle/cetc_oracle.c (a wrong index, a
 flipped comparison, a dropped condition, a wrong divisor, a broken merge step, a
-different BFS root order, a split pass that adds to the wrong set, leaves marks behind or
-drops a term, a clustering coefficient over ordered pairs), builds the copy with gcc into a temporary directory, and
-checks that at least one pin from test_oracle_pins fails against it.  The committed
-oracle is never modified.
+cover-edge count over both stored copies of an edge or with the wrong level test, a
+different BFS root order, a split pass that adds to the wrong set, leaves marks behind
+or drops a term, a clustering coefficient over ordered pairs), builds the copy with gcc
+into a temporary directory, and checks that at least one pin from test_oracle_pins
+fails against it.  The committed oracle is never modified.
 """
 import os
 import subprocess
@@ -22,10 +23,17 @@ from tests.test_oracle_pins import bfs_certificate, split_by_enumeration
 SRC = os.path.join(os.path.dirname(oracle.__file__), "cetc_oracle.c")
 
 MUTATIONS = {
-    "rule_uses_u_not_v": ("(level[u] == level[w] && v < w)", "(level[u] == level[w] && u < w)"),
-    "rule_level_test_flipped": ("if (level[u] != level[w] || (", "if (level[u] == level[w] || ("),
-    "edge_loop_drops_u_lt_v": ("if (!(level[u] == level[v] && u < v)) continue; /* not a cover edge */",
-                               "if (!(level[u] == level[v])) continue;"),
+    "rule_uses_u_not_v": ("if (one_horizontal || w > v) {", "if (one_horizontal || w > u) {"),
+    "rule_level_test_flipped": ("const int one_horizontal = level[w] != level[u];",
+                                "const int one_horizontal = level[w] == level[u];"),
+    "edge_loop_drops_u_lt_v": ("      if (v <= u) continue;                /* the copy in the larger endpoint's row */\n",
+                               ""),
+    "edge_loop_not_horizontal": ("if (level[v] != level[u]) continue;  /* not horizontal: covers nothing */",
+                                 "if (level[v] == level[u]) continue;"),
+    "cover_edges_drops_u_lt_v": ("S += (u < colidx[e] && level[colidx[e]] == level[u]) ? 1u : 0u;",
+                                 "S += (level[colidx[e]] == level[u]) ? 1u : 0u;"),
+    "cover_edges_level_test_flipped": ("S += (u < colidx[e] && level[colidx[e]] == level[u]) ? 1u : 0u;",
+                                       "S += (u < colidx[e] && level[colidx[e]] != level[u]) ? 1u : 0u;"),
     "bfs_level_step_two": ("level[y] = level[x] + 1;", "level[y] = level[x] + 2;"),
     "sm_divides_by_two": ("return c1 + c2 / 3;", "return c1 + c2 / 2;"),
     "merge_advances_wrong_list": ("if (colidx[i] < colidx[j]) {\n          ++i;",
@@ -50,6 +58,10 @@ def pins_hold() -> bool:
         g = gg.from_edges(34, list(k.edges()))
         r = oracle.cetc_seq(g)
         if r.triangles != 45 or round(100.0 * r.cover_edges / 78, 1) != 35.9:
+            return False
+        if oracle.cover_edges(g, r.level) != 28:
+            return False
+        if oracle.cover_edges(gg.cycle(9), oracle.bfs_levels(gg.cycle(9))[0]) != 1:
             return False
         for seed in range(6):
             g = gg.gnp_small(12 + seed, 0.5, seed)

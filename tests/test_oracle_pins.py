@@ -10,6 +10,8 @@
   for an arbitrarily rooted BFS), CETC-SM's T = c1 + c2 / 3, per-vertex counts sum to 3T
   and equal diag(A^3) / 2;
 - a BFS certificate for the levels (exact distances from the smallest-ID root);
+- the cover-edge set size |S| (Theorem Gen-CES): closed forms, networkx BFS distances on
+  tiny graphs, and CETC-Seq's own |S|;
 - the split variant CETC-Seq-S (Section 4.3): closed forms, both terms against triangle
   enumeration by kind under BFS levels and under arbitrary labels, and t1 = c1,
   3 t0 = c2 of CETC-SM;
@@ -153,6 +155,88 @@ def test_disjoint_union_additive():
     parts = [gg.complete(6), gg.wheel(8), gg.rmat(8, 16, 5), gg.empty_graph(3), gg.cycle(3)]
     u = gg.disjoint_union(parts)
     assert full_check(u).triangles == sum(full_check(p).triangles for p in parts)
+
+
+# ---- the cover-edge set (Theorem Gen-CES, Section 4.1) ------------------------------------
+# orc_cover_edges counts the horizontal edges.  Its pins: closed forms of |S| under the
+# smallest-ID roots, a count over networkx's own BFS distances on tiny graphs, and the
+# separately written edge loop of CETC-Seq (its |S|).
+
+def cover_edges(g):
+    level, _ = oracle.bfs_levels(g)
+    return oracle.cover_edges(g, level)
+
+
+def test_cover_edges_karate_table1():
+    # Table 1: c = 35.9 % of karate's 78 edges; 28 is the only |S| that rounds to it
+    ref = json.load(open(os.path.join(GOLDEN, "karate_table1.json")))
+    k = nx.karate_club_graph()
+    g = gg.from_edges(k.number_of_nodes(), list(k.edges()))
+    S = cover_edges(g)
+    assert round(100.0 * S / ref["m"], 1) == ref["covering_ratio_percent"]
+    assert S == 28
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 9, 30])
+def test_cover_edges_complete(n):
+    # root 0 is adjacent to every other vertex: levels 0, 1, 1, ...; the level-1 clique
+    assert cover_edges(gg.complete(n)) == math.comb(n - 1, 2)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.path(30), lambda: gg.star(12), lambda: gg.random_tree(200, 5),
+    lambda: gg.cycle(10), lambda: gg.hypercube(6), lambda: gg.complete_bipartite(5, 9),
+    lambda: gg.empty_graph(4)])
+def test_cover_edges_bipartite_zero(make):
+    # in a bipartite graph the BFS levels alternate sides: no edge joins equal levels
+    assert cover_edges(make()) == 0
+
+
+@pytest.mark.parametrize("k", [3, 5, 9, 21])
+def test_cover_edges_odd_cycle(k):
+    # the two BFS fronts of an odd cycle meet in exactly one edge on the same level
+    assert cover_edges(gg.cycle(k)) == 1
+
+
+@pytest.mark.parametrize("R,C", [(1, 1), (1, 6), (5, 2), (7, 7), (12, 31)])
+def test_cover_edges_triangulated_grid(R, C):
+    # from corner 0 with diagonals (i, j)-(i+1, j+1), L(i, j) = max(i, j): a row edge
+    # (i, j)-(i, j+1) is horizontal iff j + 1 <= i, a column edge iff i + 1 <= j, a
+    # diagonal never
+    S = sum(min(i, C - 1) for i in range(R)) + sum(min(j, R - 1) for j in range(C))
+    assert cover_edges(gg.tri_grid(R, C)) == S
+
+
+def test_cover_edges_clique_union_and_book():
+    # each K_k: its root alone on level 0, the rest a level-1 clique (C(k-1, 2) edges);
+    # the book K_{1,1,q}: r on level 0, the spine h and the q pages on level 1 (q edges)
+    parts, q = [(3, 4), (6, 2), (11, 1)], 17
+    S = q + sum(c * math.comb(k - 1, 2) for k, c in parts)
+    assert cover_edges(gg.clique_union(parts, q)) == S
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_cover_edges_networkx_bfs(seed):
+    # tiny graphs: levels from networkx's shortest paths from each component's smallest
+    # vertex, horizontal edges counted over networkx's edge list
+    g = gg.gnp_small(8 + 3 * seed, [0.1, 0.25, 0.5][seed % 3], 300 + seed)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    G.add_edges_from((u, int(v)) for u in range(g.n)
+                     for v in g.colidx[g.rowptr[u]:g.rowptr[u + 1]])
+    dist = {}
+    for comp in nx.connected_components(G):
+        dist.update(nx.single_source_shortest_path_length(G, min(comp)))
+    S = sum(1 for a, b in G.edges() if dist[a] == dist[b])
+    assert cover_edges(g) == S
+
+
+@pytest.mark.parametrize("make", [lambda: gg.rmat(11, 16, 41), lambda: gg.erdos_renyi(4000, 12, 8),
+                                  lambda: gg.tri_grid(30, 40, 0.03, 6)])
+def test_cover_edges_match_cetc_seq(make):
+    g = make()
+    level, _ = oracle.bfs_levels(g)
+    assert oracle.cover_edges(g, level) == oracle.cetc_seq(g, level=level).cover_edges
 
 
 # ---- invariants -------------------------------------------------------------------------
