@@ -168,9 +168,11 @@ size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows,
  * the oldest would still fit beside them.  Requests with at most small_max_entries stored
  * entries are packed, whenever the previous batch has completed, into one tc_count_batch
  * launch over everything admitted meanwhile; larger requests run through tc_count, those
- * below large_min_entries and the rest on two separate workers, so that no request waits
- * behind the upload of a much larger one.  The three paths overlap on the device.
- * Results equal tc_count's.  Each server drives the device that is current at
+ * below large_min_entries in arrival order and the rest smallest first (by stored
+ * entries; one that has waited 2 s since admission goes next) on two separate workers,
+ * so that no request waits behind the upload of a much larger one.  The three paths
+ * overlap on the device.  Results equal tc_count's.  Each server drives the device that
+ * is current at
  * tc_serve_create with three host threads and three non-blocking streams of default
  * priority; its tc_count calls keep to those streams (no second stream per call).
  */
@@ -214,8 +216,15 @@ int tc_serve_create(const tc_serve_config* cfg, tc_server** out);
  * Queues one graph.  rowptr[n + 1] and colidx[m] are HOST arrays that must stay valid
  * and unchanged until this request's result has been returned by tc_serve_poll.  Writes
  * the request's ticket.  Returns TC_ERR_INVALID_ARG for null pointers,
- * TC_ERR_TOO_LARGE for n >= 2^30 or m > 2^32 - 2^20; a request whose footprint exceeds the
- * whole budget is accepted and completes at once with TC_ERR_OUT_OF_MEMORY.
+ * TC_ERR_TOO_LARGE for n >= 2^30 or m > 2^32 - 2^20, TC_ERR_INVALID_GRAPH when
+ * rowptr[0] != 0 or rowptr[n] != m; a request whose footprint exceeds the whole budget is
+ * accepted and completes at once with TC_ERR_OUT_OF_MEMORY.  Before any kernel reads a
+ * request the server checks that rowptr is non-decreasing and every ID is below n (on the
+ * host for batched requests, on the device for the others); a request that fails
+ * completes with TC_ERR_INVALID_GRAPH and costs the requests beside it nothing.  The
+ * other properties of the format (sorted rows, symmetry, no self-loops) stay the
+ * caller's precondition: breaking them gives a wrong count, never an access outside the
+ * request's own arrays.
  */
 int tc_serve_submit(tc_server* server, const uint32_t* rowptr, const uint32_t* colidx,
                     uint32_t n, uint64_t m, uint64_t* ticket);
@@ -257,10 +266,11 @@ int tc_set_isect_params(uint32_t lane_max, uint32_t wave_max, uint32_t chunk, ui
 int tc_get_isect_params(uint32_t* out4);
 
 /*
- * Hub pass of tc_count (Section 5's pruned count, Alg. 10's per-edge sum regrouped; the
- * result is the same T).  The hubs are the vertices of the highest degree classes: as
- * many whole classes as hold at most max_hubs (<= 256) vertices together, each class at
- * least the class of min_degree (classes are four per octave of the degree).  The cover
+ * Hub pass of tc_count (the apex test of CETC-Seq, Section 4.2, applied as the pruned
+ * count, with its per-edge sum regrouped by partner; the result is the same T).  The
+ * hubs are the vertices of the highest degree classes: as many whole classes as hold at
+ * most max_hubs (<= 256) vertices together, each class at least the class of min_degree
+ * (classes are four per octave of the degree).  The cover
  * edges staged under a hub are not intersected one by one: for each partner y the pass
  * streams y's other-level neighbours and its same-level neighbours above y once and looks
  * each one up in a per-vertex bit mask of the hubs whose pruned list holds it, masked

@@ -1,8 +1,8 @@
 // Hub pass: the cover edges staged under the highest-degree vertices, counted one
 // partner at a time.
 //
-// For a cover edge {x, y} staged under x, the pruned count of Section 5 is the number of
-// w in N(x) ∩ N(y) with L(w) != L(x) or w > max(x, y).  With S(x) = x's other-level
+// For a cover edge {x, y} staged under x, the apex test of CETC-Seq (Section 4.2) counts
+// the w in N(x) ∩ N(y) with L(w) != L(x) or w > max(x, y).  With S(x) = x's other-level
 // neighbours and its same-level neighbours above x, and N'(y) the same for y, that count
 // is |S(x) ∩ N'(y)|: a w of N'(y) on x's level and at or below x is in neither part of
 // S(x).  For the hubs h_0 .. h_{K-1} (K <= 256) the pass stores, per vertex w, the bit

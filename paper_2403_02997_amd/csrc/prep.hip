@@ -352,6 +352,27 @@ bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t 
   return h == 0;
 }
 
+// Every neighbour ID below n (the bounds half of the contract: with rowptr monotone from
+// 0 to m, no kernel then reads outside the graph's arrays).
+__global__ void __launch_bounds__(256) k_check_ids(const u32* __restrict__ colidx, u32 n, u32 m,
+                                                   u32* __restrict__ flag) {
+  u32 bad = 0;
+  for (u32 e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x)
+    bad |= colidx[e] >= n ? 1u : 0u;
+  if (__ballot(bad != 0) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+int check_csr_bounds(const u32* rowptr, const u32* colidx, u32 n, u32 m, u32* flag,
+                     hipStream_t s) {
+  if (hipMemsetAsync(flag, 0, sizeof(u32), s) != hipSuccess) return -3;
+  if (m > 0) {
+    const u32 g = min(cdiv(m, 256), (u32)num_cus() * 8);
+    hipLaunchKernelGGL(k_check_ids, dim3(g), dim3(256), 0, s, colidx, n, m, flag);
+  }
+  if (hipGetLastError() != hipSuccess) return -3;
+  return validate_rowptr_ok(rowptr, n, m, flag, s) ? 0 : (hipGetLastError() != hipSuccess ? -3 : -4);
+}
+
 void launch_validate(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
                      u32* flag, hipStream_t s) {
   if (m == 0) return;

@@ -14,8 +14,13 @@
 //             CSR (uploaded once, resident until its counts are back) and counted by one
 //             tc_count_batch launch;
 //   medium  : up to `large_min_entries`, one tc_count call each, in arrival order;
-//   large   : the rest, one tc_count call each, in arrival order.
+//   large   : the rest, one tc_count call each, smallest first (a request that has
+//             waited kLargeMaxWait seconds goes next).
 // Results carry the request's submit, admit and completion times on the server clock.
+// Requests come from callers, so their bounds are checked before any kernel reads them:
+// rowptr[0] = 0 and rowptr[n] = m at submission, the rest of the bounds (rowptr
+// non-decreasing, every ID < n) on the host for batched requests and on the device for
+// the others; a request that breaks them completes with TC_ERR_INVALID_GRAPH.
 #include <stdint.h>
 #include <string.h>
 
@@ -48,6 +53,11 @@ struct Request {
   double t_submit, t_admit;
 };
 
+// The large path serves the smallest admitted request first (by stored entries), so
+// a stream of scale-22..24 requests does not queue behind a scale-26 one; a request
+// that has waited this long since admission is served next regardless.
+constexpr double kLargeMaxWait = 2.0;  // seconds
+
 inline uint64_t csr_bytes(uint32_t n, uint64_t m) { return 4ull * ((uint64_t)n + 1) + 4ull * m; }
 
 // Device bytes a request holds while admitted: its CSR and, on the single-graph path,
@@ -57,6 +67,20 @@ inline uint64_t single_footprint(uint32_t n, uint64_t m) {
 }
 inline uint64_t batched_footprint(uint32_t n, uint64_t m) {
   return csr_bytes(n, m) + 21ull * ((uint64_t)n + 1) + 8ull * m + 64;
+}
+
+// The bounds a request must keep before any kernel reads it: rowptr non-decreasing from 0
+// to m and every neighbour ID below n.  A batched request that broke them would send the
+// batch kernel into other members' slices or past the workspace, so small requests are
+// checked here on the host (at most small_max_entries entries each); the single-graph
+// paths check the same on the device after the upload (check_csr_bounds).
+bool host_bounds_ok(const Request& r) {
+  if (r.rowptr[0] != 0 || r.rowptr[r.n] != r.m) return false;
+  for (uint32_t v = 0; v < r.n; ++v)
+    if (r.rowptr[v + 1] < r.rowptr[v]) return false;
+  uint32_t mx = 0;
+  for (uint64_t e = 0; e < r.m; ++e) mx = std::max(mx, r.colidx[e]);
+  return r.m == 0 || mx < r.n;
 }
 
 }  // namespace
@@ -202,9 +226,17 @@ struct tc_server {
         }
         st.batches += 1;
       }
+      std::vector<Request> bad;
+      size_t kept = 0;
+      for (size_t i = 0; i < b.size(); ++i) {
+        if (host_bounds_ok(b[i])) b[kept++] = b[i];
+        else bad.push_back(b[i]);
+      }
+      b.resize(kept);
       std::vector<uint64_t> counts;
-      const int rc = run_batch(b, counts);
+      const int rc = b.empty() ? TC_OK : run_batch(b, counts);
       std::lock_guard<std::mutex> lk(mu);
+      for (const Request& r : bad) finish_locked(r, TC_ERR_INVALID_GRAPH, 0, 0);
       for (size_t i = 0; i < b.size(); ++i) finish_locked(b[i], rc, rc == TC_OK ? counts[i] : 0, 0);
     }
   }
@@ -213,8 +245,8 @@ struct tc_server {
   int run_single(const Request& r, hipStream_t s_single, uint64_t* tri) {
     char* dev = nullptr;
     const size_t o_ci = (4ull * (r.n + 1) + 255) / 256 * 256;
-    if (hipMallocAsync((void**)&dev, o_ci + 4ull * std::max<uint64_t>(r.m, 1), s_single) !=
-        hipSuccess) {
+    const size_t o_flag = o_ci + (4ull * std::max<uint64_t>(r.m, 1) + 255) / 256 * 256;
+    if (hipMallocAsync((void**)&dev, o_flag + 256, s_single) != hipSuccess) {
       (void)hipGetLastError();
       return TC_ERR_OUT_OF_MEMORY;
     }
@@ -224,6 +256,11 @@ struct tc_server {
         (r.m && hipMemcpyAsync(dev + o_ci, r.colidx, 4ull * r.m, hipMemcpyHostToDevice,
                                s_single) != hipSuccess))
       rc = TC_ERR_HIP;
+    if (rc == TC_OK) {
+      const int b = check_csr_bounds((const uint32_t*)dev, (const uint32_t*)(dev + o_ci), r.n,
+                                     (uint32_t)r.m, (uint32_t*)(dev + o_flag), s_single);
+      rc = b == 0 ? TC_OK : (b == -4 ? TC_ERR_INVALID_GRAPH : TC_ERR_HIP);
+    }
     if (rc == TC_OK)
       rc = tc_count((const uint32_t*)dev, (const uint32_t*)(dev + o_ci), r.n, r.m, s_single, tri);
     if (hipFreeAsync(dev, s_single) != hipSuccess && rc == TC_OK) rc = TC_ERR_HIP;
@@ -241,8 +278,15 @@ struct tc_server {
         std::unique_lock<std::mutex> lk(mu);
         cv_single[k].wait(lk, [&] { return stop || !single_ready[k].empty(); });
         if (stop) return;
-        r = single_ready[k].front();
-        single_ready[k].pop_front();
+        std::deque<Request>& q = single_ready[k];
+        auto pick = q.begin();
+        if (k == 1 && now() - q.front().t_admit < kLargeMaxWait) {
+          // shortest first by stored entries, unless the oldest has waited too long
+          for (auto it = q.begin(); it != q.end(); ++it)
+            if (it->m < pick->m) pick = it;
+        }
+        r = *pick;
+        q.erase(pick);
         st.singles += 1;
       }
       uint64_t tri = 0;
@@ -296,6 +340,7 @@ int tc_serve_submit(tc_server* s, const uint32_t* rowptr, const uint32_t* colidx
                     uint64_t m, uint64_t* ticket) {
   if (!s || !ticket || !rowptr || (m > 0 && !colidx)) return TC_ERR_INVALID_ARG;
   if (n >= 0x40000000u || m > tc::kMaxEntries) return TC_ERR_TOO_LARGE;
+  if (rowptr[0] != 0 || rowptr[n] != m) return TC_ERR_INVALID_GRAPH;
   Request r{};
   r.rowptr = rowptr;
   r.colidx = colidx;

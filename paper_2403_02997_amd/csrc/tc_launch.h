@@ -97,6 +97,11 @@ size_t scan_tmp_words(u32 count);
 void launch_scan(const u32* in, u32* out, u32 count, u32* tmp, hipStream_t s);
 void launch_validate(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
                      u32* flag, hipStream_t s);
+// Bounds check of an untrusted CSR on the device: rowptr[0] = 0, non-decreasing,
+// rowptr[n] = m, every ID < n.  flag: one device word of scratch.  Synchronises s.
+// Returns 0 (valid), -4 (a bound is broken) or -3 (a HIP call failed).
+int check_csr_bounds(const u32* rowptr, const u32* colidx, u32 n, u32 m, u32* flag,
+                     hipStream_t s);
 bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t s);
 
 // ---- BFS ----

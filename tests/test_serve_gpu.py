@@ -133,3 +133,106 @@ def test_serve_destroy_waits_for_submitted_work(tc_lib):
         srv.submit(g.rowptr, g.colidx)
     srv.close()  # returns once every request has completed
     torch.cuda.synchronize()
+
+
+def test_serve_rejects_malformed_requests(tc_lib):
+    """Requests that break the bounds of the format never reach a kernel: rowptr[0] != 0
+    or rowptr[n] != m is refused at submission; a decreasing rowptr or an ID >= n is
+    found before the batched launch (host) or before the single-graph count (device) and
+    completes with TC_ERR_INVALID_GRAPH, while valid requests beside them count as usual."""
+    good = [gg.complete(9), gg.rmat(9, 16, 31), gg.rmat(12, 16, 32), gg.wheel(40)]
+    ref = [oracle.count(g) for g in good]
+    small = gg.rmat(8, 8, 33)
+    big = gg.rmat(12, 16, 34)  # above small_max_entries: the medium single-graph path
+    bad_id_small = small.colidx.copy()
+    bad_id_small[len(bad_id_small) // 2] = small.n + 5
+    bad_id_big = big.colidx.copy()
+    bad_id_big[-1] = 0xFFFFFFF0
+    bad_rp = small.rowptr.copy()
+    bad_rp[3] = bad_rp[4] + 1  # rowptr decreases from row 3 to row 4; both ends unchanged
+    shifted = small.rowptr.copy() + 1  # rowptr[0] != 0
+    say("[serve] malformed requests beside valid ones")
+    with tc_lib.Server(small_max_entries=20000, large_min_entries=1 << 30) as srv:
+        with pytest.raises(tc_lib.TCError) as ei:
+            srv.submit(shifted, small.colidx)
+        assert ei.value.status == -4
+        with pytest.raises(tc_lib.TCError) as ei:
+            srv.submit(small.rowptr, small.colidx[:-2])  # rowptr[n] != m
+        assert ei.value.status == -4
+        tickets = {}
+        for i, g in enumerate(good):
+            tickets[srv.submit(g.rowptr, g.colidx)] = ("good", i)
+        tickets[srv.submit(small.rowptr, bad_id_small)] = ("bad", "id_small")
+        tickets[srv.submit(bad_rp, small.colidx)] = ("bad", "rowptr_small")
+        tickets[srv.submit(big.rowptr, bad_id_big)] = ("bad", "id_big")
+        for i, g in enumerate(good):
+            tickets[srv.submit(g.rowptr, g.colidx)] = ("good", i)
+        res = drain(srv, len(tickets))
+        st = srv.stats()
+    for r in res:
+        kind, i = tickets[r.ticket]
+        if kind == "good":
+            assert r.status == 0 and r.triangles == ref[i], (i, r)
+        else:
+            assert r.status == -4 and r.triangles == 0, (i, r)
+    assert st["in_flight"] == 0 and st["hbm_in_use"] == 0
+
+
+def test_serve_pool_large_requests_match_oracle(tc_lib):
+    """The serving stream's scale-22..24 R-MAT requests (and its scale-12..18 pool), all
+    submitted together through the default paths: every result equals the oracle's
+    stored count (tests/golden/serve_pool_counts.json)."""
+    import json
+    import os
+
+    from tests import workloads as wl
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "serve_pool_counts.json")))
+    specs = wl.serve_pool_specs(huge_scale=0)
+    graphs = {}
+    for (sc, k), seed in sorted(specs.items()):
+        if sc >= 22:
+            say(f"[serve] generating R-MAT scale {sc}")
+        graphs[(sc, k)] = (wl.serve_graph(sc, seed), seed)
+    say(f"[serve] submitting {len(graphs)} pool graphs")
+    with tc_lib.Server() as srv:
+        tickets = {}
+        for key, (g, seed) in graphs.items():
+            tickets[srv.submit(g.rowptr, g.colidx)] = key
+        res = drain(srv, len(tickets), deadline_s=300.0)
+    paths = set()
+    for r in res:
+        sc, k = tickets[r.ticket]
+        g, seed = graphs[(sc, k)]
+        want = gold[wl.rmat_key(sc, wl.SERVE_EDGE_FACTOR, seed)]
+        assert r.status == 0 and r.input_edges == want["input_edges"]
+        assert r.triangles == want["triangles"], (sc, k)
+        paths.add(r.path)
+    assert paths == {0, 1, 3}
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("TC_TEST_HUGE"),
+                    reason="the scale-26 request takes minutes to generate; set TC_TEST_HUGE=1")
+def test_serve_huge_request_matches_oracle(tc_lib):
+    """The serving stream's scale-26 R-MAT request (about 2.1e9 stored entries) against the
+    oracle's stored count, through the server's large path."""
+    import json
+    import os
+
+    from tests import workloads as wl
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "serve_pool_counts.json")))
+    sc = wl.SERVE_HUGE_SCALE
+    seed = wl.serve_pool_specs()[(sc, 0)]
+    want = gold[wl.rmat_key(sc, wl.SERVE_EDGE_FACTOR, seed)]
+    say(f"[serve] generating R-MAT scale {sc}")
+    g = wl.serve_graph(sc, seed)
+    assert g.num_edges == want["input_edges"]
+    say("[serve] counting it through the large path")
+    with tc_lib.Server() as srv:
+        t = srv.submit(g.rowptr, g.colidx)
+        (r,) = drain(srv, 1, deadline_s=600.0)
+    assert r.ticket == t and r.status == 0 and r.path == 3
+    assert r.triangles == want["triangles"]
