@@ -3,27 +3,38 @@
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
 
-One step is one whole tc_count call on a graph already resident in HBM: component
-roots, level BFS, cover-edge extraction, intersections and reduction, including the
-call's own workspace allocation (the paper charges auxiliary arrays to the algorithm).
-The timed region brackets exactly K steps with device synchronisations.  value =
-input edges (undirected, after cleaning) x K / elapsed seconds.
+Default workload: batch4096, the headline configuration (input edges/s, batched vs
+per-graph launch).  One step is one replay of a captured tc_count_batch over 4096
+uneven graphs already resident in HBM (component roots, level BFS, cover-edge
+extraction, intersections and the per-graph totals, all inside one persistent kernel);
+the timed region brackets exactly K replays with device synchronisations, and value =
+input edges of the whole batch (undirected, after cleaning) x K / elapsed seconds.
+The same graphs then go through one tc_count call each (on one stream, and spread over
+four host threads with a stream each): per_graph_launch and batched_over_per_graph.
+Every batched count must equal its per-graph count.
 
 Alongside, per JSON line:
-  roofline     : the dominant intersection kernel's algorithmic bytes per launch over its
-                 average launch time, from HIP events recorded by the library on the
-                 kernel's own stream in --profile-steps step-timed calls after the timed
-                 steps (there the intersection classes run one after another), against
-                 8 TB/s HBM; traffic is the counter-measured HBM bytes per launch stored
-                 under profiles/ when the kernel sources and the class and hub settings
-                 still match, else null.
-  cpu_baseline : the CPU oracle (CETC-SM, OpenMP) timed on this host on a bounded
-                 sample of the same graph, extrapolated in the oracle's merge work.
+  roofline     : the batched kernel's algorithmic bytes per launch (per member: the BFS,
+                 extraction and intersection bytes of the measurement plan, the last the
+                 short list of every cover edge plus every list touched by a cover edge
+                 once; summed over the 4096 members) over its average launch time, from
+                 HIP events recorded on the stream the replays run on, against 8 TB/s
+                 HBM.  traffic is the counter-measured HBM bytes per launch stored under
+                 profiles/ for the current kernel sources, else null.
+  cpu_baseline : the CPU oracle timed on this host on a bounded sample of the batch's
+                 members (single-thread CETC-Seq and CETC-SM on every host thread,
+                 several runs each, mean and median).
+  single_graph : the same figures for one tc_count call on R-MAT scale 22 (the
+                 single-graph configuration), unless --no-single-graph.
 
-Workloads: rmat22 (default; R-MAT scale 22), rmat10, grid4096, er22, batch4096
-(4096 uneven graphs: one captured tc_count_batch launch against 4096 tc_count calls),
-and serve (a Poisson stream of requests through the tc_serve_* server: p50/p99 latency
-and input edges/s, every result checked against the standalone count).
+Single-graph workloads (--workload rmat22 | rmat10 | grid4096 | er22): one step is one
+whole tc_count call on a graph already resident in HBM (including the call's own
+workspace allocation: the paper charges auxiliary arrays to the algorithm).  Their
+roofline is the dominant intersection kernel's bytes over its launch time from step-timed
+calls; frac is taken on the measurement plan's intersection bytes for that kernel's
+cover edges, with the bytes the pruned kernel streams beside it.  serve: a Poisson
+stream of requests through the tc_serve_* server (p50/p99 latency and input edges/s,
+every result checked against the oracle's stored count).
 
 --autotune picks the intersection thresholds (tc_set_isect_params) and, for a single
 graph, the hub count (tc_set_hub_params) on the workload itself before the warm-up, by
@@ -35,7 +46,7 @@ Counter helpers (no bench line):
                         known-size kernel that FETCH_SIZE / WRITE_SIZE are scaled by;
   --traffic-summary     reads the four rocprofv3 --pmc CSVs (bench FETCH_SIZE and
                         WRITE_SIZE passes, copy FETCH_SIZE and WRITE_SIZE passes) and
-                        stores the per-launch HBM bytes of each intersection kernel in
+                        stores the per-launch HBM bytes of each counting kernel in
                         profiles/traffic.json under the current kernel source hash.
 """
 from __future__ import annotations
@@ -174,7 +185,13 @@ def class_bytes(g, level: np.ndarray, params, hubs=(0, 0)) -> dict:
             same_x = cs[rp[xs + 1]] - cs[rp[xs]]
             above = cs[rp[xs + 1]] - cs[np.searchsorted(key, xs * (1 << 32) + xs, side="right")]
             staged = int((d[xs] - same_x + above).sum())
-        out[name] = {"cover_edges": int(sel.sum()), "bytes": 4 * (streamed + staged)}
+        # the measurement plan's intersection bytes for these cover edges: the shorter
+        # list of each once, every list they touch once
+        xe, ye = x[sel], y[sel]
+        touched = np.unique(np.concatenate([xe, ye]))
+        b_int = 4 * int(np.minimum(d[xe], d[ye]).sum()) + 4 * int(d[touched].sum())
+        out[name] = {"cover_edges": int(sel.sum()), "bytes": 4 * (streamed + staged),
+                     "plan_bytes": b_int}
     nh = int(hub.sum())
     hb = 0
     if nh:
@@ -186,8 +203,41 @@ def class_bytes(g, level: np.ndarray, params, hubs=(0, 0)) -> dict:
         ys = np.unique(y[hx])
         hb = int((4 + 4 * nw) * nprime[ys].sum() + 4 * nw * len(ys)
                  + 4 * nprime[hub].sum() + 4 * nw * g.n)
-    out["isect_hub"] = {"cover_edges": int(hx.sum()), "bytes": hb}
+    xe, ye = x[hx], y[hx]
+    touched = np.unique(np.concatenate([xe, ye]))
+    out["isect_hub"] = {"cover_edges": int(hx.sum()), "bytes": hb,
+                        "plan_bytes": 4 * int(np.minimum(d[xe], d[ye]).sum())
+                        + 4 * int(d[touched].sum())}
     return out
+
+
+def plan_bytes(rowptr: np.ndarray, colidx: np.ndarray, level: np.ndarray) -> dict:
+    """Algorithmic bytes of the counting path on one graph, or on a disjoint union of
+    graphs with global IDs (each term is a sum over vertices or edges): the BFS reads the
+    CSR once and writes the levels, 4 (n + 1) + 4 nnz + 4 n; the extraction reads the CSR
+    once and writes the cover edges, 4 (n + 1) + 4 nnz + 8 |S|; the intersections read
+    the shorter list of every cover edge once and every list that a cover edge touches
+    once, B_int = 4 sum_S min(d_u, d_v) + 4 sum_{x in V(S)} d_x (B_merge = 4 sum_S
+    (d_u + d_v), the two-pointer merge, beside it); the output is 8 bytes per graph
+    (added by the caller)."""
+    n = int(rowptr.shape[0]) - 1
+    d = np.diff(rowptr.astype(np.int64))
+    rows = np.repeat(np.arange(n, dtype=np.int64), d)
+    cols = colidx.astype(np.int64)
+    lv = level.astype(np.int64)
+    h = (rows < cols) & (lv[rows] == lv[cols])
+    u, v = rows[h], cols[h]
+    del rows, cols, h
+    touched = np.zeros(n, dtype=bool)
+    touched[u] = True
+    touched[v] = True
+    nnz = int(colidx.shape[0])
+    S = int(u.shape[0])
+    short = int(np.minimum(d[u], d[v]).sum())
+    merge = int((d[u] + d[v]).sum())
+    return {"cover_edges": S, "bfs": 4 * (n + 1) + 4 * nnz + 4 * n,
+            "extract": 4 * (n + 1) + 4 * nnz + 8 * S,
+            "intersect": 4 * short + 4 * int(d[touched].sum()), "merge": 4 * merge}
 
 
 def stored_traffic(workload: str, kernel: str, settings: dict):
@@ -312,13 +362,21 @@ def bench_single(args, tcm, torch):
     isect = {k: steps_ms.get(k, 0.0) for k in KERNEL_OF_STEP}
     dom = max(isect, key=isect.get)
     dom_ms = isect[dom]
-    achieved = cb[dom]["bytes"] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    achieved = cb[dom]["plan_bytes"] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    streamed = cb[dom]["bytes"] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    traffic = stored_traffic(args.workload, KERNEL_OF_STEP[dom], current_settings(tcm))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(args.workload, KERNEL_OF_STEP[dom], current_settings(tcm)),
+                "traffic": traffic,
                 "kernel": KERNEL_OF_STEP[dom], "avg_launch_ms": round(dom_ms, 4),
                 "timed_in": f"{calls} step-timed calls (intersection classes one after another)",
-                "algorithmic_bytes_per_launch": cb[dom]["bytes"]}
+                "algorithmic_bytes_per_launch": cb[dom]["plan_bytes"],
+                "algorithmic_bytes": "shorter list of each of the kernel's cover edges once "
+                                     "plus every list they touch once",
+                "pruned_bytes_per_launch": cb[dom]["bytes"],
+                "pruned_gbs": round(streamed, 1),
+                "traffic_gbs": (round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+                                if traffic and dom_ms > 0 else None)}
     out = {
         "metric": METRIC,
         "value": g.num_edges * args.steps / elapsed,
@@ -342,24 +400,159 @@ def bench_single(args, tcm, torch):
                    "autotuned": tuned is not None},
         "triangles_per_s": T * args.steps / elapsed,
         "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
-        "isect_classes": {k: {"cover_edges": v["cover_edges"],
-                              "algorithmic_bytes": v["bytes"]} for k, v in cb.items()},
+        "isect_classes": {k: {"cover_edges": v["cover_edges"], "pruned_bytes": v["bytes"],
+                              "plan_bytes": v["plan_bytes"],
+                              "ms": round(isect.get(k, 0.0), 4)} for k, v in cb.items()},
         "roofline": roofline,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    isect_ms = sum(isect.values())
+    out["isect_classes"]["isect_all"] = {
+        "plan_bytes": sum(v["plan_bytes"] for v in cb.values()),
+        "ms": round(isect_ms, 4)}
     return out
 
 
 # ---- batched workload ------------------------------------------------------------------------
 
+def batch_levels(tcm, dev):
+    """Levels of every member, from one tc_count_ex call per member (the levels are
+    checked against the oracle's BFS in the parity tests)."""
+    out = []
+    for r, c in dev:
+        if c.numel() == 0:
+            out.append(np.zeros(r.numel() - 1, dtype=np.uint32))
+            continue
+        _, lv = tcm.tc_count_ex(r, c, want_levels=True)
+        out.append(lv.cpu().numpy().view(np.uint32))
+    return out
+
+
+def batch_plan_bytes(b, levels, chunk_entries: int = 1 << 27) -> dict:
+    """plan_bytes summed over the members, computed over groups of members joined into
+    one disjoint union with global IDs."""
+    tot = {"cover_edges": 0, "bfs": 0, "extract": 0, "intersect": 0, "merge": 0,
+           "output": 8 * b.num_graphs}
+    g0 = 0
+    while g0 < b.num_graphs:
+        g1, ent = g0, 0
+        while g1 < b.num_graphs and (g1 == g0 or ent + int(b.col_off[g1 + 1] - b.col_off[g1])
+                                      <= chunk_entries):
+            ent += int(b.col_off[g1 + 1] - b.col_off[g1])
+            g1 += 1
+        degs, cols, lvs, base = [], [], [], 0
+        for i in range(g0, g1):
+            gi = b.graph(i)
+            degs.append(np.diff(gi.rowptr.astype(np.int64)))
+            cols.append(gi.colidx.astype(np.int64) + base)
+            lvs.append(levels[i])
+            base += gi.n
+        d = np.concatenate(degs)
+        rp = np.zeros(d.shape[0] + 1, dtype=np.int64)
+        np.cumsum(d, out=rp[1:])
+        r = plan_bytes(rp, np.concatenate(cols), np.concatenate(lvs))
+        # each member has its own n_g + 1 rowptr entries, read by both steps
+        r["bfs"] += 4 * (g1 - g0 - 1)
+        r["extract"] += 4 * (g1 - g0 - 1)
+        for k, v in r.items():
+            tot[k] += v
+        g0 = g1
+    tot["total"] = tot["bfs"] + tot["extract"] + tot["intersect"] + tot["output"]
+    return tot
+
+
+def cpu_baseline_batch(b, target_s: float, reps: int = 3):
+    """The oracle on a bounded sample of the batch's members, as it stands: CETC-Seq on
+    one thread (BFS restart loop and edge loop) and the BFS restart loop plus CETC-SM on
+    every host thread, `reps` runs of each over the same sample; the members are taken
+    every k-th in order of size, k sized from a calibration run so that all runs together
+    take about target_s."""
+    import oracle
+
+    threads = oracle.max_threads()
+    ent = np.diff(b.col_off)
+    by_size = np.argsort(ent, kind="stable")
+
+    def run_single(ids):
+        t = time.perf_counter()
+        for i in ids:
+            oracle.cetc_seq(b.graph(int(i)))
+        return time.perf_counter() - t
+
+    def run_omp(ids):
+        t = time.perf_counter()
+        for i in ids:
+            g = b.graph(int(i))
+            lv, _ = oracle.bfs_levels(g)
+            oracle.cetc_sm(g, lv)
+        return time.perf_counter() - t
+
+    cal = by_size[::256]
+    t_cal = run_single(cal) + run_omp(cal)
+    per_edge = t_cal / max(int(ent[cal].sum()) // 2, 1)
+    want_edges = target_s / (reps * max(per_edge, 1e-12))
+    k = max(1, int(np.ceil(b.total_edges / max(want_edges, 1.0))))
+    sample = by_size[k // 2::k]
+    edges = int(ent[sample].sum()) // 2
+    ts = [run_single(sample) for _ in range(reps)]
+    to = [run_omp(sample) for _ in range(reps)]
+    rate = lambda t: edges / t  # noqa: E731
+    return {
+        "value": edges / float(np.median(to)),
+        "unit": "input edges/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{len(sample)} of {b.num_graphs} members (every {k}th by size, "
+                   f"{edges} input edges = {100.0 * edges / b.total_edges:.2f}% of the batch); "
+                   f"{reps} runs each of the BFS restart loop + CETC-SM edge loop on "
+                   f"{threads} threads (value: median) and of CETC-Seq on one thread"),
+        "omp_threads": threads,
+        "omp_edges_per_s_median": rate(float(np.median(to))),
+        "omp_edges_per_s_mean": edges * reps / float(np.sum(to)),
+        "single_thread_edges_per_s_median": rate(float(np.median(ts))),
+        "single_thread_edges_per_s_mean": edges * reps / float(np.sum(ts)),
+        "runs_s": {"omp": [round(t, 3) for t in to], "single_thread": [round(t, 3) for t in ts]},
+    }
+
+
+def per_graph_streams(tcm, torch, dev, nstreams: int):
+    """All members through tc_count, spread round-robin over nstreams host threads, each
+    with its own stream (tc_count blocks its caller until its stream is done)."""
+    import threading
+
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    out = np.zeros(len(dev), dtype=np.uint64)
+    errors = []
+
+    def work(k):
+        try:
+            for i in range(k, len(dev), nstreams):
+                out[i] = tcm.tc_count(dev[i][0], dev[i][1], stream=streams[k])
+        except Exception as e:  # noqa: BLE001
+            errors.append(e)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=work, args=(k,)) for k in range(nstreams)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    return out, elapsed
+
+
 def bench_batch(args, tcm, torch):
-    import graphgen as gg
+    from tests import workloads as wl
 
     t = time.perf_counter()
-    b = gg.make_batch(4096, gg.config_seed(3))
+    b = wl.batch4096()
     log(f"[bench] generated batch: {b.num_graphs} graphs, {b.total_edges} input edges "
         f"({time.perf_counter() - t:.1f}s)")
     rp, ci = tcm.to_device(b.rowptr_cat, b.colidx_cat)
@@ -387,13 +580,20 @@ def bench_batch(args, tcm, torch):
     with torch.cuda.graph(graph):
         tcm.tc_count_batch(rp, ci, ro, co, total_rows=rows, workspace=ws, counts=counts)
     torch.cuda.synchronize()
+    # the replays run on the current stream: events recorded there bracket each launch
+    cur = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record(cur)
+    for i in range(args.steps):
         graph.replay()
+        ev[i + 1].record(cur)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
+    launch_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
     batched = tcm.as_u64(counts).copy()
-    log(f"[bench] batched: {t_batch * 1e3:.3f} ms per batch")
+    log(f"[bench] batched: {t_batch * 1e3:.3f} ms per batch (events: "
+        f"{np.mean(launch_ms):.3f} ms per launch)")
 
     # the same graphs through one tc_count call each
     dev = []
@@ -405,9 +605,30 @@ def bench_batch(args, tcm, torch):
     single = np.array([tcm.tc_count(r, c) for r, c in dev], dtype=np.uint64)
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
-    log(f"[bench] per-graph: {t_single * 1e3:.3f} ms for {b.num_graphs} calls")
+    log(f"[bench] per-graph: {t_single * 1e3:.3f} ms for {b.num_graphs} calls on one stream")
     assert np.array_equal(single, batched), "batched and per-graph counts differ"
-    return {
+    single4, t_single4 = per_graph_streams(tcm, torch, dev, 4)
+    log(f"[bench] per-graph: {t_single4 * 1e3:.3f} ms for {b.num_graphs} calls on 4 streams")
+    assert np.array_equal(single4, batched), "batched and per-graph counts differ (4 streams)"
+
+    levels = batch_levels(tcm, dev)
+    del dev
+    pb = batch_plan_bytes(b, levels)
+    del levels
+    kern_ms = float(np.mean(launch_ms))
+    achieved = pb["total"] / (kern_ms * 1e-3) / 1e9
+    traffic = stored_traffic("batch4096", "k_batch_main<true>", current_settings(tcm))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_batch_main<true>", "avg_launch_ms": round(kern_ms, 4),
+                "timed_in": f"HIP events around {args.steps} graph replays on their stream "
+                            "(the replay also holds two kernels of a few microseconds)",
+                "algorithmic_bytes_per_launch": pb["total"],
+                "algorithmic_bytes": {k: pb[k] for k in ("bfs", "extract", "intersect", "output")},
+                "intersect_frac": round(pb["intersect"] / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "merge_bytes_per_launch": pb["merge"],
+                "traffic_gbs": (round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None)}
+    out = {
         "metric": METRIC,
         "value": b.total_edges / t_batch,
         "unit": "input edges/s",
@@ -422,15 +643,25 @@ def bench_batch(args, tcm, torch):
         "data": "synthetic",
         "config": {"workload": "batch4096", "graph": WORKLOAD_TEXT["batch4096"],
                    "num_graphs": b.num_graphs, "input_edges": b.total_edges,
-                   "triangles": int(batched.sum()),
+                   "triangles": int(batched.sum()), "cover_edges": pb["cover_edges"],
                    "isect_params": list(tcm.tc_get_isect_params()),
-                   "autotuned": tuned is not None},
+                   "autotuned": tuned is not None, "launch": "hipGraph replay"},
+        "triangles_per_s": float(batched.sum()) / t_batch,
         "per_graph_launch": {"value": b.total_edges / t_single, "unit": "input edges/s",
-                             "ms_total": t_single * 1e3},
+                             "ms_total": round(t_single * 1e3, 3), "streams": 1,
+                             "four_streams": {"value": b.total_edges / t_single4,
+                                              "ms_total": round(t_single4 * 1e3, 3)}},
         "batched_over_per_graph": t_single / t_batch,
-        "roofline": None,
+        "batched_over_per_graph_four_streams": t_single4 / t_batch,
+        "launch_ms": {"mean": round(kern_ms, 4), "median": round(float(np.median(launch_ms)), 4),
+                      "min": round(float(np.min(launch_ms)), 4)},
+        "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a sample of the members ...")
+        out["cpu_baseline"] = cpu_baseline_batch(b, args.cpu_seconds)
+    return out
 
 
 # ---- continuous-batching server ----------------------------------------------------------
@@ -439,20 +670,23 @@ def bench_serve(args, tcm, torch):
     """Requests arrive as a Poisson stream whose offered load is --serve-load (default
     0.8) times the capacity of one-at-a-time standalone processing (pinned upload +
     tc_count); each result is checked against the standalone count of the same graph."""
-    import graphgen as gg
+    from tests import workloads as wl
 
-    base = gg.config_seed(5)
-    rng = np.random.default_rng(base)
-    small_scales = list(range(12, 19))
-    large_scales = [22, 23, 24]
+    rng = np.random.default_rng(wl.SERVE_BASE_SEED)
+    small_scales = list(wl.SERVE_SMALL_SCALES)
+    large_scales = list(wl.SERVE_LARGE_SCALES)
+    specs = wl.serve_pool_specs(args.serve_huge_scale)
     pool = {}
     t = time.perf_counter()
-    for sc in small_scales:
-        for k in range(3):
-            pool[(sc, k)] = gg.rmat(sc, 16, base + 100 * sc + k)
-    for sc in large_scales + ([args.serve_huge_scale] if args.serve_huge_scale else []):
-        pool[(sc, 0)] = gg.rmat(sc, 16, base + 100 * sc)
-        log(f"[bench] generated R-MAT scale {sc} ({time.perf_counter() - t:.1f}s)")
+    for key, seed in specs.items():
+        pool[key] = wl.serve_graph(key[0], seed)
+        if key[0] >= 22:
+            log(f"[bench] generated R-MAT scale {key[0]} ({time.perf_counter() - t:.1f}s)")
+    # the oracle's counts of the pool, stored by tests/golden/make_full_counts.py
+    gold_path = os.path.join(ROOT, "tests", "golden", "serve_pool_counts.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else {}
+    oracle_T = {key: gold.get(wl.rmat_key(key[0], wl.SERVE_EDGE_FACTOR, seed), {}).get("triangles")
+                for key, seed in specs.items()}
     # Host CSRs in pinned memory (where a front end would receive them), standalone
     # results, and standalone service times (upload + count).
     host, ref, svc = {}, {}, {}
@@ -508,6 +742,12 @@ def bench_serve(args, tcm, torch):
     srv.close()
     bad = [r for r in results if r.status != 0 or r.triangles != ref[tickets[r.ticket]]]
     assert not bad, f"{len(bad)} server results differ from the standalone counts"
+    unchecked = sorted({tickets[r.ticket] for r in results if oracle_T[tickets[r.ticket]] is None})
+    wrong = [r for r in results
+             if oracle_T[tickets[r.ticket]] is not None
+             and r.triangles != oracle_T[tickets[r.ticket]]]
+    assert not wrong, f"{len(wrong)} server results differ from the oracle's stored counts"
+    assert all(ref[k] == oracle_T[k] for k in ref if oracle_T[k] is not None)
     lat = np.array([r.latency_s for r in results])
     first = min(r.submit_s for r in results)
     last = max(r.done_s for r in results)
@@ -560,6 +800,9 @@ def bench_serve(args, tcm, torch):
         "input_edges": int(edges),
         "paths": paths,
         "server": {k: st[k] for k in ("batches", "singles", "hbm_peak", "hbm_budget")},
+        "oracle_checked": {"requests": sum(oracle_T[tickets[r.ticket]] is not None
+                                           for r in results),
+                           "pool_graphs_without_stored_count": [list(k) for k in unchecked]},
         "large_path": large_path,
         "roofline": None,
         "cpu_baseline": None,
@@ -627,9 +870,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="batch4096", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-single-graph", action="store_true",
+                    help="batch4096: leave out the nested R-MAT scale 22 single-graph figures")
+    ap.add_argument("--single-cpu-seconds", type=float, default=8.0,
+                    help="CPU-oracle budget of the nested single-graph figures")
     ap.add_argument("--isect", default="", metavar="LANE,WAVE,CHUNK,SEG",
                     help="intersection class parameters (tc_set_isect_params) for this run")
     ap.add_argument("--profile-steps", type=int, default=3,
@@ -638,7 +885,7 @@ def main():
                     help="hub pass parameters (tc_set_hub_params) for this run; 0,0 turns it off")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the intersection class parameters on the workload first")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-huge-scale", type=int, default=26)
     ap.add_argument("--serve-small-max", type=int, default=1 << 18)
     ap.add_argument("--serve-load", type=float, default=0.8)
@@ -682,6 +929,15 @@ def main():
         tcm.tc_set_hub_params(*[int(v) for v in args.hubs.split(",")])
     if args.workload == "batch4096":
         out = bench_batch(args, tcm, torch)
+        torch.cuda.empty_cache()
+        if not args.no_single_graph:
+            sub = argparse.Namespace(**vars(args))
+            sub.workload = "rmat22"
+            sub.cpu_seconds = args.single_cpu_seconds
+            one = bench_single(sub, tcm, torch)
+            out["single_graph"] = {k: one[k] for k in (
+                "value", "unit", "ms_per_step", "steps", "config", "triangles_per_s",
+                "steps_ms", "isect_classes", "roofline", "cpu_baseline")}
     elif args.workload == "serve":
         out = bench_serve(args, tcm, torch)
     else:

@@ -38,9 +38,10 @@ def brute_class_bytes(g, level, lane_max, wave_max, hubs=frozenset()):
     d = np.diff(g.rowptr.astype(np.int64))
     cls = bench.degree_class(d)
     par = [int(level[v]) & 1 for v in range(n)]
-    out = {k: {"cover_edges": 0, "bytes": 0}
+    out = {k: {"cover_edges": 0, "bytes": 0, "plan_bytes": 0}
            for k in ("isect_lane", "isect_wave", "isect_block", "isect_hub")}
     staged = {k: set() for k in out}
+    touched = {k: set() for k in out}  # vertices of the class's cover edges
     hub_partners = set()
 
     def pruned(v):
@@ -55,11 +56,15 @@ def brute_class_bytes(g, level, lane_max, wave_max, hubs=frozenset()):
                     x, y = v, u
                 if x in hubs:
                     out["isect_hub"]["cover_edges"] += 1
+                    out["isect_hub"]["plan_bytes"] += 4 * min(d[x], d[y])
+                    touched["isect_hub"] |= {x, y}
                     hub_partners.add(y)
                     continue
                 name = ("isect_lane" if d[x] <= lane_max else
                         "isect_wave" if d[x] <= wave_max else "isect_block")
                 out[name]["cover_edges"] += 1
+                out[name]["plan_bytes"] += 4 * min(d[x], d[y])
+                touched[name] |= {x, y}
                 if name == "isect_lane":
                     streamed = len(rows[y])
                 else:
@@ -72,6 +77,8 @@ def brute_class_bytes(g, level, lane_max, wave_max, hubs=frozenset()):
                 out[name]["bytes"] += 4 * len(rows[x])
             else:
                 out[name]["bytes"] += 4 * pruned(x)
+    for name, vs in touched.items():
+        out[name]["plan_bytes"] += sum(4 * int(d[v]) for v in vs)
     if hubs:
         nw = 4 if len(hubs) <= 128 else 8
         out["isect_hub"]["bytes"] = (sum((4 + 4 * nw) * pruned(y) + 4 * nw for y in hub_partners)
@@ -126,3 +133,48 @@ def test_gpu_hub_cases_reach_the_hub_pass():
     for g in (gg.rmat(14, 32, 14), gg.rmat(16, 16, 16)):
         for hubs in [(1, 1), (7, 1), (128, 1), (129, 1), (256, 1), (200, 64)]:
             assert bench.hub_set(g.degrees(), *hubs).sum() > 0, (g.name, hubs)
+
+
+def brute_plan_bytes(g, level):
+    """The measurement plan's bytes written out per edge: BFS 4 (n + 1) + 4 nnz + 4 n,
+    extraction 4 (n + 1) + 4 nnz + 8 |S|, intersections 4 min(d_u, d_v) per cover edge
+    plus 4 d_x once for every vertex of a cover edge, merge 4 (d_u + d_v) per cover edge."""
+    n = g.n
+    d = [int(g.rowptr[v + 1] - g.rowptr[v]) for v in range(n)]
+    S, short, merge, touched = 0, 0, 0, set()
+    for u in range(n):
+        for v in g.colidx[g.rowptr[u]:g.rowptr[u + 1]].tolist():
+            if u < v and level[u] == level[v]:
+                S += 1
+                short += min(d[u], d[v])
+                merge += d[u] + d[v]
+                touched |= {u, v}
+    return {"cover_edges": S, "bfs": 4 * (n + 1) + 4 * g.nnz + 4 * n,
+            "extract": 4 * (n + 1) + 4 * g.nnz + 8 * S,
+            "intersect": 4 * short + 4 * sum(d[x] for x in touched), "merge": 4 * merge}
+
+
+@pytest.mark.parametrize("graph", [lambda: gg.rmat(9, 8, seed=7), lambda: gg.complete(12),
+                                   lambda: gg.tri_grid(9, 13, 0.05, 3), lambda: gg.empty_graph(5)])
+def test_plan_bytes_match_definition(graph):
+    g = graph()
+    level, _ = oracle.bfs_levels(g)
+    got = bench.plan_bytes(g.rowptr, g.colidx, np.asarray(level, dtype=np.uint32))
+    assert got == brute_plan_bytes(g, level)
+
+
+def test_batch_plan_bytes_sum_over_members():
+    """Members joined into groups (several groups: a tiny group size) give the sum of the
+    members' own plan bytes, with 8 output bytes per member."""
+    graphs = [gg.rmat(7, 8, seed=1), gg.complete(9), gg.empty_graph(3), gg.tri_grid(6, 7),
+              gg.erdos_renyi(300, 6, 2)]
+    b = gg.pack(graphs)
+    levels = [np.asarray(oracle.bfs_levels(g)[0], dtype=np.uint32) for g in graphs]
+    got = bench.batch_plan_bytes(b, levels, chunk_entries=600)
+    want = {"cover_edges": 0, "bfs": 0, "extract": 0, "intersect": 0, "merge": 0}
+    for g, lv in zip(graphs, levels):
+        for k, v in brute_plan_bytes(g, lv).items():
+            want[k] += v
+    want["output"] = 8 * len(graphs)
+    want["total"] = want["bfs"] + want["extract"] + want["intersect"] + want["output"]
+    assert got == want

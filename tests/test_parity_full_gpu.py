@@ -4,8 +4,9 @@ For R-MAT scale 22, the triangulated 4096 x 4096 grid with 1% deletions, Erd≈ës‚
 2^22 and R-MAT scale 10, the GPU's T, c1, c2 and |S| must equal the oracle's stored
 results (tests/golden/full_size_counts.json, written by make_full_counts.py from the
 oracle alone), and the GPU's BFS level of every vertex must equal the oracle's BFS run
-here on the host.  For the 4096-graph batch, a seeded sample of members is checked one
-by one against the oracle and every member against tc_count.
+here on the host.  For the 4096-graph batch, every member's count, from the batched
+launch and from its own tc_count call, must equal the oracle's stored count
+(tests/golden/batch4096_counts.json).
 """
 import json
 import os
@@ -15,9 +16,8 @@ import numpy as np
 import pytest
 import torch
 
-import graphgen as gg
 import oracle
-from tests.workloads import WORKLOADS
+from tests.workloads import BATCH_BASE_SEED, WORKLOADS, batch4096
 
 pytestmark = pytest.mark.gpu
 
@@ -50,9 +50,13 @@ def test_full_size_matches_oracle(tc_lib, name):
     assert tc_lib.tc_count(rp, ci) == ref["triangles"]
 
 
-def test_batch4096_sampled_members(tc_lib):
+def test_batch4096_every_member(tc_lib):
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "batch4096_counts.json")))
     say("[full] generating the 4096-graph batch")
-    b = gg.make_batch(4096, gg.config_seed(3))
+    b = batch4096()
+    assert b.num_graphs == ref["num_graphs"] and ref["base_seed"] == BATCH_BASE_SEED
+    assert [g.num_edges for g in (b.graph(i) for i in range(b.num_graphs))] == ref["input_edges"]
     rp, ci = tc_lib.to_device(b.rowptr_cat, b.colidx_cat)
     ro = torch.from_numpy(b.row_off).cuda()
     co = torch.from_numpy(b.col_off).cuda()
@@ -62,13 +66,11 @@ def test_batch4096_sampled_members(tc_lib):
                      dtype=torch.uint8, device="cuda")
     say("[full] tc_count_batch 4096 graphs")
     counts = tc_lib.as_u64(tc_lib.tc_count_batch(rp, ci, ro, co, total_rows=rows, workspace=ws))
-    rng = np.random.default_rng(4096)
-    sample = sorted(set(rng.choice(b.num_graphs, 48, replace=False).tolist()) |
-                    {int(np.argmax(np.diff(b.col_off)))})  # plus the largest member
-    for i in sample:
-        assert int(counts[i]) == oracle.count(b.graph(i)), f"member {i}"
-    say("[full] every member against tc_count")
+    want = np.array(ref["triangles"], dtype=np.uint64)
+    bad = np.flatnonzero(counts != want)
+    assert bad.size == 0, f"{bad.size} members differ from the oracle, first {bad[:8].tolist()}"
+    say("[full] every member through tc_count against the oracle")
     for i in range(b.num_graphs):
         gi = b.graph(i)
         r1, c1 = tc_lib.to_device(gi.rowptr, gi.colidx)
-        assert tc_lib.tc_count(r1, c1) == int(counts[i]), f"member {i}"
+        assert tc_lib.tc_count(r1, c1) == int(want[i]), f"member {i}"
