@@ -160,6 +160,28 @@ size_t tc_count_batch_workspace_size(uint32_t num_graphs, uint64_t total_rows,
                                      uint64_t total_cols);
 
 /*
+ * tc_count_batch_noalloc — tc_count_batch for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid allocation, harnesses
+ * that disallow hipMalloc).  Same arguments, meaning and results as tc_count_batch with
+ * a caller workspace, but the workspace is a fixed array inside the library of
+ * TC_NOALLOC_SCRATCH_BYTES bytes per device, held by every GPU the library runs on until
+ * the process ends.  The call allocates nothing, issues no memset, never synchronises
+ * and reads no device data on the host.  Its first call on a device looks up that
+ * device's copy of the array (hipGetSymbolAddress).
+ * All calls on one device share the array, which keeps the last call's contents: calls
+ * that overlap in time on one device race and must be serialised by the caller (for
+ * example by issuing them on one stream).  A batch whose
+ * tc_count_batch_workspace_size(num_graphs, total_rows, total_cols) exceeds
+ * TC_NOALLOC_SCRATCH_BYTES is refused with TC_ERR_TOO_LARGE before any launch.
+ * Errors as tc_count_batch (TC_ERR_HIP also when the array's address cannot be found).
+ */
+#define TC_NOALLOC_SCRATCH_BYTES (64u << 20) /* 64 MiB per device */
+int tc_count_batch_noalloc(const uint32_t* rowptr_cat, const uint32_t* colidx_cat,
+                           const int64_t* row_off, const int64_t* col_off,
+                           uint32_t num_graphs, uint64_t total_rows, uint64_t total_cols,
+                           hipStream_t stream, uint64_t* counts);
+
+/*
  * ---- continuous-batching server ----------------------------------------------------
  * A server counts a stream of independent graphs handed over as HOST CSR arrays (same
  * format as above).  It admits a request when the request's device footprint (its CSR

@@ -9,6 +9,7 @@ C ABI of ``include/tc.h``; :mod:`.tc` is the Python binding with the same names,
 """
 from .tc import (  # noqa: F401
     EXPORTS,
+    NOALLOC_SCRATCH_BYTES,
     Server,
     ServeResult,
     Stats,
@@ -17,6 +18,7 @@ from .tc import (  # noqa: F401
     load,
     tc_count,
     tc_count_batch,
+    tc_count_batch_noalloc,
     tc_count_batch_workspace_size,
     tc_count_ex,
     tc_count_per_vertex,

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtc.so")
 SOURCES = ["prep.hip", "bfs.hip", "cover.hip", "hub.hip", "intersect.hip", "batch.hip",
-           "cluster.hip", "api.hip", "serve.hip"]
+           "cluster.hip", "api.hip", "serve.hip", "noalloc.hip"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

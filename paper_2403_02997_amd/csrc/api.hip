@@ -529,6 +529,8 @@ int check_args(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint6
 
 }  // namespace
 
+IsectParams current_isect_params() { return g_params; }
+
 size_t single_call_bytes(u32 n, u64 m) {
   const IsectParams prm = g_params;
   const size_t items = (size_t)n + m / prm.seg + 1;  // workgroup items (allocated after planning)

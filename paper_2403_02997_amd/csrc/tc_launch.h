@@ -30,6 +30,9 @@ struct IsectParams {
   u32 seg;         // partners per block item
 };
 
+// The thresholds in force (set by tc_set_isect_params).
+IsectParams current_isect_params();
+
 // Planning output (device), read back once by the host.
 struct Plan {
   u32 num_lane_x;   // vertices of the lane class

@@ -36,6 +36,7 @@ EXPORTS = (
     "tc_local_clustering",
     "tc_count_batch",
     "tc_count_batch_workspace_size",
+    "tc_count_batch_noalloc",
     "tc_serve_create",
     "tc_serve_submit",
     "tc_serve_poll",
@@ -163,6 +164,8 @@ def load() -> ctypes.CDLL:
     lib.tc_count_batch.restype = i
     lib.tc_count_batch_workspace_size.argtypes = [u32, u64, u64]
     lib.tc_count_batch_workspace_size.restype = sz
+    lib.tc_count_batch_noalloc.argtypes = [vp, vp, vp, vp, u32, u64, u64, vp, vp]
+    lib.tc_count_batch_noalloc.restype = i
     P = ctypes.POINTER
     lib.tc_serve_create.argtypes = [P(_ServeConfig), P(vp)]
     lib.tc_serve_create.restype = i
@@ -341,6 +344,33 @@ def tc_count_batch(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor, row_off: 
                             _ptr(workspace) if workspace is not None else None, ws_bytes,
                             _stream_handle(stream), _ptr(counts) if G else None)
     _check(rc, "tc_count_batch")
+    return counts
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # TC_NOALLOC_SCRATCH_BYTES
+
+
+def tc_count_batch_noalloc(rowptr_cat: torch.Tensor, colidx_cat: torch.Tensor,
+                           row_off: torch.Tensor, col_off: torch.Tensor, counts: torch.Tensor,
+                           total_rows: int | None = None, total_cols: int | None = None,
+                           stream=None) -> torch.Tensor:
+    """tc_count_batch with the library's fixed per-device scratch array as its workspace:
+    nothing is allocated, so `counts` (int64 device tensor of num_graphs entries) is
+    required.  Calls that overlap on one device race (the caller serialises them)."""
+    lib = load()
+    if row_off.dtype != torch.int64 or col_off.dtype != torch.int64:
+        raise TypeError("row_off / col_off must be int64")
+    G = row_off.numel() - 1
+    if G > 0 and (counts is None or counts.numel() < G or counts.dtype != torch.int64):
+        raise ValueError("counts must be an int64 device tensor of num_graphs entries")
+    if total_rows is None:
+        total_rows = rowptr_cat.numel()
+    if total_cols is None:
+        total_cols = colidx_cat.numel()
+    rc = lib.tc_count_batch_noalloc(_ptr(rowptr_cat), _ptr(colidx_cat) or None, _ptr(row_off),
+                                    _ptr(col_off), G, int(total_rows), int(total_cols),
+                                    _stream_handle(stream), _ptr(counts) if G else None)
+    _check(rc, "tc_count_batch_noalloc")
     return counts
 
 

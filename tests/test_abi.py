@@ -81,6 +81,21 @@ def test_argument_errors_without_gpu(lib):
     p = ctypes.cast(dummy, ctypes.c_void_p)
     assert lib.tc_count_batch(p, p, p, p, 1, 2, (1 << 32) - (1 << 20) + 1, None, 0, None,
                               p) == -5
+    # the allocation-free batch: the same argument checks, and a batch whose workspace
+    # exceeds the fixed scratch array is refused before any device call
+    lib.tc_count_batch_noalloc.argtypes = [ctypes.c_void_p] * 4 + [
+        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.tc_count_batch_noalloc(None, None, None, None, 3, 10, 20, None, None) == -1
+    assert lib.tc_count_batch_noalloc(None, None, None, None, 0, 0, 0, None, None) == 0
+    assert lib.tc_count_batch_noalloc(p, p, p, p, 1, 2, (1 << 32) - (1 << 20) + 1, None, p) == -5
+    lib.tc_count_batch_workspace_size.argtypes = [ctypes.c_uint32, ctypes.c_uint64,
+                                                  ctypes.c_uint64]
+    lib.tc_count_batch_workspace_size.restype = ctypes.c_size_t
+    cap = 64 << 20
+    rows = 1 << 20
+    cols = (cap - lib.tc_count_batch_workspace_size(4, rows, 0)) // 8 + 64
+    assert lib.tc_count_batch_workspace_size(4, rows, cols) > cap
+    assert lib.tc_count_batch_noalloc(p, p, p, p, 4, rows, cols, None, p) == -5
     # clustering coefficients: checked before the launch
     lib.tc_local_clustering.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_void_p]
