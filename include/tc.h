@@ -94,6 +94,24 @@ int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_
              hipStream_t stream, uint64_t* count);
 
 /*
+ * tc_count_split — the two terms of the split form CETC-Seq-S (Section 4.3, Alg.
+ * CETC-Seq-S) from tc_count's own pruned pass.  With the BFS levels, G0 is the
+ * subgraph of the horizontal edges and G1 that of the other edges.  t0_t1 is a HOST
+ * uint64[2]:
+ *   t0_t1[0] = t0, the triangles whose three edges are all in G0 (all three vertices on
+ *              one level; the paper counts them by forward hashing on G0);
+ *   t0_t1[1] = t1, the triangles with an edge in G1 (the apex on another level; the
+ *              paper counts them by hashed intersections in G1 over the edges of G0).
+ * t0 + t1 = T.  The call runs exactly the kernels of tc_count (same classes, hub pass and
+ * streams); every counted apex is tallied by the level of the streamed entry: an entry
+ * of the partner's same-level range counts towards t0, one of its other-level range
+ * towards t1.  Same arguments, workspace, blocking and errors as tc_count (a null t0_t1
+ * is TC_ERR_INVALID_ARG); n == 0 or m == 0 gives {0, 0} without a launch.
+ */
+int tc_count_split(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+                   hipStream_t stream, uint64_t* t0_t1);
+
+/*
  * tc_count_ex — tc_count plus diagnostics.  `level_out` (DEVICE uint32[n], may be NULL)
  * receives the BFS level of every vertex; `stats` (HOST, may be NULL) the statistics
  * above.  `count` may be NULL when `stats` is given.  With `stats` every intersection

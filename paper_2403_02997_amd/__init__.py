@@ -22,6 +22,7 @@ from .tc import (  # noqa: F401
     tc_count_batch_workspace_size,
     tc_count_ex,
     tc_count_per_vertex,
+    tc_count_split,
     tc_local_clustering,
     tc_get_hub_params,
     tc_get_isect_params,

@@ -313,9 +313,10 @@ size_t carve_single(void* base, u32 n, u32 m, bool hub_on, SingleWs* out) {
 }
 
 // The whole single-graph pipeline.  `level_out` (device) may be null; `tri` (device,
-// zeroed by the caller) selects per-vertex attribution.
+// zeroed by the caller) selects per-vertex attribution.  split_stats (with pruned): the
+// pruned kernels tally same-level apexes in t2 and other-level ones in c1.
 int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s,
-               u32* level_out, u64* tri, bool pruned, RunOut* out) {
+               u32* level_out, u64* tri, bool pruned, RunOut* out, bool split_stats = false) {
   prepare_pool();
   const IsectParams prm = g_params;
   // the hub pass serves the pruned count only (per-vertex and c1 / c2 tallies stay per
@@ -462,29 +463,29 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     // side stream first: the hub count and the wavefront class take compute units while
     // the workgroup class (persistent workgroups that hold their units to the end) ramps up
     if (hubs)
-      launch_hub_count(rowptr, colidx2, sabove, h_plan.num_hubs, hy, hubmask, hitems,
-                       h_plan.num_hub_items, ctr, sw);
+      launch_hub_count(rowptr, colidx2, sabove, split, h_plan.num_hubs, hy, hubmask, hitems,
+                       h_plan.num_hub_items, ctr, split_stats, sw);
     launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
-                      tri, pruned && !tri, sw);
+                      tri, pruned && !tri, split_stats, sw);
     launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
     launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
-                       pruned && !tri, s);
+                       pruned && !tri, split_stats, s);
   } else {
     timer.mark();
     launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
     timer.mark();
     launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
-                       pruned && !tri, s);
+                       pruned && !tri, split_stats, s);
     timer.mark();
     launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
-                      tri, pruned && !tri, s);
+                      tri, pruned && !tri, split_stats, s);
     timer.mark();
     if (hubs && timer.on)
       launch_hub_masks(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hcuts, hubmask,
                        s);
     if (hubs)
-      launch_hub_count(rowptr, colidx2, sabove, h_plan.num_hubs, hy, hubmask, hitems,
-                       h_plan.num_hub_items, ctr, s);
+      launch_hub_count(rowptr, colidx2, sabove, split, h_plan.num_hubs, hy, hubmask, hitems,
+                       h_plan.num_hub_items, ctr, split_stats, s);
     timer.mark();
   }
   TC_LAUNCHED();
@@ -600,6 +601,26 @@ int tc_count(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_
              hipStream_t stream, uint64_t* count) {
   if (!count) return TC_ERR_INVALID_ARG;
   return tc_count_ex(rowptr, colidx, n, m, stream, count, nullptr, nullptr);
+}
+
+int tc_count_split(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,
+                   hipStream_t stream, uint64_t* t0_t1) {
+  int rc = check_args(rowptr, colidx, n, m);
+  if (rc) return rc;
+  if (!t0_t1) return TC_ERR_INVALID_ARG;
+  if (n == 0 || m == 0) {
+    t_last_info = tc_call_info{};
+    t0_t1[0] = 0;
+    t0_t1[1] = 0;
+    return TC_OK;
+  }
+  RunOut ro;
+  memset(&ro, 0, sizeof(ro));
+  rc = run_single(rowptr, colidx, n, (u32)m, stream, nullptr, nullptr, true, &ro, true);
+  if (rc) return rc;
+  t0_t1[0] = ro.c[2];  // same-level apexes above both ends: the triangles inside G0
+  t0_t1[1] = ro.c[0];  // other-level apexes: the triangles with an edge in G1
+  return TC_OK;
 }
 
 int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n,

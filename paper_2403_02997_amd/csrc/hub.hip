@@ -169,29 +169,33 @@ __global__ void __launch_bounds__(kHubThreads) k_hub_mask(const u32* __restrict_
 // One wavefront per work item (y, offset): up to kHubChunk entries of N'(y), each
 // looked up in M and masked with H(y).  The entries of a lane are all loaded before the
 // mask lookups, and the lookups of a lane are all in flight before the first count.
+// ST: the apexes w before split[y] (on y's level, hence on the hub's) are tallied in the
+// t2 counter, the others in c1 (the two terms of the split).
 constexpr u32 kHubU = kHubChunk / kWave;  // entries per lane and item
 
-template <u32 NW>
+template <u32 NW, bool ST>
 __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowptr,
                                                    const u32* __restrict__ colidx2,
                                                    const u32* __restrict__ sabove,
+                                                   const u32* __restrict__ split,
                                                    const u32* __restrict__ hy,
                                                    const u32* __restrict__ hubmask,
                                                    const uint2* __restrict__ items, u32 nitems,
                                                    u64* __restrict__ ctr) {
   constexpr u32 NQ = NW / 4;  // 16-byte words per mask
-  __shared__ u64 s_red[256 / kWave];
+  __shared__ u64 s_red[2 * 256 / kWave];
   const u32 lane = lane_id();
   const u32 wid = threadIdx.x / kWave;
   const u32 gw = blockIdx.x * (blockDim.x / kWave) + wid;
   const u32 nwv = gridDim.x * (blockDim.x / kWave);
   const uint4* __restrict__ m4 = reinterpret_cast<const uint4*>(hubmask);
-  u64 acc = 0;
+  u64 acc = 0, acc_same = 0;
   for (u32 i = gw; i < nitems; i += nwv) {
     const uint2 it = items[i];
     const u32 y = it.x;
     const u32 b = sabove[y] + it.y;               // < rowptr[y + 1] (items cover N'(y))
     const u32 e = b + min(kHubChunk, rowptr[y + 1] - b);
+    const u32 ys = ST ? split[y] : 0u;            // start of y's other-level part
     uint4 hq[NQ];
     const uint4* hy4 = reinterpret_cast<const uint4*>(hy + (size_t)y * kHubWords);
 #pragma unroll
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowpt
       const u32 j = b + u * kWave + lane;
       w[u] = j < e ? colidx2[j] : kInf;
     }
-    u32 part = 0;
+    u32 part = 0, part_same = 0;
     constexpr u32 G = 8;  // lookups in flight per lane
 #pragma unroll
     for (u32 u0 = 0; u0 < kHubU; u0 += G) {
@@ -214,23 +218,35 @@ __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowpt
         for (u32 q = 0; q < NQ; ++q)
           mv[u][q] = w[u0 + u] != kInf ? m4[(size_t)w[u0 + u] * NQ + q] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-      for (u32 u = 0; u < G; ++u)
+      for (u32 u = 0; u < G; ++u) {
+        u32 h = 0;
 #pragma unroll
         for (u32 q = 0; q < NQ; ++q)
-          part += __popc(mv[u][q].x & hq[q].x) + __popc(mv[u][q].y & hq[q].y) +
-                  __popc(mv[u][q].z & hq[q].z) + __popc(mv[u][q].w & hq[q].w);
+          h += __popc(mv[u][q].x & hq[q].x) + __popc(mv[u][q].y & hq[q].y) +
+               __popc(mv[u][q].z & hq[q].z) + __popc(mv[u][q].w & hq[q].w);
+        if (ST && b + (u0 + u) * kWave + lane < ys) part_same += h;
+        else part += h;
+      }
     }
     acc += part;
+    acc_same += part_same;
   }
   acc = wave_sum_u64(acc);
-  if (lane == 0) s_red[wid] = acc;
+  if (ST) acc_same = wave_sum_u64(acc_same);
+  if (lane == 0) {
+    s_red[wid] = acc;
+    if (ST) s_red[blockDim.x / kWave + wid] = acc_same;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    u64 sum = 0;
-    for (u32 k = 0; k < blockDim.x / kWave; ++k) sum += s_red[k];
-    if (sum)
-      atomicAdd((unsigned long long*)&ctr[(blockIdx.x % kCounterSlots) * kNumCtr + 0],
-                (unsigned long long)sum);
+    u64 sum = 0, sum_same = 0;
+    for (u32 k = 0; k < blockDim.x / kWave; ++k) {
+      sum += s_red[k];
+      if (ST) sum_same += s_red[blockDim.x / kWave + k];
+    }
+    u64* slot = &ctr[(blockIdx.x % kCounterSlots) * kNumCtr];
+    if (sum) atomicAdd((unsigned long long*)&slot[0], (unsigned long long)sum);
+    if (sum_same) atomicAdd((unsigned long long*)&slot[2], (unsigned long long)sum_same);
   }
 }
 
@@ -252,17 +268,23 @@ void launch_hub_masks(const u32* rowptr, const u32* colidx2, const u32* split,
                        nwin, hubmask);
 }
 
-void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove, u32 nhubs,
-                      const u32* hy, const u32* hubmask, const uint2* items, u32 nitems,
-                      u64* ctr, hipStream_t s) {
+void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove,
+                      const u32* split, u32 nhubs, const u32* hy, const u32* hubmask,
+                      const uint2* items, u32 nitems, u64* ctr, bool split_stats,
+                      hipStream_t s) {
   if (nhubs == 0 || nitems == 0) return;
   const u32 gc = min(cdiv(nitems, 256 / kWave), (u32)num_cus() * 8);
-  if (hub_mask_words(nhubs) == 4)
-    hipLaunchKernelGGL(k_hub_count<4>, dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, hy,
-                       hubmask, items, nitems, ctr);
-  else
-    hipLaunchKernelGGL(k_hub_count<8>, dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, hy,
-                       hubmask, items, nitems, ctr);
+#define TC_LAUNCH_HUB(NW, ST)                                                                  \
+  hipLaunchKernelGGL((k_hub_count<NW, ST>), dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, \
+                     split, hy, hubmask, items, nitems, ctr)
+  if (hub_mask_words(nhubs) == 4) {
+    if (split_stats) TC_LAUNCH_HUB(4, true);
+    else TC_LAUNCH_HUB(4, false);
+  } else {
+    if (split_stats) TC_LAUNCH_HUB(8, true);
+    else TC_LAUNCH_HUB(8, false);
+  }
+#undef TC_LAUNCH_HUB
 }
 
 }  // namespace tc

@@ -48,8 +48,9 @@ __global__ void __launch_bounds__(kTileThreads) k_isect_lane(
 
 // ---- wave class: one wavefront per staged vertex x ---------------------------------------
 // REC: the pruned form over the level-split rows (colidx = colidx2, tail4 = its padded
-// last quad); otherwise the full form over colidx.
-template <bool PV, bool VEC, bool REC>
+// last quad); otherwise the full form over colidx.  ST (with REC): same-level hits are
+// tallied as t2 and other-level ones as c1 (the two terms of the split).
+template <bool PV, bool VEC, bool REC, bool ST = false>
 __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
         if (REC) mt1 = wave_meta(rowptr, sabove, hcnt, x1);
       }
       Tally tl{0, 0, 0, 0};
-      wave_vertex<PV, VEC, REC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
+      wave_vertex<PV, VEC, REC, 4, ST>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
                                    hrec, sabove, x, mt, s_table[wid], s_pinfo[wid], s_end[wid],
                                    s_mark[wid], tl, c, tri);
       tl.fold(c);
@@ -106,7 +107,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
 }
 
 // ---- block class: one 1024-thread workgroup per (x, segment of partners) ----------------
-template <bool PV, bool VEC, bool PRUNED>
+template <bool PV, bool VEC, bool PRUNED, bool ST = false>
 __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const u32* __restrict__ colidx2,
@@ -132,8 +133,8 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     if (it >= nitems) break;
     const Item item = items[it];
     if (PRUNED)
-      block_item_rec<VEC, true>(rowptr, colidx2, m, tail4b, split, sabove, hcnt, hrec, item.x,
-                                item.seg, prm, sh, tl, c);
+      block_item_rec<VEC, true, ST>(rowptr, colidx2, m, tail4b, split, sabove, hcnt, hrec,
+                                    item.x, item.seg, prm, sh, tl, c);
     else
       block_item<PV, VEC, false, 4>(rowptr, 0u, colidx, m, tail4, colidx2, m, split, tail4b,
                                     vinfo, hcnt, record_ids(hrec), item.x, item.seg, prm, sh, tl,
@@ -182,26 +183,30 @@ void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinf
 
 void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                        const uint8_t* vinfo, const SplitView& sv, const u32* wave_x, u32 nwx,
-                       Plan* plan, u64* ctr, u64* tri, bool pruned, hipStream_t s) {
+                       Plan* plan, u64* ctr, u64* tri, bool pruned, bool split_stats,
+                       hipStream_t s) {
   if (nwx == 0) return;
   const u32 g = min(cdiv(nwx, kIsectThreads / kWave), resident_blocks(8));
   const bool rec = pruned && !tri;
   const u32* src = rec ? sv.colidx2 : colidx;  // the streamed and staged rows
   const u32* tail = rec ? sv.tail4b : tail4;
   const bool vec = ((uintptr_t)src & 15u) == 0;
-#define TC_LAUNCH_WAVE(PV, VEC, REC)                                                           \
-  hipLaunchKernelGGL((k_isect_wave<PV, VEC, REC>), dim3(g), dim3(kIsectThreads), 0, s, rowptr,  \
-                     src, m, tail, vinfo, sv.hcnt, sv.hrec, sv.sabove, wave_x, nwx, plan, ctr,  \
-                     tri)
+#define TC_LAUNCH_WAVE(PV, VEC, REC, ST)                                                       \
+  hipLaunchKernelGGL((k_isect_wave<PV, VEC, REC, ST>), dim3(g), dim3(kIsectThreads), 0, s,      \
+                     rowptr, src, m, tail, vinfo, sv.hcnt, sv.hrec, sv.sabove, wave_x, nwx,     \
+                     plan, ctr, tri)
   if (tri) {
-    if (vec) TC_LAUNCH_WAVE(true, true, false);
-    else TC_LAUNCH_WAVE(true, false, false);
+    if (vec) TC_LAUNCH_WAVE(true, true, false, false);
+    else TC_LAUNCH_WAVE(true, false, false, false);
+  } else if (rec && split_stats) {
+    if (vec) TC_LAUNCH_WAVE(false, true, true, true);
+    else TC_LAUNCH_WAVE(false, false, true, true);
   } else if (rec) {
-    if (vec) TC_LAUNCH_WAVE(false, true, true);
-    else TC_LAUNCH_WAVE(false, false, true);
+    if (vec) TC_LAUNCH_WAVE(false, true, true, false);
+    else TC_LAUNCH_WAVE(false, false, true, false);
   } else {
-    if (vec) TC_LAUNCH_WAVE(false, true, false);
-    else TC_LAUNCH_WAVE(false, false, false);
+    if (vec) TC_LAUNCH_WAVE(false, true, false, false);
+    else TC_LAUNCH_WAVE(false, false, false, false);
   }
 #undef TC_LAUNCH_WAVE
 }
@@ -209,24 +214,27 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* t
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                         const uint8_t* vinfo, const SplitView& sv, const Item* items,
                         u32 nitems, IsectParams p, Plan* plan, u64* ctr, u64* tri, bool pruned,
-                        hipStream_t s) {
+                        bool split_stats, hipStream_t s) {
   if (nitems == 0) return;
   const u32 g = min(nitems, resident_blocks(1));
   const bool rec = pruned && !tri;
   const bool vec = ((uintptr_t)(rec ? sv.colidx2 : colidx) & 15u) == 0;
-#define TC_LAUNCH_BLOCK(PV, VEC, PR)                                                           \
-  hipLaunchKernelGGL((k_isect_block<PV, VEC, PR>), dim3(g), dim3(kBigThreads), 0, s, rowptr,    \
-                     colidx, m, tail4, sv.colidx2, sv.split, sv.sabove, sv.tail4b, vinfo,       \
-                     sv.hcnt, sv.hrec, items, nitems, p, plan, ctr, tri)
+#define TC_LAUNCH_BLOCK(PV, VEC, PR, ST)                                                       \
+  hipLaunchKernelGGL((k_isect_block<PV, VEC, PR, ST>), dim3(g), dim3(kBigThreads), 0, s,        \
+                     rowptr, colidx, m, tail4, sv.colidx2, sv.split, sv.sabove, sv.tail4b,      \
+                     vinfo, sv.hcnt, sv.hrec, items, nitems, p, plan, ctr, tri)
   if (tri) {
-    if (vec) TC_LAUNCH_BLOCK(true, true, false);
-    else TC_LAUNCH_BLOCK(true, false, false);
+    if (vec) TC_LAUNCH_BLOCK(true, true, false, false);
+    else TC_LAUNCH_BLOCK(true, false, false, false);
+  } else if (rec && split_stats) {
+    if (vec) TC_LAUNCH_BLOCK(false, true, true, true);
+    else TC_LAUNCH_BLOCK(false, false, true, true);
   } else if (rec) {
-    if (vec) TC_LAUNCH_BLOCK(false, true, true);
-    else TC_LAUNCH_BLOCK(false, false, true);
+    if (vec) TC_LAUNCH_BLOCK(false, true, true, false);
+    else TC_LAUNCH_BLOCK(false, false, true, false);
   } else {
-    if (vec) TC_LAUNCH_BLOCK(false, true, false);
-    else TC_LAUNCH_BLOCK(false, false, false);
+    if (vec) TC_LAUNCH_BLOCK(false, true, false, false);
+    else TC_LAUNCH_BLOCK(false, false, false, false);
   }
 #undef TC_LAUNCH_BLOCK
 }

@@ -304,9 +304,14 @@ __device__ __forceinline__ bool bucket_holds(uint4 v, u32 w) {
 }
 __device__ __forceinline__ bool bucket_flagged(uint4 v) { return v.w - kFlag < kInf - kFlag; }
 
-template <int N>
-__device__ __forceinline__ void hash_count_n(const u32* table, u32 bmask, const u32 (&w)[N],
-                                             const bool (&ok)[N], u32& hits) {
+// SPLIT: present keys with sm[i] set go to hits_same instead of hits (the split
+// statistics of the pruned count tell same-level apexes from other-level ones by the
+// streamed element's position).
+template <int N, bool SPLIT>
+__device__ __forceinline__ void hash_count_split_n(const u32* table, u32 bmask,
+                                                   const u32 (&w)[N], const bool (&ok)[N],
+                                                   const bool (&sm)[N], u32& hits,
+                                                   u32& hits_same) {
   const uint4* t4 = reinterpret_cast<const uint4*>(table);
   uint4 v[N];
   u32 b[N];
@@ -318,8 +323,13 @@ __device__ __forceinline__ void hash_count_n(const u32* table, u32 bmask, const 
   bool more = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const bool hit = bucket_holds(v[i], w[i]);
-    hits += ok[i] && hit ? 1u : 0u;
+    const bool hit = ok[i] && bucket_holds(v[i], w[i]);
+    if (SPLIT) {
+      hits += hit && !sm[i] ? 1u : 0u;
+      hits_same += hit && sm[i] ? 1u : 0u;
+    } else {
+      hits += hit ? 1u : 0u;
+    }
     more |= ok[i] && !hit && bucket_flagged(v[i]);
   }
   if (!__ballot(more)) return;
@@ -331,10 +341,12 @@ __device__ __forceinline__ void hash_count_n(const u32* table, u32 bmask, const 
     if (pend) {
       const u32 i = __ffs(pend) - 1;
       u32 wi = w[0], bi = b[0];
+      bool si = sm[0];
 #pragma unroll
       for (int j = 1; j < N; ++j) {
         wi = (u32)j == i ? w[j] : wi;
         bi = (u32)j == i ? b[j] : bi;
+        si = (u32)j == i ? sm[j] : si;
       }
       bi = (bi + 1) & bmask;
       const uint4 vv = t4[bi];
@@ -342,10 +354,21 @@ __device__ __forceinline__ void hash_count_n(const u32* table, u32 bmask, const 
 #pragma unroll
       for (int j = 0; j < N; ++j)
         if ((u32)j == i) b[j] = bi;
-      hits += hit ? 1u : 0u;
+      if (SPLIT && si) hits_same += hit ? 1u : 0u;
+      else hits += hit ? 1u : 0u;
       if (hit || !bucket_flagged(vv)) pend &= pend - 1;
     }
   }
+}
+
+template <int N>
+__device__ __forceinline__ void hash_count_n(const u32* table, u32 bmask, const u32 (&w)[N],
+                                             const bool (&ok)[N], u32& hits) {
+  bool sm[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) sm[i] = false;
+  u32 unused = 0;
+  hash_count_split_n<N, false>(table, bmask, w, ok, sm, hits, unused);
 }
 
 struct Counts;

@@ -95,8 +95,10 @@ __device__ __forceinline__ WaveMeta wave_meta(const u32* __restrict__ rowptr,
 // is then colidx2): x's entries from sabove[x] on against each partner record's range,
 // membership only; every hit goes to s.  With REC the row data comes in mt (loaded
 // ahead by the caller) and the first 64 partner records are loaded before the staged
-// set is built, so their latency overlaps the inserts.
-template <bool PV, bool VEC, bool REC = false, int HS = 1>
+// set is built, so their latency overlaps the inserts.  ST (with REC): hits in a
+// record's same-level range (.x .. .y) go to tl.t2, those in its other-level range
+// (.y .. .z) to tl.s, so the two terms of the split (Alg. CETC-Seq-S) come out apart.
+template <bool PV, bool VEC, bool REC = false, int HS = 1, bool ST = false>
 __device__ __forceinline__ void wave_vertex(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
@@ -105,6 +107,7 @@ __device__ __forceinline__ void wave_vertex(
     u32* table, uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c,
     u64* __restrict__ tri) {
   static_assert(!(REC && PV), "per-vertex counts use the full form");
+  static_assert(!ST || REC, "split statistics come from the partner records");
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
   const u32 lane = lane_id();
   const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
@@ -135,7 +138,7 @@ __device__ __forceinline__ void wave_vertex(
     if (p < np) {
       if (REC) {
         const uint4 r = pb == 0 ? r0 : hrec[hs + p];
-        y = r.w;
+        y = ST ? r.y : r.w;  // the pruned form never reads y; ST keeps the range split there
         lo = r.x;
         hi = r.z;
       } else {
@@ -207,7 +210,12 @@ __device__ __forceinline__ void wave_vertex(
         bool ok[NE];
 #pragma unroll
         for (u32 i = 0; i < NE; ++i) ok[i] = live[u] && (addr[u] + i - inf[u].y) < span;
-        if (REC) {
+        if (REC && ST) {
+          bool sm[NE];
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) sm[i] = addr[u] + i < inf[u].w;
+          hash_count_split_n<NE, true>(table, mask, e[u], ok, sm, tl.s, tl.t2);
+        } else if (REC) {
           hash_count_n<NE>(table, mask, e[u], ok, tl.s);
         } else {
           u32 res[NE];
@@ -249,7 +257,9 @@ __device__ __forceinline__ void wave_vertex(
 //               (hits are the counted apexes of both kinds).
 // A same-level apex w <= max(x, y) is never counted (the apex rule), so the pruned
 // passes skip those list entries entirely and leave c2 uncounted.  kOther, kSame and
-// kMember stage plain IDs, probe for membership only and add their hits to s.
+// kMember stage plain IDs, probe for membership only; kSame adds its hits to t2, kOther
+// and kMember to s (with ST, kMember's hits in the range before the split point carried
+// in place of y go to t2).
 enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3, kMember = 4 };
 
 struct BlockShared {
@@ -270,7 +280,8 @@ constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
 // PAD: the streamed array has at least 4 readable entries past its m counted ones, so
 // every live quad is read in place and dead lanes only clamp their address.
 // QU windows of 64 quads per wavefront are loaded before probing.
-template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false, int QU = kQuadUnroll>
+template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false, int QU = kQuadUnroll,
+          bool ST = false>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
@@ -278,7 +289,9 @@ __device__ __forceinline__ void block_pass(
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad (a quad is one element without VEC)
   const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   static_assert(!BM || MODE == kOther || MODE == kSame, "bitmaps hold membership only");
+  static_assert(!ST || MODE == kMember, "only the one-chunk member pass mixes both kinds");
   constexpr bool MEMBER = MODE == kOther || MODE == kSame || MODE == kMember;
+  u32& hits = MODE == kSame ? tl.t2 : tl.s;  // same-level apexes above both ends: t2
   const u32 glen = ge - gs;
   // hash chunks by count, or bitmap windows by ID
   const u32 w_first = BM && glen ? ga[gs] >> kWinBits : 0u;
@@ -406,10 +419,15 @@ __device__ __forceinline__ void block_pass(
             const u32 k = e[u][i] - wb;
             const bool in = ok[i] && k < (1u << kWinBits);
             const u32 kk = in ? k : 0u;
-            tl.s += in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
+            hits += in ? (sh.table[kk >> 5] >> (kk & 31u)) & 1u : 0u;
           }
+        } else if (ST) {
+          bool sm[NE];
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) sm[i] = addr[u] + i < inf[u].w;
+          hash_count_split_n<NE, true>(sh.table, mask, e[u], ok, sm, tl.s, tl.t2);
         } else if (MEMBER) {
-          hash_count_n<NE>(sh.table, mask, e[u], ok, tl.s);
+          hash_count_n<NE>(sh.table, mask, e[u], ok, hits);
         } else {
           u32 res[NE];
           hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
@@ -503,8 +521,9 @@ __device__ __forceinline__ void block_item(
 // pass streams each record's range .x .. .z; otherwise a kOther pass (x's other-level
 // part against .y .. .z) and a kSame pass (x's same-level part above x against
 // .x .. .y), each with hash chunks or bitmap windows, whichever takes fewer passes.
-// PAD: colidx2 has 4 readable entries past its m2 counted ones.
-template <bool VEC, bool PAD = false>
+// PAD: colidx2 has 4 readable entries past its m2 counted ones.  ST: the member pass
+// tallies same-level and other-level hits apart (see block_pass).
+template <bool VEC, bool PAD = false, bool ST = false>
 __device__ __forceinline__ void block_item_rec(
     const u32* __restrict__ rowptr, const u32* __restrict__ colidx2, u32 m2,
     const u32* __restrict__ tail4b, const u32* __restrict__ split,
@@ -519,8 +538,9 @@ __device__ __forceinline__ void block_item_rec(
   uint4 r = make_uint4(0, 0, 0, 0);
   if (tid < pn) r = hrec[hs + tid];
   if (ex - gx <= prm.chunk) {
-    block_pass<false, VEC, kMember, false, PAD>(colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0,
-                                           r.w, pn, r.x, r.z, prm, sh, tl, c, nullptr);
+    block_pass<false, VEC, kMember, false, PAD, kQuadUnroll, ST>(
+        colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0, ST ? r.y : r.w, pn, r.x, r.z, prm,
+        sh, tl, c, nullptr);
   } else {
     if (use_bitmap(colidx2, sx, ex, prm.chunk))
       block_pass<false, VEC, kOther, true, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,

@@ -154,16 +154,19 @@ u32 hub_mask_words(u32 nhubs);
 void launch_hub_masks(const u32* rowptr, const u32* colidx2, const u32* split,
                       const u32* sabove, const u32* hublist, u32 nhubs, u32 n, u32* cuts,
                       u32* hubmask, hipStream_t s);
-// Counts the hub items' triangles into the c1 counter (no LDS).
-void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove, u32 nhubs,
-                      const u32* hy, const u32* hubmask, const uint2* items, u32 nitems,
-                      u64* ctr, hipStream_t s);
+// Counts the hub items' triangles into the c1 counter (no LDS); with split_stats the
+// same-level apexes go to the t2 counter instead.
+void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove,
+                      const u32* split, u32 nhubs, const u32* hy, const u32* hubmask,
+                      const uint2* items, u32 nitems, u64* ctr, bool split_stats,
+                      hipStream_t s);
 
 // ---- intersection ----
 // The intersection launchers take the split's outputs in one struct.  pruned: count
-// only T (in the c1 slot), from the level-split rows (colidx2 holds m entries plus 4
-// readable padding entries) and the partner records; otherwise c1, c2 and t2 from
-// colidx, with the partners read from the records' .w fields.
+// only T (in the c1 and t2 slots), from the level-split rows (colidx2 holds m entries
+// plus 4 readable padding entries) and the partner records; otherwise c1, c2 and t2 from
+// colidx, with the partners read from the records' .w fields.  split_stats (with
+// pruned): every same-level apex is tallied in t2 and every other-level one in c1.
 struct SplitView {
   const u32* colidx2;
   const u32* split;
@@ -177,12 +180,13 @@ void launch_isect_lane(const u32* rowptr, const u32* colidx, const uint8_t* vinf
                        hipStream_t s);
 void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                        const uint8_t* vinfo, const SplitView& sv, const u32* wave_x, u32 nwx,
-                       Plan* plan, u64* ctr, u64* tri, bool pruned, hipStream_t s);
+                       Plan* plan, u64* ctr, u64* tri, bool pruned, bool split_stats,
+                       hipStream_t s);
 void launch_tail4(const u32* colidx, u32 m, u32* tail4, hipStream_t s);
 void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* tail4,
                         const uint8_t* vinfo, const SplitView& sv, const Item* items,
                         u32 nitems, IsectParams p, Plan* plan, u64* ctr, u64* tri, bool pruned,
-                        hipStream_t s);
+                        bool split_stats, hipStream_t s);
 void launch_finalize(const u64* ctr, u64* out, hipStream_t s);
 
 // ---- batched, fused per-graph pipeline ----

@@ -32,6 +32,7 @@ STATUS = {
 EXPORTS = (
     "tc_count",
     "tc_count_ex",
+    "tc_count_split",
     "tc_count_per_vertex",
     "tc_local_clustering",
     "tc_count_batch",
@@ -153,6 +154,8 @@ def load() -> ctypes.CDLL:
     i = ctypes.c_int
     lib.tc_count.argtypes = [vp, vp, u32, u64, vp, ctypes.POINTER(u64)]
     lib.tc_count.restype = i
+    lib.tc_count_split.argtypes = [vp, vp, u32, u64, vp, ctypes.POINTER(u64)]
+    lib.tc_count_split.restype = i
     lib.tc_count_ex.argtypes = [vp, vp, u32, u64, vp, ctypes.POINTER(u64), vp,
                                 ctypes.POINTER(_Stats)]
     lib.tc_count_ex.restype = i
@@ -266,6 +269,17 @@ def tc_count(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None) -> int:
                       ctypes.byref(out))
     _check(rc, "tc_count")
     return int(out.value)
+
+
+def tc_count_split(rowptr: torch.Tensor, colidx: torch.Tensor, stream=None) -> tuple:
+    """(t0, t1) of the split form CETC-Seq-S from the pruned pass of tc_count: t0 = the
+    triangles inside the subgraph of horizontal edges, t1 = the others (blocking)."""
+    lib = load()
+    n, m = _n_m(rowptr, colidx)
+    out = (ctypes.c_uint64 * 2)()
+    rc = lib.tc_count_split(_ptr(rowptr), _ptr(colidx), n, m, _stream_handle(stream), out)
+    _check(rc, "tc_count_split")
+    return int(out[0]), int(out[1])
 
 
 def tc_count_ex(rowptr: torch.Tensor, colidx: torch.Tensor, want_levels: bool = False,

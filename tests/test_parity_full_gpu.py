@@ -48,6 +48,10 @@ def test_full_size_matches_oracle(tc_lib, name):
     assert np.array_equal(level.cpu().numpy().view(np.uint32), lv_ref)
     assert oracle.cover_edges(g, lv_ref) == ref["cover_edges"]
     assert tc_lib.tc_count(rp, ci) == ref["triangles"]
+    # the split's two terms from the pruned pass: t1 = c1 and 3 t0 = c2 of CETC-SM (both
+    # identities pinned on the CPU against the oracle's own CETC-Seq-S)
+    t0, t1 = tc_lib.tc_count_split(rp, ci)
+    assert t1 == ref["c1"] and 3 * t0 == ref["c2"]
 
 
 def test_batch4096_every_member(tc_lib):

@@ -112,6 +112,45 @@ def test_split_terms_match_cetc_s(tc_lib, name):
     assert tc_lib.tc_count(rp, ci) == t0 + t1
 
 
+SPLIT_SETTINGS = {
+    "default": (None, None),
+    "hubs": (None, (16, 1)),            # the hub pass on every graph of >= 1024 entries
+    "chunked": ((0, 16, 100, 7), None),  # workgroup class in other/same-level passes
+    "wave": ((0, 512, 16384, 1024), None),
+}
+
+
+@pytest.mark.parametrize("setting", list(SPLIT_SETTINGS))
+@pytest.mark.parametrize("name", ["karate", "wheel500", "tripartite", "grid64_del", "rmat12",
+                                  "rmat16", "er16_d32", "union", "book10000", "K40"])
+def test_pruned_split_terms_match_cetc_s(tc_lib, name, setting):
+    # tc_count_split tallies the apexes of tc_count's own pruned pass by the level of the
+    # streamed entry: same-level ones are the triangles inside G0 (t0, the forward-hashed
+    # term of CETC-Seq-S, Section 4.3), other-level ones the G1 intersections (t1).
+    g, r, _, _ = case(name)
+    T, t0, t1 = oracle.cetc_split(g, r.level)
+    isect, hubs = SPLIT_SETTINGS[setting]
+    say(f"[parity] pruned split terms {name} ({setting}): t0={t0} t1={t1}")
+    rp, ci = upload(g, tc_lib)
+    saved_i, saved_h = tc_lib.tc_get_isect_params(), tc_lib.tc_get_hub_params()
+    try:
+        if isect:
+            tc_lib.tc_set_isect_params(*isect)
+        if hubs:
+            tc_lib.tc_set_hub_params(*hubs)
+        got = tc_lib.tc_count_split(rp, ci)
+        info = tc_lib.tc_last_call_info()
+        pruned = tc_lib.tc_count(rp, ci)
+    finally:
+        tc_lib.tc_set_isect_params(*saved_i)
+        tc_lib.tc_set_hub_params(*saved_h)
+    assert T == r.triangles
+    assert got == (t0, t1)
+    assert pruned == t0 + t1
+    if hubs and name in ("rmat12", "rmat16"):
+        assert info["hubs"] > 0  # the hub pass took part
+
+
 @pytest.mark.parametrize("name", ["karate", "wheel500", "rmat12", "er14_d4", "book10000",
                                   "grid64_del", "union"])
 def test_per_vertex_matches_oracle(tc_lib, name):
