@@ -116,6 +116,74 @@ __device__ __forceinline__ void block_for_each_entry(const u32* __restrict__ rp,
   }
 }
 
+// Vertices of a graph whose BFS keeps its visited bitmap in the workgroup's LDS table.
+constexpr u32 kLdsBfsMax = (u32)kBigSlots * 32u;
+
+// Sampled links of every vertex with its neighbours number `first` and `first + 1` in
+// ascending order (cc_min_link), then a full compression.  All threads call it.
+__device__ __forceinline__ void batch_sample_links(const u32* __restrict__ rp,
+                                                   const u32* __restrict__ ci, u32 n,
+                                                   u32* parent, u32 first) {
+  for (u32 v = threadIdx.x; v < n; v += kBT) {
+    const u32 lo = rp[v], d = rp[v + 1] - lo;
+    if (d > first) {
+      const u32 a = ci[lo + first];
+      if (first > 0 || a > v) cc_min_link(parent, v, a);
+    }
+    if (d > first + 1) cc_min_link(parent, v, ci[lo + first + 1]);
+  }
+  __syncthreads();
+  for (u32 v = threadIdx.x; v < n; v += kBT) parent[v] = cc_find(parent, v);
+  __syncthreads();
+}
+
+// The most frequent root among up to kBatchModeSamples spread-out vertices that have
+// neighbours (the dominant set of the sampled union-find); *thin is set when it holds
+// fewer than 90 % of them.  All threads call it and get the same result; s_root holds
+// kBT words, s_best kBW words, s_live kBW words.
+constexpr u32 kBatchModeSamples = 512;
+
+__device__ __forceinline__ u32 batch_dominant_root(const u32* __restrict__ rp, u32 n,
+                                                   u32* parent, u32* s_root, u64* s_best,
+                                                   u32* s_live, bool* thin) {
+  const u32 i = threadIdx.x, lane = lane_id(), wid = threadIdx.x / kWave;
+  const u32 ns = min(n, kBatchModeSamples);
+  u32 r = kInf;
+  bool live = false;
+  if (i < ns) {
+    const u32 v = n <= kBatchModeSamples ? i : (u32)(((u64)i * 2654435761ull + 12345u) % n);
+    live = rp[v + 1] > rp[v];
+    r = live ? cc_find(parent, v) : kInf;
+    s_root[i] = r;
+  }
+  __syncthreads();
+  u32 cnt = 0;
+  if (live)
+    for (u32 j = 0; j < ns; ++j) cnt += s_root[j] == r;
+  // largest (count, root) pair; ties go to the larger root, any choice is correct
+  u64 key = live ? ((u64)cnt << 32) | r : 0ull;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const u64 o = __shfl_xor(key, off, kWave);
+    key = o > key ? o : key;
+  }
+  const u32 nlive = (u32)__popcll(__ballot(live));
+  if (lane == 0) {
+    s_best[wid] = key;
+    s_live[wid] = nlive;
+  }
+  __syncthreads();
+  u64 b = 0;
+  u32 tl = 0;
+  for (u32 w = 0; w < (u32)kBW; ++w) {
+    b = s_best[w] > b ? s_best[w] : b;
+    tl += s_live[w];
+  }
+  __syncthreads();  // s_root, s_best and s_live are free again
+  *thin = (u32)(b >> 32) * 10u < tl * 9u;
+  return tl ? (u32)b : kInf;
+}
+
 struct BatchArrays {
   const u32* rowptr_cat;
   const u32* colidx_cat;
@@ -177,20 +245,48 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
     u32* hcnt = A.hcnt_all + rb;
     u32* split = A.split_all + rb;
 
-    // ---- 1. component roots ----
+    // ---- 1. component roots: sampled union-find, smallest-ID roots ----
     for (u32 v = threadIdx.x; v < n; v += kBT) {
       const u32 lo = rp[v], hi = rp[v + 1];
       parent[v] = lo < hi ? min(v, ci[lo]) : v;
     }
     __syncthreads();
-    block_for_each_entry(rp, ci, n, nullptr, [&](u32 u, u32 v, bool act) {
-      if (act && v < u && load_coherent(&parent[u]) != v) cc_union(parent, u, v);
+    for (u32 v = threadIdx.x; v < n; v += kBT) parent[v] = cc_find(parent, v);
+    __syncthreads();
+    batch_sample_links(rp, ci, n, parent, 0);
+    bool thin = false;
+    u32 dom = batch_dominant_root(rp, n, parent, s_mark, s_red, s_tmp, &thin);
+    if (thin) {  // many sampled links lost to races: a second round before the full pass
+      batch_sample_links(rp, ci, n, parent, 2);
+      dom = batch_dominant_root(rp, n, parent, s_mark, s_red, s_tmp, &thin);
+    }
+    // every vertex outside the dominant set joins all its neighbours
+    {
+      const u32 nr = (n + kWave - 1) / kWave * kWave;
+      for (u32 v = threadIdx.x; v < nr; v += kBT) {
+        const bool out = v < n && load_coherent(&parent[v]) != dom && rp[v + 1] > rp[v];
+        const u32 pos = wave_append(&s_cnt, out);
+        if (out) queue[pos] = v;
+      }
+    }
+    __syncthreads();
+    block_for_each_entry(rp, ci, s_cnt, queue, [&](u32 u, u32 v, bool act) {
+      if (act) cc_union(parent, u, v);
     });
     __syncthreads();
     for (u32 v = threadIdx.x; v < n; v += kBT) parent[v] = cc_find(parent, v);
+    if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
 
     // ---- 2. level BFS from every root ----
+    // Graphs of up to kLdsBfsMax vertices keep a visited bitmap in LDS (the intersection
+    // table is free until step 5): a neighbour is claimed by one LDS atomicOr instead of
+    // a global compare-and-swap on its level.
+    const bool lds_bfs = n <= kLdsBfsMax;
+    u32* s_vis = s_table;
+    if (lds_bfs)
+      for (u32 i = threadIdx.x; i < (n + 31) / 32; i += kBT) s_vis[i] = 0;
+    __syncthreads();
     {
       const u32 nr = (n + kWave - 1) / kWave * kWave;
       for (u32 v = threadIdx.x; v < nr; v += kBT) {
@@ -199,6 +295,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const bool root = parent[v] == v;
           level[v] = root ? 0u : kInf;
           push = root && rp[v + 1] > rp[v];
+          if (root && lds_bfs) atomicOr(&s_vis[v >> 5], 1u << (v & 31u));
         }
         const u32 pos = wave_append(&s_qtail, push);
         if (push) queue[pos] = v;
@@ -211,18 +308,33 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
       if (qs == qe) break;
       __syncthreads();
       const u32 next = k + 1;
-      block_for_each_entry(rp, ci, qe - qs, queue + qs, [&](u32 u, u32 v, bool act) {
-        (void)u;
-        bool claimed = false;
-        if (act && load_coherent(&level[v]) == kInf)
-          claimed = atomicCAS(&level[v], kInf, next) == kInf;
-        const u32 pos = wave_append(&s_qtail, claimed);
-        if (claimed) queue[pos] = v;
-      });
+      if (lds_bfs) {
+        block_for_each_entry(rp, ci, qe - qs, queue + qs, [&](u32 u, u32 v, bool act) {
+          (void)u;
+          bool claimed = false;
+          if (act) {
+            const u32 bit = 1u << (v & 31u);
+            claimed = (s_vis[v >> 5] & bit) == 0 && (atomicOr(&s_vis[v >> 5], bit) & bit) == 0;
+          }
+          if (claimed) level[v] = next;
+          const u32 pos = wave_append(&s_qtail, claimed);
+          if (claimed) queue[pos] = v;
+        });
+      } else {
+        block_for_each_entry(rp, ci, qe - qs, queue + qs, [&](u32 u, u32 v, bool act) {
+          (void)u;
+          bool claimed = false;
+          if (act && load_coherent(&level[v]) == kInf)
+            claimed = atomicCAS(&level[v], kInf, next) == kInf;
+          const u32 pos = wave_append(&s_qtail, claimed);
+          if (claimed) queue[pos] = v;
+        });
+      }
       __syncthreads();
       qs = qe;
       ++k;
     }
+    __syncthreads();
 
     // ---- 3. per-vertex info ----
     for (u32 v = threadIdx.x; v < n; v += kBT)
@@ -316,26 +428,37 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
         lane_vertex<false>(rp, cb, A.colidx_cat, vinfo, hcnt, A.hadj_all, v, c, nullptr);
 
     // ---- 5b. wavefront class: 16 wavefront tables in the workgroup table ----
+    // A wavefront claims 64 vertices at once and reads their row bounds, partner counts
+    // and split points in one load per lane; the vertices of the class are then taken
+    // one by one with their row data already in registers.  The staged and streamed rows
+    // come from the level-split rows, whose positions give the level flags.
     {
-      u32 idx = 0, idx_end = 0;
       while (true) {
-        if (idx == idx_end) {
-          u32 c0 = 0;
-          if (lane == 0) c0 = atomicAdd(&s_next, kWaveClaim);
-          idx = __shfl(c0, 0, kWave);
-          idx_end = min(idx + kWaveClaim, n);
+        u32 c0 = 0;
+        if (lane == 0) c0 = atomicAdd(&s_next, (u32)kWave);
+        const u32 base = __shfl(c0, 0, kWave);
+        if (base >= n) break;  // wave-uniform
+        const u32 x = base + lane;
+        WaveMeta mt{0, 0, 0, 0};
+        bool cls = false;
+        if (x < n) {
+          const u32 lo = rp[x], hi = rp[x + 1], np = hcnt[x];
+          cls = np > 0 && hi - lo > prm.lane_max && hi - lo <= prm.wave_max;
+          if (cls) mt = WaveMeta{cb + lo, cb + hi, cb + split[x], np};
         }
-        if (idx >= n) break;
-        const u32 x = idx++;
-        const u32 dx = rp[x + 1] - rp[x];
-        if (hcnt[x] == 0 || dx <= prm.lane_max || dx > prm.wave_max) continue;  // wave-uniform
-        Tally tl{0, 0, 0, 0};
-        wave_vertex<false, VEC>(rp, cb, A.colidx_cat, A.m_total, A.tail4, vinfo, hcnt,
-                                A.hadj_all, nullptr, nullptr, x, WaveMeta{},
-                                s_table + wid * kWaveSlots,
-                                s_pinfo + wid * kWave,
-                                s_qincl + wid * kWave, s_mark + wid * kWave, tl, c, nullptr);
-        tl.fold(c);
+        u64 todo = __ballot(cls);
+        while (todo) {
+          const int b = __ffsll((unsigned long long)todo) - 1;
+          todo &= todo - 1;
+          const WaveMeta mb{(u32)__shfl(mt.bx, b, kWave), (u32)__shfl(mt.ex, b, kWave),
+                            (u32)__shfl(mt.sb, b, kWave), (u32)__shfl(mt.np, b, kWave)};
+          Tally tl{0, 0, 0, 0};
+          wave_vertex<false, true, false, 1, false, true>(
+              rp, cb, A.colidx2_all, A.m_total, A.tail4, vinfo, hcnt, A.hadj_all, nullptr,
+              nullptr, (u32)__shfl(x, b, kWave), mb, s_table + wid * kWaveSlots,
+              s_pinfo + wid * kWave, s_qincl + wid * kWave, s_mark + wid * kWave, tl, c, nullptr);
+          tl.fold(c);
+        }
       }
     }
     __syncthreads();

@@ -55,18 +55,9 @@ __global__ void k_cc_init(const u32* __restrict__ rowptr, const u32* __restrict_
 }
 
 // Sampled links (Afforest, Sutton, Ben-Nun & Barak, IPDPS 2018): every vertex links the
-// current roots of itself and of its two smallest neighbours, which already assembles
-// most of a dominant component.  A link lowers parent[r_hi] to r_lo with one atomicMin
-// (no retry loop): if r_hi had been linked meanwhile, its old link may be dropped, which
-// only leaves two sets unmerged that are truly connected.  Every parent stays within
-// its component, and the links not made here are made by k_cc_finish.
-__device__ __forceinline__ void cc_min_link(u32* parent, u32 a, u32 b) {
-  const u32 ra = load_coherent(&parent[a]), rb = load_coherent(&parent[b]);
-  if (ra == rb) return;
-  const u32 hi = max(ra, rb), lo = min(ra, rb);
-  if (load_coherent(&parent[hi]) > lo) atomicMin(&parent[hi], lo);
-}
-
+// current roots of itself and of its two smallest neighbours (cc_min_link), which
+// already assembles most of a dominant component; the links not made here are made by
+// k_cc_finish.
 __global__ void k_cc_sample(const u32* __restrict__ rowptr, const u32* __restrict__ colidx,
                             u32 n, u32* parent) {
   for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {

@@ -417,6 +417,19 @@ __device__ __forceinline__ void cc_union(u32* parent, u32 a, u32 b) {
   }
 }
 
+// One sampled link (Afforest, Sutton, Ben-Nun & Barak, IPDPS 2018): lowers
+// parent[r_hi] to r_lo for the current parents r of a and b with one atomicMin and no
+// retry loop.  If r_hi had been linked meanwhile, its old link may be dropped, which only
+// leaves two sets unmerged that are truly connected (a later pass over every edge of the
+// vertices outside the dominant set makes the links left out); every parent stays
+// within its component and parent[x] <= x holds throughout.
+__device__ __forceinline__ void cc_min_link(u32* parent, u32 a, u32 b) {
+  const u32 ra = load_coherent(&parent[a]), rb = load_coherent(&parent[b]);
+  if (ra == rb) return;
+  const u32 hi = max(ra, rb), lo = min(ra, rb);
+  if (load_coherent(&parent[hi]) > lo) atomicMin(&parent[hi], lo);
+}
+
 // ---- result counters ----------------------------------------------------------------
 // ctr[slot * kNumCtr + i]: i = 0 c1, 1 c2, 2 t2 (same-level apex with w > max(u, v)),
 // 3 + cls: elements streamed from partner lists, 6 + cls: elements of N(x) staged or

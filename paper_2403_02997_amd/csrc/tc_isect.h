@@ -98,7 +98,12 @@ __device__ __forceinline__ WaveMeta wave_meta(const u32* __restrict__ rowptr,
 // set is built, so their latency overlaps the inserts.  ST (with REC): hits in a
 // record's same-level range (.x .. .y) go to tl.t2, those in its other-level range
 // (.y .. .z) to tl.s, so the two terms of the split (Alg. CETC-Seq-S) come out apart.
-template <bool PV, bool VEC, bool REC = false, int HS = 1, bool ST = false>
+// SR: the full form over the level-split rows (colidx is then colidx2, with 4 readable
+// entries past m): mt holds x's row, its split point (mt.sb, the start of its
+// other-level part) and its partner count, so an entry's level flag is its position in
+// the row (no level gathers); the first 64 partners and their row bounds are loaded
+// before the staged set is built.
+template <bool PV, bool VEC, bool REC = false, int HS = 1, bool ST = false, bool SR = false>
 __device__ __forceinline__ void wave_vertex(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
@@ -108,16 +113,25 @@ __device__ __forceinline__ void wave_vertex(
     u64* __restrict__ tri) {
   static_assert(!(REC && PV), "per-vertex counts use the full form");
   static_assert(!ST || REC, "split statistics come from the partner records");
+  static_assert(!(SR && (REC || PV || HS != 1)), "split rows: full form over plain partner lists");
+  constexpr bool MT = REC || SR;   // row data from mt
   constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
   const u32 lane = lane_id();
   const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
-  const u32 bx = REC ? mt.bx : cb + rowptr[x], ex = REC ? mt.ex : cb + rowptr[x + 1];
+  const u32 bx = MT ? mt.bx : cb + rowptr[x], ex = MT ? mt.ex : cb + rowptr[x + 1];
   const u32 sb = REC ? mt.sb : bx;  // first staged entry
+  const u32 sp = SR ? mt.sb : 0u;   // SR: first other-level entry of x's row
   const u32 dx = ex - sb;
-  const u32 hs = bx, np = REC ? mt.np : hcnt[x];  // H+(x) sits in place of N(x)
-  const u32 px = REC ? 0u : vinfo[x] & 0x80u;
+  const u32 hs = bx, np = MT ? mt.np : hcnt[x];  // H+(x) sits in place of N(x)
+  const u32 px = MT ? 0u : vinfo[x] & 0x80u;
   uint4 r0 = make_uint4(0, 0, 0, 0);  // REC: the first batch of partner records
   if (REC && lane < np) r0 = hrec[hs + lane];
+  u32 y0 = 0, lo0 = 0, hi0 = 0;       // SR: the first batch of partners and their rows
+  if (SR && lane < np) {
+    y0 = hadj[hs + lane];
+    lo0 = cb + rowptr[y0];
+    hi0 = cb + rowptr[y0 + 1];
+  }
   const u32 mask = bucket_mask(dx, kWaveSlots);
   c.staged += lane == 0 ? dx : 0;
   for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
@@ -126,6 +140,8 @@ __device__ __forceinline__ void wave_vertex(
     const u32 w = colidx[sb + i];
     if (REC) {
       hash_insert_key(table, mask, w, w);
+    } else if (SR) {
+      hash_insert(table, mask, w, sb + i < sp ? 1u : 0u);
     } else {
       const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
       hash_insert(table, mask, w, same);
@@ -141,6 +157,10 @@ __device__ __forceinline__ void wave_vertex(
         y = ST ? r.y : r.w;  // the pruned form never reads y; ST keeps the range split there
         lo = r.x;
         hi = r.z;
+      } else if (SR && pb == 0) {
+        y = y0;
+        lo = lo0;
+        hi = hi0;
       } else {
         y = hadj[(size_t)(hs + p) * HS];
         lo = cb + rowptr[y];
@@ -189,10 +209,10 @@ __device__ __forceinline__ void wave_vertex(
         addr[u] = (inf[u].x + q) * NE;
         if (VEC) {
           // one unconditional 16-byte load: a quad that would run past the end of colidx
-          // (or a dead lane) reads the padded copy of the last partial quad; REC rows
-          // (colidx2) have 4 readable entries past m, so a quad only clamps its address
-          const u32* src = REC ? colidx + min(addr[u], (m - 1) & ~3u)
-                               : (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
+          // (or a dead lane) reads the padded copy of the last partial quad; REC and SR
+          // rows (colidx2) have 4 readable entries past m, so a quad only clamps its address
+          const u32* src = MT ? colidx + min(addr[u], (m - 1) & ~3u)
+                              : (live[u] && addr[u] + 3 < m) ? colidx + addr[u] : tail4;
           const uint4 v = *reinterpret_cast<const uint4*>(src);
           e[u][0] = v.x;
           e[u][NE > 1 ? 1 : 0] = v.y;
@@ -280,8 +300,10 @@ constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
 // PAD: the streamed array has at least 4 readable entries past its m counted ones, so
 // every live quad is read in place and dead lanes only clamp their address.
 // QU windows of 64 quads per wavefront are loaded before probing.
+// SPOS (kPrunedOne): the staged keys are a level-split row and px is the position in ga
+// of its first other-level entry, so a key's level flag is its position (no gathers).
 template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false, int QU = kQuadUnroll,
-          bool ST = false>
+          bool ST = false, bool SPOS = false>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
@@ -290,6 +312,7 @@ __device__ __forceinline__ void block_pass(
   const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   static_assert(!BM || MODE == kOther || MODE == kSame, "bitmaps hold membership only");
   static_assert(!ST || MODE == kMember, "only the one-chunk member pass mixes both kinds");
+  static_assert(!SPOS || MODE == kPrunedOne, "position flags: one chunk of a split row");
   constexpr bool MEMBER = MODE == kOther || MODE == kSame || MODE == kMember;
   u32& hits = MODE == kSame ? tl.t2 : tl.s;  // same-level apexes above both ends: t2
   const u32 glen = ge - gs;
@@ -342,7 +365,8 @@ __device__ __forceinline__ void block_pass(
         if (MEMBER) {
           hash_insert_key(sh.table, mask, w, w);
         } else {
-          const u32 same = (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
+          const bool same = SPOS ? c0 + i < px
+                                 : (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
           hash_insert(sh.table, mask, w, same ? 1u : 0u);
         }
       }
@@ -461,7 +485,8 @@ __device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32
 // One work item: staged vertex x, partner segment `seg` (all threads call it together).
 // PRUNED = false: one kFull pass over colidx.  PRUNED = true: the level-split rows
 // colidx2 (split[v] = local start of v's other-level neighbours), one kPrunedOne pass
-// when N(x) fits one chunk, else a kOther and a kSame pass.  m / m2 bound the quad loads
+// when N(x) fits one chunk (x's split row staged, its level flags by position), else a
+// kOther and a kSame pass.  m / m2 bound the quad loads
 // from colidx / colidx2 (beyond them the padded copies tail4 / tail4b are read).
 template <bool PV, bool VEC, bool PRUNED, int HS = 1, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item(
@@ -491,12 +516,11 @@ __device__ __forceinline__ void block_item(
       ys = cb + split[y];
       lb = lower_bound_g(colidx2, yr, ys, max(x, y) + 1u);  // same-level part above max
     }
+    const u32 sx = cb + split[x];
     if (dx <= prm.chunk) {
-      block_pass<false, VEC, kPrunedOne, false, false, QU>(colidx2, m2, tail4b, colidx, bx, ex,
-                                                           vinfo, x, px, y, pn, lb, ye, prm, sh,
-                                                           tl, c, tri);
+      block_pass<false, VEC, kPrunedOne, false, false, QU, false, true>(
+          colidx2, m2, tail4b, colidx2, bx, ex, vinfo, x, sx, y, pn, lb, ye, prm, sh, tl, c, tri);
     } else {
-      const u32 sx = cb + split[x];
       const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
       // bitmap windows where they need fewer passes than hash chunks
       if (use_bitmap(colidx2, sx, ex, prm.chunk))
