@@ -29,7 +29,6 @@ namespace tc {
 constexpr int kBT = kBigThreads;   // threads per workgroup
 constexpr int kBW = kBT / kWave;   // wavefronts per workgroup
 constexpr u32 kBuckets = 40;       // planner cost classes
-constexpr u32 kLaneDeg = 32;       // lists up to this length are walked per lane
 
 struct BatchCtl {
   u32 next;
@@ -76,8 +75,14 @@ __global__ void __launch_bounds__(256) k_batch_prepare(const int64_t* __restrict
 
 // ---- workgroup-wide traversal of adjacency lists -----------------------------------------
 // Calls f(u, v, active) for every v in N(u), u = list[i] (or i when list is null),
-// i < count.  Short lists are walked one per lane in lockstep, long lists by the whole
-// wavefront; f is reached by all lanes of a wavefront together (for wave_append).
+// i < count.  Each wavefront takes 64 list entries and walks the concatenation of their
+// adjacency lists, 64 lanes wide and kTravU positions per lane in flight: the owner of
+// position k is the first lane whose inclusive degree prefix exceeds k (a binary search
+// over the lanes' prefixes with cross-lane reads), so short lists cost no extra round
+// trips and long ones are read coalesced.  f is reached by all lanes of a wavefront
+// together (for wave_append).
+constexpr u32 kTravU = 4;
+
 template <typename F>
 __device__ __forceinline__ void block_for_each_entry(const u32* __restrict__ rp,
                                                      const u32* __restrict__ ci, u32 count,
@@ -91,27 +96,31 @@ __device__ __forceinline__ void block_for_each_entry(const u32* __restrict__ rp,
       lo = rp[u];
       d = rp[u + 1] - lo;
     }
-    const bool big = d > kLaneDeg;
-    const u32 dl = big ? 0 : d;
-    u32 dmax = dl;
+    const u32 incl = wave_incl_scan(d);
+    const u32 total = __shfl(incl, kWave - 1, kWave);
+    const u32 base = lo - (incl - d);  // entry of position k of this lane's list: base + k
+    for (u32 k0 = 0; k0 < total; k0 += kWave * kTravU) {
+      u32 vv[kTravU], uu[kTravU];
+      bool act[kTravU];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, (u32)__shfl_xor(dmax, off, kWave));
-    for (u32 j = 0; j < dmax; ++j) {
-      const bool act = j < dl;
-      const u32 v = act ? ci[lo + j] : 0u;
-      f(u, v, act);
-    }
-    u64 bigmask = __ballot(big);
-    while (bigmask) {
-      const int b = __ffsll((unsigned long long)bigmask) - 1;
-      bigmask &= bigmask - 1;
-      const u32 bu = __shfl(u, b, kWave), blo = __shfl(lo, b, kWave), bd = __shfl(d, b, kWave);
-      for (u32 j0 = 0; j0 < bd; j0 += kWave) {
-        const u32 j = j0 + lane;
-        const bool act = j < bd;
-        const u32 v = act ? ci[blo + j] : 0u;
-        f(bu, v, act);
+      for (u32 t = 0; t < kTravU; ++t) {
+        const u32 k = k0 + t * kWave + lane;
+        act[t] = k < total;
+        // first lane j with incl_j > k (lanes past the total search harmlessly)
+        u32 a = 0, b = kWave - 1;
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+          const u32 mid = (a + b) >> 1;
+          const u32 im = (u32)__shfl(incl, (int)mid, kWave);
+          if (im > k) b = mid;
+          else a = mid + 1;
+        }
+        uu[t] = (u32)__shfl(u, (int)a, kWave);
+        const u32 eb = (u32)__shfl(base, (int)a, kWave);
+        vv[t] = act[t] ? ci[eb + k] : 0u;
       }
+#pragma unroll
+      for (u32 t = 0; t < kTravU; ++t) f(uu[t], vv[t], act[t]);
     }
   }
 }
@@ -351,10 +360,14 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           d = rp[v + 1] - lo;
           vx = vinfo[v];
         }
-        if (v < n && d <= kSplitLane) {
+        const bool short_row = v < n && d <= kSplitLane;
+        bool more[kSplitLane / 8];
+#pragma unroll
+        for (u32 b = 0; b < kSplitLane / 8; ++b) more[b] = __ballot(short_row && d > b * 8) != 0;
+        if (short_row) {
           u32 ns, nh;
-          split_short_row(A.colidx_cat, vinfo, v, vx, cb + lo, d, A.colidx2_all, A.hadj_all, &ns,
-                          &nh);
+          split_short_row(A.colidx_cat, vinfo, v, vx, cb + lo, d, more, A.colidx2_all,
+                          A.hadj_all, &ns, &nh);
           split[v] = lo + ns;
           hcnt[v] = nh;
         }
@@ -367,14 +380,20 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           mm &= mm - 1;
           const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
           const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
-          u32 ns = 0, no = 0, nh = 0;
-          for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
-            split_steps<true>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, 0, 0,
-                              A.colidx2_all, A.hadj_all, ns, no, nh);
-          u32 cs = 0, co = 0, ch = 0;
-          for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
-            split_steps<false>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, ns, 0,
-                               A.colidx2_all, A.hadj_all, cs, co, ch);
+          u32 ns = 0, nh = 0;
+          if (bd <= kSplitReg) {
+            split_wave_row(A.colidx_cat, vinfo, bv, bvx, cb + blo, bd, A.colidx2_all, A.hadj_all,
+                           &ns, &nh);
+          } else {
+            u32 no = 0;
+            for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
+              split_steps<true>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, 0, 0,
+                                A.colidx2_all, A.hadj_all, ns, no, nh);
+            u32 cs = 0, co = 0, ch = 0;
+            for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
+              split_steps<false>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, ns, 0,
+                                 A.colidx2_all, A.hadj_all, cs, co, ch);
+          }
           if ((int)lane == b) {
             split[bv] = blo + ns;
             hcnt[bv] = nh;

@@ -190,9 +190,7 @@ __device__ __forceinline__ void split_lane_row_reg(const u32* __restrict__ colid
 }
 
 // Entries c0 .. min(c0 + kSplitReg, cend) of the row of v (colidx[lo .. lo + d)), one
-// wavefront, lane l holding entries c0 + 64 u + l.
-constexpr u32 kSplitRegU = 16;
-constexpr u32 kSplitReg = kSplitRegU * kWave;
+// wavefront, lane l holding entries c0 + 64 u + l (kSplitReg = 16 entries per lane).
 
 struct ChunkRegs {
   u32 w[kSplitRegU];

@@ -484,9 +484,11 @@ __device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32
 
 // One work item: staged vertex x, partner segment `seg` (all threads call it together).
 // PRUNED = false: one kFull pass over colidx.  PRUNED = true: the level-split rows
-// colidx2 (split[v] = local start of v's other-level neighbours), one kPrunedOne pass
-// when N(x) fits one chunk (x's split row staged, its level flags by position), else a
-// kOther and a kSame pass.  m / m2 bound the quad loads
+// colidx2 (split[v] = local start of v's other-level neighbours): when N(x) fits one
+// chunk, one kPrunedOne pass of x's split row (level flags by position) against each
+// partner's same-level entries above max(x, y) and its other-level ones, else a kOther
+// and a kSame pass over the same ranges.  (Streaming the partners' whole rows instead,
+// with the apex rule per hit, saves the searches but measured slower.)  m / m2 bound the quad loads
 // from colidx / colidx2 (beyond them the padded copies tail4 / tail4b are read).
 template <bool PV, bool VEC, bool PRUNED, int HS = 1, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item(
@@ -518,7 +520,7 @@ __device__ __forceinline__ void block_item(
     }
     const u32 sx = cb + split[x];
     if (dx <= prm.chunk) {
-      block_pass<false, VEC, kPrunedOne, false, false, QU, false, true>(
+      block_pass<false, true, kPrunedOne, false, false, QU, false, true>(
           colidx2, m2, tail4b, colidx2, bx, ex, vinfo, x, sx, y, pn, lb, ye, prm, sh, tl, c, tri);
     } else {
       const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
@@ -627,45 +629,120 @@ __device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
   }
 }
 
-// A row of at most kSplitLane entries, by one lane (four entries per step keep four
-// independent gathers in flight).  Returns the number of same-level entries in *ns and
-// of partners in *nh.
+// A row of at most kSplitLane entries, by one lane, held in registers: every entry is
+// loaded before the first vinfo gather and the same-level and partner flags are kept as
+// bit masks, so the row costs one load and one gather round trip.  more[b]
+// (wavefront-uniform) says whether any lane's row is longer than 8 b entries; blocks of
+// 8 past every lane's row are skipped.  Returns the number of same-level entries in *ns
+// and of partners in *nh.
 __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
                                                 const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
-                                                u32 lo, u32 d, u32* __restrict__ colidx2,
+                                                u32 lo, u32 d, const bool* more,
+                                                u32* __restrict__ colidx2,
                                                 u32* __restrict__ hadj, u32* ns_out,
                                                 u32* nh_out) {
-  u32 ns = 0;
-  for (u32 j = 0; j < d; j += 4) {
-    u32 w[4], vw[4];
+  constexpr u32 B = 8, NB = kSplitLane / B;
+  static_assert(kSplitLane <= 32, "flags are one 32-bit mask per lane");
+  u32 w[kSplitLane];
 #pragma unroll
-    for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b]) {
 #pragma unroll
-    for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
-#pragma unroll
-    for (u32 i = 0; i < 4; ++i) ns += (j + i < d) && ((vw[i] ^ vx) & 0x80u) == 0;
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        w[j] = j < d ? colidx[lo + j] : v;
+      }
+    }
   }
-  u32 is = lo, io = lo + ns, ih = lo;
-  for (u32 j = 0; j < d; j += 4) {
-    u32 w[4], vw[4];
+  u32 sm = 0, pm = 0;  // same level, partner of v
 #pragma unroll
-    for (u32 i = 0; i < 4; ++i) w[i] = j + i < d ? colidx[lo + j + i] : v;
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b]) {
 #pragma unroll
-    for (u32 i = 0; i < 4; ++i) vw[i] = vinfo[w[i]];
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        const u32 vw = vinfo[w[j]];
+        const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
+        sm |= (same ? 1u : 0u) << j;
+        pm |= (same && key_less(vw & 127u, w[j], vx & 127u, v) ? 1u : 0u) << j;
+      }
+    }
+  }
+  const u32 ns = (u32)__popc(sm);
 #pragma unroll
-    for (u32 i = 0; i < 4; ++i) {
-      if (j + i < d) {
-        if (((vw[i] ^ vx) & 0x80u) == 0) {
-          colidx2[is++] = w[i];
-          if (key_less(vw[i] & 127u, w[i], vx & 127u, v)) hadj[ih++] = w[i];
-        } else {
-          colidx2[io++] = w[i];
+  for (u32 b = 0; b < NB; ++b) {
+    if (more[b]) {
+#pragma unroll
+      for (u32 i = 0; i < B; ++i) {
+        const u32 j = b * B + i;
+        if (j < d) {
+          const u32 below = (1u << j) - 1u;
+          const u32 rs = (u32)__popc(sm & below);
+          if ((sm >> j) & 1u) colidx2[lo + rs] = w[j];
+          else colidx2[lo + ns + (j - rs)] = w[j];
+          if ((pm >> j) & 1u) hadj[lo + (u32)__popc(pm & below)] = w[j];
         }
       }
     }
   }
   *ns_out = ns;
-  *nh_out = ih - lo;
+  *nh_out = (u32)__popc(pm);
+}
+
+// A row of kSplitLane < d <= kSplitReg entries by one wavefront, held in registers (lane l
+// holds entries 64 u + l): one load and one gather round trip, then the ballot-ranked
+// writes.  Returns the number of same-level entries in *ns and of partners in *nh.
+constexpr u32 kSplitRegU = 16;
+constexpr u32 kSplitReg = kSplitRegU * kWave;
+
+__device__ __forceinline__ void split_wave_row(const u32* __restrict__ colidx,
+                                               const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
+                                               u32 lo, u32 d, u32* __restrict__ colidx2,
+                                               u32* __restrict__ hadj, u32* ns_out,
+                                               u32* nh_out) {
+  constexpr u32 U = kSplitRegU;
+  const u32 lane = lane_id();
+  const u32 nu = (d + kWave - 1) / kWave;  // wavefront-uniform
+  u32 w[U];
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      const u32 j = u * kWave + lane;
+      w[u] = j < d ? colidx[lo + j] : v;
+    }
+  }
+  u32 sm = 0, pm = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      const u32 j = u * kWave + lane;
+      const u32 vw = vinfo[w[u]];
+      const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
+      sm |= (same ? 1u : 0u) << u;
+      pm |= (same && key_less(vw & 127u, w[u], vx & 127u, v) ? 1u : 0u) << u;
+    }
+  }
+  u32 ns = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u)
+    if (u < nu) ns += (u32)__popcll(__ballot((sm >> u) & 1u));
+  u32 cs = 0, co = 0, ch = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      const bool in = u * kWave + lane < d;
+      const bool same = (sm >> u) & 1u, part = (pm >> u) & 1u;
+      const u64 ms = __ballot(same), mo = __ballot(in && !same), mh = __ballot(part);
+      if (same) colidx2[lo + cs + mask_rank(ms)] = w[u];
+      else if (in) colidx2[lo + ns + co + mask_rank(mo)] = w[u];
+      if (part) hadj[lo + ch + mask_rank(mh)] = w[u];
+      cs += (u32)__popcll(ms);
+      co += (u32)__popcll(mo);
+      ch += (u32)__popcll(mh);
+    }
+  }
+  *ns_out = ns;
+  *nh_out = ch;
 }
 
 }  // namespace tc
