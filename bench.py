@@ -79,6 +79,7 @@ WORKLOAD_TEXT = {
     "rmat22": "R-MAT scale 22, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1001",
     "grid4096": "triangulated 4096x4096 grid, 1% of edges deleted, seed 1002",
     "er22": "Erdos-Renyi G(n=2^22, average degree 32), seed 1003",
+    "er14_d256": "Erdos-Renyi G(n=2^14, average degree 256), seed 1004",
     "batch4096": "4096 graphs: half R-MAT (scale 8-16, edge factor 8-32), half Erdos-Renyi "
                  "(n log-uniform in [2^8, 2^16], average degree 4-64), seed 1003",
     "serve": "Poisson request stream: 90% R-MAT scale 12-18, 10% R-MAT scale 22-24, one "
@@ -338,6 +339,7 @@ def bench_single(args, tcm, torch):
         T = tcm.tc_count(rp, ci)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    forward = tcm.tc_last_call_info()["forward"]
     elapsed = t1 - t0
     log(f"[bench] timed {args.steps} steps: {elapsed * 1e3 / args.steps:.3f} ms/step")
     # Step breakdown and roofline: further calls with step timing on.  The library then
@@ -357,7 +359,8 @@ def bench_single(args, tcm, torch):
     level_np = level.cpu().numpy().view(np.uint32)
     params = tcm.tc_get_isect_params()
     hubs = tcm.tc_get_hub_params()
-    cb = class_bytes(g, level_np, params, hubs)
+    # the forward ordering runs the same kernels with every vertex on one level
+    cb = class_bytes(g, np.zeros_like(level_np) if forward else level_np, params, hubs)
     steps_ms = {k: v / max(calls, 1) for k, v in prof.items()}
     isect = {k: steps_ms.get(k, 0.0) for k in KERNEL_OF_STEP}
     dom = max(isect, key=isect.get)
@@ -396,6 +399,8 @@ def bench_single(args, tcm, torch):
                    "covering_ratio": round(stats.cover_edges / max(g.num_edges, 1), 4),
                    "bfs_depth": stats.depth, "components": stats.num_roots,
                    "isect_params": list(params), "hub_params": list(hubs),
+                   "forward_threshold": tcm.tc_get_forward_threshold(),
+                   "forward_ordering": bool(forward),
                    "hubs": int(hub_set(g.degrees(), *hubs).sum()),
                    "autotuned": tuned is not None},
         "triangles_per_s": T * args.steps / elapsed,
@@ -881,6 +886,9 @@ def main():
                     help="intersection class parameters (tc_set_isect_params) for this run")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="step-timed calls after the timed steps (step breakdown, roofline)")
+    ap.add_argument("--forward-threshold", type=float, default=None,
+                    help="CETC-Seq-FE covering-ratio threshold (library default 0.7; "
+                         "0 always counts in the forward ordering, 2 never)")
     ap.add_argument("--hubs", default="", metavar="MAX_HUBS,MIN_DEGREE",
                     help="hub pass parameters (tc_set_hub_params) for this run; 0,0 turns it off")
     ap.add_argument("--autotune", action="store_true",
@@ -927,6 +935,8 @@ def main():
         tcm.tc_set_isect_params(*[int(v) for v in args.isect.split(",")])
     if args.hubs:
         tcm.tc_set_hub_params(*[int(v) for v in args.hubs.split(",")])
+    if args.forward_threshold is not None:
+        tcm.tc_set_forward_threshold(args.forward_threshold)
     if args.workload == "batch4096":
         out = bench_batch(args, tcm, torch)
         torch.cuda.empty_cache()

@@ -33,7 +33,7 @@
  * All entry points are stream-ordered on `stream` (0 = the null stream).
  * Thread safety: calls on different streams may run concurrently; the library keeps no
  * mutable global state besides a per-device cache of the device properties and the
- * tuning set by tc_set_isect_params and tc_set_hub_params.
+ * tuning set by tc_set_isect_params, tc_set_hub_params and tc_set_forward_threshold.
  *
  * Streams: on graphs of at least 2^22 stored entries, tc_count runs its wavefront-class
  * intersections and its hub count on a second stream that it creates for the call
@@ -87,6 +87,9 @@ typedef struct {
  * and synchronises `stream`.  n == 0 or m == 0 gives T = 0 without a launch.
  * For cover edges staged as long lists, a same-level apex w <= max(u, v) can never
  * count, so those list entries are skipped: T = c1 + t2 is computed, c2 is not.
+ * When the covering ratio |S| / |E| reaches the forward threshold (0.7 by default, see
+ * tc_set_forward_threshold) the count runs with every vertex on one level instead
+ * (CETC-Seq-FE's switch to the forward algorithm).
  * Returns TC_ERR_INVALID_ARG for null pointers (when m > 0) or a null `count`,
  * TC_ERR_TOO_LARGE for n >= 2^30 or m > 2^32 - 2^20, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
@@ -322,6 +325,24 @@ int tc_get_isect_params(uint32_t* out4);
  * work item (at most n + m / 1024 items).
  */
 int tc_set_hub_params(uint32_t max_hubs, uint32_t min_degree);
+
+/*
+ * tc_set_forward_threshold — the switch of CETC-Seq-FE (Section 4.3, Alg. CETC-Seq-FE).
+ * After the BFS and the extraction, tc_count has the covering ratio c = |S| / |E|
+ * (|E| = m / 2).  When c >= threshold it counts again with every vertex on one level:
+ * every edge is then a cover edge and the apex rule keeps exactly the apexes above both
+ * endpoints, so the same kernels run the ID-ordered forward algorithm (Alg. TC_forward
+ * with the hashed intersections of Alg. TC_forward-hashed), which the paper picks for
+ * graphs whose covering ratio leaves little to skip.  T is the same either way.
+ * Default 0.7, the paper's value.  A threshold above 1 never switches, 0 always does.
+ * Only the counting call switches (tc_count, tc_count_ex without statistics, the
+ * server's single-graph paths); statistics, per-vertex counts, tc_count_split and the
+ * batch keep the BFS levels.  Set it while no count is running.  A negative or NaN
+ * threshold gives TC_ERR_INVALID_ARG.
+ */
+int tc_set_forward_threshold(double threshold);
+/* Current threshold. */
+double tc_get_forward_threshold(void);
 /* Current setting as {max_hubs, min_degree} into the HOST array out2[2]. */
 int tc_get_hub_params(uint32_t* out2);
 
@@ -340,7 +361,9 @@ typedef struct {
   uint32_t hub_items;       /* hub-pass work items                                   */
   uint32_t side_stream;     /* 1: the wavefront class and hub count ran on a second  */
                             /*    stream beside the workgroup class                  */
-  uint32_t reserved;
+  uint32_t forward;         /* 1: c >= the forward threshold, so the count ran with  */
+                            /*    every vertex on one level (the other fields then   */
+                            /*    describe that run; cover_edges stays the BFS |S|)  */
 } tc_call_info;
 int tc_last_call_info(tc_call_info* out);
 

@@ -24,11 +24,13 @@ from .tc import (  # noqa: F401
     tc_count_per_vertex,
     tc_count_split,
     tc_local_clustering,
+    tc_get_forward_threshold,
     tc_get_hub_params,
     tc_get_isect_params,
     tc_last_call_info,
     tc_profile_enable,
     tc_profile_read,
+    tc_set_forward_threshold,
     tc_set_hub_params,
     tc_set_isect_params,
     tc_validate_csr,

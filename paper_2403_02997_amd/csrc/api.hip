@@ -192,6 +192,10 @@ constexpr u64 kHubEntriesPerDegree = 1024;
 u32 g_hub_max = kDefaultHubs;
 u32 g_hub_min_degree = kDefaultHubDegree;
 
+// CETC-Seq-FE's covering-ratio threshold (the paper's experiments use 0.7).
+constexpr double kDefaultForwardThreshold = 0.7;
+double g_fe_threshold = kDefaultForwardThreshold;
+
 struct RunOut {
   u64 c[kNumCtr];  // see kNumCtr: c1, c2, t2, streamed[3], staged[3]
   u64 cover_edges;
@@ -410,32 +414,52 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     }
   }
   timer.mark();
-  launch_vinfo(rowptr, level, n, vinfo, hcur, hub_on ? chist : nullptr, hp.min_class, s);
-  if (hub_on) launch_hub_select(vinfo, n, chist, hp, hubidx, hublist, plan, s);
-
-  // ---- a3: cover-edge extraction ----
-  // the BFS queues are free again: q1 lists the long rows
+  // ---- a3: cover-edge extraction and planning ----
+  // level_par = nullptr puts every vertex on one level (the forward ordering below)
   const HubView hv{&plan->hub_lim, hubidx, hy, hitems, &plan->num_hub_items, (u32)hub_cap};
-  launch_split_rows(rowptr, colidx, vinfo, n, m, colidx2, split, sabove, hcnt, hcur, hrec, q1,
-                    &plan->num_long, hv, s);
-  timer.mark();
-  launch_plan(rowptr, hcnt, hcur, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
-  launch_scan(bitems, bitems, n, scan_tmp, s);
-  // padded last quads of both rows arrays, queued before the host waits for the plan
-  launch_tail4(colidx, m, tail4, s);
-  launch_tail4(colidx2, m, tail4b, s);
-  TC_LAUNCHED();
   u32 h_items = 0;
   Plan h_plan;
-  TC_HIP(hipMemcpyAsync(&h_items, bitems + n, sizeof(u32), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipMemcpyAsync(&h_plan, plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  // a graph that is not symmetric can leave partner records unwritten: stop before
-  // any intersection reads them
-  if (h_plan.bad_records) return TC_ERR_INVALID_GRAPH;
-  const u32 h_ns = h_plan.num_cover;
-  if (h_ns > max_s) return TC_ERR_INTERNAL;
-  if (h_plan.num_hubs > hp.max_hubs || h_plan.num_hub_items > hub_cap) return TC_ERR_INTERNAL;
+  auto extract = [&](const u32* level_par) -> int {
+    launch_vinfo(rowptr, level_par, n, vinfo, hcur, hub_on ? chist : nullptr, hp.min_class, s);
+    if (hub_on) launch_hub_select(vinfo, n, chist, hp, hubidx, hublist, plan, s);
+    // the BFS queues are free again: q1 lists the long rows
+    launch_split_rows(rowptr, colidx, vinfo, n, m, colidx2, split, sabove, hcnt, hcur, hrec, q1,
+                      &plan->num_long, hv, s);
+    if (level_par) timer.mark();  // a second extraction is timed as planning
+    launch_plan(rowptr, hcnt, hcur, n, prm, lane_x, wave_x, block_x, bitems, plan, s);
+    launch_scan(bitems, bitems, n, scan_tmp, s);
+    // padded last quads of both rows arrays, queued before the host waits for the plan
+    launch_tail4(colidx, m, tail4, s);
+    launch_tail4(colidx2, m, tail4b, s);
+    TC_LAUNCHED();
+    TC_HIP(hipMemcpyAsync(&h_items, bitems + n, sizeof(u32), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(&h_plan, plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    // a graph that is not symmetric can leave partner records unwritten: stop before
+    // any intersection reads them
+    if (h_plan.bad_records) return TC_ERR_INVALID_GRAPH;
+    if (h_plan.num_cover > max_s) return TC_ERR_INTERNAL;
+    if (h_plan.num_hubs > hp.max_hubs || h_plan.num_hub_items > hub_cap) return TC_ERR_INTERNAL;
+    return TC_OK;
+  };
+  rc = extract(level);
+  if (rc) return rc;
+  const u32 h_ns = h_plan.num_cover;  // |S| under the BFS levels
+  // CETC-Seq-FE (Alg. 11): with a covering ratio c = |S| / |E| at or above the threshold,
+  // count by the forward algorithm instead.  With every vertex on one level every edge
+  // is a cover edge and the apex rule keeps exactly the apexes above both endpoints, so
+  // the same kernels then run the ID-ordered forward count (Alg. 5 with Alg. 6's hashed
+  // intersections).  The first extraction is the computation of c; the counting call
+  // only (per-vertex counts and the statistics keep the BFS levels).
+  const bool forward = pruned && !tri && !split_stats && m > 0 &&
+                       (double)h_ns >= g_fe_threshold * (double)(m / 2);
+  if (forward) {
+    TC_HIP(hipMemsetAsync(plan, 0, sizeof(Plan), s));
+    TC_HIP(hipMemsetAsync(chist, 0, sizeof(u32) * 128, s));
+    TC_HIP(hipMemsetAsync(bitems, 0, sizeof(u32) * ((size_t)n + 1), s));
+    rc = extract(nullptr);
+    if (rc) return rc;
+  }
 
   // ---- a4: intersections ----
   DevAlloc items_mem;
@@ -514,6 +538,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   info.hubs = hubs ? h_plan.num_hubs : 0u;
   info.hub_items = hubs ? h_plan.num_hub_items : 0u;
   info.side_stream = sw != s ? 1u : 0u;
+  info.forward = forward ? 1u : 0u;
   t_last_info = info;
   return TC_OK;
 }
@@ -720,6 +745,14 @@ int tc_set_hub_params(uint32_t max_hubs, uint32_t min_degree) {
   g_hub_min_degree = min_degree;
   return TC_OK;
 }
+
+int tc_set_forward_threshold(double threshold) {
+  if (!(threshold >= 0.0) || threshold != threshold || threshold > 1e300) return TC_ERR_INVALID_ARG;
+  g_fe_threshold = threshold;
+  return TC_OK;
+}
+
+double tc_get_forward_threshold(void) { return g_fe_threshold; }
 
 int tc_get_hub_params(uint32_t* out2) {
   if (!out2) return TC_ERR_INVALID_ARG;

@@ -201,7 +201,8 @@ __global__ void __launch_bounds__(256) k_vinfo(const u32* __restrict__ rowptr,
     const u32 lo = rowptr[v];
     const u32 d = rowptr[v + 1] - lo;
     const u32 c = degree_class(d);
-    vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | c);
+    const u32 par = level ? level[v] & 1u : 0u;  // no levels: every vertex on one level
+    vinfo[v] = (uint8_t)((par << 7) | c);
     hcur[v] = lo;
     if (class_hist && c >= hist_min) atomicAdd(&s_hist[c], 1u);
   }

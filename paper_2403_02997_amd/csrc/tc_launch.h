@@ -92,6 +92,7 @@ void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n,
 // vinfo[v] = (L(v) mod 2) << 7 | degree class; hcur[v] = rowptr[v] (the record cursors).
 // class_hist (128 words, zeroed; may be null): vertices per degree class, for the
 // classes >= hist_min (the others stay 0).
+// level = nullptr: every vertex gets parity 0 (all on one level).
 void launch_vinfo(const u32* rowptr, const u32* level, u32 n, uint8_t* vinfo, u32* hcur,
                   u32* class_hist, u32 hist_min, hipStream_t s);
 // Exclusive scan of in[0..count) into out[0..count] (out[count] = total); in may == out.

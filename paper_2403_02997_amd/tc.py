@@ -49,6 +49,8 @@ EXPORTS = (
     "tc_set_hub_params",
     "tc_get_hub_params",
     "tc_last_call_info",
+    "tc_set_forward_threshold",
+    "tc_get_forward_threshold",
     "tc_profile_enable",
     "tc_profile_read",
     "tc_profile_step_name",
@@ -103,7 +105,7 @@ class _CallInfo(ctypes.Structure):
         ("hubs", ctypes.c_uint32),
         ("hub_items", ctypes.c_uint32),
         ("side_stream", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("forward", ctypes.c_uint32),
     ]
 
 
@@ -188,6 +190,10 @@ def load() -> ctypes.CDLL:
     lib.tc_get_isect_params.restype = i
     lib.tc_last_call_info.argtypes = [ctypes.POINTER(_CallInfo)]
     lib.tc_last_call_info.restype = i
+    lib.tc_set_forward_threshold.argtypes = [ctypes.c_double]
+    lib.tc_set_forward_threshold.restype = i
+    lib.tc_get_forward_threshold.argtypes = []
+    lib.tc_get_forward_threshold.restype = ctypes.c_double
     lib.tc_set_hub_params.argtypes = [u32, u32]
     lib.tc_set_hub_params.restype = i
     lib.tc_get_hub_params.argtypes = [ctypes.POINTER(u32)]
@@ -410,8 +416,16 @@ def tc_last_call_info() -> dict:
     """How this thread's last single-graph call divided its work (tc_last_call_info)."""
     info = _CallInfo()
     _check(load().tc_last_call_info(ctypes.byref(info)), "tc_last_call_info")
-    return {name: int(getattr(info, name)) for name, _ in _CallInfo._fields_
-            if name != "reserved"}
+    return {name: int(getattr(info, name)) for name, _ in _CallInfo._fields_}
+
+
+def tc_set_forward_threshold(threshold: float) -> None:
+    """CETC-Seq-FE's covering-ratio threshold (default 0.7; > 1 never switches)."""
+    _check(load().tc_set_forward_threshold(float(threshold)), "tc_set_forward_threshold")
+
+
+def tc_get_forward_threshold() -> float:
+    return float(load().tc_get_forward_threshold())
 
 
 def tc_set_hub_params(max_hubs: int, min_degree: int) -> None:

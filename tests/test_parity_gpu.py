@@ -59,6 +59,7 @@ CASES = {
     "rmat17_ef32": lambda: gg.rmat(17, 32, 17),
     "er16_d32": lambda: gg.erdos_renyi(1 << 16, 32, 5),
     "er14_d4": lambda: gg.erdos_renyi(1 << 14, 4, 6),
+    "er14_d256": lambda: gg.erdos_renyi(1 << 14, 256, 7),
     "union": lambda: gg.disjoint_union([gg.rmat(9, 16, 1), gg.empty_graph(5), gg.wheel(30),
                                         gg.tri_grid(10, 13, 0.1, 2), gg.complete(20)]),
 }
@@ -149,6 +150,68 @@ def test_pruned_split_terms_match_cetc_s(tc_lib, name, setting):
     assert pruned == t0 + t1
     if hubs and name in ("rmat12", "rmat16"):
         assert info["hubs"] > 0  # the hub pass took part
+
+
+FE_GRAPHS = ["karate", "K40", "tripartite", "rmat12", "er14_d256", "rmat16", "er16_d32",
+             "union", "book10000", "grid64_del"]
+
+
+@pytest.mark.parametrize("name", FE_GRAPHS)
+def test_forward_dispatch_matches_oracle(tc_lib, name):
+    # CETC-Seq-FE (Section 4.3): tc_count switches to the forward ordering (every vertex
+    # on one level) when c = |S| / |E| reaches the threshold (0.7 by default).  The
+    # oracle's split with one shared label is the forward-hashed count of every triangle.
+    g, r, _, _ = case(name)
+    c = r.cover_edges / g.num_edges
+    T_fwd, t0, t1 = oracle.cetc_split(g, np.zeros(g.n, dtype=np.uint32))
+    assert (T_fwd, t0, t1) == (r.triangles, r.triangles, 0)
+    say(f"[parity] forward dispatch {name}: c={c:.3f}")
+    rp, ci = upload(g, tc_lib)
+    saved = tc_lib.tc_get_forward_threshold()
+    assert saved == 0.7
+    try:
+        assert tc_lib.tc_count(rp, ci) == r.triangles
+        info = tc_lib.tc_last_call_info()
+        assert info["forward"] == (1 if c >= 0.7 else 0)
+        assert info["cover_edges"] == r.cover_edges  # the BFS |S| that decided
+        tc_lib.tc_set_forward_threshold(0.0)  # always the forward ordering
+        assert tc_lib.tc_count(rp, ci) == T_fwd
+        assert tc_lib.tc_last_call_info()["forward"] == 1
+        tc_lib.tc_set_forward_threshold(2.0)  # never
+        assert tc_lib.tc_count(rp, ci) == r.triangles
+        assert tc_lib.tc_last_call_info()["forward"] == 0
+        # the statistics and the split terms keep the BFS levels
+        tc_lib.tc_set_forward_threshold(0.0)
+        stats, _ = tc_lib.tc_count_ex(rp, ci)
+        assert stats.triangles == r.triangles and tc_lib.tc_last_call_info()["forward"] == 0
+        assert sum(tc_lib.tc_count_split(rp, ci)) == r.triangles
+        assert tc_lib.tc_last_call_info()["forward"] == 0
+    finally:
+        tc_lib.tc_set_forward_threshold(saved)
+
+
+@pytest.mark.parametrize("setting", ["hubs", "chunked", "wave"])
+@pytest.mark.parametrize("name", ["K40", "rmat12", "er14_d256", "rmat16", "book10000"])
+def test_forward_ordering_under_class_and_hub_settings(tc_lib, name, setting):
+    g, r, _, _ = case(name)
+    isect, hubs = SPLIT_SETTINGS[setting]
+    say(f"[parity] forward ordering {name} ({setting})")
+    rp, ci = upload(g, tc_lib)
+    saved = (tc_lib.tc_get_forward_threshold(), tc_lib.tc_get_isect_params(),
+             tc_lib.tc_get_hub_params())
+    try:
+        tc_lib.tc_set_forward_threshold(0.0)
+        if isect:
+            tc_lib.tc_set_isect_params(*isect)
+        if hubs:
+            tc_lib.tc_set_hub_params(*hubs)
+        got = tc_lib.tc_count(rp, ci)
+        fwd = tc_lib.tc_last_call_info()["forward"]
+    finally:
+        tc_lib.tc_set_forward_threshold(saved[0])
+        tc_lib.tc_set_isect_params(*saved[1])
+        tc_lib.tc_set_hub_params(*saved[2])
+    assert got == r.triangles and fwd == 1
 
 
 @pytest.mark.parametrize("name", ["karate", "wheel500", "rmat12", "er14_d4", "book10000",

@@ -12,6 +12,9 @@ WORKLOADS = {
     "grid4096": lambda: gg.tri_grid(4096, 4096, 0.01, gg.config_seed(2)),
     # Erdős–Rényi G(n = 2^22, average degree 32)
     "er22": lambda: gg.erdos_renyi(1 << 22, 32, gg.config_seed(2) + 1),
+    # Erdős–Rényi G(n = 2^14, average degree 256): covering ratio about 0.94, above the
+    # 0.7 at which CETC-Seq-FE switches to the forward algorithm
+    "er14_d256": lambda: gg.erdos_renyi(1 << 14, 256, gg.config_seed(2) + 2),
 }
 
 # 4096 uneven graphs: half R-MAT (scale 8..16, edge factor 8..32), half Erdős–Rényi
