@@ -94,12 +94,13 @@ def log(*a):
 def source_sha() -> str:
     """Hash of every source that defines a counting kernel or its launch shape (all of csrc
     but the host-side call orchestration of api.hip, serve.hip and host_api.h, and the
-    clustering-coefficient kernel of cluster.hip, which no counting step runs): any change
+    clustering-coefficient kernel of cluster.hip, which no counting step runs, and the
+    allocation-free entry point of noalloc.hip, which only hands over a workspace): any change
     to how the work is divided or done makes a stored traffic record stale."""
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
         if f.endswith((".hip", ".h")) and f not in ("api.hip", "serve.hip", "host_api.h",
-                                                    "cluster.hip"):
+                                                    "cluster.hip", "noalloc.hip"):
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
@@ -843,7 +844,8 @@ def traffic_summary(args, settings: dict):
     lines = [f"copy calibration: {mib} MiB device copy reads FETCH_SIZE {cf:.1f} KiB "
              f"(factor {f_fetch:.4f}) and WRITE_SIZE {cw:.1f} KiB (factor {f_write:.4f})"]
     for k in sorted(fetch):
-        if not k.startswith(("k_isect", "k_hub_count")) or k not in write:
+        if not k.startswith(("k_isect", "k_hub_count", "k_batch_main", "k_split_rows")) or \
+                k not in write:
             continue
         fb = fetch[k][0] * 1024 / f_fetch
         wb = write[k][0] * 1024 / f_write

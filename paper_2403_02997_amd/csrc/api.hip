@@ -127,6 +127,9 @@ struct SideFork {
 // overlap saves).
 constexpr u32 kSideMinEntries = 1u << 22;
 
+// Top-down levels per cooperative BFS launch at most.
+constexpr u32 kBfsRunLevels = 1u << 16;
+
 struct DevAlloc {
   void* p = nullptr;
   hipStream_t s = nullptr;
@@ -258,6 +261,7 @@ struct SingleWs {
   size_t fb_words;
   u64* bfs_part;
   u32* bigq0;
+  uint8_t* bfs_run;
   uint8_t* vinfo;
   u32 *hcnt, *split, *sabove, *hcur, *scan_tmp;
   uint4* hrec;
@@ -286,6 +290,7 @@ size_t carve_single(void* base, u32 n, u32 m, bool hub_on, SingleWs* out) {
   w.fb = c.take<u32>(w.fb_words);
   w.bfs_part = c.take<u64>(bfs_part_words());   // per-workgroup BFS level totals
   w.bigq0 = c.take<u32>(2 * bfs_big_cap(n, m));  // queues of big frontier vertices
+  w.bfs_run = c.take<uint8_t>(bfs_run_bytes());  // state of the cooperative BFS launch
   w.vinfo = c.take<uint8_t>(n);
   w.hcnt = c.take<u32>(n);
   w.split = c.take<u32>(n);
@@ -349,6 +354,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   u64* bfs_part = w.bfs_part;
   u32* bigq0 = w.bigq0;
   u32* bigq1 = bigq0 + bfs_big_cap(n, m);
+  uint8_t* bfs_run = w.bfs_run;
   uint8_t* vinfo = w.vinfo;
   u32* hcnt = w.hcnt;
   u32* split = w.split;
@@ -396,7 +402,12 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   SideFork fork;  // its stream is made while the first BFS levels run
   const bool want_side = !timer.on && m >= kSideMinEntries;
   {
+    // Batches of one launch per level, with a poll of the control block after each; a
+    // search still in top-down mode after a batch (a large diameter) continues in one
+    // cooperative launch that runs its top-down levels back to back (launch_bfs_run),
+    // and resumes with per-level launches only for bottom-up levels.
     const u32 grid = bfs_grid(n);
+    bool run_ok = true;  // cleared if the device refuses the cooperative launch
     u32 k = 0, batch = 8;  // low-diameter graphs finish within one poll
     while (true) {
       for (u32 i = 0; i < batch; ++i)
@@ -405,12 +416,28 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
       TC_LAUNCHED();
       if (k == 0 && want_side) fork.create();
       k += batch;
-      u32 done = 0;
-      TC_HIP(hipMemcpyAsync(&done, &ctl->done, sizeof(u32), hipMemcpyDeviceToHost, s));
+      BfsCtl hc;
+      TC_HIP(hipMemcpyAsync(&hc, ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
       TC_HIP(hipStreamSynchronize(s));
-      if (done) break;
+      if (hc.done) break;
       if ((u64)k > (u64)n + 2) return TC_ERR_INTERNAL;  // a BFS has at most n levels
       batch = batch < 64 ? batch * 2 : 64;
+      if (hc.mode != 0 || !run_ok) continue;
+      run_ok = launch_bfs_run(rowptr, colidx, n, k, kBfsRunLevels, level, q0, q1, bigq0, bigq1,
+                              ctl, bfs_run, bfs_run_grid(n), s);
+      if (!run_ok) {
+        (void)hipGetLastError();
+        continue;
+      }
+      alignas(16) char hr[kBfsRunMaxBytes];
+      TC_HIP(hipMemcpyAsync(hr, bfs_run, bfs_run_bytes(), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipMemcpyAsync(&hc, ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+      TC_HIP(hipStreamSynchronize(s));
+      const u32 nk = bfs_run_next_level(hr);
+      if (nk < k || (u64)nk > (u64)n + 2) return TC_ERR_INTERNAL;
+      k = nk;
+      if (hc.done) break;
+      launch_bfs_bitmap(n, k, q0, q1, ctl, fb, s);  // per-level launches resume at level k
     }
   }
   timer.mark();

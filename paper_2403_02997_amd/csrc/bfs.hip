@@ -122,7 +122,7 @@ struct BfsOut {
   u32* qlen;
   u32* bq;
   u32* bqlen;
-  u32* bits;
+  u32* bits;  // null: no frontier bitmap (persistent top-down levels)
 };
 
 // Top-down visit of the neighbours y[i] with act[i] of every lane; all lanes of the
@@ -153,7 +153,7 @@ __device__ __forceinline__ void td_visit(const u32 (&y)[kBfsVisit], const bool (
   for (u32 i = 0; i < kBfsVisit; ++i) {
     if (cl[i]) {
       o.q[pos++] = y[i];
-      atomicOr(&o.bits[y[i] >> 5], 1u << (y[i] & 31));
+      if (o.bits) atomicOr(&o.bits[y[i] >> 5], 1u << (y[i] & 31));
       const u32 dy = rowptr[y[i] + 1] - rowptr[y[i]];
       mf += dy;
       mu_dec += dy;
@@ -412,6 +412,231 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_level(
   }
 }
 
+// ---- persistent top-down levels (long searches) -------------------------------------
+// A search still running after the first batch of levels (a large diameter: grids,
+// road-like graphs, paths) continues in one cooperative launch that runs consecutive
+// top-down levels with a grid barrier between them, instead of one launch, one ticket and
+// one last-workgroup decision per level.  Every workgroup is resident (cooperative
+// launch), takes every decision from the same values read after a barrier, and so
+// passes the same barriers and leaves at the same level.  The kernel keeps the frontier
+// queues, the big-vertex queues, the unvisited degree sum mu and the Beamer switch of
+// k_bfs_level; it stops at an empty frontier (done), when the switch picks bottom-up for
+// the next level, or after max_levels levels, and then writes the state k_bfs_level
+// resumes from (the frontier bitmaps are rebuilt by k_bfs_bitmap first).  Per-level
+// counters rotate over four slots: the frontier length of level k is appended during
+// level k - 1 and read up to the barrier that ends level k + 1 (every workgroup reads the
+// level's totals right after the barrier that ends level k), so slot k mod 4 is cleared
+// during level k + 2, before level k + 3 appends to it again.
+constexpr u32 kRunSlots = 4;
+
+struct BfsRun {
+  u32 bar;                // barrier arrivals of this launch (zeroed before it)
+  u32 next_k;             // out: level of the frontier left in the queues
+  u32 qcnt[kRunSlots];    // frontier lengths by level mod 4
+  u32 bcnt[kRunSlots];    // big-vertex queue lengths by level mod 4
+  u64 mf[kRunSlots];      // frontier edges of the level, by level mod 4
+  u64 dec[kRunSlots];     // degree of the vertices claimed in the level, by level mod 4
+};
+
+static_assert(sizeof(BfsRun) <= kBfsRunMaxBytes, "host copies of the run state are this large");
+size_t bfs_run_bytes() { return sizeof(BfsRun); }
+
+// All workgroups arrive once per barrier; `target` = barriers so far x grid size.
+__device__ __forceinline__ void bfs_grid_sync(u32* bar, u32 target) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1u);
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+      __builtin_amdgcn_s_sleep(1);
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBfsThreads) k_bfs_run(
+    const u32* __restrict__ rowptr, const u32* __restrict__ colidx, u32 n, u32 k0,
+    u32 max_levels, u32* __restrict__ level, u32* __restrict__ queue0,
+    u32* __restrict__ queue1, u32* __restrict__ bigq0, u32* __restrict__ bigq1,
+    BfsCtl* __restrict__ ctl, BfsRun* __restrict__ st) {
+  __shared__ u64 s_red[2 * (kBfsThreads / kWave)];
+  // entry state, written by earlier kernels: the same values in every workgroup
+  if (load_coherent(&ctl->done) || load_coherent(&ctl->mode) != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->next_k = k0;
+    return;
+  }
+  const u32 g = gridDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->qcnt[k0 % kRunSlots] = load_coherent(&ctl->qlen[k0 & 1]);
+    st->bcnt[k0 % kRunSlots] = load_coherent(&ctl->bqlen[k0 & 1]);
+  }
+  u32 nbar = 1;
+  bfs_grid_sync(&st->bar, nbar * g);
+  u64 mus = __hip_atomic_load(&ctl->mu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  u32 depth = load_coherent(&ctl->depth);
+  const u32 lane = lane_id(), wid = threadIdx.x / kWave;
+  const u32 stride = g * blockDim.x;
+  u32 k = k0, mode = 0, done = 0;
+  while (true) {
+    const u32 qn = load_coherent(&st->qcnt[k % kRunSlots]);
+    if (qn == 0) {
+      done = 1;
+      break;
+    }
+    if (k == k0 + max_levels) break;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the slot of level k - 2 (and k + 2)
+      const u32 r = (k + 2) % kRunSlots;
+      __hip_atomic_store(&st->qcnt[r], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->bcnt[r], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store((unsigned long long*)&st->mf[r], 0ull, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store((unsigned long long*)&st->dec[r], 0ull, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const u32* qin = (k & 1) ? queue1 : queue0;
+    const u32* bqin = (k & 1) ? bigq1 : bigq0;
+    const u32 next = k + 1;
+    const BfsOut o{(k & 1) ? queue0 : queue1, &st->qcnt[next % kRunSlots],
+                   (k & 1) ? bigq0 : bigq1, &st->bcnt[next % kRunSlots], nullptr};
+    u64 mf = 0, mu_dec = 0;
+    const u32 qr = (qn + kWave - 1) / kWave * kWave;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < qr; i += stride) {
+      u32 x = 0, lo = 0, d = 0;
+      if (i < qn) {
+        x = qin[i];
+        lo = rowptr[x];
+        d = rowptr[x + 1] - lo;
+        if (d > kBfsBig) d = 0;  // shared by the grid below
+      }
+      const bool big = d > kBfsLaneMax;
+      u32 dl = big ? 0 : d;
+      u32 dmax = dl;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, (u32)__shfl_xor(dmax, off, kWave));
+      for (u32 j = 0; j < dmax; j += kBfsVisit) {
+        u32 y[kBfsVisit];
+        bool act[kBfsVisit];
+#pragma unroll
+        for (u32 t = 0; t < kBfsVisit; ++t) {
+          act[t] = j + t < dl;
+          y[t] = act[t] ? colidx[lo + j + t] : 0u;
+        }
+        td_visit(y, act, next, rowptr, level, o, mf, mu_dec);
+      }
+      u64 bigmask = __ballot(big);
+      while (bigmask) {
+        const int b = __ffsll((unsigned long long)bigmask) - 1;
+        bigmask &= bigmask - 1;
+        const u32 blo = __shfl(lo, b, kWave), bd = __shfl(d, b, kWave);
+        for (u32 j0 = 0; j0 < bd; j0 += kWave * kBfsVisit) {
+          u32 y[kBfsVisit];
+          bool act[kBfsVisit];
+#pragma unroll
+          for (u32 t = 0; t < kBfsVisit; ++t) {
+            const u32 j = j0 + t * kWave + lane;
+            act[t] = j < bd;
+            y[t] = act[t] ? colidx[blo + j] : 0u;
+          }
+          td_visit(y, act, next, rowptr, level, o, mf, mu_dec);
+        }
+      }
+    }
+    const u32 nbq = load_coherent(&st->bcnt[k % kRunSlots]);
+    for (u32 bi = 0; bi < nbq; ++bi) {
+      const u32 x = bqin[bi];
+      const u32 lo = rowptr[x], d = rowptr[x + 1] - lo;
+      const u32 nch = (d + kBfsChunk - 1) / kBfsChunk;
+      const u32 shift = (u32)(((u64)bi * 131u) % g);
+      for (u32 c = (blockIdx.x + g - shift) % g; c < nch; c += g) {
+        const u32 ce = min(d, (c + 1) * kBfsChunk);
+        for (u32 j0 = c * kBfsChunk; j0 < ce; j0 += blockDim.x * kBfsVisit) {
+          u32 y[kBfsVisit];
+          bool act[kBfsVisit];
+#pragma unroll
+          for (u32 t = 0; t < kBfsVisit; ++t) {
+            const u32 j = j0 + t * blockDim.x + threadIdx.x;
+            act[t] = j < ce;
+            y[t] = act[t] ? colidx[lo + j] : 0u;
+          }
+          td_visit(y, act, next, rowptr, level, o, mf, mu_dec);
+        }
+      }
+    }
+    // the level's totals: one atomic per workgroup and counter
+    mf = wave_sum_u64(mf);
+    mu_dec = wave_sum_u64(mu_dec);
+    if (lane == 0) {
+      s_red[2 * wid] = mf;
+      s_red[2 * wid + 1] = mu_dec;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      u64 a = 0, b = 0;
+      for (u32 w = 0; w < blockDim.x / kWave; ++w) {
+        a += s_red[2 * w];
+        b += s_red[2 * w + 1];
+      }
+      if (a) atomicAdd((unsigned long long*)&st->mf[k % kRunSlots], (unsigned long long)a);
+      if (b) atomicAdd((unsigned long long*)&st->dec[k % kRunSlots], (unsigned long long)b);
+    }
+    ++nbar;
+    bfs_grid_sync(&st->bar, nbar * g);
+    // every workgroup takes the same decision from the same totals
+    const u32 nf = load_coherent(&st->qcnt[next % kRunSlots]);
+    const u64 mfs =
+        __hip_atomic_load(&st->mf[k % kRunSlots], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mus -= __hip_atomic_load(&st->dec[k % kRunSlots], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    k = next;
+    if (nf == 0) {
+      done = 1;
+      break;
+    }
+    depth = next;
+    if (mfs > mus / 14) {
+      mode = 1;
+      break;
+    }
+  }
+  // the state k_bfs_level resumes from (level k's frontier in queue[k & 1])
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const u32 qk = load_coherent(&st->qcnt[k % kRunSlots]);
+    const u32 bk = load_coherent(&st->bcnt[k % kRunSlots]);
+    __hip_atomic_store(&ctl->qlen[k & 1], done ? 0u : qk, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->qlen[(k + 1) & 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->bqlen[k & 1], done ? 0u : bk, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->bqlen[(k + 1) & 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((unsigned long long*)&ctl->mu, (unsigned long long)mus, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->depth, depth, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->mode, mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->next_k, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+}
+
+// The three frontier bitmaps for level k after k_bfs_run: bitmap k mod 3 holds the
+// frontier in queue[k & 1] (qn vertices), the other two are cleared.
+__global__ void __launch_bounds__(kBfsThreads) k_bfs_bitmap(u32 n, u32 k,
+                                                            const u32* __restrict__ queue0,
+                                                            const u32* __restrict__ queue1,
+                                                            const BfsCtl* __restrict__ ctl,
+                                                            u32* __restrict__ fb, u32 phase) {
+  const u32 nw = (n + 31) / 32;
+  const u32 stride = gridDim.x * blockDim.x;
+  if (phase == 0) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nw; i += stride) fb[i] = 0;
+  } else {
+    const u32 qn = ctl->qlen[k & 1];
+    const u32* q = (k & 1) ? queue1 : queue0;
+    u32* bits = fb + (k % 3) * (size_t)nw;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < qn; i += stride)
+      atomicOr(&bits[q[i] >> 5], 1u << (q[i] & 31u));
+  }
+}
+
 u32 bfs_grid(u32 n) {
   return max(1u, min(cdiv(n, kBfsThreads * kBfsPer), (u32)num_cus() * kBfsBlocksPerCu));
 }
@@ -431,6 +656,38 @@ void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* l
                       u64* part, u32 grid, hipStream_t s) {
   hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kBfsThreads), 0, s, rowptr, colidx, n, k,
                      level, queue0, queue1, bigq0, bigq1, fb, ctl, part);
+}
+
+// Grid of the persistent levels: half the compute units at most (so that a few
+// concurrent searches on other streams still fit beside each other), fewer for small
+// graphs (the barrier's cost grows with the number of workgroups).
+u32 bfs_run_grid(u32 n) {
+  return max(1u, min(cdiv(n, kBfsThreads * kBfsPer), (u32)num_cus() / 2));
+}
+
+bool launch_bfs_run(const u32* rowptr, const u32* colidx, u32 n, u32 k0, u32 max_levels,
+                    u32* level, u32* queue0, u32* queue1, u32* bigq0, u32* bigq1, BfsCtl* ctl,
+                    void* run_state, u32 grid, hipStream_t s) {
+  BfsRun* st = (BfsRun*)run_state;
+  if (hipMemsetAsync(st, 0, sizeof(BfsRun), s) != hipSuccess) return false;
+  void* args[] = {(void*)&rowptr, (void*)&colidx, (void*)&n, (void*)&k0, (void*)&max_levels,
+                  (void*)&level, (void*)&queue0, (void*)&queue1, (void*)&bigq0, (void*)&bigq1,
+                  (void*)&ctl, (void*)&st};
+  return hipLaunchCooperativeKernel((const void*)k_bfs_run, dim3(grid), dim3(kBfsThreads), args,
+                                    0, s) == hipSuccess;
+}
+
+u32 bfs_run_next_level(const void* run_state) {
+  return ((const BfsRun*)run_state)->next_k;
+}
+
+void launch_bfs_bitmap(u32 n, u32 k, const u32* queue0, const u32* queue1, const BfsCtl* ctl,
+                       u32* fb, hipStream_t s) {
+  const u32 g = max(1u, min(cdiv(3 * ((n + 31) / 32), kBfsThreads), (u32)num_cus() * 4));
+  hipLaunchKernelGGL(k_bfs_bitmap, dim3(g), dim3(kBfsThreads), 0, s, n, k, queue0, queue1, ctl,
+                     fb, 0u);
+  hipLaunchKernelGGL(k_bfs_bitmap, dim3(g), dim3(kBfsThreads), 0, s, n, k, queue0, queue1, ctl,
+                     fb, 1u);
 }
 
 }  // namespace tc

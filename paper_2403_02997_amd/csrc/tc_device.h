@@ -323,14 +323,14 @@ __device__ __forceinline__ void hash_count_split_n(const u32* table, u32 bmask,
   bool more = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const bool hit = ok[i] && bucket_holds(v[i], w[i]);
+    const bool hold = bucket_holds(v[i], w[i]);
     if (SPLIT) {
-      hits += hit && !sm[i] ? 1u : 0u;
-      hits_same += hit && sm[i] ? 1u : 0u;
+      hits += ok[i] && hold && !sm[i] ? 1u : 0u;
+      hits_same += ok[i] && hold && sm[i] ? 1u : 0u;
     } else {
-      hits += hit ? 1u : 0u;
+      hits += ok[i] && hold ? 1u : 0u;
     }
-    more |= ok[i] && !hit && bucket_flagged(v[i]);
+    more |= ok[i] && !hold && bucket_flagged(v[i]);
   }
   if (!__ballot(more)) return;
   u32 pend = 0;

@@ -121,6 +121,21 @@ void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* l
 u32 bfs_grid(u32 n);
 size_t bfs_part_words();
 size_t bfs_big_cap(u32 n, u64 m);
+// Persistent top-down levels from level k0 (one cooperative launch, at most max_levels
+// levels): run_state is bfs_run_bytes() of device memory (cleared here), grid at most
+// bfs_run_grid(n).  False if the launch was refused (the caller then stays with
+// launch_bfs_level).  Afterwards the search resumes at level bfs_run_next_level(host copy
+// of run_state), with ctl updated; launch_bfs_bitmap rebuilds the frontier bitmaps for
+// that level before any launch_bfs_level.
+constexpr size_t kBfsRunMaxBytes = 256;  // bfs_run_bytes() is at most this
+size_t bfs_run_bytes();
+u32 bfs_run_grid(u32 n);
+bool launch_bfs_run(const u32* rowptr, const u32* colidx, u32 n, u32 k0, u32 max_levels,
+                    u32* level, u32* queue0, u32* queue1, u32* bigq0, u32* bigq1, BfsCtl* ctl,
+                    void* run_state, u32 grid, hipStream_t s);
+u32 bfs_run_next_level(const void* run_state);
+void launch_bfs_bitmap(u32 n, u32 k, const u32* queue0, const u32* queue1, const BfsCtl* ctl,
+                       u32* fb, hipStream_t s);
 
 // ---- cover-edge extraction ----
 // Per vertex v: colidx2[rowptr[v] .. split[v]) = neighbours on v's level (ascending),
