@@ -448,10 +448,13 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
 
     // ---- 5b. wavefront class: 16 wavefront tables in the workgroup table ----
     // A wavefront claims 64 vertices at once and reads their row bounds, partner counts
-    // and split points in one load per lane; the vertices of the class are then taken
-    // one by one with their row data already in registers.  The staged and streamed rows
-    // come from the level-split rows, whose positions give the level flags.
+    // and split points in one load per lane.  Vertices of up to kSubMax entries are then
+    // taken four at a time, one per group of 16 lanes (subwave_vertex, each group with a
+    // quarter of the wavefront's table); longer ones one at a time with the whole
+    // wavefront (wave_vertex).  Staged and streamed rows are the level-split rows, whose
+    // positions give the level flags.
     {
+      const u32 sub_max = min(kSubMax, prm.wave_max);
       while (true) {
         u32 c0 = 0;
         if (lane == 0) c0 = atomicAdd(&s_next, (u32)kWave);
@@ -459,13 +462,36 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
         if (base >= n) break;  // wave-uniform
         const u32 x = base + lane;
         WaveMeta mt{0, 0, 0, 0};
-        bool cls = false;
+        bool sub = false, whole = false;
         if (x < n) {
           const u32 lo = rp[x], hi = rp[x + 1], np = hcnt[x];
-          cls = np > 0 && hi - lo > prm.lane_max && hi - lo <= prm.wave_max;
+          const u32 d = hi - lo;
+          const bool cls = np > 0 && d > prm.lane_max && d <= prm.wave_max;
+          sub = cls && d <= sub_max;
+          whole = cls && !sub;
           if (cls) mt = WaveMeta{cb + lo, cb + hi, cb + split[x], np};
         }
-        u64 todo = __ballot(cls);
+        u64 todo = __ballot(sub);
+        u32* gtab = s_table + wid * kWaveSlots + (lane / kSubLanes) * kSubSlots;
+        while (todo) {
+          // up to four vertices, the g-th lowest remaining lane for group g
+          int src = -1;
+#pragma unroll
+          for (u32 g = 0; g < kSubGroups; ++g) {
+            const int b = todo ? __ffsll((unsigned long long)todo) - 1 : -1;
+            if (b >= 0) todo &= todo - 1;
+            if (g == lane / kSubLanes) src = b;
+          }
+          const int s0 = src < 0 ? 0 : src;
+          WaveMeta gm{(u32)__shfl(mt.bx, s0, kWave), (u32)__shfl(mt.ex, s0, kWave),
+                      (u32)__shfl(mt.sb, s0, kWave), (u32)__shfl(mt.np, s0, kWave)};
+          const u32 gx = (u32)__shfl(x, s0, kWave);
+          if (src < 0) gm = WaveMeta{0, 0, 0, 0};
+          Tally tl{0, 0, 0, 0};
+          subwave_vertex(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, gx, gm, gtab, tl, c);
+          tl.fold(c);
+        }
+        todo = __ballot(whole);
         while (todo) {
           const int b = __ffsll((unsigned long long)todo) - 1;
           todo &= todo - 1;

@@ -658,11 +658,15 @@ void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* l
                      level, queue0, queue1, bigq0, bigq1, fb, ctl, part);
 }
 
-// Grid of the persistent levels: half the compute units at most (so that a few
-// concurrent searches on other streams still fit beside each other), fewer for small
-// graphs (the barrier's cost grows with the number of workgroups).
+// Grid of the persistent levels: at most 32 workgroups, fewer for small graphs.  The
+// levels these searches run are thin, and each barrier costs more with more workgroups
+// (measured: 2.0 us with 32, 5.4 us with 128, 13.7 us with 256); on the 4096 x 4096 grid
+// the BFS took 78.8, 74.5, 88.0 and 102.6 ms with 16, 32, 64 and 128 workgroups.  A
+// small grid also leaves room for concurrent searches on other streams.
+constexpr u32 kBfsRunMaxGrid = 32;
+
 u32 bfs_run_grid(u32 n) {
-  return max(1u, min(cdiv(n, kBfsThreads * kBfsPer), (u32)num_cus() / 2));
+  return max(1u, min(cdiv(n, kBfsThreads * kBfsPer), min(kBfsRunMaxGrid, (u32)num_cus())));
 }
 
 bool launch_bfs_run(const u32* rowptr, const u32* colidx, u32 n, u32 k0, u32 max_levels,

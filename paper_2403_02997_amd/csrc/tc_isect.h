@@ -252,6 +252,113 @@ __device__ __forceinline__ void wave_vertex(
   }
 }
 
+// ---- sub-wavefront class (batched, level-split rows): four staged vertices per wavefront
+// A staged vertex with a few dozen entries and a handful of partners fills a small part
+// of a wavefront's 64 lanes and windows.  Here each group of 16 lanes takes its own x:
+// its split row goes to the group's 256-slot LDS hash set (level flag = position), its
+// partners' split rows are streamed 16 partners at a time, 4 quads per lane in flight,
+// and the owner of a quad is found by a binary search over the group's quad prefix sums
+// (cross-lane reads, no LDS marks).  Full form: c1, c2 and t2.  All 64 lanes call it
+// together; a group without a vertex passes mt.np = 0 and an empty row.
+constexpr u32 kSubLanes = 16;
+constexpr u32 kSubGroups = kWave / kSubLanes;
+constexpr u32 kSubMax = 64;     // d(x) of the sub-wavefront class at most
+constexpr u32 kSubSlots = 256;  // LDS hash slots per group
+constexpr u32 kSubU = 4;        // quads per lane in flight
+static_assert(kSubGroups * kSubSlots <= kWaveSlots, "the groups share one wavefront table");
+
+__device__ __forceinline__ u32 group_incl_scan(u32 v) {
+  const u32 gl = lane_id() & (kSubLanes - 1);
+#pragma unroll
+  for (u32 off = 1; off < kSubLanes; off <<= 1) {
+    const u32 t = __shfl_up(v, off, kSubLanes);
+    if (gl >= off) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ u32 wave_max_u32(u32 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (u32)__shfl_xor(v, off, kWave));
+  return v;
+}
+
+// colidx2 has 4 readable entries past m; table is this group's kSubSlots slots.
+__device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u32 cb,
+                                               const u32* __restrict__ colidx2, u32 m,
+                                               const u32* __restrict__ hadj, u32 x,
+                                               const WaveMeta& mt, u32* table, Tally& tl,
+                                               Counts& c) {
+  const u32 lane = lane_id(), gl = lane & (kSubLanes - 1), gb = lane & ~(kSubLanes - 1);
+  const u32 bx = mt.bx, dx = mt.ex - mt.bx, np = mt.np;
+  const u32 mask = bucket_mask(dx ? dx : 1u, kSubSlots);
+  c.staged += gl == 0 ? dx : 0;
+  for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) table[i] = kInf;
+  wave_lds_sync();
+  for (u32 i = gl; i < dx; i += kSubLanes)
+    hash_insert(table, mask, colidx2[bx + i], bx + i < mt.sb ? 1u : 0u);
+  wave_lds_sync();
+  const u32 nbat = wave_max_u32((np + kSubLanes - 1) / kSubLanes);
+  for (u32 b = 0; b < nbat; ++b) {
+    const u32 p = b * kSubLanes + gl;
+    u32 y = 0, lo = 0, hi = 0;
+    if (p < np) {
+      y = hadj[bx + p];
+      lo = cb + rowptr[y];
+      hi = cb + rowptr[y + 1];
+    }
+    tl.probes += hi - lo;
+    const u32 qa = lo & ~3u;
+    const u32 nq = lo < hi ? (hi - qa + 3u) >> 2 : 0u;
+    const u32 incl = group_incl_scan(nq);
+    const u32 total = __shfl(incl, (int)(gb + kSubLanes - 1), kWave);
+    const u32 qbase = (qa >> 2) - (incl - nq);  // quad q of the group's concatenation: qbase + q
+    const u32 tmax = wave_max_u32(total);
+    for (u32 k0 = 0; k0 < tmax; k0 += kSubLanes * kSubU) {
+      u32 e[kSubU][4];
+      u32 addr[kSubU], jlo[kSubU], jspan[kSubU], jy[kSubU];
+      bool live[kSubU];
+#pragma unroll
+      for (u32 u = 0; u < kSubU; ++u) {
+        const u32 q = k0 + u * kSubLanes + gl;
+        live[u] = q < total;
+        // owner: the first lane of the group whose inclusive quad count exceeds q
+        u32 a = 0, z = kSubLanes - 1;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const u32 mid = (a + z) >> 1;
+          const u32 im = (u32)__shfl(incl, (int)(gb + mid), kWave);
+          if (im > q) z = mid;
+          else a = mid + 1;
+        }
+        const int j = (int)(gb + a);
+        const u32 qb = (u32)__shfl(qbase, j, kWave);
+        jlo[u] = (u32)__shfl(lo, j, kWave);
+        jspan[u] = (u32)__shfl(hi, j, kWave) - jlo[u];
+        jy[u] = (u32)__shfl(y, j, kWave);
+        addr[u] = (qb + q) * 4;
+        const uint4 v = *reinterpret_cast<const uint4*>(colidx2 + min(addr[u], (m - 1) & ~3u));
+        e[u][0] = v.x;
+        e[u][1] = v.y;
+        e[u][2] = v.z;
+        e[u][3] = v.w;
+      }
+#pragma unroll
+      for (u32 u = 0; u < kSubU; ++u) {
+        const u32 vmax = max(x, jy[u]);
+        bool ok[4];
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) ok[i] = live[u] && (addr[u] + i - jlo[u]) < jspan[u];
+        u32 res[4];
+        hash_probe_n<4>(table, mask, e[u], ok, res);
+#pragma unroll
+        for (u32 i = 0; i < 4; ++i) tl.add(res[i], e[u][i], vmax);
+      }
+    }
+  }
+  wave_lds_sync();  // the table is reused by the next vertex of the group
+}
+
 // ---- block class: one 1024-thread workgroup per (x, segment of partners) ------------
 // N(x) is staged chunk by chunk (at most prm.chunk <= 16384 entries per chunk, 4096 by
 // default so that the 128 KB LDS hash set stays at most 1/8 full).  For each chunk every
