@@ -488,7 +488,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const u32 gx = (u32)__shfl(x, s0, kWave);
           if (src < 0) gm = WaveMeta{0, 0, 0, 0};
           Tally tl{0, 0, 0, 0};
-          subwave_vertex(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, gx, gm, gtab, tl, c);
+          subwave_vertex<false>(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, nullptr, gx, gm,
+                                gtab, tl, c);
           tl.fold(c);
         }
         todo = __ballot(whole);

@@ -65,42 +65,94 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
   __shared__ u64 s_red[5 * kW];
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   Counts c{0, 0, 0, 0, 0};
-  // Vertices are claimed kWaveClaim at a time (one counter atomic per vertex would
-  // serialise hundreds of thousands of same-address atomics at the L2), with all their
-  // IDs loaded at once; the next vertex's row data is loaded while the current one runs.
-  u32 base = 0, cnt = 0, xs = 0, j = 0;
-  auto claim = [&]() {
-    u32 c0 = 0;
-    if (lane == 0) c0 = atomicAdd(&plan->next_wave, kWaveClaim);
-    base = __shfl(c0, 0, kWave);
-    cnt = base < nwx ? min(kWaveClaim, nwx - base) : 0u;
-    xs = lane < cnt ? wave_x[base + lane] : 0u;
-    j = 0;
-  };
-  claim();
-  if (cnt > 0) {
-    u32 x = __shfl(xs, 0, kWave);
-    j = 1;
-    WaveMeta mt{};
-    if (REC) mt = wave_meta(rowptr, sabove, hcnt, x);
+  if constexpr (REC && !ST && !PV) {
+    // Pruned count: 64 vertices claimed per counter atomic, their row data loaded in one
+    // step; those of up to kSubMax entries are counted four at a time, one per 16-lane
+    // group (subwave_vertex), the others one at a time by the whole wavefront.
     while (true) {
-      if (j == cnt) claim();
-      const bool more = cnt > 0;
-      u32 x1 = 0;
-      WaveMeta mt1{};
-      if (more) {
-        x1 = __shfl(xs, j, kWave);
-        ++j;
-        if (REC) mt1 = wave_meta(rowptr, sabove, hcnt, x1);
+      u32 c0 = 0;
+      if (lane == 0) c0 = atomicAdd(&plan->next_wave, (u32)kWave);
+      const u32 base = __shfl(c0, 0, kWave);
+      if (base >= nwx) break;  // wave-uniform
+      const u32 i = base + lane;
+      const bool live = i < nwx;
+      u32 x = 0;
+      WaveMeta mt{0, 0, 0, 0};
+      if (live) {
+        x = wave_x[i];
+        mt = wave_meta(rowptr, sabove, hcnt, x);
       }
-      Tally tl{0, 0, 0, 0};
-      wave_vertex<PV, VEC, REC, 4, ST>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
-                                   hrec, sabove, x, mt, s_table[wid], s_pinfo[wid], s_end[wid],
-                                   s_mark[wid], tl, c, tri);
-      tl.fold(c);
-      if (!more) break;
-      x = x1;
-      mt = mt1;
+      const bool sub = live && mt.ex - mt.bx <= kSubMax;
+      u64 todo = __ballot(sub);
+      u32* gtab = s_table[wid] + (lane / kSubLanes) * kSubSlots;
+      while (todo) {
+        int src = -1;  // the g-th lowest remaining lane for group g
+#pragma unroll
+        for (u32 g = 0; g < kSubGroups; ++g) {
+          const int b = todo ? __ffsll((unsigned long long)todo) - 1 : -1;
+          if (b >= 0) todo &= todo - 1;
+          if (g == lane / kSubLanes) src = b;
+        }
+        const int s0 = src < 0 ? 0 : src;
+        WaveMeta gm{(u32)__shfl(mt.bx, s0, kWave), (u32)__shfl(mt.ex, s0, kWave),
+                    (u32)__shfl(mt.sb, s0, kWave), (u32)__shfl(mt.np, s0, kWave)};
+        if (src < 0) gm = WaveMeta{0, 0, 0, 0};
+        Tally tl{0, 0, 0, 0};
+        subwave_vertex<true>(rowptr, 0u, colidx, m, nullptr, hrec, 0u, gm, gtab, tl, c);
+        tl.fold(c);
+      }
+      todo = __ballot(live && !sub);
+      while (todo) {
+        const int b = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const WaveMeta mb{(u32)__shfl(mt.bx, b, kWave), (u32)__shfl(mt.ex, b, kWave),
+                          (u32)__shfl(mt.sb, b, kWave), (u32)__shfl(mt.np, b, kWave)};
+        Tally tl{0, 0, 0, 0};
+        wave_vertex<PV, VEC, REC, 4, ST>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt,
+                                         record_ids(hrec), hrec, sabove, (u32)__shfl(x, b, kWave),
+                                         mb, s_table[wid], s_pinfo[wid], s_end[wid], s_mark[wid],
+                                         tl, c, tri);
+        tl.fold(c);
+      }
+    }
+  } else {
+    // Vertices are claimed kWaveClaim at a time (one counter atomic per vertex would
+    // serialise hundreds of thousands of same-address atomics at the L2), with all their
+    // IDs loaded at once; the next vertex's row data is loaded while the current one runs.
+    u32 base = 0, cnt = 0, xs = 0, j = 0;
+    auto claim = [&]() {
+      u32 c0 = 0;
+      if (lane == 0) c0 = atomicAdd(&plan->next_wave, kWaveClaim);
+      base = __shfl(c0, 0, kWave);
+      cnt = base < nwx ? min(kWaveClaim, nwx - base) : 0u;
+      xs = lane < cnt ? wave_x[base + lane] : 0u;
+      j = 0;
+    };
+    claim();
+    if (cnt > 0) {
+      u32 x = __shfl(xs, 0, kWave);
+      j = 1;
+      WaveMeta mt{};
+      if (REC) mt = wave_meta(rowptr, sabove, hcnt, x);
+      while (true) {
+        if (j == cnt) claim();
+        const bool more = cnt > 0;
+        u32 x1 = 0;
+        WaveMeta mt1{};
+        if (more) {
+          x1 = __shfl(xs, j, kWave);
+          ++j;
+          if (REC) mt1 = wave_meta(rowptr, sabove, hcnt, x1);
+        }
+        Tally tl{0, 0, 0, 0};
+        wave_vertex<PV, VEC, REC, 4, ST>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
+                                     hrec, sabove, x, mt, s_table[wid], s_pinfo[wid], s_end[wid],
+                                     s_mark[wid], tl, c, tri);
+        tl.fold(c);
+        if (!more) break;
+        x = x1;
+        mt = mt1;
+      }
     }
   }
   block_flush_counts(c, 1, ctr, s_red);

@@ -252,14 +252,18 @@ __device__ __forceinline__ void wave_vertex(
   }
 }
 
-// ---- sub-wavefront class (batched, level-split rows): four staged vertices per wavefront
+// ---- sub-wavefront class: four staged vertices per wavefront ---------------------------
 // A staged vertex with a few dozen entries and a handful of partners fills a small part
 // of a wavefront's 64 lanes and windows.  Here each group of 16 lanes takes its own x:
-// its split row goes to the group's 256-slot LDS hash set (level flag = position), its
-// partners' split rows are streamed 16 partners at a time, 4 quads per lane in flight,
-// and the owner of a quad is found by a binary search over the group's quad prefix sums
-// (cross-lane reads, no LDS marks).  Full form: c1, c2 and t2.  All 64 lanes call it
-// together; a group without a vertex passes mt.np = 0 and an empty row.
+// its staged entries go to the group's 256-slot LDS hash set, its partners' ranges are
+// streamed 16 partners at a time, 4 quads per lane in flight, and the owner of a quad is
+// found by a binary search over the group's quad prefix sums (cross-lane reads, no LDS
+// marks).  REC = false (batched, level-split rows): x's split row staged with level
+// flags by position (mt.sb = its first other-level entry), each partner's whole split
+// row streamed, full form (c1, c2, t2).  REC = true (single graph, pruned count): x's
+// entries from mt.sb = sabove[x] on staged as plain keys, each partner record's range
+// .x .. .z streamed, membership only (every hit a counted apex, in tl.s).  All 64 lanes
+// call it together; a group without a vertex passes mt.np = 0 and an empty row.
 constexpr u32 kSubLanes = 16;
 constexpr u32 kSubGroups = kWave / kSubLanes;
 constexpr u32 kSubMax = 64;     // d(x) of the sub-wavefront class at most
@@ -284,28 +288,41 @@ __device__ __forceinline__ u32 wave_max_u32(u32 v) {
 }
 
 // colidx2 has 4 readable entries past m; table is this group's kSubSlots slots.
+template <bool REC>
 __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u32 cb,
                                                const u32* __restrict__ colidx2, u32 m,
-                                               const u32* __restrict__ hadj, u32 x,
+                                               const u32* __restrict__ hadj,
+                                               const uint4* __restrict__ hrec, u32 x,
                                                const WaveMeta& mt, u32* table, Tally& tl,
                                                Counts& c) {
   const u32 lane = lane_id(), gl = lane & (kSubLanes - 1), gb = lane & ~(kSubLanes - 1);
-  const u32 bx = mt.bx, dx = mt.ex - mt.bx, np = mt.np;
+  const u32 bx = mt.bx, np = mt.np;
+  const u32 sb = REC ? mt.sb : bx;  // first staged entry
+  const u32 dx = mt.ex - sb;
   const u32 mask = bucket_mask(dx ? dx : 1u, kSubSlots);
   c.staged += gl == 0 ? dx : 0;
   for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) table[i] = kInf;
   wave_lds_sync();
-  for (u32 i = gl; i < dx; i += kSubLanes)
-    hash_insert(table, mask, colidx2[bx + i], bx + i < mt.sb ? 1u : 0u);
+  for (u32 i = gl; i < dx; i += kSubLanes) {
+    const u32 w = colidx2[sb + i];
+    if (REC) hash_insert_key(table, mask, w, w);
+    else hash_insert(table, mask, w, sb + i < mt.sb ? 1u : 0u);
+  }
   wave_lds_sync();
   const u32 nbat = wave_max_u32((np + kSubLanes - 1) / kSubLanes);
   for (u32 b = 0; b < nbat; ++b) {
     const u32 p = b * kSubLanes + gl;
     u32 y = 0, lo = 0, hi = 0;
     if (p < np) {
-      y = hadj[bx + p];
-      lo = cb + rowptr[y];
-      hi = cb + rowptr[y + 1];
+      if (REC) {
+        const uint4 r = hrec[bx + p];  // the records sit in place of N(x)
+        lo = r.x;
+        hi = r.z;
+      } else {
+        y = hadj[bx + p];
+        lo = cb + rowptr[y];
+        hi = cb + rowptr[y + 1];
+      }
     }
     tl.probes += hi - lo;
     const u32 qa = lo & ~3u;
@@ -335,7 +352,7 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
         const u32 qb = (u32)__shfl(qbase, j, kWave);
         jlo[u] = (u32)__shfl(lo, j, kWave);
         jspan[u] = (u32)__shfl(hi, j, kWave) - jlo[u];
-        jy[u] = (u32)__shfl(y, j, kWave);
+        jy[u] = REC ? 0u : (u32)__shfl(y, j, kWave);
         addr[u] = (qb + q) * 4;
         const uint4 v = *reinterpret_cast<const uint4*>(colidx2 + min(addr[u], (m - 1) & ~3u));
         e[u][0] = v.x;
@@ -345,14 +362,18 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
       }
 #pragma unroll
       for (u32 u = 0; u < kSubU; ++u) {
-        const u32 vmax = max(x, jy[u]);
         bool ok[4];
 #pragma unroll
         for (u32 i = 0; i < 4; ++i) ok[i] = live[u] && (addr[u] + i - jlo[u]) < jspan[u];
-        u32 res[4];
-        hash_probe_n<4>(table, mask, e[u], ok, res);
+        if (REC) {
+          hash_count_n<4>(table, mask, e[u], ok, tl.s);
+        } else {
+          const u32 vmax = max(x, jy[u]);
+          u32 res[4];
+          hash_probe_n<4>(table, mask, e[u], ok, res);
 #pragma unroll
-        for (u32 i = 0; i < 4; ++i) tl.add(res[i], e[u][i], vmax);
+          for (u32 i = 0; i < 4; ++i) tl.add(res[i], e[u][i], vmax);
+        }
       }
     }
   }
