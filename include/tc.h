@@ -87,9 +87,9 @@ typedef struct {
  * and synchronises `stream`.  n == 0 or m == 0 gives T = 0 without a launch.
  * For cover edges staged as long lists, a same-level apex w <= max(u, v) can never
  * count, so those list entries are skipped: T = c1 + t2 is computed, c2 is not.
- * When the covering ratio |S| / |E| reaches the forward threshold (0.7 by default, see
- * tc_set_forward_threshold) the count runs with every vertex on one level instead
- * (CETC-Seq-FE's switch to the forward algorithm).
+ * When the covering ratio |S| / |E| reaches the forward threshold (off by default; the
+ * paper uses 0.7; see tc_set_forward_threshold) the count runs with every vertex on one
+ * level instead (CETC-Seq-FE's switch to the forward algorithm).
  * Returns TC_ERR_INVALID_ARG for null pointers (when m > 0) or a null `count`,
  * TC_ERR_TOO_LARGE for n >= 2^30 or m > 2^32 - 2^20, TC_ERR_OUT_OF_MEMORY, TC_ERR_HIP.
  */
@@ -334,7 +334,9 @@ int tc_set_hub_params(uint32_t max_hubs, uint32_t min_degree);
  * endpoints, so the same kernels run the ID-ordered forward algorithm (Alg. TC_forward
  * with the hashed intersections of Alg. TC_forward-hashed), which the paper picks for
  * graphs whose covering ratio leaves little to skip.  T is the same either way.
- * Default 0.7, the paper's value.  A threshold above 1 never switches, 0 always does.
+ * Default 2.0, i.e. off: in this implementation the pruned pass already skips what the
+ * forward ordering skips, so the switch only adds its second extraction.  Pass 0.7 for
+ * the paper's setting; a threshold above 1 never switches, 0 always does.
  * Only the counting call switches (tc_count, tc_count_ex without statistics, the
  * server's single-graph paths); statistics, per-vertex counts, tc_count_split and the
  * batch keep the BFS levels.  Set it while no count is running.  A negative or NaN

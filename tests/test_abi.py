@@ -96,15 +96,15 @@ def test_argument_errors_without_gpu(lib):
     cols = (cap - lib.tc_count_batch_workspace_size(4, rows, 0)) // 8 + 64
     assert lib.tc_count_batch_workspace_size(4, rows, cols) > cap
     assert lib.tc_count_batch_noalloc(p, p, p, p, 4, rows, cols, None, p) == -5
-    # CETC-Seq-FE's threshold: 0.7 by default, negative and NaN refused
+    # CETC-Seq-FE's threshold: 2.0 (off) by default, negative and NaN refused
     lib.tc_get_forward_threshold.restype = ctypes.c_double
     lib.tc_set_forward_threshold.argtypes = [ctypes.c_double]
-    assert lib.tc_get_forward_threshold() == 0.7
+    assert lib.tc_get_forward_threshold() == 2.0
     assert lib.tc_set_forward_threshold(-0.5) == -1
     assert lib.tc_set_forward_threshold(float("nan")) == -1
-    assert lib.tc_get_forward_threshold() == 0.7
-    assert lib.tc_set_forward_threshold(1.5) == 0 and lib.tc_get_forward_threshold() == 1.5
-    assert lib.tc_set_forward_threshold(0.7) == 0
+    assert lib.tc_get_forward_threshold() == 2.0
+    assert lib.tc_set_forward_threshold(0.7) == 0 and lib.tc_get_forward_threshold() == 0.7
+    assert lib.tc_set_forward_threshold(2.0) == 0
     # clustering coefficients: checked before the launch
     lib.tc_local_clustering.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_void_p]

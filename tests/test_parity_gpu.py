@@ -159,8 +159,9 @@ FE_GRAPHS = ["karate", "K40", "tripartite", "rmat12", "er14_d256", "rmat16", "er
 @pytest.mark.parametrize("name", FE_GRAPHS)
 def test_forward_dispatch_matches_oracle(tc_lib, name):
     # CETC-Seq-FE (Section 4.3): tc_count switches to the forward ordering (every vertex
-    # on one level) when c = |S| / |E| reaches the threshold (0.7 by default).  The
-    # oracle's split with one shared label is the forward-hashed count of every triangle.
+    # on one level) when c = |S| / |E| reaches the threshold (the paper's 0.7 here; the
+    # library's default 2.0 never switches).  The oracle's split with one shared label is
+    # the forward-hashed count of every triangle.
     g, r, _, _ = case(name)
     c = r.cover_edges / g.num_edges
     T_fwd, t0, t1 = oracle.cetc_split(g, np.zeros(g.n, dtype=np.uint32))
@@ -168,8 +169,11 @@ def test_forward_dispatch_matches_oracle(tc_lib, name):
     say(f"[parity] forward dispatch {name}: c={c:.3f}")
     rp, ci = upload(g, tc_lib)
     saved = tc_lib.tc_get_forward_threshold()
-    assert saved == 0.7
+    assert saved == 2.0
     try:
+        assert tc_lib.tc_count(rp, ci) == r.triangles
+        assert tc_lib.tc_last_call_info()["forward"] == 0  # off by default
+        tc_lib.tc_set_forward_threshold(0.7)  # the paper's setting
         assert tc_lib.tc_count(rp, ci) == r.triangles
         info = tc_lib.tc_last_call_info()
         assert info["forward"] == (1 if c >= 0.7 else 0)
@@ -416,6 +420,36 @@ def test_concurrent_counts_on_two_streams(tc_lib):
     assert not errors, errors
     for i, (g, r, _, _) in enumerate(cases):
         assert got[i] == [r.triangles] * 6, (g.name, got[i])
+
+
+def test_concurrent_long_searches_on_four_streams(tc_lib):
+    """Four host threads count high-diameter graphs at once, each on its own stream, so
+    that several calls reach the cooperative BFS launch together: every result is exact."""
+    import threading
+    names = ["path", "cycle1001", "grid64_del", "grid1x300"]
+    cases = [case(nm) for nm in names]
+    say("[parity] concurrent long searches on four streams")
+    dev = [upload(g, tc_lib) for g, _, _, _ in cases]
+    streams = [torch.cuda.Stream() for _ in names]
+    got = [[] for _ in names]
+    errors = []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                for _ in range(8):
+                    got[i].append(tc_lib.tc_count(*dev[i], stream=streams[i]))
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(names))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not errors, errors
+    for i, (g, r, _, _) in enumerate(cases):
+        assert got[i] == [r.triangles] * 8, (names[i], got[i])
 
 
 @pytest.mark.parametrize("hubs", [(1, 1), (7, 1), (129, 1), (256, 1), (0, 0)])
