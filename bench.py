@@ -764,19 +764,29 @@ def bench_serve(args, tcm, torch):
     paths = {"batched": sum(r.path == 0 for r in results),
              "single_medium": sum(r.path == 1 for r in results),
              "single_large": sum(r.path == 3 for r in results)}
-    # the large path's requests: admission wait, admit-to-done time and the standalone
-    # service time, per request in submission order (the huge request is marked)
+    # the large path's requests: wait from submission to the start of their job, job
+    # time and the standalone service time (the huge request is marked)
     large = sorted((r for r in results if r.path == 3), key=lambda r: r.submit_s)
     huge = (args.serve_huge_scale, 0) if args.serve_huge_scale else None
     large_path = {
         "admit_wait_ms_sum": round(sum(r.admit_s - r.submit_s for r in large) * 1e3, 1),
         "service_ms_sum": round(sum(r.done_s - r.admit_s for r in large) * 1e3, 1),
+        "count_ms_sum": round(sum(r.done_s - r.count_s for r in large) * 1e3, 1),
         "standalone_ms_sum": round(sum(svc[tickets[r.ticket]] for r in large) * 1e3, 1),
         "huge": [{"latency_ms": round(r.latency_s * 1e3, 1),
                   "admit_wait_ms": round((r.admit_s - r.submit_s) * 1e3, 1),
                   "standalone_ms": round(svc[tickets[r.ticket]] * 1e3, 1)}
                  for r in large if tickets[r.ticket] == huge],
     }
+    if args.serve_trace:
+        # one line per request: its graph, path, server times and standalone service
+        with open(args.serve_trace, "w") as f:
+            for r in sorted(results, key=lambda r: r.submit_s):
+                key = tickets[r.ticket]
+                f.write(json.dumps({"scale": key[0], "graph": key[1], "path": r.path,
+                                    "submit": r.submit_s, "admit": r.admit_s,
+                                    "count": r.count_s, "done": r.done_s,
+                                    "standalone_ms": round(svc[key] * 1e3, 3)}) + "\n")
     lat_by = {}
     for name, ids in (("batched", (0,)), ("single_medium", (1,)), ("single_large", (3,))):
         v = np.array([r.latency_s for r in results if r.path in ids])
@@ -808,7 +818,8 @@ def bench_serve(args, tcm, torch):
         "latency_ms_by_path": lat_by,
         "input_edges": int(edges),
         "paths": paths,
-        "server": {k: st[k] for k in ("batches", "singles", "hbm_peak", "hbm_budget")},
+        "server": {k: st[k] for k in ("batches", "singles", "hbm_peak", "hbm_budget",
+                                      "busy_s", "device_s")},
         "oracle_checked": {"requests": sum(oracle_T[tickets[r.ticket]] is not None
                                            for r in results),
                            "pool_graphs_without_stored_count": [list(k) for k in unchecked]},
@@ -904,6 +915,8 @@ def main():
     ap.add_argument("--serve-huge-scale", type=int, default=26)
     ap.add_argument("--serve-small-max", type=int, default=1 << 18)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-trace", default="",
+                    help="serve: write one JSON line per request (times, path, graph) here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--traffic-summary", action="store_true")
     ap.add_argument("--pmc-fetch")

@@ -205,19 +205,24 @@ int tc_count_batch_noalloc(const uint32_t* rowptr_cat, const uint32_t* colidx_ca
 /*
  * ---- continuous-batching server ----------------------------------------------------
  * A server counts a stream of independent graphs handed over as HOST CSR arrays (same
- * format as above).  It admits a request when the request's device footprint (its CSR
- * plus the scratch of its path) fits the HBM budget: first-fit in arrival order, except
- * that while the oldest waiting request does not fit, later ones are admitted only if
- * the oldest would still fit beside them.  Requests with at most small_max_entries stored
- * entries are packed, whenever the previous batch has completed, into one tc_count_batch
- * launch over everything admitted meanwhile; larger requests run through tc_count, those
- * below large_min_entries in arrival order and the rest smallest first (by stored
- * entries; one that has waited 2 s since admission goes next) on two separate workers,
- * so that no request waits behind the upload of a much larger one.  The three paths
- * overlap on the device.  Results equal tc_count's.  Each server drives the device that
- * is current at
- * tc_serve_create with three host threads and three non-blocking streams of default
- * priority; its tc_count calls keep to those streams (no second stream per call).
+ * format as above).  Each request is routed at submission, by its stored entries, to one
+ * of three paths: at most small_max_entries go to the batched path, which packs
+ * everything queued, whenever its previous batch has completed, into one tc_count_batch
+ * launch; larger requests run through tc_count, those below large_min_entries in
+ * arrival order (medium path) and the rest smallest first (large path; one that has
+ * waited 2 s since submission goes next), so that no request waits behind the upload of
+ * a much larger one.  The paths' uploads overlap with each other and with the counting;
+ * the counting runs one job at a time, the device going to the waiting path of smallest
+ * jobs first (batched, medium, large) unless another has waited 0.5 s for it.  Each path
+ * keeps one device buffer for its jobs, grown when a job needs more, so that a steady
+ * stream of requests allocates nothing; the buffers are held against the HBM budget (a
+ * path that must grow waits, in the order the paths asked, while the new size does not
+ * fit beside the other paths' buffers, which they give back when idle or after their
+ * current job).  A request's job starts (its admit time) once its path has its buffer;
+ * queued requests hold no device memory.  Results equal tc_count's.  Each server drives
+ * the device that is current at tc_serve_create with three host threads and three
+ * non-blocking streams of default priority; its tc_count calls keep to those streams (no
+ * second stream per call) and take their workspace from the path's buffer.
  */
 typedef struct tc_server tc_server;
 
@@ -241,15 +246,21 @@ typedef struct {
   uint32_t path;               /* 0 batched, 1 single-graph (medium), 3 single-graph
                                   (large), 2 rejected at submission                      */
   uint64_t input_edges;        /* m / 2                                                   */
-  double submit_s, admit_s, done_s;  /* server clock, seconds since tc_serve_create       */
+  double submit_s, admit_s, count_s, done_s;
+                               /* server clock, seconds since tc_serve_create: submitted,
+                                  job started (memory reserved, upload begins), counting
+                                  took the device, result ready                          */
 } tc_serve_result;
 
 typedef struct {
   uint64_t submitted, completed, rejected;
   uint64_t batches, singles;   /* launches of each path                                   */
-  uint64_t queued;             /* waiting for admission                                   */
+  uint64_t queued;             /* submitted and not yet started                           */
   uint64_t in_flight;          /* submitted and not yet completed                         */
-  uint64_t hbm_in_use, hbm_peak, hbm_budget;  /* admitted footprint, bytes                */
+  uint64_t hbm_in_use, hbm_peak, hbm_budget;  /* bytes of the paths' buffers             */
+  double busy_s[3];            /* seconds each path spent running jobs (start to result):
+                                  batched, medium, large                                  */
+  double device_s[3];          /* of which holding the device for counting                */
 } tc_serve_stats;
 
 /* Creates a server on the current device; `cfg` may be NULL (all defaults). */
@@ -271,6 +282,14 @@ int tc_serve_create(const tc_serve_config* cfg, tc_server** out);
  */
 int tc_serve_submit(tc_server* server, const uint32_t* rowptr, const uint32_t* colidx,
                     uint32_t n, uint64_t m, uint64_t* ticket);
+
+/*
+ * Device bytes a request of n vertices and m stored entries needs when its job runs
+ * alone (its path's buffer: CSR, bounds flag or offsets, counting workspace), under the
+ * current counting settings; a request above the budget is rejected at submission.
+ * Returns TC_ERR_TOO_LARGE as tc_serve_submit would.
+ */
+int tc_serve_footprint(const tc_server* server, uint32_t n, uint64_t m, uint64_t* bytes);
 
 /*
  * Moves up to `cap` completed results (completion order) into the HOST array `out`;

@@ -25,6 +25,14 @@ namespace tc {
 
 thread_local tc_call_info t_last_info{};  // see tc_last_call_info
 thread_local bool t_side_on = true;  // see set_thread_side_stream
+
+// A caller's device arena from which the calling thread's calls take their workspaces in
+// place of the stream-ordered allocator (see set_thread_arena).
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+};
+thread_local Arena t_arena;
 void set_thread_side_stream(bool on) { t_side_on = on; }
 
 
@@ -135,8 +143,9 @@ std::mutex g_coop_mu;  // serialises the cooperative BFS launches of concurrent 
 struct DevAlloc {
   void* p = nullptr;
   hipStream_t s = nullptr;
+  bool owned = false;  // false: taken from the thread's arena
   ~DevAlloc() {
-    if (p) hipFreeAsync(p, s);
+    if (p && owned) hipFreeAsync(p, s);
   }
 };
 
@@ -155,7 +164,16 @@ struct DevAlloc {
 
 int alloc_async(DevAlloc& a, size_t bytes, hipStream_t s) {
   a.s = s;
-  hipError_t e = hipMallocAsync(&a.p, bytes ? bytes : 256, s);
+  if (bytes == 0) bytes = 256;
+  if (t_arena.base) {
+    const size_t off = (t_arena.used + 255) / 256 * 256;
+    if (off > t_arena.size || bytes > t_arena.size - off) return TC_ERR_OUT_OF_MEMORY;
+    a.p = t_arena.base + off;
+    t_arena.used = off + bytes;
+    return TC_OK;
+  }
+  a.owned = true;
+  hipError_t e = hipMallocAsync(&a.p, bytes, s);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     a.p = nullptr;
@@ -594,6 +612,12 @@ int check_args(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint6
 }  // namespace
 
 IsectParams current_isect_params() { return g_params; }
+
+void set_thread_arena(void* base, size_t bytes) {
+  t_arena.base = base ? static_cast<char*>(base) : nullptr;
+  t_arena.size = base ? bytes : 0;
+  t_arena.used = 0;
+}
 
 size_t single_call_bytes(u32 n, u64 m) {
   const IsectParams prm = g_params;

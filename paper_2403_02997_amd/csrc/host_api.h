@@ -22,4 +22,12 @@ void set_thread_side_stream(bool on);
 // workspace and its workgroup items), under the current settings.
 size_t single_call_bytes(uint32_t n, uint64_t m);
 
+// Until called again with base = nullptr, the calling thread's calls take their device
+// memory from [base, base + bytes), from the start again at every call of this function,
+// instead of allocating it; a call that needs more than is left returns
+// TC_ERR_OUT_OF_MEMORY.  The memory must stay valid, and untouched by other work, while
+// such calls run; their work is ordered on their own stream.  single_call_bytes(n, m)
+// bytes suffice for one tc_count call.
+void set_thread_arena(void* base, size_t bytes);
+
 }  // namespace tc

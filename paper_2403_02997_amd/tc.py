@@ -42,6 +42,7 @@ EXPORTS = (
     "tc_serve_submit",
     "tc_serve_poll",
     "tc_serve_get_stats",
+    "tc_serve_footprint",
     "tc_serve_destroy",
     "tc_validate_csr",
     "tc_set_isect_params",
@@ -129,6 +130,7 @@ class _ServeResult(ctypes.Structure):
         ("input_edges", ctypes.c_uint64),
         ("submit_s", ctypes.c_double),
         ("admit_s", ctypes.c_double),
+        ("count_s", ctypes.c_double),
         ("done_s", ctypes.c_double),
     ]
 
@@ -136,7 +138,8 @@ class _ServeResult(ctypes.Structure):
 class _ServeStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "submitted", "completed", "rejected", "batches", "singles", "queued", "in_flight",
-        "hbm_in_use", "hbm_peak", "hbm_budget")]
+        "hbm_in_use", "hbm_peak", "hbm_budget")] + [("busy_s", ctypes.c_double * 3),
+                                                    ("device_s", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -178,6 +181,8 @@ def load() -> ctypes.CDLL:
     lib.tc_serve_submit.restype = i
     lib.tc_serve_poll.argtypes = [vp, P(_ServeResult), u32, P(u32), ctypes.c_int32]
     lib.tc_serve_poll.restype = i
+    lib.tc_serve_footprint.argtypes = [vp, u32, u64, P(u64)]
+    lib.tc_serve_footprint.restype = i
     lib.tc_serve_get_stats.argtypes = [vp, P(_ServeStats)]
     lib.tc_serve_get_stats.restype = i
     lib.tc_serve_destroy.argtypes = [vp]
@@ -472,7 +477,8 @@ class ServeResult:
     path: int  # 0 batched, 1 single-graph medium, 3 single-graph large, 2 rejected
     input_edges: int
     submit_s: float
-    admit_s: float
+    admit_s: float  # job started: device memory reserved, upload begins
+    count_s: float  # the count took the device
     done_s: float
 
     @property
@@ -529,13 +535,24 @@ class Server:
             self._held.pop(int(r.ticket), None)
             out.append(ServeResult(int(r.ticket), int(r.triangles), int(r.status), int(r.path),
                                    int(r.input_edges), float(r.submit_s), float(r.admit_s),
-                                   float(r.done_s)))
+                                   float(r.count_s), float(r.done_s)))
         return out
+
+    def footprint(self, n: int, m: int) -> int:
+        """Device bytes a request of n vertices and m stored entries needs alone."""
+        b = ctypes.c_uint64(0)
+        _check(load().tc_serve_footprint(self._h, int(n), int(m), ctypes.byref(b)),
+               "tc_serve_footprint")
+        return int(b.value)
 
     def stats(self) -> dict:
         st = _ServeStats()
         _check(load().tc_serve_get_stats(self._h, ctypes.byref(st)), "tc_serve_get_stats")
-        return {k: int(getattr(st, k)) for k, _ in _ServeStats._fields_}
+        out = {k: int(getattr(st, k)) for k, _ in _ServeStats._fields_[:-2]}
+        for k in ("busy_s", "device_s"):
+            a = getattr(st, k)
+            out[k] = {"batched": float(a[0]), "medium": float(a[1]), "large": float(a[2])}
+        return out
 
     def close(self) -> None:
         if self._h:
