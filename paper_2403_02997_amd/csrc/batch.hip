@@ -350,7 +350,10 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
       vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | degree_class(rp[v + 1] - rp[v]));
     __syncthreads();
 
-    // ---- 4. level split and partner lists (split[] local, arrays at cb) ----
+    // ---- 4. level split and partner lists (split[] and sabove[] local, arrays at cb) ----
+    // sabove[v]: the first entry of v's same-level part above v (the union-find parents
+    // are dead once the BFS has found the roots)
+    u32* const sabove = parent;
     {
       const u32 nr = (n + kWave - 1) / kWave * kWave;
       for (u32 v = threadIdx.x; v < nr; v += kBT) {
@@ -365,10 +368,11 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
 #pragma unroll
         for (u32 b = 0; b < kSplitLane / 8; ++b) more[b] = __ballot(short_row && d > b * 8) != 0;
         if (short_row) {
-          u32 ns, nh;
+          u32 ns, nh, sr;
           split_short_row(A.colidx_cat, vinfo, v, vx, cb + lo, d, more, A.colidx2_all,
-                          A.hadj_all, &ns, &nh);
+                          A.hadj_all, &ns, &nh, &sr);
           split[v] = lo + ns;
+          sabove[v] = lo + sr;
           hcnt[v] = nh;
         }
         const bool lng = d > kSplitWave;
@@ -380,22 +384,23 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           mm &= mm - 1;
           const u32 bv = __shfl(v, b, kWave), blo = __shfl(lo, b, kWave);
           const u32 bd = __shfl(d, b, kWave), bvx = __shfl(vx, b, kWave);
-          u32 ns = 0, nh = 0;
+          u32 ns = 0, nh = 0, sr = 0;
           if (bd <= kSplitReg) {
             split_wave_row(A.colidx_cat, vinfo, bv, bvx, cb + blo, bd, A.colidx2_all, A.hadj_all,
-                           &ns, &nh);
+                           &ns, &nh, &sr);
           } else {
             u32 no = 0;
             for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
               split_steps<true>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, 0, 0,
-                                A.colidx2_all, A.hadj_all, ns, no, nh);
-            u32 cs = 0, co = 0, ch = 0;
+                                A.colidx2_all, A.hadj_all, ns, no, nh, sr);
+            u32 cs = 0, co = 0, ch = 0, cl = 0;
             for (u32 j0 = 0; j0 < bd; j0 += kWave * kSplitUnroll)
               split_steps<false>(A.colidx_cat, vinfo, bv, bvx, cb + blo, j0, bd, 0, ns, 0,
-                                 A.colidx2_all, A.hadj_all, cs, co, ch);
+                                 A.colidx2_all, A.hadj_all, cs, co, ch, cl);
           }
           if ((int)lane == b) {
             split[bv] = blo + ns;
+            sabove[bv] = blo + sr;
             hcnt[bv] = nh;
           }
         }
@@ -409,16 +414,17 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
         const u32 step = kWave * kSplitUnroll;
         const u32 segw = (d + kBW * step - 1) / (kBW * step) * step;
         const u32 j0 = min(wid * segw, d), j1 = min(j0 + segw, d);
-        u32 ns = 0, no = 0, nh = 0;
+        u32 ns = 0, no = 0, nh = 0, sr = 0;
         for (u32 j = j0; j < j1; j += step)
           split_steps<true>(A.colidx_cat, vinfo, v, vx, cb + lo, j, j1, 0, 0, 0, A.colidx2_all,
-                            A.hadj_all, ns, no, nh);
+                            A.hadj_all, ns, no, nh, sr);
         if (lane == 0) {
           s_mark[wid] = ns;
           s_mark[kBW + wid] = nh;
+          s_mark[2 * kBW + wid] = sr;
         }
         __syncthreads();
-        u32 bs = 0, bh = 0, ts = 0, th = 0;
+        u32 bs = 0, bh = 0, ts = 0, th = 0, tsr = 0;
         for (u32 w = 0; w < (u32)kBW; ++w) {
           if (w < wid) {
             bs += s_mark[w];
@@ -426,13 +432,15 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           }
           ts += s_mark[w];
           th += s_mark[kBW + w];
+          tsr += s_mark[2 * kBW + w];
         }
-        u32 cs = 0, co = 0, ch = 0;
+        u32 cs = 0, co = 0, ch = 0, cl = 0;
         for (u32 j = j0; j < j1; j += step)
           split_steps<false>(A.colidx_cat, vinfo, v, vx, cb + lo, j, j1, bs, ts + (j0 - bs), bh,
-                             A.colidx2_all, A.hadj_all, cs, co, ch);
+                             A.colidx2_all, A.hadj_all, cs, co, ch, cl);
         if (threadIdx.x == 0) {
           split[v] = lo + ts;
+          sabove[v] = lo + tsr;
           hcnt[v] = th;
         }
         __syncthreads();
@@ -446,13 +454,14 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
       if (hcnt[v] > 0 && rp[v + 1] - rp[v] <= prm.lane_max)
         lane_vertex<false>(rp, cb, A.colidx_cat, vinfo, hcnt, A.hadj_all, v, c, nullptr);
 
-    // ---- 5b. wavefront class: 16 wavefront tables in the workgroup table ----
+    // ---- 5b. wavefront class, pruned: 16 wavefront tables in the workgroup table ----
     // A wavefront claims 64 vertices at once and reads their row bounds, partner counts
-    // and split points in one load per lane.  Vertices of up to kSubMax entries are then
+    // and sabove points in one load per lane.  Vertices of up to kSubMax entries are then
     // taken four at a time, one per group of 16 lanes (subwave_vertex, each group with a
     // quarter of the wavefront's table); longer ones one at a time with the whole
-    // wavefront (wave_vertex).  Staged and streamed rows are the level-split rows, whose
-    // positions give the level flags.
+    // wavefront (wave_vertex).  Each x stages its level-split row from sabove[x] on (its
+    // other-level neighbours and same-level ones above x) as plain keys; each partner y
+    // streams its split row from sabove[y] on, and every hit is a counted apex.
     {
       const u32 sub_max = min(kSubMax, prm.wave_max);
       while (true) {
@@ -469,7 +478,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const bool cls = np > 0 && d > prm.lane_max && d <= prm.wave_max;
           sub = cls && d <= sub_max;
           whole = cls && !sub;
-          if (cls) mt = WaveMeta{cb + lo, cb + hi, cb + split[x], np};
+          if (cls) mt = WaveMeta{cb + lo, cb + hi, cb + sabove[x], np};
         }
         u64 todo = __ballot(sub);
         u32* gtab = s_table + wid * kWaveSlots + (lane / kSubLanes) * kSubSlots;
@@ -488,8 +497,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const u32 gx = (u32)__shfl(x, s0, kWave);
           if (src < 0) gm = WaveMeta{0, 0, 0, 0};
           Tally tl{0, 0, 0, 0};
-          subwave_vertex<false>(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, nullptr, gx, gm,
-                                gtab, tl, c);
+          subwave_vertex<kPartAbove>(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, nullptr,
+                                     sabove, gx, gm, gtab, tl, c);
           tl.fold(c);
         }
         todo = __ballot(whole);
@@ -499,9 +508,9 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const WaveMeta mb{(u32)__shfl(mt.bx, b, kWave), (u32)__shfl(mt.ex, b, kWave),
                             (u32)__shfl(mt.sb, b, kWave), (u32)__shfl(mt.np, b, kWave)};
           Tally tl{0, 0, 0, 0};
-          wave_vertex<false, true, false, 1, false, true>(
+          wave_vertex<false, true, false, 1, false, false, true>(
               rp, cb, A.colidx2_all, A.m_total, A.tail4, vinfo, hcnt, A.hadj_all, nullptr,
-              nullptr, (u32)__shfl(x, b, kWave), mb, s_table + wid * kWaveSlots,
+              sabove, (u32)__shfl(x, b, kWave), mb, s_table + wid * kWaveSlots,
               s_pinfo + wid * kWave, s_qincl + wid * kWave, s_mark + wid * kWave, tl, c, nullptr);
           tl.fold(c);
         }
@@ -510,6 +519,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
     __syncthreads();
 
     // ---- 5c. workgroup class, pruned, over batches of up to 1024 staged vertices ----
+    // x's row from sabove[x] on staged as plain keys, each partner y's row streamed from
+    // sabove[y] on (block_item_rec with kPartAbove)
     {
       Tally tl{0, 0, 0, 0};
       for (u32 base = 0; base < n; base += kBT) {
@@ -525,9 +536,9 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           for (u32 sg = 0; sg < nseg; ++sg)
             // colidx2 carries 4 padding entries, so its quad loads never need a tail copy
             // (two windows per wavefront keep the whole kernel within its registers)
-            block_item<false, VEC, true, 1, 2>(rp, cb, A.colidx_cat, A.m_total, A.tail4,
-                                               A.colidx2_all, A.m_total + 4, split, A.tail4, vinfo,
-                                               hcnt, A.hadj_all, x, sg, prm, sh, tl, c, nullptr);
+            block_item_rec<VEC, true, false, kPartAbove, 2>(
+                rp, cb, A.colidx2_all, A.m_total, A.tail4, split, sabove, hcnt, nullptr,
+                A.hadj_all, x, sg, prm, sh, tl, c);
         }
         __syncthreads();  // s_mark is rewritten by the next batch
       }

@@ -98,7 +98,8 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
                     (u32)__shfl(mt.sb, s0, kWave), (u32)__shfl(mt.np, s0, kWave)};
         if (src < 0) gm = WaveMeta{0, 0, 0, 0};
         Tally tl{0, 0, 0, 0};
-        subwave_vertex<true>(rowptr, 0u, colidx, m, nullptr, hrec, 0u, gm, gtab, tl, c);
+        subwave_vertex<kPartRec>(rowptr, 0u, colidx, m, nullptr, hrec, nullptr, 0u, gm, gtab,
+                                 tl, c);
         tl.fold(c);
       }
       todo = __ballot(live && !sub);
@@ -185,12 +186,11 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     if (it >= nitems) break;
     const Item item = items[it];
     if (PRUNED)
-      block_item_rec<VEC, true, ST>(rowptr, colidx2, m, tail4b, split, sabove, hcnt, hrec,
-                                    item.x, item.seg, prm, sh, tl, c);
+      block_item_rec<VEC, true, ST>(rowptr, 0u, colidx2, m, tail4b, split, sabove, hcnt, hrec,
+                                    nullptr, item.x, item.seg, prm, sh, tl, c);
     else
-      block_item<PV, VEC, false, 4>(rowptr, 0u, colidx, m, tail4, colidx2, m, split, tail4b,
-                                    vinfo, hcnt, record_ids(hrec), item.x, item.seg, prm, sh, tl,
-                                    c, tri);
+      block_item<PV, VEC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
+                             item.x, item.seg, prm, sh, tl, c, tri);
     tl.fold(c);
   }
   block_flush_counts(c, 2, ctr, s_red);

@@ -103,7 +103,12 @@ __device__ __forceinline__ WaveMeta wave_meta(const u32* __restrict__ rowptr,
 // other-level part) and its partner count, so an entry's level flag is its position in
 // the row (no level gathers); the first 64 partners and their row bounds are loaded
 // before the staged set is built.
-template <bool PV, bool VEC, bool REC = false, int HS = 1, bool ST = false, bool SR = false>
+// SA: the pruned count over the level-split rows with a plain partner list: mt as with
+// SR but mt.sb = sabove[x], x's entries from there on staged as plain keys, each partner
+// y's row streamed from sabove[y] (graph-local, like rowptr) to its end, membership only
+// (the hits are those of the records' ranges, see kPartAbove).
+template <bool PV, bool VEC, bool REC = false, int HS = 1, bool ST = false, bool SR = false,
+          bool SA = false>
 __device__ __forceinline__ void wave_vertex(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
@@ -114,22 +119,25 @@ __device__ __forceinline__ void wave_vertex(
   static_assert(!(REC && PV), "per-vertex counts use the full form");
   static_assert(!ST || REC, "split statistics come from the partner records");
   static_assert(!(SR && (REC || PV || HS != 1)), "split rows: full form over plain partner lists");
-  constexpr bool MT = REC || SR;   // row data from mt
-  constexpr u32 NE = VEC ? 4 : 1;  // elements per quad
+  static_assert(!(SA && (REC || SR || PV || HS != 1)), "sabove ranges: plain partner lists");
+  constexpr bool MT = REC || SR || SA;  // row data from mt
+  constexpr bool KEYS = REC || SA;      // pruned: plain staged keys, membership count
+  constexpr bool PL = SR || SA;         // plain partner list, first 64 partners ahead
+  constexpr u32 NE = VEC ? 4 : 1;       // elements per quad
   const u32 lane = lane_id();
   const u64 le = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
   const u32 bx = MT ? mt.bx : cb + rowptr[x], ex = MT ? mt.ex : cb + rowptr[x + 1];
-  const u32 sb = REC ? mt.sb : bx;  // first staged entry
-  const u32 sp = SR ? mt.sb : 0u;   // SR: first other-level entry of x's row
+  const u32 sb = KEYS ? mt.sb : bx;  // first staged entry
+  const u32 sp = SR ? mt.sb : 0u;    // SR: first other-level entry of x's row
   const u32 dx = ex - sb;
   const u32 hs = bx, np = MT ? mt.np : hcnt[x];  // H+(x) sits in place of N(x)
   const u32 px = MT ? 0u : vinfo[x] & 0x80u;
   uint4 r0 = make_uint4(0, 0, 0, 0);  // REC: the first batch of partner records
   if (REC && lane < np) r0 = hrec[hs + lane];
-  u32 y0 = 0, lo0 = 0, hi0 = 0;       // SR: the first batch of partners and their rows
-  if (SR && lane < np) {
+  u32 y0 = 0, lo0 = 0, hi0 = 0;       // PL: the first batch of partners and their rows
+  if (PL && lane < np) {
     y0 = hadj[hs + lane];
-    lo0 = cb + rowptr[y0];
+    lo0 = cb + (SA ? sabove[y0] : rowptr[y0]);
     hi0 = cb + rowptr[y0 + 1];
   }
   const u32 mask = bucket_mask(dx, kWaveSlots);
@@ -138,7 +146,7 @@ __device__ __forceinline__ void wave_vertex(
   wave_lds_sync();
   for (u32 i = lane; i < dx; i += kWave) {
     const u32 w = colidx[sb + i];
-    if (REC) {
+    if (KEYS) {
       hash_insert_key(table, mask, w, w);
     } else if (SR) {
       hash_insert(table, mask, w, sb + i < sp ? 1u : 0u);
@@ -157,13 +165,13 @@ __device__ __forceinline__ void wave_vertex(
         y = ST ? r.y : r.w;  // the pruned form never reads y; ST keeps the range split there
         lo = r.x;
         hi = r.z;
-      } else if (SR && pb == 0) {
+      } else if (PL && pb == 0) {
         y = y0;
         lo = lo0;
         hi = hi0;
       } else {
         y = hadj[(size_t)(hs + p) * HS];
-        lo = cb + rowptr[y];
+        lo = cb + (SA ? sabove[y] : rowptr[y]);
         hi = cb + rowptr[y + 1];
       }
     }
@@ -235,7 +243,7 @@ __device__ __forceinline__ void wave_vertex(
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) sm[i] = addr[u] + i < inf[u].w;
           hash_count_split_n<NE, true>(table, mask, e[u], ok, sm, tl.s, tl.t2);
-        } else if (REC) {
+        } else if (KEYS) {
           hash_count_n<NE>(table, mask, e[u], ok, tl.s);
         } else {
           u32 res[NE];
@@ -258,12 +266,21 @@ __device__ __forceinline__ void wave_vertex(
 // its staged entries go to the group's 256-slot LDS hash set, its partners' ranges are
 // streamed 16 partners at a time, 4 quads per lane in flight, and the owner of a quad is
 // found by a binary search over the group's quad prefix sums (cross-lane reads, no LDS
-// marks).  REC = false (batched, level-split rows): x's split row staged with level
-// flags by position (mt.sb = its first other-level entry), each partner's whole split
-// row streamed, full form (c1, c2, t2).  REC = true (single graph, pruned count): x's
-// entries from mt.sb = sabove[x] on staged as plain keys, each partner record's range
-// .x .. .z streamed, membership only (every hit a counted apex, in tl.s).  All 64 lanes
-// call it together; a group without a vertex passes mt.np = 0 and an empty row.
+// marks).  Where the partners and their ranges come from (PM):
+//   kPartFull  : plain partner list hadj (level-split rows): x's split row staged with
+//                level flags by position (mt.sb = its first other-level entry), each
+//                partner's whole split row streamed, full form (c1, c2, t2);
+//   kPartRec   : partner records hrec (pruned count): x's entries from mt.sb = sabove[x]
+//                on staged as plain keys, each record's range .x .. .z streamed,
+//                membership only (every hit a counted apex, in tl.s);
+//   kPartAbove : plain partner list hadj with per-vertex sabove (pruned count): staged as
+//                kPartRec, each partner y's row streamed from sabove[y], its first
+//                same-level entry above y, to its end, membership only.  For x > y the
+//                range also holds y's same-level entries in (y, x], which the staged
+//                keys (same-level ones above x only) never match, so the hits are the
+//                same as with the range from above max(x, y).
+// All 64 lanes call it together; a group without a vertex passes mt.np = 0 and an empty
+// row.
 constexpr u32 kSubLanes = 16;
 constexpr u32 kSubGroups = kWave / kSubLanes;
 constexpr u32 kSubMax = 64;     // d(x) of the sub-wavefront class at most
@@ -287,14 +304,19 @@ __device__ __forceinline__ u32 wave_max_u32(u32 v) {
   return v;
 }
 
-// colidx2 has 4 readable entries past m; table is this group's kSubSlots slots.
-template <bool REC>
+enum PartnerMode { kPartFull = 0, kPartRec = 1, kPartAbove = 2 };
+
+// colidx2 has 4 readable entries past m; table is this group's kSubSlots slots; sabove
+// (kPartAbove) is local to the graph like rowptr.
+template <int PM>
 __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u32 cb,
                                                const u32* __restrict__ colidx2, u32 m,
                                                const u32* __restrict__ hadj,
-                                               const uint4* __restrict__ hrec, u32 x,
+                                               const uint4* __restrict__ hrec,
+                                               const u32* __restrict__ sabove, u32 x,
                                                const WaveMeta& mt, u32* table, Tally& tl,
                                                Counts& c) {
+  constexpr bool REC = PM != kPartFull;  // pruned: plain keys, membership count
   const u32 lane = lane_id(), gl = lane & (kSubLanes - 1), gb = lane & ~(kSubLanes - 1);
   const u32 bx = mt.bx, np = mt.np;
   const u32 sb = REC ? mt.sb : bx;  // first staged entry
@@ -314,13 +336,13 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
     const u32 p = b * kSubLanes + gl;
     u32 y = 0, lo = 0, hi = 0;
     if (p < np) {
-      if (REC) {
+      if (PM == kPartRec) {
         const uint4 r = hrec[bx + p];  // the records sit in place of N(x)
         lo = r.x;
         hi = r.z;
       } else {
         y = hadj[bx + p];
-        lo = cb + rowptr[y];
+        lo = cb + (PM == kPartAbove ? sabove[y] : rowptr[y]);
         hi = cb + rowptr[y + 1];
       }
     }
@@ -394,9 +416,6 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
 // What one pass of the workgroup kernel stages, streams and tallies:
 //   kFull     : N(x) with level flags; each partner's whole list; c1, c2 and t2
 //               (diagnostics and per-vertex counts);
-//   kPrunedOne: N(x) with level flags in one chunk; each partner's same-level
-//               neighbours above max(x, y) and its other-level ones (one contiguous
-//               range of the level-split rows); c1 and t2;
 //   kOther    : the other-level part of N(x); each partner's other-level part (hits
 //               are the other-level apexes);
 //   kSame     : the same-level part of N(x) above x; each partner's same-level part
@@ -408,7 +427,7 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
 // kMember stage plain IDs, probe for membership only; kSame adds its hits to t2, kOther
 // and kMember to s (with ST, kMember's hits in the range before the split point carried
 // in place of y go to t2).
-enum BlockMode { kFull = 0, kPrunedOne = 1, kOther = 2, kSame = 3, kMember = 4 };
+enum BlockMode { kFull = 0, kOther = 1, kSame = 2, kMember = 3 };
 
 struct BlockShared {
   u32* table;
@@ -428,10 +447,8 @@ constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
 // PAD: the streamed array has at least 4 readable entries past its m counted ones, so
 // every live quad is read in place and dead lanes only clamp their address.
 // QU windows of 64 quads per wavefront are loaded before probing.
-// SPOS (kPrunedOne): the staged keys are a level-split row and px is the position in ga
-// of its first other-level entry, so a key's level flag is its position (no gathers).
 template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false, int QU = kQuadUnroll,
-          bool ST = false, bool SPOS = false>
+          bool ST = false>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
@@ -440,7 +457,6 @@ __device__ __forceinline__ void block_pass(
   const u32 tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   static_assert(!BM || MODE == kOther || MODE == kSame, "bitmaps hold membership only");
   static_assert(!ST || MODE == kMember, "only the one-chunk member pass mixes both kinds");
-  static_assert(!SPOS || MODE == kPrunedOne, "position flags: one chunk of a split row");
   constexpr bool MEMBER = MODE == kOther || MODE == kSame || MODE == kMember;
   u32& hits = MODE == kSame ? tl.t2 : tl.s;  // same-level apexes above both ends: t2
   const u32 glen = ge - gs;
@@ -493,8 +509,7 @@ __device__ __forceinline__ void block_pass(
         if (MEMBER) {
           hash_insert_key(sh.table, mask, w, w);
         } else {
-          const bool same = SPOS ? c0 + i < px
-                                 : (MODE == kFull || MODE == kPrunedOne) && (vinfo[w] & 0x80u) == px;
+          const bool same = MODE == kFull && (vinfo[w] & 0x80u) == px;
           hash_insert(sh.table, mask, w, same ? 1u : 0u);
         }
       }
@@ -610,24 +625,17 @@ __device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32
   return wins < (e - s + chunk - 1) / chunk;
 }
 
-// One work item: staged vertex x, partner segment `seg` (all threads call it together).
-// PRUNED = false: one kFull pass over colidx.  PRUNED = true: the level-split rows
-// colidx2 (split[v] = local start of v's other-level neighbours): when N(x) fits one
-// chunk, one kPrunedOne pass of x's split row (level flags by position) against each
-// partner's same-level entries above max(x, y) and its other-level ones, else a kOther
-// and a kSame pass over the same ranges.  (Streaming the partners' whole rows instead,
-// with the apex rule per hit, saves the searches but measured slower.)  m / m2 bound the quad loads
-// from colidx / colidx2 (beyond them the padded copies tail4 / tail4b are read).
-template <bool PV, bool VEC, bool PRUNED, int HS = 1, int QU = kQuadUnroll>
+// One work item of the full form: staged vertex x, partner segment `seg` (all threads
+// call it together), one kFull pass over colidx.  m bounds the quad loads from colidx
+// (beyond it the padded copy tail4 is read).
+template <bool PV, bool VEC, int HS = 1, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
-    const u32* __restrict__ tail4, const u32* __restrict__ colidx2, u32 m2,
-    const u32* __restrict__ split, const u32* __restrict__ tail4b,
-    const uint8_t* __restrict__ vinfo, const u32* __restrict__ hcnt,
-    const u32* __restrict__ hadj, u32 x, u32 seg, IsectParams prm, const BlockShared& sh,
-    Tally& tl, Counts& c, u64* __restrict__ tri) {
+    const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
+    const u32* __restrict__ hcnt, const u32* __restrict__ hadj, u32 x, u32 seg, IsectParams prm,
+    const BlockShared& sh, Tally& tl, Counts& c, u64* __restrict__ tri) {
   const u32 tid = threadIdx.x;
-  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1], dx = ex - bx;
+  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
   const u32 px = vinfo[x] & 0x80u;
   const u32 hs = bx + seg * prm.seg;  // H+(x) sits in place of N(x)
   const u32 pn = min(prm.seg, hcnt[x] - seg * prm.seg);
@@ -637,77 +645,63 @@ __device__ __forceinline__ void block_item(
     yr = cb + rowptr[y];
     ye = cb + rowptr[y + 1];
   }
-  if (!PRUNED) {
-    block_pass<PV, VEC, kFull, false, false, QU>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px,
-                                                 y, pn, yr, ye, prm, sh, tl, c, tri);
-  } else {
-    u32 ys = 0, lb = 0;
-    if (tid < pn) {
-      ys = cb + split[y];
-      lb = lower_bound_g(colidx2, yr, ys, max(x, y) + 1u);  // same-level part above max
-    }
-    const u32 sx = cb + split[x];
-    if (dx <= prm.chunk) {
-      block_pass<false, true, kPrunedOne, false, false, QU, false, true>(
-          colidx2, m2, tail4b, colidx2, bx, ex, vinfo, x, sx, y, pn, lb, ye, prm, sh, tl, c, tri);
-    } else {
-      const u32 gx = lower_bound_g(colidx2, bx, sx, x + 1u);  // same-level part above x
-      // bitmap windows where they need fewer passes than hash chunks
-      if (use_bitmap(colidx2, sx, ex, prm.chunk))
-        block_pass<false, VEC, kOther, true, false, QU>(colidx2, m2, tail4b, colidx2, sx, ex, vinfo,
-                                                        x, px, y, pn, ys, ye, prm, sh, tl, c, tri);
-      else
-        block_pass<false, VEC, kOther, false, false, QU>(colidx2, m2, tail4b, colidx2, sx, ex,
-                                                         vinfo, x, px, y, pn, ys, ye, prm, sh, tl,
-                                                         c, tri);
-      if (use_bitmap(colidx2, gx, sx, prm.chunk))
-        block_pass<false, VEC, kSame, true, false, QU>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo,
-                                                       x, px, y, pn, lb, ys, prm, sh, tl, c, tri);
-      else
-        block_pass<false, VEC, kSame, false, false, QU>(colidx2, m2, tail4b, colidx2, gx, sx, vinfo,
-                                                        x, px, y, pn, lb, ys, prm, sh, tl, c, tri);
-    }
-  }
+  block_pass<PV, VEC, kFull, false, false, QU>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y,
+                                               pn, yr, ye, prm, sh, tl, c, tri);
 }
 
-// One work item from partner records (single graph, counting only): x's entries from
-// sabove[x] on are staged once, membership only.  When they fit one chunk, one kMember
-// pass streams each record's range .x .. .z; otherwise a kOther pass (x's other-level
-// part against .y .. .z) and a kSame pass (x's same-level part above x against
-// .x .. .y), each with hash chunks or bitmap windows, whichever takes fewer passes.
-// PAD: colidx2 has 4 readable entries past its m2 counted ones.  ST: the member pass
-// tallies same-level and other-level hits apart (see block_pass).
-template <bool VEC, bool PAD = false, bool ST = false>
+// One work item of the pruned count: x's entries from sabove[x] on are staged once,
+// membership only.  When they fit one chunk, one kMember pass streams each partner's
+// range .x .. .z; otherwise a kOther pass (x's other-level part against .y .. .z) and a
+// kSame pass (x's same-level part above x against .x .. .y), each with hash chunks or
+// bitmap windows, whichever takes fewer passes.  The ranges come from the partner records
+// (PM = kPartRec, single graph) or from the plain partner list with the per-vertex
+// {sabove[y], split[y], end of y's row} (PM = kPartAbove, batched; see kPartAbove for why
+// the hits agree).  rowptr, split and sabove are local to the graph, whose entries start
+// at cb.  PAD: colidx2 has 4 readable entries past its m2 counted ones.  ST (kPartRec):
+// the member pass tallies same-level and other-level hits apart (see block_pass).
+template <bool VEC, bool PAD = false, bool ST = false, int PM = kPartRec, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item_rec(
-    const u32* __restrict__ rowptr, const u32* __restrict__ colidx2, u32 m2,
+    const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx2, u32 m2,
     const u32* __restrict__ tail4b, const u32* __restrict__ split,
     const u32* __restrict__ sabove, const u32* __restrict__ hcnt,
-    const uint4* __restrict__ hrec, u32 x, u32 seg, IsectParams prm, const BlockShared& sh,
-    Tally& tl, Counts& c) {
+    const uint4* __restrict__ hrec, const u32* __restrict__ hadj, u32 x, u32 seg,
+    IsectParams prm, const BlockShared& sh, Tally& tl, Counts& c) {
+  static_assert(PM == kPartRec || (PM == kPartAbove && !ST), "split tallies need records");
   const u32 tid = threadIdx.x;
-  const u32 bx = rowptr[x], ex = rowptr[x + 1];
-  const u32 gx = sabove[x], sx = split[x];
-  const u32 hs = bx + seg * prm.seg;  // the records sit in place of N(x)
+  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
+  const u32 gx = cb + sabove[x], sx = cb + split[x];
+  const u32 hs = bx + seg * prm.seg;  // the partners sit in place of N(x)
   const u32 pn = min(prm.seg, hcnt[x] - seg * prm.seg);
   uint4 r = make_uint4(0, 0, 0, 0);
-  if (tid < pn) r = hrec[hs + tid];
+  if (tid < pn) {
+    if (PM == kPartRec) {
+      r = hrec[hs + tid];
+    } else {
+      const u32 y = hadj[hs + tid];
+      r = make_uint4(cb + sabove[y], cb + split[y], cb + rowptr[y + 1], y);
+    }
+  }
   if (ex - gx <= prm.chunk) {
-    block_pass<false, VEC, kMember, false, PAD, kQuadUnroll, ST>(
+    block_pass<false, VEC, kMember, false, PAD, QU, ST>(
         colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0, ST ? r.y : r.w, pn, r.x, r.z, prm,
         sh, tl, c, nullptr);
   } else {
     if (use_bitmap(colidx2, sx, ex, prm.chunk))
-      block_pass<false, VEC, kOther, true, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x, 0,
-                                           r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
+      block_pass<false, VEC, kOther, true, PAD, QU>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr,
+                                                    x, 0, r.w, pn, r.y, r.z, prm, sh, tl, c,
+                                                    nullptr);
     else
-      block_pass<false, VEC, kOther, false, PAD>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr, x,
-                                                 0, r.w, pn, r.y, r.z, prm, sh, tl, c, nullptr);
+      block_pass<false, VEC, kOther, false, PAD, QU>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr,
+                                                     x, 0, r.w, pn, r.y, r.z, prm, sh, tl, c,
+                                                     nullptr);
     if (use_bitmap(colidx2, gx, sx, prm.chunk))
-      block_pass<false, VEC, kSame, true, PAD>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
-                                          r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
+      block_pass<false, VEC, kSame, true, PAD, QU>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr,
+                                                   x, 0, r.w, pn, r.x, r.y, prm, sh, tl, c,
+                                                   nullptr);
     else
-      block_pass<false, VEC, kSame, false, PAD>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr, x, 0,
-                                           r.w, pn, r.x, r.y, prm, sh, tl, c, nullptr);
+      block_pass<false, VEC, kSame, false, PAD, QU>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr,
+                                                    x, 0, r.w, pn, r.x, r.y, prm, sh, tl, c,
+                                                    nullptr);
   }
 }
 
@@ -722,14 +716,15 @@ constexpr u32 kSplitUnroll = 4;    // 64-entry steps per wavefront iteration
 
 // Partition step over entries j0 .. j0 + 64 kSplitUnroll of the row at `lo` (d entries):
 // counts (COUNT) or writes (!COUNT) the same-level entries, the other-level entries and
-// the partners, advancing the running counts cs / co / ch.
+// the partners, advancing the running counts cs / co / ch, and cl, the same-level entries
+// below v.
 template <bool COUNT>
 __device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
                                             const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
                                             u32 lo, u32 j0, u32 jend, u32 same_base,
                                             u32 other_base, u32 part_base,
                                             u32* __restrict__ colidx2, u32* __restrict__ hadj,
-                                            u32& cs, u32& co, u32& ch) {
+                                            u32& cs, u32& co, u32& ch, u32& cl) {
   const u32 lane = lane_id();
   u32 w[kSplitUnroll], vw[kSplitUnroll];
 #pragma unroll
@@ -754,6 +749,7 @@ __device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
     cs += (u32)__popcll(ms);
     co += (u32)__popcll(mo);
     ch += (u32)__popcll(mh);
+    cl += (u32)__popcll(__ballot(same && w[u] < v));
   }
 }
 
@@ -761,14 +757,14 @@ __device__ __forceinline__ void split_steps(const u32* __restrict__ colidx,
 // loaded before the first vinfo gather and the same-level and partner flags are kept as
 // bit masks, so the row costs one load and one gather round trip.  more[b]
 // (wavefront-uniform) says whether any lane's row is longer than 8 b entries; blocks of
-// 8 past every lane's row are skipped.  Returns the number of same-level entries in *ns
-// and of partners in *nh.
+// 8 past every lane's row are skipped.  Returns the number of same-level entries in *ns,
+// of partners in *nh and of same-level entries below v in *sr.
 __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
                                                 const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
                                                 u32 lo, u32 d, const bool* more,
                                                 u32* __restrict__ colidx2,
                                                 u32* __restrict__ hadj, u32* ns_out,
-                                                u32* nh_out) {
+                                                u32* nh_out, u32* sr_out) {
   constexpr u32 B = 8, NB = kSplitLane / B;
   static_assert(kSplitLane <= 32, "flags are one 32-bit mask per lane");
   u32 w[kSplitLane];
@@ -782,7 +778,7 @@ __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
       }
     }
   }
-  u32 sm = 0, pm = 0;  // same level, partner of v
+  u32 sm = 0, pm = 0, lm = 0;  // same level, partner of v, same level below v
 #pragma unroll
   for (u32 b = 0; b < NB; ++b) {
     if (more[b]) {
@@ -793,6 +789,7 @@ __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
         const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
         sm |= (same ? 1u : 0u) << j;
         pm |= (same && key_less(vw & 127u, w[j], vx & 127u, v) ? 1u : 0u) << j;
+        lm |= (same && w[j] < v ? 1u : 0u) << j;
       }
     }
   }
@@ -815,11 +812,13 @@ __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
   }
   *ns_out = ns;
   *nh_out = (u32)__popc(pm);
+  *sr_out = (u32)__popc(lm);
 }
 
 // A row of kSplitLane < d <= kSplitReg entries by one wavefront, held in registers (lane l
 // holds entries 64 u + l): one load and one gather round trip, then the ballot-ranked
-// writes.  Returns the number of same-level entries in *ns and of partners in *nh.
+// writes.  Returns the number of same-level entries in *ns, of partners in *nh and of
+// same-level entries below v in *sr.
 constexpr u32 kSplitRegU = 16;
 constexpr u32 kSplitReg = kSplitRegU * kWave;
 
@@ -827,7 +826,7 @@ __device__ __forceinline__ void split_wave_row(const u32* __restrict__ colidx,
                                                const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
                                                u32 lo, u32 d, u32* __restrict__ colidx2,
                                                u32* __restrict__ hadj, u32* ns_out,
-                                               u32* nh_out) {
+                                               u32* nh_out, u32* sr_out) {
   constexpr u32 U = kSplitRegU;
   const u32 lane = lane_id();
   const u32 nu = (d + kWave - 1) / kWave;  // wavefront-uniform
@@ -839,7 +838,7 @@ __device__ __forceinline__ void split_wave_row(const u32* __restrict__ colidx,
       w[u] = j < d ? colidx[lo + j] : v;
     }
   }
-  u32 sm = 0, pm = 0;
+  u32 sm = 0, pm = 0, lm = 0;
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
     if (u < nu) {
@@ -848,12 +847,17 @@ __device__ __forceinline__ void split_wave_row(const u32* __restrict__ colidx,
       const bool same = j < d && ((vw ^ vx) & 0x80u) == 0;
       sm |= (same ? 1u : 0u) << u;
       pm |= (same && key_less(vw & 127u, w[u], vx & 127u, v) ? 1u : 0u) << u;
+      lm |= (same && w[u] < v ? 1u : 0u) << u;
     }
   }
-  u32 ns = 0;
+  u32 ns = 0, sr = 0;
 #pragma unroll
-  for (u32 u = 0; u < U; ++u)
-    if (u < nu) ns += (u32)__popcll(__ballot((sm >> u) & 1u));
+  for (u32 u = 0; u < U; ++u) {
+    if (u < nu) {
+      ns += (u32)__popcll(__ballot((sm >> u) & 1u));
+      sr += (u32)__popcll(__ballot((lm >> u) & 1u));
+    }
+  }
   u32 cs = 0, co = 0, ch = 0;
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
@@ -871,6 +875,7 @@ __device__ __forceinline__ void split_wave_row(const u32* __restrict__ colidx,
   }
   *ns_out = ns;
   *nh_out = ch;
+  *sr_out = sr;
 }
 
 }  // namespace tc
