@@ -187,9 +187,12 @@ int alloc_async(DevAlloc& a, size_t bytes, hipStream_t s) {
   return TC_OK;
 }
 
+// lane_max 8: with the pruned wavefront path, rows of 9..16 entries count faster four
+// per wavefront (16-lane groups) than by one lane's full merge (4096-graph batch 108.0 ->
+// 104.8 ms; R-MAT 22, er22 and the grid unchanged; 4 slowed the grid's lane-class edges)
 IsectParams default_params() {
   IsectParams p;
-  p.lane_max = 16;
+  p.lane_max = 8;
   p.wave_max = 512;
   p.chunk = 4096;
   p.seg = 1024;
