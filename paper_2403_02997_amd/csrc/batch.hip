@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           for (u32 sg = 0; sg < nseg; ++sg)
             // colidx2 carries 4 padding entries, so its quad loads never need a tail copy
             // (two windows per wavefront keep the whole kernel within its registers)
-            block_item_rec<VEC, true, false, kPartAbove, 2>(
+            block_item_rec<VEC, true, false, kPartAbove, 4>(
                 rp, cb, A.colidx2_all, A.m_total, A.tail4, split, sabove, hcnt, nullptr,
                 A.hadj_all, x, sg, prm, sh, tl, c);
         }

@@ -230,6 +230,7 @@ __device__ __forceinline__ void wave_vertex(
           e[u][0] = colidx[live[u] ? addr[u] : 0u];
         }
       }
+      if constexpr (SA) __builtin_amdgcn_sched_barrier(0);  // as in subwave_vertex
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const u32 y2 = inf[u].w;
@@ -382,6 +383,11 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
         e[u][2] = v.z;
         e[u][3] = v.w;
       }
+      // batched (kPartAbove): all kSubU loads in flight before the probes; in the fused
+      // kernel's register budget the scheduler otherwise starts hashing the first
+      // window's elements, which waits for its load, before it issues the next one (the
+      // single-graph kernels are scheduled well and measured slower with the barrier)
+      if constexpr (PM == kPartAbove) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (u32 u = 0; u < kSubU; ++u) {
         bool ok[4];
@@ -446,9 +452,10 @@ constexpr u32 kWinBits = 20;  // 2^20 IDs per bitmap window = 128 KB of LDS
 
 // PAD: the streamed array has at least 4 readable entries past its m counted ones, so
 // every live quad is read in place and dead lanes only clamp their address.
-// QU windows of 64 quads per wavefront are loaded before probing.
+// QU windows of 64 quads per wavefront are loaded before probing; FENCE keeps the
+// scheduler from moving probe work between those loads (batched kernel).
 template <bool PV, bool VEC, int MODE, bool BM, bool PAD = false, int QU = kQuadUnroll,
-          bool ST = false>
+          bool ST = false, bool FENCE = false>
 __device__ __forceinline__ void block_pass(
     const u32* __restrict__ sa, u32 m, const u32* __restrict__ st4, const u32* __restrict__ ga,
     u32 gs, u32 ge, const uint8_t* __restrict__ vinfo, u32 x, u32 px, u32 y, u32 pn, u32 plo,
@@ -571,6 +578,7 @@ __device__ __forceinline__ void block_pass(
           e[u][0] = sa[live[u] ? addr[u] : 0u];
         }
       }
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);  // as in subwave_vertex
 #pragma unroll
       for (int u = 0; u < QU; ++u) {
         const u32 y2 = inf[u].w;
@@ -667,6 +675,7 @@ __device__ __forceinline__ void block_item_rec(
     const uint4* __restrict__ hrec, const u32* __restrict__ hadj, u32 x, u32 seg,
     IsectParams prm, const BlockShared& sh, Tally& tl, Counts& c) {
   static_assert(PM == kPartRec || (PM == kPartAbove && !ST), "split tallies need records");
+  constexpr bool kFence = PM == kPartAbove;
   const u32 tid = threadIdx.x;
   const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
   const u32 gx = cb + sabove[x], sx = cb + split[x];
@@ -682,24 +691,24 @@ __device__ __forceinline__ void block_item_rec(
     }
   }
   if (ex - gx <= prm.chunk) {
-    block_pass<false, VEC, kMember, false, PAD, QU, ST>(
+    block_pass<false, VEC, kMember, false, PAD, QU, ST, kFence>(
         colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0, ST ? r.y : r.w, pn, r.x, r.z, prm,
         sh, tl, c, nullptr);
   } else {
     if (use_bitmap(colidx2, sx, ex, prm.chunk))
-      block_pass<false, VEC, kOther, true, PAD, QU>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr,
+      block_pass<false, VEC, kOther, true, PAD, QU, false, kFence>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr,
                                                     x, 0, r.w, pn, r.y, r.z, prm, sh, tl, c,
                                                     nullptr);
     else
-      block_pass<false, VEC, kOther, false, PAD, QU>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr,
+      block_pass<false, VEC, kOther, false, PAD, QU, false, kFence>(colidx2, m2, tail4b, colidx2, sx, ex, nullptr,
                                                      x, 0, r.w, pn, r.y, r.z, prm, sh, tl, c,
                                                      nullptr);
     if (use_bitmap(colidx2, gx, sx, prm.chunk))
-      block_pass<false, VEC, kSame, true, PAD, QU>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr,
+      block_pass<false, VEC, kSame, true, PAD, QU, false, kFence>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr,
                                                    x, 0, r.w, pn, r.x, r.y, prm, sh, tl, c,
                                                    nullptr);
     else
-      block_pass<false, VEC, kSame, false, PAD, QU>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr,
+      block_pass<false, VEC, kSame, false, PAD, QU, false, kFence>(colidx2, m2, tail4b, colidx2, gx, sx, nullptr,
                                                     x, 0, r.w, pn, r.x, r.y, prm, sh, tl, c,
                                                     nullptr);
   }
