@@ -378,7 +378,31 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
         const bool lng = d > kSplitWave;
         const u32 pos = wave_append(&s_cnt, lng);
         if (lng) queue[pos] = v;  // the BFS queue is free again
-        u64 mm = __ballot(d > kSplitLane && d <= kSplitWave);
+        // rows of kSplitLane < d <= kSplitGroup: four at a time, one per 16-lane group
+        u64 mg = __ballot(d > kSplitLane && d <= kSplitGroup);
+        while (mg) {
+          int src = -1;  // the g-th lowest remaining lane for group g
+#pragma unroll
+          for (u32 gi = 0; gi < 4; ++gi) {
+            const int bl = mg ? __ffsll((unsigned long long)mg) - 1 : -1;
+            if (bl >= 0) mg &= mg - 1;
+            if (gi == lane / 16) src = bl;
+          }
+          const int s0 = src < 0 ? 0 : src;
+          // every lane takes part in the shuffles (a source lane outside them reads as 0)
+          const u32 gv = __shfl(v, s0, kWave), glo = __shfl(lo, s0, kWave);
+          const u32 gd0 = __shfl(d, s0, kWave), gvx = __shfl(vx, s0, kWave);
+          const u32 gd = src < 0 ? 0u : gd0;
+          u32 ns, nh, sr;
+          split_group_row(A.colidx_cat, vinfo, gv, gvx, cb + glo, gd, A.colidx2_all, A.hadj_all,
+                          &ns, &nh, &sr);
+          if (src >= 0 && (lane & 15u) == 0) {
+            split[gv] = glo + ns;
+            sabove[gv] = glo + sr;
+            hcnt[gv] = nh;
+          }
+        }
+        u64 mm = __ballot(d > kSplitGroup && d <= kSplitWave);
         while (mm) {
           const int b = __ffsll((unsigned long long)mm) - 1;
           mm &= mm - 1;

@@ -824,6 +824,59 @@ __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
   *sr_out = (u32)__popc(lm);
 }
 
+// A row of kSplitLane < d <= kSplitGroup entries by one group of 16 lanes (four rows per
+// wavefront), held in registers: lane gl of the group holds entries 16 u + gl, u < 4, so
+// the row costs one load and one gather round trip; ranks come from the group's 16 bits
+// of each ballot.  All 64 lanes call it together; a group without a row passes d = 0.
+// Returns the row's same-level entries in *ns, partners in *nh and same-level entries
+// below v in *sr (on every lane of the group).
+constexpr u32 kSplitGroup = 64;
+
+__device__ __forceinline__ void split_group_row(const u32* __restrict__ colidx,
+                                                const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
+                                                u32 lo, u32 d, u32* __restrict__ colidx2,
+                                                u32* __restrict__ hadj, u32* ns_out,
+                                                u32* nh_out, u32* sr_out) {
+  constexpr u32 U = kSplitGroup / 16;
+  const u32 lane = lane_id(), gl = lane & 15u, gb = lane & ~15u;
+  const u32 below = (1u << gl) - 1u;
+  u32 w[U];
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    const u32 j = u * 16 + gl;
+    w[u] = j < d ? colidx[lo + j] : v;
+  }
+  u32 ms[U], mp[U], mo[U];
+  u32 ns = 0, nh = 0, sr = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    const u32 j = u * 16 + gl;
+    const u32 vw = vinfo[w[u]];
+    const bool in = j < d;
+    const bool same = in && ((vw ^ vx) & 0x80u) == 0;
+    const bool part = same && key_less(vw & 127u, w[u], vx & 127u, v);
+    ms[u] = (u32)(__ballot(same) >> gb) & 0xFFFFu;
+    mp[u] = (u32)(__ballot(part) >> gb) & 0xFFFFu;
+    mo[u] = (u32)(__ballot(in && !same) >> gb) & 0xFFFFu;
+    ns += (u32)__popc(ms[u]);
+    nh += (u32)__popc(mp[u]);
+    sr += (u32)__popc((u32)(__ballot(same && w[u] < v) >> gb) & 0xFFFFu);
+  }
+  u32 cs = 0, co = 0, ch = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    if ((ms[u] >> gl) & 1u) colidx2[lo + cs + (u32)__popc(ms[u] & below)] = w[u];
+    else if ((mo[u] >> gl) & 1u) colidx2[lo + ns + co + (u32)__popc(mo[u] & below)] = w[u];
+    if ((mp[u] >> gl) & 1u) hadj[lo + ch + (u32)__popc(mp[u] & below)] = w[u];
+    cs += (u32)__popc(ms[u]);
+    co += (u32)__popc(mo[u]);
+    ch += (u32)__popc(mp[u]);
+  }
+  *ns_out = ns;
+  *nh_out = nh;
+  *sr_out = sr;
+}
+
 // A row of kSplitLane < d <= kSplitReg entries by one wavefront, held in registers (lane l
 // holds entries 64 u + l): one load and one gather round trip, then the ballot-ranked
 // writes.  Returns the number of same-level entries in *ns, of partners in *nh and of
