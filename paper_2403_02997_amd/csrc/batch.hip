@@ -18,7 +18,7 @@
 //      16 wavefront tables), and the pruned workgroup passes for longer lists;
 //   6. counts[g] = c1 + t2.
 //
-// Per-vertex scratch (parent, level, queue, info, partner counts, split points) lives in
+// Per-vertex scratch (parent, level, queue, info, partner counts, row records) lives in
 // the workspace at the graph's row offset, per-entry scratch (level-split rows, partner
 // lists) at its column offset, so graphs never share memory and the call allocates
 // nothing.
@@ -205,10 +205,43 @@ struct BatchArrays {
   u32* queue_all;
   uint8_t* vinfo_all;
   u32* hcnt_all;
-  u32* split_all;
+  uint4* vrec_all;    // per row: {row start, sabove, split, row end}, local to the graph
   u32* colidx2_all;   // m_total + 4 entries (the padding keeps quad loads in bounds)
   u32* hadj_all;
 };
+
+// The wavefront's rows with `sel` (lane's own row v at local offset lo, d entries, info
+// vx), 64 / GL at a time, one per group of GL lanes (split_group_row); writes their row
+// records and partner counts.
+template <u32 GL, u32 U>
+__device__ __forceinline__ void batch_split_groups(const BatchArrays& A, const uint8_t* vinfo,
+                                                   u32 v, u32 lo, u32 d, u32 vx, u32 cb,
+                                                   bool sel, uint4* vrec, u32* hcnt) {
+  constexpr u32 NG = kWave / GL;
+  const u32 lane = lane_id();
+  u64 mg = __ballot(sel);
+  while (mg) {
+    int src = -1;  // the g-th lowest remaining lane for group g
+#pragma unroll
+    for (u32 gi = 0; gi < NG; ++gi) {
+      const int bl = mg ? __ffsll((unsigned long long)mg) - 1 : -1;
+      if (bl >= 0) mg &= mg - 1;
+      if (gi == lane / GL) src = bl;
+    }
+    // every lane takes part in the shuffles (a source lane outside them reads as 0)
+    const int s0 = src < 0 ? 0 : src;
+    const u32 gv = __shfl(v, s0, kWave), glo = __shfl(lo, s0, kWave);
+    const u32 gd0 = __shfl(d, s0, kWave), gvx = __shfl(vx, s0, kWave);
+    const u32 gd = src < 0 ? 0u : gd0;
+    u32 ns, nh, sr;
+    split_group_row<GL, U>(A.colidx_cat, vinfo, gv, gvx, cb + glo, gd, A.colidx2_all, A.hadj_all,
+                           &ns, &nh, &sr);
+    if (src >= 0 && (lane & (GL - 1u)) == 0) {
+      vrec[gv] = make_uint4(glo, glo + sr, glo + ns, glo + gd);
+      hcnt[gv] = nh;
+    }
+  }
+}
 
 template <bool VEC>
 __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
@@ -252,7 +285,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
     u32* queue = A.queue_all + rb;
     uint8_t* vinfo = A.vinfo_all + rb;
     u32* hcnt = A.hcnt_all + rb;
-    u32* split = A.split_all + rb;
+    uint4* vrec = A.vrec_all + rb;
 
     // ---- 1. component roots: sampled union-find, smallest-ID roots ----
     for (u32 v = threadIdx.x; v < n; v += kBT) {
@@ -350,10 +383,9 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
       vinfo[v] = (uint8_t)(((level[v] & 1u) << 7) | degree_class(rp[v + 1] - rp[v]));
     __syncthreads();
 
-    // ---- 4. level split and partner lists (split[] and sabove[] local, arrays at cb) ----
-    // sabove[v]: the first entry of v's same-level part above v (the union-find parents
-    // are dead once the BFS has found the roots)
-    u32* const sabove = parent;
+    // ---- 4. level split and partner lists (vrec[] local, arrays at cb) ----
+    // vrec[v] = {row start, sabove, split, row end}: sabove is the first entry of v's
+    // same-level part above v, split the first of its other-level part
     {
       const u32 nr = (n + kWave - 1) / kWave * kWave;
       for (u32 v = threadIdx.x; v < nr; v += kBT) {
@@ -371,37 +403,17 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           u32 ns, nh, sr;
           split_short_row(A.colidx_cat, vinfo, v, vx, cb + lo, d, more, A.colidx2_all,
                           A.hadj_all, &ns, &nh, &sr);
-          split[v] = lo + ns;
-          sabove[v] = lo + sr;
+          vrec[v] = make_uint4(lo, lo + sr, lo + ns, lo + d);
           hcnt[v] = nh;
         }
         const bool lng = d > kSplitWave;
         const u32 pos = wave_append(&s_cnt, lng);
         if (lng) queue[pos] = v;  // the BFS queue is free again
         // rows of kSplitLane < d <= kSplitGroup: four at a time, one per 16-lane group
-        u64 mg = __ballot(d > kSplitLane && d <= kSplitGroup);
-        while (mg) {
-          int src = -1;  // the g-th lowest remaining lane for group g
-#pragma unroll
-          for (u32 gi = 0; gi < 4; ++gi) {
-            const int bl = mg ? __ffsll((unsigned long long)mg) - 1 : -1;
-            if (bl >= 0) mg &= mg - 1;
-            if (gi == lane / 16) src = bl;
-          }
-          const int s0 = src < 0 ? 0 : src;
-          // every lane takes part in the shuffles (a source lane outside them reads as 0)
-          const u32 gv = __shfl(v, s0, kWave), glo = __shfl(lo, s0, kWave);
-          const u32 gd0 = __shfl(d, s0, kWave), gvx = __shfl(vx, s0, kWave);
-          const u32 gd = src < 0 ? 0u : gd0;
-          u32 ns, nh, sr;
-          split_group_row(A.colidx_cat, vinfo, gv, gvx, cb + glo, gd, A.colidx2_all, A.hadj_all,
-                          &ns, &nh, &sr);
-          if (src >= 0 && (lane & 15u) == 0) {
-            split[gv] = glo + ns;
-            sabove[gv] = glo + sr;
-            hcnt[gv] = nh;
-          }
-        }
+        // (rows of up to 256 entries two at a time in 32-lane halves measured slower)
+        batch_split_groups<16, kSplitGroup / 16>(A, vinfo, v, lo, d, vx, cb,
+                                                 d > kSplitLane && d <= kSplitGroup, vrec,
+                                                 hcnt);
         u64 mm = __ballot(d > kSplitGroup && d <= kSplitWave);
         while (mm) {
           const int b = __ffsll((unsigned long long)mm) - 1;
@@ -423,8 +435,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
                                  A.colidx2_all, A.hadj_all, cs, co, ch, cl);
           }
           if ((int)lane == b) {
-            split[bv] = blo + ns;
-            sabove[bv] = blo + sr;
+            vrec[bv] = make_uint4(blo, blo + sr, blo + ns, blo + bd);
             hcnt[bv] = nh;
           }
         }
@@ -463,8 +474,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           split_steps<false>(A.colidx_cat, vinfo, v, vx, cb + lo, j, j1, bs, ts + (j0 - bs), bh,
                              A.colidx2_all, A.hadj_all, cs, co, ch, cl);
         if (threadIdx.x == 0) {
-          split[v] = lo + ts;
-          sabove[v] = lo + tsr;
+          vrec[v] = make_uint4(lo, lo + tsr, lo + ts, lo + d);
           hcnt[v] = th;
         }
         __syncthreads();
@@ -497,12 +507,13 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
         WaveMeta mt{0, 0, 0, 0};
         bool sub = false, whole = false;
         if (x < n) {
-          const u32 lo = rp[x], hi = rp[x + 1], np = hcnt[x];
-          const u32 d = hi - lo;
+          const uint4 r = vrec[x];
+          const u32 np = hcnt[x];
+          const u32 d = r.w - r.x;
           const bool cls = np > 0 && d > prm.lane_max && d <= prm.wave_max;
           sub = cls && d <= sub_max;
           whole = cls && !sub;
-          if (cls) mt = WaveMeta{cb + lo, cb + hi, cb + sabove[x], np};
+          if (cls) mt = WaveMeta{cb + r.x, cb + r.w, cb + r.y, np};
         }
         u64 todo = __ballot(sub);
         u32* gtab = s_table + wid * kWaveSlots + (lane / kSubLanes) * kSubSlots;
@@ -522,7 +533,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           if (src < 0) gm = WaveMeta{0, 0, 0, 0};
           Tally tl{0, 0, 0, 0};
           subwave_vertex<kPartAbove>(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, nullptr,
-                                     sabove, gx, gm, gtab, tl, c);
+                                     vrec, gx, gm, gtab, tl, c);
           tl.fold(c);
         }
         todo = __ballot(whole);
@@ -534,7 +545,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           Tally tl{0, 0, 0, 0};
           wave_vertex<false, true, false, 1, false, false, true>(
               rp, cb, A.colidx2_all, A.m_total, A.tail4, vinfo, hcnt, A.hadj_all, nullptr,
-              sabove, (u32)__shfl(x, b, kWave), mb, s_table + wid * kWaveSlots,
+              vrec, (u32)__shfl(x, b, kWave), mb, s_table + wid * kWaveSlots,
               s_pinfo + wid * kWave, s_qincl + wid * kWave, s_mark + wid * kWave, tl, c, nullptr);
           tl.fold(c);
         }
@@ -561,8 +572,8 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
             // colidx2 carries 4 padding entries, so its quad loads never need a tail copy
             // (two windows per wavefront keep the whole kernel within its registers)
             block_item_rec<VEC, true, false, kPartAbove, 4>(
-                rp, cb, A.colidx2_all, A.m_total, A.tail4, split, sabove, hcnt, nullptr,
-                A.hadj_all, x, sg, prm, sh, tl, c);
+                rp, cb, A.colidx2_all, A.m_total, A.tail4, nullptr, nullptr, hcnt, nullptr,
+                A.hadj_all, vrec, x, sg, prm, sh, tl, c);
         }
         __syncthreads();  // s_mark is rewritten by the next batch
       }
@@ -590,7 +601,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
 
 // ---- workspace ------------------------------------------------------------------------
 struct BatchLayout {
-  size_t ctl, order, parent, level, queue, vinfo, hcnt, split, colidx2, hadj, tail, bytes;
+  size_t ctl, order, parent, level, queue, vinfo, hcnt, vrec, colidx2, hadj, tail, bytes;
 };
 
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
@@ -605,7 +616,7 @@ static BatchLayout batch_layout(u32 G, u64 rows, u64 cols) {
   L.queue = o; o += up256(rows * 4);
   L.vinfo = o; o += up256(rows);
   L.hcnt = o; o += up256(rows * 4);
-  L.split = o; o += up256(rows * 4);
+  L.vrec = o; o += up256(rows * 16);
   L.colidx2 = o; o += up256((cols + 4) * 4);
   L.hadj = o; o += up256(cols * 4);
   L.tail = o; o += 256;
@@ -637,7 +648,7 @@ void launch_batch(const u32* rowptr_cat, const u32* colidx_cat, const int64_t* r
   A.queue_all = (u32*)(base + L.queue);
   A.vinfo_all = (uint8_t*)(base + L.vinfo);
   A.hcnt_all = (u32*)(base + L.hcnt);
-  A.split_all = (u32*)(base + L.split);
+  A.vrec_all = (uint4*)(base + L.vrec);
   A.colidx2_all = (u32*)(base + L.colidx2);
   A.hadj_all = (u32*)(base + L.hadj);
   hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(256), 0, s, col_off, G, ctl, order);

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
                           (u32)__shfl(mt.sb, b, kWave), (u32)__shfl(mt.np, b, kWave)};
         Tally tl{0, 0, 0, 0};
         wave_vertex<PV, VEC, REC, 4, ST>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt,
-                                         record_ids(hrec), hrec, sabove, (u32)__shfl(x, b, kWave),
+                                         record_ids(hrec), hrec, nullptr, (u32)__shfl(x, b, kWave),
                                          mb, s_table[wid], s_pinfo[wid], s_end[wid], s_mark[wid],
                                          tl, c, tri);
         tl.fold(c);
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
         }
         Tally tl{0, 0, 0, 0};
         wave_vertex<PV, VEC, REC, 4, ST>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
-                                     hrec, sabove, x, mt, s_table[wid], s_pinfo[wid], s_end[wid],
+                                     hrec, nullptr, x, mt, s_table[wid], s_pinfo[wid], s_end[wid],
                                      s_mark[wid], tl, c, tri);
         tl.fold(c);
         if (!more) break;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const Item item = items[it];
     if (PRUNED)
       block_item_rec<VEC, true, ST>(rowptr, 0u, colidx2, m, tail4b, split, sabove, hcnt, hrec,
-                                    nullptr, item.x, item.seg, prm, sh, tl, c);
+                                    nullptr, nullptr, item.x, item.seg, prm, sh, tl, c);
     else
       block_item<PV, VEC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
                              item.x, item.seg, prm, sh, tl, c, tri);

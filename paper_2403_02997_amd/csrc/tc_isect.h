@@ -105,15 +105,15 @@ __device__ __forceinline__ WaveMeta wave_meta(const u32* __restrict__ rowptr,
 // before the staged set is built.
 // SA: the pruned count over the level-split rows with a plain partner list: mt as with
 // SR but mt.sb = sabove[x], x's entries from there on staged as plain keys, each partner
-// y's row streamed from sabove[y] (graph-local, like rowptr) to its end, membership only
-// (the hits are those of the records' ranges, see kPartAbove).
+// y's row streamed from vrec[y].y = sabove[y] to vrec[y].w (graph-local, like rowptr),
+// membership only (the hits are those of the records' ranges, see kPartAbove).
 template <bool PV, bool VEC, bool REC = false, int HS = 1, bool ST = false, bool SR = false,
           bool SA = false>
 __device__ __forceinline__ void wave_vertex(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
     const u32* __restrict__ hcnt, const u32* __restrict__ hadj,
-    const uint4* __restrict__ hrec, const u32* __restrict__ sabove, u32 x, WaveMeta mt,
+    const uint4* __restrict__ hrec, const uint4* __restrict__ vrec, u32 x, WaveMeta mt,
     u32* table, uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c,
     u64* __restrict__ tri) {
   static_assert(!(REC && PV), "per-vertex counts use the full form");
@@ -137,8 +137,14 @@ __device__ __forceinline__ void wave_vertex(
   u32 y0 = 0, lo0 = 0, hi0 = 0;       // PL: the first batch of partners and their rows
   if (PL && lane < np) {
     y0 = hadj[hs + lane];
-    lo0 = cb + (SA ? sabove[y0] : rowptr[y0]);
-    hi0 = cb + rowptr[y0 + 1];
+    if (SA) {
+      const uint4 r = vrec[y0];
+      lo0 = cb + r.y;
+      hi0 = cb + r.w;
+    } else {
+      lo0 = cb + rowptr[y0];
+      hi0 = cb + rowptr[y0 + 1];
+    }
   }
   const u32 mask = bucket_mask(dx, kWaveSlots);
   c.staged += lane == 0 ? dx : 0;
@@ -169,9 +175,14 @@ __device__ __forceinline__ void wave_vertex(
         y = y0;
         lo = lo0;
         hi = hi0;
+      } else if (SA) {
+        y = hadj[hs + p];
+        const uint4 r = vrec[y];
+        lo = cb + r.y;
+        hi = cb + r.w;
       } else {
         y = hadj[(size_t)(hs + p) * HS];
-        lo = cb + (SA ? sabove[y] : rowptr[y]);
+        lo = cb + rowptr[y];
         hi = cb + rowptr[y + 1];
       }
     }
@@ -274,9 +285,10 @@ __device__ __forceinline__ void wave_vertex(
 //   kPartRec   : partner records hrec (pruned count): x's entries from mt.sb = sabove[x]
 //                on staged as plain keys, each record's range .x .. .z streamed,
 //                membership only (every hit a counted apex, in tl.s);
-//   kPartAbove : plain partner list hadj with per-vertex sabove (pruned count): staged as
-//                kPartRec, each partner y's row streamed from sabove[y], its first
-//                same-level entry above y, to its end, membership only.  For x > y the
+//   kPartAbove : plain partner list hadj with the per-vertex row records vrec (pruned
+//                count, batched): staged as kPartRec, each partner y's row streamed from
+//                vrec[y].y = sabove[y], its first same-level entry above y, to its end
+//                vrec[y].w, membership only.  For x > y the
 //                range also holds y's same-level entries in (y, x], which the staged
 //                keys (same-level ones above x only) never match, so the hits are the
 //                same as with the range from above max(x, y).
@@ -307,14 +319,14 @@ __device__ __forceinline__ u32 wave_max_u32(u32 v) {
 
 enum PartnerMode { kPartFull = 0, kPartRec = 1, kPartAbove = 2 };
 
-// colidx2 has 4 readable entries past m; table is this group's kSubSlots slots; sabove
-// (kPartAbove) is local to the graph like rowptr.
+// colidx2 has 4 readable entries past m; table is this group's kSubSlots slots; vrec
+// (kPartAbove) is local to the graph like rowptr: {row start, sabove, split, row end}.
 template <int PM>
 __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u32 cb,
                                                const u32* __restrict__ colidx2, u32 m,
                                                const u32* __restrict__ hadj,
                                                const uint4* __restrict__ hrec,
-                                               const u32* __restrict__ sabove, u32 x,
+                                               const uint4* __restrict__ vrec, u32 x,
                                                const WaveMeta& mt, u32* table, Tally& tl,
                                                Counts& c) {
   constexpr bool REC = PM != kPartFull;  // pruned: plain keys, membership count
@@ -341,9 +353,14 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
         const uint4 r = hrec[bx + p];  // the records sit in place of N(x)
         lo = r.x;
         hi = r.z;
+      } else if (PM == kPartAbove) {
+        y = hadj[bx + p];
+        const uint4 r = vrec[y];  // one 16-byte load: the row's sabove and end
+        lo = cb + r.y;
+        hi = cb + r.w;
       } else {
         y = hadj[bx + p];
-        lo = cb + (PM == kPartAbove ? sabove[y] : rowptr[y]);
+        lo = cb + rowptr[y];
         hi = cb + rowptr[y + 1];
       }
     }
@@ -662,23 +679,36 @@ __device__ __forceinline__ void block_item(
 // range .x .. .z; otherwise a kOther pass (x's other-level part against .y .. .z) and a
 // kSame pass (x's same-level part above x against .x .. .y), each with hash chunks or
 // bitmap windows, whichever takes fewer passes.  The ranges come from the partner records
-// (PM = kPartRec, single graph) or from the plain partner list with the per-vertex
-// {sabove[y], split[y], end of y's row} (PM = kPartAbove, batched; see kPartAbove for why
-// the hits agree).  rowptr, split and sabove are local to the graph, whose entries start
-// at cb.  PAD: colidx2 has 4 readable entries past its m2 counted ones.  ST (kPartRec):
-// the member pass tallies same-level and other-level hits apart (see block_pass).
+// (PM = kPartRec, single graph: x's row from rowptr, sabove, split) or from the plain
+// partner list with the per-vertex row records vrec = {row start, sabove, split, row
+// end}, local to the graph whose entries start at cb (PM = kPartAbove, batched; see
+// kPartAbove for why the hits agree).  PAD: colidx2 has 4 readable entries past its m2
+// counted ones.  ST (kPartRec): the member pass tallies same-level and other-level hits
+// apart (see block_pass).
 template <bool VEC, bool PAD = false, bool ST = false, int PM = kPartRec, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item_rec(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx2, u32 m2,
     const u32* __restrict__ tail4b, const u32* __restrict__ split,
     const u32* __restrict__ sabove, const u32* __restrict__ hcnt,
-    const uint4* __restrict__ hrec, const u32* __restrict__ hadj, u32 x, u32 seg,
-    IsectParams prm, const BlockShared& sh, Tally& tl, Counts& c) {
+    const uint4* __restrict__ hrec, const u32* __restrict__ hadj,
+    const uint4* __restrict__ vrec, u32 x, u32 seg, IsectParams prm, const BlockShared& sh,
+    Tally& tl, Counts& c) {
   static_assert(PM == kPartRec || (PM == kPartAbove && !ST), "split tallies need records");
   constexpr bool kFence = PM == kPartAbove;
   const u32 tid = threadIdx.x;
-  const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
-  const u32 gx = cb + sabove[x], sx = cb + split[x];
+  u32 bx, ex, gx, sx;
+  if (PM == kPartRec) {
+    bx = cb + rowptr[x];
+    ex = cb + rowptr[x + 1];
+    gx = cb + sabove[x];
+    sx = cb + split[x];
+  } else {
+    const uint4 rx = vrec[x];
+    bx = cb + rx.x;
+    gx = cb + rx.y;
+    sx = cb + rx.z;
+    ex = cb + rx.w;
+  }
   const u32 hs = bx + seg * prm.seg;  // the partners sit in place of N(x)
   const u32 pn = min(prm.seg, hcnt[x] - seg * prm.seg);
   uint4 r = make_uint4(0, 0, 0, 0);
@@ -687,7 +717,8 @@ __device__ __forceinline__ void block_item_rec(
       r = hrec[hs + tid];
     } else {
       const u32 y = hadj[hs + tid];
-      r = make_uint4(cb + sabove[y], cb + split[y], cb + rowptr[y + 1], y);
+      const uint4 ry = vrec[y];
+      r = make_uint4(cb + ry.y, cb + ry.z, cb + ry.w, y);
     }
   }
   if (ex - gx <= prm.chunk) {
@@ -824,53 +855,63 @@ __device__ __forceinline__ void split_short_row(const u32* __restrict__ colidx,
   *sr_out = (u32)__popc(lm);
 }
 
-// A row of kSplitLane < d <= kSplitGroup entries by one group of 16 lanes (four rows per
-// wavefront), held in registers: lane gl of the group holds entries 16 u + gl, u < 4, so
-// the row costs one load and one gather round trip; ranks come from the group's 16 bits
-// of each ballot.  All 64 lanes call it together; a group without a row passes d = 0.
-// Returns the row's same-level entries in *ns, partners in *nh and same-level entries
-// below v in *sr (on every lane of the group).
-constexpr u32 kSplitGroup = 64;
+// A row of at most GL * U entries by one group of GL lanes (64 / GL rows per wavefront),
+// held in registers: lane gl of the group holds entries GL u + gl, u < U, so the row
+// costs one load and one gather round trip; the level, partner and below-v flags are kept
+// as bit masks per lane and ranked by the group's bits of each ballot.  All 64 lanes call
+// it together; a group without a row passes d = 0.  Returns the row's same-level entries
+// in *ns, partners in *nh and same-level entries below v in *sr (on every lane of the
+// group).
+constexpr u32 kSplitGroup = 64;  // rows up to this length: 16-lane groups, 4 entries each
 
+template <u32 GL, u32 U>
 __device__ __forceinline__ void split_group_row(const u32* __restrict__ colidx,
                                                 const uint8_t* __restrict__ vinfo, u32 v, u32 vx,
                                                 u32 lo, u32 d, u32* __restrict__ colidx2,
                                                 u32* __restrict__ hadj, u32* ns_out,
                                                 u32* nh_out, u32* sr_out) {
-  constexpr u32 U = kSplitGroup / 16;
-  const u32 lane = lane_id(), gl = lane & 15u, gb = lane & ~15u;
-  const u32 below = (1u << gl) - 1u;
+  static_assert(GL == 16 || GL == 32, "groups of 16 or 32 lanes");
+  static_assert(U <= 32, "flags are one 32-bit mask per lane");
+  constexpr u64 gm = (1ull << GL) - 1ull;
+  const u32 lane = lane_id(), gl = lane & (GL - 1u), gb = lane & ~(GL - 1u);
+  const u64 below = (1ull << gl) - 1ull;
   u32 w[U];
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
-    const u32 j = u * 16 + gl;
+    const u32 j = u * GL + gl;
     w[u] = j < d ? colidx[lo + j] : v;
   }
-  u32 ms[U], mp[U], mo[U];
-  u32 ns = 0, nh = 0, sr = 0;
+  u32 sm = 0, pm = 0, lm = 0, im = 0;  // same level, partner, same level below v, in row
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
-    const u32 j = u * 16 + gl;
+    const u32 j = u * GL + gl;
     const u32 vw = vinfo[w[u]];
     const bool in = j < d;
     const bool same = in && ((vw ^ vx) & 0x80u) == 0;
-    const bool part = same && key_less(vw & 127u, w[u], vx & 127u, v);
-    ms[u] = (u32)(__ballot(same) >> gb) & 0xFFFFu;
-    mp[u] = (u32)(__ballot(part) >> gb) & 0xFFFFu;
-    mo[u] = (u32)(__ballot(in && !same) >> gb) & 0xFFFFu;
-    ns += (u32)__popc(ms[u]);
-    nh += (u32)__popc(mp[u]);
-    sr += (u32)__popc((u32)(__ballot(same && w[u] < v) >> gb) & 0xFFFFu);
+    sm |= (same ? 1u : 0u) << u;
+    pm |= (same && key_less(vw & 127u, w[u], vx & 127u, v) ? 1u : 0u) << u;
+    lm |= (same && w[u] < v ? 1u : 0u) << u;
+    im |= (in ? 1u : 0u) << u;
+  }
+  u32 ns = 0, nh = 0, sr = 0;
+#pragma unroll
+  for (u32 u = 0; u < U; ++u) {
+    ns += (u32)__popcll((__ballot((sm >> u) & 1u) >> gb) & gm);
+    nh += (u32)__popcll((__ballot((pm >> u) & 1u) >> gb) & gm);
+    sr += (u32)__popcll((__ballot((lm >> u) & 1u) >> gb) & gm);
   }
   u32 cs = 0, co = 0, ch = 0;
 #pragma unroll
   for (u32 u = 0; u < U; ++u) {
-    if ((ms[u] >> gl) & 1u) colidx2[lo + cs + (u32)__popc(ms[u] & below)] = w[u];
-    else if ((mo[u] >> gl) & 1u) colidx2[lo + ns + co + (u32)__popc(mo[u] & below)] = w[u];
-    if ((mp[u] >> gl) & 1u) hadj[lo + ch + (u32)__popc(mp[u] & below)] = w[u];
-    cs += (u32)__popc(ms[u]);
-    co += (u32)__popc(mo[u]);
-    ch += (u32)__popc(mp[u]);
+    const bool same = (sm >> u) & 1u, other = ((im & ~sm) >> u) & 1u, part = (pm >> u) & 1u;
+    const u64 ms = (__ballot(same) >> gb) & gm, mo = (__ballot(other) >> gb) & gm;
+    const u64 mp = (__ballot(part) >> gb) & gm;
+    if (same) colidx2[lo + cs + (u32)__popcll(ms & below)] = w[u];
+    else if (other) colidx2[lo + ns + co + (u32)__popcll(mo & below)] = w[u];
+    if (part) hadj[lo + ch + (u32)__popcll(mp & below)] = w[u];
+    cs += (u32)__popcll(ms);
+    co += (u32)__popcll(mo);
+    ch += (u32)__popcll(mp);
   }
   *ns_out = ns;
   *nh_out = nh;
