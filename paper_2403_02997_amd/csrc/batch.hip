@@ -529,11 +529,10 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
           const int s0 = src < 0 ? 0 : src;
           WaveMeta gm{(u32)__shfl(mt.bx, s0, kWave), (u32)__shfl(mt.ex, s0, kWave),
                       (u32)__shfl(mt.sb, s0, kWave), (u32)__shfl(mt.np, s0, kWave)};
-          const u32 gx = (u32)__shfl(x, s0, kWave);
           if (src < 0) gm = WaveMeta{0, 0, 0, 0};
           Tally tl{0, 0, 0, 0};
-          subwave_vertex<kPartAbove>(rp, cb, A.colidx2_all, A.m_total, A.hadj_all, nullptr,
-                                     vrec, gx, gm, gtab, tl, c);
+          subwave_vertex<kPartAbove>(A.colidx2_all, A.m_total, cb, A.hadj_all, nullptr, vrec,
+                                     gm, gtab, tl, c);
           tl.fold(c);
         }
         todo = __ballot(whole);

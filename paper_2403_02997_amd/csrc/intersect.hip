@@ -98,8 +98,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
                     (u32)__shfl(mt.sb, s0, kWave), (u32)__shfl(mt.np, s0, kWave)};
         if (src < 0) gm = WaveMeta{0, 0, 0, 0};
         Tally tl{0, 0, 0, 0};
-        subwave_vertex<kPartRec>(rowptr, 0u, colidx, m, nullptr, hrec, nullptr, 0u, gm, gtab,
-                                 tl, c);
+        subwave_vertex<kPartRec>(colidx, m, 0u, nullptr, hrec, nullptr, gm, gtab, tl, c);
         tl.fold(c);
       }
       todo = __ballot(live && !sub);

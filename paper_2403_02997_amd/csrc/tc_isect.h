@@ -278,10 +278,9 @@ __device__ __forceinline__ void wave_vertex(
 // its staged entries go to the group's 256-slot LDS hash set, its partners' ranges are
 // streamed 16 partners at a time, 4 quads per lane in flight, and the owner of a quad is
 // found by a binary search over the group's quad prefix sums (cross-lane reads, no LDS
-// marks).  Where the partners and their ranges come from (PM):
-//   kPartFull  : plain partner list hadj (level-split rows): x's split row staged with
-//                level flags by position (mt.sb = its first other-level entry), each
-//                partner's whole split row streamed, full form (c1, c2, t2);
+// marks).  x's entries from mt.sb = sabove[x] on are staged as plain keys, and the
+// staged keys and the first 16 partners' ranges are loaded before the table is built.
+// Where the partners and their ranges come from (PM):
 //   kPartRec   : partner records hrec (pruned count): x's entries from mt.sb = sabove[x]
 //                on staged as plain keys, each record's range .x .. .z streamed,
 //                membership only (every hit a counted apex, in tl.s);
@@ -317,53 +316,60 @@ __device__ __forceinline__ u32 wave_max_u32(u32 v) {
   return v;
 }
 
-enum PartnerMode { kPartFull = 0, kPartRec = 1, kPartAbove = 2 };
+enum PartnerMode { kPartRec = 1, kPartAbove = 2 };
 
 // colidx2 has 4 readable entries past m; table is this group's kSubSlots slots; vrec
 // (kPartAbove) is local to the graph like rowptr: {row start, sabove, split, row end}.
 template <int PM>
-__device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u32 cb,
-                                               const u32* __restrict__ colidx2, u32 m,
+__device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, u32 m, u32 cb,
                                                const u32* __restrict__ hadj,
                                                const uint4* __restrict__ hrec,
-                                               const uint4* __restrict__ vrec, u32 x,
+                                               const uint4* __restrict__ vrec,
                                                const WaveMeta& mt, u32* table, Tally& tl,
                                                Counts& c) {
-  constexpr bool REC = PM != kPartFull;  // pruned: plain keys, membership count
+  static_assert(PM == kPartRec || PM == kPartAbove, "pruned forms only");
+  constexpr u32 SK = kSubMax / kSubLanes;  // staged keys per lane at most
   const u32 lane = lane_id(), gl = lane & (kSubLanes - 1), gb = lane & ~(kSubLanes - 1);
-  const u32 bx = mt.bx, np = mt.np;
-  const u32 sb = REC ? mt.sb : bx;  // first staged entry
-  const u32 dx = mt.ex - sb;
-  const u32 mask = bucket_mask(dx ? dx : 1u, kSubSlots);
-  c.staged += gl == 0 ? dx : 0;
-  for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) table[i] = kInf;
-  wave_lds_sync();
-  for (u32 i = gl; i < dx; i += kSubLanes) {
-    const u32 w = colidx2[sb + i];
-    if (REC) hash_insert_key(table, mask, w, w);
-    else hash_insert(table, mask, w, sb + i < mt.sb ? 1u : 0u);
-  }
-  wave_lds_sync();
-  const u32 nbat = wave_max_u32((np + kSubLanes - 1) / kSubLanes);
-  for (u32 b = 0; b < nbat; ++b) {
+  const u32 bx = mt.bx, np = mt.np, sb = mt.sb;
+  const u32 dx = mt.ex - sb;  // staged entries: x's row from sabove[x] on
+  // the partner info of batch b (up to 16 partners, one per lane of the group)
+  auto partner = [&](u32 b, u32& lo, u32& hi) {
     const u32 p = b * kSubLanes + gl;
-    u32 y = 0, lo = 0, hi = 0;
+    lo = hi = 0;
     if (p < np) {
       if (PM == kPartRec) {
         const uint4 r = hrec[bx + p];  // the records sit in place of N(x)
         lo = r.x;
         hi = r.z;
-      } else if (PM == kPartAbove) {
-        y = hadj[bx + p];
-        const uint4 r = vrec[y];  // one 16-byte load: the row's sabove and end
+      } else {
+        const uint4 r = vrec[hadj[bx + p]];  // one 16-byte load: the row's sabove and end
         lo = cb + r.y;
         hi = cb + r.w;
-      } else {
-        y = hadj[bx + p];
-        lo = cb + rowptr[y];
-        hi = cb + rowptr[y + 1];
       }
     }
+  };
+  // the staged keys and the first batch of partners are loaded before the table is
+  // cleared and filled, so their round trips overlap
+  u32 sk[SK];
+#pragma unroll
+  for (u32 t = 0; t < SK; ++t) {
+    const u32 i = gl + t * kSubLanes;
+    sk[t] = i < dx ? colidx2[sb + i] : 0u;
+  }
+  u32 lo0, hi0;
+  partner(0, lo0, hi0);
+  const u32 mask = bucket_mask(dx ? dx : 1u, kSubSlots);
+  c.staged += gl == 0 ? dx : 0;
+  for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) table[i] = kInf;
+  wave_lds_sync();
+#pragma unroll
+  for (u32 t = 0; t < SK; ++t)
+    if (gl + t * kSubLanes < dx) hash_insert_key(table, mask, sk[t], sk[t]);
+  wave_lds_sync();
+  const u32 nbat = wave_max_u32((np + kSubLanes - 1) / kSubLanes);
+  for (u32 b = 0; b < nbat; ++b) {
+    u32 lo = lo0, hi = hi0;
+    if (b > 0) partner(b, lo, hi);
     tl.probes += hi - lo;
     const u32 qa = lo & ~3u;
     const u32 nq = lo < hi ? (hi - qa + 3u) >> 2 : 0u;
@@ -373,7 +379,7 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
     const u32 tmax = wave_max_u32(total);
     for (u32 k0 = 0; k0 < tmax; k0 += kSubLanes * kSubU) {
       u32 e[kSubU][4];
-      u32 addr[kSubU], jlo[kSubU], jspan[kSubU], jy[kSubU];
+      u32 addr[kSubU], jlo[kSubU], jspan[kSubU];
       bool live[kSubU];
 #pragma unroll
       for (u32 u = 0; u < kSubU; ++u) {
@@ -392,7 +398,6 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
         const u32 qb = (u32)__shfl(qbase, j, kWave);
         jlo[u] = (u32)__shfl(lo, j, kWave);
         jspan[u] = (u32)__shfl(hi, j, kWave) - jlo[u];
-        jy[u] = REC ? 0u : (u32)__shfl(y, j, kWave);
         addr[u] = (qb + q) * 4;
         const uint4 v = *reinterpret_cast<const uint4*>(colidx2 + min(addr[u], (m - 1) & ~3u));
         e[u][0] = v.x;
@@ -410,15 +415,7 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ rowptr, u
         bool ok[4];
 #pragma unroll
         for (u32 i = 0; i < 4; ++i) ok[i] = live[u] && (addr[u] + i - jlo[u]) < jspan[u];
-        if (REC) {
-          hash_count_n<4>(table, mask, e[u], ok, tl.s);
-        } else {
-          const u32 vmax = max(x, jy[u]);
-          u32 res[4];
-          hash_probe_n<4>(table, mask, e[u], ok, res);
-#pragma unroll
-          for (u32 i = 0; i < 4; ++i) tl.add(res[i], e[u][i], vmax);
-        }
+        hash_count_n<4>(table, mask, e[u], ok, tl.s);
       }
     }
   }
