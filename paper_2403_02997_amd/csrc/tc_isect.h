@@ -148,13 +148,27 @@ __device__ __forceinline__ void wave_vertex(
   }
   const u32 mask = bucket_mask(dx, kWaveSlots);
   c.staged += lane == 0 ? dx : 0;
+  // pruned forms: the staged keys (at most kWaveSlots / 4, i.e. 8 per lane) are all
+  // loaded before the table is cleared and filled
+  constexpr u32 SK = KEYS ? kWaveSlots / 4 / kWave : 1;
+  u32 sk[SK];
+  if (KEYS) {
+#pragma unroll
+    for (u32 t = 0; t < SK; ++t) {
+      const u32 i = lane + t * kWave;
+      sk[t] = i < dx ? colidx[sb + i] : 0u;
+    }
+  }
   for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
   wave_lds_sync();
-  for (u32 i = lane; i < dx; i += kWave) {
+  if (KEYS) {
+#pragma unroll
+    for (u32 t = 0; t < SK; ++t)
+      if (lane + t * kWave < dx) hash_insert_key(table, mask, sk[t], sk[t]);
+  }
+  for (u32 i = lane; !KEYS && i < dx; i += kWave) {
     const u32 w = colidx[sb + i];
-    if (KEYS) {
-      hash_insert_key(table, mask, w, w);
-    } else if (SR) {
+    if (SR) {
       hash_insert(table, mask, w, sb + i < sp ? 1u : 0u);
     } else {
       const u32 same = ((vinfo[w] & 0x80u) == px) ? 1u : 0u;
