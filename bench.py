@@ -69,10 +69,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
 # The kernel instance tc_count launches for each intersection step (16-byte aligned
 # colidx, no per-vertex attribution; the workgroup class in its pruned form).
+# the kernel instantiations of the counting call (the fourth template argument, false,
+# leaves out the split-term tallies of tc_count_split)
 KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>",
-                  "isect_wave": "k_isect_wave<false, true, true>",
-                  "isect_block": "k_isect_block<false, true, true>",
-                  "isect_hub": "k_hub_count<8u>"}
+                  "isect_wave": "k_isect_wave<false, true, true, false>",
+                  "isect_block": "k_isect_block<false, true, true, false>",
+                  "isect_hub": "k_hub_count<8u, false>"}
 
 WORKLOAD_TEXT = {
     "rmat10": "R-MAT scale 10, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1000",
