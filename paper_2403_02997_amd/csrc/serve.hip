@@ -85,9 +85,9 @@ inline size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Buffer of a single-graph job: rowptr, colidx, the bounds-check flag, then the arena of
 // the tc_count call.
-struct SingleLayout {
+struct SingleJobLayout {
   size_t o_ci, o_flag, o_ws, ws, total;
-  SingleLayout(uint32_t n, uint64_t m) {
+  SingleJobLayout(uint32_t n, uint64_t m) {
     o_ci = up256(4ull * ((uint64_t)n + 1));
     o_flag = o_ci + up256(4ull * std::max<uint64_t>(m, 1));
     o_ws = o_flag + 256;
@@ -98,9 +98,9 @@ struct SingleLayout {
 
 // Buffer of a batched job: concatenated rowptrs and colidx, row and entry offsets, counts,
 // then the tc_count_batch workspace.
-struct BatchLayout {
+struct BatchJobLayout {
   size_t o_ci, o_ro, o_co, o_cnt, o_ws, ws, total;
-  BatchLayout(uint32_t G, uint64_t rows, uint64_t cols) {
+  BatchJobLayout(uint32_t G, uint64_t rows, uint64_t cols) {
     o_ci = up256(4 * rows);
     o_ro = o_ci + up256(4 * cols);
     o_co = o_ro + up256(8 * ((size_t)G + 1));
@@ -166,8 +166,8 @@ struct tc_server {
 
   // Buffer bytes a request needs on its own (what submission checks against the budget).
   uint64_t footprint(uint32_t n, uint64_t m) const {
-    return path_of(m) == 0 ? BatchLayout(1, (uint64_t)n + 1, m).total
-                           : SingleLayout(n, m).total;
+    return path_of(m) == 0 ? BatchJobLayout(1, (uint64_t)n + 1, m).total
+                           : SingleJobLayout(n, m).total;
   }
 
   // ---- device memory -----------------------------------------------------------------
@@ -307,7 +307,7 @@ struct tc_server {
 
   // ---- batched path ------------------------------------------------------------------
   // Uploads the batch into the path's buffer, takes the device, counts, reads the counts.
-  int run_batch(const std::vector<Request>& b, const BatchLayout& L, uint64_t rows,
+  int run_batch(const std::vector<Request>& b, const BatchJobLayout& L, uint64_t rows,
                 uint64_t cols, std::vector<uint64_t>& counts, double* t_count) {
     const hipStream_t s = stream[0];
     char* const dev = buf[0].p;
@@ -368,7 +368,7 @@ struct tc_server {
           const Request& r = ready[0].front();
           if (!b.empty() &&
               (cols + r.m > cfg.batch_max_entries ||
-               BatchLayout((uint32_t)b.size() + 1, rows + r.n + 1, cols + r.m).total >
+               BatchJobLayout((uint32_t)b.size() + 1, rows + r.n + 1, cols + r.m).total >
                    st.hbm_budget))
             break;
           rows += r.n + 1;
@@ -378,7 +378,7 @@ struct tc_server {
         }
         st.queued -= b.size();
         st.batches += 1;
-        rc = take_buf(lk, 0, BatchLayout((uint32_t)b.size(), rows, cols).total);
+        rc = take_buf(lk, 0, BatchJobLayout((uint32_t)b.size(), rows, cols).total);
         t_start = now();
         for (Request& r : b) r.t_admit = r.t_count = t_start;
       }
@@ -397,7 +397,7 @@ struct tc_server {
       std::vector<uint64_t> counts;
       if (rc == TC_OK && !b.empty()) {
         double t_count = t_start;
-        rc = run_batch(b, BatchLayout((uint32_t)b.size(), rows, cols), rows, cols, counts,
+        rc = run_batch(b, BatchJobLayout((uint32_t)b.size(), rows, cols), rows, cols, counts,
                        &t_count);
         for (Request& r : b) r.t_count = t_count;
       }
@@ -416,7 +416,7 @@ struct tc_server {
   int run_single(const Request& r, int k, uint64_t* tri, double* t_count) {
     const hipStream_t s = stream[k];
     char* const dev = buf[k].p;
-    const SingleLayout L(r.n, r.m);
+    const SingleJobLayout L(r.n, r.m);
     int rc = TC_OK;
     if (hipMemcpyAsync(dev, r.rowptr, 4ull * (r.n + 1), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
@@ -464,7 +464,7 @@ struct tc_server {
         q.erase(pick);
         st.queued -= 1;
         st.singles += 1;
-        rc = take_buf(lk, k, SingleLayout(r.n, r.m).total);
+        rc = take_buf(lk, k, SingleJobLayout(r.n, r.m).total);
         r.t_admit = r.t_count = now();
       }
       uint64_t tri = 0;
