@@ -344,13 +344,66 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
       }
     }
     __syncthreads();
+    // Direction-optimising levels (Beamer et al., SC 2012) when the frontier bitmap fits
+    // beside the visited one: a level whose frontier holds more than 1/14 of the entries
+    // still unexplored runs bottom-up (every unvisited vertex looks for a frontier
+    // neighbour and stops at the first), and the search returns to top-down once the
+    // frontier holds fewer than n / 24 vertices.
+    const u32 nw = (n + 31) / 32;
+    const bool bu_ok = lds_bfs && 2 * nw <= (u32)kBigSlots;
+    u32* s_fr = s_table + nw;
+    u32 mu = m;  // entries of the vertices that have not been in a frontier yet
+    bool bu = false;
     u32 qs = 0, k = 0;
     while (true) {
       const u32 qe = s_qtail;
       if (qs == qe) break;
+      if (threadIdx.x == 0) s_cnt = 0;
       __syncthreads();
       const u32 next = k + 1;
-      if (lds_bfs) {
+      if (bu_ok) {  // the frontier's entries
+        u32 mf = 0;
+        for (u32 i = threadIdx.x; i < qe - qs; i += kBT) {
+          const u32 u = queue[qs + i];
+          mf += rp[u + 1] - rp[u];
+        }
+        mf = wave_sum_u32(mf);
+        if (lane == 0 && mf) atomicAdd(&s_cnt, mf);
+        __syncthreads();
+        const u32 mfs = s_cnt;
+        mu -= min(mu, mfs);
+        bu = bu ? qe - qs >= n / 24 : mfs > mu / 14;
+      }
+      if (bu) {
+        for (u32 i = threadIdx.x; i < nw; i += kBT) s_fr[i] = 0;
+        __syncthreads();
+        for (u32 i = threadIdx.x; i < qe - qs; i += kBT) {
+          const u32 u = queue[qs + i];
+          atomicOr(&s_fr[u >> 5], 1u << (u & 31u));
+        }
+        __syncthreads();
+        const u32 nr = (n + kWave - 1) / kWave * kWave;
+        for (u32 v = threadIdx.x; v < nr; v += kBT) {
+          bool claimed = false;
+          if (v < n && ((s_vis[v >> 5] >> (v & 31u)) & 1u) == 0) {
+            const u32 lo = rp[v], hi = rp[v + 1];
+            for (u32 j = lo; j < hi && !claimed; j += 4) {
+              u32 w[4];
+#pragma unroll
+              for (u32 t = 0; t < 4; ++t) w[t] = j + t < hi ? ci[j + t] : 0u;
+#pragma unroll
+              for (u32 t = 0; t < 4; ++t)
+                claimed |= j + t < hi && ((s_fr[w[t] >> 5] >> (w[t] & 31u)) & 1u) != 0;
+            }
+          }
+          if (claimed) {
+            level[v] = next;
+            atomicOr(&s_vis[v >> 5], 1u << (v & 31u));
+          }
+          const u32 pos = wave_append(&s_qtail, claimed);
+          if (claimed) queue[pos] = v;
+        }
+      } else if (lds_bfs) {
         block_for_each_entry(rp, ci, qe - qs, queue + qs, [&](u32 u, u32 v, bool act) {
           (void)u;
           bool claimed = false;
@@ -376,6 +429,7 @@ __global__ void __launch_bounds__(kBT) k_batch_main(BatchArrays A, u32 G,
       qs = qe;
       ++k;
     }
+    if (threadIdx.x == 0) s_cnt = 0;  // the split's long-row count starts from zero
     __syncthreads();
 
     // ---- 3. per-vertex info ----
