@@ -283,7 +283,7 @@ size_t hub_item_cap(u32 n, u32 m) { return (size_t)n + m / kHubChunk + 1; }
 // array 256-byte aligned).  The control block (ctl .. outc) is contiguous so that one
 // memset clears it.  Returns the bytes needed; with base = nullptr only sizes.
 struct SingleWs {
-  u32 *tile_row, *parent, *level, *q0, *q1, *fb;
+  u32 *parent, *level, *q0, *q1, *fb;
   size_t fb_words;
   u64* bfs_part;
   u32* bigq0;
@@ -306,8 +306,6 @@ struct SingleWs {
 size_t carve_single(void* base, u32 n, u32 m, bool hub_on, SingleWs* out) {
   SingleWs w;
   Carver c(base);
-  const u32 ntiles = (m + kTile - 1) / kTile;
-  w.tile_row = c.take<u32>(ntiles + 1);
   w.parent = c.take<u32>(n);
   w.level = c.take<u32>(n);
   w.q0 = c.take<u32>(n);
@@ -370,7 +368,6 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   if (rc) return rc;
   SingleWs w;
   carve_single(ws.p, n, m, hub_on, &w);
-  u32* tile_row = w.tile_row;
   u32* parent = w.parent;
   u32* level = w.level;
   u32* q0 = w.q0;
@@ -416,22 +413,27 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   StepTimer timer(s);
 
   // ---- a1: component roots ----
+  // The first search runs from v0, the smallest vertex with neighbours (the first root of
+  // the ascending restart loop); a union-find over the vertices it does not reach gives
+  // the roots of the other components, which a second search then covers.  A graph
+  // whose non-isolated vertices form one component needs no union-find at all.
   timer.mark();
-  launch_tile_rows(rowptr, n, m, tile_row, s);
-  launch_cc(rowptr, colidx, tile_row, n, m, parent, cc_mode, s);
+  launch_first_root(rowptr, n, parent, cc_mode, s);
   TC_LAUNCHED();
 
   // ---- a2: level BFS ----
   timer.mark();
-  launch_bfs_init(rowptr, parent, n, level, q0, bigq0, fb, ctl, s);
-  TC_LAUNCHED();
   SideFork fork;  // its stream is made while the first BFS levels run
   const bool want_side = !timer.on && m >= kSideMinEntries;
-  {
-    // Batches of one launch per level, with a poll of the control block after each; a
-    // search still in top-down mode after a batch (a large diameter) continues in one
-    // cooperative launch that runs its top-down levels back to back (launch_bfs_run),
-    // and resumes with per-level launches only for bottom-up levels.
+  BfsCtl hc;
+  // One search from the roots in parent[] (keep: vertices already reached keep their
+  // levels).  Batches of one launch per level, with a poll of the control block after
+  // each; a search still in top-down mode after a batch (a large diameter) continues in
+  // one cooperative launch that runs its top-down levels back to back (launch_bfs_run),
+  // and resumes with per-level launches only for bottom-up levels.
+  auto search = [&](bool keep) -> int {
+    launch_bfs_init(rowptr, parent, n, level, q0, bigq0, fb, ctl, s, keep);
+    TC_LAUNCHED();
     const u32 grid = bfs_grid(n);
     bool run_ok = true;  // cleared if the device refuses the cooperative launch
     u32 k = 0, batch = 8;  // low-diameter graphs finish within one poll
@@ -440,9 +442,8 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
         launch_bfs_level(rowptr, colidx, n, k + i, level, q0, q1, bigq0, bigq1, fb, ctl, bfs_part,
                          grid, s);
       TC_LAUNCHED();
-      if (k == 0 && want_side) fork.create();
+      if (k == 0 && want_side && !keep) fork.create();
       k += batch;
-      BfsCtl hc;
       TC_HIP(hipMemcpyAsync(&hc, ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
       TC_HIP(hipStreamSynchronize(s));
       if (hc.done) break;
@@ -471,6 +472,30 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
       if (hc.done) break;
       launch_bfs_bitmap(n, k, q0, q1, ctl, fb, s);  // per-level launches resume at level k
     }
+    return TC_OK;
+  };
+  rc = search(false);
+  if (rc) return rc;
+  // the vertices the first search did not reach, if any: their roots, then their search
+  launch_rest_init(level, n, parent, cc_mode, s);
+  TC_LAUNCHED();
+  u32 h_rest = 0;
+  TC_HIP(hipMemcpyAsync(&h_rest, cc_mode + 2, sizeof(u32), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  BfsCtl first_ctl = hc;  // the first search's depth, roots and bottom-up levels
+  bool two = false;
+  if (h_rest > 0) {
+    two = true;
+    // a few unreached vertices (small components): join just their edges; many (v0 sat
+    // in a small component): the sampled union-find over the whole graph, whose roots of
+    // the reached vertices are v0 as well
+    if (h_rest <= n / 8) launch_rest_links(rowptr, colidx, n, parent, cc_mode, s);
+    else launch_cc(rowptr, colidx, n, m, parent, cc_mode, s);
+    TC_HIP(hipMemsetAsync(ctl, 0, sizeof(BfsCtl), s));
+    TC_HIP(hipMemsetAsync(fb, 0, sizeof(u32) * fb_words, s));
+    TC_LAUNCHED();
+    rc = search(true);
+    if (rc) return rc;
   }
   timer.mark();
   // ---- a3: cover-edge extraction and planning ----
@@ -584,6 +609,11 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
   TC_HIP(hipMemcpyAsync(&out->ctl, ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
   timer.collect();
+  if (two) {  // both searches' statistics
+    out->ctl.depth = std::max(out->ctl.depth, first_ctl.depth);
+    out->ctl.num_roots += first_ctl.num_roots;
+    out->ctl.bu_levels += first_ctl.bu_levels;
+  }
   out->cover_edges = h_ns;
   // Two independent tallies of the same-level apexes must agree (CETC-SM: c2 / 3); the
   // pruned count does not tally c2.

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict_
                                                           u32* __restrict__ queue0,
                                                           u32* __restrict__ bigq0,
                                                           u32* __restrict__ fb0,
-                                                          BfsCtl* __restrict__ ctl) {
+                                                          BfsCtl* __restrict__ ctl, u32 keep) {
   __shared__ u32 s_tmp[kBfsThreads / kWave];
   __shared__ u32 s_base;
   u64 mu = 0;
@@ -65,10 +65,12 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_init(const u32* __restrict_
       const u32 v = base + k * blockDim.x + threadIdx.x;
       if (v < n) {
         const u32 d = rowptr[v + 1] - rowptr[v];
-        const bool root = parent[v] == v;
-        level[v] = root ? 0u : kInf;
+        // keep: a vertex an earlier search reached keeps its level and takes no part
+        const bool reached = keep && level[v] != kInf;
+        const bool root = !reached && parent[v] == v;
+        if (!reached) level[v] = root ? 0u : kInf;
         roots += root;
-        if (!root) mu += d;
+        if (!root && !reached) mu += d;
         if (root && d > 0) {
           bits |= 1u << k;
           ++cnt;
@@ -644,11 +646,11 @@ size_t bfs_part_words() { return 2 * (size_t)num_cus() * kBfsBlocksPerCu; }
 size_t bfs_big_cap(u32 n, u64 m) { return (size_t)min((u64)n, m / (kBfsBig + 1) + 1); }
 
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
-                     u32* bigq0, u32* fb, BfsCtl* ctl, hipStream_t s) {
+                     u32* bigq0, u32* fb, BfsCtl* ctl, hipStream_t s, bool keep) {
   // each workgroup adds its totals with same-address atomics
   const u32 g = max(1u, min(cdiv(n, kBfsThreads), (u32)num_cus() * kBfsBlocksPerCu));
   hipLaunchKernelGGL(k_bfs_init, dim3(g), dim3(kBfsThreads), 0, s, rowptr, parent, n, level,
-                     queue0, bigq0, fb, ctl);
+                     queue0, bigq0, fb, ctl, keep ? 1u : 0u);
 }
 
 void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,

@@ -162,9 +162,8 @@ __global__ void __launch_bounds__(256) k_cc_finish(const u32* __restrict__ rowpt
   }
 }
 
-void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
-               u32* parent, u32* mode, hipStream_t s) {
-  (void)tile_row;
+void launch_cc(const u32* rowptr, const u32* colidx, u32 n, u32 m, u32* parent, u32* mode,
+               hipStream_t s) {
   if (n == 0) return;
   const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
   hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent);
@@ -183,6 +182,74 @@ void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n,
                        mode);
     hipLaunchKernelGGL(k_cc_finish, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent, mode);
   }
+  hipLaunchKernelGGL(k_cc_compress<false>, dim3(gv), dim3(256), 0, s, n, parent, mode);
+}
+
+// ---- the first component and the rest ----------------------------------------------
+// The restart loop of CETC-Seq starts its first BFS from the smallest ID; every vertex
+// below the smallest one with neighbours is isolated, so that vertex v0 is the smallest
+// of its component and roots it.  The first search runs from v0 alone (the isolated
+// vertices are their own roots); only the vertices it does not reach need the
+// union-find, which then joins just their edges (k_cc_finish with v0 as the dominant
+// root).  mode[0] receives v0 (kInf when no vertex has neighbours), mode[2] the number
+// of unreached vertices.
+__global__ void __launch_bounds__(256) k_first_active(const u32* __restrict__ rowptr, u32 n,
+                                                      u32* __restrict__ mode) {
+  u32 best = kInf;
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (rowptr[v + 1] > rowptr[v]) {
+      best = v;  // the grid-stride order visits this thread's vertices ascending
+      break;
+    }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) best = min(best, (u32)__shfl_xor(best, off, kWave));
+  if (lane_id() == 0 && best != kInf) atomicMin(&mode[0], best);
+}
+
+// parent[v] = v for v0 and the isolated vertices (the first search's roots), v0 for
+// every other vertex.
+__global__ void k_seed_first(const u32* __restrict__ rowptr, u32 n, u32* __restrict__ parent,
+                             const u32* __restrict__ mode) {
+  const u32 v0 = mode[0];
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    parent[v] = rowptr[v + 1] == rowptr[v] || v == v0 || v0 == kInf ? v : v0;
+}
+
+// After the first search: every vertex it did not reach becomes its own parent and is
+// counted in mode[2]; the reached ones keep parent v0.
+__global__ void __launch_bounds__(256) k_rest_init(const u32* __restrict__ level, u32 n,
+                                                   u32* __restrict__ parent,
+                                                   u32* __restrict__ mode) {
+  u32 cnt = 0;
+  for (u32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (level[v] == kInf) {
+      parent[v] = v;
+      ++cnt;
+    }
+  cnt = wave_sum_u32(cnt);
+  if (lane_id() == 0 && cnt) atomicAdd(&mode[2], cnt);
+}
+
+void launch_first_root(const u32* rowptr, u32 n, u32* parent, u32* mode, hipStream_t s) {
+  if (n == 0) return;
+  const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipMemsetAsync(mode, 0xFF, sizeof(u32), s);  // mode[0] = kInf
+  hipMemsetAsync(mode + 2, 0, sizeof(u32), s);
+  hipLaunchKernelGGL(k_first_active, dim3(gv), dim3(256), 0, s, rowptr, n, mode);
+  hipLaunchKernelGGL(k_seed_first, dim3(gv), dim3(256), 0, s, rowptr, n, parent, mode);
+}
+
+void launch_rest_init(const u32* level, u32 n, u32* parent, u32* mode, hipStream_t s) {
+  if (n == 0) return;
+  const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_rest_init, dim3(gv), dim3(256), 0, s, level, n, parent, mode);
+}
+
+void launch_rest_links(const u32* rowptr, const u32* colidx, u32 n, u32* parent, u32* mode,
+                       hipStream_t s) {
+  if (n == 0) return;
+  const u32 gv = min(cdiv(n, 256), (u32)num_cus() * 8);
+  hipLaunchKernelGGL(k_cc_finish, dim3(gv), dim3(256), 0, s, rowptr, colidx, n, parent, mode);
   hipLaunchKernelGGL(k_cc_compress<false>, dim3(gv), dim3(256), 0, s, n, parent, mode);
 }
 

@@ -85,10 +85,21 @@ struct Item {
 
 // ---- prep ----
 void launch_tile_rows(const u32* rowptr, u32 n, u32 m, u32* tile_row, hipStream_t s);
-// Component roots: parent[v] = smallest vertex ID of v's component.  `mode` is one
-// device word of scratch.
-void launch_cc(const u32* rowptr, const u32* colidx, const u32* tile_row, u32 n, u32 m,
-               u32* parent, u32* mode, hipStream_t s);
+// Component roots: parent[v] = smallest vertex ID of v's component (sampled union-find).
+// `mode` is two device words of scratch.
+void launch_cc(const u32* rowptr, const u32* colidx, u32 n, u32 m, u32* parent, u32* mode,
+               hipStream_t s);
+// The first search's roots: mode[0] = v0, the smallest vertex with neighbours (kInf if
+// none), parent[v] = v for v0 and the isolated vertices, v0 for the others; mode[2] = 0.
+// `mode` is four device words.
+void launch_first_root(const u32* rowptr, u32 n, u32* parent, u32* mode, hipStream_t s);
+// After the first search: the unreached vertices become their own parents, counted in
+// mode[2].
+void launch_rest_init(const u32* level, u32 n, u32* parent, u32* mode, hipStream_t s);
+// Roots of the unreached vertices: their edges joined (mode[0] = v0 marks the reached
+// component), then every parent compressed to its root.
+void launch_rest_links(const u32* rowptr, const u32* colidx, u32 n, u32* parent, u32* mode,
+                       hipStream_t s);
 // vinfo[v] = (L(v) mod 2) << 7 | degree class; hcur[v] = rowptr[v] (the record cursors).
 // class_hist (128 words, zeroed; may be null): vertices per degree class, for the
 // classes >= hist_min (the others stay 0).
@@ -111,8 +122,10 @@ bool validate_rowptr_ok(const u32* rowptr, u32 n, u32 m, u32* flag, hipStream_t 
 // ---- BFS ----
 // queue0 / queue1: n words each; bigq0 / bigq1: bfs_big_cap(n, m) words each (room for
 // every vertex whose list is shared by the grid in top-down levels).
+// keep: vertices with a level from an earlier search keep it and take no part (level
+// holds that search's result; the others must be kInf).
 void launch_bfs_init(const u32* rowptr, const u32* parent, u32 n, u32* level, u32* queue0,
-                     u32* bigq0, u32* fb, BfsCtl* ctl, hipStream_t s);
+                     u32* bigq0, u32* fb, BfsCtl* ctl, hipStream_t s, bool keep = false);
 // fb: three frontier bitmaps of (n + 31) / 32 words each, zeroed before launch_bfs_init.
 // part: bfs_part_words() words of per-workgroup totals; grid <= bfs_grid(n).
 void launch_bfs_level(const u32* rowptr, const u32* colidx, u32 n, u32 k, u32* level,

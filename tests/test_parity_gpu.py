@@ -62,7 +62,23 @@ CASES = {
     "er14_d256": lambda: gg.erdos_renyi(1 << 14, 256, 7),
     "union": lambda: gg.disjoint_union([gg.rmat(9, 16, 1), gg.empty_graph(5), gg.wheel(30),
                                         gg.tri_grid(10, 13, 0.1, 2), gg.complete(20)]),
+    # the smallest vertex with neighbours sits in a triangle, the large component after
+    # it: the first search reaches three vertices, the union-find finds the rest
+    "small_first": lambda: gg.disjoint_union([gg.empty_graph(3), gg.complete(3),
+                                              gg.rmat(12, 16, 21)]),
+    # a large first component and many small ones after it (their edges joined alone)
+    "big_first": lambda: gg.disjoint_union([gg.erdos_renyi(1 << 12, 16, 8)]
+                                           + [gg.complete(4)] * 40 + [gg.empty_graph(7)]
+                                           + [gg.path(9)] * 5),
 }
+
+
+def components(g):
+    """Connected components (isolated vertices included), via scipy."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    a = sp.csr_matrix((np.ones(g.nnz, dtype=np.int8), g.colidx, g.rowptr), shape=(g.n, g.n))
+    return int(connected_components(a, directed=False)[0]) if g.n else 0
 
 
 _cache = {}
@@ -93,6 +109,7 @@ def test_count_matches_oracle(tc_lib, name):
     assert stats.c1 == c1 and stats.c2 == c2
     assert np.array_equal(level.cpu().numpy().view(np.uint32), r.level)
     assert stats.depth == int(r.level.max(initial=0))
+    assert stats.num_roots == components(g)
     assert tc_lib.tc_count(rp, ci) == r.triangles
 
 
