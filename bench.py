@@ -417,11 +417,38 @@ def bench_single(args, tcm, torch):
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    if args.per_vertex:
+        out["per_vertex"] = bench_per_vertex(args, tcm, torch, rp, ci, g, T)
     isect_ms = sum(isect.values())
     out["isect_classes"]["isect_all"] = {
         "plan_bytes": sum(v["plan_bytes"] for v in cb.values()),
         "ms": round(isect_ms, 4)}
     return out
+
+
+def bench_per_vertex(args, tcm, torch, rp, ci, g, T) -> dict:
+    """t(v) for every vertex (tc_count_per_vertex) and C(v) from it (tc_local_clustering):
+    one untimed call, then --per-vertex calls timed like the count's steps."""
+    tri = tcm.tc_count_per_vertex(rp, ci)
+    assert int(tri.sum().item()) == 3 * T
+    torch.cuda.synchronize()
+    k = args.per_vertex
+    t0 = time.perf_counter()
+    for _ in range(k):
+        tri = tcm.tc_count_per_vertex(rp, ci)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(k):
+        cc = tcm.tc_local_clustering(rp, tri)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert int(tri.sum().item()) == 3 * T and cc.numel() == g.n
+    ms = (t1 - t0) * 1e3 / k
+    log(f"[bench] per-vertex counts: {ms:.3f} ms/call")
+    return {"calls": k, "ms_per_call": round(ms, 4),
+            "input_edges_per_s": g.num_edges / (ms * 1e-3),
+            "counted_triangles": T, "attributions": 3 * T,
+            "clustering_ms_per_call": round((t2 - t1) * 1e3 / k, 4)}
 
 
 # ---- batched workload ------------------------------------------------------------------------
@@ -913,6 +940,9 @@ def main():
                     help="hub pass parameters (tc_set_hub_params) for this run; 0,0 turns it off")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the intersection class parameters on the workload first")
+    ap.add_argument("--per-vertex", type=int, default=0, metavar="K",
+                    help="single-graph workloads: also time K tc_count_per_vertex and "
+                         "tc_local_clustering calls")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-huge-scale", type=int, default=26)
     ap.add_argument("--serve-small-max", type=int, default=1 << 18)

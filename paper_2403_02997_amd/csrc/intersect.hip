@@ -174,7 +174,8 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
   __shared__ u32 s_tmp[kBigWaves];
   __shared__ u64 s_red[5 * kBigWaves];
   __shared__ u32 s_item;
-  const BlockShared sh{s_table, s_qincl, s_pinfo, s_tmp};
+  __shared__ u32 s_ycnt[PV ? kBigSeg : 1];
+  const BlockShared sh{s_table, s_qincl, s_pinfo, s_tmp, s_ycnt};
   const u32 tid = threadIdx.x;
   Counts c{0, 0, 0, 0, 0};
   Tally tl{0, 0, 0, 0};

@@ -227,6 +227,21 @@ __device__ __forceinline__ u32 bucket_has(uint4 v, u32 k2) {
   return hit ? 1u : (flagged ? 3u : 0u);
 }
 
+// Slot index (4 b + j) of w in a set built by hash_insert, for a w known to be present
+// (a probe found it): per-vertex attribution keeps a hit counter per slot.
+__device__ __forceinline__ u32 hash_slot_of(const u32* table, u32 bmask, u32 w) {
+  const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  u32 b = hash_mix(w) & bmask;
+  while (true) {
+    const uint4 v = t4[b];
+    if (v.x != kInf && v.x >> 1 == w) return 4 * b;
+    if (v.y != kInf && v.y >> 1 == w) return 4 * b + 1;
+    if (v.z != kInf && v.z >> 1 == w) return 4 * b + 2;
+    if (v.w != kInf && (v.w & ~kFlag) >> 1 == w) return 4 * b + 3;
+    b = (b + 1) & bmask;
+  }
+}
+
 template <bool MEMBER>
 __device__ __forceinline__ u32 bucket_result(uint4 v, u32 k2) {
   return MEMBER ? bucket_has(v, k2) : bucket_check(v, k2);
@@ -448,37 +463,34 @@ __device__ __forceinline__ void Tally::fold(Counts& c) {
   s = c2 = t2 = probes = 0;
 }
 
-// Per-vertex attribution of a counted triangle {x, y, w} (result r of a probe of w).
-__device__ __forceinline__ void attribute(u64* tri, u32 r, u32 w, u32 x, u32 y, u32 vmax) {
-  if (r == 1u || (r == 2u && w > vmax)) {
-    atomicAdd((unsigned long long*)&tri[x], 1ull);
-    atomicAdd((unsigned long long*)&tri[y], 1ull);
-    atomicAdd((unsigned long long*)&tri[w], 1ull);
-  }
+// Whether the probe result r of a common neighbour w of the cover edge {x, y} is a
+// counted triangle: w on another level than x, or on the same level and larger than
+// both endpoints (vmax = max(x, y)).
+__device__ __forceinline__ bool counted_hit(u32 r, u32 w, u32 vmax) {
+  return r == 1u || (r == 2u && w > vmax);
 }
 
 // Tally one common neighbour w of the cover edge {x, y}: r = 1 when w is on another
 // level than x (c1), r = 2 on the same level (c2; counted into T only when w is larger
-// than both endpoints).  PV attributes each counted triangle to its three vertices.
-template <bool PV>
-__device__ __forceinline__ void count_hit(u32 r, u32 w, u32 x, u32 y, u32 vmax, Counts& c,
-                                          u64* tri) {
-  bool counted = false;
+// than both endpoints).  Returns whether the triangle {x, y, w} is counted.
+__device__ __forceinline__ bool count_hit(u32 r, u32 w, u32 vmax, Counts& c) {
   if (r == 1) {
     c.c1 += 1;
-    counted = true;
-  } else if (r == 2) {
+    return true;
+  }
+  if (r == 2) {
     c.c2 += 1;
     if (w > vmax) {
       c.t2 += 1;
-      counted = true;
+      return true;
     }
   }
-  if (PV && counted) {
-    atomicAdd((unsigned long long*)&tri[x], 1ull);
-    atomicAdd((unsigned long long*)&tri[y], 1ull);
-    atomicAdd((unsigned long long*)&tri[w], 1ull);
-  }
+  return false;
+}
+
+// Adds v to the per-vertex count tri[u] (skipped when v is 0).
+__device__ __forceinline__ void tri_add(u64* tri, u32 u, u64 v) {
+  if (v) atomicAdd((unsigned long long*)&tri[u], (unsigned long long)v);
 }
 
 // First index in [lo, hi) of the sorted array a with a[i] >= v.

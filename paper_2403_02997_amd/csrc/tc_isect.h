@@ -44,8 +44,10 @@ __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 
                                             u64* __restrict__ tri) {
   const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1], np = hcnt[x];
   const u32 px = vinfo[x] & 0x80u;
+  u64 xh = 0;  // PV: counted triangles of x, added once at the end
   for (u32 q = 0; q < np; ++q) {
     const u32 y = hadj[(size_t)(bx + q) * HS];
+    u32 yh = 0;  // PV: counted triangles of this cover edge, added to t(y) once
     u32 i = bx, j = cb + rowptr[y];
     const u32 je = cb + rowptr[y + 1];
     c.probes += je - j;
@@ -62,14 +64,22 @@ __device__ __forceinline__ void lane_vertex(const u32* __restrict__ rowptr, u32 
           b = colidx[j];
         } else {
           const u32 r = 1u + (((vinfo[a] & 0x80u) == px) ? 1u : 0u);
-          count_hit<PV>(r, a, x, y, vmax, c, tri);
+          if (count_hit(r, a, vmax, c) && PV) {
+            tri_add(tri, a, 1);
+            ++yh;
+          }
           if (++i == ex || ++j == je) break;
           a = colidx[i];
           b = colidx[j];
         }
       }
     }
+    if (PV) {
+      tri_add(tri, y, yh);
+      xh += yh;
+    }
   }
+  if (PV) tri_add(tri, x, xh);
 }
 
 // ---- wave class: one wavefront per staged vertex x -----------------------------------
@@ -148,6 +158,7 @@ __device__ __forceinline__ void wave_vertex(
   }
   const u32 mask = bucket_mask(dx, kWaveSlots);
   c.staged += lane == 0 ? dx : 0;
+  u32 xh = 0;  // PV: this lane's counted triangles of x, summed over the wavefront at the end
   // pruned forms: the staged keys (at most kWaveSlots / 4, i.e. 8 per lane) are all
   // loaded before the table is cleared and filled
   constexpr u32 SK = KEYS ? kWaveSlots / 4 / kWave : 1;
@@ -274,15 +285,27 @@ __device__ __forceinline__ void wave_vertex(
         } else {
           u32 res[NE];
           hash_probe_n<NE>(table, mask, e[u], ok, res);
+          u32 qh = 0;  // PV: counted triangles of this quad, one t(y) add per quad
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) {
             tl.add(res[i], e[u][i], vmax);
-            if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+            if (PV && counted_hit(res[i], e[u][i], vmax)) {
+              tri_add(tri, e[u][i], 1);
+              ++qh;
+            }
+          }
+          if (PV) {
+            tri_add(tri, y2, qh);
+            xh += qh;
           }
         }
       }
     }
     wave_lds_sync();
+  }
+  if (PV) {
+    const u64 sx = wave_sum_u64(xh);
+    if (lane == 0) tri_add(tri, x, sx);
   }
 }
 
@@ -468,7 +491,14 @@ struct BlockShared {
   u32* qincl;
   uint4* pinfo;
   u32* tmp;
+  u32* ycnt;  // per-vertex counts: counted triangles per partner of the item (LDS)
 };
+
+// Per-vertex counts in the kFull pass: hash chunks of at most kPvChunk keys fill the
+// lower half of the table, and the upper half (from kPvCnt) counts the hits of each
+// slot's key, added to t(w) once per chunk.
+constexpr u32 kPvCnt = kBigSlots / 2;
+constexpr u32 kPvChunk = kPvCnt / 8;
 
 // One pass over the partners of a work item.  The staged keys ga[gs .. ge) (ascending)
 // go to LDS either as hash sets of at most prm.chunk keys (BM = false) or, for the
@@ -495,10 +525,14 @@ __device__ __forceinline__ void block_pass(
   constexpr bool MEMBER = MODE == kOther || MODE == kSame || MODE == kMember;
   u32& hits = MODE == kSame ? tl.t2 : tl.s;  // same-level apexes above both ends: t2
   const u32 glen = ge - gs;
+  static_assert(!PV || MODE == kFull, "per-vertex counts use the full form");
+  const u32 chunk = PV ? min(prm.chunk, kPvChunk) : prm.chunk;
+  u32 xh = 0;  // PV: this thread's counted triangles of x
+  if (PV && tid < pn) sh.ycnt[tid] = 0;
   // hash chunks by count, or bitmap windows by ID
   const u32 w_first = BM && glen ? ga[gs] >> kWinBits : 0u;
   const u32 nch = BM ? (glen ? (ga[ge - 1] >> kWinBits) - w_first + 1 : 0u)
-                     : (glen + prm.chunk - 1) / prm.chunk;
+                     : (glen + chunk - 1) / chunk;
   u32 lo = plo;  // cursor: elements below it were probed against earlier chunks
   u32 c0 = gs;   // first staged key of the chunk
   for (u32 ch = 0; ch < nch; ++ch) {
@@ -508,15 +542,18 @@ __device__ __forceinline__ void block_pass(
       clen = lower_bound_g(ga, c0, ge, wb + (1u << kWinBits)) - c0;
       if (clen == 0) continue;  // no staged key in this window (uniform)
     } else {
-      clen = min(prm.chunk, ge - c0);
+      clen = min(chunk, ge - c0);
     }
-    const u32 mask = BM ? 0u : bucket_mask(clen, kBigSlots);
+    const u32 mask = BM ? 0u : bucket_mask(clen, PV ? kPvCnt : (u32)kBigSlots);
     c.staged += tid == 0 ? clen : 0;
     if (BM) {
       uint4* t4 = reinterpret_cast<uint4*>(sh.table);
       for (u32 i = tid; i < (u32)kBigSlots / 4; i += blockDim.x) t4[i] = make_uint4(0, 0, 0, 0);
     } else {
-      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) sh.table[i] = kInf;
+      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) {
+        sh.table[i] = kInf;
+        if (PV) sh.table[kPvCnt + i] = 0;
+      }
     }
     // this partner's elements up to the chunk's largest ID or the window's end (the
     // ones between two chunks are in no chunk and find nothing in either)
@@ -568,6 +605,7 @@ __device__ __forceinline__ void block_pass(
       uint4 inf[QU];
       u32 addr[QU];
       bool live[QU];
+      u32 pidx[QU];  // PV: the quad's partner
 #pragma unroll
       for (int u = 0; u < QU; ++u) {
         const u32 w0 = qw + u * kWave;        // first quad of this window
@@ -589,6 +627,7 @@ __device__ __forceinline__ void block_pass(
           if (nb < (u32)kWave) break;
         }
         p = min(p, pn - 1);  // lanes past the range keep a valid index
+        pidx[u] = p;
         inf[u] = sh.pinfo[p];
         addr[u] = (inf[u].x + q) * NE;
         if (VEC) {
@@ -634,22 +673,44 @@ __device__ __forceinline__ void block_pass(
         } else {
           u32 res[NE];
           hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
+          u32 qh = 0;  // PV: counted triangles of this quad
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) {
             if (MODE == kFull) {
               tl.add(res[i], e[u][i], vmax);
-              if (PV) attribute(tri, res[i], e[u][i], x, y2, vmax);
+              if (PV && counted_hit(res[i], e[u][i], vmax)) {
+                atomicAdd(&sh.table[kPvCnt + hash_slot_of(sh.table, mask, e[u][i])], 1u);
+                ++qh;
+              }
             } else {
               tl.s += res[i] & 1u;  // other-level apex (c1)
               tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
             }
           }
+          if (PV && qh) {
+            atomicAdd(&sh.ycnt[pidx[u]], qh);
+            xh += qh;
+          }
         }
       }
     }
     __syncthreads();
+    if (PV) {
+      // t(w) for the chunk's keys; the table is rebuilt only after every thread is done
+      for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) {
+        const u32 k = sh.table[kPvCnt + i];
+        if (k) tri_add(tri, (sh.table[i] & ~kFlag) >> 1, k);
+      }
+      __syncthreads();
+    }
     lo = hi;
     c0 += clen;
+  }
+  if (PV) {
+    // every partner's count is complete after the last chunk's barrier
+    if (tid < pn) tri_add(tri, y, sh.ycnt[tid]);
+    const u64 sx = wave_sum_u64(xh);
+    if (lane == 0) tri_add(tri, x, sx);
   }
 }
 

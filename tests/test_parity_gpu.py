@@ -235,13 +235,35 @@ def test_forward_ordering_under_class_and_hub_settings(tc_lib, name, setting):
     assert got == r.triangles and fwd == 1
 
 
-@pytest.mark.parametrize("name", ["karate", "wheel500", "rmat12", "er14_d4", "book10000",
-                                  "grid64_del", "union"])
+@pytest.mark.parametrize("name", ["karate", "K40", "star5000", "wheel500", "rmat12", "er14_d4",
+                                  "book10000", "grid64_del", "union", "small_first", "rmat16",
+                                  "rmat14_ef32", "er16_d32"])
 def test_per_vertex_matches_oracle(tc_lib, name):
+    # rmat16, rmat14_ef32 and book10000 have staged vertices of more than 2048 entries,
+    # whose per-vertex pass stages N(x) in several hash chunks
     g, r, _, _ = case(name)
     say(f"[parity] tc_count_per_vertex {name}")
     rp, ci = upload(g, tc_lib)
     t = tc_lib.as_u64(tc_lib.tc_count_per_vertex(rp, ci))
+    assert np.array_equal(t, r.per_vertex)
+
+
+@pytest.mark.parametrize("setting", ["chunked", "wave"])
+@pytest.mark.parametrize("name", ["rmat16", "book10000", "er16_d32", "union"])
+def test_per_vertex_under_isect_settings(tc_lib, name, setting):
+    # chunked: every vertex above 16 entries in the workgroup class, 100-key chunks and
+    # 7-partner items; wave: the wavefront class up to 512 entries, chunks of up to
+    # 16384 keys asked for (the per-vertex pass caps them at 2048)
+    g, r, _, _ = case(name)
+    isect, _ = SPLIT_SETTINGS[setting]
+    say(f"[parity] tc_count_per_vertex {name} ({setting})")
+    rp, ci = upload(g, tc_lib)
+    saved = tc_lib.tc_get_isect_params()
+    try:
+        tc_lib.tc_set_isect_params(*isect)
+        t = tc_lib.as_u64(tc_lib.tc_count_per_vertex(rp, ci))
+    finally:
+        tc_lib.tc_set_isect_params(*saved)
     assert np.array_equal(t, r.per_vertex)
 
 
