@@ -156,7 +156,10 @@ __device__ __forceinline__ void wave_vertex(
       hi0 = cb + rowptr[y0 + 1];
     }
   }
-  const u32 mask = bucket_mask(dx, kWaveSlots);
+  // PV: the set fills the lower half of the wavefront's table and the upper half counts
+  // the hits of each slot's key, added to t(w) once at the end
+  constexpr u32 kCnt = kWaveSlots / 2;
+  const u32 mask = bucket_mask(dx, PV ? kCnt : (u32)kWaveSlots);
   c.staged += lane == 0 ? dx : 0;
   u32 xh = 0;  // PV: this lane's counted triangles of x, summed over the wavefront at the end
   // pruned forms: the staged keys (at most kWaveSlots / 4, i.e. 8 per lane) are all
@@ -170,7 +173,10 @@ __device__ __forceinline__ void wave_vertex(
       sk[t] = i < dx ? colidx[sb + i] : 0u;
     }
   }
-  for (u32 i = lane; i < (mask + 1) * 4; i += kWave) table[i] = kInf;
+  for (u32 i = lane; i < (mask + 1) * 4; i += kWave) {
+    table[i] = kInf;
+    if (PV) table[kCnt + i] = 0;
+  }
   wave_lds_sync();
   if (KEYS) {
 #pragma unroll
@@ -290,7 +296,7 @@ __device__ __forceinline__ void wave_vertex(
           for (u32 i = 0; i < NE; ++i) {
             tl.add(res[i], e[u][i], vmax);
             if (PV && counted_hit(res[i], e[u][i], vmax)) {
-              tri_add(tri, e[u][i], 1);
+              atomicAdd(&table[kCnt + hash_slot_of(table, mask, e[u][i])], 1u);
               ++qh;
             }
           }
@@ -304,8 +310,13 @@ __device__ __forceinline__ void wave_vertex(
     wave_lds_sync();
   }
   if (PV) {
+    for (u32 i = lane; i < (mask + 1) * 4; i += kWave) {
+      const u32 k = table[kCnt + i];
+      if (k) tri_add(tri, (table[i] & ~kFlag) >> 1, k);
+    }
     const u64 sx = wave_sum_u64(xh);
     if (lane == 0) tri_add(tri, x, sx);
+    wave_lds_sync();  // the next vertex clears the table
   }
 }
 
