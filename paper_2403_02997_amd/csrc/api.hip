@@ -352,8 +352,8 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
                u32* level_out, u64* tri, bool pruned, RunOut* out, bool split_stats = false) {
   prepare_pool();
   const IsectParams prm = g_params;
-  // the hub pass serves the pruned count only (per-vertex and c1 / c2 tallies stay per
-  // edge), on graphs of at least kHubEntriesPerDegree stored entries per unit of the hub
+  // the hub pass serves the pruned count only (per-vertex counts and c1 / c2 tallies stay
+  // per cover edge: a hub mask says how many hubs close a triangle, not which), on graphs of at least kHubEntriesPerDegree stored entries per unit of the hub
   // degree floor (smaller ones cannot give hubs enough partners to pay for the pass)
   const bool hub_size = (u64)m >= (u64)kHubEntriesPerDegree * g_hub_min_degree;
   const HubParams hp{pruned && !tri && hub_size ? g_hub_max : 0u,
@@ -574,19 +574,19 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
       launch_hub_count(rowptr, colidx2, sabove, split, h_plan.num_hubs, hy, hubmask, hitems,
                        h_plan.num_hub_items, ctr, split_stats, sw);
     launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
-                      tri, pruned && !tri, split_stats, sw);
+                      tri, pruned, split_stats, sw);
     launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
     launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
-                       pruned && !tri, split_stats, s);
+                       pruned, split_stats, s);
   } else {
     timer.mark();
     launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
     timer.mark();
     launch_isect_block(rowptr, colidx, m, tail4, vinfo, sv, items, h_items, prm, plan, ctr, tri,
-                       pruned && !tri, split_stats, s);
+                       pruned, split_stats, s);
     timer.mark();
     launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
-                      tri, pruned && !tri, split_stats, s);
+                      tri, pruned, split_stats, s);
     timer.mark();
     if (hubs && timer.on)
       launch_hub_masks(rowptr, colidx2, split, sabove, hublist, h_plan.num_hubs, n, hcuts, hubmask,
@@ -757,7 +757,7 @@ int tc_count_per_vertex(const uint32_t* rowptr, const uint32_t* colidx, uint32_t
   }
   RunOut ro;
   memset(&ro, 0, sizeof(ro));
-  return run_single(rowptr, colidx, n, (u32)m, stream, nullptr, (u64*)tri_out, false, &ro);
+  return run_single(rowptr, colidx, n, (u32)m, stream, nullptr, (u64*)tri_out, true, &ro);
 }
 
 int tc_validate_csr(const uint32_t* rowptr, const uint32_t* colidx, uint32_t n, uint64_t m,

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
   __shared__ u64 s_red[5 * kW];
   const u32 wid = threadIdx.x / kWave, lane = lane_id();
   Counts c{0, 0, 0, 0, 0};
-  if constexpr (REC && !ST && !PV) {
+  if constexpr (REC && !ST) {
     // Pruned count: 64 vertices claimed per counter atomic, their row data loaded in one
     // step; those of up to kSubMax entries are counted four at a time, one per 16-lane
     // group (subwave_vertex), the others one at a time by the whole wavefront.
@@ -96,9 +96,14 @@ __global__ void __launch_bounds__(kIsectThreads) k_isect_wave(
         const int s0 = src < 0 ? 0 : src;
         WaveMeta gm{(u32)__shfl(mt.bx, s0, kWave), (u32)__shfl(mt.ex, s0, kWave),
                     (u32)__shfl(mt.sb, s0, kWave), (u32)__shfl(mt.np, s0, kWave)};
+        // every lane shuffles (the source lane may sit in a group without a vertex), then
+        // a group without one drops the value
+        const u32 xs = (u32)__shfl(x, s0, kWave);
+        const u32 gx = src < 0 ? 0u : xs;
         if (src < 0) gm = WaveMeta{0, 0, 0, 0};
         Tally tl{0, 0, 0, 0};
-        subwave_vertex<kPartRec>(colidx, m, 0u, nullptr, hrec, nullptr, gm, gtab, tl, c);
+        subwave_vertex<kPartRec, PV>(colidx, m, 0u, nullptr, hrec, nullptr, gm, gtab, tl, c, gx,
+                                     tri);
         tl.fold(c);
       }
       todo = __ballot(live && !sub);
@@ -185,12 +190,13 @@ __global__ void __launch_bounds__(kBigThreads) k_isect_block(
     const u32 it = s_item;
     if (it >= nitems) break;
     const Item item = items[it];
-    if (PRUNED)
-      block_item_rec<VEC, true, ST>(rowptr, 0u, colidx2, m, tail4b, split, sabove, hcnt, hrec,
-                                    nullptr, nullptr, item.x, item.seg, prm, sh, tl, c);
+    if constexpr (PRUNED)
+      block_item_rec<VEC, true, ST, kPartRec, kQuadUnroll, PV>(
+          rowptr, 0u, colidx2, m, tail4b, split, sabove, hcnt, hrec, nullptr, nullptr, item.x,
+          item.seg, prm, sh, tl, c, tri);
     else
-      block_item<PV, VEC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec),
-                             item.x, item.seg, prm, sh, tl, c, tri);
+      block_item<VEC, 4>(rowptr, 0u, colidx, m, tail4, vinfo, hcnt, record_ids(hrec), item.x,
+                         item.seg, prm, sh, tl, c);
     tl.fold(c);
   }
   block_flush_counts(c, 2, ctr, s_red);
@@ -239,7 +245,7 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* t
                        hipStream_t s) {
   if (nwx == 0) return;
   const u32 g = min(cdiv(nwx, kIsectThreads / kWave), resident_blocks(8));
-  const bool rec = pruned && !tri;
+  const bool rec = pruned;
   const u32* src = rec ? sv.colidx2 : colidx;  // the streamed and staged rows
   const u32* tail = rec ? sv.tail4b : tail4;
   const bool vec = ((uintptr_t)src & 15u) == 0;
@@ -247,9 +253,9 @@ void launch_isect_wave(const u32* rowptr, const u32* colidx, u32 m, const u32* t
   hipLaunchKernelGGL((k_isect_wave<PV, VEC, REC, ST>), dim3(g), dim3(kIsectThreads), 0, s,      \
                      rowptr, src, m, tail, vinfo, sv.hcnt, sv.hrec, sv.sabove, wave_x, nwx,     \
                      plan, ctr, tri)
-  if (tri) {
-    if (vec) TC_LAUNCH_WAVE(true, true, false, false);
-    else TC_LAUNCH_WAVE(true, false, false, false);
+  if (tri) {  // per-vertex counts: the pruned form
+    if (vec) TC_LAUNCH_WAVE(true, true, true, false);
+    else TC_LAUNCH_WAVE(true, false, true, false);
   } else if (rec && split_stats) {
     if (vec) TC_LAUNCH_WAVE(false, true, true, true);
     else TC_LAUNCH_WAVE(false, false, true, true);
@@ -269,15 +275,15 @@ void launch_isect_block(const u32* rowptr, const u32* colidx, u32 m, const u32* 
                         bool split_stats, hipStream_t s) {
   if (nitems == 0) return;
   const u32 g = min(nitems, resident_blocks(1));
-  const bool rec = pruned && !tri;
+  const bool rec = pruned;
   const bool vec = ((uintptr_t)(rec ? sv.colidx2 : colidx) & 15u) == 0;
 #define TC_LAUNCH_BLOCK(PV, VEC, PR, ST)                                                       \
   hipLaunchKernelGGL((k_isect_block<PV, VEC, PR, ST>), dim3(g), dim3(kBigThreads), 0, s,        \
                      rowptr, colidx, m, tail4, sv.colidx2, sv.split, sv.sabove, sv.tail4b,      \
                      vinfo, sv.hcnt, sv.hrec, items, nitems, p, plan, ctr, tri)
-  if (tri) {
-    if (vec) TC_LAUNCH_BLOCK(true, true, false, false);
-    else TC_LAUNCH_BLOCK(true, false, false, false);
+  if (tri) {  // per-vertex counts: the pruned form
+    if (vec) TC_LAUNCH_BLOCK(true, true, true, false);
+    else TC_LAUNCH_BLOCK(true, false, true, false);
   } else if (rec && split_stats) {
     if (vec) TC_LAUNCH_BLOCK(false, true, true, true);
     else TC_LAUNCH_BLOCK(false, false, true, true);

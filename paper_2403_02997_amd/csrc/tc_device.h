@@ -227,17 +227,19 @@ __device__ __forceinline__ u32 bucket_has(uint4 v, u32 k2) {
   return hit ? 1u : (flagged ? 3u : 0u);
 }
 
-// Slot index (4 b + j) of w in a set built by hash_insert, for a w known to be present
-// (a probe found it): per-vertex attribution keeps a hit counter per slot.
-__device__ __forceinline__ u32 hash_slot_of(const u32* table, u32 bmask, u32 w) {
+// Slot index (4 b + j) of the plain key w in a membership set built by hash_insert_key
+// with key = w, or kInf when w is absent: per-vertex attribution counts the hits of
+// each staged key.
+__device__ __forceinline__ u32 hash_find_key(const u32* table, u32 bmask, u32 w) {
   const uint4* t4 = reinterpret_cast<const uint4*>(table);
   u32 b = hash_mix(w) & bmask;
   while (true) {
     const uint4 v = t4[b];
-    if (v.x != kInf && v.x >> 1 == w) return 4 * b;
-    if (v.y != kInf && v.y >> 1 == w) return 4 * b + 1;
-    if (v.z != kInf && v.z >> 1 == w) return 4 * b + 2;
-    if (v.w != kInf && (v.w & ~kFlag) >> 1 == w) return 4 * b + 3;
+    if (v.x == w) return 4 * b;
+    if (v.y == w) return 4 * b + 1;
+    if (v.z == w) return 4 * b + 2;
+    if ((v.w & ~kFlag) == w && v.w != kInf) return 4 * b + 3;
+    if (v.w - kFlag >= kInf - kFlag) return kInf;  // the bucket is not flagged: absent
     b = (b + 1) & bmask;
   }
 }
@@ -461,13 +463,6 @@ __device__ __forceinline__ void Tally::fold(Counts& c) {
   c.t2 += t2;
   c.probes += probes;
   s = c2 = t2 = probes = 0;
-}
-
-// Whether the probe result r of a common neighbour w of the cover edge {x, y} is a
-// counted triangle: w on another level than x, or on the same level and larger than
-// both endpoints (vmax = max(x, y)).
-__device__ __forceinline__ bool counted_hit(u32 r, u32 w, u32 vmax) {
-  return r == 1u || (r == 2u && w > vmax);
 }
 
 // Tally one common neighbour w of the cover edge {x, y}: r = 1 when w is on another

@@ -126,7 +126,7 @@ __device__ __forceinline__ void wave_vertex(
     const uint4* __restrict__ hrec, const uint4* __restrict__ vrec, u32 x, WaveMeta mt,
     u32* table, uint4* pinfo, u32* pend, u32* mark, Tally& tl, Counts& c,
     u64* __restrict__ tri) {
-  static_assert(!(REC && PV), "per-vertex counts use the full form");
+  static_assert(!PV || (REC && !ST), "per-vertex counts: the pruned form without split tallies");
   static_assert(!ST || REC, "split statistics come from the partner records");
   static_assert(!(SR && (REC || PV || HS != 1)), "split rows: full form over plain partner lists");
   static_assert(!(SA && (REC || SR || PV || HS != 1)), "sabove ranges: plain partner lists");
@@ -199,7 +199,7 @@ __device__ __forceinline__ void wave_vertex(
     if (p < np) {
       if (REC) {
         const uint4 r = pb == 0 ? r0 : hrec[hs + p];
-        y = ST ? r.y : r.w;  // the pruned form never reads y; ST keeps the range split there
+        y = ST ? r.y : r.w;  // the pruned form reads y for per-vertex counts only; ST keeps the range split there
         lo = r.x;
         hi = r.z;
       } else if (PL && pb == 0) {
@@ -286,24 +286,27 @@ __device__ __forceinline__ void wave_vertex(
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) sm[i] = addr[u] + i < inf[u].w;
           hash_count_split_n<NE, true>(table, mask, e[u], ok, sm, tl.s, tl.t2);
+        } else if (KEYS && PV) {
+          // every hit is a counted apex: count it under its slot, its partner and x
+          u32 qh = 0;
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) {
+            const u32 sl = ok[i] ? hash_find_key(table, mask, e[u][i]) : kInf;
+            if (sl != kInf) {
+              atomicAdd(&table[kCnt + sl], 1u);
+              ++qh;
+            }
+          }
+          tri_add(tri, y2, qh);
+          xh += qh;
+          tl.s += qh;
         } else if (KEYS) {
           hash_count_n<NE>(table, mask, e[u], ok, tl.s);
         } else {
           u32 res[NE];
           hash_probe_n<NE>(table, mask, e[u], ok, res);
-          u32 qh = 0;  // PV: counted triangles of this quad, one t(y) add per quad
 #pragma unroll
-          for (u32 i = 0; i < NE; ++i) {
-            tl.add(res[i], e[u][i], vmax);
-            if (PV && counted_hit(res[i], e[u][i], vmax)) {
-              atomicAdd(&table[kCnt + hash_slot_of(table, mask, e[u][i])], 1u);
-              ++qh;
-            }
-          }
-          if (PV) {
-            tri_add(tri, y2, qh);
-            xh += qh;
-          }
+          for (u32 i = 0; i < NE; ++i) tl.add(res[i], e[u][i], vmax);
         }
       }
     }
@@ -312,7 +315,7 @@ __device__ __forceinline__ void wave_vertex(
   if (PV) {
     for (u32 i = lane; i < (mask + 1) * 4; i += kWave) {
       const u32 k = table[kCnt + i];
-      if (k) tri_add(tri, (table[i] & ~kFlag) >> 1, k);
+      if (k) tri_add(tri, table[i] & ~kFlag, k);
     }
     const u64 sx = wave_sum_u64(xh);
     if (lane == 0) tri_add(tri, x, sx);
@@ -339,6 +342,9 @@ __device__ __forceinline__ void wave_vertex(
 //                range also holds y's same-level entries in (y, x], which the staged
 //                keys (same-level ones above x only) never match, so the hits are the
 //                same as with the range from above max(x, y).
+// PV (kPartRec): per-vertex counts of the group's vertex x: t(x) summed over the group,
+// t(y) added once per quad, t(w) counted per slot of the group's set in the unused upper
+// half of the wavefront table and added once at the end.
 // All 64 lanes call it together; a group without a vertex passes mt.np = 0 and an empty
 // row.
 constexpr u32 kSubLanes = 16;
@@ -346,7 +352,8 @@ constexpr u32 kSubGroups = kWave / kSubLanes;
 constexpr u32 kSubMax = 64;     // d(x) of the sub-wavefront class at most
 constexpr u32 kSubSlots = 256;  // LDS hash slots per group
 constexpr u32 kSubU = 4;        // quads per lane in flight
-static_assert(kSubGroups * kSubSlots <= kWaveSlots, "the groups share one wavefront table");
+constexpr u32 kSubCnt = kSubGroups * kSubSlots;  // PV: a group's slot counters sit this far on
+static_assert(2 * kSubCnt <= kWaveSlots, "the groups' sets and counters share one wavefront table");
 
 __device__ __forceinline__ u32 group_incl_scan(u32 v) {
   const u32 gl = lane_id() & (kSubLanes - 1);
@@ -368,27 +375,29 @@ enum PartnerMode { kPartRec = 1, kPartAbove = 2 };
 
 // colidx2 has 4 readable entries past m; table is this group's kSubSlots slots; vrec
 // (kPartAbove) is local to the graph like rowptr: {row start, sabove, split, row end}.
-template <int PM>
+template <int PM, bool PV = false>
 __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, u32 m, u32 cb,
                                                const u32* __restrict__ hadj,
                                                const uint4* __restrict__ hrec,
                                                const uint4* __restrict__ vrec,
                                                const WaveMeta& mt, u32* table, Tally& tl,
-                                               Counts& c) {
+                                               Counts& c, u32 x = 0, u64* __restrict__ tri = nullptr) {
   static_assert(PM == kPartRec || PM == kPartAbove, "pruned forms only");
+  static_assert(!PV || PM == kPartRec, "per-vertex counts come from the records");
   constexpr u32 SK = kSubMax / kSubLanes;  // staged keys per lane at most
   const u32 lane = lane_id(), gl = lane & (kSubLanes - 1), gb = lane & ~(kSubLanes - 1);
   const u32 bx = mt.bx, np = mt.np, sb = mt.sb;
   const u32 dx = mt.ex - sb;  // staged entries: x's row from sabove[x] on
   // the partner info of batch b (up to 16 partners, one per lane of the group)
-  auto partner = [&](u32 b, u32& lo, u32& hi) {
+  auto partner = [&](u32 b, u32& lo, u32& hi, u32& y) {
     const u32 p = b * kSubLanes + gl;
-    lo = hi = 0;
+    lo = hi = y = 0;
     if (p < np) {
       if (PM == kPartRec) {
         const uint4 r = hrec[bx + p];  // the records sit in place of N(x)
         lo = r.x;
         hi = r.z;
+        y = r.w;
       } else {
         const uint4 r = vrec[hadj[bx + p]];  // one 16-byte load: the row's sabove and end
         lo = cb + r.y;
@@ -404,11 +413,15 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, 
     const u32 i = gl + t * kSubLanes;
     sk[t] = i < dx ? colidx2[sb + i] : 0u;
   }
-  u32 lo0, hi0;
-  partner(0, lo0, hi0);
+  u32 lo0, hi0, y0;
+  partner(0, lo0, hi0, y0);
   const u32 mask = bucket_mask(dx ? dx : 1u, kSubSlots);
   c.staged += gl == 0 ? dx : 0;
-  for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) table[i] = kInf;
+  u32 xh = 0;  // PV: this lane's counted triangles of x
+  for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) {
+    table[i] = kInf;
+    if (PV) table[kSubCnt + i] = 0;
+  }
   wave_lds_sync();
 #pragma unroll
   for (u32 t = 0; t < SK; ++t)
@@ -416,8 +429,8 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, 
   wave_lds_sync();
   const u32 nbat = wave_max_u32((np + kSubLanes - 1) / kSubLanes);
   for (u32 b = 0; b < nbat; ++b) {
-    u32 lo = lo0, hi = hi0;
-    if (b > 0) partner(b, lo, hi);
+    u32 lo = lo0, hi = hi0, y = y0;
+    if (b > 0) partner(b, lo, hi, y);
     tl.probes += hi - lo;
     const u32 qa = lo & ~3u;
     const u32 nq = lo < hi ? (hi - qa + 3u) >> 2 : 0u;
@@ -427,7 +440,7 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, 
     const u32 tmax = wave_max_u32(total);
     for (u32 k0 = 0; k0 < tmax; k0 += kSubLanes * kSubU) {
       u32 e[kSubU][4];
-      u32 addr[kSubU], jlo[kSubU], jspan[kSubU];
+      u32 addr[kSubU], jlo[kSubU], jspan[kSubU], jy[kSubU];
       bool live[kSubU];
 #pragma unroll
       for (u32 u = 0; u < kSubU; ++u) {
@@ -446,6 +459,7 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, 
         const u32 qb = (u32)__shfl(qbase, j, kWave);
         jlo[u] = (u32)__shfl(lo, j, kWave);
         jspan[u] = (u32)__shfl(hi, j, kWave) - jlo[u];
+        jy[u] = PV ? (u32)__shfl(y, j, kWave) : 0u;
         addr[u] = (qb + q) * 4;
         const uint4 v = *reinterpret_cast<const uint4*>(colidx2 + min(addr[u], (m - 1) & ~3u));
         e[u][0] = v.x;
@@ -463,11 +477,36 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, 
         bool ok[4];
 #pragma unroll
         for (u32 i = 0; i < 4; ++i) ok[i] = live[u] && (addr[u] + i - jlo[u]) < jspan[u];
-        hash_count_n<4>(table, mask, e[u], ok, tl.s);
+        if (PV) {
+          u32 qh = 0;
+#pragma unroll
+          for (u32 i = 0; i < 4; ++i) {
+            const u32 sl = ok[i] ? hash_find_key(table, mask, e[u][i]) : kInf;
+            if (sl != kInf) {
+              atomicAdd(&table[kSubCnt + sl], 1u);
+              ++qh;
+            }
+          }
+          tri_add(tri, jy[u], qh);
+          xh += qh;
+          tl.s += qh;
+        } else {
+          hash_count_n<4>(table, mask, e[u], ok, tl.s);
+        }
       }
     }
   }
   wave_lds_sync();  // the table is reused by the next vertex of the group
+  if (PV) {
+    for (u32 i = gl; i < (mask + 1) * 4; i += kSubLanes) {
+      const u32 k = table[kSubCnt + i];
+      if (k) tri_add(tri, table[i] & ~kFlag, k);
+    }
+#pragma unroll
+    for (u32 off = kSubLanes / 2; off > 0; off >>= 1) xh += (u32)__shfl_xor(xh, (int)off, kSubLanes);
+    if (gl == 0) tri_add(tri, x, xh);
+    wave_lds_sync();
+  }
 }
 
 // ---- block class: one 1024-thread workgroup per (x, segment of partners) ------------
@@ -536,7 +575,7 @@ __device__ __forceinline__ void block_pass(
   constexpr bool MEMBER = MODE == kOther || MODE == kSame || MODE == kMember;
   u32& hits = MODE == kSame ? tl.t2 : tl.s;  // same-level apexes above both ends: t2
   const u32 glen = ge - gs;
-  static_assert(!PV || MODE == kFull, "per-vertex counts use the full form");
+  static_assert(!PV || (MEMBER && !BM && !ST), "per-vertex counts: pruned hash passes only");
   const u32 chunk = PV ? min(prm.chunk, kPvChunk) : prm.chunk;
   u32 xh = 0;  // PV: this thread's counted triangles of x
   if (PV && tid < pn) sh.ycnt[tid] = 0;
@@ -679,28 +718,35 @@ __device__ __forceinline__ void block_pass(
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) sm[i] = addr[u] + i < inf[u].w;
           hash_count_split_n<NE, true>(sh.table, mask, e[u], ok, sm, tl.s, tl.t2);
+        } else if (MEMBER && PV) {
+          // every hit is a counted apex: count it under its slot, its partner and x
+          u32 qh = 0;
+#pragma unroll
+          for (u32 i = 0; i < NE; ++i) {
+            const u32 sl = ok[i] ? hash_find_key(sh.table, mask, e[u][i]) : kInf;
+            if (sl != kInf) {
+              atomicAdd(&sh.table[kPvCnt + sl], 1u);
+              ++qh;
+            }
+          }
+          if (qh) {
+            atomicAdd(&sh.ycnt[pidx[u]], qh);
+            xh += qh;
+            hits += qh;
+          }
         } else if (MEMBER) {
           hash_count_n<NE>(sh.table, mask, e[u], ok, hits);
         } else {
           u32 res[NE];
           hash_probe_n<NE>(sh.table, mask, e[u], ok, res);
-          u32 qh = 0;  // PV: counted triangles of this quad
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) {
             if (MODE == kFull) {
               tl.add(res[i], e[u][i], vmax);
-              if (PV && counted_hit(res[i], e[u][i], vmax)) {
-                atomicAdd(&sh.table[kPvCnt + hash_slot_of(sh.table, mask, e[u][i])], 1u);
-                ++qh;
-              }
             } else {
               tl.s += res[i] & 1u;  // other-level apex (c1)
               tl.t2 += res[i] >> 1;  // same-level apex above both endpoints
             }
-          }
-          if (PV && qh) {
-            atomicAdd(&sh.ycnt[pidx[u]], qh);
-            xh += qh;
           }
         }
       }
@@ -710,7 +756,7 @@ __device__ __forceinline__ void block_pass(
       // t(w) for the chunk's keys; the table is rebuilt only after every thread is done
       for (u32 i = tid; i < (mask + 1) * 4; i += blockDim.x) {
         const u32 k = sh.table[kPvCnt + i];
-        if (k) tri_add(tri, (sh.table[i] & ~kFlag) >> 1, k);
+        if (k) tri_add(tri, sh.table[i] & ~kFlag, k);
       }
       __syncthreads();
     }
@@ -736,12 +782,12 @@ __device__ __forceinline__ bool use_bitmap(const u32* __restrict__ a, u32 s, u32
 // One work item of the full form: staged vertex x, partner segment `seg` (all threads
 // call it together), one kFull pass over colidx.  m bounds the quad loads from colidx
 // (beyond it the padded copy tail4 is read).
-template <bool PV, bool VEC, int HS = 1, int QU = kQuadUnroll>
+template <bool VEC, int HS = 1, int QU = kQuadUnroll>
 __device__ __forceinline__ void block_item(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx, u32 m,
     const u32* __restrict__ tail4, const uint8_t* __restrict__ vinfo,
     const u32* __restrict__ hcnt, const u32* __restrict__ hadj, u32 x, u32 seg, IsectParams prm,
-    const BlockShared& sh, Tally& tl, Counts& c, u64* __restrict__ tri) {
+    const BlockShared& sh, Tally& tl, Counts& c) {
   const u32 tid = threadIdx.x;
   const u32 bx = cb + rowptr[x], ex = cb + rowptr[x + 1];
   const u32 px = vinfo[x] & 0x80u;
@@ -753,8 +799,8 @@ __device__ __forceinline__ void block_item(
     yr = cb + rowptr[y];
     ye = cb + rowptr[y + 1];
   }
-  block_pass<PV, VEC, kFull, false, false, QU>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px, y,
-                                               pn, yr, ye, prm, sh, tl, c, tri);
+  block_pass<false, VEC, kFull, false, false, QU>(colidx, m, tail4, colidx, bx, ex, vinfo, x, px,
+                                                  y, pn, yr, ye, prm, sh, tl, c, nullptr);
 }
 
 // One work item of the pruned count: x's entries from sabove[x] on are staged once,
@@ -768,15 +814,17 @@ __device__ __forceinline__ void block_item(
 // kPartAbove for why the hits agree).  PAD: colidx2 has 4 readable entries past its m2
 // counted ones.  ST (kPartRec): the member pass tallies same-level and other-level hits
 // apart (see block_pass).
-template <bool VEC, bool PAD = false, bool ST = false, int PM = kPartRec, int QU = kQuadUnroll>
+template <bool VEC, bool PAD = false, bool ST = false, int PM = kPartRec, int QU = kQuadUnroll,
+          bool PV = false>
 __device__ __forceinline__ void block_item_rec(
     const u32* __restrict__ rowptr, u32 cb, const u32* __restrict__ colidx2, u32 m2,
     const u32* __restrict__ tail4b, const u32* __restrict__ split,
     const u32* __restrict__ sabove, const u32* __restrict__ hcnt,
     const uint4* __restrict__ hrec, const u32* __restrict__ hadj,
     const uint4* __restrict__ vrec, u32 x, u32 seg, IsectParams prm, const BlockShared& sh,
-    Tally& tl, Counts& c) {
+    Tally& tl, Counts& c, u64* __restrict__ tri = nullptr) {
   static_assert(PM == kPartRec || (PM == kPartAbove && !ST), "split tallies need records");
+  static_assert(!PV || (PM == kPartRec && !ST), "per-vertex counts: records, no split tallies");
   constexpr bool kFence = PM == kPartAbove;
   const u32 tid = threadIdx.x;
   u32 bx, ex, gx, sx;
@@ -804,7 +852,22 @@ __device__ __forceinline__ void block_item_rec(
       r = make_uint4(cb + ry.y, cb + ry.z, cb + ry.w, y);
     }
   }
-  if (ex - gx <= prm.chunk) {
+  if (PV) {
+    // per-vertex counts: hash chunks of at most kPvChunk keys (their slot counters fill
+    // the other half of the table), never bitmaps
+    if (ex - gx <= min(prm.chunk, kPvChunk)) {
+      block_pass<true, VEC, kMember, false, PAD, QU>(colidx2, m2, tail4b, colidx2, gx, ex,
+                                                     nullptr, x, 0, r.w, pn, r.x, r.z, prm, sh,
+                                                     tl, c, tri);
+    } else {
+      block_pass<true, VEC, kOther, false, PAD, QU>(colidx2, m2, tail4b, colidx2, sx, ex,
+                                                    nullptr, x, 0, r.w, pn, r.y, r.z, prm, sh,
+                                                    tl, c, tri);
+      block_pass<true, VEC, kSame, false, PAD, QU>(colidx2, m2, tail4b, colidx2, gx, sx,
+                                                   nullptr, x, 0, r.w, pn, r.x, r.y, prm, sh,
+                                                   tl, c, tri);
+    }
+  } else if (ex - gx <= prm.chunk) {
     block_pass<false, VEC, kMember, false, PAD, QU, ST, kFence>(
         colidx2, m2, tail4b, colidx2, gx, ex, nullptr, x, 0, ST ? r.y : r.w, pn, r.x, r.z, prm,
         sh, tl, c, nullptr);
