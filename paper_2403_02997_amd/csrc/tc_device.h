@@ -227,23 +227,6 @@ __device__ __forceinline__ u32 bucket_has(uint4 v, u32 k2) {
   return hit ? 1u : (flagged ? 3u : 0u);
 }
 
-// Slot index (4 b + j) of the plain key w in a membership set built by hash_insert_key
-// with key = w, or kInf when w is absent: per-vertex attribution counts the hits of
-// each staged key.
-__device__ __forceinline__ u32 hash_find_key(const u32* table, u32 bmask, u32 w) {
-  const uint4* t4 = reinterpret_cast<const uint4*>(table);
-  u32 b = hash_mix(w) & bmask;
-  while (true) {
-    const uint4 v = t4[b];
-    if (v.x == w) return 4 * b;
-    if (v.y == w) return 4 * b + 1;
-    if (v.z == w) return 4 * b + 2;
-    if ((v.w & ~kFlag) == w && v.w != kInf) return 4 * b + 3;
-    if (v.w - kFlag >= kInf - kFlag) return kInf;  // the bucket is not flagged: absent
-    b = (b + 1) & bmask;
-  }
-}
-
 template <bool MEMBER>
 __device__ __forceinline__ u32 bucket_result(uint4 v, u32 k2) {
   return MEMBER ? bucket_has(v, k2) : bucket_check(v, k2);
@@ -374,6 +357,58 @@ __device__ __forceinline__ void hash_count_split_n(const u32* table, u32 bmask,
       if (SPLIT && si) hits_same += hit ? 1u : 0u;
       else hits += hit ? 1u : 0u;
       if (hit || !bucket_flagged(vv)) pend &= pend - 1;
+    }
+  }
+}
+
+// Slot (4 b + j) of the plain key w in bucket b, or kInf.
+__device__ __forceinline__ u32 bucket_slot(uint4 v, u32 w, u32 b) {
+  return v.x == w ? 4 * b
+                  : v.y == w ? 4 * b + 1
+                             : v.z == w ? 4 * b + 2 : (v.w & ~kFlag) == w ? 4 * b + 3 : kInf;
+}
+
+// Membership probes of N keys in a set built by hash_insert_key with key = w, giving the
+// slot that holds each (kInf where absent or !ok[i]): per-vertex attribution counts the
+// hits of each staged key.  First buckets are read for all keys before any is examined;
+// keys whose bucket was full continue in one wave-uniform loop, as in hash_count_split_n.
+template <int N>
+__device__ __forceinline__ void hash_slots_n(const u32* table, u32 bmask, const u32 (&w)[N],
+                                             const bool (&ok)[N], u32 (&slot)[N]) {
+  const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  uint4 v[N];
+  u32 b[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    b[i] = hash_mix(w[i]) & bmask;
+    v[i] = t4[b[i]];
+  }
+  u32 pend = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    slot[i] = ok[i] ? bucket_slot(v[i], w[i], b[i]) : kInf;
+    pend |= (ok[i] && slot[i] == kInf && bucket_flagged(v[i]) ? 1u : 0u) << i;
+  }
+  while (__ballot(pend != 0)) {
+    if (pend) {
+      const u32 i = __ffs(pend) - 1;
+      u32 wi = w[0], bi = b[0];
+#pragma unroll
+      for (int j = 1; j < N; ++j) {
+        wi = (u32)j == i ? w[j] : wi;
+        bi = (u32)j == i ? b[j] : bi;
+      }
+      bi = (bi + 1) & bmask;
+      const uint4 vv = t4[bi];
+      const u32 sl = bucket_slot(vv, wi, bi);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if ((u32)j == i) {
+          b[j] = bi;
+          slot[j] = sl;
+        }
+      }
+      if (sl != kInf || !bucket_flagged(vv)) pend &= pend - 1;
     }
   }
 }

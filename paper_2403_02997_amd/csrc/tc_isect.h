@@ -288,12 +288,12 @@ __device__ __forceinline__ void wave_vertex(
           hash_count_split_n<NE, true>(table, mask, e[u], ok, sm, tl.s, tl.t2);
         } else if (KEYS && PV) {
           // every hit is a counted apex: count it under its slot, its partner and x
-          u32 qh = 0;
+          u32 sl[NE], qh = 0;
+          hash_slots_n<NE>(table, mask, e[u], ok, sl);
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) {
-            const u32 sl = ok[i] ? hash_find_key(table, mask, e[u][i]) : kInf;
-            if (sl != kInf) {
-              atomicAdd(&table[kCnt + sl], 1u);
+            if (sl[i] != kInf) {
+              atomicAdd(&table[kCnt + sl[i]], 1u);
               ++qh;
             }
           }
@@ -478,12 +478,12 @@ __device__ __forceinline__ void subwave_vertex(const u32* __restrict__ colidx2, 
 #pragma unroll
         for (u32 i = 0; i < 4; ++i) ok[i] = live[u] && (addr[u] + i - jlo[u]) < jspan[u];
         if (PV) {
-          u32 qh = 0;
+          u32 sl[4], qh = 0;
+          hash_slots_n<4>(table, mask, e[u], ok, sl);
 #pragma unroll
           for (u32 i = 0; i < 4; ++i) {
-            const u32 sl = ok[i] ? hash_find_key(table, mask, e[u][i]) : kInf;
-            if (sl != kInf) {
-              atomicAdd(&table[kSubCnt + sl], 1u);
+            if (sl[i] != kInf) {
+              atomicAdd(&table[kSubCnt + sl[i]], 1u);
               ++qh;
             }
           }
@@ -544,11 +544,11 @@ struct BlockShared {
   u32* ycnt;  // per-vertex counts: counted triangles per partner of the item (LDS)
 };
 
-// Per-vertex counts in the kFull pass: hash chunks of at most kPvChunk keys fill the
+// Per-vertex counts in the pruned hash passes: chunks of at most kPvChunk keys fill the
 // lower half of the table, and the upper half (from kPvCnt) counts the hits of each
 // slot's key, added to t(w) once per chunk.
 constexpr u32 kPvCnt = kBigSlots / 2;
-constexpr u32 kPvChunk = kPvCnt / 8;
+constexpr u32 kPvChunk = kPvCnt / 4;  // buckets at most a quarter full
 
 // One pass over the partners of a work item.  The staged keys ga[gs .. ge) (ascending)
 // go to LDS either as hash sets of at most prm.chunk keys (BM = false) or, for the
@@ -578,6 +578,7 @@ __device__ __forceinline__ void block_pass(
   static_assert(!PV || (MEMBER && !BM && !ST), "per-vertex counts: pruned hash passes only");
   const u32 chunk = PV ? min(prm.chunk, kPvChunk) : prm.chunk;
   u32 xh = 0;  // PV: this thread's counted triangles of x
+  u32 yp = 0, ya = 0;  // PV: a partner index and its hits not yet in sh.ycnt
   if (PV && tid < pn) sh.ycnt[tid] = 0;
   // hash chunks by count, or bitmap windows by ID
   const u32 w_first = BM && glen ? ga[gs] >> kWinBits : 0u;
@@ -720,17 +721,24 @@ __device__ __forceinline__ void block_pass(
           hash_count_split_n<NE, true>(sh.table, mask, e[u], ok, sm, tl.s, tl.t2);
         } else if (MEMBER && PV) {
           // every hit is a counted apex: count it under its slot, its partner and x
-          u32 qh = 0;
+          u32 sl[NE], qh = 0;
+          hash_slots_n<NE>(sh.table, mask, e[u], ok, sl);
 #pragma unroll
           for (u32 i = 0; i < NE; ++i) {
-            const u32 sl = ok[i] ? hash_find_key(sh.table, mask, e[u][i]) : kInf;
-            if (sl != kInf) {
-              atomicAdd(&sh.table[kPvCnt + sl], 1u);
+            if (sl[i] != kInf) {
+              atomicAdd(&sh.table[kPvCnt + sl[i]], 1u);
               ++qh;
             }
           }
           if (qh) {
-            atomicAdd(&sh.ycnt[pidx[u]], qh);
+            // a lane's quads of one partner run on across windows: add to the partner's
+            // counter when the partner changes
+            if (pidx[u] != yp) {
+              if (ya) atomicAdd(&sh.ycnt[yp], ya);
+              yp = pidx[u];
+              ya = 0;
+            }
+            ya += qh;
             xh += qh;
             hits += qh;
           }
@@ -750,6 +758,10 @@ __device__ __forceinline__ void block_pass(
           }
         }
       }
+    }
+    if (PV && ya) {
+      atomicAdd(&sh.ycnt[yp], ya);
+      ya = 0;
     }
     __syncthreads();
     if (PV) {

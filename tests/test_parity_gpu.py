@@ -239,8 +239,8 @@ def test_forward_ordering_under_class_and_hub_settings(tc_lib, name, setting):
                                   "book10000", "grid64_del", "union", "small_first", "rmat16",
                                   "rmat14_ef32", "er16_d32"])
 def test_per_vertex_matches_oracle(tc_lib, name):
-    # rmat16, rmat14_ef32 and book10000 have staged vertices of more than 2048 entries,
-    # whose per-vertex pass stages N(x) in several hash chunks
+    # book10000's two hubs stage more than 4096 keys each, which the per-vertex pass
+    # takes in several hash chunks
     g, r, _, _ = case(name)
     say(f"[parity] tc_count_per_vertex {name}")
     rp, ci = upload(g, tc_lib)
@@ -253,7 +253,7 @@ def test_per_vertex_matches_oracle(tc_lib, name):
 def test_per_vertex_under_isect_settings(tc_lib, name, setting):
     # chunked: every vertex above 16 entries in the workgroup class, 100-key chunks and
     # 7-partner items; wave: the wavefront class up to 512 entries, chunks of up to
-    # 16384 keys asked for (the per-vertex pass caps them at 2048)
+    # 16384 keys asked for (the per-vertex pass caps them at 4096)
     g, r, _, _ = case(name)
     isect, _ = SPLIT_SETTINGS[setting]
     say(f"[parity] tc_count_per_vertex {name} ({setting})")
