@@ -352,11 +352,11 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
                u32* level_out, u64* tri, bool pruned, RunOut* out, bool split_stats = false) {
   prepare_pool();
   const IsectParams prm = g_params;
-  // the hub pass serves the pruned count only (per-vertex counts and c1 / c2 tallies stay
-  // per cover edge: a hub mask says how many hubs close a triangle, not which), on graphs of at least kHubEntriesPerDegree stored entries per unit of the hub
+  // the hub pass serves the pruned count and per-vertex counts only (c1 / c2 tallies stay
+  // per cover edge), on graphs of at least kHubEntriesPerDegree stored entries per unit of the hub
   // degree floor (smaller ones cannot give hubs enough partners to pay for the pass)
   const bool hub_size = (u64)m >= (u64)kHubEntriesPerDegree * g_hub_min_degree;
-  const HubParams hp{pruned && !tri && hub_size ? g_hub_max : 0u,
+  const HubParams hp{pruned && hub_size ? g_hub_max : 0u,
                      host_degree_class(g_hub_min_degree)};
   const bool hub_on = hp.max_hubs > 0;
   const size_t hub_cap = hub_on ? hub_item_cap(n, m) : 0;
@@ -572,7 +572,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
     // the workgroup class (persistent workgroups that hold their units to the end) ramps up
     if (hubs)
       launch_hub_count(rowptr, colidx2, sabove, split, h_plan.num_hubs, hy, hubmask, hitems,
-                       h_plan.num_hub_items, ctr, split_stats, sw);
+                       h_plan.num_hub_items, ctr, split_stats, hublist, tri, sw);
     launch_isect_wave(rowptr, colidx, m, tail4, vinfo, sv, wave_x, h_plan.num_wave_x, plan, ctr,
                       tri, pruned, split_stats, sw);
     launch_isect_lane(rowptr, colidx, vinfo, sv, lane_x, h_plan.num_lane_x, ctr, tri, s);
@@ -593,7 +593,7 @@ int run_single(const u32* rowptr, const u32* colidx, u32 n, u32 m, hipStream_t s
                        s);
     if (hubs)
       launch_hub_count(rowptr, colidx2, sabove, split, h_plan.num_hubs, hy, hubmask, hitems,
-                       h_plan.num_hub_items, ctr, split_stats, s);
+                       h_plan.num_hub_items, ctr, split_stats, hublist, tri, s);
     timer.mark();
   }
   TC_LAUNCHED();

@@ -173,7 +173,17 @@ __global__ void __launch_bounds__(kHubThreads) k_hub_mask(const u32* __restrict_
 // t2 counter, the others in c1 (the two terms of the split).
 constexpr u32 kHubU = kHubChunk / kWave;  // entries per lane and item
 
-template <u32 NW, bool ST>
+// One 32-bit word c of a 16-byte mask word.
+__device__ __forceinline__ u32 word_of(const uint4& v, u32 c) {
+  return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+}
+
+// PV: per-vertex counts.  Each unit of popcount(M(w) & H(y)) is the triangle {h, y, w} of
+// one hub h: t(w) gets the popcount of its entry, t(y) the item's sum, and t(h) for every
+// hub bit of H(y) the number of the item's entries whose mask holds it (ballot counts,
+// gathered per workgroup in LDS and added once per hub at the end; hublist maps the bit
+// to the hub's ID).
+template <u32 NW, bool ST, bool PV = false>
 __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowptr,
                                                    const u32* __restrict__ colidx2,
                                                    const u32* __restrict__ sabove,
@@ -181,9 +191,17 @@ __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowpt
                                                    const u32* __restrict__ hy,
                                                    const u32* __restrict__ hubmask,
                                                    const uint2* __restrict__ items, u32 nitems,
-                                                   u64* __restrict__ ctr) {
+                                                   u64* __restrict__ ctr,
+                                                   const u32* __restrict__ hublist, u32 nhubs,
+                                                   u64* __restrict__ tri) {
+  static_assert(!(PV && ST), "per-vertex counts tally no split");
   constexpr u32 NQ = NW / 4;  // 16-byte words per mask
   __shared__ u64 s_red[2 * 256 / kWave];
+  __shared__ unsigned long long s_hub[PV ? kMaxHubs : 1];
+  if (PV) {
+    for (u32 k = threadIdx.x; k < kMaxHubs; k += blockDim.x) s_hub[k] = 0;
+    __syncthreads();
+  }
   const u32 lane = lane_id();
   const u32 wid = threadIdx.x / kWave;
   const u32 gw = blockIdx.x * (blockDim.x / kWave) + wid;
@@ -226,10 +244,33 @@ __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowpt
                __popc(mv[u][q].z & hq[q].z) + __popc(mv[u][q].w & hq[q].w);
         if (ST && b + (u0 + u) * kWave + lane < ys) part_same += h;
         else part += h;
+        if (PV) tri_add(tri, w[u0 + u], h);  // h is 0 past the end (zero masks)
+      }
+      if (PV) {
+#pragma unroll
+        for (u32 q = 0; q < NQ; ++q) {
+#pragma unroll
+          for (u32 cw = 0; cw < 4; ++cw) {
+            u32 hw = (u32)__builtin_amdgcn_readfirstlane((int)word_of(hq[q], cw));  // uniform
+            while (hw) {
+              const u32 bit = __ffs(hw) - 1;
+              hw &= hw - 1;
+              u32 cnt = 0;
+#pragma unroll
+              for (u32 u = 0; u < G; ++u)
+                cnt += (u32)__popcll(__ballot((word_of(mv[u][q], cw) >> bit) & 1u));
+              if (lane == 0 && cnt) atomicAdd(&s_hub[(4 * q + cw) * 32 + bit], (unsigned long long)cnt);
+            }
+          }
+        }
       }
     }
     acc += part;
     acc_same += part_same;
+    if (PV) {
+      const u64 sy = wave_sum_u64(part);
+      if (lane == 0) tri_add(tri, y, sy);
+    }
   }
   acc = wave_sum_u64(acc);
   if (ST) acc_same = wave_sum_u64(acc_same);
@@ -247,6 +288,10 @@ __global__ void __launch_bounds__(256) k_hub_count(const u32* __restrict__ rowpt
     u64* slot = &ctr[(blockIdx.x % kCounterSlots) * kNumCtr];
     if (sum) atomicAdd((unsigned long long*)&slot[0], (unsigned long long)sum);
     if (sum_same) atomicAdd((unsigned long long*)&slot[2], (unsigned long long)sum_same);
+  }
+  if (PV) {
+    // every wavefront's hub counts are in after the barrier above
+    for (u32 k = threadIdx.x; k < nhubs; k += blockDim.x) tri_add(tri, hublist[k], s_hub[k]);
   }
 }
 
@@ -271,18 +316,20 @@ void launch_hub_masks(const u32* rowptr, const u32* colidx2, const u32* split,
 void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove,
                       const u32* split, u32 nhubs, const u32* hy, const u32* hubmask,
                       const uint2* items, u32 nitems, u64* ctr, bool split_stats,
-                      hipStream_t s) {
+                      const u32* hublist, u64* tri, hipStream_t s) {
   if (nhubs == 0 || nitems == 0) return;
   const u32 gc = min(cdiv(nitems, 256 / kWave), (u32)num_cus() * 8);
-#define TC_LAUNCH_HUB(NW, ST)                                                                  \
-  hipLaunchKernelGGL((k_hub_count<NW, ST>), dim3(gc), dim3(256), 0, s, rowptr, colidx2, sabove, \
-                     split, hy, hubmask, items, nitems, ctr)
+#define TC_LAUNCH_HUB(NW, ST, PV)                                                              \
+  hipLaunchKernelGGL((k_hub_count<NW, ST, PV>), dim3(gc), dim3(256), 0, s, rowptr, colidx2,     \
+                     sabove, split, hy, hubmask, items, nitems, ctr, hublist, nhubs, tri)
   if (hub_mask_words(nhubs) == 4) {
-    if (split_stats) TC_LAUNCH_HUB(4, true);
-    else TC_LAUNCH_HUB(4, false);
+    if (tri) TC_LAUNCH_HUB(4, false, true);
+    else if (split_stats) TC_LAUNCH_HUB(4, true, false);
+    else TC_LAUNCH_HUB(4, false, false);
   } else {
-    if (split_stats) TC_LAUNCH_HUB(8, true);
-    else TC_LAUNCH_HUB(8, false);
+    if (tri) TC_LAUNCH_HUB(8, false, true);
+    else if (split_stats) TC_LAUNCH_HUB(8, true, false);
+    else TC_LAUNCH_HUB(8, false, false);
   }
 #undef TC_LAUNCH_HUB
 }

@@ -184,11 +184,13 @@ void launch_hub_masks(const u32* rowptr, const u32* colidx2, const u32* split,
                       const u32* sabove, const u32* hublist, u32 nhubs, u32 n, u32* cuts,
                       u32* hubmask, hipStream_t s);
 // Counts the hub items' triangles into the c1 counter (no LDS); with split_stats the
-// same-level apexes go to the t2 counter instead.
+// same-level apexes go to the t2 counter instead.  With tri (device, per-vertex counts)
+// each triangle {h, y, w} also adds 1 to t(h), t(y) and t(w); hublist maps hub numbers
+// to vertex IDs.
 void launch_hub_count(const u32* rowptr, const u32* colidx2, const u32* sabove,
                       const u32* split, u32 nhubs, const u32* hy, const u32* hubmask,
                       const uint2* items, u32 nitems, u64* ctr, bool split_stats,
-                      hipStream_t s);
+                      const u32* hublist, u64* tri, hipStream_t s);
 
 // ---- intersection ----
 // The intersection launchers take the split's outputs in one struct.  pruned: count

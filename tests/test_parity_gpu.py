@@ -248,23 +248,31 @@ def test_per_vertex_matches_oracle(tc_lib, name):
     assert np.array_equal(t, r.per_vertex)
 
 
-@pytest.mark.parametrize("setting", ["chunked", "wave"])
-@pytest.mark.parametrize("name", ["rmat16", "book10000", "er16_d32", "union"])
+@pytest.mark.parametrize("setting", ["chunked", "wave", "hubs"])
+@pytest.mark.parametrize("name", ["rmat16", "book10000", "er16_d32", "union", "K40"])
 def test_per_vertex_under_isect_settings(tc_lib, name, setting):
     # chunked: every vertex above 16 entries in the workgroup class, 100-key chunks and
     # 7-partner items; wave: the wavefront class up to 512 entries, chunks of up to
-    # 16384 keys asked for (the per-vertex pass caps them at 4096)
+    # 16384 keys asked for (the per-vertex pass caps them at 4096); hubs: the hub pass
+    # (its triangles attributed per hub bit) on every graph of at least 1024 entries
     g, r, _, _ = case(name)
-    isect, _ = SPLIT_SETTINGS[setting]
+    isect, hubs = SPLIT_SETTINGS[setting]
     say(f"[parity] tc_count_per_vertex {name} ({setting})")
     rp, ci = upload(g, tc_lib)
-    saved = tc_lib.tc_get_isect_params()
+    saved_i, saved_h = tc_lib.tc_get_isect_params(), tc_lib.tc_get_hub_params()
     try:
-        tc_lib.tc_set_isect_params(*isect)
+        if isect:
+            tc_lib.tc_set_isect_params(*isect)
+        if hubs:
+            tc_lib.tc_set_hub_params(*hubs)
         t = tc_lib.as_u64(tc_lib.tc_count_per_vertex(rp, ci))
+        info = tc_lib.tc_last_call_info()
     finally:
-        tc_lib.tc_set_isect_params(*saved)
+        tc_lib.tc_set_isect_params(*saved_i)
+        tc_lib.tc_set_hub_params(*saved_h)
     assert np.array_equal(t, r.per_vertex)
+    if hubs and name in ("rmat16", "book10000"):
+        assert info["hubs"] > 0  # the hub pass took part
 
 
 @pytest.mark.parametrize("name", ["karate", "K40", "K2", "K1", "wheel500", "friendship100", "star5000",
