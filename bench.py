@@ -74,7 +74,7 @@ CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
 KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>",
                   "isect_wave": "k_isect_wave<false, true, true, false>",
                   "isect_block": "k_isect_block<false, true, true, false>",
-                  "isect_hub": "k_hub_count<8u, false>"}
+                  "isect_hub": "k_hub_count<8u, false, false>"}
 
 WORKLOAD_TEXT = {
     "rmat10": "R-MAT scale 10, edge factor 16, initiator (0.57,0.19,0.19,0.05), seed 1000",
@@ -445,10 +445,18 @@ def bench_per_vertex(args, tcm, torch, rp, ci, g, T) -> dict:
     assert int(tri.sum().item()) == 3 * T and cc.numel() == g.n
     ms = (t1 - t0) * 1e3 / k
     log(f"[bench] per-vertex counts: {ms:.3f} ms/call")
+    # step breakdown: the same calls with step timing on (classes one after another)
+    tcm.tc_profile_read(reset=True)
+    tcm.tc_profile_enable(True)
+    for _ in range(k):
+        tcm.tc_count_per_vertex(rp, ci)
+    tcm.tc_profile_enable(False)
+    prof, calls = tcm.tc_profile_read(reset=True)
     return {"calls": k, "ms_per_call": round(ms, 4),
             "input_edges_per_s": g.num_edges / (ms * 1e-3),
             "counted_triangles": T, "attributions": 3 * T,
-            "clustering_ms_per_call": round((t2 - t1) * 1e3 / k, 4)}
+            "clustering_ms_per_call": round((t2 - t1) * 1e3 / k, 4),
+            "steps_ms": {key: round(v / max(calls, 1), 4) for key, v in prof.items()}}
 
 
 # ---- batched workload ------------------------------------------------------------------------
