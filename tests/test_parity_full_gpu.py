@@ -6,7 +6,9 @@ results (tests/golden/full_size_counts.json, written by make_full_counts.py from
 oracle alone), and the GPU's BFS level of every vertex must equal the oracle's BFS run
 here on the host.  For the 4096-graph batch, every member's count, from the batched
 launch and from its own tc_count call, must equal the oracle's stored count
-(tests/golden/batch4096_counts.json).
+(tests/golden/batch4096_counts.json).  Per-vertex counts at full size sum to 3 T and
+agree, on the largest-degree vertex and a seeded sample, with a count of the edges among
+each sampled vertex's neighbours.
 """
 import json
 import os
@@ -28,6 +30,23 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def edges_among_neighbours(g, v):
+    """Edges between two neighbours of v (the triangles through v): every entry of a
+    neighbour's row that is itself a neighbour of v, halved."""
+    rp = g.rowptr.astype(np.int64)
+    nb = g.colidx[rp[v]:rp[v + 1]].astype(np.int64)
+    mark = np.zeros(g.n, dtype=bool)
+    mark[nb] = True
+    starts, lens = rp[nb], rp[nb + 1] - rp[nb]
+    total = int(lens.sum())
+    if total == 0:
+        return 0
+    idx = np.repeat(starts - np.concatenate(([0], np.cumsum(lens)[:-1])), lens) + np.arange(total)
+    hits = int(mark[g.colidx[idx]].sum())
+    assert hits % 2 == 0
+    return hits // 2
 
 
 @pytest.mark.parametrize("name", ["rmat10", "er22", "grid4096", "rmat22"])
@@ -52,6 +71,18 @@ def test_full_size_matches_oracle(tc_lib, name):
     # identities pinned on the CPU against the oracle's own CETC-Seq-S)
     t0, t1 = tc_lib.tc_count_split(rp, ci)
     assert t1 == ref["c1"] and 3 * t0 == ref["c2"]
+    # per-vertex counts at full size: they sum to 3 T, and the largest-degree vertex and
+    # 31 seeded others have t(v) = the edges among their neighbours, counted here from
+    # that definition
+    say(f"[full] tc_count_per_vertex {name}")
+    tri = tc_lib.as_u64(tc_lib.tc_count_per_vertex(rp, ci))
+    assert int(tri.sum()) == 3 * ref["triangles"]
+    deg = np.diff(g.rowptr.astype(np.int64))
+    rng = np.random.default_rng(2403)
+    cand = np.flatnonzero(deg >= 2)
+    sample = [int(np.argmax(deg))] + [int(v) for v in rng.choice(cand, 31, replace=False)]
+    for v in sample:
+        assert int(tri[v]) == edges_among_neighbours(g, v), f"vertex {v} (degree {deg[v]})"
 
 
 def test_batch4096_every_member(tc_lib):
