@@ -71,6 +71,7 @@ CSRC = os.path.join(ROOT, "paper_2403_02997_amd", "csrc")
 # colidx, no per-vertex attribution; the workgroup class in its pruned form).
 # the kernel instantiations of the counting call (the fourth template argument, false,
 # leaves out the split-term tallies of tc_count_split)
+BATCH_KERNEL = "k_batch_main<true>"
 KERNEL_OF_STEP = {"isect_lane": "k_isect_lane<false>",
                   "isect_wave": "k_isect_wave<false, true, true, false>",
                   "isect_block": "k_isect_block<false, true, true, false>",
@@ -663,10 +664,10 @@ def bench_batch(args, tcm, torch):
     del levels
     kern_ms = float(np.mean(launch_ms))
     achieved = pb["total"] / (kern_ms * 1e-3) / 1e9
-    traffic = stored_traffic("batch4096", "k_batch_main<true>", current_settings(tcm))
+    traffic = stored_traffic("batch4096", BATCH_KERNEL, current_settings(tcm))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_batch_main<true>", "avg_launch_ms": round(kern_ms, 4),
+                "kernel": BATCH_KERNEL, "avg_launch_ms": round(kern_ms, 4),
                 "timed_in": f"HIP events around {args.steps} graph replays on their stream "
                             "(the replay also holds two kernels of a few microseconds)",
                 "algorithmic_bytes_per_launch": pb["total"],

@@ -1,5 +1,8 @@
 """Host logic of bench.py: the algorithmic bytes of each intersection class and the hub
 selection, checked against counts written directly from the definitions (no GPU)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -178,3 +181,19 @@ def test_batch_plan_bytes_sum_over_members():
     want["output"] = 8 * len(graphs)
     want["total"] = want["bfs"] + want["extract"] + want["intersect"] + want["output"]
     assert got == want
+
+
+def test_stored_traffic_names_the_reported_kernels():
+    # bench.py looks counter traffic up by kernel name; whenever profiles/traffic.json
+    # holds records of the current kernel sources for a workload, the kernels bench.py
+    # reports for it must be among them (a renamed template would otherwise leave
+    # roofline.traffic null without notice)
+    rec = json.load(open(os.path.join(bench.PROFILES, "traffic.json")))
+    sha = bench.source_sha()
+    wanted = {"batch4096": [bench.BATCH_KERNEL],
+              "rmat22": [bench.KERNEL_OF_STEP[k] for k in ("isect_block", "isect_wave", "isect_hub")],
+              "er22": [bench.KERNEL_OF_STEP["isect_wave"]]}
+    for wl, kernels in wanted.items():
+        current = {k for k, v in rec.get(wl, {}).items() if v.get("source_sha") == sha}
+        if current:
+            assert set(kernels) <= current, (wl, sorted(set(kernels) - current))
