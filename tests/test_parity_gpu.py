@@ -330,6 +330,8 @@ def test_unaligned_colidx(tc_lib, name):
             stats, _ = tc_lib.tc_count_ex(rp, shifted)
             assert stats.triangles == r.triangles and stats.cover_edges == r.cover_edges
             assert tc_lib.tc_count(rp, shifted) == r.triangles
+            t = tc_lib.as_u64(tc_lib.tc_count_per_vertex(rp, shifted))
+            assert np.array_equal(t, r.per_vertex)
     finally:
         tc_lib.tc_set_isect_params(*saved)
 
