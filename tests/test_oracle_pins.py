@@ -438,3 +438,15 @@ def test_clustering_against_networkx(seed):
     G.add_edges_from(zip(rows.tolist(), g.colidx.tolist()))
     ref = nx.clustering(G)
     assert np.array_equal(oracle.local_clustering(g), np.array([ref[v] for v in range(g.n)]))
+
+
+def test_full_size_per_vertex_reference_matches_oracle():
+    # the full-size GPU test checks sampled t(v) against edges_among_neighbours (the
+    # edges between two neighbours of v); on graphs the oracle handles whole, that count
+    # equals the oracle's per-vertex counts at every vertex
+    from tests.test_parity_full_gpu import edges_among_neighbours
+    for g in [gg.rmat(11, 16, 11), gg.wheel(40), gg.complete(15), gg.tri_grid(20, 20, 0.02, 4),
+              gg.friendship(9), gg.empty_graph(4)]:
+        r = oracle.cetc_seq(g, per_vertex=True)
+        got = np.array([edges_among_neighbours(g, v) for v in range(g.n)], dtype=np.int64)
+        assert np.array_equal(got, r.per_vertex.astype(np.int64))
